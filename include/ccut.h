@@ -1,0 +1,234 @@
+/*
+ * ccut -- Clifford-based circuit cutting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libccut.so.  The problem statement follows the paper
+ * (SuperSim, arXiv 2303.10788): a circuit whose inputs start in |0> and
+ * whose outputs are measured in Z (Sec. V-B), plus a list of wire cuts
+ * (Secs. III-B, V-A), goes in; the uncut circuit's output marginal or
+ * Z-string expectations, rebuilt from fragment variants by the tensor
+ * contraction of Sec. V-C, come out.
+ *
+ * Conventions shared by every call:
+ *  - every call returns a ccut_status; no C++ exception crosses the ABI;
+ *    on failure ccut_last_error() describes the first error;
+ *  - handles are owned by the library and freed by the matching *_destroy;
+ *  - a context is not thread-safe: use one per host thread;
+ *  - device work runs on the context's HIP stream and every call returns
+ *    only after its results are in the caller's buffer (host or device);
+ *  - results are a pure function of (ops, cuts, request, seed, shots, mode):
+ *    every random bit is Philox4x32-10 keyed by seed and counted by
+ *    (variant id, shot, measurement index);
+ *  - estimates are raw quasi-probabilities (no maximum-likelihood
+ *    correction): sampled marginals can be slightly negative.
+ *
+ * Readings of the method where the paper is silent:
+ *  - quantum inputs are prepared in {|0>, |1>, |+>, |+i>}, quantum outputs
+ *    measured in {X, Y, Z}; the I term of an output comes from its Z basis;
+ *  - a fragment variant is numbered in mixed radix over the fragment's
+ *    incident cut axes in cut-list order (upstream side before downstream
+ *    side of the same cut), first axis least significant; bases radix 3
+ *    (X, Y, Z), preparations radix 4 (0, 1, +, +i);
+ *  - the variant id is (circuit << 40) | (fragment << 32) | variant;
+ *  - a fragment measures only its measured set: requested circuit outputs
+ *    plus quantum outputs, in ascending fragment-local order, local qubits
+ *    being ordered by (wire, segment along the wire);
+ *  - the Philox bit of measurement index a in shot s is bit (a & 31) of
+ *    output word (s & 3) of philox(ctr = (a >> 5, s >> 2, lo32(vid),
+ *    hi32(vid)), key = (lo32(seed), hi32(seed))); a random outcome equals
+ *    its bit.
+ */
+#ifndef CCUT_ABI_H_
+#define CCUT_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccut_ctx ccut_ctx;   /* opaque, library-owned */
+typedef struct ccut_plan ccut_plan; /* opaque, library-owned */
+
+typedef enum {
+  CCUT_OK = 0,
+  CCUT_E_INVALID = -1,        /* malformed circuit, cut list or request */
+  CCUT_E_OOM = -2,            /* a device or host allocation failed */
+  CCUT_E_DEVICE = -3,         /* no device on this context, or a HIP error */
+  CCUT_E_NC_TOO_WIDE = -4,    /* a non-Clifford fragment exceeds max_nc_qubits */
+  CCUT_E_TOO_MANY_CUTS = -5,  /* k exceeds max_cuts */
+  CCUT_E_CANCELLED = -6,      /* ccut_cancel() was called during the evaluation */
+  CCUT_E_UNSUPPORTED = -7     /* a size beyond what the kernels implement */
+} ccut_status;
+
+/* Gates (Sec. II): Paulis, H = (Z+X)/sqrt2, S = Z^(1/2), S^dag, CX, CZ,
+ * T = Z^(1/4) = diag(1, e^{i pi/4}), T^dag, RZ(theta) = diag(1, e^{i theta}).
+ * H, S, SDG, X, Y, Z, CX, CZ are Clifford; T, TDG, RZ are not. */
+typedef enum {
+  CCUT_H = 0, CCUT_S = 1, CCUT_SDG = 2, CCUT_X = 3, CCUT_Y = 4, CCUT_Z = 5,
+  CCUT_CX = 6, CCUT_CZ = 7, CCUT_T = 8, CCUT_TDG = 9, CCUT_RZ = 10
+} ccut_gate_kind;
+
+/* One gate.  q1 is the target of CX (q0 the control) and the second qubit
+ * of CZ; it is ignored for one-qubit gates.  theta is used by RZ only. */
+typedef struct {
+  uint32_t kind;
+  uint32_t q0;
+  uint32_t q1;
+  uint32_t reserved;
+  double theta;
+} ccut_op;
+
+/* Cut wire `qubit` right after global op index `after_op`, which must act
+ * on that wire (the cut locations of Sec. V-A). */
+typedef struct {
+  uint32_t qubit;
+  uint32_t after_op;
+} ccut_cut;
+
+/* Optional device allocator (for example a framework's caching allocator).
+ * alloc returns NULL on failure, which the library reports as CCUT_E_OOM. */
+typedef void *(*ccut_alloc_fn)(size_t bytes, void *user);
+typedef void (*ccut_free_fn)(void *ptr, void *user);
+
+typedef struct {
+  int device;             /* HIP device ordinal; -1 = host-only (plan and validate only) */
+  void *hip_stream;       /* hipStream_t for all device work; NULL = null stream */
+  ccut_alloc_fn alloc;    /* NULL: hipMalloc */
+  ccut_free_fn free;      /* NULL: hipFree */
+  void *user;             /* passed to alloc/free */
+  uint32_t max_nc_qubits; /* 0 = default 12: the state vector of a non-Clifford fragment lives in LDS */
+  uint32_t max_cuts;      /* 0 = default 12: exhaustive recombination sums 4^k terms */
+} ccut_opts;
+
+enum { CCUT_FP64 = 0, CCUT_FP32_MFMA_FP64SUM = 1 };
+
+typedef struct {
+  uint64_t seed;              /* Philox key */
+  uint64_t shots_per_variant; /* 0 = exact ("strong simulation", Sec. V-C) Clifford tables */
+  int32_t precision;          /* CCUT_FP64, or CCUT_FP32_MFMA_FP64SUM for the recombination */
+  uint32_t circuit;           /* circuit index in variant ids (batch position) */
+} ccut_eval_opts;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context.  opts may be NULL (device 0, null stream, hipMalloc,
+ * defaults).  Selects the device; errors: CCUT_E_DEVICE (no such device),
+ * CCUT_E_OOM. */
+ccut_status ccut_ctx_create(const ccut_opts *opts, ccut_ctx **out);
+void ccut_ctx_destroy(ccut_ctx *ctx);
+
+/* Text of the last error on this context (valid until the next call on
+ * it); "" if none.  ctx may be NULL for errors of ccut_ctx_create. */
+const char *ccut_last_error(const ccut_ctx *ctx);
+
+/* Ask a running evaluation on this context to stop; it returns
+ * CCUT_E_CANCELLED.  The flag is cleared when the next evaluation starts. */
+void ccut_cancel(ccut_ctx *ctx);
+
+/* ---------------------------------------------------------------- plans */
+
+/* Validate the circuit and cut list, split cut wires into segments, form
+ * fragments as connected components of segments joined by two-qubit gates
+ * (Secs. III-B, V-A), tag each fragment Clifford or not (Sec. V-B) and
+ * enumerate its variants.  ops/cuts are host arrays, copied.
+ * Errors: CCUT_E_INVALID (qubit out of range, q0 == q1 on a two-qubit gate,
+ * unknown kind, a cut whose after_op does not act on its qubit, duplicate
+ * cut), CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_OOM. */
+ccut_status ccut_plan_create(ccut_ctx *ctx, uint32_t n_qubits, const ccut_op *ops, size_t n_ops,
+                             const ccut_cut *cuts, size_t k, ccut_plan **out);
+void ccut_plan_destroy(ccut_plan *plan);
+
+/* Number of fragments, total fragment variants, and 4^k cut terms. */
+ccut_status ccut_plan_info(const ccut_plan *plan, uint32_t *n_fragments, uint64_t *n_variants,
+                           uint64_t *n_terms);
+
+/* Fragment f: its width m, 1 if Clifford, number of incident cut axes, and
+ * number of variants (4^inputs * 3^outputs). */
+ccut_status ccut_fragment_info(const ccut_plan *plan, uint32_t f, uint32_t *m, int32_t *clifford,
+                               uint32_t *n_axes, uint64_t *n_variants);
+
+/* Fragment f's local qubits in order: wires[i], segments[i] (segment index
+ * along the wire); arrays of length m. */
+ccut_status ccut_fragment_segments(const ccut_plan *plan, uint32_t f, uint32_t *wires,
+                                   uint32_t *segments);
+
+/* Fragment f's cut axes in variant-digit order: cut index, side (0 = quantum
+ * output, upstream of the cut; 1 = quantum input, downstream) and local
+ * qubit; arrays of length n_axes. */
+ccut_status ccut_fragment_axes(const ccut_plan *plan, uint32_t f, uint32_t *cut, uint32_t *side,
+                               uint32_t *local);
+
+/* ---------------------------------------------------------------- evaluation */
+
+/* Reconstructed output marginal over qubits[0..nq) (Sec. V-C):
+ *   R[b] = 2^-k sum_{P in {I,X,Y,Z}^k} prod_f T_f[b_f; P|f],
+ * bit i of b = outcome of qubits[i].  out has 2^nq doubles, caller-owned,
+ * on the device if out_on_device else on the host.  nq <= 24.
+ * Errors: CCUT_E_INVALID (repeated or out-of-range qubit, nq > 24),
+ * CCUT_E_DEVICE (host-only context), CCUT_E_UNSUPPORTED (a Clifford
+ * fragment with more than 64 measured qubits, or an exact table over
+ * more than 24 measured qubits), CCUT_E_CANCELLED, CCUT_E_OOM. */
+ccut_status ccut_marginal(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
+                          uint32_t nq, double *out, int out_on_device);
+
+/* <Z_z> for n_strings masks; masks is a host array [n_strings][ceil(n/64)]
+ * of uint64 words (bit q of the mask = qubit q).  out has n_strings doubles.
+ * Each fragment measures its circuit outputs that occur in any mask plus
+ * its quantum outputs (at most 64 for a sampled Clifford fragment).
+ * In exact mode each Clifford variant gives -1, 0 or +1 (Sec. IX). */
+ccut_status ccut_zexpect(ccut_plan *plan, const ccut_eval_opts *eo, const uint64_t *masks,
+                         uint32_t n_strings, double *out, int out_on_device);
+
+/* Parity hook: the sampled shot records of Clifford fragment `fragment`
+ * for variants [v_begin, v_end) under the marginal request qubits[0..nq):
+ * out[(v - v_begin) * shots + s] holds the outcome bits of shot s (bit j =
+ * measurement j of the measured set, at most 64).  Needs shots > 0. */
+ccut_status ccut_shot_records(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
+                              uint32_t nq, uint32_t fragment, uint64_t v_begin, uint64_t v_end,
+                              uint64_t *out, int out_on_device);
+
+/* Parity hook: per-variant outcome distributions of fragment `fragment`
+ * under the request: out[v][x], 2^|measured set| doubles per variant
+ * (exact tables, state-vector marginals, or shot frequencies). */
+ccut_status ccut_variant_tables(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
+                                uint32_t nq, uint32_t fragment, double *out, int out_on_device);
+
+/* Parity hook: the fragment's Pauli-basis tensor T_f[p_f][b_f] (p_f =
+ * sum_j P_j 4^j over its axes, I=0 X=1 Y=2 Z=3; b_f bit i = i-th requested
+ * output of the fragment in measured order). */
+ccut_status ccut_fragment_tensor(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
+                                 uint32_t nq, uint32_t fragment, double *out, int out_on_device);
+
+/* Number of measured qubits and requested outputs of fragment `fragment`
+ * under the marginal request (sizes of the two parity hooks above). */
+ccut_status ccut_request_info(ccut_plan *plan, const uint32_t *qubits, uint32_t nq,
+                              uint32_t fragment, uint32_t *n_measured, uint32_t *n_requested);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Kernel timing with HIP events recorded around every launch on the
+ * context's stream.  While enabled, ccut_timing_read returns for kernel id
+ * `kid` the number of launches and their summed duration in ms since the
+ * last reset. */
+enum {
+  CCUT_K_TABLEAU = 0,
+  CCUT_K_SAMPLE = 1,
+  CCUT_K_HIST_REDUCE = 2,
+  CCUT_K_EXACT = 3,
+  CCUT_K_SV = 4,
+  CCUT_K_PARITY = 5,
+  CCUT_K_TRANSFORM = 6,
+  CCUT_K_RECOMBINE = 7,
+  CCUT_K_ZRECOMBINE = 8,
+  CCUT_K_COUNT = 9
+};
+ccut_status ccut_timing_enable(ccut_ctx *ctx, int enable);
+ccut_status ccut_timing_reset(ccut_ctx *ctx);
+ccut_status ccut_timing_read(ccut_ctx *ctx, uint32_t kid, uint64_t *launches, double *total_ms);
+const char *ccut_kernel_name(uint32_t kid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCUT_ABI_H_ */

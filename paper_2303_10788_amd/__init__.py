@@ -1,0 +1,398 @@
+"""Clifford-based circuit cutting on MI355X: Python binding of libccut.so.
+
+The functions named ``ccut_*`` mirror the C ABI in include/ccut.h one to
+one (argument marshalling only; every step runs in the library's HIP
+kernels).  ``Context`` and ``Plan`` are thin conveniences over them that
+hand the library torch's current stream and caching allocator.
+
+The library is loaded from this package directory; if it is missing the
+import of the binding fails loudly (build it with
+``python -m paper_2303_10788_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccut.so")
+
+GATES = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CZ": 7, "T": 8, "TDG": 9, "RZ": 10}
+CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
+CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
+CCUT_FP64, CCUT_FP32_MFMA_FP64SUM = 0, 1
+KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
+           "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel")
+STATUS_NAMES = {0: "CCUT_OK", -1: "CCUT_E_INVALID", -2: "CCUT_E_OOM", -3: "CCUT_E_DEVICE",
+                -4: "CCUT_E_NC_TOO_WIDE", -5: "CCUT_E_TOO_MANY_CUTS", -6: "CCUT_E_CANCELLED",
+                -7: "CCUT_E_UNSUPPORTED"}
+
+
+class ccut_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("q0", ctypes.c_uint32), ("q1", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("theta", ctypes.c_double)]
+
+
+class ccut_cut(ctypes.Structure):
+    _fields_ = [("qubit", ctypes.c_uint32), ("after_op", ctypes.c_uint32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class ccut_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("user", ctypes.c_void_p), ("max_nc_qubits", ctypes.c_uint32),
+                ("max_cuts", ctypes.c_uint32)]
+
+
+class ccut_eval_opts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("shots_per_variant", ctypes.c_uint64),
+                ("precision", ctypes.c_int32), ("circuit", ctypes.c_uint32)]
+
+
+class CcutError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# exported symbols and their signatures (argtypes, restype)
+_P = ctypes.c_void_p
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "ccut_ctx_create": ([ctypes.POINTER(ccut_opts), ctypes.POINTER(_P)], ctypes.c_int),
+    "ccut_ctx_destroy": ([_P], None),
+    "ccut_last_error": ([_P], ctypes.c_char_p),
+    "ccut_cancel": ([_P], None),
+    "ccut_plan_create": ([_P, ctypes.c_uint32, ctypes.POINTER(ccut_op), ctypes.c_size_t,
+                          ctypes.POINTER(ccut_cut), ctypes.c_size_t, ctypes.POINTER(_P)], ctypes.c_int),
+    "ccut_plan_destroy": ([_P], None),
+    "ccut_plan_info": ([_P, _U32P, _U64P, _U64P], ctypes.c_int),
+    "ccut_fragment_info": ([_P, ctypes.c_uint32, _U32P, _I32P, _U32P, _U64P], ctypes.c_int),
+    "ccut_fragment_segments": ([_P, ctypes.c_uint32, _U32P, _U32P], ctypes.c_int),
+    "ccut_fragment_axes": ([_P, ctypes.c_uint32, _U32P, _U32P, _U32P], ctypes.c_int),
+    "ccut_marginal": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, _P, ctypes.c_int],
+                      ctypes.c_int),
+    "ccut_zexpect": ([_P, ctypes.POINTER(ccut_eval_opts), _U64P, ctypes.c_uint32, _P, ctypes.c_int],
+                     ctypes.c_int),
+    "ccut_shot_records": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.c_uint32,
+                           ctypes.c_uint64, ctypes.c_uint64, _P, ctypes.c_int], ctypes.c_int),
+    "ccut_variant_tables": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.c_uint32,
+                             _P, ctypes.c_int], ctypes.c_int),
+    "ccut_fragment_tensor": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.c_uint32,
+                              _P, ctypes.c_int], ctypes.c_int),
+    "ccut_request_info": ([_P, _U32P, ctypes.c_uint32, ctypes.c_uint32, _U32P, _U32P], ctypes.c_int),
+    "ccut_timing_enable": ([_P, ctypes.c_int], ctypes.c_int),
+    "ccut_timing_reset": ([_P], ctypes.c_int),
+    "ccut_timing_read": ([_P, ctypes.c_uint32, _U64P, _DP], ctypes.c_int),
+    "ccut_kernel_name": ([ctypes.c_uint32], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libccut.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2303_10788_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(st: int, ctx) -> None:
+    if st != CCUT_OK:
+        msg = lib().ccut_last_error(ctx)
+        raise CcutError(st, msg.decode() if msg else "")
+
+
+# ----------------------------------------------------------- same-name calls
+
+def ccut_ctx_create(opts: Optional[ccut_opts]):
+    h = _P()
+    st = lib().ccut_ctx_create(ctypes.byref(opts) if opts is not None else None, ctypes.byref(h))
+    _check(st, None)
+    return h
+
+
+def ccut_ctx_destroy(ctx) -> None:
+    lib().ccut_ctx_destroy(ctx)
+
+
+def ccut_last_error(ctx) -> str:
+    return (lib().ccut_last_error(ctx) or b"").decode()
+
+
+def ccut_cancel(ctx) -> None:
+    lib().ccut_cancel(ctx)
+
+
+def _ops_array(ops):
+    arr = (ccut_op * max(len(ops), 1))()
+    for i, (k, a, b, th) in enumerate(ops):
+        arr[i] = ccut_op(GATES[k] if isinstance(k, str) else int(k), int(a), int(b) if b >= 0 else 0, 0,
+                         float(th))
+    return arr
+
+
+def _cuts_array(cuts):
+    arr = (ccut_cut * max(len(cuts), 1))()
+    for i, (q, a) in enumerate(cuts):
+        arr[i] = ccut_cut(int(q), int(a))
+    return arr
+
+
+def ccut_plan_create(ctx, n_qubits: int, ops, cuts):
+    h = _P()
+    st = lib().ccut_plan_create(ctx, n_qubits, _ops_array(ops), len(ops), _cuts_array(cuts), len(cuts),
+                                ctypes.byref(h))
+    _check(st, ctx)
+    return h
+
+
+def ccut_plan_destroy(plan) -> None:
+    lib().ccut_plan_destroy(plan)
+
+
+def ccut_plan_info(plan):
+    nf, nv, nt = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = lib().ccut_plan_info(plan, ctypes.byref(nf), ctypes.byref(nv), ctypes.byref(nt))
+    _check(st, None)
+    return nf.value, nv.value, nt.value
+
+
+def ccut_fragment_info(plan, f: int):
+    m, cl, na, nv = ctypes.c_uint32(), ctypes.c_int32(), ctypes.c_uint32(), ctypes.c_uint64()
+    st = lib().ccut_fragment_info(plan, f, ctypes.byref(m), ctypes.byref(cl), ctypes.byref(na), ctypes.byref(nv))
+    _check(st, None)
+    return m.value, bool(cl.value), na.value, nv.value
+
+
+def ccut_fragment_segments(plan, f: int):
+    m = ccut_fragment_info(plan, f)[0]
+    w = (ctypes.c_uint32 * m)()
+    s = (ctypes.c_uint32 * m)()
+    _check(lib().ccut_fragment_segments(plan, f, w, s), None)
+    return list(zip(list(w), list(s)))
+
+
+def ccut_fragment_axes(plan, f: int):
+    na = ccut_fragment_info(plan, f)[2]
+    c, s, l = (ctypes.c_uint32 * max(na, 1))(), (ctypes.c_uint32 * max(na, 1))(), (ctypes.c_uint32 * max(na, 1))()
+    _check(lib().ccut_fragment_axes(plan, f, c, s, l), None)
+    return [(c[j], s[j], l[j]) for j in range(na)]
+
+
+def _eval_opts(shots=0, seed=0, precision=CCUT_FP64, circuit=0):
+    return ccut_eval_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(shots), int(precision), int(circuit))
+
+
+def _u32(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+    return a, a.ctypes.data_as(_U32P)
+
+
+def _out_ptr(out):
+    """(pointer, on_device) for a numpy array or a torch tensor."""
+    if isinstance(out, np.ndarray):
+        return ctypes.c_void_p(out.ctypes.data), 0
+    return ctypes.c_void_p(out.data_ptr()), 1 if out.is_cuda else 0
+
+
+def ccut_marginal(plan, ctx, eo: ccut_eval_opts, qubits, out) -> None:
+    q, qp = _u32(qubits)
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_marginal(plan, ctypes.byref(eo), qp, len(q), p, dev), ctx)
+
+
+def ccut_zexpect(plan, ctx, eo: ccut_eval_opts, masks: np.ndarray, out) -> None:
+    m = np.ascontiguousarray(masks, dtype=np.uint64)
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_zexpect(plan, ctypes.byref(eo), m.ctypes.data_as(_U64P), m.shape[0], p, dev), ctx)
+
+
+def ccut_shot_records(plan, ctx, eo, qubits, fragment, v_begin, v_end, out) -> None:
+    q, qp = _u32(qubits)
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_shot_records(plan, ctypes.byref(eo), qp, len(q), fragment, v_begin, v_end, p, dev), ctx)
+
+
+def ccut_variant_tables(plan, ctx, eo, qubits, fragment, out) -> None:
+    q, qp = _u32(qubits)
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_variant_tables(plan, ctypes.byref(eo), qp, len(q), fragment, p, dev), ctx)
+
+
+def ccut_fragment_tensor(plan, ctx, eo, qubits, fragment, out) -> None:
+    q, qp = _u32(qubits)
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_fragment_tensor(plan, ctypes.byref(eo), qp, len(q), fragment, p, dev), ctx)
+
+
+def ccut_request_info(plan, qubits, fragment):
+    q, qp = _u32(qubits)
+    nm, nr = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().ccut_request_info(plan, qp, len(q), fragment, ctypes.byref(nm), ctypes.byref(nr)), None)
+    return nm.value, nr.value
+
+
+def ccut_timing_enable(ctx, on: bool) -> None:
+    _check(lib().ccut_timing_enable(ctx, 1 if on else 0), ctx)
+
+
+def ccut_timing_reset(ctx) -> None:
+    _check(lib().ccut_timing_reset(ctx), ctx)
+
+
+def ccut_timing_read(ctx, kid: int):
+    n, ms = ctypes.c_uint64(), ctypes.c_double()
+    _check(lib().ccut_timing_read(ctx, kid, ctypes.byref(n), ctypes.byref(ms)), ctx)
+    return n.value, ms.value
+
+
+def ccut_kernel_name(kid: int) -> str:
+    return lib().ccut_kernel_name(kid).decode()
+
+
+# ----------------------------------------------------------- conveniences
+
+class Context:
+    """A library context on one device.  ``device=None`` uses torch's
+    current device, stream and caching allocator; ``device=-1`` makes a
+    host-only context (planning and validation only)."""
+
+    def __init__(self, device: Optional[int] = None, *, max_nc_qubits: int = 0, max_cuts: int = 0,
+                 use_torch: bool = True):
+        self._keep = []
+        opts = ccut_opts()
+        opts.max_nc_qubits = max_nc_qubits
+        opts.max_cuts = max_cuts
+        if device is not None and device < 0:
+            opts.device = -1
+        else:
+            import torch
+            dev = torch.cuda.current_device() if device is None else int(device)
+            opts.device = dev
+            if use_torch:
+                stream = torch.cuda.current_stream(dev)
+                opts.hip_stream = ctypes.c_void_p(stream.cuda_stream)
+
+                def _alloc(size, user, _dev=dev, _s=stream):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(size, _dev, _s)
+                    except Exception:
+                        return None
+
+                def _free(ptr, user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+                self._keep += [a, f]
+                opts.alloc, opts.free = a, f
+        self.device = opts.device
+        self.handle = ccut_ctx_create(opts)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ccut_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self, on: bool = True):
+        ccut_timing_enable(self.handle, on)
+
+    def timing_reset(self):
+        ccut_timing_reset(self.handle)
+
+    def kernel_times(self):
+        """{kernel name: (launches, total ms)} since the last reset."""
+        return {KERNELS[k]: ccut_timing_read(self.handle, k) for k in range(len(KERNELS))}
+
+
+class Plan:
+    """A planned circuit + cut list (fragments and variants fixed)."""
+
+    def __init__(self, ctx: Context, n: int, ops: Sequence, cuts: Sequence):
+        self.ctx = ctx
+        self.n = n
+        self.handle = ccut_plan_create(ctx.handle, n, ops, cuts)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ccut_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        return ccut_plan_info(self.handle)
+
+    def fragments(self):
+        nf = self.info()[0]
+        out = []
+        for f in range(nf):
+            m, cl, na, nv = ccut_fragment_info(self.handle, f)
+            out.append(dict(m=m, clifford=cl, n_variants=nv, segments=ccut_fragment_segments(self.handle, f),
+                            axes=ccut_fragment_axes(self.handle, f)))
+        return out
+
+    def marginal(self, qubits, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, out=None):
+        eo = _eval_opts(shots, seed, precision, circuit)
+        if out is None:
+            out = np.zeros(1 << len(qubits), dtype=np.float64)
+        ccut_marginal(self.handle, self.ctx.handle, eo, qubits, out)
+        return out
+
+    def zexpect(self, masks, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, out=None):
+        masks = np.asarray(masks, dtype=np.uint64)
+        if masks.ndim == 1:
+            masks = masks[:, None]
+        if out is None:
+            out = np.zeros(masks.shape[0], dtype=np.float64)
+        ccut_zexpect(self.handle, self.ctx.handle, _eval_opts(shots, seed, precision, circuit), masks, out)
+        return out
+
+    def shot_records(self, qubits, fragment, v_begin, v_end, *, shots, seed=0, circuit=0):
+        out = np.zeros((v_end - v_begin) * shots, dtype=np.uint64)
+        ccut_shot_records(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits, fragment,
+                          v_begin, v_end, out)
+        return out.reshape(v_end - v_begin, shots)
+
+    def variant_tables(self, qubits, fragment, *, shots=0, seed=0, circuit=0):
+        nm, _ = ccut_request_info(self.handle, qubits, fragment)
+        nv = ccut_fragment_info(self.handle, fragment)[3]
+        out = np.zeros(nv << nm, dtype=np.float64)
+        ccut_variant_tables(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits, fragment,
+                            out)
+        return out.reshape(nv, 1 << nm)
+
+    def fragment_tensor(self, qubits, fragment, *, shots=0, seed=0, circuit=0):
+        _, nr = ccut_request_info(self.handle, qubits, fragment)
+        na = ccut_fragment_info(self.handle, fragment)[2]
+        out = np.zeros((4 ** na) << nr, dtype=np.float64)
+        ccut_fragment_tensor(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits,
+                             fragment, out)
+        return out.reshape(4 ** na, 1 << nr)

@@ -1,0 +1,128 @@
+// Pauli-basis transform of fragment variant data, and the recombination
+// sum over cut terms (the contraction of the paper's Sec. V-C, one tensor
+// per fragment and one index per cut).
+//
+// Transform, per cut axis (wire-cutting identity
+// rho = 1/2 sum_P Tr(P rho) P):
+//   quantum input, prepared in (0, 1, +, +i):
+//     I = p0 + p1, X = 2 p+ - p0 - p1, Y = 2 p+i - p0 - p1, Z = p0 - p1
+//   quantum output, measured in basis (X, Y, Z) with outcome bit o:
+//     I = Z0 + Z1, X = X0 - X1, Y = Y0 - Y1, Z = Z0 - Z1
+// applied one axis at a time; the fragment tensor ends as T_f[p_f][b_f].
+#include "common.hpp"
+
+namespace ccut {
+
+namespace {
+
+inline unsigned blocks_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Layout of the data before the pass: flat = ((o * rin + d) * R + r) * X + x.
+// mode 0: input axis (rin = 4); mode 1/2: output axis (rin = 3), its
+// outcome (mode 1) or parity-selection (mode 2) bit sits in x at stride lo.
+__global__ void transform_pass_kernel(const double *__restrict__ in, double *__restrict__ out,
+                                      uint64_t outer, uint64_t R, uint64_t Xin, uint64_t lo, int mode) {
+  const uint64_t Xout = mode == 0 ? Xin : Xin / 2;
+  const uint64_t total = outer * 4 * R * Xout;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t x = i % Xout;
+  const uint64_t r = (i / Xout) % R;
+  const uint32_t P = (uint32_t)((i / (Xout * R)) % 4);
+  const uint64_t o = i / (Xout * R * 4);
+  double acc;
+  if (mode == 0) {
+    auto at = [&](uint32_t s) { return in[((o * 4 + s) * R + r) * Xin + x]; };
+    const double p0 = at(0), p1 = at(1);
+    switch (P) {
+      case 0: acc = p0 + p1; break;
+      case 1: acc = 2.0 * at(2) - p0 - p1; break;
+      case 2: acc = 2.0 * at(3) - p0 - p1; break;
+      default: acc = p0 - p1; break;
+    }
+  } else {
+    const uint64_t xhi = x / lo, xlo = x % lo;
+    const uint64_t x0 = (xhi * 2) * lo + xlo, x1 = x0 + lo;
+    const uint32_t basis = (P == 1) ? 0u : (P == 2) ? 1u : 2u;  // X, Y, Z(for I and Z)
+    const double *src = in + ((o * 3 + basis) * R + r) * Xin;
+    if (mode == 1)
+      acc = (P == 0) ? src[x0] + src[x1] : src[x0] - src[x1];
+    else
+      acc = (P == 0) ? src[x0] : src[x1];
+  }
+  out[i] = acc;
+}
+
+// R[b] = 2^-k sum_P prod_f T_f[p_f(P)][b_f(b)], P ascending, fragments in order.
+__global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
+                                      double *__restrict__ outp) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (1ull << nq)) return;
+  const uint32_t nf = A->n_frags, k = A->k;
+  uint32_t row[kMaxFrags];
+  for (uint32_t f = 0; f < nf; ++f) {
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < A->f[f].n_req; ++i) r |= (uint32_t)((b >> A->f[f].req_user[i]) & 1ull) << i;
+    row[f] = r;
+  }
+  const uint64_t nterms = 1ull << (2 * k);
+  double acc = 0.0;
+  for (uint64_t P = 0; P < nterms; ++P) {
+    double term = 1.0;
+    for (uint32_t f = 0; f < nf; ++f) {
+      const RecombFrag &F = A->f[f];
+      uint32_t p = 0;
+      for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+      term *= F.T[(uint64_t)p * F.rows + row[f]];
+    }
+    acc += term;
+  }
+  outp[b] = ldexp(acc, -(int)k);
+}
+
+// <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s]
+__global__ void zrecombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings,
+                                       double *__restrict__ outp) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_strings) return;
+  const uint32_t nf = A->n_frags, k = A->k;
+  const uint64_t nterms = 1ull << (2 * k);
+  double acc = 0.0;
+  for (uint64_t P = 0; P < nterms; ++P) {
+    double term = 1.0;
+    for (uint32_t f = 0; f < nf; ++f) {
+      const RecombFrag &F = A->f[f];
+      uint32_t p = 0;
+      for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+      term *= F.T[(uint64_t)p * F.rows + s];
+    }
+    acc += term;
+  }
+  outp[s] = ldexp(acc, -(int)k);
+}
+
+}  // namespace
+
+hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, uint64_t R, uint64_t Xin,
+                                 uint64_t lo, int mode, hipStream_t s) {
+  const uint64_t Xout = mode == 0 ? Xin : Xin / 2;
+  const uint64_t total = outer * 4 * R * Xout;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(transform_pass_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, in, out, outer, R,
+                     Xin, lo, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *out, hipStream_t s) {
+  const uint64_t n = 1ull << nq;
+  hipLaunchKernelGGL(recombine_fp64_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, d_args, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zrecombine_fp64(const RecombArgs *d_args, uint32_t n_strings, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(zrecombine_fp64_kernel, dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args,
+                     n_strings, out);
+  return hipGetLastError();
+}
+
+}  // namespace ccut

@@ -1,0 +1,304 @@
+// Shots, exact tables and Z-parity statistics of Clifford variants from
+// their affine sample models (x0, randmask, Gcol): shot s of variant vid
+// draws u = the Philox bits of its measurement indices and outputs
+// x = x0 ^ (xor of Gcol[a] over random a with u_a = 1).
+//
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of
+// (c0..c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
+// key bumped by the Weyl constants between rounds.  One call yields four
+// 32-bit words: four consecutive shots x 32 measurement indices.
+#include "common.hpp"
+
+namespace ccut {
+
+namespace {
+
+struct U4 {
+  uint32_t w[4];
+};
+
+__device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return U4{{c0, c1, c2, c3}};
+}
+
+// Shot-bit words of one quad (4 shots): bits of measurement indices 0..31
+// in lo[r], 32..63 in hi[r].
+__device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, bool wide,
+                                 uint64_t u[4]) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const U4 lo = philox10(0u, (uint32_t)quad, (uint32_t)vid, (uint32_t)(vid >> 32), k0, k1);
+  if (wide) {
+    const U4 hi = philox10(1u, (uint32_t)quad, (uint32_t)vid, (uint32_t)(vid >> 32), k0, k1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = (uint64_t)lo.w[r] | ((uint64_t)hi.w[r] << 32);
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = lo.w[r];
+  }
+}
+
+constexpr int kSampleBlock = 256;
+constexpr uint32_t kLdsHistBits = 14;  // up to 2^14 u32 bins = 64 KiB per workgroup
+
+// grid: (nblk_x, nv).  Each thread handles `qpt` quads; quads are
+// interleaved across the workgroup so record writes are contiguous.
+__global__ __launch_bounds__(kSampleBlock) void sample_kernel(
+    const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
+    uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
+  extern __shared__ uint32_t s_hist[];
+  __shared__ uint64_t s_model[2 + kMaxMeas];
+  const uint32_t mw = model_words(n_meas);
+  const uint64_t v = blockIdx.y;
+  const uint64_t *md = models + v * mw;
+  for (uint32_t i = threadIdx.x; i < mw; i += kSampleBlock) s_model[i] = md[i];
+  const uint32_t bins = 1u << n_meas;
+  const bool lds_hist = partial != nullptr && n_meas <= kLdsHistBits;
+  if (lds_hist)
+    for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) s_hist[i] = 0;
+  __syncthreads();
+  const uint64_t x0 = s_model[0], rmask = s_model[1];
+  const uint64_t vid = vid0 + v;
+  const bool wide = n_meas > 32;
+  const uint64_t nquads = (shots + 3) >> 2;
+  for (uint32_t q = 0; q < qpt; ++q) {
+    const uint64_t quad = ((uint64_t)blockIdx.x * qpt + q) * kSampleBlock + threadIdx.x;
+    if (quad >= nquads) break;
+    uint64_t u[4];
+    quad_bits(quad, vid, seed, wide, u);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint64_t s = quad * 4 + r;
+      if (s >= shots) break;
+      const uint64_t ur = u[r] & rmask;
+      uint64_t x = x0;
+      for (uint64_t mm = rmask; mm; mm &= mm - 1) {
+        const int a = __ffsll((unsigned long long)mm) - 1;
+        x ^= s_model[2 + a] & (0ull - ((ur >> a) & 1ull));
+      }
+      if (records) records[v * shots + s] = x;
+      if (lds_hist)
+        atomicAdd(&s_hist[x], 1u);
+      else if (partial)
+        atomicAdd(&partial[v * (uint64_t)bins + x], 1u);
+    }
+  }
+  if (lds_hist) {
+    __syncthreads();
+    uint32_t *dst = partial + (v * gridDim.x + blockIdx.x) * (uint64_t)bins;
+    for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) dst[i] = s_hist[i];
+  }
+}
+
+// dist[v][b] = (sum over shot blocks of counts) / shots
+__global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_t nv, uint32_t nblk,
+                                   uint32_t bins, uint64_t shots, double *__restrict__ dist) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * bins) return;
+  const uint64_t v = i / bins, b = i % bins;
+  uint64_t c = 0;
+  for (uint32_t k = 0; k < nblk; ++k) c += partial[(v * nblk + k) * (uint64_t)bins + b];
+  dist[i] = (double)c / (double)shots;
+}
+
+// Exact table: x is an outcome iff y = x ^ x0 equals the xor of the G
+// columns of the random measurements a with y_a = 1 (column a of G has
+// bit a set and otherwise only bits of later deterministic measurements);
+// every outcome has probability 2^-R.
+__global__ void exact_kernel(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t nv,
+                             double *__restrict__ dist) {
+  const uint64_t bins = 1ull << n_meas;
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * bins) return;
+  const uint64_t v = i >> n_meas, x = i & (bins - 1);
+  const uint64_t *md = models + v * model_words(n_meas);
+  const uint64_t rmask = md[1];
+  const uint64_t y = x ^ md[0];
+  uint64_t e = 0;
+  for (uint64_t mm = rmask; mm; mm &= mm - 1) {
+    const int a = __ffsll((unsigned long long)mm) - 1;
+    if ((y >> a) & 1ull) e ^= md[2 + a];
+  }
+  const int R = __popcll(rmask);
+  dist[i] = (e == y) ? ldexp(1.0, -R) : 0.0;
+}
+
+// For mask z over the measured set: z.x = z.x0 ^ g.u with g_a = z.Gcol[a].
+__device__ inline void parity_form(const uint64_t *md, uint32_t n_meas, uint64_t z, uint32_t &c,
+                                   uint64_t &g) {
+  c = __popcll(z & md[0]) & 1u;
+  g = 0;
+  for (uint32_t a = 0; a < n_meas; ++a) g |= (uint64_t)(__popcll(z & md[2 + a]) & 1) << a;
+}
+
+// Exact <(-1)^{z.x}> = (-1)^c if g = 0 else 0 (Clifford expectations are
+// -1, 0 or +1).  grid over (v, ext mask).
+__global__ void parity_exact_kernel(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t nv,
+                                    const uint64_t *__restrict__ ext, uint32_t n_ext,
+                                    double *__restrict__ E) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * n_ext) return;
+  const uint64_t v = i / n_ext;
+  const uint32_t s = (uint32_t)(i % n_ext);
+  uint32_t c;
+  uint64_t g;
+  parity_form(models + v * model_words(n_meas), n_meas, ext[s], c, g);
+  E[i] = g ? 0.0 : (c ? -1.0 : 1.0);
+}
+
+constexpr int kParityBlock = 256;
+constexpr int kParityQuads = 16;  // 64 shots per thread
+
+// Odd-parity counts per (variant, ext mask) over all shots.  grid (nblk_x, nv).
+__global__ __launch_bounds__(kParityBlock) void parity_sampled_kernel(
+    const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
+    uint64_t vid0, const uint64_t *__restrict__ ext, uint32_t n_ext,
+    uint32_t *__restrict__ odd_counts) {
+  extern __shared__ uint64_t s_dyn[];
+  uint64_t *s_g = s_dyn;                                       // [n_ext]
+  uint32_t *s_c = reinterpret_cast<uint32_t *>(s_g + n_ext);    // [n_ext]
+  uint32_t *s_cnt = s_c + n_ext;                                // [n_ext]
+  const uint64_t v = blockIdx.y;
+  const uint64_t *md = models + v * model_words(n_meas);
+  for (uint32_t s = threadIdx.x; s < n_ext; s += kParityBlock) {
+    uint32_t c;
+    uint64_t g;
+    parity_form(md, n_meas, ext[s], c, g);
+    s_g[s] = g;
+    s_c[s] = c;
+    s_cnt[s] = 0;
+  }
+  __syncthreads();
+  const uint64_t vid = vid0 + v;
+  const bool wide = n_meas > 32;
+  const uint64_t nquads = (shots + 3) >> 2;
+  uint64_t u[4 * kParityQuads];
+  uint32_t valid = 0;
+#pragma unroll
+  for (int q = 0; q < kParityQuads; ++q) {
+    const uint64_t quad = ((uint64_t)blockIdx.x * kParityQuads + q) * kParityBlock + threadIdx.x;
+    uint64_t w[4] = {0, 0, 0, 0};
+    if (quad < nquads) quad_bits(quad, vid, seed, wide, w);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool ok = quad < nquads && quad * 4 + r < shots;
+      u[q * 4 + r] = ok ? w[r] : 0ull;
+      valid += ok ? 1u : 0u;
+    }
+  }
+  for (uint32_t s = 0; s < n_ext; ++s) {
+    const uint64_t g = s_g[s];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4 * kParityQuads; ++k) cnt += __popcll(g & u[k]) & 1u;
+    uint32_t odd = s_c[s] ? valid - cnt : cnt;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) odd += __shfl_xor(odd, off);
+    if ((threadIdx.x & 63) == 0 && odd) atomicAdd(&s_cnt[s], odd);
+  }
+  __syncthreads();
+  for (uint32_t s = threadIdx.x; s < n_ext; s += kParityBlock)
+    if (s_cnt[s]) atomicAdd(&odd_counts[v * n_ext + s], s_cnt[s]);
+}
+
+__global__ void parity_finish_kernel(const uint32_t *__restrict__ odd, uint64_t n, uint64_t shots,
+                                     double *__restrict__ E) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  E[i] = ((double)shots - 2.0 * (double)odd[i]) / (double)shots;
+}
+
+// <(-1)^{z.x}> from an outcome distribution over n_meas bits, summed in
+// ascending x.  grid over (v, ext mask).
+__global__ void dist_parity_kernel(const double *__restrict__ dist, uint32_t n_meas, uint64_t nv,
+                                   const uint64_t *__restrict__ ext, uint32_t n_ext,
+                                   double *__restrict__ E) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * n_ext) return;
+  const uint64_t v = i / n_ext;
+  const uint64_t z = ext[i % n_ext];
+  const uint64_t bins = 1ull << n_meas;
+  const double *p = dist + v * bins;
+  double acc = 0.0;
+  for (uint64_t x = 0; x < bins; ++x) acc += (__popcll(x & z) & 1) ? -p[x] : p[x];
+  E[i] = acc;
+}
+
+inline unsigned blocks_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
+                              uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
+                              uint32_t qpt, uint64_t *records, hipStream_t s) {
+  if (n_meas > (uint32_t)kMaxMeas || nv == 0 || nv > 65535) return hipErrorInvalidValue;
+  const size_t lds = (partial && n_meas <= kLdsHistBits) ? (size_t(1) << n_meas) * 4 : 0;
+  hipLaunchKernelGGL(sample_kernel, dim3(nblk_x, (unsigned)nv), dim3(kSampleBlock), lds, s, models,
+                     n_meas, shots, seed, vid0, partial, qpt, records);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nblk, uint32_t bins,
+                              uint64_t shots, double *dist, hipStream_t s) {
+  const uint64_t n = nv * bins;
+  hipLaunchKernelGGL(hist_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, partial, nv, nblk,
+                     bins, shots, dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,
+                               hipStream_t s) {
+  if (n_meas > (uint32_t)kMaxTableBits) return hipErrorInvalidValue;
+  const uint64_t n = nv << n_meas;
+  hipLaunchKernelGGL(exact_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, models, n_meas, nv, dist);
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
+                               const uint64_t *ext, uint32_t n_ext, double *E, hipStream_t s) {
+  const uint64_t n = nv * n_ext;
+  hipLaunchKernelGGL(parity_exact_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, models, n_meas, nv,
+                     ext, n_ext, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
+                                 uint64_t seed, uint64_t vid0, const uint64_t *ext, uint32_t n_ext,
+                                 uint32_t *odd_counts, hipStream_t s) {
+  if (nv == 0 || nv > 65535) return hipErrorInvalidValue;
+  const uint64_t per_block = (uint64_t)kParityBlock * kParityQuads * 4;
+  const unsigned nbx = blocks_for(shots, (unsigned)per_block);
+  const size_t lds = (size_t)n_ext * 16;
+  hipLaunchKernelGGL(parity_sampled_kernel, dim3(nbx, (unsigned)nv), dim3(kParityBlock), lds, s, models,
+                     n_meas, shots, seed, vid0, ext, n_ext, odd_counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_finish(const uint32_t *odd, uint64_t n, uint64_t shots, double *E, hipStream_t s) {
+  hipLaunchKernelGGL(parity_finish_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, odd, n, shots, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv, const uint64_t *ext,
+                              uint32_t n_ext, double *E, hipStream_t s) {
+  const uint64_t n = nv * n_ext;
+  hipLaunchKernelGGL(dist_parity_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dist, n_meas, nv, ext,
+                     n_ext, E);
+  return hipGetLastError();
+}
+
+}  // namespace ccut
