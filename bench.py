@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--workload", choices=["mid", "batching", "precision"], default="mid",
+                    help="mid (default): the 32-qubit, 2-cut workload; batching: 256 uneven circuits in one "
+                         "graph-captured batch; precision: the 400-qubit, 6-cut workload with FP32-MFMA recombination")
     return ap.parse_args()
 
 
@@ -70,6 +73,10 @@ def main():
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batching":
+        return bench_batching(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     import numpy as np
     import torch
 
@@ -148,6 +155,109 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bench_batching(args):
+    """256 circuits (width 20-200, depth 20-60, 1-4 cuts), 1e4 shots per
+    variant, 16-qubit marginals; one step = one replay of the captured batch."""
+    import torch
+
+    import paper_2303_10788_amd as cc
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    shots = min(args.shots, 10_000)
+    ws = W.batching(256, shots=shots)
+    ctx = cc.Context(0)
+    plans = [cc.Plan(ctx, w.n, w.ops, w.cuts) for w in ws]
+    t0 = time.perf_counter()
+    batch = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=2000, use_graph=True)
+    t_create = time.perf_counter() - t0
+    info = batch.info()
+    outs = [torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda") for w in ws]
+    dt = _timed(lambda: batch.run(outs), args.steps, args.warmup)
+    n_var = sum(f["n_variants"] for p in plans for f in p.fragments() if f["clifford"])
+    shots_per_step = n_var * shots
+    line = {
+        "metric": METRIC, "value": shots_per_step / (dt / args.steps), "unit": "shots/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batching: 256 near-Clifford circuits, width 20-200, depth 20-60, 1-6 T, 1-4 cuts, "
+                               "1e4 shots per variant, 16-qubit marginals, one graph-captured batch",
+                   "clifford_variants": n_var, "shots_per_step": shots_per_step},
+        "batch": dict(info, create_s=t_create),
+        "roofline": {"bound": "alu", "kernel": "tableau_batch_kernel", "achieved": None, "peak": PEAK_INT32_OPS / 1e9,
+                     "unit": "Gop/s", "frac": None, "traffic": None, "avg_launch_us": info["tableau_ms"] * 1e3},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_precision(args):
+    """400 qubits, 6 cuts (4096 terms): exact Clifford tensors, 16-qubit
+    marginal and 64 Z strings recombined with FP32 MFMA + FP64 sums; the
+    per-result error against the FP64 contraction is reported."""
+    import numpy as np
+    import torch
+
+    import paper_2303_10788_amd as cc
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.precision()
+    ctx = cc.Context(0)
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    masks = w.zmask_words()
+    out_m = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
+    out_z = torch.empty(masks.shape[0], dtype=torch.float64, device="cuda")
+    f32 = cc.CCUT_FP32_MFMA_FP64SUM
+
+    def step():
+        plan.marginal(w.qubits, precision=f32, out=out_m)
+        plan.zexpect(masks, precision=f32, out=out_z)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    dt = _timed(step, args.steps, 0)
+    times = ctx.kernel_times()
+    ctx.timing(False)
+    r64 = plan.marginal(w.qubits)
+    z64 = plan.zexpect(masks)
+    err_m = float(np.abs(out_m.cpu().numpy() - r64).max())
+    err_z = float(np.abs(out_z.cpu().numpy() - z64).max())
+    K = 4 ** len(w.cuts)
+    M, N = 1 << 6, 1 << 10
+    launches, gemm_ms = times["recombine_fp64_kernel"]
+    per_launch_s = gemm_ms / max(launches, 1) / 1e3
+    flops = 2.0 * M * N * K
+    terms = K * ((1 << len(w.qubits)) + masks.shape[0])
+    line = {
+        "metric": METRIC, "value": terms / (dt / args.steps), "unit": "terms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32-mfma/f64", "data": "synthetic",
+        "config": {"workload": "precision: 400-qubit nearest-neighbour ladder, 30 layers, 8 T in two 6-qubit blocks, "
+                               "6 cuts (4096 terms), exact Clifford tensors, 16-qubit marginal + 64 Z strings"},
+        "per_result_error_vs_fp64": {"marginal_max_abs": err_m, "zstring_max_abs": err_z},
+        "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
+        "roofline": {"bound": "mfma", "kernel": "gemm_kernel<fp32> (+reduce)", "achieved": flops / per_launch_s / 1e12,
+                     "peak": 157.3, "unit": "TFLOP/s", "frac": flops / per_launch_s / 157.3e12, "traffic": None,
+                     "avg_launch_us": per_launch_s * 1e6},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -103,11 +103,24 @@ typedef struct {
 
 enum { CCUT_FP64 = 0, CCUT_FP32_MFMA_FP64SUM = 1 };
 
+/* How exact-mode Clifford fragments are evaluated (sampled mode always
+ * evaluates every variant on the tableau):
+ *  CCUT_METHOD_AUTO / CCUT_METHOD_HEISENBERG: the Pauli-basis tensor is read
+ *    off directly in the Heisenberg picture (the Clifford-specific
+ *    optimisation of Sec. IX): the requested Z's and the quantum outputs'
+ *    X, Z are carried back through the fragment once, no variant is
+ *    enumerated;
+ *  CCUT_METHOD_VARIANTS: every variant is evaluated on the tableau, its
+ *    exact dyadic outcome table formed, then rewritten in the Pauli basis. */
+enum { CCUT_METHOD_AUTO = 0, CCUT_METHOD_VARIANTS = 1, CCUT_METHOD_HEISENBERG = 2 };
+
 typedef struct {
   uint64_t seed;              /* Philox key */
   uint64_t shots_per_variant; /* 0 = exact ("strong simulation", Sec. V-C) Clifford tables */
   int32_t precision;          /* CCUT_FP64, or CCUT_FP32_MFMA_FP64SUM for the recombination */
   uint32_t circuit;           /* circuit index in variant ids (batch position) */
+  uint32_t method;            /* CCUT_METHOD_*, exact mode only */
+  uint32_t reserved;          /* must be 0 */
 } ccut_eval_opts;
 
 /* ---------------------------------------------------------------- context */
@@ -205,6 +218,34 @@ ccut_status ccut_fragment_tensor(ccut_plan *plan, const ccut_eval_opts *eo, cons
 ccut_status ccut_request_info(ccut_plan *plan, const uint32_t *qubits, uint32_t nq,
                               uint32_t fragment, uint32_t *n_measured, uint32_t *n_requested);
 
+/* ---------------------------------------------------------------- batches */
+
+/* Many circuits at once (each plan is one circuit; its variant ids use its
+ * position i in the batch as the circuit index, eo->circuit is ignored).
+ * All Clifford fragment variants of all plans run in one persistent,
+ * work-queue tableau launch whose workgroup size and workgroups per CU are
+ * picked by timing the candidates on this batch at creation; the remaining
+ * per-plan steps follow, and with use_graph != 0 the whole evaluation is
+ * captured once as a HIP graph and replayed by ccut_batch_run.
+ * qubits[i] / nq[i] are each plan's marginal request (nq[i] <= 24).  The
+ * batch owns its device memory; plans must outlive it.  Creating a batch
+ * runs one full evaluation.  Errors: as ccut_marginal. */
+typedef struct ccut_batch ccut_batch;
+ccut_status ccut_batch_create(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
+                              const uint32_t *const *qubits, const uint32_t *nq, int use_graph, ccut_batch **out);
+/* Evaluate the batch again (graph replay when captured); outs[i] receives
+ * plan i's 2^nq[i] marginal, on the device if outs_on_device. */
+ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_device);
+/* Work items of the persistent launch, the chosen workgroup size, grid,
+ * register-tableau use, whether a graph was captured, and the best tuned
+ * time of the tableau launch in ms. */
+ccut_status ccut_batch_info(const ccut_batch *b, uint64_t *n_items, uint32_t *block, uint32_t *grid,
+                            int32_t *use_reg, int32_t *graphed, double *tableau_ms);
+void ccut_batch_destroy(ccut_batch *b);
+/* One-shot convenience: create (no graph), run into host buffers, destroy. */
+ccut_status ccut_run_batch(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
+                           const uint32_t *const *qubits, const uint32_t *nq, double *const *outs);
+
 /* ---------------------------------------------------------------- timing */
 
 /* Kernel timing with HIP events recorded around every launch on the
@@ -221,7 +262,8 @@ enum {
   CCUT_K_TRANSFORM = 6,
   CCUT_K_RECOMBINE = 7,
   CCUT_K_ZRECOMBINE = 8,
-  CCUT_K_COUNT = 9
+  CCUT_K_HEISENBERG = 9,
+  CCUT_K_COUNT = 10
 };
 ccut_status ccut_timing_enable(ccut_ctx *ctx, int enable);
 ccut_status ccut_timing_reset(ccut_ctx *ctx);

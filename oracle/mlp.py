@@ -1,0 +1,133 @@
+"""Learned importance proposal over cut terms: fp64 MLP with hand-derived
+backprop, the proposal q, term sampling and the importance-sampling
+estimator of the recombination sum (test infrastructure).
+
+The recombination sum (Sec. V-C) is R[b] = sum_P w_P(b) with
+w_P(b) = 2^-k prod_f T_f[b_f; P|f] over the 4^k cut terms (Sec. III-B: the
+cost grows as 4^k).  A proposal q over terms gives the unbiased estimator
+    R_hat[b] = (1/N) sum_j w_{P_j}(b) / q(P_j),   P_j ~ q.
+Readings (the paper has no learned part):
+* the network regresses y(P) = log(||w_P||_2 + 2^-60) with mean squared
+  error; q = (1 - eps) softmax(y_hat) + eps / 4^k (defensive mixture,
+  eps = 0.05);
+* the network is F -> H -> H -> H -> 1 with ReLU activations;
+* term sampling: integer weights W_P = floor(q_P 2^40), inclusive prefix
+  sums C_P; draw j takes u = (o1 2^32 + o0) mod C_last from
+  philox(ctr = (j, 0, lo32(cid), hi32(cid)), key = (lo32(seed) ^ 0x7E570001,
+  hi32(seed))) and picks the smallest P with C_P > u (the modulo bias is at
+  most C_last / 2^64).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .philox import philox4x32_10
+
+EPS = 0.05
+LABEL_FLOOR = 2.0 ** -60
+
+
+def init_params(F: int, H: int, seed: int):
+    """He-style uniform initialisation; returns a list of (W, b) with W of
+    shape (out, in)."""
+    rng = np.random.default_rng([seed, 31])
+    dims = [F, H, H, H, 1]
+    params = []
+    for i in range(4):
+        fan_in = dims[i]
+        lim = np.sqrt(6.0 / fan_in) if i < 3 else np.sqrt(3.0 / fan_in)
+        W = rng.uniform(-lim, lim, size=(dims[i + 1], fan_in))
+        b = np.zeros(dims[i + 1])
+        params.append((W, b))
+    return params
+
+
+def forward(params, X):
+    """Returns the prediction y_hat (shape (B,)) and the activations."""
+    acts = [X]
+    h = X
+    for i, (W, b) in enumerate(params):
+        z = h @ W.T + b
+        h = np.maximum(z, 0.0) if i < 3 else z
+        acts.append(h)
+    return h[:, 0], acts
+
+
+def loss_and_grads(params, X, y):
+    """Mean squared error and its gradients, by hand:
+    L = mean (y_hat - y)^2;  dL/dy_hat = 2 (y_hat - y) / B;
+    for a layer z = h W^T + b:  dW = dz^T h,  db = sum dz,  dh = dz W;
+    through a ReLU, dz = dh * [z > 0] (and [h > 0] is the same test)."""
+    y_hat, acts = forward(params, X)
+    B = X.shape[0]
+    r = y_hat - y
+    L = float(np.mean(r * r))
+    dz = (2.0 / B) * r[:, None]
+    grads = [None] * 4
+    for i in range(3, -1, -1):
+        W, b = params[i]
+        h_in = acts[i]
+        grads[i] = (dz.T @ h_in, dz.sum(axis=0))
+        if i > 0:
+            dh = dz @ W
+            dz = dh * (acts[i] > 0.0)
+    return L, grads
+
+
+def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba) on every tensor; state holds (m, v, t)."""
+    m, v, t = state
+    t += 1
+    new = []
+    for i, ((W, b), (gW, gb)) in enumerate(zip(params, grads)):
+        out = []
+        for j, (p, g) in enumerate(((W, gW), (b, gb))):
+            m[i][j] = b1 * m[i][j] + (1 - b1) * g
+            v[i][j] = b2 * v[i][j] + (1 - b2) * g * g
+            mh = m[i][j] / (1 - b1 ** t)
+            vh = v[i][j] / (1 - b2 ** t)
+            out.append(p - lr * mh / (np.sqrt(vh) + eps))
+        new.append(tuple(out))
+    return new, (m, v, t)
+
+
+def adam_state(params):
+    m = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+    v = [[np.zeros_like(W), np.zeros_like(b)] for W, b in params]
+    return (m, v, 0)
+
+
+# ------------------------------------------------------------ proposal
+
+def proposal(logits, eps=EPS):
+    """q = (1 - eps) softmax(logits) + eps / K."""
+    z = logits - logits.max()
+    e = np.exp(z)
+    return (1.0 - eps) * e / e.sum() + eps / logits.size
+
+
+def integer_cdf(q):
+    W = np.floor(q * 2.0 ** 40).astype(np.uint64)
+    return np.cumsum(W, dtype=np.uint64)
+
+
+def sample_terms(cdf, n, seed, cid):
+    """n term indices drawn by inverse CDF from the Philox stream above."""
+    total = int(cdf[-1])
+    key = ((seed & 0xFFFFFFFF) ^ 0x7E570001, (seed >> 32) & 0xFFFFFFFF)
+    out = np.empty(n, dtype=np.int64)
+    for j in range(n):
+        o = philox4x32_10((j, 0, cid & 0xFFFFFFFF, (cid >> 32) & 0xFFFFFFFF), key)
+        u = ((o[1] << 32) | o[0]) % total
+        out[j] = int(np.searchsorted(cdf, np.uint64(u), side="right"))
+    return out
+
+
+def is_estimate(term_weight, terms, q):
+    """R_hat[b] = (1/N) sum_j w_{P_j}(b) / q(P_j); term_weight(P) returns
+    the vector w_P(b) over all b."""
+    acc = None
+    for P in terms:
+        v = term_weight(int(P)) / q[P]
+        acc = v if acc is None else acc + v
+    return acc / len(terms)

@@ -128,6 +128,40 @@ def z_expectation(xs, zs, ss, support) -> int:
     return -1 if sign else 1
 
 
+def z_expectations(xs, zs, ss, masks, n) -> list:
+    """<Z_support> for many supports at once (each mask an int over qubits
+    0..n-1): one elimination of the Z-type subgroup on all qubits, then for
+    each mask a membership test by reduction against its row echelon form."""
+    C, s = z_constraints(xs, zs, ss, list(range(n)))
+    A = np.concatenate([C.astype(np.uint8), s.astype(np.uint8)[:, None]], axis=1)
+    piv = []
+    r = 0
+    for j in range(n):
+        cand = np.nonzero(A[r:, j])[0]
+        if cand.size == 0:
+            continue
+        i = r + int(cand[0])
+        A[[r, i]] = A[[i, r]]
+        hit = np.nonzero(A[:, j])[0]
+        hit = hit[hit != r]
+        A[hit] ^= A[r]
+        piv.append(j)
+        r += 1
+        if r == A.shape[0]:
+            break
+    out = []
+    for mk in masks:
+        t = np.array([(mk >> q) & 1 for q in range(n)] + [0], dtype=np.uint8)
+        for i, j in enumerate(piv):
+            if t[j]:
+                t ^= A[i]
+        if t[:n].any():
+            out.append(0)
+        else:
+            out.append(-1 if t[n] else 1)
+    return out
+
+
 def pauli_matrix(x_row, z_row, sign) -> np.ndarray:
     """Dense matrix of (-1)^sign * prod_q sigma_q (bit q of the basis index =
     qubit q), for pinning tableau rows against a state vector."""

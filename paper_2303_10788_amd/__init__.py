@@ -24,8 +24,10 @@ GATES = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CZ": 7, "T"
 CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
 CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
 CCUT_FP64, CCUT_FP32_MFMA_FP64SUM = 0, 1
+CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
 KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
-           "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel")
+           "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
+           "heisenberg_kernels")
 STATUS_NAMES = {0: "CCUT_OK", -1: "CCUT_E_INVALID", -2: "CCUT_E_OOM", -3: "CCUT_E_DEVICE",
                 -4: "CCUT_E_NC_TOO_WIDE", -5: "CCUT_E_TOO_MANY_CUTS", -6: "CCUT_E_CANCELLED",
                 -7: "CCUT_E_UNSUPPORTED"}
@@ -52,7 +54,8 @@ class ccut_opts(ctypes.Structure):
 
 class ccut_eval_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("shots_per_variant", ctypes.c_uint64),
-                ("precision", ctypes.c_int32), ("circuit", ctypes.c_uint32)]
+                ("precision", ctypes.c_int32), ("circuit", ctypes.c_uint32), ("method", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class CcutError(RuntimeError):
@@ -90,6 +93,13 @@ SIGNATURES = {
     "ccut_fragment_tensor": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.c_uint32,
                               _P, ctypes.c_int], ctypes.c_int),
     "ccut_request_info": ([_P, _U32P, ctypes.c_uint32, ctypes.c_uint32, _U32P, _U32P], ctypes.c_int),
+    "ccut_batch_create": ([_P, ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(ccut_eval_opts),
+                           ctypes.POINTER(_U32P), _U32P, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
+    "ccut_batch_run": ([_P, ctypes.POINTER(_P), ctypes.c_int], ctypes.c_int),
+    "ccut_batch_info": ([_P, _U64P, _U32P, _U32P, _I32P, _I32P, _DP], ctypes.c_int),
+    "ccut_batch_destroy": ([_P], None),
+    "ccut_run_batch": ([_P, ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(ccut_eval_opts),
+                        ctypes.POINTER(_U32P), _U32P, ctypes.POINTER(_P)], ctypes.c_int),
     "ccut_timing_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "ccut_timing_reset": ([_P], ctypes.c_int),
     "ccut_timing_read": ([_P, ctypes.c_uint32, _U64P, _DP], ctypes.c_int),
@@ -197,8 +207,8 @@ def ccut_fragment_axes(plan, f: int):
     return [(c[j], s[j], l[j]) for j in range(na)]
 
 
-def _eval_opts(shots=0, seed=0, precision=CCUT_FP64, circuit=0):
-    return ccut_eval_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(shots), int(precision), int(circuit))
+def _eval_opts(shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO):
+    return ccut_eval_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(shots), int(precision), int(circuit), int(method), 0)
 
 
 def _u32(a):
@@ -250,6 +260,48 @@ def ccut_request_info(plan, qubits, fragment):
     return nm.value, nr.value
 
 
+def _batch_args(plans, qubits):
+    n = len(plans)
+    ph = (_P * n)(*[p.handle for p in plans])
+    qarrs = [np.ascontiguousarray(np.asarray(q, dtype=np.uint32)) for q in qubits]
+    qp = (_U32P * n)(*[a.ctypes.data_as(_U32P) for a in qarrs])
+    nq = (ctypes.c_uint32 * n)(*[len(q) for q in qubits])
+    return ph, qarrs, qp, nq
+
+
+def ccut_batch_create(ctx, plans, eo, qubits, use_graph=True):
+    ph, keep, qp, nq = _batch_args(plans, qubits)
+    h = _P()
+    _check(lib().ccut_batch_create(ctx, ph, len(plans), ctypes.byref(eo), qp, nq, 1 if use_graph else 0,
+                                   ctypes.byref(h)), ctx)
+    return h
+
+
+def ccut_batch_run(batch, ctx, outs) -> None:
+    ptrs = [_out_ptr(o) for o in outs]
+    arr = (_P * len(outs))(*[p for p, _ in ptrs])
+    _check(lib().ccut_batch_run(batch, arr, ptrs[0][1] if ptrs else 0), ctx)
+
+
+def ccut_batch_info(batch):
+    n, blk, grid, reg, gr, ms = (ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_int32(),
+                                  ctypes.c_int32(), ctypes.c_double())
+    _check(lib().ccut_batch_info(batch, ctypes.byref(n), ctypes.byref(blk), ctypes.byref(grid), ctypes.byref(reg),
+                                 ctypes.byref(gr), ctypes.byref(ms)), None)
+    return dict(n_items=n.value, block=blk.value, grid=grid.value, use_reg=bool(reg.value), graphed=bool(gr.value),
+                tableau_ms=ms.value)
+
+
+def ccut_batch_destroy(batch) -> None:
+    lib().ccut_batch_destroy(batch)
+
+
+def ccut_run_batch(ctx, plans, eo, qubits, outs) -> None:
+    ph, keep, qp, nq = _batch_args(plans, qubits)
+    arr = (_P * len(outs))(*[o.ctypes.data for o in outs])
+    _check(lib().ccut_run_batch(ctx, ph, len(plans), ctypes.byref(eo), qp, nq, arr), ctx)
+
+
 def ccut_timing_enable(ctx, on: bool) -> None:
     _check(lib().ccut_timing_enable(ctx, 1 if on else 0), ctx)
 
@@ -291,14 +343,17 @@ class Context:
                 stream = torch.cuda.current_stream(dev)
                 opts.hip_stream = ctypes.c_void_p(stream.cuda_stream)
 
-                def _alloc(size, user, _dev=dev, _s=stream):
+                def _alloc(size, user, _dev=dev, _s=stream, _a=torch.cuda.caching_allocator_alloc):
                     try:
-                        return torch.cuda.caching_allocator_alloc(size, _dev, _s)
+                        return _a(size, _dev, _s)
                     except Exception:
                         return None
 
-                def _free(ptr, user):
-                    torch.cuda.caching_allocator_delete(ptr)
+                def _free(ptr, user, _d=torch.cuda.caching_allocator_delete):
+                    try:
+                        _d(ptr)
+                    except Exception:  # interpreter shutdown: torch already torn down
+                        pass
 
                 a, f = ALLOC_FN(_alloc), FREE_FN(_free)
                 self._keep += [a, f]
@@ -359,20 +414,22 @@ class Plan:
                             axes=ccut_fragment_axes(self.handle, f)))
         return out
 
-    def marginal(self, qubits, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, out=None):
-        eo = _eval_opts(shots, seed, precision, circuit)
+    def marginal(self, qubits, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,
+                 out=None):
+        eo = _eval_opts(shots, seed, precision, circuit, method)
         if out is None:
             out = np.zeros(1 << len(qubits), dtype=np.float64)
         ccut_marginal(self.handle, self.ctx.handle, eo, qubits, out)
         return out
 
-    def zexpect(self, masks, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, out=None):
+    def zexpect(self, masks, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,
+                out=None):
         masks = np.asarray(masks, dtype=np.uint64)
         if masks.ndim == 1:
             masks = masks[:, None]
         if out is None:
             out = np.zeros(masks.shape[0], dtype=np.float64)
-        ccut_zexpect(self.handle, self.ctx.handle, _eval_opts(shots, seed, precision, circuit), masks, out)
+        ccut_zexpect(self.handle, self.ctx.handle, _eval_opts(shots, seed, precision, circuit, method), masks, out)
         return out
 
     def shot_records(self, qubits, fragment, v_begin, v_end, *, shots, seed=0, circuit=0):
@@ -389,10 +446,44 @@ class Plan:
                             out)
         return out.reshape(nv, 1 << nm)
 
-    def fragment_tensor(self, qubits, fragment, *, shots=0, seed=0, circuit=0):
+    def fragment_tensor(self, qubits, fragment, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO):
         _, nr = ccut_request_info(self.handle, qubits, fragment)
         na = ccut_fragment_info(self.handle, fragment)[2]
         out = np.zeros((4 ** na) << nr, dtype=np.float64)
-        ccut_fragment_tensor(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits,
+        ccut_fragment_tensor(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, method), qubits,
                              fragment, out)
         return out.reshape(4 ** na, 1 << nr)
+
+
+class Batch:
+    """Many plans evaluated together: one persistent autotuned tableau
+    launch for all Clifford variants, the rest per plan, captured once as a
+    HIP graph (``use_graph``) and replayed by ``run``."""
+
+    def __init__(self, ctx: Context, plans, qubits, *, shots=0, seed=0, precision=CCUT_FP64,
+                 method=CCUT_METHOD_AUTO, use_graph=True):
+        self.ctx = ctx
+        self.plans = list(plans)
+        self.qubits = [list(q) for q in qubits]
+        self.handle = ccut_batch_create(ctx.handle, self.plans, _eval_opts(shots, seed, precision, 0, method),
+                                        self.qubits, use_graph)
+
+    def info(self):
+        return ccut_batch_info(self.handle)
+
+    def run(self, outs=None):
+        if outs is None:
+            outs = [np.zeros(1 << len(q), dtype=np.float64) for q in self.qubits]
+        ccut_batch_run(self.handle, self.ctx.handle, outs)
+        return outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ccut_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -77,7 +77,10 @@ struct PendingTiming {
 
 struct ccut_ctx {
   int device = -1;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // the caller's stream: results are ordered on it
+  hipStream_t aux = nullptr;      // library stream for non-Clifford fragments (default priority)
+  hipStream_t cur = nullptr;      // stream the next launch goes to
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   uint32_t max_nc = 12, max_cuts = 12;
   std::string err;
   std::atomic<int> cancel{0};
@@ -87,18 +90,20 @@ struct ccut_ctx {
   std::vector<hipEvent_t> event_pool;
   uint64_t launches[CCUT_K_COUNT] = {};
   double total_ms[CCUT_K_COUNT] = {};
+  std::vector<std::vector<char>> staged;  // host copies kept alive until the call's final sync
+  bool use_aux = true;       // route non-Clifford fragments to the auxiliary stream
+  bool replay_uploads = false;  // re-enqueue of an identical sequence: reuse earlier uploads, copy nothing
 };
 
 struct ccut_plan {
   ccut_ctx *ctx = nullptr;
   PlanData pd;
   std::vector<uint32_t *> d_ops;   // per fragment, uploaded on first evaluation
-  std::vector<double *> d_theta;
-  std::vector<size_t> op_bytes;
+  std::vector<double *> d_mats;
   ~ccut_plan() {
     for (auto p : d_ops)
       if (p) (void)hipFree(p);
-    for (auto p : d_theta)
+    for (auto p : d_mats)
       if (p) (void)hipFree(p);
   }
 };
@@ -139,12 +144,12 @@ struct KTimer {
     if (c->timing) {
       a = take_event(c);
       b = take_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, c->cur);
     }
   }
   ~KTimer() {
     if (c->timing && a && b) {
-      (void)hipEventRecord(b, c->stream);
+      (void)hipEventRecord(b, c->cur);
       c->pending.push_back({kid, a, b});
     }
   }
@@ -155,21 +160,29 @@ T *aget(ccut_ctx *c, size_t count) {
   return (T *)c->arena.get(count * sizeof(T));
 }
 
+// Upload each fragment's op stream once per plan: the circuit-order words
+// for Clifford fragments, the fused stream (with its matrices) for
+// non-Clifford ones; padded with no-ops to a multiple of 16 words so kernels
+// can fetch ops sixteen at a time.
 ccut_status ensure_ops(ccut_plan *p) {
   ccut_ctx *c = p->ctx;
   if (!p->d_ops.empty()) return CCUT_OK;
   for (const Fragment &f : p->pd.frags) {
+    std::vector<uint32_t> words = f.clifford ? f.op_words : f.sv_words;
+    std::vector<double> mats = f.clifford ? std::vector<double>() : f.sv_mats;
+    while (words.size() % 16 || words.empty()) {
+      words.push_back(pack_op(G_NOP, 0, 0));
+      if (!f.clifford) mats.insert(mats.end(), 8, 0.0);
+    }
+    if (mats.empty()) mats.assign(8, 0.0);
     uint32_t *o = nullptr;
     double *t = nullptr;
-    size_t n = std::max<size_t>(f.op_words.size(), 1);
-    HIP_TRY(c, hipMalloc(&o, n * sizeof(uint32_t)));
-    HIP_TRY(c, hipMalloc(&t, n * sizeof(double)));
-    if (!f.op_words.empty()) {
-      HIP_TRY(c, hipMemcpy(o, f.op_words.data(), f.op_words.size() * 4, hipMemcpyHostToDevice));
-      HIP_TRY(c, hipMemcpy(t, f.op_theta.data(), f.op_theta.size() * 8, hipMemcpyHostToDevice));
-    }
+    HIP_TRY(c, hipMalloc(&o, words.size() * sizeof(uint32_t)));
+    HIP_TRY(c, hipMalloc(&t, mats.size() * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(o, words.data(), words.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(t, mats.data(), mats.size() * 8, hipMemcpyHostToDevice));
     p->d_ops.push_back(o);
-    p->d_theta.push_back(t);
+    p->d_mats.push_back(t);
   }
   return CCUT_OK;
 }
@@ -181,9 +194,52 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   if (eo->precision != CCUT_FP64 && eo->precision != CCUT_FP32_MFMA_FP64SUM)
     return fail(c, CCUT_E_INVALID, "unknown precision mode");
   HIP_TRY(c, hipSetDevice(c->device));
+  if (eo->method > CCUT_METHOD_HEISENBERG || eo->reserved != 0)
+    return fail(c, CCUT_E_INVALID, "unknown evaluation method");
   c->cancel.store(0);
   c->arena.reset();
+  c->staged.clear();
+  if (!c->aux) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+  }
+  c->cur = c->stream;
+  // the auxiliary stream starts after everything already queued on the caller's stream
+  HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
+  HIP_TRY(c, hipStreamWaitEvent(c->aux, c->fork_ev, 0));
   return ensure_ops(p);
+}
+
+// Route the next launches of fragment f: non-Clifford fragments go to the
+// auxiliary stream so they overlap the Clifford chain.
+void route(ccut_ctx *c, const Fragment &f) { c->cur = (f.clifford || !c->use_aux) ? c->stream : c->aux; }
+
+// Join the auxiliary stream back into the caller's stream.
+ccut_status join(ccut_ctx *c) {
+  c->cur = c->stream;
+  if (!c->use_aux) return CCUT_OK;
+  HIP_TRY(c, hipEventRecord(c->join_ev, c->aux));
+  HIP_TRY(c, hipStreamWaitEvent(c->stream, c->join_ev, 0));
+  return CCUT_OK;
+}
+
+// Copy host bytes to fresh device memory on the context stream; the host
+// copy is kept until the call synchronizes.  A null source (an empty host
+// vector) gets the allocation without a copy.
+void *upload(ccut_ctx *c, const void *src, size_t bytes) {
+  void *d = c->arena.get(bytes);
+  if (!d) return nullptr;
+  if (c->replay_uploads || !src || bytes == 0) return d;  // replay: the bytes are already there
+  c->staged.emplace_back((const char *)src, (const char *)src + bytes);
+  if (hipMemcpyAsync(d, c->staged.back().data(), bytes, hipMemcpyHostToDevice, c->cur) != hipSuccess)
+    return nullptr;
+  return d;
+}
+
+uint32_t row_words(uint32_t m) {
+  const uint32_t w = (m + 63) / 64;
+  return w <= 1 ? 1 : w <= 2 ? 2 : w <= 4 ? 4 : w <= 8 ? 8 : 0;
 }
 
 ccut_status check_request(ccut_ctx *c, uint32_t n, const uint32_t *qubits, uint32_t nq,
@@ -204,21 +260,16 @@ ccut_status cancelled(ccut_ctx *c) {
   return CCUT_OK;
 }
 
-FragDev *upload_frag(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_t circuit,
-                     FragDev &h) {
-  ccut_ctx *c = p->ctx;
-  h = make_frag_dev(f, r, ((uint64_t)circuit << 40) | ((uint64_t)f.index << 32));
+FragDev frag_desc(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_t circuit) {
+  FragDev h = make_frag_dev(f, r, ((uint64_t)circuit << 40) | ((uint64_t)f.index << 32));
   h.ops = p->d_ops[f.index];
-  h.theta = p->d_theta[f.index];
-  FragDev *d = aget<FragDev>(c, 1);
-  if (!d) return nullptr;
-  if (hipMemcpyAsync(d, &h, sizeof(FragDev), hipMemcpyHostToDevice, c->stream) != hipSuccess) return nullptr;
-  return d;
+  h.mats = p->d_mats[f.index];
+  return h;
 }
 
 // Per-variant outcome distributions dist[v][x] over the measured set.
 ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment &f,
-                          const FragRequest &r, double **dist_out) {
+                          const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr) {
   ccut_ctx *c = p->ctx;
   const uint32_t nm = (uint32_t)r.meas.size();
   const uint64_t nv = f.n_variants;
@@ -228,23 +279,23 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     return fail(c, CCUT_E_UNSUPPORTED, "outcome table over more than 24 measured qubits");
   if ((nv << nm) > (uint64_t(1) << 34))
     return fail(c, CCUT_E_UNSUPPORTED, "variant tables exceed 2^34 entries");
-  FragDev h;
-  FragDev *d = upload_frag(p, f, r, eo->circuit, h);
+  const FragDev h = frag_desc(p, f, r, eo->circuit);
   double *dist = aget<double>(c, nv << nm);
-  if (!d || !dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if (!dist) return fail(c, CCUT_E_OOM, "device allocation failed");
   if (!f.clifford) {
     KTimer t(c, CCUT_K_SV);
-    HIP_TRY(c, launch_sv(d, h, 0, nv, dist, c->stream));
+    HIP_TRY(c, launch_sv(h, dist, c->cur));
   } else {
-    uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
-    if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
-    {
+    uint64_t *models = pre_models;
+    if (!models) {
+      models = aget<uint64_t>(c, nv * model_words(nm));
+      if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
       KTimer t(c, CCUT_K_TABLEAU);
-      HIP_TRY(c, launch_tableau(d, h, 0, nv, models, c->stream));
+      HIP_TRY(c, launch_tableau(h, 0, nv, models, c->cur));
     }
     if (eo->shots_per_variant == 0) {
       KTimer t(c, CCUT_K_EXACT);
-      HIP_TRY(c, launch_exact_tables(models, nm, nv, dist, c->stream));
+      HIP_TRY(c, launch_exact_tables(models, nm, nv, dist, c->cur));
     } else {
       const uint64_t shots = eo->shots_per_variant;
       const uint32_t bins = 1u << nm;
@@ -254,7 +305,9 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
         const bool lds = nm <= 14;
         uint32_t nblk = 1;
         if (lds) {
-          uint64_t want = (1024 + cnv - 1) / cnv;
+          // enough shots per workgroup that its partial histogram is not mostly empty
+          const uint64_t per_block = std::max<uint64_t>(bins, 2048);
+          uint64_t want = (shots + per_block - 1) / per_block;
           uint64_t maxb = (nquads + 255) / 256;
           nblk = (uint32_t)std::max<uint64_t>(1, std::min(want, maxb));
         } else {
@@ -264,16 +317,16 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
         const uint64_t pcount = lds ? cnv * nblk * (uint64_t)bins : cnv * (uint64_t)bins;
         uint32_t *partial = aget<uint32_t>(c, pcount);
         if (!partial) return fail(c, CCUT_E_OOM, "device allocation failed");
-        if (!lds) HIP_TRY(c, hipMemsetAsync(partial, 0, pcount * 4, c->stream));
+        if (!lds) HIP_TRY(c, launch_fill_u32(partial, pcount, 0u, c->cur));
         {
           KTimer t(c, CCUT_K_SAMPLE);
           HIP_TRY(c, launch_sample_hist(models + v0 * model_words(nm), nm, cnv, shots, eo->seed,
-                                        h.vid_base + v0, partial, nblk, qpt, nullptr, c->stream));
+                                        h.vid_base + v0, partial, nblk, qpt, nullptr, c->cur));
         }
         {
           KTimer t(c, CCUT_K_HIST_REDUCE);
           HIP_TRY(c, launch_hist_reduce(partial, cnv, lds ? nblk : 1, bins, shots, dist + (v0 << nm),
-                                        c->stream));
+                                        c->cur));
         }
       }
     }
@@ -315,7 +368,7 @@ ccut_status pauli_passes(ccut_ctx *c, const Fragment &f, const FragRequest &r, d
     }
     {
       KTimer t(c, CCUT_K_TRANSFORM);
-      HIP_TRY(c, launch_transform_pass(cur, nxt, outer, R, xsize, lo, mode, c->stream));
+      HIP_TRY(c, launch_transform_pass(cur, nxt, outer, R, xsize, lo, mode, c->cur));
     }
     cur = nxt;
     rad[j] = 4;
@@ -325,10 +378,117 @@ ccut_status pauli_passes(ccut_ctx *c, const Fragment &f, const FragRequest &r, d
   return CCUT_OK;
 }
 
+
+// Exact Pauli-basis tensor of a Clifford fragment in the Heisenberg picture.
+// Marginal mode (strings == nullptr): T[p_f][b] over the requested outputs.
+// String mode: t[p_f][s] for Z strings given as local z masks (W words each).
+ccut_status heis_tensor(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_t circuit,
+                        const std::vector<std::vector<uint64_t>> *strings, double **out) {
+  ccut_ctx *c = p->ctx;
+  const uint32_t W = row_words(f.m());
+  if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
+  const uint32_t RW = 2 * W + 1;
+  std::vector<uint64_t> rows;
+  auto add_row = [&](int xq, int zq, const std::vector<uint64_t> *zmask) {
+    std::vector<uint64_t> row(RW, 0);
+    if (xq >= 0) row[xq >> 6] |= 1ull << (xq & 63);
+    if (zq >= 0) row[W + (zq >> 6)] |= 1ull << (zq & 63);
+    if (zmask)
+      for (uint32_t w = 0; w < W; ++w) row[W + w] |= (*zmask)[w];
+    rows.insert(rows.end(), row.begin(), row.end());
+  };
+  const uint32_t nreq = (uint32_t)r.req_pos.size();
+  if (!strings) {
+    for (uint32_t i = 0; i < nreq; ++i) add_row(-1, (int)r.meas[r.req_pos[i]], nullptr);
+  } else {
+    for (const auto &z : *strings) add_row(-1, -1, &z);
+  }
+  uint32_t n_in = 0, n_out = 0;
+  for (const Axis &a : f.axes) {
+    if (a.side == 0) {
+      add_row((int)a.local, -1, nullptr);
+      add_row(-1, (int)a.local, nullptr);
+      ++n_out;
+    } else {
+      ++n_in;
+    }
+  }
+  if (n_out > 8) return fail(c, CCUT_E_UNSUPPORTED, "more than 8 quantum outputs on a Clifford fragment");
+  std::vector<uint64_t> cin(8, 0);
+  for (uint32_t i = 0; i < f.m(); ++i)
+    if (f.segs[i] == 0) cin[i >> 6] |= 1ull << (i & 63);
+  const uint32_t n_rows = (uint32_t)(rows.size() / RW);
+  if (rows.empty()) rows.assign(RW, 0);  // a fragment with nothing to carry back still gets a valid buffer
+  const uint64_t ncols = strings ? strings->size() : (1ull << nreq);
+  const uint64_t total = ncols << (2 * f.axes.size());
+  if (total > (1ull << 34)) return fail(c, CCUT_E_UNSUPPORTED, "Pauli-basis tensor exceeds 2^34 entries");
+  double *tau = aget<double>(c, total);
+  uint64_t *d_out = aget<uint64_t>(c, rows.size());
+  uint64_t *d_in = (uint64_t *)upload(c, rows.data(), rows.size() * 8);
+  if (!tau || !d_out || !d_in) return fail(c, CCUT_E_OOM, "device allocation failed");
+  FragRequest rq = r;
+  const FragDev h = frag_desc(p, f, rq, circuit);
+  {
+    KTimer t(c, CCUT_K_HEISENBERG);
+    HIP_TRY(c, launch_heisenberg(h, W, n_in, n_out, strings ? 0 : nreq, strings ? (uint32_t)strings->size() : 0,
+                                 cin.data(), d_in, d_out, n_rows, tau, c->cur));
+  }
+  *out = tau;
+  return cancelled(c);
+}
+
+
+// Contract the fragment tensors into out[2^nq].  fp64 with few terms x
+// outputs: the plain ascending sum; otherwise the K-split MFMA contraction
+// (fp32 products with fp64 across K-chunks, or fp64 MFMA).
+ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
+  const uint64_t K = 1ull << (2 * args.k);
+  if (!fp32 && (K << nq) <= (1ull << 26)) {
+    RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
+    if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_recombine_fp64(dargs, nq, res, c->cur));
+    return CCUT_OK;
+  }
+  GemmArgs g{};
+  g.k = args.k;
+  g.K = K;
+  uint32_t rf = 0;
+  for (uint32_t f = 1; f < args.n_frags; ++f)
+    if (args.f[f].n_req > args.f[rf].n_req) rf = f;
+  uint32_t lbits = 0;
+  for (uint32_t f = 0; f < args.n_frags; ++f) {
+    g.f[f] = args.f[f];
+    bool ident = args.f[f].n_axes == args.k;
+    for (uint32_t j = 0; ident && j < args.f[f].n_axes; ++j) ident = args.f[f].axis_cut[j] == j;
+    g.ident[f] = ident ? 1u : 0u;
+    GemmSide &S = (f == rf) ? g.R : g.L;
+    const uint32_t sh = (f == rf) ? 0u : lbits;
+    S.frag[S.n] = f;
+    S.shift[S.n] = sh;
+    S.bits[S.n] = args.f[f].n_req;
+    S.n++;
+    if (f != rf) lbits += args.f[f].n_req;
+  }
+  g.M = 1u << lbits;
+  g.N = 1u << args.f[rf].n_req;
+  const uint32_t splits = gemm_splits(g);
+  GemmArgs *dg = (GemmArgs *)upload(c, &g, sizeof(g));
+  double *partial = aget<double>(c, (size_t)splits * g.M * g.N);
+  if (!dg || !partial) return fail(c, CCUT_E_OOM, "device allocation failed");
+  KTimer t(c, CCUT_K_RECOMBINE);
+  HIP_TRY(c, launch_recombine_gemm(g, dg, fp32, partial, splits, res, c->cur));
+  return CCUT_OK;
+}
+
+bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo) {
+  return f.clifford && eo->shots_per_variant == 0 && eo->method != CCUT_METHOD_VARIANTS;
+}
+
 ccut_status finish_out(ccut_ctx *c, const double *dev, double *out, size_t count, int on_device) {
   HIP_TRY(c, hipMemcpyAsync(out, dev, count * sizeof(double),
-                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->cur));
+  HIP_TRY(c, hipStreamSynchronize(c->cur));
   return CCUT_OK;
 }
 
@@ -386,6 +546,12 @@ void ccut_ctx_destroy(ccut_ctx *c) {
       (void)hipEventDestroy(pt.b);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->aux) {
+      (void)hipStreamSynchronize(c->aux);
+      (void)hipStreamDestroy(c->aux);
+      (void)hipEventDestroy(c->fork_ev);
+      (void)hipEventDestroy(c->join_ev);
+    }
     c->arena.release();
   }
   delete c;
@@ -503,29 +669,42 @@ ccut_status ccut_fragment_tensor(ccut_plan *p, const ccut_eval_opts *eo, const u
   const Fragment &f = p->pd.frags[fragment];
   FragRequest r = marginal_request(f, qubits, nq);
   double *dist = nullptr, *T = nullptr;
-  if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;
-  if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+  if (use_heisenberg(f, eo)) {
+    if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
+  } else {
+    if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;
+    if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+  }
   size_t count = ((size_t)1 << (2 * f.axes.size())) << r.req_pos.size();
   return finish_out(c, T, out, count, on_device);
 }
 
-ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
-                          double *out, int on_device) {
-  ccut_status st = check_eval(p, eo);
-  if (st != CCUT_OK) return st;
+}  // extern "C"
+
+namespace {
+// Enqueue the whole marginal evaluation of one plan (no final copy, no
+// sync); res receives 2^nq doubles.  pre_models[f], if given, holds the
+// already computed sample models of Clifford fragment f.
+ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                             double *res, const std::vector<uint64_t *> *pre_models) {
   ccut_ctx *c = p->ctx;
-  if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
-  if ((st = check_request(c, p->pd.n, qubits, nq)) != CCUT_OK) return st;
+  ccut_status st;
   const PlanData &pd = p->pd;
   if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
   RecombArgs args{};
   args.n_frags = (uint32_t)pd.frags.size();
   args.k = pd.k;
   for (const Fragment &f : pd.frags) {
+    route(c, f);
     FragRequest r = marginal_request(f, qubits, nq);
     double *dist = nullptr, *T = nullptr;
-    if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;
-    if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+    if (use_heisenberg(f, eo)) {
+      if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
+    } else {
+      uint64_t *pm = pre_models ? (*pre_models)[f.index] : nullptr;
+      if ((st = variant_dists(p, eo, f, r, &dist, pm)) != CCUT_OK) return st;
+      if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+    }
     RecombFrag &rf = args.f[f.index];
     rf.T = T;
     rf.n_axes = (uint32_t)f.axes.size();
@@ -535,14 +714,23 @@ ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t
     for (size_t i = 0; i < r.req_user.size(); ++i) rf.req_user[i] = r.req_user[i];
     if ((st = cancelled(c)) != CCUT_OK) return st;
   }
-  RecombArgs *dargs = aget<RecombArgs>(c, 1);
+  if ((st = join(c)) != CCUT_OK) return st;
+  return recombine(c, args, nq, eo->precision == CCUT_FP32_MFMA_FP64SUM, res);
+}
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                          double *out, int on_device) {
+  ccut_status st = check_eval(p, eo);
+  if (st != CCUT_OK) return st;
+  ccut_ctx *c = p->ctx;
+  if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
+  if ((st = check_request(c, p->pd.n, qubits, nq)) != CCUT_OK) return st;
   double *res = aget<double>(c, (size_t)1 << nq);
-  if (!dargs || !res) return fail(c, CCUT_E_OOM, "device allocation failed");
-  HIP_TRY(c, hipMemcpyAsync(dargs, &args, sizeof(args), hipMemcpyHostToDevice, c->stream));
-  {
-    KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_recombine_fp64(dargs, nq, res, c->stream));
-  }
+  if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if ((st = marginal_enqueue(p, eo, qubits, nq, res, nullptr)) != CCUT_OK) return st;
   return finish_out(c, res, out, (size_t)1 << nq, on_device);
 }
 
@@ -565,9 +753,30 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   args.n_frags = (uint32_t)pd.frags.size();
   args.k = pd.k;
   for (const Fragment &f : pd.frags) {
+    route(c, f);
     FragRequest r = zstring_request(f, anymask);
     const uint32_t nm = (uint32_t)r.meas.size();
     const uint64_t nv = f.n_variants;
+    if (use_heisenberg(f, eo)) {
+      const uint32_t W = row_words(f.m());
+      if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
+      std::vector<std::vector<uint64_t>> zs(n_strings, std::vector<uint64_t>(W, 0));
+      for (uint32_t s2 = 0; s2 < n_strings; ++s2)
+        for (uint32_t q = 0; q < pd.n; ++q) {
+          const int32_t l = f.out_local[q];
+          if (l >= 0 && ((masks[(size_t)s2 * nw + (q >> 6)] >> (q & 63)) & 1ull))
+            zs[s2][l >> 6] |= 1ull << (l & 63);
+        }
+      double *T = nullptr;
+      if ((st = heis_tensor(p, f, r, eo->circuit, &zs, &T)) != CCUT_OK) return st;
+      RecombFrag &rf = args.f[f.index];
+      rf.T = T;
+      rf.n_axes = (uint32_t)f.axes.size();
+      rf.rows = n_strings;
+      rf.n_req = 0;
+      for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
+      continue;
+    }
     if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits in a fragment");
     // extended masks [J][string] over measured positions
     std::vector<uint32_t> outpos;
@@ -591,44 +800,41 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
         ext[(size_t)J * n_strings + s] = e;
       }
     }
-    uint64_t *d_ext = aget<uint64_t>(c, n_ext);
+    uint64_t *d_ext = (uint64_t *)upload(c, ext.data(), n_ext * 8);
     double *E = aget<double>(c, nv * n_ext);
     if (!d_ext || !E) return fail(c, CCUT_E_OOM, "device allocation failed");
-    HIP_TRY(c, hipMemcpyAsync(d_ext, ext.data(), n_ext * 8, hipMemcpyHostToDevice, c->stream));
-    FragDev h;
-    FragDev *d = upload_frag(p, f, r, eo->circuit, h);
-    if (!d) return fail(c, CCUT_E_OOM, "device allocation failed");
+    const FragDev h = frag_desc(p, f, r, eo->circuit);
     if (!f.clifford) {
       double *dist = aget<double>(c, nv << nm);
       if (!dist) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
         KTimer t(c, CCUT_K_SV);
-        HIP_TRY(c, launch_sv(d, h, 0, nv, dist, c->stream));
+        HIP_TRY(c, launch_sv(h, dist, c->cur));
       }
       KTimer t(c, CCUT_K_PARITY);
-      HIP_TRY(c, launch_dist_parity(dist, nm, nv, d_ext, n_ext, E, c->stream));
+      HIP_TRY(c, launch_dist_parity(dist, nm, nv, d_ext, n_ext, E, c->cur));
     } else {
       uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
         KTimer t(c, CCUT_K_TABLEAU);
-        HIP_TRY(c, launch_tableau(d, h, 0, nv, models, c->stream));
+        HIP_TRY(c, launch_tableau(h, 0, nv, models, c->cur));
       }
       if (eo->shots_per_variant == 0) {
         KTimer t(c, CCUT_K_PARITY);
-        HIP_TRY(c, launch_parity_exact(models, nm, nv, d_ext, n_ext, E, c->stream));
+        HIP_TRY(c, launch_parity_exact(models, nm, nv, d_ext, n_ext, E, c->cur));
       } else {
         uint32_t *odd = aget<uint32_t>(c, nv * n_ext);
         if (!odd) return fail(c, CCUT_E_OOM, "device allocation failed");
-        HIP_TRY(c, hipMemsetAsync(odd, 0, nv * n_ext * 4, c->stream));
+        HIP_TRY(c, launch_fill_u32(odd, nv * n_ext, 0u, c->cur));
         for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
           const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
           KTimer t(c, CCUT_K_PARITY);
           HIP_TRY(c, launch_parity_sampled(models + v0 * model_words(nm), nm, cnv, eo->shots_per_variant,
                                            eo->seed, h.vid_base + v0, d_ext, n_ext, odd + v0 * n_ext,
-                                           c->stream));
+                                           c->cur));
         }
-        HIP_TRY(c, launch_parity_finish(odd, nv * n_ext, eo->shots_per_variant, E, c->stream));
+        HIP_TRY(c, launch_parity_finish(odd, nv * n_ext, eo->shots_per_variant, E, c->cur));
       }
     }
     double *T = nullptr;
@@ -641,13 +847,13 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
     for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
     if ((st = cancelled(c)) != CCUT_OK) return st;
   }
-  RecombArgs *dargs = aget<RecombArgs>(c, 1);
+  if ((st = join(c)) != CCUT_OK) return st;
+  RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
   double *res = aget<double>(c, n_strings);
   if (!dargs || !res) return fail(c, CCUT_E_OOM, "device allocation failed");
-  HIP_TRY(c, hipMemcpyAsync(dargs, &args, sizeof(args), hipMemcpyHostToDevice, c->stream));
   {
     KTimer t(c, CCUT_K_ZRECOMBINE);
-    HIP_TRY(c, launch_zrecombine_fp64(dargs, n_strings, res, c->stream));
+    HIP_TRY(c, launch_zrecombine(dargs, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM, res, c->cur));
   }
   return finish_out(c, res, out, n_strings, on_device);
 }
@@ -669,15 +875,14 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   FragRequest r = marginal_request(f, qubits, nq);
   const uint32_t nm = (uint32_t)r.meas.size();
   if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits");
-  FragDev h;
-  FragDev *d = upload_frag(p, f, r, eo->circuit, h);
+  const FragDev h = frag_desc(p, f, r, eo->circuit);
   uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
   const uint64_t shots = eo->shots_per_variant;
   uint64_t *rec = aget<uint64_t>(c, nv * shots);
-  if (!d || !models || !rec) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if (!models || !rec) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
     KTimer t(c, CCUT_K_TABLEAU);
-    HIP_TRY(c, launch_tableau(d, h, v_begin, nv, models, c->stream));
+    HIP_TRY(c, launch_tableau(h, v_begin, nv, models, c->cur));
   }
   const uint64_t nquads = (shots + 3) / 4;
   for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
@@ -686,11 +891,11 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
     const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
     KTimer t(c, CCUT_K_SAMPLE);
     HIP_TRY(c, launch_sample_hist(models + v0 * model_words(nm), nm, cnv, shots, eo->seed,
-                                  h.vid_base + v_begin + v0, nullptr, nblk, qpt, rec + v0 * shots, c->stream));
+                                  h.vid_base + v_begin + v0, nullptr, nblk, qpt, rec + v0 * shots, c->cur));
   }
   HIP_TRY(c, hipMemcpyAsync(out, rec, nv * shots * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+                            c->cur));
+  HIP_TRY(c, hipStreamSynchronize(c->cur));
   return CCUT_OK;
 }
 
@@ -737,8 +942,284 @@ const char *ccut_kernel_name(uint32_t kid) {
   static const char *names[CCUT_K_COUNT] = {"tableau_kernel", "sample_kernel", "hist_reduce_kernel",
                                             "exact_kernel", "sv_kernel", "parity_kernel",
                                             "transform_pass_kernel", "recombine_fp64_kernel",
-                                            "zrecombine_fp64_kernel"};
+                                            "zrecombine_fp64_kernel", "heisenberg_kernels"};
   return kid < CCUT_K_COUNT ? names[kid] : "";
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Batches: many plans evaluated together.  The Clifford variants of all
+// plans go through one persistent, work-queue tableau launch (tile shape
+// picked by a small autotuner); everything else per plan follows; the whole
+// sequence is captured once into a HIP graph and replayed.
+
+struct ccut_batch {
+  ccut_ctx *ctx = nullptr;
+  std::vector<ccut_plan *> plans;
+  std::vector<std::vector<uint32_t>> qubits;
+  ccut_eval_opts eo{};
+  Arena arena;
+  std::vector<std::vector<char>> staged;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graphed = false;
+  std::vector<double *> res;
+  std::vector<FragDev> descs;
+  std::vector<BatchItem> items;
+  std::vector<std::vector<int64_t>> model_off;  // per plan, per fragment: word offset or -1
+  uint64_t model_words_total = 0;
+  uint32_t max_m = 0, block = 64, grid = 0, use_reg = 1;
+  double tuned_ms = 0.0;
+  ~ccut_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (stream) (void)hipStreamDestroy(stream);
+    arena.release();
+  }
+};
+
+namespace {
+
+// Swap the context's execution state for the batch's while enqueueing.
+struct BatchScope {
+  ccut_ctx *c;
+  ccut_batch *b;
+  hipStream_t saved_stream;
+  bool saved_timing, saved_aux;
+  BatchScope(ccut_batch *bb) : c(bb->ctx), b(bb) {
+    std::swap(c->arena, b->arena);
+    std::swap(c->staged, b->staged);
+    saved_stream = c->stream;
+    saved_timing = c->timing;
+    saved_aux = c->use_aux;
+    c->stream = c->cur = b->stream;
+    c->timing = false;
+    c->use_aux = false;
+  }
+  ~BatchScope() {
+    std::swap(c->arena, b->arena);
+    std::swap(c->staged, b->staged);
+    c->stream = c->cur = saved_stream;
+    c->timing = saved_timing;
+    c->use_aux = saved_aux;
+    c->replay_uploads = false;
+  }
+};
+
+ccut_status batch_tableau(ccut_batch *b, FragDev *d_descs, BatchItem *d_items, uint32_t *d_counter,
+                          uint64_t *d_models, uint32_t block, uint32_t grid, uint32_t use_reg) {
+  ccut_ctx *c = b->ctx;
+  if (b->items.empty()) return CCUT_OK;
+  HIP_TRY(c, launch_tableau_batch(d_descs, d_items, (uint32_t)b->items.size(), d_counter, d_models, b->max_m, block,
+                                  grid, use_reg, c->cur));
+  return CCUT_OK;
+}
+
+// Enqueue one whole batch evaluation on the batch stream (inside a
+// BatchScope).  Allocation order is fixed, so a replay reuses the same memory.
+ccut_status batch_enqueue(ccut_batch *b, bool tune) {
+  ccut_ctx *c = b->ctx;
+  ccut_status st;
+  c->arena.reset();
+  if (!c->replay_uploads) c->staged.clear();
+  // (an all-Heisenberg batch has no tableau items: allocate a placeholder, copy nothing)
+  FragDev *d_descs = (FragDev *)upload(c, b->descs.empty() ? nullptr : b->descs.data(),
+                                       std::max<size_t>(b->descs.size(), 1) * sizeof(FragDev));
+  BatchItem *d_items = (BatchItem *)upload(c, b->items.empty() ? nullptr : b->items.data(),
+                                           std::max<size_t>(b->items.size(), 1) * sizeof(BatchItem));
+  uint32_t *d_counter = aget<uint32_t>(c, 64);
+  uint64_t *d_models = aget<uint64_t>(c, std::max<uint64_t>(b->model_words_total, 1));
+  if (!d_descs || !d_items || !d_counter || !d_models) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if (tune && !b->items.empty()) {
+    // autotune the persistent launch: workgroup size x workgroups per CU
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    double best = 1e30;
+    for (uint32_t block : {64u, 128u, 256u}) {
+      const size_t lds = tableau_batch_lds(b->max_m, block);
+      if (lds > 160 * 1024) continue;
+      for (uint32_t per_cu : {1u, 2u, 4u, 8u}) {
+        if (lds * per_cu > 160 * 1024) continue;
+        for (uint32_t reg : {0u, 1u}) {
+          if (reg && block != 64) continue;
+          const uint32_t grid = (uint32_t)cus * per_cu;
+          // warm once, then time
+          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg)) != CCUT_OK) return st;
+          HIP_TRY(c, hipEventRecord(e0, c->cur));
+          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg)) != CCUT_OK) return st;
+          HIP_TRY(c, hipEventRecord(e1, c->cur));
+          HIP_TRY(c, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            b->block = block;
+            b->grid = grid;
+            b->use_reg = reg;
+          }
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tuned_ms = best;
+  }
+  if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg)) != CCUT_OK)
+    return st;
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    ccut_plan *p = b->plans[i];
+    ccut_eval_opts eo = b->eo;
+    eo.circuit = (uint32_t)i;
+    std::vector<uint64_t *> pre(p->pd.frags.size(), nullptr);
+    for (size_t f = 0; f < pre.size(); ++f)
+      if (b->model_off[i][f] >= 0) pre[f] = d_models + b->model_off[i][f];
+    double *res = aget<double>(c, (size_t)1 << b->qubits[i].size());
+    if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
+    if (b->res.size() <= i) b->res.push_back(res);
+    b->res[i] = res;
+    if ((st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre)) != CCUT_OK)
+      return st;
+  }
+  return CCUT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
+                              const uint32_t *const *qubits, const uint32_t *nq, int use_graph, ccut_batch **out) {
+  if (!c || !out || !eo || (n && (!plans || !qubits || !nq))) return fail(c, CCUT_E_INVALID, "NULL argument");
+  *out = nullptr;
+  if (c->device < 0) return fail(c, CCUT_E_DEVICE, "host-only context: evaluation needs a device");
+  if (n == 0 || n > 65535) return fail(c, CCUT_E_INVALID, "batch size must be in [1, 65535]");
+  std::unique_ptr<ccut_batch> b(new (std::nothrow) ccut_batch());
+  if (!b) return fail(c, CCUT_E_OOM, "host allocation failed");
+  b->ctx = c;
+  b->eo = *eo;
+  b->arena.alloc = c->arena.alloc;
+  b->arena.free_fn = c->arena.free_fn;
+  b->arena.user = c->arena.user;
+  ccut_status st;
+  for (size_t i = 0; i < n; ++i) {
+    ccut_plan *p = plans[i];
+    if (!p || p->ctx != c) return fail(c, CCUT_E_INVALID, "plan from another context");
+    if ((st = check_eval(p, eo)) != CCUT_OK) return st;
+    if ((st = check_request(c, p->pd.n, qubits[i], nq[i])) != CCUT_OK) return st;
+    b->plans.push_back(p);
+    b->qubits.emplace_back(qubits[i], qubits[i] + nq[i]);
+    std::vector<int64_t> offs(p->pd.frags.size(), -1);
+    for (const Fragment &f : p->pd.frags) {
+      if (!f.clifford || use_heisenberg(f, eo)) continue;
+      FragRequest r = marginal_request(f, qubits[i], nq[i]);
+      const uint32_t nm = (uint32_t)r.meas.size();
+      if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits");
+      if (f.m() > 512) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
+      FragDev h = frag_desc(p, f, r, (uint32_t)i);
+      const uint32_t di = (uint32_t)b->descs.size();
+      b->descs.push_back(h);
+      offs[f.index] = (int64_t)b->model_words_total;
+      for (uint64_t v = 0; v < f.n_variants; ++v)
+        b->items.push_back({di, 0u, v, b->model_words_total + v * model_words(nm)});
+      b->model_words_total += f.n_variants * model_words(nm);
+      b->max_m = std::max(b->max_m, f.m());
+    }
+    b->model_off.push_back(offs);
+  }
+  // longest items first: cost ~ width x gate count
+  std::stable_sort(b->items.begin(), b->items.end(), [&](const BatchItem &x, const BatchItem &y) {
+    const FragDev &a = b->descs[x.desc], &d = b->descs[y.desc];
+    return (uint64_t)a.m * (a.n_ops + a.n_meas * a.m) > (uint64_t)d.m * (d.n_ops + d.n_meas * d.m);
+  });
+  HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  {
+    BatchScope scope(b.get());
+    if ((st = batch_enqueue(b.get(), true)) != CCUT_OK) return st;
+  }
+  HIP_TRY(c, hipStreamSynchronize(b->stream));
+  if (use_graph) {
+    BatchScope scope(b.get());
+    c->replay_uploads = true;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      st = batch_enqueue(b.get(), false);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(b->stream, &g);
+      if (st == CCUT_OK && e == hipSuccess && g) {
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess) b->graphed = true;
+      } else if (g) {
+        (void)hipGraphDestroy(g);
+      }
+    }
+    (void)hipGetLastError();
+    c->err.clear();
+  }
+  *out = b.release();
+  return CCUT_OK;
+}
+
+ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_device) {
+  if (!b || !outs) return CCUT_E_INVALID;
+  ccut_ctx *c = b->ctx;
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->cancel.store(0);
+  // order after the caller's queued work
+  if (!c->fork_ev) {
+    HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+  }
+  HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
+  HIP_TRY(c, hipStreamWaitEvent(b->stream, c->fork_ev, 0));
+  if (b->graphed) {
+    HIP_TRY(c, hipGraphLaunch(b->exec, b->stream));
+  } else {
+    BatchScope scope(b);
+    c->replay_uploads = true;
+    ccut_status st = batch_enqueue(b, false);
+    if (st != CCUT_OK) return st;
+  }
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    HIP_TRY(c, hipMemcpyAsync(outs[i], b->res[i], sizeof(double) << b->qubits[i].size(),
+                              outs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(c, hipStreamSynchronize(b->stream));
+  return CCUT_OK;
+}
+
+ccut_status ccut_batch_info(const ccut_batch *b, uint64_t *n_items, uint32_t *block, uint32_t *grid,
+                            int32_t *use_reg, int32_t *graphed, double *tableau_ms) {
+  if (!b) return CCUT_E_INVALID;
+  if (n_items) *n_items = b->items.size();
+  if (block) *block = b->block;
+  if (grid) *grid = b->grid;
+  if (use_reg) *use_reg = (int32_t)b->use_reg;
+  if (graphed) *graphed = b->graphed ? 1 : 0;
+  if (tableau_ms) *tableau_ms = b->tuned_ms;
+  return CCUT_OK;
+}
+
+void ccut_batch_destroy(ccut_batch *b) {
+  if (!b) return;
+  if (b->ctx && b->ctx->device >= 0) {
+    (void)hipSetDevice(b->ctx->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+  }
+  delete b;
+}
+
+ccut_status ccut_run_batch(ccut_ctx *c, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
+                           const uint32_t *const *qubits, const uint32_t *nq, double *const *outs) {
+  ccut_batch *b = nullptr;
+  ccut_status st = ccut_batch_create(c, plans, n, eo, qubits, nq, 0, &b);
+  if (st != CCUT_OK) return st;
+  st = ccut_batch_run(b, outs, 0);
+  ccut_batch_destroy(b);
+  return st;
 }
 
 }  // extern "C"

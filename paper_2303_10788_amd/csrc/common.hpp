@@ -14,7 +14,9 @@ constexpr int kMaxTableBits = 24;
 
 enum GateKind : uint32_t {
   G_H = 0, G_S = 1, G_SDG = 2, G_X = 3, G_Y = 4, G_Z = 5, G_CX = 6, G_CZ = 7,
-  G_T = 8, G_TDG = 9, G_RZ = 10
+  G_T = 8, G_TDG = 9, G_RZ = 10,
+  G_U2 = 11,   // fused one-qubit unitary (state-vector path only), matrix in FragDev::mats
+  G_NOP = 15   // padding of op arrays to a multiple of 4 words
 };
 
 // op word: kind in bits 0-3, q0 in bits 4-17, q1 in bits 18-31 (local qubits < 16384)
@@ -25,7 +27,32 @@ __host__ __device__ inline uint32_t op_kind(uint32_t w) { return w & 15u; }
 __host__ __device__ inline uint32_t op_q0(uint32_t w) { return (w >> 4) & 0x3FFFu; }
 __host__ __device__ inline uint32_t op_q1(uint32_t w) { return w >> 18; }
 
-// One fragment under one request, as the kernels see it (device memory).
+// Global-address-space views: loads through them with a wave-uniform index
+// compile to scalar (SMEM) loads, so op decoding stays in SGPRs.
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
+typedef __attribute__((address_space(1))) const double g_double;
+
+// Four op words starting at word 4*g4 (a uniform index: one scalar load).
+__device__ inline uint4 load_ops4(const uint32_t *ops, uint32_t g4) {
+  const g_u32 *p = (const g_u32 *)ops + 4 * g4;
+  return make_uint4(p[0], p[1], p[2], p[3]);
+}
+
+// Sixteen op words starting at word 16*g16: one wait per sixteen gates
+// (op arrays are padded with G_NOP to a multiple of 16 words).
+struct Ops16 {
+  uint32_t w[16];
+};
+__device__ inline Ops16 load_ops16(const uint32_t *ops, uint32_t g16) {
+  const g_u32 *p = (const g_u32 *)ops + 16 * g16;
+  Ops16 o;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) o.w[i] = p[i];
+  return o;
+}
+
+// One fragment under one request, as the kernels see it (passed by value in
+// the kernel-argument segment, so every field read is a scalar load).
 struct FragDev {
   uint32_t m;          // local qubits
   uint32_t n_ops;      // fragment gates (preparations and rotations are implied by the variant)
@@ -40,8 +67,8 @@ struct FragDev {
   uint32_t axis_radix[kMaxAxes];
   uint32_t axis_cut[kMaxAxes];
   uint16_t meas[kMaxMeas];         // local qubit of measurement j (ascending)
-  const uint32_t *ops;             // packed op words
-  const double *theta;             // per op angle (RZ), may be null
+  const uint32_t *ops;             // packed op words, padded with G_NOP to a multiple of 16
+  const double *mats;              // per op 2x2 complex matrix (re00 im00 re01 im01 re10 im10 re11 im11), G_U2 only
 };
 
 // Per-variant affine sample model of a Clifford variant: a shot's outcome
@@ -49,11 +76,24 @@ struct FragDev {
 // Philox bit is 1).  Layout per variant: [x0, randmask, Gcol[0..n_meas)].
 __host__ __device__ inline uint32_t model_words(uint32_t n_meas) { return 2u + n_meas; }
 
+// One unit of the batched tableau launch: variant `variant` of descriptor
+// `desc`, its model written at word offset `model_off`.
+struct BatchItem {
+  uint32_t desc;
+  uint32_t pad;
+  uint64_t variant;
+  uint64_t model_off;
+};
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
-hipError_t launch_tableau(const FragDev *d_frag, const FragDev &h_frag, uint64_t v0, uint64_t nv,
-                          uint64_t *models, hipStream_t s);
+hipError_t launch_tableau(const FragDev &frag, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s);
+size_t tableau_batch_lds(uint32_t max_m, uint32_t block);
+hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, uint32_t n_items, uint32_t *counter,
+                                uint64_t *models, uint32_t max_m, uint32_t block, uint32_t grid, uint32_t use_reg,
+                                hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
                               uint32_t quads_per_thread, uint64_t *records, hipStream_t s);
@@ -61,8 +101,7 @@ hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nbl
                               uint64_t shots, double *dist, hipStream_t s);
 hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,
                                hipStream_t s);
-hipError_t launch_sv(const FragDev *d_frag, const FragDev &h_frag, uint64_t v0, uint64_t nv,
-                     double *dist, hipStream_t s);
+hipError_t launch_sv(const FragDev &frag, double *dist, hipStream_t s);
 hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
                                const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
 hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
@@ -77,6 +116,12 @@ hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv,
 // mode 2 = quantum output on parity tables (basis x J-bit -> 4).
 hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, uint64_t inner_digits,
                                  uint64_t xsize_in, uint64_t lo, int mode, hipStream_t s);
+
+// Exact Pauli-basis tensor of a Clifford fragment without enumerating
+// variants (Heisenberg picture); see k_heis.hip for the row layout.
+hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
+                             uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
+                             uint32_t n_rows, double *tau, hipStream_t s);
 
 struct RecombFrag {
   const double *T;          // T_f[p_f][row], row count `rows`
@@ -93,6 +138,27 @@ struct RecombArgs {
   RecombFrag f[kMaxFrags];
 };
 hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *out, hipStream_t s);
-hipError_t launch_zrecombine_fp64(const RecombArgs *d_args, uint32_t n_strings, double *out, hipStream_t s);
+// Z strings: fp64 products and sum, or (fp32 = true) fp32 products summed
+// in fp32 over chunks of 32 terms and in fp64 across chunks.
+hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t n_strings, bool fp32, double *out, hipStream_t s);
+
+// Recombination as a dense contraction A (row fragments) x B^T (column
+// fragments) over the 4^k cut terms, split along K.
+struct GemmSide {
+  uint32_t n;
+  uint32_t frag[kMaxFrags];
+  uint32_t shift[kMaxFrags];  // position of the fragment's row bits in the side's index
+  uint32_t bits[kMaxFrags];
+};
+struct GemmArgs {
+  uint32_t k, M, N;
+  uint64_t K;
+  GemmSide L, R;
+  uint32_t ident[kMaxFrags];  // 1 if the fragment's axes are cuts 0..k-1 in order (p_f(P) = P)
+  RecombFrag f[kMaxFrags];
+};
+uint32_t gemm_splits(const GemmArgs &h);
+hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
+                                 uint32_t splits, double *out, hipStream_t s);
 
 }  // namespace ccut

@@ -80,23 +80,43 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
   outp[b] = ldexp(acc, -(int)k);
 }
 
-// <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s]
-__global__ void zrecombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings,
-                                       double *__restrict__ outp) {
+// <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s].  fp64: products and sum in
+// fp64, P ascending.  fp32: every factor split into fp32 parts t = hi + lo,
+// the product taken in fp32 to first order (prod hi + sum_f lo_f prod_{g!=f}
+// hi_g), summed in fp32 over 8 consecutive terms, those sums added in fp64.
+template <bool F32>
+__global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings, double *__restrict__ outp) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_strings) return;
   const uint32_t nf = A->n_frags, k = A->k;
   const uint64_t nterms = 1ull << (2 * k);
   double acc = 0.0;
+  float chunk = 0.f;
   for (uint64_t P = 0; P < nterms; ++P) {
     double term = 1.0;
+    float hi = 1.f, corr = 0.f;
     for (uint32_t f = 0; f < nf; ++f) {
       const RecombFrag &F = A->f[f];
       uint32_t p = 0;
       for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
-      term *= F.T[(uint64_t)p * F.rows + s];
+      const double t = F.T[(uint64_t)p * F.rows + s];
+      if (F32) {
+        const float th = (float)t, tl = (float)(t - (double)th);
+        corr = corr * th + hi * tl;
+        hi *= th;
+      } else {
+        term *= t;
+      }
     }
-    acc += term;
+    if (F32) {
+      chunk += hi + corr;
+      if ((P & 7) == 7 || P + 1 == nterms) {
+        acc += (double)chunk;
+        chunk = 0.f;
+      }
+    } else {
+      acc += term;
+    }
   }
   outp[s] = ldexp(acc, -(int)k);
 }
@@ -119,9 +139,13 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *
   return hipGetLastError();
 }
 
-hipError_t launch_zrecombine_fp64(const RecombArgs *d_args, uint32_t n_strings, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(zrecombine_fp64_kernel, dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args,
-                     n_strings, out);
+hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t n_strings, bool fp32, double *out, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL((zrecombine_kernel<true>), dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args, n_strings,
+                       out);
+  else
+    hipLaunchKernelGGL((zrecombine_kernel<false>), dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args, n_strings,
+                       out);
   return hipGetLastError();
 }
 

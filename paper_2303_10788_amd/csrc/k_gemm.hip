@@ -1,0 +1,204 @@
+// Recombination as one dense contraction over the 4^k cut terms:
+//   R[b] = 2^-k sum_P A[b_L; P] B[b_R; P],
+//   A[b_L; P] = prod_{f in L} T_f[p_f(P)][b_f],  B[b_R; P] = prod_{f in R} T_f[p_f(P)][b_f],
+// the tensor-network contraction of Sec. V-C grouped into two operands
+// (one fragment on the column side, the rest on the row side).  Operand
+// tiles are formed on the fly from the fragment tensors (never
+// materialised: for 10 cuts the row operand alone would be 2^10 x 4^10).
+//
+// Precision modes:
+//  - FP32 MFMA with FP64 across K tiles: each fp64 operand is split into
+//    fp32 parts a = a_hi + a_lo; every group of 4 terms is multiplied by
+//    three v_mfma_f32_16x16x4_f32 (a_hi b_hi + a_hi b_lo + a_lo b_hi, the
+//    dropped a_lo b_lo is 2^-48 relative), summed in fp32 over 8 terms, and
+//    those partial sums are added into fp64 accumulators (the signed sum over
+//    cut terms cancels heavily, so it is kept in fp64);
+//  - FP64 MFMA (v_mfma_f64_16x16x4_f64) end to end (reference path).
+// Split-K partials are summed in fp64 in split order by a second kernel.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace ccut {
+
+namespace {
+
+constexpr int MT = 64, NT = 64, KC = 32, GEMM_THREADS = 256;
+
+typedef float float4v __attribute__((ext_vector_type(4)));
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+__device__ inline uint64_t frag_p(const GemmArgs *__restrict__ G, uint32_t f, uint64_t P) {
+  const RecombFrag &F = G->f[f];
+  if (G->ident[f]) return P;
+  uint64_t p = 0;
+  for (uint32_t j = 0; j < F.n_axes; ++j) p |= ((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+  return p;
+}
+
+__device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t row, uint64_t P) {
+  double v = 1.0;
+  for (uint32_t i = 0; i < S.n; ++i) {
+    const uint32_t f = S.frag[i];
+    const uint32_t r = (row >> S.shift[i]) & ((1u << S.bits[i]) - 1u);
+    v *= G->f[f].T[frag_p(G, f, P) * G->f[f].rows + r];
+  }
+  return v;
+}
+
+template <bool F32>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
+                                                            double *__restrict__ partial) {
+  typedef typename std::conditional<F32, float, double>::type TS;
+  __shared__ TS As[KC][MT + 1];
+  __shared__ TS Bs[KC][NT + 1];
+  __shared__ TS Al[F32 ? KC : 1][MT + 1];  // fp32 mode: low parts of the split operands
+  __shared__ TS Bl[F32 ? KC : 1][NT + 1];
+  const uint32_t M = G->M, N = G->N;
+  const uint64_t K = G->K;
+  const uint32_t tilesM = (M + MT - 1) / MT;
+  const uint32_t tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
+  const uint64_t k0 = (uint64_t)blockIdx.y * k_per_split;
+  const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  double acc64[2][2][4];
+  float4v acc32[2][2];
+  double4v accd[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc32[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
+      accd[i][j] = double4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int g = 0; g < 4; ++g) acc64[i][j][g] = 0.0;
+    }
+  for (uint64_t kb = k0; kb < k1; kb += KC) {
+    for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
+      const uint32_t kk = e / MT, mm = e % MT;
+      const uint32_t m = tm * MT + mm;
+      const uint64_t P = kb + kk;
+      const double a = (m < M && P < k1) ? side_value(G, G->L, m, P) : 0.0;
+      As[kk][mm] = (TS)a;
+      if constexpr (F32) Al[kk][mm] = (float)(a - (double)(float)a);
+    }
+    for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
+      const uint32_t kk = e / NT, nn = e % NT;
+      const uint32_t n = tn * NT + nn;
+      const uint64_t P = kb + kk;
+      const double b = (n < N && P < k1) ? side_value(G, G->R, n, P) : 0.0;
+      Bs[kk][nn] = (TS)b;
+      if constexpr (F32) Bl[kk][nn] = (float)(b - (double)(float)b);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      TS a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[kk + lane / 16][wm + 16 * i + lane % 16];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lane / 16][wn + 16 * j + lane % 16];
+      if constexpr (F32) {
+        float al[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) al[i] = Al[kk + lane / 16][wm + 16 * i + lane % 16];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bl[j] = Bl[kk + lane / 16][wn + 16 * j + lane % 16];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], bl[j], acc32[i][j], 0, 0, 0);
+            acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[i], (float)b[j], acc32[i][j], 0, 0, 0);
+            acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], (float)b[j], acc32[i][j], 0, 0, 0);
+          }
+        if (kk & 4) {  // fold every 8 terms into fp64
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+              for (int g = 0; g < 4; ++g) acc64[i][j][g] += (double)acc32[i][j][g];
+              acc32[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            accd[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[i], (double)b[j], accd[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  double *dst = partial + (uint64_t)blockIdx.y * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        // accumulator register g of a lane holds row 4 (lane / 16) + g of the
+        // 16x16 block for the fp32 instruction, row lane / 16 + 4 g for fp64
+        const uint32_t r = F32 ? 4 * (lane / 16) + g : lane / 16 + 4 * g;
+        const uint32_t m = tm * MT + wm + 16 * i + r;
+        const uint32_t n = tn * NT + wn + 16 * j + lane % 16;
+        if (m < M && n < N) dst[(uint64_t)m * N + n] = F32 ? acc64[i][j][g] : accd[i][j][g];
+      }
+}
+
+// out[b(m, n)] = 2^-k sum_split partial[split][m][n], splits in order
+__global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
+                                   uint32_t splits, double *__restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t MN = (uint64_t)G->M * G->N;
+  if (i >= MN) return;
+  double s = 0.0;
+  for (uint32_t sp = 0; sp < splits; ++sp) s += partial[sp * MN + i];
+  const uint32_t m = (uint32_t)(i / G->N), n = (uint32_t)(i % G->N);
+  uint64_t b = 0;
+  for (uint32_t t = 0; t < G->L.n; ++t) {
+    const RecombFrag &F = G->f[G->L.frag[t]];
+    const uint32_t r = (m >> G->L.shift[t]) & ((1u << G->L.bits[t]) - 1u);
+    for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
+  }
+  for (uint32_t t = 0; t < G->R.n; ++t) {
+    const RecombFrag &F = G->f[G->R.frag[t]];
+    const uint32_t r = (n >> G->R.shift[t]) & ((1u << G->R.bits[t]) - 1u);
+    for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
+  }
+  out[b] = ldexp(s, -(int)G->k);
+}
+
+}  // namespace
+
+uint32_t gemm_splits(const GemmArgs &h) {
+  const uint64_t tiles = (uint64_t)((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
+  const uint64_t kchunks = (h.K + KC - 1) / KC;
+  uint64_t s = std::max<uint64_t>(1, 1024 / std::max<uint64_t>(tiles, 1));
+  s = std::min<uint64_t>(s, kchunks);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
+}
+
+hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
+                                 uint32_t splits, double *out, hipStream_t s) {
+  const uint32_t tiles = ((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
+  const uint64_t kchunks = (h.K + KC - 1) / KC;
+  const uint64_t k_per_split = ((kchunks + splits - 1) / splits) * KC;
+  if (fp32)
+    hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
+                       partial);
+  else
+    hipLaunchKernelGGL((gemm_kernel<false>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
+                       partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t MN = (uint64_t)h.M * h.N;
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, d_args, partial,
+                     splits, out);
+  return hipGetLastError();
+}
+
+}  // namespace ccut

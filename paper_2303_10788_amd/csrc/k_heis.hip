@@ -1,0 +1,339 @@
+// Exact Pauli-basis tensors of Clifford fragments in the Heisenberg picture
+// (the Clifford-specific cutting optimisation the paper outlines in Sec. IX:
+// Clifford expectations are -1, 0 or +1 and most Pauli terms vanish).
+//
+// For a Clifford fragment U with quantum inputs (prepared as the operator
+// P_in), circuit inputs |0> and a measured set, the Pauli-basis entry is
+//   tau[S; P_out, P_in] = Tr[(Z_S (x) Q_out) U rho_in U^dag]
+//                       = Tr[O rho_in],   O = U^dag (Z_S (x) Q_out) U,
+// and with O = (-1)^s sigma_1 (x) ... (x) sigma_m:
+//   Tr[O rho_in] = (-1)^s 2^#in [sigma|inputs == P_in] [sigma|circuit inputs in {I, Z}].
+// The marginal tensor is T[b; P] = 2^-r sum_S (-1)^{b.S} tau[S; P] (the
+// projector onto outcome b is 2^-r sum_S (-1)^{b.S} Z_S), a Walsh-Hadamard
+// transform over subsets S of the r requested outputs.  No variant is
+// enumerated: only the r requested Z's and the X, Z of each quantum output
+// are carried back through the fragment once.
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace ccut {
+
+namespace {
+
+// row layout in memory: x[W], z[W], sign word (bit 0)
+template <int W>
+struct PRow {
+  uint64_t x[W], z[W];
+  uint32_t s;
+};
+
+// conjugation P -> G P G^dag of one Hermitian Pauli row by gate `kind`
+template <int W>
+__device__ inline void conj_gate(PRow<W> &r, uint32_t kind, uint32_t a, uint32_t b) {
+  const uint32_t wa = a >> 6, wb = b >> 6;
+  const uint64_t ma = 1ull << (a & 63), mb = 1ull << (b & 63);
+  uint64_t xa_w = r.x[0], za_w = r.z[0];
+#pragma unroll
+  for (int w = 1; w < W; ++w)
+    if (wa == (uint32_t)w) {
+      xa_w = r.x[w];
+      za_w = r.z[w];
+    }
+  const uint32_t xa = (xa_w & ma) != 0, za = (za_w & ma) != 0;
+  uint64_t nxa = xa_w, nza = za_w;
+  switch (kind) {
+    case G_H:
+      r.s ^= xa & za;
+      if (xa != za) {
+        nxa ^= ma;
+        nza ^= ma;
+      }
+      break;
+    case G_S:
+      r.s ^= xa & za;
+      if (xa) nza ^= ma;
+      break;
+    case G_SDG:
+      r.s ^= xa & (za ^ 1u);
+      if (xa) nza ^= ma;
+      break;
+    case G_X: r.s ^= za; break;
+    case G_Y: r.s ^= xa ^ za; break;
+    case G_Z: r.s ^= xa; break;
+    case G_CX:
+    case G_CZ: {
+      uint64_t xb_w = r.x[0], zb_w = r.z[0];
+#pragma unroll
+      for (int w = 1; w < W; ++w)
+        if (wb == (uint32_t)w) {
+          xb_w = r.x[w];
+          zb_w = r.z[w];
+        }
+      const uint32_t xb = (xb_w & mb) != 0, zb = (zb_w & mb) != 0;
+      uint64_t flip_xb = 0, flip_zb = 0;
+      if (kind == G_CX) {
+        r.s ^= xa & zb & (xb ^ za ^ 1u);
+        if (xa) flip_xb = mb;
+        if (zb) nza ^= ma;
+      } else {
+        r.s ^= xa & xb & (za ^ zb);
+        if (xb) nza ^= ma;
+        if (xa) flip_zb = mb;
+      }
+      // write qubit-a word first, then apply the qubit-b flips to the
+      // (possibly same) word
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (wa == (uint32_t)w) {
+          r.x[w] = nxa;
+          r.z[w] = nza;
+        }
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (wb == (uint32_t)w) {
+          r.x[w] ^= flip_xb;
+          r.z[w] ^= flip_zb;
+        }
+      return;
+    }
+    default:
+      return;
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (wa == (uint32_t)w) {
+      r.x[w] = nxa;
+      r.z[w] = nza;
+    }
+}
+
+// Carry each row back through the fragment: O = U^dag P U, i.e. conjugate
+// by the inverse gates from the last gate to the first.
+template <int W>
+__global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uint64_t *__restrict__ in,
+                                                      uint64_t *__restrict__ out, uint32_t n_rows) {
+  const uint32_t row = blockIdx.x * 64 + threadIdx.x;
+  const bool ok = row < n_rows;
+  const uint64_t *src = in + (size_t)(ok ? row : 0) * (2 * W + 1);
+  PRow<W> r;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    r.x[w] = ok ? src[w] : 0;
+    r.z[w] = ok ? src[W + w] : 0;
+  }
+  r.s = ok ? (uint32_t)src[2 * W] & 1u : 0u;
+  const uint32_t n16 = (F.n_ops + 15) / 16;
+  for (uint32_t g16 = n16; g16-- > 0;) {
+    const Ops16 o = load_ops16(F.ops, g16);
+#pragma unroll
+    for (int t = 15; t >= 0; --t) {  // last gate first
+      uint32_t kind = op_kind(o.w[t]);
+      if (kind == G_S)  // inverse gate
+        kind = G_SDG;
+      else if (kind == G_SDG)
+        kind = G_S;
+      conj_gate<W>(r, kind, op_q0(o.w[t]), op_q1(o.w[t]));
+    }
+  }
+  if (ok) {
+    uint64_t *dst = out + (size_t)row * (2 * W + 1);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      dst[w] = r.x[w];
+      dst[W + w] = r.z[w];
+    }
+    dst[2 * W] = r.s;
+  }
+}
+
+struct HeisArgs {
+  uint32_t m, W, n_axes, n_in, n_out, r;
+  uint32_t axis_side[kMaxAxes];
+  uint32_t axis_local[kMaxAxes];
+  uint64_t cin_mask[8];  // local qubits that are circuit inputs
+  uint32_t n_str;        // Z-string mode: number of string rows (0 = marginal mode)
+};
+
+// Phase-tracked product: P = i^a X^x Z^z.
+template <int W>
+struct PAcc {
+  uint64_t x[W], z[W];
+  uint32_t a;
+};
+
+template <int W>
+__device__ inline void pmul(PAcc<W> &L, const uint64_t *R) {  // L <- L * R (R a Hermitian row)
+  uint32_t cross = 0, pr = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    cross += __popcll(L.z[w] & R[w]);
+    pr += __popcll(R[w] & R[W + w]);
+  }
+  L.a = (L.a + 2u * (uint32_t)R[2 * W] + pr + 2u * cross) & 3u;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    L.x[w] ^= R[w];
+    L.z[w] ^= R[W + w];
+  }
+}
+
+template <int W>
+__device__ inline uint32_t pbit(const uint64_t (&v)[W], uint32_t q) {
+  uint64_t word = v[0];
+#pragma unroll
+  for (int w = 1; w < W; ++w)
+    if ((q >> 6) == (uint32_t)w) word = v[w];
+  return (uint32_t)(word >> (q & 63)) & 1u;
+}
+
+// One thread per (S or string, P_out combination).  rows: for the marginal
+// mode the r requested Z images followed by (X_c, Z_c) images per output;
+// for the string mode n_str string images followed by the output images.
+// tau[p_f][col] (zero-filled by the caller) receives the single nonzero
+// entry of this (col, P_out) if the circuit-input condition holds.
+template <int W>
+__global__ void tau_kernel(const HeisArgs A, const uint64_t *__restrict__ rows, double *__restrict__ tau,
+                           uint64_t ncols) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n_pout = 1ull << (2 * A.n_out);
+  if (t >= ncols * n_pout) return;
+  const uint64_t col = t % ncols;
+  const uint64_t pc = t / ncols;
+  const uint32_t RW = 2 * W + 1;
+  PAcc<W> acc;
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc.x[w] = acc.z[w] = 0;
+  acc.a = 0;
+  uint32_t out_base;
+  if (A.n_str == 0) {
+    for (uint32_t j = 0; j < A.r; ++j)
+      if ((col >> j) & 1ull) pmul<W>(acc, rows + (size_t)j * RW);
+    out_base = A.r;
+  } else {
+    pmul<W>(acc, rows + (size_t)col * RW);
+    out_base = A.n_str;
+  }
+  // output Paulis, in output-axis order; Y = i X Z
+  uint32_t oc = 0;
+  uint64_t pf = 0;
+  for (uint32_t j = 0; j < A.n_axes; ++j) {
+    if (A.axis_side[j] != 0) continue;
+    const uint32_t P = (uint32_t)((pc >> (2 * oc)) & 3ull);  // I, X, Y, Z
+    const uint64_t *rx = rows + (size_t)(out_base + 2 * oc) * RW;
+    const uint64_t *rz = rx + RW;
+    if (P == 1) pmul<W>(acc, rx);
+    if (P == 3) pmul<W>(acc, rz);
+    if (P == 2) {
+      acc.a = (acc.a + 1u) & 3u;
+      pmul<W>(acc, rx);
+      pmul<W>(acc, rz);
+    }
+    pf |= (uint64_t)P << (2 * j);
+    ++oc;
+  }
+  // circuit inputs must carry I or Z
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (acc.x[w] & A.cin_mask[w]) return;
+  for (uint32_t j = 0; j < A.n_axes; ++j) {
+    if (A.axis_side[j] != 1) continue;
+    const uint32_t q = A.axis_local[j];
+    const uint32_t xq = pbit<W>(acc.x, q), zq = pbit<W>(acc.z, q);
+    const uint32_t P = xq ? (zq ? 2u : 1u) : (zq ? 3u : 0u);
+    pf |= (uint64_t)P << (2 * j);
+  }
+  uint32_t pxz = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) pxz += __popcll(acc.x[w] & acc.z[w]);
+  const uint32_t sgn = ((acc.a - pxz) & 3u) >> 1;  // acc is Hermitian: a - x.z in {0, 2}
+  tau[pf * ncols + col] = ldexp(sgn ? -1.0 : 1.0, (int)A.n_in);
+}
+
+// T[row][b] = 2^-r sum_S (-1)^{b.S} tau[row][S]: in-place WHT per row in LDS.
+constexpr int kWht = 256;
+__global__ __launch_bounds__(kWht) void subset_wht_kernel(double *__restrict__ data, uint32_t r) {
+  extern __shared__ double w[];
+  const uint32_t n = 1u << r;
+  double *row = data + (uint64_t)blockIdx.x * n;
+  for (uint32_t i = threadIdx.x; i < n; i += kWht) w[i] = row[i];
+  __syncthreads();
+  for (uint32_t s = 0; s < r; ++s) {
+    for (uint32_t k = threadIdx.x; k < n / 2; k += kWht) {
+      const uint32_t i0 = ((k >> s) << (s + 1)) | (k & ((1u << s) - 1)), i1 = i0 | (1u << s);
+      const double a = w[i0], b = w[i1];
+      w[i0] = a + b;
+      w[i1] = a - b;
+    }
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kWht) row[i] = ldexp(w[i], -(int)r);
+}
+
+__global__ void fill_zero_kernel(double *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+template <int W>
+hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, uint64_t *rows_out, uint32_t n_rows,
+                 double *tau, uint64_t ncols, hipStream_t s) {
+  hipError_t e;
+  if (n_rows) {
+    hipLaunchKernelGGL((backprop_kernel<W>), dim3((n_rows + 63) / 64), dim3(64), 0, s, F, rows_in, rows_out, n_rows);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint64_t total_tau = ncols << (2 * A.n_axes);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<uint64_t>((total_tau + 255) / 256, 65536)), dim3(256),
+                     0, s, tau, total_tau);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const uint64_t nt = ncols << (2 * A.n_out);
+  hipLaunchKernelGGL((tau_kernel<W>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, A, rows_out, tau, ncols);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// rows_in: host-built Pauli rows [n_rows][2W+1] with W = words(m) rounded up
+// to {1, 2, 4, 8}; see k_heis layout.  Marginal mode (n_str == 0): rows are
+// r requested Z's then (X_c, Z_c) per output axis; tau is [4^n_axes][2^r] and
+// is turned into T[p_f][b] in place.  String mode: rows are n_str strings then
+// the output pairs; tau is [4^n_axes][n_str] = t_f[p_f][string].
+hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
+                             uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
+                             uint32_t n_rows, double *tau, hipStream_t s) {
+  HeisArgs A{};
+  A.m = F.m;
+  A.W = W;
+  A.n_axes = F.n_axes;
+  A.n_in = n_in;
+  A.n_out = n_out;
+  A.r = r;
+  A.n_str = n_str;
+  for (uint32_t j = 0; j < F.n_axes; ++j) {
+    A.axis_side[j] = F.axis_side[j];
+    A.axis_local[j] = F.axis_local[j];
+  }
+  for (uint32_t w = 0; w < 8; ++w) A.cin_mask[w] = w < W ? cin_mask[w] : 0;
+  const uint64_t ncols = n_str ? n_str : (1ull << r);
+  hipError_t e;
+  switch (W) {
+    case 1: e = run_w<1>(F, A, rows_in, rows_out, n_rows, tau, ncols, s); break;
+    case 2: e = run_w<2>(F, A, rows_in, rows_out, n_rows, tau, ncols, s); break;
+    case 4: e = run_w<4>(F, A, rows_in, rows_out, n_rows, tau, ncols, s); break;
+    case 8: e = run_w<8>(F, A, rows_in, rows_out, n_rows, tau, ncols, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || n_str) return e;
+  const uint64_t nrows = 1ull << (2 * F.n_axes);
+  if (r == 0) return hipSuccess;
+  for (uint64_t r0 = 0; r0 < nrows; r0 += (1ull << 30)) {
+    const uint64_t cnt = std::min<uint64_t>(nrows - r0, 1ull << 30);
+    hipLaunchKernelGGL(subset_wht_kernel, dim3((unsigned)cnt), dim3(kWht), (size_t(1) << r) * 8, s,
+                       tau + (r0 << r), r);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ccut

@@ -222,20 +222,30 @@ __global__ void parity_finish_kernel(const uint32_t *__restrict__ odd, uint64_t 
   E[i] = ((double)shots - 2.0 * (double)odd[i]) / (double)shots;
 }
 
-// <(-1)^{z.x}> from an outcome distribution over n_meas bits, summed in
-// ascending x.  grid over (v, ext mask).
-__global__ void dist_parity_kernel(const double *__restrict__ dist, uint32_t n_meas, uint64_t nv,
-                                   const uint64_t *__restrict__ ext, uint32_t n_ext,
-                                   double *__restrict__ E) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv * n_ext) return;
-  const uint64_t v = i / n_ext;
-  const uint64_t z = ext[i % n_ext];
-  const uint64_t bins = 1ull << n_meas;
-  const double *p = dist + v * bins;
-  double acc = 0.0;
-  for (uint64_t x = 0; x < bins; ++x) acc += (__popcll(x & z) & 1) ? -p[x] : p[x];
-  E[i] = acc;
+// <(-1)^{z.x}> for every mask z from an outcome distribution over n_meas
+// bits: the Walsh-Hadamard transform W[z] = sum_x (-1)^{z.x} p(x), done in
+// place in LDS with n_meas butterfly stages (fixed order, deterministic),
+// then gathered at the requested masks.  One workgroup per variant.
+constexpr int kWhtBlock = 256;
+__global__ __launch_bounds__(kWhtBlock) void dist_parity_kernel(const double *__restrict__ dist, uint32_t n_meas,
+                                                                const uint64_t *__restrict__ ext, uint32_t n_ext,
+                                                                double *__restrict__ E) {
+  extern __shared__ double w[];
+  const uint32_t bins = 1u << n_meas;
+  const double *p = dist + (uint64_t)blockIdx.x * bins;
+  for (uint32_t i = threadIdx.x; i < bins; i += kWhtBlock) w[i] = p[i];
+  __syncthreads();
+  for (uint32_t s = 0; s < n_meas; ++s) {
+    for (uint32_t k = threadIdx.x; k < bins / 2; k += kWhtBlock) {
+      const uint32_t i0 = ((k >> s) << (s + 1)) | (k & ((1u << s) - 1)), i1 = i0 | (1u << s);
+      const double a = w[i0], b = w[i1];
+      w[i0] = a + b;
+      w[i1] = a - b;
+    }
+    __syncthreads();
+  }
+  double *out = E + (uint64_t)blockIdx.x * n_ext;
+  for (uint32_t e = threadIdx.x; e < n_ext; e += kWhtBlock) out[e] = w[ext[e]];
 }
 
 inline unsigned blocks_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -295,10 +305,16 @@ hipError_t launch_parity_finish(const uint32_t *odd, uint64_t n, uint64_t shots,
 
 hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv, const uint64_t *ext,
                               uint32_t n_ext, double *E, hipStream_t s) {
-  const uint64_t n = nv * n_ext;
-  hipLaunchKernelGGL(dist_parity_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dist, n_meas, nv, ext,
-                     n_ext, E);
-  return hipGetLastError();
+  if (n_meas > (uint32_t)kMaxNcQubits || nv == 0) return nv ? hipErrorInvalidValue : hipSuccess;
+  const size_t lds = (size_t(1) << n_meas) * sizeof(double);
+  for (uint64_t v0 = 0; v0 < nv; v0 += (1ull << 30)) {
+    const uint64_t cnv = nv - v0 < (1ull << 30) ? nv - v0 : (1ull << 30);
+    hipLaunchKernelGGL(dist_parity_kernel, dim3((unsigned)cnv), dim3(kWhtBlock), lds, s, dist + (v0 << n_meas),
+                       n_meas, ext, n_ext, E + v0 * n_ext);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ccut

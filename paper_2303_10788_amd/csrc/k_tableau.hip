@@ -21,6 +21,9 @@
 // phase exponent a = 2r + popc(x & z) (mod 4), and the product of
 // P1 = i^a1 X^x1 Z^z1 and P2 = i^a2 X^x2 Z^z2 is
 // i^(a1 + a2 + 2 popc(z1 & x2)) X^(x1^x2) Z^(z1^z2).
+#include <algorithm>
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace ccut {
@@ -143,15 +146,14 @@ size_t tableau_lds(size_t m) {
   return (b + 15) & ~size_t(15);
 }
 
-template <int W, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev *__restrict__ fd, uint64_t v0,
-                                                        uint64_t *__restrict__ models) {
-  extern __shared__ uint64_t smem[];
-  const FragDev &F = *fd;
+// One variant with the tableau in LDS; D is the descriptor's access type
+// (a kernel argument, or an entry of a device-memory descriptor array read
+// through a global-address-space reference).
+template <int W, int BLOCK, class D>
+__device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ out, uint64_t *smem) {
   const int m = (int)F.m;
   const int R2 = 2 * m;
   const int tid = threadIdx.x;
-  const uint64_t v = v0 + blockIdx.x;
   const uint32_t n_meas = F.n_meas;
 
   uint64_t *X = smem;                    // [W][2m]
@@ -198,10 +200,13 @@ __global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev *__restric
       }
     }
   }
-  for (uint32_t g = 0; g < F.n_ops; ++g) {
-    const uint32_t word = F.ops[g];
-    const uint32_t kind = op_kind(word), a = op_q0(word), b = op_q1(word);
-    for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, kind, a, b);
+  for (uint32_t g16 = 0; g16 < (F.n_ops + 15) / 16; ++g16) {
+    const Ops16 o = load_ops16(F.ops, g16);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const uint32_t kind = op_kind(o.w[t]), a = op_q0(o.w[t]), b = op_q1(o.w[t]);
+      for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, kind, a, b);
+    }
   }
   // basis rotations on quantum outputs: X -> H, Y -> S^dag then H, Z -> none
   {
@@ -328,7 +333,6 @@ __global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev *__restric
   }
 
   // ---- write the model: x0, randmask, and G by columns
-  uint64_t *out = models + (size_t)blockIdx.x * model_words(n_meas);
   if (tid == 0) {
     out[0] = *X0;
     out[1] = randmask;
@@ -341,8 +345,300 @@ __global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev *__restric
 }
 
 template <int W, int BLOCK>
-hipError_t launch_w(const FragDev *d_frag, const FragDev &h, uint64_t v0, uint64_t nv,
-                    uint64_t *models, hipStream_t s) {
+__global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev F, uint64_t v0,
+                                                        uint64_t *__restrict__ models) {
+  extern __shared__ uint64_t smem[];
+  tableau_lds_body<W, BLOCK>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas), smem);
+}
+
+// ---------------------------------------------------------------------------
+// Fragments of at most 64 qubits: one wavefront per variant with the whole
+// tableau in VGPRs (lane l holds rows l and l + 64).  Gates are pure ALU
+// work on the rows' words, the pivot search is a ballot, the pivot row is
+// broadcast with readlane, and the deterministic-outcome product is a
+// butterfly reduction across the wave: no LDS and no barriers.
+
+__device__ inline uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int RPL>
+__device__ inline void gate_reg(uint64_t (&x)[RPL], uint64_t (&z)[RPL], uint32_t (&cst)[RPL], uint32_t kind,
+                                uint32_t a, uint32_t b) {
+  const uint64_t ma = 1ull << a, mb = 1ull << b;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const uint64_t xr = x[r], zr = z[r];
+    const uint32_t xa = (uint32_t)(xr >> a) & 1u, za = (uint32_t)(zr >> a) & 1u;
+    switch (kind) {
+      case G_H: {
+        cst[r] ^= xa & za;
+        const uint64_t d = (xr ^ zr) & ma;
+        x[r] = xr ^ d;
+        z[r] = zr ^ d;
+        break;
+      }
+      case G_S:
+        cst[r] ^= xa & za;
+        z[r] = zr ^ (xr & ma);
+        break;
+      case G_SDG:
+        cst[r] ^= xa & (za ^ 1u);
+        z[r] = zr ^ (xr & ma);
+        break;
+      case G_X: cst[r] ^= za; break;
+      case G_Y: cst[r] ^= xa ^ za; break;
+      case G_Z: cst[r] ^= xa; break;
+      case G_CX: {
+        const uint32_t xt = (uint32_t)(xr >> b) & 1u, zt = (uint32_t)(zr >> b) & 1u;
+        cst[r] ^= xa & zt & (xt ^ za ^ 1u);
+        x[r] = xr ^ (xa ? mb : 0ull);
+        z[r] = zr ^ (zt ? ma : 0ull);
+        break;
+      }
+      case G_CZ: {
+        const uint32_t xb = (uint32_t)(xr >> b) & 1u, zb = (uint32_t)(zr >> b) & 1u;
+        cst[r] ^= xa & xb & (za ^ zb);
+        z[r] = zr ^ (xb ? ma : 0ull) ^ (xa ? mb : 0ull);
+        break;
+      }
+      default:
+        break;
+    }
+  }
+}
+
+struct Acc1 {
+  uint64_t x, z, form;
+  uint32_t num;
+};
+
+__device__ inline void acc1_combine(Acc1 &L, const Acc1 &R) {
+  L.num = (L.num + R.num + 2u * (uint32_t)__popcll(L.z & R.x)) & 3u;
+  L.x ^= R.x;
+  L.z ^= R.z;
+  L.form ^= R.form;
+}
+
+template <int RPL, class D>
+__device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ out) {
+  const int m = (int)F.m;
+  const int R2 = 2 * m;
+  const int lane = threadIdx.x & 63;
+  const uint32_t n_meas = F.n_meas;
+  uint64_t x[RPL], z[RPL], form[RPL];
+  uint32_t cst[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    x[r] = (i < m) ? (1ull << i) : 0ull;
+    z[r] = (i >= m && i < R2) ? (1ull << (i - m)) : 0ull;
+    form[r] = 0;
+    cst[r] = 0;
+  }
+  {  // preparations: |1> = X|0>, |+> = H|0>, |+i> = S H|0>
+    uint64_t t = v;
+    for (uint32_t j = 0; j < F.n_axes; ++j) {
+      const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
+      t /= F.axis_radix[j];
+      if (F.axis_side[j] != 1 || d == 0) continue;
+      const uint32_t q = F.axis_local[j];
+      if (d == 1) {
+        gate_reg<RPL>(x, z, cst, G_X, q, 0);
+      } else {
+        gate_reg<RPL>(x, z, cst, G_H, q, 0);
+        if (d == 3) gate_reg<RPL>(x, z, cst, G_S, q, 0);
+      }
+    }
+  }
+  const uint32_t n16 = (F.n_ops + 15) / 16;
+  for (uint32_t g16 = 0; g16 < n16; ++g16) {
+    const Ops16 o = load_ops16(F.ops, g16);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) gate_reg<RPL>(x, z, cst, op_kind(o.w[t]), op_q0(o.w[t]), op_q1(o.w[t]));
+  }
+  {  // basis rotations: X -> H, Y -> S^dag then H
+    uint64_t t = v;
+    for (uint32_t j = 0; j < F.n_axes; ++j) {
+      const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
+      t /= F.axis_radix[j];
+      if (F.axis_side[j] != 0 || d == 2) continue;
+      const uint32_t q = F.axis_local[j];
+      if (d == 1) gate_reg<RPL>(x, z, cst, G_SDG, q, 0);
+      gate_reg<RPL>(x, z, cst, G_H, q, 0);
+    }
+  }
+  uint64_t x0 = 0, randmask = 0, my_grow = 0;
+  for (uint32_t j = 0; j < n_meas; ++j) {
+    const uint32_t a = F.meas[j];
+    const uint64_t ma = 1ull << a;
+    uint64_t bal[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      bal[r] = __ballot(i >= m && i < R2 && (x[r] & ma));
+    }
+    int p = -1;
+#pragma unroll
+    for (int r = RPL - 1; r >= 0; --r)
+      if (bal[r]) p = 64 * r + __ffsll((unsigned long long)bal[r]) - 1;
+    if (p >= 0) {
+      // random: row p multiplies into every other row with x_a = 1
+      const int pl = p & 63, pr = p >> 6;
+      uint64_t xsel = x[0], zsel = z[0], fsel = form[0];
+      uint32_t csel = cst[0];
+      if (RPL > 1 && pr == 1) {
+        xsel = x[RPL - 1];
+        zsel = z[RPL - 1];
+        fsel = form[RPL - 1];
+        csel = cst[RPL - 1];
+      }
+      const uint64_t xp = readlane64(xsel, pl), zp = readlane64(zsel, pl), formp = readlane64(fsel, pl);
+      const uint32_t cstp = (uint32_t)__builtin_amdgcn_readlane((int)csel, pl);
+      const uint32_t pcp = (uint32_t)__popcll(xp & zp);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < R2 && i != p && (x[r] & ma)) {
+          const uint64_t xi = x[r], zi = z[r];
+          const uint64_t xn = xi ^ xp, zn = zi ^ zp;
+          const uint32_t num = 2u * cstp + pcp + 2u * cst[r] + (uint32_t)__popcll(xi & zi) +
+                               2u * (uint32_t)__popcll(zp & xi) - (uint32_t)__popcll(xn & zn);
+          cst[r] = (num & 3u) >> 1;
+          form[r] ^= formp;
+          x[r] = xn;
+          z[r] = zn;
+        }
+      }
+      const int q = p - m;  // destabilizer row paired with the pivot (q < 64: row set 0)
+      if (lane == q) {
+        x[0] = xp;
+        z[0] = zp;
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        if (lane == pl && r == pr) {
+          x[r] = 0;
+          z[r] = ma;
+          form[r] = 1ull << j;
+          cst[r] = 0;
+        }
+      randmask |= 1ull << j;
+      if (lane == (int)j) my_grow = 1ull << j;
+    } else {
+      // deterministic: product of the stabilizers paired with destabilizers
+      // that have x_a = 1 (destabilizers are rows 0..m-1 < 64: row set 0)
+      const uint64_t dsel = __ballot(lane < m && (x[0] & ma));
+      Acc1 acc{0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i >= m && i < R2 && ((dsel >> (i - m)) & 1ull)) {
+          Acc1 row{x[r], z[r], form[r], (2u * cst[r] + (uint32_t)__popcll(x[r] & z[r])) & 3u};
+          acc1_combine(acc, row);
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        Acc1 o;
+        o.x = __shfl_xor(acc.x, off);
+        o.z = __shfl_xor(acc.z, off);
+        o.form = __shfl_xor(acc.form, off);
+        o.num = (uint32_t)__shfl_xor((int)acc.num, off);
+        if ((lane & off) == 0) {
+          acc1_combine(acc, o);
+        } else {
+          acc1_combine(o, acc);
+          acc = o;
+        }
+      }
+      x0 |= (uint64_t)((acc.num & 3u) >> 1) << j;
+      if (lane == (int)j) my_grow = acc.form;
+    }
+  }
+  if (lane == 0) {
+    out[0] = x0;
+    out[1] = randmask;
+  }
+  uint64_t col = 0;
+  for (uint32_t j = 0; j < n_meas; ++j) col |= ((readlane64(my_grow, (int)j) >> lane) & 1ull) << j;
+  if ((uint32_t)lane < n_meas) out[2 + lane] = col;
+}
+
+template <int RPL>
+__global__ __launch_bounds__(64) void tableau_reg_kernel(const FragDev F, uint64_t v0,
+                                                         uint64_t *__restrict__ models) {
+  tableau_reg_body<RPL>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas));
+}
+
+// ---------------------------------------------------------------------------
+// Batched evaluation: one persistent launch over the Clifford variants of
+// many circuits.  Workgroups pull (descriptor, variant) items from an atomic
+// queue (items are pre-sorted by cost, longest first) until it runs dry;
+// every wave sees the same item index, so the exit is uniform.
+typedef __attribute__((address_space(1))) const FragDev g_FragDev;
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tableau_batch_kernel(const FragDev *__restrict__ descs,
+                                                              const BatchItem *__restrict__ items,
+                                                              uint32_t n_items, uint32_t *__restrict__ counter,
+                                                              uint64_t *__restrict__ models, uint32_t use_reg) {
+  extern __shared__ uint64_t smem[];
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_item);
+    __syncthreads();
+    if (it >= n_items) break;
+    const __attribute__((address_space(1))) const BatchItem &item = ((const __attribute__((address_space(1))) const BatchItem *)items)[it];
+    const uint32_t di = item.desc;
+    const uint64_t v = item.variant;
+    uint64_t *out = models + item.model_off;
+    const g_FragDev &F = ((const g_FragDev *)descs)[di];
+    const uint32_t m = F.m;
+    if (BLOCK == 64 && use_reg && 2 * m <= 64) {
+      tableau_reg_body<1>(F, v, out);
+    } else if (BLOCK == 64 && use_reg && m <= 64) {
+      tableau_reg_body<2>(F, v, out);
+    } else {
+      const uint32_t W = (m + 63) / 64;
+      if (W <= 1)
+        tableau_lds_body<1, BLOCK>(F, v, out, smem);
+      else if (W <= 2)
+        tableau_lds_body<2, BLOCK>(F, v, out, smem);
+      else if (W <= 4)
+        tableau_lds_body<4, BLOCK>(F, v, out, smem);
+      else
+        tableau_lds_body<8, BLOCK>(F, v, out, smem);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t value) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+template <int RPL>
+hipError_t launch_reg(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
+  for (uint64_t done = 0; done < nv;) {
+    uint64_t chunk = nv - done;
+    if (chunk > (1ull << 30)) chunk = 1ull << 30;
+    hipLaunchKernelGGL((tableau_reg_kernel<RPL>), dim3((unsigned)chunk), dim3(64), 0, s, h, v0 + done,
+                       models + done * model_words(h.n_meas));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  return hipSuccess;
+}
+
+template <int W, int BLOCK>
+hipError_t launch_w(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
   const size_t lds = tableau_lds<W, BLOCK>(h.m);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void *)tableau_kernel<W, BLOCK>,
@@ -351,7 +647,7 @@ hipError_t launch_w(const FragDev *d_frag, const FragDev &h, uint64_t v0, uint64
   for (uint64_t done = 0; done < nv;) {
     uint64_t chunk = nv - done;
     if (chunk > (1ull << 30)) chunk = 1ull << 30;
-    hipLaunchKernelGGL((tableau_kernel<W, BLOCK>), dim3((unsigned)chunk), dim3(BLOCK), lds, s, d_frag,
+    hipLaunchKernelGGL((tableau_kernel<W, BLOCK>), dim3((unsigned)chunk), dim3(BLOCK), lds, s, h,
                        v0 + done, models + done * model_words(h.n_meas));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -362,15 +658,70 @@ hipError_t launch_w(const FragDev *d_frag, const FragDev &h, uint64_t v0, uint64
 
 }  // namespace
 
-hipError_t launch_tableau(const FragDev *d_frag, const FragDev &h, uint64_t v0, uint64_t nv,
-                          uint64_t *models, hipStream_t s) {
+hipError_t launch_tableau(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
   if (h.n_meas > (uint32_t)kMaxMeas) return hipErrorInvalidValue;
   const uint32_t W = (h.m + 63) / 64;
-  if (W <= 1) return launch_w<1, 64>(d_frag, h, v0, nv, models, s);
-  if (W <= 2) return launch_w<2, 128>(d_frag, h, v0, nv, models, s);
-  if (W <= 4) return launch_w<4, 256>(d_frag, h, v0, nv, models, s);
-  if (W <= 8) return launch_w<8, 256>(d_frag, h, v0, nv, models, s);
+  if (2 * h.m <= 64) return launch_reg<1>(h, v0, nv, models, s);
+  if (h.m <= 64) return launch_reg<2>(h, v0, nv, models, s);
+  if (W <= 2) return launch_w<2, 128>(h, v0, nv, models, s);
+  if (W <= 4) return launch_w<4, 256>(h, v0, nv, models, s);
+  if (W <= 8) return launch_w<8, 256>(h, v0, nv, models, s);
   return hipErrorInvalidValue;
+}
+
+size_t tableau_batch_lds(uint32_t max_m, uint32_t block) {
+  const uint32_t W = (max_m + 63) / 64;
+  auto pick = [&](auto wtag) -> size_t {
+    constexpr int Wc = decltype(wtag)::value;
+    if (block == 64) return tableau_lds<Wc, 64>(max_m);
+    if (block == 128) return tableau_lds<Wc, 128>(max_m);
+    return tableau_lds<Wc, 256>(max_m);
+  };
+  if (W <= 1) return pick(std::integral_constant<int, 1>());
+  if (W <= 2) return pick(std::integral_constant<int, 2>());
+  if (W <= 4) return pick(std::integral_constant<int, 4>());
+  return pick(std::integral_constant<int, 8>());
+}
+
+hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, uint32_t n_items, uint32_t *counter,
+                                uint64_t *models, uint32_t max_m, uint32_t block, uint32_t grid, uint32_t use_reg,
+                                hipStream_t s) {
+  if (max_m > 512 || grid == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, counter, (uint64_t)1, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = tableau_batch_lds(max_m, block);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  switch (block) {
+    case 64:
+      (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      hipLaunchKernelGGL(tableau_batch_kernel<64>, dim3(grid), dim3(64), lds, s, descs, items, n_items, counter,
+                         models, use_reg);
+      break;
+    case 128:
+      (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      hipLaunchKernelGGL(tableau_batch_kernel<128>, dim3(grid), dim3(128), lds, s, descs, items, n_items, counter,
+                         models, 0u);
+      break;
+    case 256:
+      (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      hipLaunchKernelGGL(tableau_batch_kernel<256>, dim3(grid), dim3(256), lds, s, descs, items, n_items, counter,
+                         models, 0u);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<uint64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
 }
 
 }  // namespace ccut

@@ -4,6 +4,8 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <cmath>
+#include <complex>
 #include <map>
 #include <numeric>
 #include <set>
@@ -34,6 +36,65 @@ struct DSU {
     if (a != b) p[a] = b;
   }
 };
+
+using cplx = std::complex<double>;
+struct M2 {
+  cplx a, b, c, d;  // [[a, b], [c, d]]
+};
+M2 mul(const M2 &L, const M2 &R) {  // L * R
+  return {L.a * R.a + L.b * R.c, L.a * R.b + L.b * R.d, L.c * R.a + L.d * R.c, L.c * R.b + L.d * R.d};
+}
+M2 gate_matrix(uint32_t kind, double theta) {
+  const double r = 1.0 / std::sqrt(2.0);
+  const cplx i(0, 1);
+  switch (kind) {
+    case G_H: return {r, r, r, -r};
+    case G_S: return {1, 0, 0, i};
+    case G_SDG: return {1, 0, 0, -i};
+    case G_X: return {0, 1, 1, 0};
+    case G_Y: return {0, -i, i, 0};
+    case G_Z: return {1, 0, 0, -1};
+    case G_T: return {1, 0, 0, std::polar(1.0, M_PI / 4)};
+    case G_TDG: return {1, 0, 0, std::polar(1.0, -M_PI / 4)};
+    case G_RZ: return {1, 0, 0, std::polar(1.0, theta)};
+    default: return {1, 0, 0, 1};
+  }
+}
+
+// Fuse every run of one-qubit gates on a qubit (up to the next two-qubit
+// gate touching it) into one matrix; runs on different qubits commute with
+// the two-qubit gates that do not touch them, so emitting a run just before
+// the first two-qubit gate on its qubit preserves the circuit.
+void fuse_one_qubit_runs(Fragment &F) {
+  const uint32_t m = F.m();
+  std::vector<M2> pend(m, M2{1, 0, 0, 1});
+  std::vector<char> has(m, 0);
+  auto flush = [&](uint32_t q) {
+    if (!has[q]) return;
+    const M2 &M = pend[q];
+    F.sv_words.push_back(pack_op(G_U2, q, 0));
+    const cplx e[4] = {M.a, M.b, M.c, M.d};
+    for (auto &z : e) {
+      F.sv_mats.push_back(z.real());
+      F.sv_mats.push_back(z.imag());
+    }
+    pend[q] = M2{1, 0, 0, 1};
+    has[q] = 0;
+  };
+  for (size_t g = 0; g < F.op_words.size(); ++g) {
+    const uint32_t w = F.op_words[g], k = op_kind(w), a = op_q0(w), b = op_q1(w);
+    if (is_two_qubit(k)) {
+      flush(a);
+      flush(b);
+      F.sv_words.push_back(w);
+      for (int t = 0; t < 8; ++t) F.sv_mats.push_back(0.0);
+    } else {
+      pend[a] = mul(gate_matrix(k, F.op_theta[g]), pend[a]);
+      has[a] = 1;
+    }
+  }
+  for (uint32_t q = 0; q < m; ++q) flush(q);
+}
 
 }  // namespace
 
@@ -189,6 +250,7 @@ int build_plan(uint32_t n, const HostOp *ops, size_t n_ops, const uint32_t *cut_
       return CCUT_E_UNSUPPORTED;
     }
     F.n_variants = nv;
+    if (!F.clifford) fuse_one_qubit_runs(F);
     if (!F.clifford && F.m() > max_nc) {
       err = "non-Clifford fragment " + std::to_string(F.index) + " has " + std::to_string(F.m()) +
             " qubits > max_nc_qubits = " + std::to_string(max_nc);
@@ -244,7 +306,7 @@ FragRequest zstring_request(const Fragment &f, const std::vector<uint64_t> &anym
 FragDev make_frag_dev(const Fragment &f, const FragRequest &r, uint64_t vid_base) {
   FragDev d{};
   d.m = f.m();
-  d.n_ops = (uint32_t)f.op_words.size();
+  d.n_ops = (uint32_t)(f.clifford ? f.op_words.size() : f.sv_words.size());
   d.n_axes = (uint32_t)f.axes.size();
   d.n_meas = (uint32_t)r.meas.size();
   d.n_req = (uint32_t)r.req_pos.size();

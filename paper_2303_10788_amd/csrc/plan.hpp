@@ -28,8 +28,12 @@ struct Axis {
 struct Fragment {
   uint32_t index = 0;
   std::vector<uint32_t> wires, segs;        // local qubit i = (wires[i], segs[i])
-  std::vector<uint32_t> op_words;           // packed local ops
+  std::vector<uint32_t> op_words;           // packed local ops, in circuit order
   std::vector<double> op_theta;
+  // non-Clifford fragments: the same ops with runs of one-qubit gates on a
+  // qubit fused into one 2x2 unitary (G_U2) for the state-vector kernel
+  std::vector<uint32_t> sv_words;
+  std::vector<double> sv_mats;              // 8 doubles per sv word
   bool clifford = true;
   std::vector<Axis> axes;
   std::vector<int32_t> out_local;           // per wire: local qubit if this fragment ends the wire, else -1

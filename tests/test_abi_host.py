@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     import ctypes
     assert ctypes.sizeof(cc.ccut_op) == 24
     assert ctypes.sizeof(cc.ccut_cut) == 8
-    assert ctypes.sizeof(cc.ccut_eval_opts) == 24
+    assert ctypes.sizeof(cc.ccut_eval_opts) == 32
 
 
 def _host_ctx(**kw):

@@ -1,0 +1,77 @@
+"""Batched evaluation (persistent autotuned tableau launch + HIP graph)
+against per-plan evaluation and the oracle, and graph replays."""
+import numpy as np
+import pytest
+
+import paper_2303_10788_amd as cc
+import workloads as W
+from oracle import cutting as C
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return cc.Context()
+
+
+def _plans(ctx, ws):
+    return [cc.Plan(ctx, w.n, w.ops, w.cuts) for w in ws]
+
+
+@pytest.mark.parametrize("shots", [0, 2000])
+def test_batch_equals_per_plan(ctx, shots):
+    ws = [W.batching_circuit(i, shots=shots) for i in range(24)]
+    print(f"batch of {len(ws)} circuits, shots={shots}", flush=True)
+    plans = _plans(ctx, ws)
+    b = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=7, method=cc.CCUT_METHOD_VARIANTS)
+    info = b.info()
+    assert info["n_items"] > 0 and info["graphed"]
+    outs = b.run()
+    for i, (p, w) in enumerate(zip(plans, ws)):
+        ref = p.marginal(w.qubits, shots=shots, seed=7, circuit=i, method=cc.CCUT_METHOD_VARIANTS)
+        assert np.array_equal(outs[i], ref), i
+        assert abs(outs[i].sum() - 1.0) < 1e-9
+
+
+def test_batch_against_oracle_small(ctx):
+    ws = [W.batching_circuit(i, shots=200) for i in (2, 6)]
+    qs = [w.qubits[:6] for w in ws]
+    plans = _plans(ctx, ws)
+    b = cc.Batch(ctx, plans, qs, shots=200, seed=3)
+    outs = b.run()
+    for i, w in enumerate(ws):
+        exp = C.marginal(w.n, w.ops, w.cuts, qs[i], shots=200, seed=3, circuit=i)
+        assert np.abs(outs[i] - exp).max() <= 1e-10, i
+
+
+def test_graph_replays_match_eager(ctx):
+    import torch
+    ws = [W.batching_circuit(i, shots=1000) for i in range(12)]
+    plans = _plans(ctx, ws)
+    qs = [w.qubits for w in ws]
+    eager = cc.Batch(ctx, plans, qs, shots=1000, seed=5, use_graph=False).run()
+    g = cc.Batch(ctx, plans, qs, shots=1000, seed=5, use_graph=True)
+    assert g.info()["graphed"]
+    other = W.tiny()
+    po = cc.Plan(ctx, other.n, other.ops, other.cuts)
+    for rep in range(4):
+        outs = g.run()
+        for i in range(len(ws)):
+            assert np.array_equal(outs[i], eager[i]), (rep, i)
+        # unrelated eager work and synchronisation between replays
+        po.marginal(other.qubits, shots=100, seed=rep)
+        x = torch.randn(1 << 16, device="cuda")
+        torch.cuda.synchronize()
+        assert float(x.abs().sum()) > 0
+
+
+def test_run_batch_one_shot(ctx):
+    ws = [W.batching_circuit(i) for i in range(3)]
+    plans = _plans(ctx, ws)
+    outs = [np.zeros(1 << len(w.qubits)) for w in ws]
+    cc.ccut_run_batch(ctx.handle, plans, cc._eval_opts(0, 0), [w.qubits for w in ws], outs)
+    for i, (p, w) in enumerate(zip(plans, ws)):
+        assert np.abs(outs[i] - p.marginal(w.qubits, circuit=i)).max() <= 1e-12

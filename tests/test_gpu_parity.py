@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import paper_2303_10788_amd as cc
 import workloads as W
 from oracle import cutting as C, philox as PX, statevector as sv
 
@@ -128,9 +129,13 @@ def test_variant_tables_random(ctx, seed):
             assert np.array_equal(got, exp), (seed, f)   # dyadic: bit-exact
         else:
             assert np.abs(got - exp).max() <= 1e-12, (seed, f)
-        Tg = plan.fragment_tensor(qubits, f)
         Te = C.pauli_tensor(fr, req, exp).T
-        assert np.abs(Tg - Te).max() <= 1e-12, (seed, f)
+        for method in (cc.CCUT_METHOD_AUTO, cc.CCUT_METHOD_VARIANTS):
+            Tg = plan.fragment_tensor(qubits, f, method=method)
+            if fr.clifford:
+                assert np.array_equal(Tg, Te), (seed, f, method)   # dyadic either way
+            else:
+                assert np.abs(Tg - Te).max() <= 1e-12, (seed, f, method)
 
 
 # ------------------------------------------------------------ marginals
@@ -170,6 +175,8 @@ def test_random_marginals(ctx, seed):
     exp = C.marginal(n, ops, cuts, qubits)
     assert np.abs(got - exp).max() <= TOL
     assert np.abs(got - sv.uncut_marginal(n, ops, qubits)).max() <= TOL
+    gv = plan.marginal(qubits, method=cc.CCUT_METHOD_VARIANTS)
+    assert np.abs(gv - exp).max() <= TOL
     gs = plan.marginal(qubits, shots=257, seed=seed)
     es = C.marginal(n, ops, cuts, qubits, shots=257, seed=seed)
     assert np.abs(gs - es).max() <= TOL
@@ -182,6 +189,7 @@ def test_mid_exact_marginal_and_sampled_small(ctx):
     got = plan.marginal(w.qubits)
     exp = C.marginal(w.n, w.ops, w.cuts, w.qubits)
     assert np.abs(got - exp).max() <= TOL
+    assert np.abs(plan.marginal(w.qubits, method=cc.CCUT_METHOD_VARIANTS) - exp).max() <= TOL
     gs = plan.marginal(w.qubits, shots=2000, seed=w.seed)
     es = C.marginal(w.n, w.ops, w.cuts, w.qubits, shots=2000, seed=w.seed)
     assert np.abs(gs - es).max() <= TOL
@@ -234,6 +242,7 @@ def test_mid_zexpect(ctx):
     got = plan.zexpect(masks)
     exp = C.zexpect(w.n, w.ops, w.cuts, w.zmasks)
     assert np.abs(got - exp).max() <= TOL
+    assert np.abs(plan.zexpect(masks, method=cc.CCUT_METHOD_VARIANTS) - exp).max() <= TOL
     gs = plan.zexpect(masks, shots=300, seed=w.seed)
     es = C.zexpect(w.n, w.ops, w.cuts, w.zmasks, shots=300, seed=w.seed)
     assert np.abs(gs - es).max() <= TOL

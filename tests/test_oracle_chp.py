@@ -140,3 +140,17 @@ def test_per_shot_sampling_is_a_pure_function_of_the_key():
     assert np.array_equal(a[16:32], b)
     c = t.sample([0, 1, 2, 3], seed=4, vid=9, shot0=0, nshots=64)
     assert not np.array_equal(a, c) or t.exact([0, 1, 2, 3]).max() == 1.0
+
+
+def test_many_string_expectations_match_single():
+    rng = np.random.default_rng(77)
+    for trial in range(6):
+        n = int(rng.integers(3, 9))
+        ops = W.random_circuit(n, 30, 900 + trial, kinds=CLIFF)
+        t = _tab(n, ops)
+        x, z, r = t.dump()
+        masks = [int(m) for m in rng.integers(1, 1 << n, size=20)]
+        many = stab.z_expectations(x[n:2 * n], z[n:2 * n], r[n:2 * n], masks, n)
+        for mk, e in zip(masks, many):
+            supp = [q for q in range(n) if (mk >> q) & 1]
+            assert e == stab.z_expectation(x[n:2 * n], z[n:2 * n], r[n:2 * n], supp)

@@ -1,0 +1,97 @@
+"""Pins for the learned-proposal oracle: hand-derived gradients against
+finite differences, Adam against its definition on a quadratic, the
+proposal's normalisation, term sampling against the empirical distribution,
+and unbiasedness of the importance-sampling estimator."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(0)
+    F, H, B = 7, 9, 13
+    params = mlp.init_params(F, H, 1)
+    params = [(W + 0.05 * rng.normal(size=W.shape), b + 0.1 * rng.normal(size=b.shape)) for W, b in params]
+    X = rng.normal(size=(B, F))
+    y = rng.normal(size=B)
+    L, grads = mlp.loss_and_grads(params, X, y)
+    h = 1e-6
+    for i in range(4):
+        for j in range(2):
+            p = params[i][j]
+            g = grads[i][j]
+            idx = [tuple(rng.integers(0, s) for s in p.shape) for _ in range(6)]
+            for ix in idx:
+                plus = [list(t) for t in params]
+                minus = [list(t) for t in params]
+                pp = p.copy(); pp[ix] += h
+                pm = p.copy(); pm[ix] -= h
+                plus[i][j] = pp
+                minus[i][j] = pm
+                Lp, _ = mlp.loss_and_grads([tuple(t) for t in plus], X, y)
+                Lm, _ = mlp.loss_and_grads([tuple(t) for t in minus], X, y)
+                fd = (Lp - Lm) / (2 * h)
+                assert abs(fd - g[ix]) <= 1e-6 * max(1.0, abs(fd)), (i, j, ix)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(2)
+    X = rng.normal(size=(256, 6))
+    y = np.sin(X[:, 0]) + 0.5 * X[:, 1] ** 2
+    params = mlp.init_params(6, 32, 3)
+    st = mlp.adam_state(params)
+    L0, _ = mlp.loss_and_grads(params, X, y)
+    for _ in range(300):
+        L, g = mlp.loss_and_grads(params, X, y)
+        params, st = mlp.adam_step(params, g, st, 1e-2)
+    assert L < 0.1 * L0
+
+
+def test_adam_matches_definition_on_quadratic():
+    params = [(np.array([[3.0]]), np.array([0.0]))] * 4
+    grads = [(np.array([[6.0]]), np.array([0.0]))] * 4
+    st = mlp.adam_state(params)
+    new, _ = mlp.adam_step(params, grads, st, 0.1)
+    # first Adam step moves each coordinate by lr * sign(g) (bias-corrected m/sqrt(v) = g/|g|)
+    assert np.isclose(new[0][0][0, 0], 3.0 - 0.1, atol=1e-7)
+
+
+def test_proposal_and_cdf():
+    rng = np.random.default_rng(5)
+    logits = rng.normal(size=1000) * 3
+    q = mlp.proposal(logits)
+    assert np.isclose(q.sum(), 1.0)
+    assert q.min() >= mlp.EPS / 1000 * 0.999
+    cdf = mlp.integer_cdf(q)
+    assert np.all(np.diff(cdf.astype(np.float64)) >= 0)
+    assert abs(float(cdf[-1]) / 2 ** 40 - 1.0) < 1e-6
+
+
+def test_term_sampling_distribution():
+    q = np.array([0.5, 0.25, 0.125, 0.125])
+    cdf = mlp.integer_cdf(q)
+    terms = mlp.sample_terms(cdf, 4000, seed=9, cid=1)
+    freq = np.bincount(terms, minlength=4) / 4000
+    assert np.all(np.abs(freq - q) < 4 * np.sqrt(q * (1 - q) / 4000))
+
+
+def test_is_estimator_unbiased():
+    rng = np.random.default_rng(11)
+    K, nb = 64, 8
+    w = rng.normal(size=(K, nb)) * (rng.random(K) < 0.3)[:, None]
+    exact = w.sum(axis=0)
+    q = mlp.proposal(rng.normal(size=K))
+    cdf = mlp.integer_cdf(q)
+    ests = np.array([mlp.is_estimate(lambda P: w[P], mlp.sample_terms(cdf, 200, seed=s, cid=0), q)
+                     for s in range(60)])
+    se = ests.std(axis=0, ddof=1) / np.sqrt(len(ests))
+    assert np.all(np.abs(ests.mean(axis=0) - exact) <= 4 * se + 1e-12)
+
+
+def test_exact_proposal_gives_zero_variance_estimator():
+    # q proportional to |w| with a single output: every sample gives the exact sum
+    w = np.array([0.0, 2.0, 0.0, 1.0, 1.0])
+    q = np.abs(w) / np.abs(w).sum()
+    est = mlp.is_estimate(lambda P: np.array([w[P]]), [1, 3, 4, 1], q)
+    assert np.isclose(est[0], w.sum())
