@@ -16,6 +16,12 @@ Readings (the paper has no learned part):
   philox(ctr = (j, 0, lo32(cid), hi32(cid)), key = (lo32(seed) ^ 0x7E570001,
   hi32(seed))) and picks the smallest P with C_P > u (the modulo bias is at
   most C_last / 2^64).
+* term features (F = 6k, padded to a multiple of 64): per cut c, a one-hot
+  of P_c, then phi(s_up) and phi(s_dn), where s_side(c, p) is the share of
+  the squared column-norm mass of the fragment on that side of cut c (up =
+  the fragment where c is a quantum output, dn = where it is a quantum
+  input) carried by columns whose digit for c equals p, and
+  phi(s) = max(ln s, -40) / 40.
 """
 from __future__ import annotations
 
@@ -131,3 +137,69 @@ def is_estimate(term_weight, terms, q):
         v = term_weight(int(P)) / q[P]
         acc = v if acc is None else acc + v
     return acc / len(terms)
+
+
+# ------------------------------------------------------ term model inputs
+
+FEATURE_FLOOR = -40.0
+
+
+def column_norms(T):
+    """n_f[p] = ||T_f[.; p]||_2 for a fragment tensor T_f[b][p]."""
+    return np.sqrt(np.sum(np.asarray(T, dtype=np.float64) ** 2, axis=0))
+
+
+def cut_shares(frags, tensors, k):
+    """(up, dn): arrays [k][4]; side[c][p] = sum over columns p_f of the
+    fragment on that side of cut c with digit p on c of n_f[p_f]^2, divided
+    by the sum over all columns."""
+    up = np.zeros((k, 4))
+    dn = np.zeros((k, 4))
+    for f, T in zip(frags, tensors):
+        n2 = column_norms(T) ** 2
+        tot = n2.sum()
+        idx = np.arange(n2.size)
+        for j, ax in enumerate(f.axes):
+            digit = (idx >> (2 * j)) & 3
+            share = np.array([n2[digit == p].sum() for p in range(4)]) / tot
+            (up if ax.side == 0 else dn)[ax.cut] = share
+    return up, dn
+
+
+def phi(s):
+    with np.errstate(divide="ignore"):
+        return np.maximum(np.log(np.asarray(s, dtype=np.float64)), FEATURE_FLOOR) / -FEATURE_FLOOR
+
+
+def features(P, k, up, dn, F=None):
+    """Feature row of term P (length F, default 6k rounded up to 64)."""
+    if F is None:
+        F = -(-6 * k // 64) * 64
+    x = np.zeros(F)
+    for c in range(k):
+        p = (P >> (2 * c)) & 3
+        x[6 * c + p] = 1.0
+        x[6 * c + 4] = phi(up[c][p])
+        x[6 * c + 5] = phi(dn[c][p])
+    return x
+
+
+def log_weight(P, frags, tensors, k):
+    """y(P) = ln(2^-k prod_f n_f[P|f] + 2^-60): the outer-product structure
+    of w_P makes its 2-norm the product of the fragments' column norms."""
+    v = 2.0 ** (-k)
+    for f, T in zip(frags, tensors):
+        v *= column_norms(T)[f.p_index(P)]
+    return float(np.log(v + LABEL_FLOOR))
+
+
+def term_vector(frags, reqs, tensors, k, P, nq):
+    """w_P(b) = 2^-k prod_f T_f[b_f; P|f] over all 2^nq outputs b."""
+    b = np.arange(1 << nq, dtype=np.int64)
+    out = np.full(1 << nq, 2.0 ** (-k))
+    for f, r, T in zip(frags, reqs, tensors):
+        bi = np.zeros_like(b)
+        for i, u in enumerate(r.req_user):
+            bi |= ((b >> u) & 1) << i
+        out = out * T[bi, f.p_index(P)]
+    return out

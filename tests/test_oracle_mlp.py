@@ -95,3 +95,66 @@ def test_exact_proposal_gives_zero_variance_estimator():
     q = np.abs(w) / np.abs(w).sum()
     est = mlp.is_estimate(lambda P: np.array([w[P]]), [1, 3, 4, 1], q)
     assert np.isclose(est[0], w.sum())
+
+
+# ---------------------------------------------------------- term model inputs
+
+def _small_cut_parts(seed=3):
+    import workloads as W
+    from oracle import cutting as C
+    ops = W.random_circuit(9, 40, seed)
+    cuts = W.random_cuts(9, ops, 3, seed)
+    qubits = [0, 2, 3, 5, 7, 8]
+    R, parts = C.marginal(9, ops, cuts, qubits, return_parts=True)
+    return ops, cuts, qubits, R, parts
+
+
+def test_term_vectors_sum_to_uncut_marginal():
+    from oracle import statevector as SV
+    ops, cuts, qubits, R, parts = _small_cut_parts()
+    k = len(cuts)
+    tot = sum(mlp.term_vector(parts["frags"], parts["reqs"], parts["tensors"], k, P, len(qubits))
+              for P in range(4 ** k))
+    ref = SV.uncut_marginal(9, ops, qubits)
+    assert np.abs(tot - ref).max() <= 1e-12
+
+
+def test_log_weight_is_norm_of_term_vector():
+    ops, cuts, qubits, R, parts = _small_cut_parts()
+    k = len(cuts)
+    for P in range(4 ** k):
+        v = mlp.term_vector(parts["frags"], parts["reqs"], parts["tensors"], k, P, len(qubits))
+        y = mlp.log_weight(P, parts["frags"], parts["tensors"], k)
+        assert abs(y - np.log(np.linalg.norm(v) + mlp.LABEL_FLOOR)) <= 1e-9, P
+
+
+def test_cut_shares_closed_form_on_product_tensor():
+    from types import SimpleNamespace as NS
+    rng = np.random.default_rng(4)
+    a = [rng.normal(size=4) for _ in range(3)]
+    # one fragment, three axes (cuts 2, 0, 1; outputs on the first two), one row
+    cols = np.array([a[0][p & 3] * a[1][(p >> 2) & 3] * a[2][(p >> 4) & 3] for p in range(64)])
+    frag = NS(axes=[NS(cut=2, side=0), NS(cut=0, side=0), NS(cut=1, side=1)])
+    up, dn = mlp.cut_shares([frag], [cols[None, :]], 3)
+    assert np.allclose(up[2], a[0] ** 2 / (a[0] ** 2).sum())
+    assert np.allclose(up[0], a[1] ** 2 / (a[1] ** 2).sum())
+    assert np.allclose(dn[1], a[2] ** 2 / (a[2] ** 2).sum())
+    assert np.allclose(up[1], 0) and np.allclose(dn[0], 0) and np.allclose(dn[2], 0)
+
+
+def test_cut_shares_sum_to_one_on_real_fragments():
+    ops, cuts, qubits, R, parts = _small_cut_parts()
+    up, dn = mlp.cut_shares(parts["frags"], parts["tensors"], len(cuts))
+    assert np.allclose(up.sum(axis=1), 1.0) and np.allclose(dn.sum(axis=1), 1.0)
+
+
+def test_feature_layout():
+    up = np.array([[1.0, np.exp(-20.0), 0.0, 0.5]])
+    dn = np.array([[0.25, 0.25, 0.25, 0.25]])
+    x = mlp.features(1, 1, up, dn)
+    assert x.shape == (64,)
+    assert list(x[:4]) == [0, 1, 0, 0]
+    assert np.isclose(x[4], -0.5) and np.isclose(x[5], np.log(0.25) / 40)
+    assert np.all(x[6:] == 0)
+    x2 = mlp.features(2, 1, up, dn)
+    assert x2[4] == -1.0 and x2[2] == 1.0
