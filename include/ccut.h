@@ -12,6 +12,9 @@
  *  - every call returns a ccut_status; no C++ exception crosses the ABI;
  *    on failure ccut_last_error() describes the first error;
  *  - handles are owned by the library and freed by the matching *_destroy;
+ *    objects created from a context (plans, batches, term models,
+ *    networks) keep it alive: destroying the context first defers its
+ *    release until the last of them is destroyed;
  *  - a context is not thread-safe: use one per host thread;
  *  - device work runs on the context's HIP stream and every call returns
  *    only after its results are in the caller's buffer (host or device);
@@ -246,6 +249,91 @@ void ccut_batch_destroy(ccut_batch *b);
 ccut_status ccut_run_batch(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
                            const uint32_t *const *qubits, const uint32_t *nq, double *const *outs);
 
+/* ------------------------------------------------ learned term proposal */
+
+/* Importance sampling of the recombination sum (Sec. V-C), whose 4^k cut
+ * terms make exhaustive contraction the method's cost wall (Sec. III-B).
+ * The paper has no learned part; readings of this extension:
+ *  - the weight of term P is the vector w_P(b) = 2^-k prod_f T_f[b_f; P|f];
+ *    its label is y(P) = ln(||w_P||_2 + 2^-60), and ||w_P||_2 is the
+ *    product of the fragments' column norms;
+ *  - features (width F = 6k rounded up to 64, bf16): per cut c, a one-hot
+ *    of P_c, then phi(share_up(c, P_c)) and phi(share_down(c, P_c)), where
+ *    share_side(c, p) is the fraction of the squared column-norm mass of the
+ *    fragment on that side of c (up: c is its quantum output; down: its
+ *    quantum input) held by columns with digit p on c, and
+ *    phi(s) = max(ln s, -40) / 40;
+ *  - proposal q = (1 - eps) softmax(logits) + eps / 4^k;
+ *  - term j of a draw: u = (o1 2^32 + o0) mod C[4^k - 1] with
+ *    (o0, o1) = philox(ctr = (j, 0, lo32(cid), hi32(cid)),
+ *    key = (lo32(seed) ^ 0x7E570001, hi32(seed))), C the inclusive prefix sum
+ *    of floor(q_P 2^40); the term is the smallest P with C[P] > u;
+ *  - estimate R_hat[b] = (1/N) sum_j w_{P_j}(b) / q(P_j), summed in fp64.
+ * Every device pointer below is caller-owned device memory. */
+typedef struct ccut_learned ccut_learned; /* per-circuit term model */
+typedef struct ccut_mlp ccut_mlp;         /* F -> H -> H -> H -> 1 ReLU network */
+
+/* Evaluate every fragment tensor of the marginal request once (as
+ * ccut_marginal would: shots, seed, method and circuit from eo) and keep
+ * them with their column norms and per-cut share tables on the device. */
+ccut_status ccut_learned_create(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                                ccut_learned **out);
+/* k cuts, 4^k terms, feature width F. */
+ccut_status ccut_learned_info(const ccut_learned *L, uint32_t *k, uint64_t *n_terms, uint32_t *width);
+/* Feature rows x[n][F] (bf16) of terms[0..n) (device u64), or of terms
+ * first..first+n-1 when terms is NULL. */
+ccut_status ccut_learned_features(ccut_learned *L, const uint64_t *terms, uint64_t first, uint64_t n,
+                                  uint16_t *x);
+/* kind 0: labels y(P) (fp32); kind 1: the product-of-shares log-weights
+ * sum_c 40 (phi_up + phi_down) (the proposal without a network); kind 2:
+ * y(P) / 40, the network's regression target. */
+ccut_status ccut_learned_log_weights(ccut_learned *L, const uint64_t *terms, uint64_t first, uint64_t n, int kind,
+                                     float *y);
+/* The terms with nonzero weight in ascending order: the first min(count,
+ * cap) go to terms[], the total count to *count (host). */
+ccut_status ccut_learned_support(ccut_learned *L, uint64_t cap, uint64_t *terms, uint64_t *count);
+/* Network logits over all 4^k terms (fp32 [4^k]): 40 times the network
+ * output on each term's feature row. */
+ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *mlp, float *logits);
+/* Draw n terms from q (fp64 [4^k]) with circuit id = eo->circuit of the
+ * create call and contract them: out[2^nq] = R_hat (host or device).
+ * terms_out (device, n entries) may be NULL. */
+ccut_status ccut_learned_estimate(ccut_learned *L, const double *q, uint64_t n, uint64_t seed, double *out,
+                                  int on_device, uint64_t *terms_out);
+/* The exhaustive contraction of the kept tensors (equals ccut_marginal). */
+ccut_status ccut_learned_exhaustive(ccut_learned *L, double *out, int on_device);
+void ccut_learned_destroy(ccut_learned *L);
+
+/* q[K] (fp64) from logits[K] (fp32), or uniform when logits is NULL. */
+ccut_status ccut_proposal(ccut_ctx *ctx, const float *logits, uint64_t K, double eps, double *q);
+/* n terms drawn from q[K] as above (device u64 out[n]). */
+ccut_status ccut_sample_terms(ccut_ctx *ctx, const double *q, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
+                              uint64_t *out);
+
+/* Network with F inputs (F % 64 == 0) and width H (H % 64 == 0, H <= 256).
+ * Parameters, flat fp32 in this order: W1[H][F], b1[H], W2[H][H], b2[H],
+ * W3[H][H], b3[H], w4[H], b4 (count H F + 2 H^2 + 4 H + 1).  Products use
+ * bf16 copies of the weights and activations with fp32 accumulation; the
+ * master parameters and Adam state are fp32. */
+ccut_status ccut_mlp_create(ccut_ctx *ctx, uint32_t F, uint32_t H, ccut_mlp **out);
+/* Set (resets the Adam state) or read the parameters (host arrays). */
+ccut_status ccut_mlp_set_params(ccut_mlp *M, const float *params, size_t count);
+ccut_status ccut_mlp_get_params(ccut_mlp *M, float *params, size_t count);
+/* y[n] (fp32, device) from x[n][F] (bf16, device). */
+ccut_status ccut_mlp_forward(ccut_mlp *M, const uint16_t *x, uint64_t n, float *y);
+/* Mean squared error against t[n] and its gradient (host, flat layout as
+ * the parameters); n % 64 == 0. */
+ccut_status ccut_mlp_gradients(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t n, float *grads,
+                               double *loss);
+/* `steps` Adam steps (lr, b1 = 0.9, b2 = 0.999, eps = 1e-8), each on a
+ * mini-batch of `batch` rows (batch % 64 == 0) of the data set x[n][F],
+ * t[n]: row i of step s is data row philox(ctr = (i, s, 0x4D4C5000, 0),
+ * key = seed) mod n, or row i when batch == n.  losses (host, `steps`
+ * entries) may be NULL. */
+ccut_status ccut_mlp_train(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t n, uint32_t batch,
+                           uint32_t steps, float lr, uint64_t seed, float *losses);
+void ccut_mlp_destroy(ccut_mlp *M);
+
 /* ---------------------------------------------------------------- timing */
 
 /* Kernel timing with HIP events recorded around every launch on the
@@ -263,7 +351,9 @@ enum {
   CCUT_K_RECOMBINE = 7,
   CCUT_K_ZRECOMBINE = 8,
   CCUT_K_HEISENBERG = 9,
-  CCUT_K_COUNT = 10
+  CCUT_K_MLP = 10,
+  CCUT_K_TERMS = 11,
+  CCUT_K_COUNT = 12
 };
 ccut_status ccut_timing_enable(ccut_ctx *ctx, int enable);
 ccut_status ccut_timing_reset(ccut_ctx *ctx);

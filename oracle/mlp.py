@@ -142,6 +142,9 @@ def is_estimate(term_weight, terms, q):
 # ------------------------------------------------------ term model inputs
 
 FEATURE_FLOOR = -40.0
+# the network regresses y / LABEL_SCALE; its logits are LABEL_SCALE times
+# its output
+LABEL_SCALE = 40.0
 
 
 def column_norms(T):

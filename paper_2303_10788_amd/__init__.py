@@ -27,7 +27,7 @@ CCUT_FP64, CCUT_FP32_MFMA_FP64SUM = 0, 1
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
 KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
            "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
-           "heisenberg_kernels")
+           "heisenberg_kernels", "mlp_kernels", "term_kernels")
 STATUS_NAMES = {0: "CCUT_OK", -1: "CCUT_E_INVALID", -2: "CCUT_E_OOM", -3: "CCUT_E_DEVICE",
                 -4: "CCUT_E_NC_TOO_WIDE", -5: "CCUT_E_TOO_MANY_CUTS", -6: "CCUT_E_CANCELLED",
                 -7: "CCUT_E_UNSUPPORTED"}
@@ -104,6 +104,27 @@ SIGNATURES = {
     "ccut_timing_reset": ([_P], ctypes.c_int),
     "ccut_timing_read": ([_P, ctypes.c_uint32, _U64P, _DP], ctypes.c_int),
     "ccut_kernel_name": ([ctypes.c_uint32], ctypes.c_char_p),
+    "ccut_learned_create": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.POINTER(_P)],
+                            ctypes.c_int),
+    "ccut_learned_info": ([_P, _U32P, _U64P, _U32P], ctypes.c_int),
+    "ccut_learned_features": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P], ctypes.c_int),
+    "ccut_learned_log_weights": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, _P], ctypes.c_int),
+    "ccut_learned_support": ([_P, ctypes.c_uint64, _P, _U64P], ctypes.c_int),
+    "ccut_learned_logits": ([_P, _P, _P], ctypes.c_int),
+    "ccut_learned_estimate": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, ctypes.c_int, _P], ctypes.c_int),
+    "ccut_learned_exhaustive": ([_P, _P, ctypes.c_int], ctypes.c_int),
+    "ccut_learned_destroy": ([_P], None),
+    "ccut_proposal": ([_P, _P, ctypes.c_uint64, ctypes.c_double, _P], ctypes.c_int),
+    "ccut_sample_terms": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _P],
+                          ctypes.c_int),
+    "ccut_mlp_create": ([_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_P)], ctypes.c_int),
+    "ccut_mlp_set_params": ([_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t], ctypes.c_int),
+    "ccut_mlp_get_params": ([_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t], ctypes.c_int),
+    "ccut_mlp_forward": ([_P, _P, ctypes.c_uint64, _P], ctypes.c_int),
+    "ccut_mlp_gradients": ([_P, _P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), _DP], ctypes.c_int),
+    "ccut_mlp_train": ([_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
+                        ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "ccut_mlp_destroy": ([_P], None),
 }
 
 _lib = None
@@ -487,3 +508,245 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------- learned term proposal
+# Device buffers are torch tensors on the context's device (bf16 rows are
+# torch.bfloat16, labels/logits float32, q float64, term lists int64).
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ccut_learned_create(plan, ctx, eo, qubits):
+    q, qp = _u32(qubits)
+    h = _P()
+    _check(lib().ccut_learned_create(plan, ctypes.byref(eo), qp, len(q), ctypes.byref(h)), ctx)
+    return h
+
+
+def ccut_learned_info(L):
+    k, K, w = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint32()
+    _check(lib().ccut_learned_info(L, ctypes.byref(k), ctypes.byref(K), ctypes.byref(w)), None)
+    return k.value, K.value, w.value
+
+
+def ccut_learned_features(L, ctx, terms, first, n, x):
+    _check(lib().ccut_learned_features(L, _dptr(terms), first, n, _dptr(x)), ctx)
+
+
+def ccut_learned_log_weights(L, ctx, terms, first, n, kind, y):
+    _check(lib().ccut_learned_log_weights(L, _dptr(terms), first, n, kind, _dptr(y)), ctx)
+
+
+def ccut_learned_support(L, ctx, cap, terms):
+    cnt = ctypes.c_uint64()
+    _check(lib().ccut_learned_support(L, cap, _dptr(terms), ctypes.byref(cnt)), ctx)
+    return cnt.value
+
+
+def ccut_learned_logits(L, ctx, mlp, logits):
+    _check(lib().ccut_learned_logits(L, mlp, _dptr(logits)), ctx)
+
+
+def ccut_learned_estimate(L, ctx, q, n, seed, out, terms_out=None):
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_learned_estimate(L, _dptr(q), n, int(seed) & 0xFFFFFFFFFFFFFFFF, p, dev, _dptr(terms_out)),
+           ctx)
+
+
+def ccut_learned_exhaustive(L, ctx, out):
+    p, dev = _out_ptr(out)
+    _check(lib().ccut_learned_exhaustive(L, p, dev), ctx)
+
+
+def ccut_learned_destroy(L) -> None:
+    lib().ccut_learned_destroy(L)
+
+
+def ccut_proposal(ctx, logits, K, eps, q):
+    _check(lib().ccut_proposal(ctx, _dptr(logits), K, eps, _dptr(q)), ctx)
+
+
+def ccut_sample_terms(ctx, q, K, n, seed, cid, out):
+    _check(lib().ccut_sample_terms(ctx, _dptr(q), K, n, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                   int(cid) & 0xFFFFFFFFFFFFFFFF, _dptr(out)), ctx)
+
+
+def ccut_mlp_create(ctx, F, H):
+    h = _P()
+    _check(lib().ccut_mlp_create(ctx, F, H, ctypes.byref(h)), ctx)
+    return h
+
+
+def ccut_mlp_set_params(M, ctx, params: np.ndarray):
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().ccut_mlp_set_params(M, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size), ctx)
+
+
+def ccut_mlp_get_params(M, ctx, count):
+    a = np.zeros(count, dtype=np.float32)
+    _check(lib().ccut_mlp_get_params(M, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), count), ctx)
+    return a
+
+
+def ccut_mlp_forward(M, ctx, x, n, y):
+    _check(lib().ccut_mlp_forward(M, _dptr(x), n, _dptr(y)), ctx)
+
+
+def ccut_mlp_gradients(M, ctx, x, t, n, count):
+    g = np.zeros(count, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(lib().ccut_mlp_gradients(M, _dptr(x), _dptr(t), n, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    ctypes.byref(loss)), ctx)
+    return g, loss.value
+
+
+def ccut_mlp_train(M, ctx, x, t, n, batch, steps, lr, seed):
+    losses = np.zeros(max(steps, 1), dtype=np.float32)
+    _check(lib().ccut_mlp_train(M, _dptr(x), _dptr(t), n, batch, steps, lr, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), ctx)
+    return losses[:steps]
+
+
+def ccut_mlp_destroy(M) -> None:
+    lib().ccut_mlp_destroy(M)
+
+
+def mlp_param_count(F: int, H: int) -> int:
+    return H * F + 2 * H * H + 4 * H + 1
+
+
+def mlp_pack(params) -> np.ndarray:
+    """Flat parameter vector from [(W1, b1), (W2, b2), (W3, b3), (w4, b4)]."""
+    return np.concatenate([np.ravel(a) for W, b in params for a in (W, b)]).astype(np.float32)
+
+
+def mlp_unpack(flat, F: int, H: int):
+    shapes = [((H, F), (H,)), ((H, H), (H,)), ((H, H), (H,)), ((1, H), (1,))]
+    out, o = [], 0
+    for sw, sb in shapes:
+        nw, nb = int(np.prod(sw)), int(np.prod(sb))
+        out.append((np.asarray(flat[o:o + nw]).reshape(sw), np.asarray(flat[o + nw:o + nw + nb]).reshape(sb)))
+        o += nw + nb
+    return out
+
+
+class Mlp:
+    """The F -> H -> H -> H -> 1 ReLU network on the device."""
+
+    def __init__(self, ctx: Context, F: int = 64, H: int = 256):
+        self.ctx, self.F, self.H = ctx, F, H
+        self.count = mlp_param_count(F, H)
+        self.handle = ccut_mlp_create(ctx.handle, F, H)
+
+    def set_params(self, flat):
+        ccut_mlp_set_params(self.handle, self.ctx.handle, flat)
+
+    def get_params(self):
+        return ccut_mlp_get_params(self.handle, self.ctx.handle, self.count)
+
+    def forward(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        ccut_mlp_forward(self.handle, self.ctx.handle, x, x.shape[0], y)
+        return y
+
+    def gradients(self, x, t):
+        return ccut_mlp_gradients(self.handle, self.ctx.handle, x, t, x.shape[0], self.count)
+
+    def train(self, x, t, *, batch, steps, lr=1e-3, seed=0):
+        return ccut_mlp_train(self.handle, self.ctx.handle, x, t, x.shape[0], batch, steps, lr, seed)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ccut_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Learned:
+    """Per-circuit term model: fragment tensors, column norms and share
+    tables of one marginal request, kept on the device."""
+
+    def __init__(self, plan: Plan, qubits, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO):
+        self.plan, self.ctx = plan, plan.ctx
+        self.nq = len(qubits)
+        self.handle = ccut_learned_create(plan.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, method),
+                                          qubits)
+        self.k, self.K, self.width = ccut_learned_info(self.handle)
+
+    def features(self, terms=None, first=0, n=None):
+        import torch
+        n = (terms.shape[0] if terms is not None else self.K - first) if n is None else n
+        x = torch.empty((n, self.width), dtype=torch.bfloat16, device="cuda")
+        ccut_learned_features(self.handle, self.ctx.handle, terms, first, n, x)
+        return x
+
+    def log_weights(self, terms=None, first=0, n=None, kind=0):
+        import torch
+        n = (terms.shape[0] if terms is not None else self.K - first) if n is None else n
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        ccut_learned_log_weights(self.handle, self.ctx.handle, terms, first, n, kind, y)
+        return y
+
+    def support(self, cap=1 << 16):
+        import torch
+        t = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+        cnt = ccut_learned_support(self.handle, self.ctx.handle, cap, t)
+        return t[:min(cnt, cap)], cnt
+
+    def logits(self, mlp: Mlp):
+        import torch
+        y = torch.empty(self.K, dtype=torch.float32, device="cuda")
+        ccut_learned_logits(self.handle, self.ctx.handle, mlp.handle, y)
+        return y
+
+    def estimate(self, q, n, seed, out=None, terms_out=None):
+        if out is None:
+            out = np.zeros(1 << self.nq)
+        ccut_learned_estimate(self.handle, self.ctx.handle, q, n, seed, out, terms_out)
+        return out
+
+    def exhaustive(self, out=None):
+        if out is None:
+            out = np.zeros(1 << self.nq)
+        ccut_learned_exhaustive(self.handle, self.ctx.handle, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ccut_learned_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def proposal(ctx: Context, logits, K=None, eps=0.05):
+    """q (float64 device tensor) from logits, or uniform when logits is None."""
+    import torch
+    K = logits.shape[0] if K is None else K
+    q = torch.empty(K, dtype=torch.float64, device="cuda")
+    ccut_proposal(ctx.handle, logits, K, eps, q)
+    return q
+
+
+def sample_terms(ctx: Context, q, n, seed, cid):
+    import torch
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    ccut_sample_terms(ctx.handle, q, q.shape[0], n, seed, cid, out)
+    return out

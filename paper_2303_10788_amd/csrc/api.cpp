@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -84,6 +85,8 @@ struct ccut_ctx {
   uint32_t max_nc = 12, max_cuts = 12;
   std::string err;
   std::atomic<int> cancel{0};
+  int children = 0;     // plans, batches, term models and networks created from this context
+  bool closed = false;  // ccut_ctx_destroy was called while children were alive
   Arena arena;
   bool timing = false;
   std::vector<PendingTiming> pending;
@@ -438,21 +441,12 @@ ccut_status heis_tensor(ccut_plan *p, const Fragment &f, const FragRequest &r, u
 }
 
 
-// Contract the fragment tensors into out[2^nq].  fp64 with few terms x
-// outputs: the plain ascending sum; otherwise the K-split MFMA contraction
-// (fp32 products with fp64 across K-chunks, or fp64 MFMA).
-ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
-  const uint64_t K = 1ull << (2 * args.k);
-  if (!fp32 && (K << nq) <= (1ull << 26)) {
-    RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
-    if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
-    KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_recombine_fp64(dargs, nq, res, c->cur));
-    return CCUT_OK;
-  }
-  GemmArgs g{};
+// Operands of the dense contraction: the fragment with the most requested
+// bits forms the column side, the others the row side.
+void make_gemm_args(const RecombArgs &args, GemmArgs &g) {
+  g = GemmArgs{};
   g.k = args.k;
-  g.K = K;
+  g.K = 1ull << (2 * args.k);
   uint32_t rf = 0;
   for (uint32_t f = 1; f < args.n_frags; ++f)
     if (args.f[f].n_req > args.f[rf].n_req) rf = f;
@@ -472,6 +466,9 @@ ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp3
   }
   g.M = 1u << lbits;
   g.N = 1u << args.f[rf].n_req;
+}
+
+ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res) {
   const uint32_t splits = gemm_splits(g);
   GemmArgs *dg = (GemmArgs *)upload(c, &g, sizeof(g));
   double *partial = aget<double>(c, (size_t)splits * g.M * g.N);
@@ -479,6 +476,23 @@ ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp3
   KTimer t(c, CCUT_K_RECOMBINE);
   HIP_TRY(c, launch_recombine_gemm(g, dg, fp32, partial, splits, res, c->cur));
   return CCUT_OK;
+}
+
+// Contract the fragment tensors into out[2^nq].  fp64 with few terms x
+// outputs: the plain ascending sum; otherwise the K-split MFMA contraction
+// (fp32 products with fp64 across K-chunks, or fp64 MFMA).
+ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
+  const uint64_t K = 1ull << (2 * args.k);
+  if (!fp32 && (K << nq) <= (1ull << 26)) {
+    RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
+    if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_recombine_fp64(dargs, nq, res, c->cur));
+    return CCUT_OK;
+  }
+  GemmArgs g;
+  make_gemm_args(args, g);
+  return run_gemm(c, g, fp32, res);
 }
 
 bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo) {
@@ -536,8 +550,10 @@ ccut_status ccut_ctx_create(const ccut_opts *opts, ccut_ctx **out) {
   return CCUT_OK;
 }
 
-void ccut_ctx_destroy(ccut_ctx *c) {
-  if (!c) return;
+}  // extern "C"
+
+namespace {
+void ctx_free(ccut_ctx *c) {
   if (c->device >= 0) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
@@ -555,6 +571,27 @@ void ccut_ctx_destroy(ccut_ctx *c) {
     c->arena.release();
   }
   delete c;
+}
+}  // namespace
+
+namespace {
+// Objects created from a context keep it alive: its release waits for the
+// last of them.
+void ctx_retain(ccut_ctx *c) { ++c->children; }
+void ctx_release(ccut_ctx *c) {
+  if (c && --c->children == 0 && c->closed) ctx_free(c);
+}
+}  // namespace
+
+extern "C" {
+
+void ccut_ctx_destroy(ccut_ctx *c) {
+  if (!c) return;
+  if (c->children > 0) {
+    c->closed = true;
+    return;
+  }
+  ctx_free(c);
 }
 
 const char *ccut_last_error(const ccut_ctx *c) { return c ? c->err.c_str() : g_create_err.c_str(); }
@@ -582,13 +619,17 @@ ccut_status ccut_plan_create(ccut_ctx *c, uint32_t n_qubits, const ccut_op *ops,
                       err);
   if (st != CCUT_OK) return fail(c, (ccut_status)st, err);
   *out = p.release();
+  ctx_retain(c);
   c->err.clear();
   return CCUT_OK;
 }
 
 void ccut_plan_destroy(ccut_plan *p) {
-  if (p && p->ctx && p->ctx->device >= 0) (void)hipSetDevice(p->ctx->device);
+  if (!p) return;
+  ccut_ctx *c = p->ctx;
+  if (c && c->device >= 0) (void)hipSetDevice(c->device);
   delete p;
+  ctx_release(c);
 }
 
 ccut_status ccut_plan_info(const ccut_plan *p, uint32_t *nf, uint64_t *nv, uint64_t *nt) {
@@ -942,7 +983,8 @@ const char *ccut_kernel_name(uint32_t kid) {
   static const char *names[CCUT_K_COUNT] = {"tableau_kernel", "sample_kernel", "hist_reduce_kernel",
                                             "exact_kernel", "sv_kernel", "parity_kernel",
                                             "transform_pass_kernel", "recombine_fp64_kernel",
-                                            "zrecombine_fp64_kernel", "heisenberg_kernels"};
+                                            "zrecombine_fp64_kernel", "heisenberg_kernels",
+                                            "mlp_kernels", "term_kernels"};
   return kid < CCUT_K_COUNT ? names[kid] : "";
 }
 
@@ -1161,6 +1203,7 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     c->err.clear();
   }
   *out = b.release();
+  ctx_retain(c);
   return CCUT_OK;
 }
 
@@ -1205,11 +1248,13 @@ ccut_status ccut_batch_info(const ccut_batch *b, uint64_t *n_items, uint32_t *bl
 
 void ccut_batch_destroy(ccut_batch *b) {
   if (!b) return;
-  if (b->ctx && b->ctx->device >= 0) {
-    (void)hipSetDevice(b->ctx->device);
+  ccut_ctx *c = b->ctx;
+  if (c && c->device >= 0) {
+    (void)hipSetDevice(c->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
   }
   delete b;
+  ctx_release(c);
 }
 
 ccut_status ccut_run_batch(ccut_ctx *c, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
@@ -1220,6 +1265,595 @@ ccut_status ccut_run_batch(ccut_ctx *c, ccut_plan *const *plans, size_t n, const
   st = ccut_batch_run(b, outs, 0);
   ccut_batch_destroy(b);
   return st;
+}
+
+}  // extern "C"
+
+// ================================================= learned term proposal
+
+struct ccut_mlp {
+  ccut_ctx *ctx = nullptr;
+  uint32_t F = 0, H = 0;
+  uint64_t n_params = 0;
+  uint64_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0, off_w4 = 0, off_b4 = 0;
+  Arena arena;  // parameters and Adam state
+  Arena work;   // activations, regrown when a call needs more rows
+  uint64_t work_rows = 0;
+  float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  uint16_t *pb = nullptr;  // bf16 copy of the parameters used by the products
+  uint64_t t = 0;          // Adam step count
+  uint16_t *xb = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;
+  float *y = nullptr, *tb = nullptr, *dy = nullptr, *sq = nullptr, *part = nullptr;
+  ~ccut_mlp() {
+    if (ctx && ctx->device >= 0) {
+      (void)hipSetDevice(ctx->device);
+      (void)hipStreamSynchronize(ctx->stream);
+    }
+    arena.release();
+    work.release();
+  }
+};
+
+struct ccut_learned {
+  ccut_ctx *ctx = nullptr;
+  ccut_plan *plan = nullptr;
+  uint32_t k = 0, nq = 0, width = 64, circuit = 0;
+  uint64_t K = 0;
+  Arena arena;  // fragment tensors, norms, share tables
+  std::vector<std::vector<char>> staged;
+  RecombArgs args{};
+  LearnedDev h{};
+  LearnedDev *d = nullptr;
+  ~ccut_learned() {
+    if (ctx && ctx->device >= 0) {
+      (void)hipSetDevice(ctx->device);
+      (void)hipStreamSynchronize(ctx->stream);
+    }
+    arena.release();
+  }
+};
+
+namespace {
+
+// Run with the context's allocations going to another arena (long-lived
+// objects), everything on the context stream.
+struct ArenaScope {
+  ccut_ctx *c;
+  Arena *a;
+  std::vector<std::vector<char>> *st;
+  bool saved_aux;
+  ArenaScope(ccut_ctx *cc, Arena *aa, std::vector<std::vector<char>> *ss) : c(cc), a(aa), st(ss) {
+    std::swap(c->arena, *a);
+    std::swap(c->staged, *st);
+    saved_aux = c->use_aux;
+    c->use_aux = false;
+    c->cur = c->stream;
+  }
+  ~ArenaScope() {
+    std::swap(c->arena, *a);
+    std::swap(c->staged, *st);
+    c->use_aux = saved_aux;
+  }
+};
+
+ccut_status begin_call(ccut_ctx *c) {
+  if (!c) return CCUT_E_INVALID;
+  if (c->device < 0) return fail(c, CCUT_E_DEVICE, "host-only context: evaluation needs a device");
+  HIP_TRY(c, hipSetDevice(c->device));
+  c->cancel.store(0);
+  c->arena.reset();
+  c->staged.clear();
+  c->cur = c->stream;
+  return CCUT_OK;
+}
+
+ccut_status sync_call(ccut_ctx *c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return CCUT_OK;
+}
+
+ccut_status mlp_gemm(ccut_ctx *c, const uint16_t *A, uint64_t sam, uint64_t sak, const uint16_t *B, uint64_t sbk,
+                     uint64_t sbn, uint64_t M, uint32_t N, uint32_t K, void *C, uint64_t ldc, int epi,
+                     const float *bias = nullptr, const uint16_t *mask = nullptr, uint64_t ldm = 0) {
+  MlpGemm g{A, sam, sak, B, sbk, sbn, M, N, K, C, ldc, bias, mask, ldm};
+  HIP_TRY(c, launch_mlp_gemm(g, epi, c->cur));
+  return CCUT_OK;
+}
+
+ccut_status mlp_ensure_work(ccut_mlp *M, uint64_t rows) {
+  ccut_ctx *c = M->ctx;
+  if (rows <= M->work_rows) return CCUT_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  M->work.release();
+  const uint64_t F = M->F, H = M->H;
+  auto b16 = [&](uint64_t n) { return (uint16_t *)M->work.get(n * 2); };
+  auto f32 = [&](uint64_t n) { return (float *)M->work.get(n * 4); };
+  M->xb = b16(rows * F);
+  M->h1 = b16(rows * H);
+  M->h2 = b16(rows * H);
+  M->h3 = b16(rows * H);
+  M->d1 = b16(rows * H);
+  M->d2 = b16(rows * H);
+  M->d3 = b16(rows * H);
+  M->y = f32(rows);
+  M->tb = f32(rows);
+  M->dy = f32(rows);
+  M->sq = f32(rows);
+  M->part = f32((uint64_t)colsum_chunks(rows) * std::max(H, F));
+  if (!M->xb || !M->h1 || !M->h2 || !M->h3 || !M->d1 || !M->d2 || !M->d3 || !M->y || !M->tb || !M->dy || !M->sq ||
+      !M->part) {
+    M->work.release();
+    M->work_rows = 0;
+    return fail(c, CCUT_E_OOM, "device allocation failed");
+  }
+  M->work_rows = rows;
+  return CCUT_OK;
+}
+
+// h1..h3 and y for rows of x (rows <= work_rows)
+ccut_status mlp_forward_rows(ccut_mlp *M, const uint16_t *x, uint64_t rows, float *y, float scale = 1.f) {
+  ccut_ctx *c = M->ctx;
+  const uint32_t F = M->F, H = M->H;
+  ccut_status st;
+  KTimer t(c, CCUT_K_MLP);
+  if ((st = mlp_gemm(c, x, F, 1, M->pb + M->off_w1, 1, F, rows, H, F, M->h1, H, MLP_EPI_BIAS_RELU,
+                     M->p + M->off_b1)) != CCUT_OK)
+    return st;
+  if ((st = mlp_gemm(c, M->h1, H, 1, M->pb + M->off_w2, 1, H, rows, H, H, M->h2, H, MLP_EPI_BIAS_RELU,
+                     M->p + M->off_b2)) != CCUT_OK)
+    return st;
+  if ((st = mlp_gemm(c, M->h2, H, 1, M->pb + M->off_w3, 1, H, rows, H, H, M->h3, H, MLP_EPI_BIAS_RELU,
+                     M->p + M->off_b3)) != CCUT_OK)
+    return st;
+  HIP_TRY(c, launch_head_forward(M->h3, H, rows, M->pb + M->off_w4, M->p + M->off_b4, scale, y, c->cur));
+  return CCUT_OK;
+}
+
+// Gradient of the mean squared error into M->g after mlp_forward_rows on
+// the same rows; loss_sum (device) receives sum (y - t)^2.
+ccut_status mlp_backward_rows(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t rows, float *loss_sum) {
+  ccut_ctx *c = M->ctx;
+  const uint32_t F = M->F, H = M->H;
+  const uint32_t R = (uint32_t)rows;
+  ccut_status st;
+  KTimer tm(c, CCUT_K_MLP);
+  HIP_TRY(c, launch_head_backward(M->h3, H, rows, M->pb + M->off_w4, M->y, t, M->dy, M->sq, M->d3, c->cur));
+  HIP_TRY(c, launch_colsum(M->h3, H, rows, M->dy, M->part, M->g + M->off_w4, c->cur));
+  HIP_TRY(c, launch_vsum(M->dy, rows, M->g + M->off_b4, c->cur));
+  HIP_TRY(c, launch_vsum(M->sq, rows, loss_sum, c->cur));
+  // layer 3: dW3 = dZ3^T H2, db3 = colsum dZ3, dZ2 = (dZ3 W3) [H2 > 0]
+  const uint16_t *hin[3] = {x, M->h1, M->h2};
+  uint16_t *dz[3] = {M->d1, M->d2, M->d3};
+  const uint64_t offw[3] = {M->off_w1, M->off_w2, M->off_w3}, offb[3] = {M->off_b1, M->off_b2, M->off_b3};
+  for (int l = 2; l >= 0; --l) {
+    const uint32_t in = l == 0 ? F : H;
+    if ((st = mlp_gemm(c, dz[l], 1, H, hin[l], in, 1, H, in, R, M->g + offw[l], in, MLP_EPI_F32)) != CCUT_OK)
+      return st;
+    HIP_TRY(c, launch_colsum(dz[l], H, rows, nullptr, M->part, M->g + offb[l], c->cur));
+    if (l > 0 && (st = mlp_gemm(c, dz[l], H, 1, M->pb + offw[l], H, 1, rows, H, H, dz[l - 1], H, MLP_EPI_MASK,
+                                nullptr, hin[l], H)) != CCUT_OK)
+      return st;
+  }
+  return CCUT_OK;
+}
+
+uint64_t splitmix64(uint64_t &s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_mlp_create(ccut_ctx *c, uint32_t F, uint32_t H, ccut_mlp **out) {
+  if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (F == 0 || H == 0 || F % 64 || H % 64 || F > 256 || H > 256)
+    return fail(c, CCUT_E_INVALID, "F and H must be multiples of 64 in [64, 256]");
+  std::unique_ptr<ccut_mlp> M(new (std::nothrow) ccut_mlp());
+  if (!M) return fail(c, CCUT_E_OOM, "host allocation failed");
+  M->ctx = c;
+  M->F = F;
+  M->H = H;
+  M->arena.alloc = M->work.alloc = c->arena.alloc;
+  M->arena.free_fn = M->work.free_fn = c->arena.free_fn;
+  M->arena.user = M->work.user = c->arena.user;
+  uint64_t o = 0;
+  M->off_w1 = o;
+  o += (uint64_t)H * F;
+  M->off_b1 = o;
+  o += H;
+  M->off_w2 = o;
+  o += (uint64_t)H * H;
+  M->off_b2 = o;
+  o += H;
+  M->off_w3 = o;
+  o += (uint64_t)H * H;
+  M->off_b3 = o;
+  o += H;
+  M->off_w4 = o;
+  o += H;
+  M->off_b4 = o;
+  o += 1;
+  M->n_params = o;
+  M->p = (float *)M->arena.get(o * 4);
+  M->g = (float *)M->arena.get(o * 4);
+  M->m = (float *)M->arena.get(o * 4);
+  M->v = (float *)M->arena.get(o * 4);
+  M->pb = (uint16_t *)M->arena.get(o * 2);
+  if (!M->p || !M->g || !M->m || !M->v || !M->pb) return fail(c, CCUT_E_OOM, "device allocation failed");
+  // He-style uniform initialisation (limits sqrt(6 / fan_in), output layer
+  // sqrt(3 / fan_in)), biases zero
+  std::vector<float> init(o, 0.f);
+  uint64_t s = 0x5EED0000A11CE5ull;
+  auto fill = [&](uint64_t off, uint64_t count, double lim) {
+    for (uint64_t i = 0; i < count; ++i) {
+      const double u = (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0);
+      init[off + i] = (float)((2.0 * u - 1.0) * lim);
+    }
+  };
+  fill(M->off_w1, (uint64_t)H * F, std::sqrt(6.0 / F));
+  fill(M->off_w2, (uint64_t)H * H, std::sqrt(6.0 / H));
+  fill(M->off_w3, (uint64_t)H * H, std::sqrt(6.0 / H));
+  fill(M->off_w4, H, std::sqrt(3.0 / H));
+  ccut_mlp *raw = M.get();
+  st = ccut_mlp_set_params(raw, init.data(), init.size());
+  if (st != CCUT_OK) return st;
+  *out = M.release();
+  ctx_retain(c);
+  return CCUT_OK;
+}
+
+ccut_status ccut_mlp_set_params(ccut_mlp *M, const float *params, size_t count) {
+  if (!M || !params) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (count != M->n_params) return fail(c, CCUT_E_INVALID, "parameter count does not match the network");
+  HIP_TRY(c, hipMemcpyAsync(M->p, params, count * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(M->m, 0, count * 4, c->stream));
+  HIP_TRY(c, hipMemsetAsync(M->v, 0, count * 4, c->stream));
+  HIP_TRY(c, launch_to_bf16(M->p, M->pb, count, c->stream));
+  M->t = 0;
+  return sync_call(c);
+}
+
+ccut_status ccut_mlp_get_params(ccut_mlp *M, float *params, size_t count) {
+  if (!M || !params) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (count != M->n_params) return fail(c, CCUT_E_INVALID, "parameter count does not match the network");
+  HIP_TRY(c, hipMemcpyAsync(params, M->p, count * 4, hipMemcpyDeviceToHost, c->stream));
+  return sync_call(c);
+}
+
+ccut_status ccut_mlp_forward(ccut_mlp *M, const uint16_t *x, uint64_t n, float *y) {
+  if (!M) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (n && (!x || !y)) return fail(c, CCUT_E_INVALID, "NULL argument");
+  const uint64_t chunk = std::min<uint64_t>(n, 1ull << 18);
+  if ((st = mlp_ensure_work(M, std::max<uint64_t>(chunk, 64))) != CCUT_OK) return st;
+  for (uint64_t r0 = 0; r0 < n; r0 += chunk)
+    if ((st = mlp_forward_rows(M, x + r0 * M->F, std::min(chunk, n - r0), y + r0)) != CCUT_OK) return st;
+  return sync_call(c);
+}
+
+ccut_status ccut_mlp_gradients(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t n, float *grads,
+                               double *loss) {
+  if (!M) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!x || !t || !grads) return fail(c, CCUT_E_INVALID, "NULL argument");
+  if (n == 0 || n % 64 || n > (1ull << 24)) return fail(c, CCUT_E_INVALID, "n must be a positive multiple of 64");
+  if ((st = mlp_ensure_work(M, n)) != CCUT_OK) return st;
+  float *lsum = aget<float>(c, 1);
+  if (!lsum) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if ((st = mlp_forward_rows(M, x, n, M->y)) != CCUT_OK) return st;
+  if ((st = mlp_backward_rows(M, x, t, n, lsum)) != CCUT_OK) return st;
+  float hl = 0.f;
+  HIP_TRY(c, hipMemcpyAsync(grads, M->g, M->n_params * 4, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(&hl, lsum, 4, hipMemcpyDeviceToHost, c->stream));
+  if ((st = sync_call(c)) != CCUT_OK) return st;
+  if (loss) *loss = (double)hl / (double)n;
+  return CCUT_OK;
+}
+
+ccut_status ccut_mlp_train(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t n, uint32_t batch,
+                           uint32_t steps, float lr, uint64_t seed, float *losses) {
+  if (!M) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!x || !t) return fail(c, CCUT_E_INVALID, "NULL argument");
+  if (n == 0 || batch == 0 || batch % 64 || batch > n || batch > (1u << 24))
+    return fail(c, CCUT_E_INVALID, "batch must be a positive multiple of 64, at most n");
+  if ((st = mlp_ensure_work(M, batch)) != CCUT_OK) return st;
+  float *lsum = aget<float>(c, std::max<uint32_t>(steps, 1));
+  if (!lsum) return fail(c, CCUT_E_OOM, "device allocation failed");
+  const int in_order = batch == n;
+  for (uint32_t s = 0; s < steps; ++s) {
+    HIP_TRY(c, launch_gather_rows(x, t, n, M->F, batch, s, seed, in_order, M->xb, M->tb, c->stream));
+    if ((st = mlp_forward_rows(M, M->xb, batch, M->y)) != CCUT_OK) return st;
+    if ((st = mlp_backward_rows(M, M->xb, M->tb, batch, lsum + s)) != CCUT_OK) return st;
+    M->t += 1;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)M->t));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)M->t));
+    KTimer tm(c, CCUT_K_MLP);
+    HIP_TRY(c, launch_adam(M->p, M->g, M->m, M->v, M->pb, M->n_params, lr, 0.9f, 0.999f, c1, c2, 1e-8f, c->stream));
+  }
+  if (losses && steps) {
+    HIP_TRY(c, hipMemcpyAsync(losses, lsum, steps * 4, hipMemcpyDeviceToHost, c->stream));
+    if ((st = sync_call(c)) != CCUT_OK) return st;
+    for (uint32_t s = 0; s < steps; ++s) losses[s] /= (float)batch;
+    return CCUT_OK;
+  }
+  return sync_call(c);
+}
+
+void ccut_mlp_destroy(ccut_mlp *M) {
+  if (!M) return;
+  ccut_ctx *c = M->ctx;
+  delete M;
+  ctx_release(c);
+}
+
+ccut_status ccut_learned_create(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                                ccut_learned **out) {
+  if (!p || !out) return CCUT_E_INVALID;
+  *out = nullptr;
+  ccut_status st = check_eval(p, eo);
+  if (st != CCUT_OK) return st;
+  ccut_ctx *c = p->ctx;
+  if ((st = check_request(c, p->pd.n, qubits, nq)) != CCUT_OK) return st;
+  const PlanData &pd = p->pd;
+  if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
+  if (pd.k == 0 || pd.k > 12) return fail(c, CCUT_E_UNSUPPORTED, "the term model needs 1 to 12 cuts");
+  std::unique_ptr<ccut_learned> L(new (std::nothrow) ccut_learned());
+  if (!L) return fail(c, CCUT_E_OOM, "host allocation failed");
+  L->ctx = c;
+  L->plan = p;
+  L->k = pd.k;
+  L->K = 1ull << (2 * pd.k);
+  L->nq = nq;
+  L->circuit = eo->circuit;
+  L->width = (uint32_t)((6 * pd.k + 63) / 64 * 64);
+  L->arena.alloc = c->arena.alloc;
+  L->arena.free_fn = c->arena.free_fn;
+  L->arena.user = c->arena.user;
+  {
+    ArenaScope scope(c, &L->arena, &L->staged);
+    RecombArgs &args = L->args;
+    args.n_frags = (uint32_t)pd.frags.size();
+    args.k = pd.k;
+    uint64_t n_slots = 0;
+    std::vector<uint64_t> slot_off(pd.frags.size());
+    for (const Fragment &f : pd.frags) {
+      slot_off[f.index] = n_slots;
+      n_slots += 4 * f.axes.size();
+    }
+    double *shares = aget<double>(c, std::max<uint64_t>(n_slots, 1));
+    if (!shares) return fail(c, CCUT_E_OOM, "device allocation failed");
+    std::vector<int64_t> src(2 * pd.k, -1);
+    LearnedDev &h = L->h;
+    h.k = pd.k;
+    h.n_frags = args.n_frags;
+    for (const Fragment &f : pd.frags) {
+      FragRequest r = marginal_request(f, qubits, nq);
+      double *dist = nullptr, *T = nullptr;
+      if (use_heisenberg(f, eo)) {
+        if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
+      } else {
+        if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;
+        if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+      }
+      RecombFrag &rf = args.f[f.index];
+      rf.T = T;
+      rf.n_axes = (uint32_t)f.axes.size();
+      rf.rows = 1u << r.req_pos.size();
+      rf.n_req = (uint32_t)r.req_pos.size();
+      for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
+      for (size_t i = 0; i < r.req_user.size(); ++i) rf.req_user[i] = r.req_user[i];
+      const uint32_t a = (uint32_t)f.axes.size();
+      const uint64_t ncols = 1ull << (2 * a);
+      double *norm = aget<double>(c, ncols);
+      double *part = aget<double>(c, (uint64_t)4 * std::max<uint32_t>(a, 1) * share_chunks(a));
+      if (!norm || !part) return fail(c, CCUT_E_OOM, "device allocation failed");
+      {
+        KTimer t(c, CCUT_K_TERMS);
+        HIP_TRY(c, launch_colnorm(T, rf.rows, ncols, norm, c->cur));
+        HIP_TRY(c, launch_shares(norm, a, part, shares + slot_off[f.index], c->cur));
+      }
+      h.norm[f.index] = norm;
+      h.n_axes[f.index] = a;
+      for (uint32_t j = 0; j < a; ++j) {
+        h.axis_cut[f.index][j] = f.axes[j].cut;
+        src[2 * f.axes[j].cut + f.axes[j].side] = (int64_t)(slot_off[f.index] + 4 * j);
+      }
+    }
+    int64_t *d_src = (int64_t *)upload(c, src.data(), src.size() * 8);
+    double *phi = aget<double>(c, 8 * pd.k);
+    if (!d_src || !phi) return fail(c, CCUT_E_OOM, "device allocation failed");
+    HIP_TRY(c, launch_phi(shares, d_src, pd.k, phi, c->cur));
+    h.phi = phi;
+    L->d = (LearnedDev *)upload(c, &h, sizeof(h));
+    if (!L->d) return fail(c, CCUT_E_OOM, "device allocation failed");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  *out = L.release();
+  ctx_retain(c);
+  return CCUT_OK;
+}
+
+ccut_status ccut_learned_info(const ccut_learned *L, uint32_t *k, uint64_t *n_terms, uint32_t *width) {
+  if (!L) return CCUT_E_INVALID;
+  if (k) *k = L->k;
+  if (n_terms) *n_terms = L->K;
+  if (width) *width = L->width;
+  return CCUT_OK;
+}
+
+ccut_status ccut_learned_features(ccut_learned *L, const uint64_t *terms, uint64_t first, uint64_t n, uint16_t *x) {
+  if (!L) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (n && !x) return fail(c, CCUT_E_INVALID, "x is NULL");
+  if (!terms && (first > L->K || n > L->K - first)) return fail(c, CCUT_E_INVALID, "term range beyond 4^k");
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_features(L->d, terms, first, n, L->width, x, c->cur));
+  }
+  return sync_call(c);
+}
+
+ccut_status ccut_learned_log_weights(ccut_learned *L, const uint64_t *terms, uint64_t first, uint64_t n, int kind,
+                                     float *y) {
+  if (!L) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (n && !y) return fail(c, CCUT_E_INVALID, "y is NULL");
+  if (kind < 0 || kind > 2) return fail(c, CCUT_E_INVALID, "kind must be 0, 1 or 2");
+  if (!terms && (first > L->K || n > L->K - first)) return fail(c, CCUT_E_INVALID, "term range beyond 4^k");
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_labels(L->d, terms, first, n, y, kind, c->cur));
+  }
+  return sync_call(c);
+}
+
+ccut_status ccut_learned_support(ccut_learned *L, uint64_t cap, uint64_t *terms, uint64_t *count) {
+  if (!L || !count) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (cap && !terms) return fail(c, CCUT_E_INVALID, "terms is NULL");
+  uint64_t *flags = aget<uint64_t>(c, L->K), *pos = aget<uint64_t>(c, L->K);
+  uint64_t *scratch = aget<uint64_t>(c, scan_scratch_words(L->K));
+  if (!flags || !pos || !scratch) return fail(c, CCUT_E_OOM, "device allocation failed");
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_support(L->d, L->K, flags, pos, scratch, cap, terms, c->cur));
+  }
+  HIP_TRY(c, hipMemcpyAsync(count, pos + L->K - 1, 8, hipMemcpyDeviceToHost, c->stream));
+  return sync_call(c);
+}
+
+ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
+  if (!L || !M) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!logits) return fail(c, CCUT_E_INVALID, "logits is NULL");
+  if (M->ctx != c || M->F != L->width) return fail(c, CCUT_E_INVALID, "network input width differs from the features");
+  const uint64_t chunk = std::min<uint64_t>(L->K, 1ull << 18);
+  if ((st = mlp_ensure_work(M, std::max<uint64_t>(chunk, 64))) != CCUT_OK) return st;
+  uint16_t *x = aget<uint16_t>(c, chunk * L->width);
+  if (!x) return fail(c, CCUT_E_OOM, "device allocation failed");
+  for (uint64_t first = 0; first < L->K; first += chunk) {
+    const uint64_t rows = std::min(chunk, L->K - first);
+    {
+      KTimer t(c, CCUT_K_TERMS);
+      HIP_TRY(c, launch_features(L->d, nullptr, first, rows, L->width, x, c->cur));
+    }
+    if ((st = mlp_forward_rows(M, x, rows, logits + first, kLabelScale)) != CCUT_OK) return st;
+  }
+  return sync_call(c);
+}
+
+ccut_status ccut_proposal(ccut_ctx *c, const float *logits, uint64_t K, double eps, double *q) {
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!q || K == 0) return fail(c, CCUT_E_INVALID, "q is NULL or K is 0");
+  if (!(eps >= 0.0 && eps <= 1.0)) return fail(c, CCUT_E_INVALID, "eps must be in [0, 1]");
+  const uint32_t nb = reduce_blocks(K);
+  float *mpart = aget<float>(c, nb);
+  double *spart = aget<double>(c, nb), *stats = aget<double>(c, 2);
+  if (!mpart || !spart || !stats) return fail(c, CCUT_E_OOM, "device allocation failed");
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_proposal(logits, K, eps, mpart, spart, stats, q, c->cur));
+  }
+  return sync_call(c);
+}
+
+}  // extern "C"
+
+namespace {
+ccut_status draw_terms(ccut_ctx *c, const double *q, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
+                       uint64_t *out) {
+  uint64_t *cdf = aget<uint64_t>(c, K), *scratch = aget<uint64_t>(c, scan_scratch_words(K));
+  if (!cdf || !scratch) return fail(c, CCUT_E_OOM, "device allocation failed");
+  KTimer t(c, CCUT_K_TERMS);
+  HIP_TRY(c, launch_int_cdf(q, K, cdf, scratch, c->cur));
+  HIP_TRY(c, launch_sample_terms(cdf, K, n, seed, cid, out, c->cur));
+  return CCUT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_sample_terms(ccut_ctx *c, const double *q, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
+                              uint64_t *out) {
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!q || K == 0 || (n && !out)) return fail(c, CCUT_E_INVALID, "NULL argument or K = 0");
+  if (n > 0xFFFFFFFFull) return fail(c, CCUT_E_INVALID, "at most 2^32 - 1 terms per draw");
+  if ((st = draw_terms(c, q, K, n, seed, cid, out)) != CCUT_OK) return st;
+  return sync_call(c);
+}
+
+ccut_status ccut_learned_estimate(ccut_learned *L, const double *q, uint64_t n, uint64_t seed, double *out,
+                                  int on_device, uint64_t *terms_out) {
+  if (!L) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!q || !out) return fail(c, CCUT_E_INVALID, "NULL argument");
+  if (n == 0 || n > 0xFFFFFFFFull) return fail(c, CCUT_E_INVALID, "n must be in [1, 2^32)");
+  uint64_t *terms = terms_out ? terms_out : aget<uint64_t>(c, n);
+  double *scale = aget<double>(c, n), *res = aget<double>(c, (size_t)1 << L->nq);
+  if (!terms || !scale || !res) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if ((st = draw_terms(c, q, L->K, n, seed, L->circuit, terms)) != CCUT_OK) return st;
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_is_scale(terms, q, n, scale, c->cur));
+  }
+  GemmArgs g;
+  make_gemm_args(L->args, g);
+  g.terms = terms;
+  g.tscale = scale;
+  g.K = n;
+  if ((st = run_gemm(c, g, false, res)) != CCUT_OK) return st;
+  return finish_out(c, res, out, (size_t)1 << L->nq, on_device);
+}
+
+ccut_status ccut_learned_exhaustive(ccut_learned *L, double *out, int on_device) {
+  if (!L) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
+  double *res = aget<double>(c, (size_t)1 << L->nq);
+  if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if ((st = recombine(c, L->args, L->nq, false, res)) != CCUT_OK) return st;
+  return finish_out(c, res, out, (size_t)1 << L->nq, on_device);
+}
+
+void ccut_learned_destroy(ccut_learned *L) {
+  if (!L) return;
+  ccut_ctx *c = L->ctx;
+  delete L;
+  ctx_release(c);
 }
 
 }  // extern "C"

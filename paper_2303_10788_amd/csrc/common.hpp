@@ -27,6 +27,32 @@ __host__ __device__ inline uint32_t op_kind(uint32_t w) { return w & 15u; }
 __host__ __device__ inline uint32_t op_q0(uint32_t w) { return (w >> 4) & 0x3FFFu; }
 __host__ __device__ inline uint32_t op_q1(uint32_t w) { return w >> 18; }
 
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of
+// (c0..c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
+// key bumped by the Weyl constants between rounds.
+struct U4 {
+  uint32_t w[4];
+};
+
+__device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                              uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return U4{{c0, c1, c2, c3}};
+}
+
 // Global-address-space views: loads through them with a wave-uniform index
 // compile to scalar (SMEM) loads, so op decoding stays in SGPRs.
 typedef __attribute__((address_space(1))) const uint32_t g_u32;
@@ -153,6 +179,10 @@ struct GemmSide {
 struct GemmArgs {
   uint32_t k, M, N;
   uint64_t K;
+  // K index -> cut term: terms[kk] if set (sampled terms), else kk; each
+  // term's row-side value is multiplied by tscale[kk] when set
+  const uint64_t *terms;
+  const double *tscale;
   GemmSide L, R;
   uint32_t ident[kMaxFrags];  // 1 if the fragment's axes are cuts 0..k-1 in order (p_f(P) = P)
   RecombFrag f[kMaxFrags];
@@ -160,5 +190,67 @@ struct GemmArgs {
 uint32_t gemm_splits(const GemmArgs &h);
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
                                  uint32_t splits, double *out, hipStream_t s);
+
+
+// ------------------------------------------------- learned term proposal
+enum MlpEpilogue : int { MLP_EPI_F32 = 0, MLP_EPI_BIAS_RELU = 1, MLP_EPI_MASK = 2 };
+struct MlpGemm {
+  const uint16_t *A;  // bf16, A(m, k) = A[m sam + k sak]
+  uint64_t sam, sak;
+  const uint16_t *B;  // bf16, B(k, n) = B[k sbk + n sbn]
+  uint64_t sbk, sbn;
+  uint64_t M;
+  uint32_t N, K;
+  void *C;             // fp32 (MLP_EPI_F32) or bf16
+  uint64_t ldc;
+  const float *bias;   // MLP_EPI_BIAS_RELU
+  const uint16_t *mask;  // MLP_EPI_MASK: bf16 layer output, row stride ldm
+  uint64_t ldm;
+};
+hipError_t launch_mlp_gemm(const MlpGemm &g, int epi, hipStream_t s);
+hipError_t launch_head_forward(const uint16_t *H, uint32_t width, uint64_t rows, const uint16_t *w, const float *b,
+                               float scale, float *y, hipStream_t s);
+hipError_t launch_head_backward(const uint16_t *H, uint32_t width, uint64_t rows, const uint16_t *w, const float *y,
+                                const float *t, float *dy, float *sq, uint16_t *dZ, hipStream_t s);
+uint32_t colsum_chunks(uint64_t rows);
+hipError_t launch_colsum(const uint16_t *X, uint32_t width, uint64_t rows, const float *sc, float *part, float *out,
+                         hipStream_t s);
+hipError_t launch_vsum(const float *x, uint64_t n, float *out, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *pb, uint64_t n, float lr, float b1,
+                       float b2, float c1, float c2, float eps, hipStream_t s);
+hipError_t launch_to_bf16(const float *p, uint16_t *pb, uint64_t n, hipStream_t s);
+hipError_t launch_gather_rows(const uint16_t *X, const float *y, uint64_t n, uint32_t width, uint32_t batch,
+                              uint32_t step, uint64_t seed, int in_order, uint16_t *Xb, float *yb, hipStream_t s);
+
+// The network regresses ln-weights divided by this scale (targets in
+// [-1.04, 0]); its logits are the scale times its output.
+constexpr float kLabelScale = 40.f;
+// Per-circuit term model: fragment column norms and per-cut phi tables.
+struct LearnedDev {
+  uint32_t k, n_frags;
+  const double *norm[kMaxFrags];  // n_f[p_f]
+  uint32_t n_axes[kMaxFrags];
+  uint32_t axis_cut[kMaxFrags][kMaxAxes];
+  const double *phi;              // [cut][side: 0 up, 1 down][digit]
+};
+hipError_t launch_colnorm(const double *T, uint32_t rows, uint64_t ncols, double *out, hipStream_t s);
+uint32_t share_chunks(uint32_t n_axes);
+hipError_t launch_shares(const double *norm, uint32_t n_axes, double *part, double *shares, hipStream_t s);
+hipError_t launch_phi(const double *shares, const int64_t *src, uint32_t k, double *phi, hipStream_t s);
+hipError_t launch_features(const LearnedDev *L, const uint64_t *terms, uint64_t first, uint64_t n, uint32_t width,
+                           uint16_t *X, hipStream_t s);
+hipError_t launch_labels(const LearnedDev *L, const uint64_t *terms, uint64_t first, uint64_t n, float *y, int kind,
+                         hipStream_t s);
+hipError_t launch_support(const LearnedDev *L, uint64_t K, uint64_t *flags, uint64_t *pos, uint64_t *scratch,
+                          uint64_t cap, uint64_t *out, hipStream_t s);
+uint64_t scan_scratch_words(uint64_t n);
+hipError_t launch_scan_u64(uint64_t *x, uint64_t n, uint64_t *scratch, hipStream_t s);
+uint32_t reduce_blocks(uint64_t n);
+hipError_t launch_proposal(const float *logits, uint64_t n, double eps, float *mpart, double *spart, double *stats,
+                           double *q, hipStream_t s);
+hipError_t launch_int_cdf(const double *q, uint64_t n, uint64_t *cdf, uint64_t *scratch, hipStream_t s);
+hipError_t launch_sample_terms(const uint64_t *cdf, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
+                               uint64_t *out, hipStream_t s);
+hipError_t launch_is_scale(const uint64_t *terms, const double *q, uint64_t n, double *scale, hipStream_t s);
 
 }  // namespace ccut

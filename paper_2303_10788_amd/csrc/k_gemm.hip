@@ -15,6 +15,8 @@
 //    cut terms cancels heavily, so it is kept in fp64);
 //  - FP64 MFMA (v_mfma_f64_16x16x4_f64) end to end (reference path).
 // Split-K partials are summed in fp64 in split order by a second kernel.
+// With a term list the K index runs over sampled terms P_j, each row-side
+// value scaled by its importance weight (the estimator of the same sum).
 #include <algorithm>
 
 #include "common.hpp"
@@ -78,16 +80,20 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
     for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
       const uint32_t kk = e / MT, mm = e % MT;
       const uint32_t m = tm * MT + mm;
-      const uint64_t P = kb + kk;
-      const double a = (m < M && P < k1) ? side_value(G, G->L, m, P) : 0.0;
+      const uint64_t j = kb + kk;
+      double a = 0.0;
+      if (m < M && j < k1) {
+        a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+        if (G->tscale) a *= G->tscale[j];
+      }
       As[kk][mm] = (TS)a;
       if constexpr (F32) Al[kk][mm] = (float)(a - (double)(float)a);
     }
     for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
       const uint32_t kk = e / NT, nn = e % NT;
       const uint32_t n = tn * NT + nn;
-      const uint64_t P = kb + kk;
-      const double b = (n < N && P < k1) ? side_value(G, G->R, n, P) : 0.0;
+      const uint64_t j = kb + kk;
+      const double b = (n < N && j < k1) ? side_value(G, G->R, n, G->terms ? G->terms[j] : j) : 0.0;
       Bs[kk][nn] = (TS)b;
       if constexpr (F32) Bl[kk][nn] = (float)(b - (double)(float)b);
     }

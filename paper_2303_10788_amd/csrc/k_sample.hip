@@ -13,29 +13,6 @@ namespace ccut {
 
 namespace {
 
-struct U4 {
-  uint32_t w[4];
-};
-
-__device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                              uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return U4{{c0, c1, c2, c3}};
-}
-
 // Shot-bit words of one quad (4 shots): bits of measurement indices 0..31
 // in lo[r], 32..63 in hi[r].
 __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, bool wide,

@@ -105,3 +105,14 @@ def test_host_only_context_refuses_evaluation():
     with pytest.raises(cc.CcutError) as e:
         plan.marginal(w.qubits)
     assert e.value.status == cc.CCUT_E_DEVICE
+
+
+def test_plan_outlives_destroyed_context():
+    """Destroying a context while a plan made from it is alive defers the
+    context's release to the plan's destruction."""
+    ctx = cc.Context(-1)
+    w = W.tiny()
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    ctx.close()
+    assert plan.info()[0] == 2
+    plan.close()
