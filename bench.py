@@ -38,9 +38,11 @@ def parse():
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["mid", "batching", "precision"], default="mid",
+    ap.add_argument("--workload", choices=["mid", "batching", "precision", "learned"], default="mid",
                     help="mid (default): the 32-qubit, 2-cut workload; batching: 256 uneven circuits in one "
-                         "graph-captured batch; precision: the 400-qubit, 6-cut workload with FP32-MFMA recombination")
+                         "graph-captured batch; precision: the 400-qubit, 6-cut workload with FP32-MFMA "
+                         "recombination; learned: the 300-qubit, 10-cut workload, learned term proposal against "
+                         "exhaustive recombination")
     return ap.parse_args()
 
 
@@ -77,6 +79,8 @@ def main():
         return bench_batching(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     import numpy as np
     import torch
 
@@ -257,6 +261,101 @@ def bench_precision(args):
         "roofline": {"bound": "mfma", "kernel": "gemm_kernel<fp32> (+reduce)", "achieved": flops / per_launch_s / 1e12,
                      "peak": 157.3, "unit": "TFLOP/s", "frac": flops / per_launch_s / 157.3e12, "traffic": None,
                      "avg_launch_us": per_launch_s * 1e6},
+    }
+    print(json.dumps(line), flush=True)
+
+
+PEAK_BF16 = 2.5e15
+
+
+def bench_learned(args):
+    """300 qubits, 50 layers, four 5-qubit non-Clifford blocks, 10 cuts
+    (4^10 terms), exact fragment tensors, 16-qubit marginal.  The network
+    (64 -> 256 -> 256 -> 256 -> 1) is trained first on 16 other circuits of
+    the same family (not timed in the steps).  One step = the whole learned
+    path on the held-out circuit: fragment tensors, network logits over all
+    4^10 terms, proposal, 16384 sampled terms contracted; against it, the
+    exhaustive path (fragment tensors + contraction of all 4^10 terms).
+    value = exhaustive time / learned time at the stated TVD."""
+    import numpy as np
+    import torch
+
+    import paper_2303_10788_amd as cc
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = cc.Context(0)
+    n_samples = 16384
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for s in range(100000, 100016):
+        w = W.learned_circuit(s)
+        plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+        L = cc.Learned(plan, w.qubits)
+        sup, _ = L.support(cap=1024)
+        drawn = cc.sample_terms(ctx, cc.proposal(ctx, L.log_weights(kind=1)), 2048, seed=s, cid=1)
+        uni = cc.sample_terms(ctx, cc.proposal(ctx, None, K=L.K), 1024, seed=s, cid=2)
+        terms = torch.cat([sup, drawn, uni]).contiguous()
+        xs.append(L.features(terms))
+        ys.append(L.log_weights(terms, kind=2))
+        L.close()
+        plan.close()
+    X = torch.cat(xs).contiguous()
+    y = torch.cat(ys).contiguous()
+    rows = (X.shape[0] // 64) * 64
+    X, y = X[:rows].contiguous(), y[:rows].contiguous()
+    t_data = time.perf_counter() - t0
+    net = cc.Mlp(ctx, 64, 256)
+    t0 = time.perf_counter()
+    losses = net.train(X, y, batch=1024, steps=2000, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    w = W.learned_circuit(200000)
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    out_ex = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
+    out_le = torch.empty_like(out_ex)
+
+    def exhaustive():
+        plan.marginal(w.qubits, out=out_ex)
+
+    def learned():
+        L = cc.Learned(plan, w.qubits)
+        q = cc.proposal(ctx, L.logits(net))
+        L.estimate(q, n_samples, 9, out=out_le)
+        L.close()
+
+    dt_ex = _timed(exhaustive, args.steps, args.warmup)
+    ctx.timing(True)
+    ctx.timing_reset()
+    dt_le = _timed(learned, args.steps, args.warmup)
+    times = ctx.kernel_times()
+    ctx.timing(False)
+    ex = out_ex.cpu().numpy()
+    le = out_le.cpu().numpy()
+    tvd = 0.5 * float(np.abs(le - ex).sum())
+    K = 4 ** len(w.cuts)
+    H, F = 256, 64
+    mlp_launches, mlp_ms = times["mlp_kernels"]
+    flops = 2.0 * K * (F * H + 2 * H * H + H) * args.steps
+    ms_le = 1e3 * dt_le / args.steps
+    ms_ex = 1e3 * dt_ex / args.steps
+    line = {
+        "metric": METRIC, "value": ms_ex / ms_le, "unit": "x (exhaustive time / learned time, TVD<=1e-2)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_le, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/f64", "data": "synthetic",
+        "config": {"workload": "learned: 300 qubits, 50 layers (CX density 0.3), four 5-qubit blocks x 3 T, "
+                               "exits (3,3,2,2) -> 10 cuts (4^10 terms), exact tensors, 16-qubit marginal; "
+                               "network trained on 16 circuits of the family, evaluated on a held-out one",
+                   "samples": n_samples, "cut_terms": K},
+        "exhaustive_ms": ms_ex, "learned_ms": ms_le, "tvd_learned_vs_exhaustive": tvd,
+        "train": {"rows": rows, "steps": 2000, "batch": 1024, "loss_first": float(losses[:5].mean()),
+                  "loss_last": float(losses[-50:].mean()), "train_s": t_train, "dataset_s": t_data},
+        "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
+        "roofline": {"bound": "mfma", "kernel": "mlp_gemm_kernel (network over all 4^10 terms)",
+                     "achieved": flops / (mlp_ms / 1e3) / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / (mlp_ms / 1e3) / PEAK_BF16, "traffic": None,
+                     "avg_launch_us": 1e3 * mlp_ms / max(mlp_launches, 1)},
     }
     print(json.dumps(line), flush=True)
 
