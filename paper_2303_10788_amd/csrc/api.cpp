@@ -103,10 +103,14 @@ struct ccut_plan {
   PlanData pd;
   std::vector<uint32_t *> d_ops;   // per fragment, uploaded on first evaluation
   std::vector<double *> d_mats;
+  std::vector<uint32_t *> d_back;  // Clifford fragments: the carry-back stream
+  std::vector<uint32_t> n_back;
   ~ccut_plan() {
     for (auto p : d_ops)
       if (p) (void)hipFree(p);
     for (auto p : d_mats)
+      if (p) (void)hipFree(p);
+    for (auto p : d_back)
       if (p) (void)hipFree(p);
   }
 };
@@ -163,15 +167,24 @@ T *aget(ccut_ctx *c, size_t count) {
   return (T *)c->arena.get(count * sizeof(T));
 }
 
-// Upload each fragment's op stream once per plan: the circuit-order words
-// for Clifford fragments, the fused stream (with its matrices) for
-// non-Clifford ones; padded with no-ops to a multiple of 16 words so kernels
-// can fetch ops sixteen at a time.
+// Upload each fragment's op streams once per plan: for Clifford fragments
+// the fused forward stream and the carry-back stream, for non-Clifford ones
+// the fused stream with its matrices; padded with no-ops (identities) to a
+// multiple of 16 words so kernels can fetch ops sixteen at a time.
 ccut_status ensure_ops(ccut_plan *p) {
   ccut_ctx *c = p->ctx;
   if (!p->d_ops.empty()) return CCUT_OK;
   for (const Fragment &f : p->pd.frags) {
-    std::vector<uint32_t> words = f.clifford ? f.op_words : f.sv_words;
+    uint32_t *bk = nullptr;
+    std::vector<uint32_t> back = f.cl_back;
+    while (back.size() % 16 || back.empty()) back.push_back(pack_op(G_NOP, 0, 0));
+    if (f.clifford) {
+      HIP_TRY(c, hipMalloc(&bk, back.size() * sizeof(uint32_t)));
+      HIP_TRY(c, hipMemcpy(bk, back.data(), back.size() * 4, hipMemcpyHostToDevice));
+    }
+    p->d_back.push_back(bk);
+    p->n_back.push_back((uint32_t)f.cl_back.size());
+    std::vector<uint32_t> words = f.clifford ? f.cl_words : f.sv_words;
     std::vector<double> mats = f.clifford ? std::vector<double>() : f.sv_mats;
     while (words.size() % 16 || words.empty()) {
       words.push_back(pack_op(G_NOP, 0, 0));
@@ -430,7 +443,9 @@ ccut_status heis_tensor(ccut_plan *p, const Fragment &f, const FragRequest &r, u
   uint64_t *d_in = (uint64_t *)upload(c, rows.data(), rows.size() * 8);
   if (!tau || !d_out || !d_in) return fail(c, CCUT_E_OOM, "device allocation failed");
   FragRequest rq = r;
-  const FragDev h = frag_desc(p, f, rq, circuit);
+  FragDev h = frag_desc(p, f, rq, circuit);
+  h.ops = p->d_back[f.index];  // the carry-back stream
+  h.n_ops = p->n_back[f.index];
   {
     KTimer t(c, CCUT_K_HEISENBERG);
     HIP_TRY(c, launch_heisenberg(h, W, n_in, n_out, strings ? 0 : nreq, strings ? (uint32_t)strings->size() : 0,

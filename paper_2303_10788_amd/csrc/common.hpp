@@ -16,6 +16,7 @@ enum GateKind : uint32_t {
   G_H = 0, G_S = 1, G_SDG = 2, G_X = 3, G_Y = 4, G_Z = 5, G_CX = 6, G_CZ = 7,
   G_T = 8, G_TDG = 9, G_RZ = 10,
   G_U2 = 11,   // fused one-qubit unitary (state-vector path only), matrix in FragDev::mats
+  G_C1 = 12,   // fused one-qubit Clifford (tableau paths), parameters in the q1 field
   G_NOP = 15   // padding of op arrays to a multiple of 4 words
 };
 
@@ -51,6 +52,52 @@ __device__ inline U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3
     c3 = lo0;
   }
   return U4{{c0, c1, c2, c3}};
+}
+
+// One-qubit Clifford action on a Pauli row's bits (x, z) at its qubit and
+// on the row's sign c (the tableau update rule P -> G P G^dag): new
+// (x, z) = M (x, z) over GF(2) and c ^= alpha x ^ beta z ^ gamma x z, both
+// from the bits before the gate.  Any run of one-qubit Cliffords composes
+// to this form.  Encoded in the q1 field of a G_C1 word: bits 0-3 hold
+// M xor I (m00, m01, m10, m11), bits 4-6 alpha, beta, gamma, so an all-zero
+// field (also every G_NOP word) is the identity.
+struct C1Map {
+  uint32_t m00, m01, m10, m11, al, be, ga;
+};
+__host__ __device__ inline C1Map c1_decode(uint32_t p) {
+  return C1Map{(p & 1u) ^ 1u, (p >> 1) & 1u, (p >> 2) & 1u, ((p >> 3) & 1u) ^ 1u, (p >> 4) & 1u, (p >> 5) & 1u,
+               (p >> 6) & 1u};
+}
+__host__ __device__ inline uint32_t c1_encode(const C1Map &c) {
+  return (c.m00 ^ 1u) | (c.m01 << 1) | (c.m10 << 2) | ((c.m11 ^ 1u) << 3) | (c.al << 4) | (c.be << 5) | (c.ga << 6);
+}
+// the single gates: H swaps x and z (c ^= x z); S and S^dag map z -> x ^ z
+// (c ^= x z, resp. x (1 ^ z)); X, Y, Z flip c by z, x ^ z, x
+__host__ __device__ inline uint32_t c1_of_gate(uint32_t kind) {
+  switch (kind) {
+    case G_H: return c1_encode(C1Map{0, 1, 1, 0, 0, 0, 1});
+    case G_S: return c1_encode(C1Map{1, 0, 1, 1, 0, 0, 1});
+    case G_SDG: return c1_encode(C1Map{1, 0, 1, 1, 1, 0, 1});
+    case G_X: return c1_encode(C1Map{1, 0, 0, 1, 0, 1, 0});
+    case G_Y: return c1_encode(C1Map{1, 0, 0, 1, 1, 1, 0});
+    case G_Z: return c1_encode(C1Map{1, 0, 0, 1, 1, 0, 0});
+    default: return 0u;
+  }
+}
+// the map of "first a, then b"
+__host__ __device__ inline uint32_t c1_then(uint32_t pa, uint32_t pb) {
+  const C1Map A = c1_decode(pa), B = c1_decode(pb);
+  C1Map C;
+  C.m00 = (B.m00 & A.m00) ^ (B.m01 & A.m10);
+  C.m01 = (B.m00 & A.m01) ^ (B.m01 & A.m11);
+  C.m10 = (B.m10 & A.m00) ^ (B.m11 & A.m10);
+  C.m11 = (B.m10 & A.m01) ^ (B.m11 & A.m11);
+  // B's sign form evaluated on A's output: x1 = m00 x ^ m01 z, z1 = m10 x ^ m11 z,
+  // x1 z1 = m00 m10 x ^ m01 m11 z ^ det(A) x z (bits: x^2 = x, z^2 = z)
+  C.al = A.al ^ (B.al & A.m00) ^ (B.be & A.m10) ^ (B.ga & A.m00 & A.m10);
+  C.be = A.be ^ (B.al & A.m01) ^ (B.be & A.m11) ^ (B.ga & A.m01 & A.m11);
+  C.ga = A.ga ^ (B.ga & ((A.m00 & A.m11) ^ (A.m01 & A.m10)));
+  return c1_encode(C);
 }
 
 // Global-address-space views: loads through them with a wave-uniform index

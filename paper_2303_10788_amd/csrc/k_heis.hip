@@ -28,11 +28,11 @@ struct PRow {
   uint32_t s;
 };
 
-// conjugation P -> G P G^dag of one Hermitian Pauli row by gate `kind`
+// conjugation P -> G P G^dag of one Hermitian Pauli row by gate `kind`:
+// CX, CZ or a fused one-qubit Clifford (G_C1 parameters in b)
 template <int W>
 __device__ inline void conj_gate(PRow<W> &r, uint32_t kind, uint32_t a, uint32_t b) {
-  const uint32_t wa = a >> 6, wb = b >> 6;
-  const uint64_t ma = 1ull << (a & 63), mb = 1ull << (b & 63);
+  const uint32_t wa = a >> 6, sa = a & 63;
   uint64_t xa_w = r.x[0], za_w = r.z[0];
 #pragma unroll
   for (int w = 1; w < W; ++w)
@@ -40,76 +40,60 @@ __device__ inline void conj_gate(PRow<W> &r, uint32_t kind, uint32_t a, uint32_t
       xa_w = r.x[w];
       za_w = r.z[w];
     }
-  const uint32_t xa = (xa_w & ma) != 0, za = (za_w & ma) != 0;
-  uint64_t nxa = xa_w, nza = za_w;
-  switch (kind) {
-    case G_H:
-      r.s ^= xa & za;
-      if (xa != za) {
-        nxa ^= ma;
-        nza ^= ma;
+  const uint32_t xa = (uint32_t)(xa_w >> sa) & 1u, za = (uint32_t)(za_w >> sa) & 1u;
+  if (kind == G_CX || kind == G_CZ) {
+    const uint32_t wb = b >> 6;
+    const uint64_t ma = 1ull << sa, mb = 1ull << (b & 63);
+    uint64_t nxa = xa_w, nza = za_w;
+    uint64_t xb_w = r.x[0], zb_w = r.z[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+      if (wb == (uint32_t)w) {
+        xb_w = r.x[w];
+        zb_w = r.z[w];
       }
-      break;
-    case G_S:
-      r.s ^= xa & za;
-      if (xa) nza ^= ma;
-      break;
-    case G_SDG:
-      r.s ^= xa & (za ^ 1u);
-      if (xa) nza ^= ma;
-      break;
-    case G_X: r.s ^= za; break;
-    case G_Y: r.s ^= xa ^ za; break;
-    case G_Z: r.s ^= xa; break;
-    case G_CX:
-    case G_CZ: {
-      uint64_t xb_w = r.x[0], zb_w = r.z[0];
-#pragma unroll
-      for (int w = 1; w < W; ++w)
-        if (wb == (uint32_t)w) {
-          xb_w = r.x[w];
-          zb_w = r.z[w];
-        }
-      const uint32_t xb = (xb_w & mb) != 0, zb = (zb_w & mb) != 0;
-      uint64_t flip_xb = 0, flip_zb = 0;
-      if (kind == G_CX) {
-        r.s ^= xa & zb & (xb ^ za ^ 1u);
-        if (xa) flip_xb = mb;
-        if (zb) nza ^= ma;
-      } else {
-        r.s ^= xa & xb & (za ^ zb);
-        if (xb) nza ^= ma;
-        if (xa) flip_zb = mb;
-      }
-      // write qubit-a word first, then apply the qubit-b flips to the
-      // (possibly same) word
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-        if (wa == (uint32_t)w) {
-          r.x[w] = nxa;
-          r.z[w] = nza;
-        }
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-        if (wb == (uint32_t)w) {
-          r.x[w] ^= flip_xb;
-          r.z[w] ^= flip_zb;
-        }
-      return;
+    const uint32_t xb = (xb_w & mb) != 0, zb = (zb_w & mb) != 0;
+    uint64_t flip_xb = 0, flip_zb = 0;
+    if (kind == G_CX) {
+      r.s ^= xa & zb & (xb ^ za ^ 1u);
+      if (xa) flip_xb = mb;
+      if (zb) nza ^= ma;
+    } else {
+      r.s ^= xa & xb & (za ^ zb);
+      if (xb) nza ^= ma;
+      if (xa) flip_zb = mb;
     }
-    default:
-      return;
+    // write qubit-a word first, then apply the qubit-b flips to the
+    // (possibly same) word
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (wa == (uint32_t)w) {
+        r.x[w] = nxa;
+        r.z[w] = nza;
+      }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (wb == (uint32_t)w) {
+        r.x[w] ^= flip_xb;
+        r.z[w] ^= flip_zb;
+      }
+    return;
   }
+  const C1Map g = c1_decode(b);
+  r.s ^= (g.al & xa) ^ (g.be & za) ^ (g.ga & xa & za);
+  const uint32_t nx = (g.m00 & xa) ^ (g.m01 & za), nz = (g.m10 & xa) ^ (g.m11 & za);
+  const uint64_t dx = (uint64_t)(xa ^ nx) << sa, dz = (uint64_t)(za ^ nz) << sa;
 #pragma unroll
   for (int w = 0; w < W; ++w)
     if (wa == (uint32_t)w) {
-      r.x[w] = nxa;
-      r.z[w] = nza;
+      r.x[w] ^= dx;
+      r.z[w] ^= dz;
     }
 }
 
 // Carry each row back through the fragment: O = U^dag P U, i.e. conjugate
-// by the inverse gates from the last gate to the first.
+// by the inverse gates from the last gate to the first.  F.ops is that
+// reversed stream of inverses (built on the host), read front to back.
 template <int W>
 __global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uint64_t *__restrict__ in,
                                                       uint64_t *__restrict__ out, uint32_t n_rows) {
@@ -124,17 +108,10 @@ __global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uin
   }
   r.s = ok ? (uint32_t)src[2 * W] & 1u : 0u;
   const uint32_t n16 = (F.n_ops + 15) / 16;
-  for (uint32_t g16 = n16; g16-- > 0;) {
+  for (uint32_t g16 = 0; g16 < n16; ++g16) {
     const Ops16 o = load_ops16(F.ops, g16);
 #pragma unroll
-    for (int t = 15; t >= 0; --t) {  // last gate first
-      uint32_t kind = op_kind(o.w[t]);
-      if (kind == G_S)  // inverse gate
-        kind = G_SDG;
-      else if (kind == G_SDG)
-        kind = G_S;
-      conj_gate<W>(r, kind, op_q0(o.w[t]), op_q1(o.w[t]));
-    }
+    for (int t = 0; t < 16; ++t) conj_gate<W>(r, op_kind(o.w[t]), op_q0(o.w[t]), op_q1(o.w[t]));
   }
   if (ok) {
     uint64_t *dst = out + (size_t)row * (2 * W + 1);

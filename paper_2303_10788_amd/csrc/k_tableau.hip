@@ -30,6 +30,16 @@ namespace ccut {
 
 namespace {
 
+// Preparation of a quantum input (digit d: |0>, |1> = X|0>, |+> = H|0>,
+// |+i> = S H|0>) and basis rotation of a quantum output (digit d: X -> H,
+// Y -> S^dag then H, Z -> none) as one-qubit Clifford maps.
+__device__ inline uint32_t prep_c1(uint32_t d) {
+  return d == 1 ? c1_of_gate(G_X) : d == 2 ? c1_of_gate(G_H) : d == 3 ? c1_then(c1_of_gate(G_H), c1_of_gate(G_S)) : 0u;
+}
+__device__ inline uint32_t basis_c1(uint32_t d) {
+  return d == 0 ? c1_of_gate(G_H) : d == 1 ? c1_then(c1_of_gate(G_SDG), c1_of_gate(G_H)) : 0u;
+}
+
 template <int W>
 struct RowAcc {
   uint64_t x[W];
@@ -66,73 +76,41 @@ __device__ inline RowAcc<W> acc_shfl_xor(const RowAcc<W> &a, int mask) {
 }
 
 // Apply one Clifford gate to row i (stabilizer rows also update their sign
-// constant; destabilizer signs never reach an outcome and are not kept).
+// constant; destabilizer signs never reach an outcome and are not kept):
+// CX, CZ, or a fused one-qubit Clifford (G_C1 parameters in b).
 template <int W>
 __device__ inline void gate_row(uint64_t *X, uint64_t *Z, uint32_t *CST, int R2, int m, int i,
                                 uint32_t kind, uint32_t a, uint32_t b) {
   const int wa = (int)(a >> 6);
-  const uint64_t ma = 1ull << (a & 63);
+  const uint32_t sa = a & 63;
   uint64_t *xa_p = X + wa * R2 + i;
   uint64_t *za_p = Z + wa * R2 + i;
   uint32_t flip = 0;
-  switch (kind) {
-    case G_H: {
-      uint64_t x = *xa_p, z = *za_p;
-      uint32_t xa = (x & ma) != 0, za = (z & ma) != 0;
-      flip = xa & za;
-      uint64_t d = (x ^ z) & ma;
-      *xa_p = x ^ d;
-      *za_p = z ^ d;
-      break;
-    }
-    case G_S: {
-      uint64_t x = *xa_p, z = *za_p;
-      uint32_t xa = (x & ma) != 0, za = (z & ma) != 0;
-      flip = xa & za;
-      if (xa) *za_p = z ^ ma;
-      break;
-    }
-    case G_SDG: {
-      uint64_t x = *xa_p, z = *za_p;
-      uint32_t xa = (x & ma) != 0, za = (z & ma) != 0;
-      flip = xa & (za ^ 1u);
-      if (xa) *za_p = z ^ ma;
-      break;
-    }
-    case G_X:
-      flip = (*za_p & ma) != 0;
-      break;
-    case G_Y:
-      flip = ((*xa_p ^ *za_p) & ma) != 0;
-      break;
-    case G_Z:
-      flip = (*xa_p & ma) != 0;
-      break;
-    case G_CX: {
-      const int wb = (int)(b >> 6);
-      const uint64_t mb = 1ull << (b & 63);
-      uint64_t *xb_p = X + wb * R2 + i;
-      uint64_t *zb_p = Z + wb * R2 + i;
-      uint32_t xc = (*xa_p & ma) != 0, zc = (*za_p & ma) != 0;
-      uint32_t xt = (*xb_p & mb) != 0, zt = (*zb_p & mb) != 0;
-      flip = xc & zt & (xt ^ zc ^ 1u);
-      if (xc) *xb_p ^= mb;
-      if (zt) *za_p ^= ma;
-      break;
-    }
-    case G_CZ: {
-      const int wb = (int)(b >> 6);
-      const uint64_t mb = 1ull << (b & 63);
-      uint64_t *zb_p = Z + wb * R2 + i;
-      uint32_t x1 = (*xa_p & ma) != 0, z1 = (*za_p & ma) != 0;
-      uint32_t x2 = (X[wb * R2 + i] & mb) != 0, z2 = (*zb_p & mb) != 0;
+  if (kind == G_CX || kind == G_CZ) {
+    const uint64_t ma = 1ull << sa;
+    const int wb = (int)(b >> 6);
+    const uint64_t mb = 1ull << (b & 63);
+    uint64_t *xb_p = X + wb * R2 + i;
+    uint64_t *zb_p = Z + wb * R2 + i;
+    const uint32_t x1 = (*xa_p & ma) != 0, z1 = (*za_p & ma) != 0;
+    const uint32_t x2 = (*xb_p & mb) != 0, z2 = (*zb_p & mb) != 0;
+    if (kind == G_CX) {
+      flip = x1 & z2 & (x2 ^ z1 ^ 1u);
+      if (x1) *xb_p ^= mb;
+      if (z2) *za_p ^= ma;
+    } else {
       flip = x1 & x2 & (z1 ^ z2);
       if (x2) *za_p ^= ma;
       if (x1) *zb_p ^= mb;
-      break;
     }
-    default:
-      break;
+  } else {
+    const C1Map g = c1_decode(b);
+    const uint64_t xw = *xa_p, zw = *za_p;
+    const uint32_t xa = (uint32_t)(xw >> sa) & 1u, za = (uint32_t)(zw >> sa) & 1u;
+    flip = (g.al & xa) ^ (g.be & za) ^ (g.ga & xa & za);
+    const uint32_t nx = (g.m00 & xa) ^ (g.m01 & za), nz = (g.m10 & xa) ^ (g.m11 & za);
+    *xa_p = xw ^ ((uint64_t)(xa ^ nx) << sa);
+    *za_p = zw ^ ((uint64_t)(za ^ nz) << sa);
   }
   if (i >= m) CST[i - m] ^= flip;
 }
@@ -190,14 +168,8 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       t /= F.axis_radix[j];
       if (F.axis_side[j] != 1 || d == 0) continue;
       const uint32_t q = F.axis_local[j];
-      for (int i = tid; i < R2; i += BLOCK) {
-        if (d == 1) {
-          gate_row<W>(X, Z, CST, R2, m, i, G_X, q, 0);
-        } else {
-          gate_row<W>(X, Z, CST, R2, m, i, G_H, q, 0);
-          if (d == 3) gate_row<W>(X, Z, CST, R2, m, i, G_S, q, 0);
-        }
-      }
+      const uint32_t g = prep_c1(d);
+      for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, G_C1, q, g);
     }
   }
   for (uint32_t g16 = 0; g16 < (F.n_ops + 15) / 16; ++g16) {
@@ -216,10 +188,8 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       t /= F.axis_radix[j];
       if (F.axis_side[j] != 0 || d == 2) continue;
       const uint32_t q = F.axis_local[j];
-      for (int i = tid; i < R2; i += BLOCK) {
-        if (d == 1) gate_row<W>(X, Z, CST, R2, m, i, G_SDG, q, 0);
-        gate_row<W>(X, Z, CST, R2, m, i, G_H, q, 0);
-      }
+      const uint32_t g = basis_c1(d);
+      for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, G_C1, q, g);
     }
   }
   __syncthreads();
@@ -367,46 +337,33 @@ __device__ inline uint64_t readlane64(uint64_t v, int lane) {
 template <int RPL>
 __device__ inline void gate_reg(uint64_t (&x)[RPL], uint64_t (&z)[RPL], uint32_t (&cst)[RPL], uint32_t kind,
                                 uint32_t a, uint32_t b) {
-  const uint64_t ma = 1ull << a, mb = 1ull << b;
+  if (kind == G_CX || kind == G_CZ) {
+    const uint64_t ma = 1ull << a, mb = 1ull << b;
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    const uint64_t xr = x[r], zr = z[r];
-    const uint32_t xa = (uint32_t)(xr >> a) & 1u, za = (uint32_t)(zr >> a) & 1u;
-    switch (kind) {
-      case G_H: {
-        cst[r] ^= xa & za;
-        const uint64_t d = (xr ^ zr) & ma;
-        x[r] = xr ^ d;
-        z[r] = zr ^ d;
-        break;
-      }
-      case G_S:
-        cst[r] ^= xa & za;
-        z[r] = zr ^ (xr & ma);
-        break;
-      case G_SDG:
-        cst[r] ^= xa & (za ^ 1u);
-        z[r] = zr ^ (xr & ma);
-        break;
-      case G_X: cst[r] ^= za; break;
-      case G_Y: cst[r] ^= xa ^ za; break;
-      case G_Z: cst[r] ^= xa; break;
-      case G_CX: {
-        const uint32_t xt = (uint32_t)(xr >> b) & 1u, zt = (uint32_t)(zr >> b) & 1u;
-        cst[r] ^= xa & zt & (xt ^ za ^ 1u);
+    for (int r = 0; r < RPL; ++r) {
+      const uint64_t xr = x[r], zr = z[r];
+      const uint32_t xa = (uint32_t)(xr >> a) & 1u, za = (uint32_t)(zr >> a) & 1u;
+      const uint32_t xb = (uint32_t)(xr >> b) & 1u, zb = (uint32_t)(zr >> b) & 1u;
+      if (kind == G_CX) {
+        cst[r] ^= xa & zb & (xb ^ za ^ 1u);
         x[r] = xr ^ (xa ? mb : 0ull);
-        z[r] = zr ^ (zt ? ma : 0ull);
-        break;
-      }
-      case G_CZ: {
-        const uint32_t xb = (uint32_t)(xr >> b) & 1u, zb = (uint32_t)(zr >> b) & 1u;
+        z[r] = zr ^ (zb ? ma : 0ull);
+      } else {
         cst[r] ^= xa & xb & (za ^ zb);
         z[r] = zr ^ (xb ? ma : 0ull) ^ (xa ? mb : 0ull);
-        break;
       }
-      default:
-        break;
     }
+    return;
+  }
+  // fused one-qubit Clifford (every other word, no-ops included)
+  const C1Map g = c1_decode(b);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const uint32_t xa = (uint32_t)(x[r] >> a) & 1u, za = (uint32_t)(z[r] >> a) & 1u;
+    cst[r] ^= (g.al & xa) ^ (g.be & za) ^ (g.ga & xa & za);
+    const uint32_t nx = (g.m00 & xa) ^ (g.m01 & za), nz = (g.m10 & xa) ^ (g.m11 & za);
+    x[r] ^= (uint64_t)(xa ^ nx) << a;
+    z[r] ^= (uint64_t)(za ^ nz) << a;
   }
 }
 
@@ -444,13 +401,7 @@ __device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
       t /= F.axis_radix[j];
       if (F.axis_side[j] != 1 || d == 0) continue;
-      const uint32_t q = F.axis_local[j];
-      if (d == 1) {
-        gate_reg<RPL>(x, z, cst, G_X, q, 0);
-      } else {
-        gate_reg<RPL>(x, z, cst, G_H, q, 0);
-        if (d == 3) gate_reg<RPL>(x, z, cst, G_S, q, 0);
-      }
+      gate_reg<RPL>(x, z, cst, G_C1, F.axis_local[j], prep_c1(d));
     }
   }
   const uint32_t n16 = (F.n_ops + 15) / 16;
@@ -465,9 +416,7 @@ __device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
       t /= F.axis_radix[j];
       if (F.axis_side[j] != 0 || d == 2) continue;
-      const uint32_t q = F.axis_local[j];
-      if (d == 1) gate_reg<RPL>(x, z, cst, G_SDG, q, 0);
-      gate_reg<RPL>(x, z, cst, G_H, q, 0);
+      gate_reg<RPL>(x, z, cst, G_C1, F.axis_local[j], basis_c1(d));
     }
   }
   uint64_t x0 = 0, randmask = 0, my_grow = 0;

@@ -96,6 +96,40 @@ void fuse_one_qubit_runs(Fragment &F) {
   for (uint32_t q = 0; q < m; ++q) flush(q);
 }
 
+// Fuse every run of one-qubit Cliffords on a qubit into one G_C1 word,
+// emitted just before the next two-qubit gate on that qubit (or at the
+// end): the forward stream for tableau passes and, from the same runs, the
+// reversed stream of inverse gates for the Heisenberg carry-back.
+void fuse_clifford_runs(Fragment &F) {
+  const uint32_t m = F.m();
+  std::vector<uint32_t> fwd(m, 0u), inv(m, 0u);
+  std::vector<char> has(m, 0);
+  std::vector<uint32_t> back;  // built forward, reversed at the end
+  auto flush = [&](uint32_t q) {
+    if (!has[q]) return;
+    F.cl_words.push_back(pack_op(G_C1, q, fwd[q]));
+    back.push_back(pack_op(G_C1, q, inv[q]));
+    fwd[q] = inv[q] = 0u;
+    has[q] = 0;
+  };
+  for (size_t g = 0; g < F.op_words.size(); ++g) {
+    const uint32_t w = F.op_words[g], k = op_kind(w), a = op_q0(w), b = op_q1(w);
+    if (is_two_qubit(k)) {
+      flush(a);
+      flush(b);
+      F.cl_words.push_back(w);
+      back.push_back(w);  // CX and CZ are their own inverses
+    } else {
+      const uint32_t kinv = k == G_S ? (uint32_t)G_SDG : k == G_SDG ? (uint32_t)G_S : k;
+      fwd[a] = c1_then(fwd[a], c1_of_gate(k));
+      inv[a] = c1_then(c1_of_gate(kinv), inv[a]);  // the inverse run applies the last gate's inverse first
+      has[a] = 1;
+    }
+  }
+  for (uint32_t q = 0; q < m; ++q) flush(q);
+  F.cl_back.assign(back.rbegin(), back.rend());
+}
+
 }  // namespace
 
 int build_plan(uint32_t n, const HostOp *ops, size_t n_ops, const uint32_t *cut_q,
@@ -250,7 +284,10 @@ int build_plan(uint32_t n, const HostOp *ops, size_t n_ops, const uint32_t *cut_
       return CCUT_E_UNSUPPORTED;
     }
     F.n_variants = nv;
-    if (!F.clifford) fuse_one_qubit_runs(F);
+    if (!F.clifford)
+      fuse_one_qubit_runs(F);
+    else
+      fuse_clifford_runs(F);
     if (!F.clifford && F.m() > max_nc) {
       err = "non-Clifford fragment " + std::to_string(F.index) + " has " + std::to_string(F.m()) +
             " qubits > max_nc_qubits = " + std::to_string(max_nc);
@@ -306,7 +343,7 @@ FragRequest zstring_request(const Fragment &f, const std::vector<uint64_t> &anym
 FragDev make_frag_dev(const Fragment &f, const FragRequest &r, uint64_t vid_base) {
   FragDev d{};
   d.m = f.m();
-  d.n_ops = (uint32_t)(f.clifford ? f.op_words.size() : f.sv_words.size());
+  d.n_ops = (uint32_t)(f.clifford ? f.cl_words.size() : f.sv_words.size());
   d.n_axes = (uint32_t)f.axes.size();
   d.n_meas = (uint32_t)r.meas.size();
   d.n_req = (uint32_t)r.req_pos.size();

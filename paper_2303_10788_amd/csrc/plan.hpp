@@ -30,6 +30,10 @@ struct Fragment {
   std::vector<uint32_t> wires, segs;        // local qubit i = (wires[i], segs[i])
   std::vector<uint32_t> op_words;           // packed local ops, in circuit order
   std::vector<double> op_theta;
+  // Clifford fragments: runs of one-qubit gates on a qubit fused into one
+  // G_C1 word (cl_words, circuit order), and the inverse stream for the
+  // Heisenberg carry-back (cl_back: last gate first, each gate inverted)
+  std::vector<uint32_t> cl_words, cl_back;
   // non-Clifford fragments: the same ops with runs of one-qubit gates on a
   // qubit fused into one 2x2 unitary (G_U2) for the state-vector kernel
   std::vector<uint32_t> sv_words;
