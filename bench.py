@@ -102,19 +102,10 @@ def main():
         plan.marginal(w.qubits, shots=w.shots, seed=w.seed, out=out_m)
         plan.zexpect(masks, shots=w.shots, seed=w.seed, out=out_z)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.timing_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    times = ctx.kernel_times()
-    ctx.timing(False)
+    dt = _timed(step, args.steps, args.warmup)
+    # per-kernel breakdown from a separate pass with event timing on (the
+    # events themselves cost time, so the timed steps above run without)
+    times = _kernel_pass(ctx, step, args.steps)
 
     shots_per_step = 2 * n_cliff_var * w.shots
     terms_per_step = (4 ** k) * ((1 << len(w.qubits)) + masks.shape[0])
@@ -160,6 +151,20 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def _kernel_pass(ctx, fn, steps):
+    """{kernel: (launches, total ms)} over `steps` calls of fn with event timing."""
+    import torch
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_reset()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    times = ctx.kernel_times()
+    ctx.timing(False)
+    return times
 
 
 def _timed(fn, steps, warmup):
@@ -235,11 +240,8 @@ def bench_precision(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.timing_reset()
     dt = _timed(step, args.steps, 0)
-    times = ctx.kernel_times()
-    ctx.timing(False)
+    times = _kernel_pass(ctx, step, args.steps)
     r64 = plan.marginal(w.qubits)
     z64 = plan.zexpect(masks)
     err_m = float(np.abs(out_m.cpu().numpy() - r64).max())
@@ -326,11 +328,8 @@ def bench_learned(args):
         L.close()
 
     dt_ex = _timed(exhaustive, args.steps, args.warmup)
-    ctx.timing(True)
-    ctx.timing_reset()
     dt_le = _timed(learned, args.steps, args.warmup)
-    times = ctx.kernel_times()
-    ctx.timing(False)
+    times = _kernel_pass(ctx, learned, args.steps)
     ex = out_ex.cpu().numpy()
     le = out_le.cpu().numpy()
     tvd = 0.5 * float(np.abs(le - ex).sum())

@@ -16,8 +16,13 @@
  *    networks) keep it alive: destroying the context first defers its
  *    release until the last of them is destroyed;
  *  - a context is not thread-safe: use one per host thread;
- *  - device work runs on the context's HIP stream and every call returns
- *    only after its results are in the caller's buffer (host or device);
+ *  - device work runs on the context's HIP stream; a call with host outputs
+ *    returns after its results are in the caller's buffer, a call with
+ *    device outputs (out_on_device != 0) returns once the copy into the
+ *    caller's buffer is enqueued as the call's last work on that stream
+ *    (read it in stream order, or after synchronizing the stream); host
+ *    inputs are staged in pinned memory and may be reused when the call
+ *    returns;
  *  - results are a pure function of (ops, cuts, request, seed, shots, mode):
  *    every random bit is Philox4x32-10 keyed by seed and counted by
  *    (variant id, shot, measurement index);

@@ -96,6 +96,19 @@ struct ccut_ctx {
   std::vector<std::vector<char>> staged;  // host copies kept alive until the call's final sync
   bool use_aux = true;       // route non-Clifford fragments to the auxiliary stream
   bool replay_uploads = false;  // re-enqueue of an identical sequence: reuse earlier uploads, copy nothing
+  // Pinned staging of host-to-device uploads: a ring of slots, one per call;
+  // a slot is reused only after the events recorded behind its call's work
+  // (on both streams) have completed, so calls with device outputs need not
+  // synchronize.
+  struct PinSlot {
+    std::vector<std::pair<char *, size_t>> chunks;
+    size_t chunk = 0, used = 0;
+    hipEvent_t ev_s = nullptr, ev_a = nullptr;
+    bool pending = false;
+  };
+  static constexpr int kPinSlots = 4;
+  PinSlot pin[kPinSlots];
+  int pin_cur = -1;
 };
 
 struct ccut_plan {
@@ -203,6 +216,8 @@ ccut_status ensure_ops(ccut_plan *p) {
   return CCUT_OK;
 }
 
+hipError_t pin_begin(ccut_ctx *c);
+
 ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   if (!p || !eo) return CCUT_E_INVALID;
   ccut_ctx *c = p->ctx;
@@ -215,6 +230,7 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   c->cancel.store(0);
   c->arena.reset();
   c->staged.clear();
+  HIP_TRY(c, pin_begin(c));
   if (!c->aux) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
@@ -240,16 +256,59 @@ ccut_status join(ccut_ctx *c) {
   return CCUT_OK;
 }
 
-// Copy host bytes to fresh device memory on the context stream; the host
-// copy is kept until the call synchronizes.  A null source (an empty host
-// vector) gets the allocation without a copy.
+// Start a call's staging slot: mark the previous slot's work with events on
+// both streams, move to the next slot and wait until its last use is done.
+hipError_t pin_begin(ccut_ctx *c) {
+  if (c->pin_cur >= 0) {
+    ccut_ctx::PinSlot &prev = c->pin[c->pin_cur];
+    if (!prev.ev_s) {
+      hipError_t e = hipEventCreateWithFlags(&prev.ev_s, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&prev.ev_a, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(prev.ev_s, c->stream);
+    if (e != hipSuccess) return e;
+    if (c->aux && (e = hipEventRecord(prev.ev_a, c->aux)) != hipSuccess) return e;
+    prev.pending = true;
+  }
+  c->pin_cur = (c->pin_cur + 1) % ccut_ctx::kPinSlots;
+  ccut_ctx::PinSlot &sl = c->pin[c->pin_cur];
+  if (sl.pending) {
+    hipError_t e = hipEventSynchronize(sl.ev_s);
+    if (e != hipSuccess) return e;
+    if (c->aux && (e = hipEventSynchronize(sl.ev_a)) != hipSuccess) return e;
+    sl.pending = false;
+  }
+  sl.chunk = 0;
+  sl.used = 0;
+  return hipSuccess;
+}
+
+// Copy host bytes to fresh device memory on the current stream, staged in
+// the call's pinned slot.  A null source (an empty host vector) gets the
+// allocation without a copy.
 void *upload(ccut_ctx *c, const void *src, size_t bytes) {
   void *d = c->arena.get(bytes);
   if (!d) return nullptr;
   if (c->replay_uploads || !src || bytes == 0) return d;  // replay: the bytes are already there
-  c->staged.emplace_back((const char *)src, (const char *)src + bytes);
-  if (hipMemcpyAsync(d, c->staged.back().data(), bytes, hipMemcpyHostToDevice, c->cur) != hipSuccess)
-    return nullptr;
+  if (c->pin_cur < 0 && pin_begin(c) != hipSuccess) return nullptr;
+  ccut_ctx::PinSlot &sl = c->pin[c->pin_cur];
+  const size_t need = (bytes + 255) & ~size_t(255);
+  while (sl.chunk < sl.chunks.size() && sl.used + need > sl.chunks[sl.chunk].second) {
+    ++sl.chunk;
+    sl.used = 0;
+  }
+  if (sl.chunk == sl.chunks.size()) {
+    const size_t cap = std::max<size_t>(need, size_t(1) << 20);
+    char *h = nullptr;
+    if (hipHostMalloc((void **)&h, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+    sl.chunks.push_back({h, cap});
+    sl.used = 0;
+  }
+  char *stage = sl.chunks[sl.chunk].first + sl.used;
+  sl.used += need;
+  std::memcpy(stage, src, bytes);
+  if (hipMemcpyAsync(d, stage, bytes, hipMemcpyHostToDevice, c->cur) != hipSuccess) return nullptr;
   return d;
 }
 
@@ -514,10 +573,13 @@ bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo) {
   return f.clifford && eo->shots_per_variant == 0 && eo->method != CCUT_METHOD_VARIANTS;
 }
 
+// Results to the caller: into host memory with a final synchronization, or
+// into device memory in stream order (the copy is the call's last work on
+// the context's stream; no synchronization).
 ccut_status finish_out(ccut_ctx *c, const double *dev, double *out, size_t count, int on_device) {
   HIP_TRY(c, hipMemcpyAsync(out, dev, count * sizeof(double),
                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->cur));
-  HIP_TRY(c, hipStreamSynchronize(c->cur));
+  if (!on_device) HIP_TRY(c, hipStreamSynchronize(c->cur));
   return CCUT_OK;
 }
 
@@ -584,6 +646,11 @@ void ctx_free(ccut_ctx *c) {
       (void)hipEventDestroy(c->join_ev);
     }
     c->arena.release();
+    for (auto &sl : c->pin) {
+      for (auto &ch : sl.chunks) (void)hipHostFree(ch.first);
+      if (sl.ev_s) (void)hipEventDestroy(sl.ev_s);
+      if (sl.ev_a) (void)hipEventDestroy(sl.ev_a);
+    }
   }
   delete c;
 }
@@ -906,10 +973,13 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   if ((st = join(c)) != CCUT_OK) return st;
   RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
   double *res = aget<double>(c, n_strings);
-  if (!dargs || !res) return fail(c, CCUT_E_OOM, "device allocation failed");
+  const uint32_t zsplits = zrecombine_splits(pd.k, n_strings);
+  double *zpart = aget<double>(c, (size_t)zsplits * n_strings);
+  if (!dargs || !res || !zpart) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
     KTimer t(c, CCUT_K_ZRECOMBINE);
-    HIP_TRY(c, launch_zrecombine(dargs, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM, res, c->cur));
+    HIP_TRY(c, launch_zrecombine(dargs, pd.k, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM, zpart, zsplits,
+                                 res, c->cur));
   }
   return finish_out(c, res, out, n_strings, on_device);
 }
@@ -1359,6 +1429,7 @@ ccut_status begin_call(ccut_ctx *c) {
   c->arena.reset();
   c->staged.clear();
   c->cur = c->stream;
+  HIP_TRY(c, pin_begin(c));
   return CCUT_OK;
 }
 

@@ -9,6 +9,8 @@
 //   quantum output, measured in basis (X, Y, Z) with outcome bit o:
 //     I = Z0 + Z1, X = X0 - X1, Y = Y0 - Y1, Z = Z0 - Z1
 // applied one axis at a time; the fragment tensor ends as T_f[p_f][b_f].
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ccut {
@@ -85,14 +87,17 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
 // the product taken in fp32 to first order (prod hi + sum_f lo_f prod_{g!=f}
 // hi_g), summed in fp32 over 8 consecutive terms, those sums added in fp64.
 template <bool F32>
-__global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings, double *__restrict__ outp) {
+__global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings, uint64_t per_split,
+                                  double *__restrict__ partial) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n_strings) return;
   const uint32_t nf = A->n_frags, k = A->k;
   const uint64_t nterms = 1ull << (2 * k);
+  const uint64_t P0 = (uint64_t)blockIdx.y * per_split;
+  const uint64_t P1 = P0 + per_split < nterms ? P0 + per_split : nterms;
   double acc = 0.0;
   float chunk = 0.f;
-  for (uint64_t P = 0; P < nterms; ++P) {
+  for (uint64_t P = P0; P < P1; ++P) {
     double term = 1.0;
     float hi = 1.f, corr = 0.f;
     for (uint32_t f = 0; f < nf; ++f) {
@@ -110,7 +115,7 @@ __global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_s
     }
     if (F32) {
       chunk += hi + corr;
-      if ((P & 7) == 7 || P + 1 == nterms) {
+      if ((P & 7) == 7 || P + 1 == P1) {
         acc += (double)chunk;
         chunk = 0.f;
       }
@@ -118,6 +123,16 @@ __global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_s
       acc += term;
     }
   }
+  partial[(uint64_t)blockIdx.y * n_strings + s] = acc;
+}
+
+// out[s] = 2^-k sum over term ranges in order
+__global__ void zrecombine_final_kernel(const double *__restrict__ partial, uint32_t n_strings, uint32_t splits,
+                                        uint32_t k, double *__restrict__ outp) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_strings) return;
+  double acc = 0.0;
+  for (uint32_t sp = 0; sp < splits; ++sp) acc += partial[(uint64_t)sp * n_strings + s];
   outp[s] = ldexp(acc, -(int)k);
 }
 
@@ -139,13 +154,30 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *
   return hipGetLastError();
 }
 
-hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t n_strings, bool fp32, double *out, hipStream_t s) {
+// term ranges of 64 terms or more (multiples of 8, so fp32 groups never
+// straddle a range), about 1024 workgroups in all
+uint32_t zrecombine_splits(uint32_t k, uint32_t n_strings) {
+  const uint64_t nterms = 1ull << (2 * k);
+  const uint64_t sblocks = (n_strings + 63) / 64;
+  uint64_t sp = std::max<uint64_t>(1, 1024 / std::max<uint64_t>(sblocks, 1));
+  sp = std::min<uint64_t>(sp, (nterms + 63) / 64);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(sp, 65535));
+}
+
+hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t k, uint32_t n_strings, bool fp32, double *partial,
+                             uint32_t splits, double *out, hipStream_t s) {
+  const uint64_t nterms = 1ull << (2 * k);
+  uint64_t per = (nterms + splits - 1) / splits;
+  per = (per + 7) & ~7ull;
+  const dim3 grid(blocks_for(n_strings, 64), splits);
   if (fp32)
-    hipLaunchKernelGGL((zrecombine_kernel<true>), dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args, n_strings,
-                       out);
+    hipLaunchKernelGGL((zrecombine_kernel<true>), grid, dim3(64), 0, s, d_args, n_strings, per, partial);
   else
-    hipLaunchKernelGGL((zrecombine_kernel<false>), dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, d_args, n_strings,
-                       out);
+    hipLaunchKernelGGL((zrecombine_kernel<false>), grid, dim3(64), 0, s, d_args, n_strings, per, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(zrecombine_final_kernel, dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, partial, n_strings,
+                     splits, k, out);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ namespace ccut {
 namespace {
 
 constexpr int kSvBlock = 256;
+constexpr int kMaxNcPerThread = (1 << kMaxNcQubits) / kSvBlock;  // amplitudes per thread, at most
 
 struct C2 {
   double re, im;
@@ -92,10 +93,87 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
   __syncthreads();
 }
 
+// The fused op stream (U2, CX, CZ and no-ops) on the state in LDS.  Each
+// thread owns PPT amplitude pairs of every op and issues all their loads
+// (and the op's 2x2 matrix, staged in LDS once per chunk of 16 ops) before
+// any arithmetic; one barrier per op.
+template <int PPT>
+__device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
+  const uint32_t half = (1u << m) >> 1;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t n16 = (F.n_ops + 15) / 16;
+  for (uint32_t g16 = 0; g16 < n16; ++g16) {
+    // (the previous op's barrier has retired every read of the last chunk)
+    if (tid < 64) s_mats[tid] = C2{F.mats[(size_t)g16 * 128 + 2 * tid], F.mats[(size_t)g16 * 128 + 2 * tid + 1]};
+    __syncthreads();
+    // one rolled op loop keeps the code small; the op word is a scalar load
+    // issued when no LDS access is outstanding
+#pragma unroll 1
+    for (int t = 0; t < 16; ++t) {
+      const uint32_t w = ((const g_u32 *)F.ops)[g16 * 16 + t];
+      const uint32_t kind = op_kind(w);
+      if (kind == G_NOP) continue;
+      const uint32_t a = op_q0(w), b = op_q1(w);
+      const uint32_t ma = 1u << a;
+      if (kind == G_U2) {
+        const C2 *M = s_mats + 4 * t;
+        const C2 m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
+        uint32_t i0[PPT];
+        double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const uint32_t k = tid + p * kSvBlock;
+          i0[p] = ins0(k < half ? k : 0, a);
+          const C2 u = amp[i0[p]], v = amp[i0[p] | ma];
+          xr[p] = u.re;
+          xi[p] = u.im;
+          yr[p] = v.re;
+          yi[p] = v.im;
+        }
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          if (tid + p * kSvBlock < half) {
+            const C2 x{xr[p], xi[p]}, y{yr[p], yi[p]};
+            amp[i0[p]] = cadd(cmul(m00, x), cmul(m01, y));
+            amp[i0[p] | ma] = cadd(cmul(m10, x), cmul(m11, y));
+          }
+        }
+      } else if (kind == G_CX) {
+        // swap the target pair where the control bit is set
+        const uint32_t mb = 1u << b;
+        uint32_t i0[PPT];
+        double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          const uint32_t k = tid + p * kSvBlock;
+          i0[p] = ins0(k < half ? k : 0, b);
+          const C2 u = amp[i0[p]], v = amp[i0[p] | mb];
+          xr[p] = u.re;
+          xi[p] = u.im;
+          yr[p] = v.re;
+          yi[p] = v.im;
+        }
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          if (tid + p * kSvBlock < half && (i0[p] & ma)) {
+            amp[i0[p]] = C2{yr[p], yi[p]};
+            amp[i0[p] | mb] = C2{xr[p], xi[p]};
+          }
+        }
+      } else if (kind == G_CZ) {
+        const uint32_t mb = 1u << b;
+        for (uint32_t i = tid; i < 2 * half; i += kSvBlock)
+          if ((i & ma) && (i & mb)) amp[i] = C2{-amp[i].re, -amp[i].im};
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int PPT>
 __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *__restrict__ dist) {
   extern __shared__ C2 smem_amp[];
-  __shared__ double part[kSvBlock];
-  __shared__ double s_mats[16 * 8];
+  __shared__ C2 s_mats[64];
   const uint32_t m = F.m;
   const uint32_t N = 1u << m;
   const uint32_t tid = threadIdx.x;
@@ -125,26 +203,12 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
       stride *= F.axis_radix[j];
     }
   }
-  // the fused 2x2 matrices of a chunk of 16 ops are staged in LDS (one
-  // coalesced load) so gates read them with broadcast LDS reads
-  for (uint32_t g16 = 0; g16 < (F.n_ops + 15) / 16; ++g16) {
-    for (uint32_t i = tid; i < 16 * 8; i += kSvBlock) s_mats[i] = F.mats[(size_t)g16 * 128 + i];
-    __syncthreads();
-    const Ops16 o = load_ops16(F.ops, g16);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const uint32_t w = o.w[t];
-      if (op_kind(w) == G_NOP) continue;
-      apply_gate(base, m, op_kind(w), op_q0(w), op_q1(w), s_mats + 8 * t);
-    }
-  }
+  sv_run_ops<PPT>(base, m, F, s_mats);
   // outcome distribution of every basis combination
   const uint32_t nm = F.n_meas;
   uint32_t mmask = 0;
   for (uint32_t j = 0; j < nm; ++j) mmask |= 1u << F.meas[j];
-  const uint32_t rest = m - nm;
   const uint32_t outs = 1u << nm;
-  const uint32_t tpo = outs >= (uint32_t)kSvBlock ? 1u : (uint32_t)kSvBlock / outs;  // threads per output
   uint32_t n_bc = 1;
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   for (uint32_t bc = 0; bc < n_bc; ++bc) {
@@ -169,34 +233,40 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
       }
     }
     double *out = dist + v * outs;
-    // entry o sums |amp|^2 over the unmeasured bits; tpo threads per entry
-    // take interleaved parts, then one thread adds the parts in order
-    for (uint32_t o0 = 0; o0 < outs; o0 += kSvBlock / tpo) {
-      const uint32_t o = o0 + tid / tpo, part_id = tid % tpo;
-      double acc = 0.0;
-      if (o < outs) {
-        uint32_t basei = 0;
-        for (uint32_t j = 0; j < nm; ++j) basei |= ((o >> j) & 1u) << F.meas[j];
-        for (uint32_t r = part_id; r < (1u << rest); r += tpo) {
-          uint32_t idx = basei, rr = r;
-          for (uint32_t q = 0; q < m; ++q) {
-            if (mmask & (1u << q)) continue;
-            idx |= (rr & 1u) << q;
-            rr >>= 1;
-          }
-          const C2 a = work[idx];
-          acc += a.re * a.re + a.im * a.im;
-        }
-      }
-      part[tid] = acc;
-      __syncthreads();
-      if (part_id == 0 && o < outs) {
-        double s = 0.0;
-        for (uint32_t t = 0; t < tpo; ++t) s += part[tid + t];
-        out[o] = s;
+    // outcome probabilities: |amp|^2 in place (reusing the work buffer as
+    // N doubles), then a pairwise sum over each unmeasured qubit in turn
+    // (fixed order, one barrier per qubit); the entry of outcome o is left
+    // at the index with o's bits on the measured qubits and zeros elsewhere
+    double pr[kMaxNcPerThread];
+#pragma unroll
+    for (int j = 0; j < kMaxNcPerThread; ++j) {
+      const uint32_t i = tid + j * kSvBlock;
+      pr[j] = 0.0;
+      if (i < N) pr[j] = work[i].re * work[i].re + work[i].im * work[i].im;
+    }
+    __syncthreads();
+    double *P = reinterpret_cast<double *>(work);
+#pragma unroll
+    for (int j = 0; j < kMaxNcPerThread; ++j) {
+      const uint32_t i = tid + j * kSvBlock;
+      if (i < N) P[i] = pr[j];
+    }
+    __syncthreads();
+    for (uint32_t q = 0; q < m; ++q) {
+      if (mmask & (1u << q)) continue;
+      const uint32_t mq = 1u << q;
+      for (uint32_t k = tid; k < N / 2; k += kSvBlock) {
+        const uint32_t i0 = ins0(k, q);
+        P[i0] += P[i0 | mq];
       }
       __syncthreads();
     }
+    for (uint32_t o = tid; o < outs; o += kSvBlock) {
+      uint32_t idx = 0;
+      for (uint32_t j = 0; j < nm; ++j) idx |= ((o >> j) & 1u) << F.meas[j];
+      out[o] = P[idx];
+    }
+    __syncthreads();  // the next basis combination overwrites the work buffer
   }
 }
 
@@ -207,10 +277,12 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   uint32_t n_in = 0, n_out = 0;
   for (uint32_t j = 0; j < h.n_axes; ++j) (h.axis_side[j] ? n_in : n_out) += 1;
   const size_t lds = (size_t(1) << h.m) * sizeof(C2) * (n_out ? 2 : 1);
-  hipError_t e = hipFuncSetAttribute((const void *)sv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // amplitude pairs per thread per op: 2^(m-1) / 256, at least one
+  auto kern = h.m <= 9 ? sv_kernel<1> : h.m == 10 ? sv_kernel<2> : h.m == 11 ? sv_kernel<4> : sv_kernel<8>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const uint64_t n_prep = 1ull << (2 * n_in);
-  hipLaunchKernelGGL(sv_kernel, dim3((unsigned)n_prep), dim3(kSvBlock), lds, s, h, dist);
+  hipLaunchKernelGGL(kern, dim3((unsigned)n_prep), dim3(kSvBlock), lds, s, h, dist);
   return hipGetLastError();
 }
 
