@@ -198,6 +198,8 @@ def bench_batching(args):
     info = batch.info()
     outs = [torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda") for w in ws]
     dt = _timed(lambda: batch.run(outs), args.steps, args.warmup)
+    eager = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=2000, use_graph=False)
+    dt_eager = _timed(lambda: eager.run(outs), args.steps, args.warmup)
     n_var = sum(f["n_variants"] for p in plans for f in p.fragments() if f["clifford"])
     shots_per_step = n_var * shots
     line = {
@@ -207,7 +209,7 @@ def bench_batching(args):
         "config": {"workload": "batching: 256 near-Clifford circuits, width 20-200, depth 20-60, 1-6 T, 1-4 cuts, "
                                "1e4 shots per variant, 16-qubit marginals, one graph-captured batch",
                    "clifford_variants": n_var, "shots_per_step": shots_per_step},
-        "batch": dict(info, create_s=t_create),
+        "batch": dict(info, create_s=t_create, eager_ms_per_step=1e3 * dt_eager / args.steps),
         "roofline": {"bound": "alu", "kernel": "tableau_batch_kernel", "achieved": None, "peak": PEAK_INT32_OPS / 1e9,
                      "unit": "Gop/s", "frac": None, "traffic": None, "avg_launch_us": info["tableau_ms"] * 1e3},
     }

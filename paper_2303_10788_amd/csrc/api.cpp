@@ -342,6 +342,28 @@ FragDev frag_desc(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_
   return h;
 }
 
+// Affine sample models of variants [v0, v0 + nv) of a Clifford fragment.
+// With more than a few variants, the fragment's gates run once on the
+// identity tableau (one row per lane) and every variant starts from that
+// shared tableau with its preparations as row substitutions.
+constexpr uint64_t kBaseMinVariants = 16;
+ccut_status tableau_models(ccut_ctx *c, const Fragment &f, const FragDev &h, uint64_t v0, uint64_t nv,
+                           uint64_t *models) {
+  const uint64_t *base = nullptr;
+  if (nv > kBaseMinVariants) {
+    const uint32_t W = row_words(f.m());
+    if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
+    uint64_t *b = aget<uint64_t>(c, (size_t)2 * f.m() * (2 * W + 1));
+    if (!b) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_TABLEAU);
+    HIP_TRY(c, launch_rows(h, W, nullptr, b, 2 * f.m(), c->cur));
+    base = b;
+  }
+  KTimer t(c, CCUT_K_TABLEAU);
+  HIP_TRY(c, launch_tableau(h, v0, nv, models, c->cur, base));
+  return CCUT_OK;
+}
+
 // Per-variant outcome distributions dist[v][x] over the measured set.
 ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment &f,
                           const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr) {
@@ -365,8 +387,8 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     if (!models) {
       models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
-      KTimer t(c, CCUT_K_TABLEAU);
-      HIP_TRY(c, launch_tableau(h, 0, nv, models, c->cur));
+      ccut_status st2 = tableau_models(c, f, h, 0, nv, models);
+      if (st2 != CCUT_OK) return st2;
     }
     if (eo->shots_per_variant == 0) {
       KTimer t(c, CCUT_K_EXACT);
@@ -552,12 +574,12 @@ ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res) {
   return CCUT_OK;
 }
 
-// Contract the fragment tensors into out[2^nq].  fp64 with few terms x
-// outputs: the plain ascending sum; otherwise the K-split MFMA contraction
+// Contract the fragment tensors into out[2^nq].  fp64 with at most 2^20
+// term-outputs: the plain ascending sum; otherwise the K-split MFMA contraction
 // (fp32 products with fp64 across K-chunks, or fp64 MFMA).
 ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
   const uint64_t K = 1ull << (2 * args.k);
-  if (!fp32 && (K << nq) <= (1ull << 26)) {
+  if (!fp32 && (K << nq) <= (1ull << 20)) {
     RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
     if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
     KTimer t(c, CCUT_K_RECOMBINE);
@@ -940,8 +962,8 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
       uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
-        KTimer t(c, CCUT_K_TABLEAU);
-        HIP_TRY(c, launch_tableau(h, 0, nv, models, c->cur));
+        ccut_status st2 = tableau_models(c, f, h, 0, nv, models);
+        if (st2 != CCUT_OK) return st2;
       }
       if (eo->shots_per_variant == 0) {
         KTimer t(c, CCUT_K_PARITY);
@@ -1006,10 +1028,7 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   const uint64_t shots = eo->shots_per_variant;
   uint64_t *rec = aget<uint64_t>(c, nv * shots);
   if (!models || !rec) return fail(c, CCUT_E_OOM, "device allocation failed");
-  {
-    KTimer t(c, CCUT_K_TABLEAU);
-    HIP_TRY(c, launch_tableau(h, v_begin, nv, models, c->cur));
-  }
+  if ((st = tableau_models(c, f, h, v_begin, nv, models)) != CCUT_OK) return st;
   const uint64_t nquads = (shots + 3) / 4;
   for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
     const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
@@ -1097,11 +1116,25 @@ struct ccut_batch {
   std::vector<BatchItem> items;
   std::vector<std::vector<int64_t>> model_off;  // per plan, per fragment: word offset or -1
   uint64_t model_words_total = 0;
+  // shared base tableaux: word offset per descriptor, and the descriptors
+  // of each row-width class (1, 2, 4, 8 words per half) with its most rows
+  std::vector<uint64_t> base_off;
+  uint64_t base_words_total = 0;
+  // independent per-plan steps run on a pool of streams (default priority),
+  // forked from and joined back into the batch stream
+  std::vector<hipStream_t> pool;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  std::vector<uint32_t> wlist[4];
+  uint32_t wrows[4] = {0, 0, 0, 0};
   uint32_t max_m = 0, block = 64, grid = 0, use_reg = 1;
   double tuned_ms = 0.0;
   ~ccut_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (auto ps : pool) (void)hipStreamDestroy(ps);
+    for (auto e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (stream) (void)hipStreamDestroy(stream);
     arena.release();
   }
@@ -1136,11 +1169,33 @@ struct BatchScope {
 };
 
 ccut_status batch_tableau(ccut_batch *b, FragDev *d_descs, BatchItem *d_items, uint32_t *d_counter,
-                          uint64_t *d_models, uint32_t block, uint32_t grid, uint32_t use_reg) {
+                          uint64_t *d_models, uint32_t block, uint32_t grid, uint32_t use_reg,
+                          const uint64_t *d_bases) {
   ccut_ctx *c = b->ctx;
   if (b->items.empty()) return CCUT_OK;
   HIP_TRY(c, launch_tableau_batch(d_descs, d_items, (uint32_t)b->items.size(), d_counter, d_models, b->max_m, block,
-                                  grid, use_reg, c->cur));
+                                  grid, use_reg, d_bases, c->cur));
+  return CCUT_OK;
+}
+
+// The shared base tableau of every Clifford descriptor: one launch per
+// row-width class, one row per lane.
+ccut_status batch_bases(ccut_batch *b, FragDev *d_descs, uint64_t **d_bases_out) {
+  ccut_ctx *c = b->ctx;
+  *d_bases_out = nullptr;
+  if (b->descs.empty()) return CCUT_OK;
+  uint64_t *d_bases = aget<uint64_t>(c, std::max<uint64_t>(b->base_words_total, 1));
+  uint64_t *d_off = (uint64_t *)upload(c, b->base_off.data(), b->base_off.size() * 8);
+  if (!d_bases || !d_off) return fail(c, CCUT_E_OOM, "device allocation failed");
+  static const uint32_t kW[4] = {1, 2, 4, 8};
+  for (int k = 0; k < 4; ++k) {
+    if (b->wlist[k].empty()) continue;
+    uint32_t *d_list = (uint32_t *)upload(c, b->wlist[k].data(), b->wlist[k].size() * 4);
+    if (!d_list) return fail(c, CCUT_E_OOM, "device allocation failed");
+    HIP_TRY(c, launch_base_batch(d_descs, kW[k], d_list, (uint32_t)b->wlist[k].size(), b->wrows[k], d_off, d_bases,
+                                 c->cur));
+  }
+  *d_bases_out = d_bases;
   return CCUT_OK;
 }
 
@@ -1159,6 +1214,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   uint32_t *d_counter = aget<uint32_t>(c, 64);
   uint64_t *d_models = aget<uint64_t>(c, std::max<uint64_t>(b->model_words_total, 1));
   if (!d_descs || !d_items || !d_counter || !d_models) return fail(c, CCUT_E_OOM, "device allocation failed");
+  uint64_t *d_bases = nullptr;
+  if ((st = batch_bases(b, d_descs, &d_bases)) != CCUT_OK) return st;
   if (tune && !b->items.empty()) {
     // autotune the persistent launch: workgroup size x workgroups per CU
     int cus = 256;
@@ -1176,9 +1233,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
           if (reg && block != 64) continue;
           const uint32_t grid = (uint32_t)cus * per_cu;
           // warm once, then time
-          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg)) != CCUT_OK) return st;
+          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg, d_bases)) != CCUT_OK) return st;
           HIP_TRY(c, hipEventRecord(e0, c->cur));
-          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg)) != CCUT_OK) return st;
+          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg, d_bases)) != CCUT_OK) return st;
           HIP_TRY(c, hipEventRecord(e1, c->cur));
           HIP_TRY(c, hipEventSynchronize(e1));
           float ms = 0.f;
@@ -1196,8 +1253,14 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     (void)hipEventDestroy(e1);
     b->tuned_ms = best;
   }
-  if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg)) != CCUT_OK)
+  if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg, d_bases)) != CCUT_OK)
     return st;
+  // the plans' remaining steps are independent: plan i runs on pool stream
+  // i mod P, after the shared tableau launch, and every pool stream joins
+  // back before the batch stream continues
+  const size_t P = b->pool.size();
+  HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+  for (size_t k = 0; k < P; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
   for (size_t i = 0; i < b->plans.size(); ++i) {
     ccut_plan *p = b->plans[i];
     ccut_eval_opts eo = b->eo;
@@ -1209,8 +1272,14 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (b->res.size() <= i) b->res.push_back(res);
     b->res[i] = res;
-    if ((st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre)) != CCUT_OK)
-      return st;
+    c->stream = c->cur = P ? b->pool[i % P] : b->stream;
+    st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre);
+    c->stream = c->cur = b->stream;
+    if (st != CCUT_OK) return st;
+  }
+  for (size_t k = 0; k < P; ++k) {
+    HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
+    HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
   }
   return CCUT_OK;
 }
@@ -1250,9 +1319,16 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
       FragDev h = frag_desc(p, f, r, (uint32_t)i);
       const uint32_t di = (uint32_t)b->descs.size();
       b->descs.push_back(h);
+      const uint32_t Wb = row_words(f.m());
+      const int wk = Wb == 1 ? 0 : Wb == 2 ? 1 : Wb == 4 ? 2 : 3;
+      b->base_off.push_back(b->base_words_total);
+      b->wlist[wk].push_back(di);
+      b->wrows[wk] = std::max(b->wrows[wk], 2 * f.m());
+      const uint64_t boff = b->base_words_total;
+      b->base_words_total += (uint64_t)2 * f.m() * (2 * Wb + 1);
       offs[f.index] = (int64_t)b->model_words_total;
       for (uint64_t v = 0; v < f.n_variants; ++v)
-        b->items.push_back({di, 0u, v, b->model_words_total + v * model_words(nm)});
+        b->items.push_back({di, 0u, v, b->model_words_total + v * model_words(nm), boff});
       b->model_words_total += f.n_variants * model_words(nm);
       b->max_m = std::max(b->max_m, f.m());
     }
@@ -1264,6 +1340,15 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     return (uint64_t)a.m * (a.n_ops + a.n_meas * a.m) > (uint64_t)d.m * (d.n_ops + d.n_meas * d.m);
   });
   HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  for (size_t k = 0; k < std::min<size_t>(n, 8); ++k) {
+    hipStream_t ps = nullptr;
+    hipEvent_t je = nullptr;
+    HIP_TRY(c, hipStreamCreateWithFlags(&ps, hipStreamNonBlocking));
+    b->pool.push_back(ps);
+    HIP_TRY(c, hipEventCreateWithFlags(&je, hipEventDisableTiming));
+    b->join_ev.push_back(je);
+  }
   {
     BatchScope scope(b.get());
     if ((st = batch_enqueue(b.get(), true)) != CCUT_OK) return st;

@@ -156,16 +156,22 @@ struct BatchItem {
   uint32_t pad;
   uint64_t variant;
   uint64_t model_off;
+  uint64_t base_off;  // word offset of the fragment's base tableau (when bases are given)
 };
 
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
-hipError_t launch_tableau(const FragDev &frag, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s);
+// Per-variant tableau passes; with `base` (the fragment's evolved identity
+// tableau from launch_rows on its forward stream: 2m rows of
+// row_words(m) words per half) the gate replay is replaced by row
+// substitutions for the preparations.
+hipError_t launch_tableau(const FragDev &frag, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s,
+                          const uint64_t *base = nullptr);
 size_t tableau_batch_lds(uint32_t max_m, uint32_t block);
 hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, uint32_t n_items, uint32_t *counter,
                                 uint64_t *models, uint32_t max_m, uint32_t block, uint32_t grid, uint32_t use_reg,
-                                hipStream_t s);
+                                const uint64_t *bases, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
@@ -192,6 +198,13 @@ hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, 
 
 // Exact Pauli-basis tensor of a Clifford fragment without enumerating
 // variants (Heisenberg picture); see k_heis.hip for the row layout.
+// Rows carried through F.ops (F.n_ops words) one per lane: rows_in null
+// starts from the identity tableau (X_r for r < m, then Z_{r-m}); rows are
+// (x[W], z[W], sign) u64 each.
+hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
+                       hipStream_t s);
+hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
+                             uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s);
 hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
                              uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
                              uint32_t n_rows, double *tau, hipStream_t s);

@@ -91,22 +91,36 @@ __device__ inline void conj_gate(PRow<W> &r, uint32_t kind, uint32_t a, uint32_t
     }
 }
 
-// Carry each row back through the fragment: O = U^dag P U, i.e. conjugate
-// by the inverse gates from the last gate to the first.  F.ops is that
-// reversed stream of inverses (built on the host), read front to back.
-template <int W>
-__global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uint64_t *__restrict__ in,
-                                                      uint64_t *__restrict__ out, uint32_t n_rows) {
-  const uint32_t row = blockIdx.x * 64 + threadIdx.x;
+// One Pauli row per lane carried through an op stream with the tableau
+// rule P -> G P G^dag (rows never interact, so there is no barrier).  Two
+// uses: the Heisenberg carry-back O = U^dag P U (F.ops is the reversed
+// stream of inverse gates built on the host), and the shared tableau pass
+// of a Clifford fragment (F.ops is the forward stream and the rows start as
+// the identity tableau: X_r for r < m, Z_{r-m} after, when `in` is null).
+template <int W, class D>
+__device__ inline void row_pass_body(const D &F, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                     uint32_t n_rows, uint32_t row) {
   const bool ok = row < n_rows;
-  const uint64_t *src = in + (size_t)(ok ? row : 0) * (2 * W + 1);
   PRow<W> r;
+  if (in) {
+    const uint64_t *src = in + (size_t)(ok ? row : 0) * (2 * W + 1);
 #pragma unroll
-  for (int w = 0; w < W; ++w) {
-    r.x[w] = ok ? src[w] : 0;
-    r.z[w] = ok ? src[W + w] : 0;
+    for (int w = 0; w < W; ++w) {
+      r.x[w] = ok ? src[w] : 0;
+      r.z[w] = ok ? src[W + w] : 0;
+    }
+    r.s = ok ? (uint32_t)src[2 * W] & 1u : 0u;
+  } else {
+    const uint32_t m = F.m;
+    const uint32_t q = row < m ? row : row - m;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t bit = (ok && (q >> 6) == (uint32_t)w) ? (1ull << (q & 63)) : 0ull;
+      r.x[w] = row < m ? bit : 0ull;
+      r.z[w] = row < m ? 0ull : bit;
+    }
+    r.s = 0;
   }
-  r.s = ok ? (uint32_t)src[2 * W] & 1u : 0u;
   const uint32_t n16 = (F.n_ops + 15) / 16;
   for (uint32_t g16 = 0; g16 < n16; ++g16) {
     const Ops16 o = load_ops16(F.ops, g16);
@@ -122,6 +136,28 @@ __global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uin
     }
     dst[2 * W] = r.s;
   }
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uint64_t *__restrict__ in,
+                                                      uint64_t *__restrict__ out, uint32_t n_rows) {
+  row_pass_body<W>(F, in, out, n_rows, blockIdx.x * 64 + threadIdx.x);
+}
+
+// Shared tableau passes of many fragments at once (one row width class):
+// grid (row blocks, fragments in the class); fragment list[y] writes its 2m
+// rows at base + base_off[list[y]].
+typedef __attribute__((address_space(1))) const FragDev g_FragDevH;
+template <int W>
+__global__ __launch_bounds__(64) void base_batch_kernel(const FragDev *__restrict__ descs,
+                                                        const uint32_t *__restrict__ list,
+                                                        const uint64_t *__restrict__ base_off,
+                                                        uint64_t *__restrict__ base) {
+  const uint32_t d = list[blockIdx.y];
+  const g_FragDevH &F = ((const g_FragDevH *)descs)[d];
+  const uint32_t n_rows = 2 * F.m;
+  if (blockIdx.x * 64 >= n_rows) return;
+  row_pass_body<W>(F, nullptr, base + base_off[d], n_rows, blockIdx.x * 64 + threadIdx.x);
 }
 
 struct HeisArgs {
@@ -276,6 +312,34 @@ hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, u
 // r requested Z's then (X_c, Z_c) per output axis; tau is [4^n_axes][2^r] and
 // is turned into T[p_f][b] in place.  String mode: rows are n_str strings then
 // the output pairs; tau is [4^n_axes][n_str] = t_f[p_f][string].
+hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
+                       hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  const dim3 grid((n_rows + 63) / 64);
+  switch (W) {
+    case 1: hipLaunchKernelGGL(backprop_kernel<1>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
+    case 2: hipLaunchKernelGGL(backprop_kernel<2>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
+    case 4: hipLaunchKernelGGL(backprop_kernel<4>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
+    case 8: hipLaunchKernelGGL(backprop_kernel<8>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
+                             uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s) {
+  if (n_list == 0) return hipSuccess;
+  const dim3 grid((max_rows + 63) / 64, n_list);
+  switch (W) {
+    case 1: hipLaunchKernelGGL(base_batch_kernel<1>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
+    case 2: hipLaunchKernelGGL(base_batch_kernel<2>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
+    case 4: hipLaunchKernelGGL(base_batch_kernel<4>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
+    case 8: hipLaunchKernelGGL(base_batch_kernel<8>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
                              uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
                              uint32_t n_rows, double *tau, hipStream_t s) {

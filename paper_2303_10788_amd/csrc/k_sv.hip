@@ -14,8 +14,6 @@ namespace ccut {
 
 namespace {
 
-constexpr int kSvBlock = 256;
-constexpr int kMaxNcPerThread = (1 << kMaxNcQubits) / kSvBlock;  // amplitudes per thread, at most
 
 struct C2 {
   double re, im;
@@ -34,7 +32,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
   switch (kind) {
     case G_U2: {
       const C2 m00{mat[0], mat[1]}, m01{mat[2], mat[3]}, m10{mat[4], mat[5]}, m11{mat[6], mat[7]};
-      for (uint32_t k = threadIdx.x; k < half; k += kSvBlock) {
+      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
         const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
         const C2 x = amp[i0], y = amp[i1];
         amp[i0] = cadd(cmul(m00, x), cmul(m01, y));
@@ -44,7 +42,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
     }
     case G_H: {
       const double r = 0.70710678118654752440;
-      for (uint32_t k = threadIdx.x; k < half; k += kSvBlock) {
+      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
         const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
         const C2 x = amp[i0], y = amp[i1];
         amp[i0] = C2{r * (x.re + y.re), r * (x.im + y.im)};
@@ -53,7 +51,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
       break;
     }
     case G_X:
-      for (uint32_t k = threadIdx.x; k < half; k += kSvBlock) {
+      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
         const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
         const C2 x = amp[i0];
         amp[i0] = amp[i1];
@@ -62,7 +60,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
       break;
     case G_S: case G_SDG: {
       const double s = kind == G_S ? 1.0 : -1.0;
-      for (uint32_t k = threadIdx.x; k < half; k += kSvBlock) {
+      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
         const uint32_t i1 = ins0(k, a) | ma;
         const C2 x = amp[i1];
         amp[i1] = C2{-s * x.im, s * x.re};
@@ -71,7 +69,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
     }
     case G_CX: {
       const uint32_t mb = 1u << b;
-      for (uint32_t k = threadIdx.x; k < half; k += kSvBlock) {
+      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
         const uint32_t i0 = ins0(k, b);
         if (!(i0 & ma)) continue;
         const uint32_t i1 = i0 | mb;
@@ -83,7 +81,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
     }
     case G_CZ: {
       const uint32_t mb = 1u << b;
-      for (uint32_t i = threadIdx.x; i < N; i += kSvBlock)
+      for (uint32_t i = threadIdx.x; i < N; i += blockDim.x)
         if ((i & ma) && (i & mb)) amp[i] = C2{-amp[i].re, -amp[i].im};
       break;
     }
@@ -97,7 +95,7 @@ __device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint3
 // thread owns PPT amplitude pairs of every op and issues all their loads
 // (and the op's 2x2 matrix, staged in LDS once per chunk of 16 ops) before
 // any arithmetic; one barrier per op.
-template <int PPT>
+template <int PPT, int BS>
 __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
   const uint32_t half = (1u << m) >> 1;
   const uint32_t tid = threadIdx.x;
@@ -122,7 +120,7 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
         double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          const uint32_t k = tid + p * kSvBlock;
+          const uint32_t k = tid + p * BS;
           i0[p] = ins0(k < half ? k : 0, a);
           const C2 u = amp[i0[p]], v = amp[i0[p] | ma];
           xr[p] = u.re;
@@ -132,7 +130,7 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
         }
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          if (tid + p * kSvBlock < half) {
+          if (tid + p * BS < half) {
             const C2 x{xr[p], xi[p]}, y{yr[p], yi[p]};
             amp[i0[p]] = cadd(cmul(m00, x), cmul(m01, y));
             amp[i0[p] | ma] = cadd(cmul(m10, x), cmul(m11, y));
@@ -145,7 +143,7 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
         double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          const uint32_t k = tid + p * kSvBlock;
+          const uint32_t k = tid + p * BS;
           i0[p] = ins0(k < half ? k : 0, b);
           const C2 u = amp[i0[p]], v = amp[i0[p] | mb];
           xr[p] = u.re;
@@ -155,14 +153,14 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
         }
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-          if (tid + p * kSvBlock < half && (i0[p] & ma)) {
+          if (tid + p * BS < half && (i0[p] & ma)) {
             amp[i0[p]] = C2{yr[p], yi[p]};
             amp[i0[p] | mb] = C2{xr[p], xi[p]};
           }
         }
       } else if (kind == G_CZ) {
         const uint32_t mb = 1u << b;
-        for (uint32_t i = tid; i < 2 * half; i += kSvBlock)
+        for (uint32_t i = tid; i < 2 * half; i += BS)
           if ((i & ma) && (i & mb)) amp[i] = C2{-amp[i].re, -amp[i].im};
       }
       __syncthreads();
@@ -170,8 +168,8 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
   }
 }
 
-template <int PPT>
-__global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *__restrict__ dist) {
+template <int PPT, int BS>
+__global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restrict__ dist) {
   extern __shared__ C2 smem_amp[];
   __shared__ C2 s_mats[64];
   const uint32_t m = F.m;
@@ -182,7 +180,7 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
   uint32_t n_out = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
   C2 *work = n_out ? smem_amp + N : smem_amp;
-  for (uint32_t i = tid; i < N; i += kSvBlock) base[i] = C2{i == 0 ? 1.0 : 0.0, 0.0};
+  for (uint32_t i = tid; i < N; i += BS) base[i] = C2{i == 0 ? 1.0 : 0.0, 0.0};
   __syncthreads();
   uint64_t vin = 0;  // variant index contribution of the input digits
   {
@@ -203,7 +201,7 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
       stride *= F.axis_radix[j];
     }
   }
-  sv_run_ops<PPT>(base, m, F, s_mats);
+  sv_run_ops<PPT, BS>(base, m, F, s_mats);
   // outcome distribution of every basis combination
   const uint32_t nm = F.n_meas;
   uint32_t mmask = 0;
@@ -213,7 +211,7 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   for (uint32_t bc = 0; bc < n_bc; ++bc) {
     if (n_out) {
-      for (uint32_t i = tid; i < N; i += kSvBlock) work[i] = base[i];
+      for (uint32_t i = tid; i < N; i += BS) work[i] = base[i];
       __syncthreads();
     }
     uint64_t v = vin;
@@ -237,31 +235,31 @@ __global__ __launch_bounds__(kSvBlock) void sv_kernel(const FragDev F, double *_
     // N doubles), then a pairwise sum over each unmeasured qubit in turn
     // (fixed order, one barrier per qubit); the entry of outcome o is left
     // at the index with o's bits on the measured qubits and zeros elsewhere
-    double pr[kMaxNcPerThread];
+    double pr[((1 << kMaxNcQubits) / BS)];
 #pragma unroll
-    for (int j = 0; j < kMaxNcPerThread; ++j) {
-      const uint32_t i = tid + j * kSvBlock;
+    for (int j = 0; j < ((1 << kMaxNcQubits) / BS); ++j) {
+      const uint32_t i = tid + j * BS;
       pr[j] = 0.0;
       if (i < N) pr[j] = work[i].re * work[i].re + work[i].im * work[i].im;
     }
     __syncthreads();
     double *P = reinterpret_cast<double *>(work);
 #pragma unroll
-    for (int j = 0; j < kMaxNcPerThread; ++j) {
-      const uint32_t i = tid + j * kSvBlock;
+    for (int j = 0; j < ((1 << kMaxNcQubits) / BS); ++j) {
+      const uint32_t i = tid + j * BS;
       if (i < N) P[i] = pr[j];
     }
     __syncthreads();
     for (uint32_t q = 0; q < m; ++q) {
       if (mmask & (1u << q)) continue;
       const uint32_t mq = 1u << q;
-      for (uint32_t k = tid; k < N / 2; k += kSvBlock) {
+      for (uint32_t k = tid; k < N / 2; k += BS) {
         const uint32_t i0 = ins0(k, q);
         P[i0] += P[i0 | mq];
       }
       __syncthreads();
     }
-    for (uint32_t o = tid; o < outs; o += kSvBlock) {
+    for (uint32_t o = tid; o < outs; o += BS) {
       uint32_t idx = 0;
       for (uint32_t j = 0; j < nm; ++j) idx |= ((o >> j) & 1u) << F.meas[j];
       out[o] = P[idx];
@@ -277,12 +275,16 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   uint32_t n_in = 0, n_out = 0;
   for (uint32_t j = 0; j < h.n_axes; ++j) (h.axis_side[j] ? n_in : n_out) += 1;
   const size_t lds = (size_t(1) << h.m) * sizeof(C2) * (n_out ? 2 : 1);
-  // amplitude pairs per thread per op: 2^(m-1) / 256, at least one
-  auto kern = h.m <= 9 ? sv_kernel<1> : h.m == 10 ? sv_kernel<2> : h.m == 11 ? sv_kernel<4> : sv_kernel<8>;
+  // one workgroup per preparation combination, sized to the state: 256
+  // threads up to 9 qubits, then 512, then 1024 (several waves per SIMD
+  // hide the LDS and fp64 latency); PPT amplitude pairs per thread per op
+  auto kern = h.m <= 9 ? sv_kernel<1, 256> : h.m == 10 ? sv_kernel<1, 512> : h.m == 11 ? sv_kernel<1, 1024>
+                                                                                   : sv_kernel<2, 1024>;
+  const int bs = h.m <= 9 ? 256 : h.m == 10 ? 512 : 1024;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const uint64_t n_prep = 1ull << (2 * n_in);
-  hipLaunchKernelGGL(kern, dim3((unsigned)n_prep), dim3(kSvBlock), lds, s, h, dist);
+  hipLaunchKernelGGL(kern, dim3((unsigned)n_prep), dim3(bs), lds, s, h, dist);
   return hipGetLastError();
 }
 

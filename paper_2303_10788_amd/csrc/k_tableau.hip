@@ -127,8 +127,25 @@ size_t tableau_lds(size_t m) {
 // One variant with the tableau in LDS; D is the descriptor's access type
 // (a kernel argument, or an entry of a device-memory descriptor array read
 // through a global-address-space reference).
+// Stabilizer row of |+i> = S H|0> after the fragment: img(Y) = i img(X) img(Z)
+// for rows in the Hermitian form (-1)^s i^(x.z) X^x Z^z; returns its sign.
+template <int W>
+__device__ inline uint32_t y_image_sign(const uint64_t *rx, const uint64_t *rz) {
+  uint32_t nx = 2u * ((uint32_t)rx[2 * W] & 1u), nz = 2u * ((uint32_t)rz[2 * W] & 1u), cross = 0, pc = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    nx += __popcll(rx[w] & rx[W + w]);
+    nz += __popcll(rz[w] & rz[W + w]);
+    cross += __popcll(rx[W + w] & rz[w]);
+    pc += __popcll((rx[w] ^ rz[w]) & (rx[W + w] ^ rz[W + w]));
+  }
+  const uint32_t n = 1u + nx + nz + 2u * cross;
+  return ((n - pc) & 3u) >> 1;
+}
+
 template <int W, int BLOCK, class D>
-__device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ out, uint64_t *smem) {
+__device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ out, uint64_t *smem,
+                                 const uint64_t *__restrict__ base = nullptr) {
   const int m = (int)F.m;
   const int R2 = 2 * m;
   const int tid = threadIdx.x;
@@ -144,15 +161,24 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
   int *PIV = reinterpret_cast<int *>(CST + m);
 
   for (int i = tid; i < R2; i += BLOCK) {
+    if (base) {  // the fragment's evolved tableau, shared by its variants
+      const uint64_t *row = base + (size_t)i * (2 * W + 1);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      X[w * R2 + i] = (i < m && (i >> 6) == w) ? (1ull << (i & 63)) : 0ull;
-      Z[w * R2 + i] = (i >= m && ((i - m) >> 6) == w) ? (1ull << ((i - m) & 63)) : 0ull;
+      for (int w = 0; w < W; ++w) {
+        X[w * R2 + i] = row[w];
+        Z[w * R2 + i] = row[W + w];
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        X[w * R2 + i] = (i < m && (i >> 6) == w) ? (1ull << (i & 63)) : 0ull;
+        Z[w * R2 + i] = (i >= m && ((i - m) >> 6) == w) ? (1ull << ((i - m) & 63)) : 0ull;
+      }
     }
   }
   for (int i = tid; i < m; i += BLOCK) {
     FORM[i] = 0;
-    CST[i] = 0;
+    CST[i] = base ? (uint32_t)base[(size_t)(m + i) * (2 * W + 1) + 2 * W] & 1u : 0u;
   }
   if (tid < 64) GROW[tid] = 0;
   if (tid == 0) *X0 = 0;
@@ -160,8 +186,33 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
 
   // ---- gate phase: every thread updates only its own rows, so no barrier
   // is needed between gates.  Preparations on quantum inputs:
-  // |0>, |1> = X|0>, |+> = H|0>, |+i> = S H|0>.
-  {
+  // |0>, |1> = X|0>, |+> = H|0>, |+i> = S H|0>.  From a shared base tableau
+  // they become row substitutions (conjugation is a homomorphism, so the
+  // rows equal those of replaying the preparation and the gates):
+  // |1>: stabilizer sign flips; |+>: stabilizer <- img(X), destabilizer <-
+  // img(Z); |+i>: stabilizer <- i img(X) img(Z), destabilizer <- img(Z).
+  if (base) {
+    uint64_t t = v;
+    for (uint32_t j = 0; j < F.n_axes; ++j) {
+      const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
+      t /= F.axis_radix[j];
+      if (F.axis_side[j] != 1 || d == 0) continue;
+      const uint32_t q = F.axis_local[j];
+      const uint64_t *rx = base + (size_t)q * (2 * W + 1), *rz = base + (size_t)(m + q) * (2 * W + 1);
+      if (d == 1) {
+        if (tid == 0) CST[q] ^= 1u;
+        continue;
+      }
+      if (tid < W) {
+        const int w = tid;
+        X[w * R2 + q] = rz[w];
+        Z[w * R2 + q] = rz[W + w];
+        X[w * R2 + m + q] = d == 2 ? rx[w] : rx[w] ^ rz[w];
+        Z[w * R2 + m + q] = d == 2 ? rx[W + w] : rx[W + w] ^ rz[W + w];
+      }
+      if (tid == 0) CST[q] = d == 2 ? (uint32_t)rx[2 * W] & 1u : y_image_sign<W>(rx, rz);
+    }
+  } else {
     uint64_t t = v;
     for (uint32_t j = 0; j < F.n_axes; ++j) {
       const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
@@ -171,15 +222,16 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       const uint32_t g = prep_c1(d);
       for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, G_C1, q, g);
     }
-  }
-  for (uint32_t g16 = 0; g16 < (F.n_ops + 15) / 16; ++g16) {
-    const Ops16 o = load_ops16(F.ops, g16);
+    for (uint32_t g16 = 0; g16 < (F.n_ops + 15) / 16; ++g16) {
+      const Ops16 o = load_ops16(F.ops, g16);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const uint32_t kind = op_kind(o.w[t]), a = op_q0(o.w[t]), b = op_q1(o.w[t]);
-      for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, kind, a, b);
+      for (int t = 0; t < 16; ++t) {
+        const uint32_t kind = op_kind(o.w[t]), a = op_q0(o.w[t]), b = op_q1(o.w[t]);
+        for (int i = tid; i < R2; i += BLOCK) gate_row<W>(X, Z, CST, R2, m, i, kind, a, b);
+      }
     }
   }
+  __syncthreads();
   // basis rotations on quantum outputs: X -> H, Y -> S^dag then H, Z -> none
   {
     uint64_t t = v;
@@ -315,10 +367,10 @@ __device__ void tableau_lds_body(const D &F, uint64_t v, uint64_t *__restrict__ 
 }
 
 template <int W, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev F, uint64_t v0,
-                                                        uint64_t *__restrict__ models) {
+__global__ __launch_bounds__(BLOCK) void tableau_kernel(const FragDev F, uint64_t v0, uint64_t *__restrict__ models,
+                                                        const uint64_t *__restrict__ base) {
   extern __shared__ uint64_t smem[];
-  tableau_lds_body<W, BLOCK>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas), smem);
+  tableau_lds_body<W, BLOCK>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas), smem, base);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +432,8 @@ __device__ inline void acc1_combine(Acc1 &L, const Acc1 &R) {
 }
 
 template <int RPL, class D>
-__device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ out) {
+__device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ out,
+                                 const uint64_t *__restrict__ base = nullptr) {
   const int m = (int)F.m;
   const int R2 = 2 * m;
   const int lane = threadIdx.x & 63;
@@ -390,12 +443,45 @@ __device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ 
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
     const int i = lane + 64 * r;
-    x[r] = (i < m) ? (1ull << i) : 0ull;
-    z[r] = (i >= m && i < R2) ? (1ull << (i - m)) : 0ull;
+    if (base) {  // the fragment's evolved tableau (one word per row half)
+      const uint64_t *row = base + (size_t)(i < R2 ? i : 0) * 3;
+      x[r] = i < R2 ? row[0] : 0ull;
+      z[r] = i < R2 ? row[1] : 0ull;
+      cst[r] = i < R2 ? (uint32_t)row[2] & 1u : 0u;
+    } else {
+      x[r] = (i < m) ? (1ull << i) : 0ull;
+      z[r] = (i >= m && i < R2) ? (1ull << (i - m)) : 0ull;
+      cst[r] = 0;
+    }
     form[r] = 0;
-    cst[r] = 0;
   }
-  {  // preparations: |1> = X|0>, |+> = H|0>, |+i> = S H|0>
+  if (base) {  // preparations as row substitutions (see the LDS body)
+    uint64_t t = v;
+    for (uint32_t j = 0; j < F.n_axes; ++j) {
+      const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
+      t /= F.axis_radix[j];
+      if (F.axis_side[j] != 1 || d == 0) continue;
+      const int q = (int)F.axis_local[j];
+      const uint64_t *rx = base + (size_t)q * 3, *rz = base + (size_t)(m + q) * 3;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i == m + q) {
+          if (d == 1) {
+            cst[r] ^= 1u;
+          } else {
+            x[r] = d == 2 ? rx[0] : rx[0] ^ rz[0];
+            z[r] = d == 2 ? rx[1] : rx[1] ^ rz[1];
+            cst[r] = d == 2 ? (uint32_t)rx[2] & 1u : y_image_sign<1>(rx, rz);
+          }
+        } else if (i == q && d >= 2) {
+          x[r] = rz[0];
+          z[r] = rz[1];
+          cst[r] = (uint32_t)rz[2] & 1u;
+        }
+      }
+    }
+  } else {  // preparations: |1> = X|0>, |+> = H|0>, |+i> = S H|0>
     uint64_t t = v;
     for (uint32_t j = 0; j < F.n_axes; ++j) {
       const uint32_t d = (uint32_t)(t % F.axis_radix[j]);
@@ -404,11 +490,13 @@ __device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ 
       gate_reg<RPL>(x, z, cst, G_C1, F.axis_local[j], prep_c1(d));
     }
   }
-  const uint32_t n16 = (F.n_ops + 15) / 16;
-  for (uint32_t g16 = 0; g16 < n16; ++g16) {
-    const Ops16 o = load_ops16(F.ops, g16);
+  if (!base) {
+    const uint32_t n16 = (F.n_ops + 15) / 16;
+    for (uint32_t g16 = 0; g16 < n16; ++g16) {
+      const Ops16 o = load_ops16(F.ops, g16);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) gate_reg<RPL>(x, z, cst, op_kind(o.w[t]), op_q0(o.w[t]), op_q1(o.w[t]));
+      for (int t = 0; t < 16; ++t) gate_reg<RPL>(x, z, cst, op_kind(o.w[t]), op_q0(o.w[t]), op_q1(o.w[t]));
+    }
   }
   {  // basis rotations: X -> H, Y -> S^dag then H
     uint64_t t = v;
@@ -517,9 +605,9 @@ __device__ void tableau_reg_body(const D &F, uint64_t v, uint64_t *__restrict__ 
 }
 
 template <int RPL>
-__global__ __launch_bounds__(64) void tableau_reg_kernel(const FragDev F, uint64_t v0,
-                                                         uint64_t *__restrict__ models) {
-  tableau_reg_body<RPL>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas));
+__global__ __launch_bounds__(64) void tableau_reg_kernel(const FragDev F, uint64_t v0, uint64_t *__restrict__ models,
+                                                         const uint64_t *__restrict__ base) {
+  tableau_reg_body<RPL>(F, v0 + blockIdx.x, models + (size_t)blockIdx.x * model_words(F.n_meas), base);
 }
 
 // ---------------------------------------------------------------------------
@@ -533,7 +621,8 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void tableau_batch_kernel(const FragDev *__restrict__ descs,
                                                               const BatchItem *__restrict__ items,
                                                               uint32_t n_items, uint32_t *__restrict__ counter,
-                                                              uint64_t *__restrict__ models, uint32_t use_reg) {
+                                                              uint64_t *__restrict__ models, uint32_t use_reg,
+                                                              const uint64_t *__restrict__ bases) {
   extern __shared__ uint64_t smem[];
   __shared__ uint32_t s_item;
   for (;;) {
@@ -546,22 +635,23 @@ __global__ __launch_bounds__(BLOCK) void tableau_batch_kernel(const FragDev *__r
     const uint32_t di = item.desc;
     const uint64_t v = item.variant;
     uint64_t *out = models + item.model_off;
+    const uint64_t *base = bases ? bases + item.base_off : nullptr;
     const g_FragDev &F = ((const g_FragDev *)descs)[di];
     const uint32_t m = F.m;
     if (BLOCK == 64 && use_reg && 2 * m <= 64) {
-      tableau_reg_body<1>(F, v, out);
+      tableau_reg_body<1>(F, v, out, base);
     } else if (BLOCK == 64 && use_reg && m <= 64) {
-      tableau_reg_body<2>(F, v, out);
+      tableau_reg_body<2>(F, v, out, base);
     } else {
       const uint32_t W = (m + 63) / 64;
       if (W <= 1)
-        tableau_lds_body<1, BLOCK>(F, v, out, smem);
+        tableau_lds_body<1, BLOCK>(F, v, out, smem, base);
       else if (W <= 2)
-        tableau_lds_body<2, BLOCK>(F, v, out, smem);
+        tableau_lds_body<2, BLOCK>(F, v, out, smem, base);
       else if (W <= 4)
-        tableau_lds_body<4, BLOCK>(F, v, out, smem);
+        tableau_lds_body<4, BLOCK>(F, v, out, smem, base);
       else
-        tableau_lds_body<8, BLOCK>(F, v, out, smem);
+        tableau_lds_body<8, BLOCK>(F, v, out, smem, base);
     }
     __syncthreads();
   }
@@ -573,12 +663,13 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t value) {
 }
 
 template <int RPL>
-hipError_t launch_reg(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
+hipError_t launch_reg(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, const uint64_t *base,
+                      hipStream_t s) {
   for (uint64_t done = 0; done < nv;) {
     uint64_t chunk = nv - done;
     if (chunk > (1ull << 30)) chunk = 1ull << 30;
     hipLaunchKernelGGL((tableau_reg_kernel<RPL>), dim3((unsigned)chunk), dim3(64), 0, s, h, v0 + done,
-                       models + done * model_words(h.n_meas));
+                       models + done * model_words(h.n_meas), base);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;
@@ -587,7 +678,8 @@ hipError_t launch_reg(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *mode
 }
 
 template <int W, int BLOCK>
-hipError_t launch_w(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
+hipError_t launch_w(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, const uint64_t *base,
+                    hipStream_t s) {
   const size_t lds = tableau_lds<W, BLOCK>(h.m);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void *)tableau_kernel<W, BLOCK>,
@@ -597,7 +689,7 @@ hipError_t launch_w(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models
     uint64_t chunk = nv - done;
     if (chunk > (1ull << 30)) chunk = 1ull << 30;
     hipLaunchKernelGGL((tableau_kernel<W, BLOCK>), dim3((unsigned)chunk), dim3(BLOCK), lds, s, h,
-                       v0 + done, models + done * model_words(h.n_meas));
+                       v0 + done, models + done * model_words(h.n_meas), base);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;
@@ -607,14 +699,15 @@ hipError_t launch_w(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models
 
 }  // namespace
 
-hipError_t launch_tableau(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s) {
+hipError_t launch_tableau(const FragDev &h, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s,
+                          const uint64_t *base) {
   if (h.n_meas > (uint32_t)kMaxMeas) return hipErrorInvalidValue;
   const uint32_t W = (h.m + 63) / 64;
-  if (2 * h.m <= 64) return launch_reg<1>(h, v0, nv, models, s);
-  if (h.m <= 64) return launch_reg<2>(h, v0, nv, models, s);
-  if (W <= 2) return launch_w<2, 128>(h, v0, nv, models, s);
-  if (W <= 4) return launch_w<4, 256>(h, v0, nv, models, s);
-  if (W <= 8) return launch_w<8, 256>(h, v0, nv, models, s);
+  if (2 * h.m <= 64) return launch_reg<1>(h, v0, nv, models, base, s);
+  if (h.m <= 64) return launch_reg<2>(h, v0, nv, models, base, s);
+  if (W <= 2) return launch_w<2, 128>(h, v0, nv, models, base, s);
+  if (W <= 4) return launch_w<4, 256>(h, v0, nv, models, base, s);
+  if (W <= 8) return launch_w<8, 256>(h, v0, nv, models, base, s);
   return hipErrorInvalidValue;
 }
 
@@ -634,7 +727,7 @@ size_t tableau_batch_lds(uint32_t max_m, uint32_t block) {
 
 hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, uint32_t n_items, uint32_t *counter,
                                 uint64_t *models, uint32_t max_m, uint32_t block, uint32_t grid, uint32_t use_reg,
-                                hipStream_t s) {
+                                const uint64_t *bases, hipStream_t s) {
   if (max_m > 512 || grid == 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, counter, (uint64_t)1, 0u);
   hipError_t e = hipGetLastError();
@@ -646,19 +739,19 @@ hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, ui
       (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
       hipLaunchKernelGGL(tableau_batch_kernel<64>, dim3(grid), dim3(64), lds, s, descs, items, n_items, counter,
-                         models, use_reg);
+                         models, use_reg, bases);
       break;
     case 128:
       (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
       hipLaunchKernelGGL(tableau_batch_kernel<128>, dim3(grid), dim3(128), lds, s, descs, items, n_items, counter,
-                         models, 0u);
+                         models, 0u, bases);
       break;
     case 256:
       (void)hipFuncSetAttribute((const void *)tableau_batch_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
       hipLaunchKernelGGL(tableau_batch_kernel<256>, dim3(grid), dim3(256), lds, s, descs, items, n_items, counter,
-                         models, 0u);
+                         models, 0u, bases);
       break;
     default:
       return hipErrorInvalidValue;
