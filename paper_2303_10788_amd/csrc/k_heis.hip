@@ -160,6 +160,118 @@ __global__ __launch_bounds__(64) void base_batch_kernel(const FragDev *__restric
   row_pass_body<W>(F, nullptr, base + base_off[d], n_rows, blockIdx.x * 64 + threadIdx.x);
 }
 
+// The same row pass bit-sliced: column q of the x (z) parts holds bit q of
+// 64 rows per word, so a gate reads and writes only its qubits' column
+// words and applies its rule to 64 rows with a few 64-bit operations.  One
+// wave; lane w owns rows 64 w .. 64 w + 63 (its sign bits stay in a
+// register); columns live in LDS ([m][RW] for x, then for z).  Rows are
+// transposed in (or start as the identity tableau when `in` is null) and
+// transposed back out in the (x[W], z[W], sign) row layout.
+template <class D>
+__device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                 uint32_t n_rows, uint64_t *cols) {
+  const uint32_t m = F.m;
+  const uint32_t RW = (n_rows + 63) / 64;
+  const uint32_t lane = threadIdx.x;
+  uint64_t *Xc = cols, *Zc = cols + (size_t)m * RW;
+  const uint32_t RS = 2 * W + 1;  // row stride in words
+  for (uint32_t idx = lane; idx < m * RW; idx += 64) {
+    const uint32_t q = idx / RW, w = idx % RW;
+    uint64_t xw = 0, zw = 0;
+    if (!in) {  // X_r for rows r < m, then Z_{r - m}
+      if (q >> 6 == w) xw = 1ull << (q & 63);
+      if ((m + q) >> 6 == w) zw = 1ull << ((m + q) & 63);
+    } else {
+      for (uint32_t i = 0; i < 64; ++i) {
+        const uint32_t r = 64 * w + i;
+        if (r >= n_rows) break;
+        const uint64_t *row = in + (size_t)r * RS;
+        xw |= ((row[q >> 6] >> (q & 63)) & 1ull) << i;
+        zw |= ((row[W + (q >> 6)] >> (q & 63)) & 1ull) << i;
+      }
+    }
+    Xc[idx] = xw;
+    Zc[idx] = zw;
+  }
+  uint64_t sg = 0;  // sign bits of this lane's rows
+  if (in && lane < RW)
+    for (uint32_t i = 0; i < 64; ++i) {
+      const uint32_t r = 64 * lane + i;
+      if (r >= n_rows) break;
+      sg |= (in[(size_t)r * RS + 2 * W] & 1ull) << i;
+    }
+  __syncthreads();
+  if (lane < RW) {
+    const uint32_t n16 = (F.n_ops + 15) / 16;
+    for (uint32_t g16 = 0; g16 < n16; ++g16) {
+      const Ops16 o = load_ops16(F.ops, g16);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const uint32_t kind = op_kind(o.w[t]), a = op_q0(o.w[t]), b = op_q1(o.w[t]);
+        uint64_t *xa = Xc + (size_t)a * RW + lane, *za = Zc + (size_t)a * RW + lane;
+        if (kind == G_CX || kind == G_CZ) {
+          uint64_t *xb = Xc + (size_t)b * RW + lane, *zb = Zc + (size_t)b * RW + lane;
+          const uint64_t x1 = *xa, z1 = *za, x2 = *xb, z2 = *zb;
+          if (kind == G_CX) {
+            sg ^= x1 & z2 & ~(x2 ^ z1);
+            *xb = x2 ^ x1;
+            *za = z1 ^ z2;
+          } else {
+            sg ^= x1 & x2 & (z1 ^ z2);
+            *za = z1 ^ x2;
+            *zb = z2 ^ x1;
+          }
+        } else {
+          const C1Map g = c1_decode(b);
+          const uint64_t x = *xa, z = *za;
+          sg ^= (x & (0ull - g.al)) ^ (z & (0ull - g.be)) ^ (x & z & (0ull - g.ga));
+          *xa = (x & (0ull - g.m00)) ^ (z & (0ull - g.m01));
+          *za = (x & (0ull - g.m10)) ^ (z & (0ull - g.m11));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t idx = lane; idx < n_rows * W; idx += 64) {
+    const uint32_t r = idx / W, wq = idx % W;
+    const uint32_t rw = r >> 6, rb = r & 63;
+    uint64_t xw = 0, zw = 0;
+    for (uint32_t i = 0; i < 64; ++i) {
+      const uint32_t q = 64 * wq + i;
+      if (q >= m) break;
+      xw |= ((Xc[(size_t)q * RW + rw] >> rb) & 1ull) << i;
+      zw |= ((Zc[(size_t)q * RW + rw] >> rb) & 1ull) << i;
+    }
+    out[(size_t)r * RS + wq] = xw;
+    out[(size_t)r * RS + W + wq] = zw;
+  }
+  // signs: lane w holds rows 64 w ..; every lane writes its own rows
+  for (uint32_t w = 0; w < RW; ++w) {
+    const uint64_t s_w = (uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)sg, (int)w) |
+                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg >> 32), (int)w) << 32);
+    const uint32_t r = 64 * w + lane;
+    if (r < n_rows) out[(size_t)r * RS + 2 * W] = (s_w >> lane) & 1ull;
+  }
+}
+
+__global__ __launch_bounds__(64) void rows_sliced_kernel(const FragDev F, uint32_t W, const uint64_t *__restrict__ in,
+                                                          uint64_t *__restrict__ out, uint32_t n_rows) {
+  extern __shared__ uint64_t cols[];
+  rows_sliced_body(F, W, in, out, n_rows, cols);
+}
+
+// Shared tableau passes of many fragments: block y runs fragment list[y]
+// (2m rows, row width W = row_words(m)) into base + base_off[list[y]].
+__global__ __launch_bounds__(64) void rows_sliced_batch_kernel(const FragDev *__restrict__ descs,
+                                                                const uint32_t *__restrict__ list, uint32_t W,
+                                                                const uint64_t *__restrict__ base_off,
+                                                                uint64_t *__restrict__ base) {
+  extern __shared__ uint64_t cols[];
+  const uint32_t d = list[blockIdx.x];
+  const g_FragDevH &F = ((const g_FragDevH *)descs)[d];
+  rows_sliced_body(F, W, nullptr, base + base_off[d], 2 * F.m, cols);
+}
+
 struct HeisArgs {
   uint32_t m, W, n_axes, n_in, n_out, r;
   uint32_t axis_side[kMaxAxes];
@@ -292,10 +404,7 @@ template <int W>
 hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, uint64_t *rows_out, uint32_t n_rows,
                  double *tau, uint64_t ncols, hipStream_t s) {
   hipError_t e;
-  if (n_rows) {
-    hipLaunchKernelGGL((backprop_kernel<W>), dim3((n_rows + 63) / 64), dim3(64), 0, s, F, rows_in, rows_out, n_rows);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
+  if (n_rows && (e = launch_rows(F, W, rows_in, rows_out, n_rows, s)) != hipSuccess) return e;
   const uint64_t total_tau = ncols << (2 * A.n_axes);
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::min<uint64_t>((total_tau + 255) / 256, 65536)), dim3(256),
                      0, s, tau, total_tau);
@@ -312,31 +421,30 @@ hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, u
 // r requested Z's then (X_c, Z_c) per output axis; tau is [4^n_axes][2^r] and
 // is turned into T[p_f][b] in place.  String mode: rows are n_str strings then
 // the output pairs; tau is [4^n_axes][n_str] = t_f[p_f][string].
+size_t rows_sliced_lds(uint32_t m, uint32_t n_rows) { return (size_t)2 * m * ((n_rows + 63) / 64) * 8; }
+
 hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
                        hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  const dim3 grid((n_rows + 63) / 64);
-  switch (W) {
-    case 1: hipLaunchKernelGGL(backprop_kernel<1>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
-    case 2: hipLaunchKernelGGL(backprop_kernel<2>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
-    case 4: hipLaunchKernelGGL(backprop_kernel<4>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
-    case 8: hipLaunchKernelGGL(backprop_kernel<8>, grid, dim3(64), 0, s, F, in, out, n_rows); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (n_rows > 4096 || (W != 1 && W != 2 && W != 4 && W != 8) || F.m > 64 * W) return hipErrorInvalidValue;
+  const size_t lds = rows_sliced_lds(F.m, n_rows);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rows_sliced_kernel, dim3(1), dim3(64), lds, s, F, W, in, out, n_rows);
   return hipGetLastError();
 }
 
 hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
                              uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s) {
   if (n_list == 0) return hipSuccess;
-  const dim3 grid((max_rows + 63) / 64, n_list);
-  switch (W) {
-    case 1: hipLaunchKernelGGL(base_batch_kernel<1>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
-    case 2: hipLaunchKernelGGL(base_batch_kernel<2>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
-    case 4: hipLaunchKernelGGL(base_batch_kernel<4>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
-    case 8: hipLaunchKernelGGL(base_batch_kernel<8>, grid, dim3(64), 0, s, descs, list, base_off, base); break;
-    default: return hipErrorInvalidValue;
-  }
+  const size_t lds = rows_sliced_lds(max_rows / 2, max_rows);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_batch_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rows_sliced_batch_kernel, dim3(n_list), dim3(64), lds, s, descs, list, W, base_off, base);
   return hipGetLastError();
 }
 
