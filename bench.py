@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 METRIC = "fragment-variant shots/s + recombination terms/s; end-to-end vs plain at TVD≤1e-2"
 PEAK_INT32_OPS = 256 * 64 * 2.4e9       # 256 CUs x 64 int32 VALU lanes/clk x 2.4 GHz
 PEAK_HBM = 8.0e12
+PEAK_FP64 = 78.6e12                     # fp64 vector (and MFMA) peak
 PHILOX_OPS = 100                        # 10 rounds x (2 mul_lo + 2 mul_hi + 4 xor + 2 key add)
 
 
@@ -37,6 +38,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 64 MiB elementwise copy first (the known-size kernel that scales the HBM "
+                         "counters of a --pmc run)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="instead of benchmarking: turn two rocprofv3 --pmc counter_collection.csv files "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy run into profiles/<workload>_traffic.json")
+    ap.add_argument("--traffic-kernel", default="sv_kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", choices=["mid", "batching", "precision", "learned"], default="mid",
                     help="mid (default): the 32-qubit, 2-cut workload; batching: 256 uneven circuits in one "
@@ -70,8 +78,62 @@ def cpu_baseline(w, target_s: float):
                       f"{total} shots in {dt:.1f} s, single-threaded literal per-shot tableau"}
 
 
+# kernel name -> the source file whose contents its traffic figure belongs to
+KERNEL_SOURCES = {"sv_kernel": "k_sv.hip", "tableau": "k_tableau.hip", "parity": "k_sample.hip",
+                  "sample_kernel": "k_sample.hip"}
+CALIB_BYTES = 64 << 20
+
+
+def _source_hash(kernel):
+    import hashlib
+    for key, fname in KERNEL_SOURCES.items():
+        if key in kernel:
+            path = os.path.join(ROOT, "paper_2303_10788_amd", "csrc", fname)
+            return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    return None
+
+
+def traffic_from_counters(args):
+    """HBM bytes per launch of one kernel from a FETCH_SIZE and a WRITE_SIZE
+    counter run, each scaled by the same counter on the 64 MiB copy
+    (elementwise kernel reading and writing CALIB_BYTES)."""
+    import csv
+    out = {"workload": args.workload, "kernel": args.traffic_kernel, "source_sha": _source_hash(args.traffic_kernel)}
+    for path, counter in zip(args.traffic, ("FETCH_SIZE", "WRITE_SIZE")):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows if args.traffic_kernel in r["Kernel_Name"]]
+        calib = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
+        calib = max(calib)  # the 64 MiB copy is the largest elementwise dispatch
+        factor = (CALIB_BYTES / 1024.0) / calib
+        key = counter.split("_")[0].lower()
+        out[f"{key}_kib_per_launch"] = sum(kern) / len(kern)
+        out[f"{key}_copy_kib"] = calib
+        out[f"{key}_factor"] = factor
+        out[f"{key}_bytes_per_launch"] = sum(kern) / len(kern) * 1024.0 * factor
+        out["launches_sampled"] = len(kern)
+    out["bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    dst = os.path.join(ROOT, "profiles", f"{args.workload}_traffic.json")
+    with open(dst, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def traffic_for(workload, kernel):
+    """HBM bytes per launch measured for this kernel, or None when there is
+    no measurement or its source changed since."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel") != kernel or rec.get("source_sha") != _source_hash(kernel):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def main():
     args = parse()
+    if args.traffic:
+        return traffic_from_counters(args)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -102,6 +164,11 @@ def main():
         plan.marginal(w.qubits, shots=w.shots, seed=w.seed, out=out_m)
         plan.zexpect(masks, shots=w.shots, seed=w.seed, out=out_z)
 
+    if args.calibrate_copy:
+        a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = a + 0.0
+        torch.cuda.synchronize()
+        del a, b
     dt = _timed(step, args.steps, args.warmup)
     # per-kernel breakdown from a separate pass with event timing on (the
     # events themselves cost time, so the timed steps above run without)
@@ -112,12 +179,34 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = shots_per_step / (dt / args.steps)
 
-    # dominant kernel and its algorithmic work per launch
-    name, (launches, total_ms) = max(times.items(), key=lambda kv: kv[1][1])
-    avg_s = total_ms / max(launches, 1) / 1e3
+    # dominant kernel (among those with an algorithmic work model: the state
+    # vector, the tableau pass, the sampler and the parity kernel) and its
+    # algorithmic work per launch
+    overall = max(times.items(), key=lambda kv: kv[1][1])[0]
     n_meas_z = 24
     n_ext = masks.shape[0]
+    nc = [f for f in frags if not f["clifford"]]
+    cl = [f for f in frags if f["clifford"]]
+    # algorithmic work per step (both calls), as stated in the design notes
+    sv_flops = 0.0
+    for f in nc:
+        n_in = sum(1 for a in f["axes"] if a[1] == 1)
+        n_out = len(f["axes"]) - n_in
+        N = 1 << f["m"]
+        # per preparation combination: 28 flops per amplitude pair of each fused
+        # 2x2 unitary; per basis combination: |a|^2 (3 flops per amplitude) and
+        # the pairwise sums over the unmeasured qubits (N/2 adds each)
+        n_meas = n_out  # the mid request measures only the quantum outputs here
+        sv_flops += 2 * (4 ** n_in) * (f["n_one"] * 14 * N + (3 ** n_out) * (3 * N + (f["m"] - n_meas) * N // 2))
+    tab_ops = 0.0
+    for f in cl:
+        rw = (2 * f["m"] + 1 + 63) // 64
+        # column-sliced rule per gate and 64 rows: 11 (one-qubit map) or 6
+        # (CX, CZ) 64-bit operations, i.e. 22 or 12 int32 operations
+        tab_ops += 2 * f["n_variants"] * rw * (22 * f["n_one"] + 12 * f["n_two"])
     work = {
+        "sv_kernel": (sv_flops, "fp64", PEAK_FP64, "GFLOP/s"),
+        "tableau_kernel": (tab_ops, "alu", PEAK_INT32_OPS, "Gop/s"),
         # per shot: a Philox call per 4 shots and 32 measurement indices, then one
         # AND + POPCOUNT + accumulate per Z string
         "parity_kernel": (n_cliff_var * w.shots * (PHILOX_OPS / 4 * ((n_meas_z + 31) // 32) + 3 * n_ext),
@@ -126,15 +215,14 @@ def main():
         "sample_kernel": (n_cliff_var * w.shots * (PHILOX_OPS / 4 + 3 * len(w.qubits) + 1), "alu",
                           PEAK_INT32_OPS, "Gop/s"),
     }
-    if name in work:
-        units, bound, peak, unit = work[name]
-        per_launch = units / max(launches / args.steps, 1)
-        achieved = per_launch / avg_s
-        roof = {"bound": bound, "kernel": name, "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "avg_launch_us": avg_s * 1e6}
-    else:
-        roof = {"bound": "unknown", "kernel": name, "achieved": None, "peak": None, "unit": None, "frac": None,
-                "traffic": None, "avg_launch_us": avg_s * 1e6}
+    name, (launches, total_ms) = max(((k, v) for k, v in times.items() if k in work), key=lambda kv: kv[1][1])
+    avg_s = total_ms / max(launches, 1) / 1e3
+    units, bound, peak, unit = work[name]
+    per_launch = units / max(launches / args.steps, 1)
+    achieved = per_launch / avg_s
+    roof = {"bound": bound, "kernel": name, "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic_for("mid", name), "avg_launch_us": avg_s * 1e6,
+            "work_per_launch": per_launch, "dominant_overall": overall}
 
     line = {
         "metric": METRIC, "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps,

@@ -221,6 +221,11 @@ ccut_status ccut_variant_tables(ccut_plan *plan, const ccut_eval_opts *eo, const
 ccut_status ccut_fragment_tensor(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
                                  uint32_t nq, uint32_t fragment, double *out, int out_on_device);
 
+/* The op stream the kernels run for fragment f: number of one-qubit words
+ * (fused runs: 2x2 unitaries on non-Clifford fragments, GF(2) maps on
+ * Clifford ones) and of two-qubit gates. */
+ccut_status ccut_fragment_ops(const ccut_plan *plan, uint32_t f, uint32_t *n_one, uint32_t *n_two);
+
 /* Number of measured qubits and requested outputs of fragment `fragment`
  * under the marginal request (sizes of the two parity hooks above). */
 ccut_status ccut_request_info(ccut_plan *plan, const uint32_t *qubits, uint32_t nq,

@@ -93,6 +93,7 @@ SIGNATURES = {
     "ccut_fragment_tensor": ([_P, ctypes.POINTER(ccut_eval_opts), _U32P, ctypes.c_uint32, ctypes.c_uint32,
                               _P, ctypes.c_int], ctypes.c_int),
     "ccut_request_info": ([_P, _U32P, ctypes.c_uint32, ctypes.c_uint32, _U32P, _U32P], ctypes.c_int),
+    "ccut_fragment_ops": ([_P, ctypes.c_uint32, _U32P, _U32P], ctypes.c_int),
     "ccut_batch_create": ([_P, ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(ccut_eval_opts),
                            ctypes.POINTER(_U32P), _U32P, ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
     "ccut_batch_run": ([_P, ctypes.POINTER(_P), ctypes.c_int], ctypes.c_int),
@@ -274,6 +275,12 @@ def ccut_fragment_tensor(plan, ctx, eo, qubits, fragment, out) -> None:
     _check(lib().ccut_fragment_tensor(plan, ctypes.byref(eo), qp, len(q), fragment, p, dev), ctx)
 
 
+def ccut_fragment_ops(plan, f: int):
+    one, two = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().ccut_fragment_ops(plan, f, ctypes.byref(one), ctypes.byref(two)), None)
+    return one.value, two.value
+
+
 def ccut_request_info(plan, qubits, fragment):
     q, qp = _u32(qubits)
     nm, nr = ctypes.c_uint32(), ctypes.c_uint32()
@@ -431,8 +438,9 @@ class Plan:
         out = []
         for f in range(nf):
             m, cl, na, nv = ccut_fragment_info(self.handle, f)
+            one, two = ccut_fragment_ops(self.handle, f)
             out.append(dict(m=m, clifford=cl, n_variants=nv, segments=ccut_fragment_segments(self.handle, f),
-                            axes=ccut_fragment_axes(self.handle, f)))
+                            axes=ccut_fragment_axes(self.handle, f), n_one=one, n_two=two))
         return out
 
     def marginal(self, qubits, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,

@@ -118,12 +118,18 @@ struct ccut_plan {
   std::vector<double *> d_mats;
   std::vector<uint32_t *> d_back;  // Clifford fragments: the carry-back stream
   std::vector<uint32_t> n_back;
+  std::vector<uint32_t *> d_layers, d_back_layers;  // layer offsets of both streams
+  std::vector<uint32_t> n_layers, n_back_layers;
   ~ccut_plan() {
     for (auto p : d_ops)
       if (p) (void)hipFree(p);
     for (auto p : d_mats)
       if (p) (void)hipFree(p);
     for (auto p : d_back)
+      if (p) (void)hipFree(p);
+    for (auto p : d_layers)
+      if (p) (void)hipFree(p);
+    for (auto p : d_back_layers)
       if (p) (void)hipFree(p);
   }
 };
@@ -197,6 +203,19 @@ ccut_status ensure_ops(ccut_plan *p) {
     }
     p->d_back.push_back(bk);
     p->n_back.push_back((uint32_t)f.cl_back.size());
+    uint32_t *dl = nullptr, *dbl = nullptr;
+    if (f.clifford) {
+      HIP_TRY(c, hipMalloc(&dl, std::max<size_t>(f.cl_layers.size(), 1) * 4));
+      HIP_TRY(c, hipMalloc(&dbl, std::max<size_t>(f.cl_back_layers.size(), 1) * 4));
+      if (!f.cl_layers.empty())
+        HIP_TRY(c, hipMemcpy(dl, f.cl_layers.data(), f.cl_layers.size() * 4, hipMemcpyHostToDevice));
+      if (!f.cl_back_layers.empty())
+        HIP_TRY(c, hipMemcpy(dbl, f.cl_back_layers.data(), f.cl_back_layers.size() * 4, hipMemcpyHostToDevice));
+    }
+    p->d_layers.push_back(dl);
+    p->d_back_layers.push_back(dbl);
+    p->n_layers.push_back(f.cl_layers.empty() ? 0u : (uint32_t)f.cl_layers.size() - 1);
+    p->n_back_layers.push_back(f.cl_back_layers.empty() ? 0u : (uint32_t)f.cl_back_layers.size() - 1);
     std::vector<uint32_t> words = f.clifford ? f.cl_words : f.sv_words;
     std::vector<double> mats = f.clifford ? std::vector<double>() : f.sv_mats;
     while (words.size() % 16 || words.empty()) {
@@ -339,6 +358,8 @@ FragDev frag_desc(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_
   FragDev h = make_frag_dev(f, r, ((uint64_t)circuit << 40) | ((uint64_t)f.index << 32));
   h.ops = p->d_ops[f.index];
   h.mats = p->d_mats[f.index];
+  h.layers = p->d_layers[f.index];
+  h.n_layers = p->n_layers[f.index];
   return h;
 }
 
@@ -527,6 +548,8 @@ ccut_status heis_tensor(ccut_plan *p, const Fragment &f, const FragRequest &r, u
   FragDev h = frag_desc(p, f, rq, circuit);
   h.ops = p->d_back[f.index];  // the carry-back stream
   h.n_ops = p->n_back[f.index];
+  h.layers = p->d_back_layers[f.index];
+  h.n_layers = p->n_back_layers[f.index];
   {
     KTimer t(c, CCUT_K_HEISENBERG);
     HIP_TRY(c, launch_heisenberg(h, W, n_in, n_out, strings ? 0 : nreq, strings ? (uint32_t)strings->size() : 0,
@@ -776,6 +799,23 @@ ccut_status ccut_fragment_axes(const ccut_plan *p, uint32_t f, uint32_t *cut, ui
     if (side) side[j] = F.axes[j].side;
     if (local) local[j] = F.axes[j].local;
   }
+  return CCUT_OK;
+}
+
+ccut_status ccut_fragment_ops(const ccut_plan *p, uint32_t f, uint32_t *n_one, uint32_t *n_two) {
+  if (!p || f >= p->pd.frags.size()) return CCUT_E_INVALID;
+  const Fragment &F = p->pd.frags[f];
+  const std::vector<uint32_t> &w = F.clifford ? F.cl_words : F.sv_words;
+  uint32_t one = 0, two = 0;
+  for (uint32_t x : w) {
+    const uint32_t k = op_kind(x);
+    if (k == G_CX || k == G_CZ)
+      ++two;
+    else if (k != G_NOP)
+      ++one;
+  }
+  if (n_one) *n_one = one;
+  if (n_two) *n_two = two;
   return CCUT_OK;
 }
 

@@ -142,6 +142,12 @@ struct FragDev {
   uint16_t meas[kMaxMeas];         // local qubit of measurement j (ascending)
   const uint32_t *ops;             // packed op words, padded with G_NOP to a multiple of 16
   const double *mats;              // per op 2x2 complex matrix (re00 im00 re01 im01 re10 im10 re11 im11), G_U2 only
+  // Clifford streams come in ASAP layers of ops on disjoint qubits (layer L
+  // is ops[layers[L] .. layers[L + 1])); reordering commuting ops changes
+  // no row and no sign
+  const uint32_t *layers;
+  uint32_t n_layers;
+  uint32_t pad_;
 };
 
 // Per-variant affine sample model of a Clifford variant: a shot's outcome

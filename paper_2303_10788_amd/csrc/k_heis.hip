@@ -162,28 +162,42 @@ __global__ __launch_bounds__(64) void base_batch_kernel(const FragDev *__restric
 
 // The same row pass bit-sliced: column q of the x (z) parts holds bit q of
 // 64 rows per word, so a gate reads and writes only its qubits' column
-// words and applies its rule to 64 rows with a few 64-bit operations.  One
-// wave; lane w owns rows 64 w .. 64 w + 63 (its sign bits stay in a
-// register); columns live in LDS ([m][RW] for x, then for z).  Rows are
-// transposed in (or start as the identity tableau when `in` is null) and
-// transposed back out in the (x[W], z[W], sign) row layout.
+// words and applies its rule to 64 rows with a few 64-bit operations.  The
+// stream comes in layers of ops on disjoint qubits.  Lane l works on row
+// word w = l mod RWp (RWp = RW rounded up to a power of two) and, within a
+// layer, on op l / RWp of each group of 64 / RWp ops, so a layer costs one
+// round trip through LDS instead of one per gate.  Each lane XORs the sign
+// changes of its ops into one private word (XOR commutes, and an op reads
+// the columns as they are before it: earlier layers are complete and its
+// own layer never touches its qubits); one reduction over the lanes of each
+// row word adds them up at the end.  One wave, so LDS accesses complete in
+// issue order; a compiler fence keeps the layers in order.  Columns live in
+// LDS ([m][RW] for x, then for z); rows are transposed in (or start as the
+// identity tableau when `in` is null) and back out in the (x[W], z[W],
+// sign) row layout.  At most 1024 rows per wave.
+constexpr uint32_t kSlicedRows = 1024;
+constexpr uint32_t kOpStage = 1024;  // op words staged in LDS (a layer has at most 512)
 template <class D>
 __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                  uint32_t n_rows, uint64_t *cols) {
   const uint32_t m = F.m;
   const uint32_t RW = (n_rows + 63) / 64;
   const uint32_t lane = threadIdx.x;
+  uint32_t lg = 0;
+  while ((1u << lg) < RW) ++lg;
+  const uint32_t RWp = 1u << lg, w = lane & (RWp - 1), o = lane >> lg, per = 64u >> lg;
   uint64_t *Xc = cols, *Zc = cols + (size_t)m * RW;
+  uint32_t *sops = reinterpret_cast<uint32_t *>(Zc + (size_t)m * RW);
   const uint32_t RS = 2 * W + 1;  // row stride in words
   for (uint32_t idx = lane; idx < m * RW; idx += 64) {
-    const uint32_t q = idx / RW, w = idx % RW;
+    const uint32_t q = idx / RW, iw = idx % RW;
     uint64_t xw = 0, zw = 0;
     if (!in) {  // X_r for rows r < m, then Z_{r - m}
-      if (q >> 6 == w) xw = 1ull << (q & 63);
-      if ((m + q) >> 6 == w) zw = 1ull << ((m + q) & 63);
+      if (q >> 6 == iw) xw = 1ull << (q & 63);
+      if ((m + q) >> 6 == iw) zw = 1ull << ((m + q) & 63);
     } else {
       for (uint32_t i = 0; i < 64; ++i) {
-        const uint32_t r = 64 * w + i;
+        const uint32_t r = 64 * iw + i;
         if (r >= n_rows) break;
         const uint64_t *row = in + (size_t)r * RS;
         xw |= ((row[q >> 6] >> (q & 63)) & 1ull) << i;
@@ -193,44 +207,54 @@ __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restr
     Xc[idx] = xw;
     Zc[idx] = zw;
   }
-  uint64_t sg = 0;  // sign bits of this lane's rows
+  uint64_t sg = 0;  // this lane's share of sign word w
   if (in && lane < RW)
     for (uint32_t i = 0; i < 64; ++i) {
       const uint32_t r = 64 * lane + i;
       if (r >= n_rows) break;
       sg |= (in[(size_t)r * RS + 2 * W] & 1ull) << i;
     }
+  const bool live = w < RW;
   __syncthreads();
-  if (lane < RW) {
-    const uint32_t n16 = (F.n_ops + 15) / 16;
-    for (uint32_t g16 = 0; g16 < n16; ++g16) {
-      const Ops16 o = load_ops16(F.ops, g16);
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const uint32_t kind = op_kind(o.w[t]), a = op_q0(o.w[t]), b = op_q1(o.w[t]);
-        uint64_t *xa = Xc + (size_t)a * RW + lane, *za = Zc + (size_t)a * RW + lane;
-        if (kind == G_CX || kind == G_CZ) {
-          uint64_t *xb = Xc + (size_t)b * RW + lane, *zb = Zc + (size_t)b * RW + lane;
-          const uint64_t x1 = *xa, z1 = *za, x2 = *xb, z2 = *zb;
-          if (kind == G_CX) {
-            sg ^= x1 & z2 & ~(x2 ^ z1);
-            *xb = x2 ^ x1;
-            *za = z1 ^ z2;
-          } else {
-            sg ^= x1 & x2 & (z1 ^ z2);
-            *za = z1 ^ x2;
-            *zb = z2 ^ x1;
-          }
+  // without layer offsets every op is a layer of its own
+  const g_u32 *lay = (const g_u32 *)F.layers;
+  const uint32_t n_layers = lay ? F.n_layers : F.n_ops;
+  uint32_t stage0 = 0xFFFFFFFFu;
+  for (uint32_t L = 0; L < n_layers; ++L) {
+    const uint32_t s0 = lay ? lay[L] : L, s1 = lay ? lay[L + 1] : L + 1;
+    if (stage0 == 0xFFFFFFFFu || s1 > stage0 + kOpStage) {
+      stage0 = s0;
+      for (uint32_t i = lane; i < kOpStage; i += 64) sops[i] = s0 + i < F.n_ops ? F.ops[s0 + i] : 0u;
+    }
+    for (uint32_t c0 = s0 + o; c0 < s1; c0 += per) {
+      if (!live) continue;
+      const uint32_t wd = sops[c0 - stage0];
+      const uint32_t kind = op_kind(wd), a = op_q0(wd), b = op_q1(wd);
+      uint64_t *xa = Xc + (size_t)a * RW + w, *za = Zc + (size_t)a * RW + w;
+      if (kind == G_CX || kind == G_CZ) {
+        uint64_t *xb = Xc + (size_t)b * RW + w, *zb = Zc + (size_t)b * RW + w;
+        const uint64_t x1 = *xa, z1 = *za, x2 = *xb, z2 = *zb;
+        if (kind == G_CX) {
+          sg ^= x1 & z2 & ~(x2 ^ z1);
+          *xb = x2 ^ x1;
+          *za = z1 ^ z2;
         } else {
-          const C1Map g = c1_decode(b);
-          const uint64_t x = *xa, z = *za;
-          sg ^= (x & (0ull - g.al)) ^ (z & (0ull - g.be)) ^ (x & z & (0ull - g.ga));
-          *xa = (x & (0ull - g.m00)) ^ (z & (0ull - g.m01));
-          *za = (x & (0ull - g.m10)) ^ (z & (0ull - g.m11));
+          sg ^= x1 & x2 & (z1 ^ z2);
+          *za = z1 ^ x2;
+          *zb = z2 ^ x1;
         }
+      } else {
+        const C1Map g = c1_decode(b);
+        const uint64_t x = *xa, z = *za;
+        sg ^= (x & (0ull - g.al)) ^ (z & (0ull - g.be)) ^ (x & z & (0ull - g.ga));
+        *xa = (x & (0ull - g.m00)) ^ (z & (0ull - g.m01));
+        *za = (x & (0ull - g.m10)) ^ (z & (0ull - g.m11));
       }
     }
+    asm volatile("" ::: "memory");
   }
+  // sign word w: XOR of the shares of every lane on row word w (lane w ends with it)
+  for (uint32_t off = RWp; off < 64; off <<= 1) sg ^= __shfl_xor(sg, off);
   __syncthreads();
   for (uint32_t idx = lane; idx < n_rows * W; idx += 64) {
     const uint32_t r = idx / W, wq = idx % W;
@@ -245,19 +269,20 @@ __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restr
     out[(size_t)r * RS + wq] = xw;
     out[(size_t)r * RS + W + wq] = zw;
   }
-  // signs: lane w holds rows 64 w ..; every lane writes its own rows
-  for (uint32_t w = 0; w < RW; ++w) {
-    const uint64_t s_w = (uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)sg, (int)w) |
-                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sg >> 32), (int)w) << 32);
-    const uint32_t r = 64 * w + lane;
-    if (r < n_rows) out[(size_t)r * RS + 2 * W] = (s_w >> lane) & 1ull;
+  for (uint32_t rw = 0; rw < RW; ++rw) {
+    const uint64_t word = __shfl(sg, rw);
+    const uint32_t r = 64 * rw + lane;
+    if (r < n_rows) out[(size_t)r * RS + 2 * W] = (word >> lane) & 1ull;
   }
 }
 
+// Block x carries rows [1024 x, 1024 x + 1024) (rows are independent).
 __global__ __launch_bounds__(64) void rows_sliced_kernel(const FragDev F, uint32_t W, const uint64_t *__restrict__ in,
                                                           uint64_t *__restrict__ out, uint32_t n_rows) {
   extern __shared__ uint64_t cols[];
-  rows_sliced_body(F, W, in, out, n_rows, cols);
+  const uint32_t r0 = blockIdx.x * kSlicedRows;
+  const size_t RS = 2 * W + 1;
+  rows_sliced_body(F, W, in ? in + r0 * RS : nullptr, out + r0 * RS, min(kSlicedRows, n_rows - r0), cols);
 }
 
 // Shared tableau passes of many fragments: block y runs fragment list[y]
@@ -421,24 +446,29 @@ hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, u
 // r requested Z's then (X_c, Z_c) per output axis; tau is [4^n_axes][2^r] and
 // is turned into T[p_f][b] in place.  String mode: rows are n_str strings then
 // the output pairs; tau is [4^n_axes][n_str] = t_f[p_f][string].
-size_t rows_sliced_lds(uint32_t m, uint32_t n_rows) { return (size_t)2 * m * ((n_rows + 63) / 64) * 8; }
+size_t rows_sliced_lds(uint32_t m, uint32_t n_rows) {
+  return (size_t)2 * m * ((n_rows + 63) / 64) * 8 + kOpStage * 4;
+}
 
 hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
                        hipStream_t s) {
   if (n_rows == 0) return hipSuccess;
-  if (n_rows > 4096 || (W != 1 && W != 2 && W != 4 && W != 8) || F.m > 64 * W) return hipErrorInvalidValue;
-  const size_t lds = rows_sliced_lds(F.m, n_rows);
+  if ((W != 1 && W != 2 && W != 4 && W != 8) || F.m > 64 * W || (!in && n_rows > kSlicedRows))
+    return hipErrorInvalidValue;
+  const size_t lds = rows_sliced_lds(F.m, std::min(n_rows, kSlicedRows));
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rows_sliced_kernel, dim3(1), dim3(64), lds, s, F, W, in, out, n_rows);
+  hipLaunchKernelGGL(rows_sliced_kernel, dim3((n_rows + kSlicedRows - 1) / kSlicedRows), dim3(64), lds, s, F, W, in,
+                     out, n_rows);
   return hipGetLastError();
 }
 
 hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
                              uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s) {
   if (n_list == 0) return hipSuccess;
+  if (max_rows > kSlicedRows) return hipErrorInvalidValue;
   const size_t lds = rows_sliced_lds(max_rows / 2, max_rows);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_batch_kernel,

@@ -96,6 +96,29 @@ void fuse_one_qubit_runs(Fragment &F) {
   for (uint32_t q = 0; q < m; ++q) flush(q);
 }
 
+// Order a Clifford stream by ASAP layer: op g goes one layer after the
+// latest earlier op on any of its qubits, so each layer acts on disjoint
+// qubits and per-qubit order is kept (ops on disjoint qubits commute).
+void layer_stream(std::vector<uint32_t> &words, std::vector<uint32_t> &starts, uint32_t m) {
+  std::vector<int32_t> qlayer(m, -1);
+  std::vector<uint32_t> lay(words.size());
+  uint32_t nl = 0;
+  for (size_t g = 0; g < words.size(); ++g) {
+    const uint32_t w = words[g], k = op_kind(w), a = op_q0(w);
+    const uint32_t b = (k == G_CX || k == G_CZ) ? op_q1(w) : a;
+    const int32_t L = std::max(qlayer[a], qlayer[b]) + 1;
+    lay[g] = (uint32_t)L;
+    qlayer[a] = qlayer[b] = L;
+    nl = std::max(nl, (uint32_t)L + 1);
+  }
+  starts.assign(nl + 1, 0);
+  for (uint32_t L : lay) starts[L + 1]++;
+  for (uint32_t L = 0; L < nl; ++L) starts[L + 1] += starts[L];
+  std::vector<uint32_t> pos(starts.begin(), starts.end() - 1), out(words.size());
+  for (size_t g = 0; g < words.size(); ++g) out[pos[lay[g]]++] = words[g];
+  words.swap(out);
+}
+
 // Fuse every run of one-qubit Cliffords on a qubit into one G_C1 word,
 // emitted just before the next two-qubit gate on that qubit (or at the
 // end): the forward stream for tableau passes and, from the same runs, the
@@ -128,6 +151,8 @@ void fuse_clifford_runs(Fragment &F) {
   }
   for (uint32_t q = 0; q < m; ++q) flush(q);
   F.cl_back.assign(back.rbegin(), back.rend());
+  layer_stream(F.cl_words, F.cl_layers, m);
+  layer_stream(F.cl_back, F.cl_back_layers, m);
 }
 
 }  // namespace

@@ -34,6 +34,9 @@ struct Fragment {
   // G_C1 word (cl_words, circuit order), and the inverse stream for the
   // Heisenberg carry-back (cl_back: last gate first, each gate inverted)
   std::vector<uint32_t> cl_words, cl_back;
+  // both streams are ordered by ASAP layer; layer L of a stream spans
+  // words [layers[L], layers[L + 1])
+  std::vector<uint32_t> cl_layers, cl_back_layers;
   // non-Clifford fragments: the same ops with runs of one-qubit gates on a
   // qubit fused into one 2x2 unitary (G_U2) for the state-vector kernel
   std::vector<uint32_t> sv_words;
