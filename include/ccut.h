@@ -201,6 +201,18 @@ ccut_status ccut_marginal(ccut_plan *plan, const ccut_eval_opts *eo, const uint3
 ccut_status ccut_zexpect(ccut_plan *plan, const ccut_eval_opts *eo, const uint64_t *masks,
                          uint32_t n_strings, double *out, int out_on_device);
 
+/* Call graphs (default on).  A ccut_marginal or ccut_zexpect call with a
+ * device output that repeats an earlier call on the same plan exactly (same
+ * options, request and output address) is captured as a HIP graph on its
+ * second occurrence and replayed from then on: every kernel and copy runs
+ * again, only the host-side planning and launch overhead is saved.  Up to 8
+ * graphs per plan (least recently used out).  Calls with host outputs, with
+ * kernel timing enabled, or issued while the context's stream is being
+ * captured by the caller always run eagerly.  enable = 0 turns replay off
+ * (captured graphs are kept until their plan is destroyed).  Errors:
+ * CCUT_E_INVALID (NULL context). */
+ccut_status ccut_call_graphs(ccut_ctx *ctx, int enable);
+
 /* Parity hook: the sampled shot records of Clifford fragment `fragment`
  * for variants [v_begin, v_end) under the marginal request qubits[0..nq):
  * out[(v - v_begin) * shots + s] holds the outcome bits of shot s (bit j =

@@ -102,6 +102,7 @@ SIGNATURES = {
     "ccut_run_batch": ([_P, ctypes.POINTER(_P), ctypes.c_size_t, ctypes.POINTER(ccut_eval_opts),
                         ctypes.POINTER(_U32P), _U32P, ctypes.POINTER(_P)], ctypes.c_int),
     "ccut_timing_enable": ([_P, ctypes.c_int], ctypes.c_int),
+    "ccut_call_graphs": ([_P, ctypes.c_int], ctypes.c_int),
     "ccut_timing_reset": ([_P], ctypes.c_int),
     "ccut_timing_read": ([_P, ctypes.c_uint32, _U64P, _DP], ctypes.c_int),
     "ccut_kernel_name": ([ctypes.c_uint32], ctypes.c_char_p),
@@ -334,6 +335,10 @@ def ccut_timing_enable(ctx, on: bool) -> None:
     _check(lib().ccut_timing_enable(ctx, 1 if on else 0), ctx)
 
 
+def ccut_call_graphs(ctx, on: bool) -> None:
+    _check(lib().ccut_call_graphs(ctx, 1 if on else 0), ctx)
+
+
 def ccut_timing_reset(ctx) -> None:
     _check(lib().ccut_timing_reset(ctx), ctx)
 
@@ -402,6 +407,11 @@ class Context:
 
     def timing(self, on: bool = True):
         ccut_timing_enable(self.handle, on)
+
+    def call_graphs(self, on: bool = True):
+        """Replay repeated device-output marginal/zexpect calls as captured
+        HIP graphs (on by default)."""
+        ccut_call_graphs(self.handle, on)
 
     def timing_reset(self):
         ccut_timing_reset(self.handle)

@@ -38,6 +38,7 @@ struct Arena {
   void reset() {
     for (auto &c : chunks) c.used = 0;
   }
+  bool frozen = false;  // set while a stream capture is open: no allocation then
   void *get(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
@@ -47,6 +48,7 @@ struct Arena {
         c.used += bytes;
         return r;
       }
+    if (frozen) return nullptr;
     size_t cap = std::max(bytes, size_t(64) << 20);
     void *p = nullptr;
     if (alloc) {
@@ -109,6 +111,31 @@ struct ccut_ctx {
   static constexpr int kPinSlots = 4;
   PinSlot pin[kPinSlots];
   int pin_cur = -1;
+  // Call graphs: a device-output call repeated with identical arguments is
+  // captured once and then replayed.  While a capture is open, uploads are
+  // staged in the captured call's own pinned block (its copy nodes read it on
+  // every replay).
+  bool call_graphs = true;
+  hipStream_t cap_stream = nullptr;  // capture stream of call graphs
+  struct CallGraph *capturing = nullptr;
+  size_t call_upload_bytes = 0;  // staged bytes of the current call
+};
+
+// One captured call: its argument key, the executable graph and the pinned
+// block its host-to-device copy nodes read.
+struct CallGraph {
+  std::vector<uint8_t> key;
+  hipGraphExec_t exec = nullptr;
+  char *pin = nullptr;
+  size_t pin_cap = 0, pin_used = 0, upload_bytes = 0;
+  bool no_graph = false;  // capture failed once: stay eager
+  uint64_t last_use = 0;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (pin) (void)hipHostFree(pin);
+    exec = nullptr;
+    pin = nullptr;
+  }
 };
 
 struct ccut_plan {
@@ -120,7 +147,13 @@ struct ccut_plan {
   std::vector<uint32_t> n_back;
   std::vector<uint32_t *> d_layers, d_back_layers;  // layer offsets of both streams
   std::vector<uint32_t> n_layers, n_back_layers;
+  std::vector<CallGraph> graphs;  // least recently used first out, at most kMaxCallGraphs
+  uint64_t graph_tick = 0;
+  static constexpr size_t kMaxCallGraphs = 8;
   ~ccut_plan() {
+    // a replay may still be reading the graphs' pinned blocks
+    if (!graphs.empty() && ctx && ctx->device >= 0) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : graphs) g.release();
     for (auto p : d_ops)
       if (p) (void)hipFree(p);
     for (auto p : d_mats)
@@ -249,7 +282,8 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   c->cancel.store(0);
   c->arena.reset();
   c->staged.clear();
-  HIP_TRY(c, pin_begin(c));
+  c->call_upload_bytes = 0;
+  if (!c->capturing) HIP_TRY(c, pin_begin(c));
   if (!c->aux) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
@@ -310,9 +344,18 @@ void *upload(ccut_ctx *c, const void *src, size_t bytes) {
   void *d = c->arena.get(bytes);
   if (!d) return nullptr;
   if (c->replay_uploads || !src || bytes == 0) return d;  // replay: the bytes are already there
+  const size_t need = (bytes + 255) & ~size_t(255);
+  c->call_upload_bytes += need;
+  if (CallGraph *g = c->capturing) {  // staged for good in the captured call's block
+    if (g->pin_used + need > g->pin_cap) return nullptr;
+    char *stage = g->pin + g->pin_used;
+    g->pin_used += need;
+    std::memcpy(stage, src, bytes);
+    if (hipMemcpyAsync(d, stage, bytes, hipMemcpyHostToDevice, c->cur) != hipSuccess) return nullptr;
+    return d;
+  }
   if (c->pin_cur < 0 && pin_begin(c) != hipSuccess) return nullptr;
   ccut_ctx::PinSlot &sl = c->pin[c->pin_cur];
-  const size_t need = (bytes + 255) & ~size_t(255);
   while (sl.chunk < sl.chunks.size() && sl.used + need > sl.chunks[sl.chunk].second) {
     ++sl.chunk;
     sl.used = 0;
@@ -364,10 +407,11 @@ FragDev frag_desc(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_
 }
 
 // Affine sample models of variants [v0, v0 + nv) of a Clifford fragment.
-// With more than a few variants, the fragment's gates run once on the
-// identity tableau (one row per lane) and every variant starts from that
-// shared tableau with its preparations as row substitutions.
-constexpr uint64_t kBaseMinVariants = 16;
+// With more than one variant, the fragment's gates run once on the identity
+// tableau (the layered bit-sliced row pass) and every variant starts from
+// that shared tableau with its preparations as row substitutions; a single
+// variant replays the gates itself.
+constexpr uint64_t kBaseMinVariants = 1;
 ccut_status tableau_models(ccut_ctx *c, const Fragment &f, const FragDev &h, uint64_t v0, uint64_t nv,
                            uint64_t *models) {
   const uint64_t *base = nullptr;
@@ -684,6 +728,7 @@ void ctx_free(ccut_ctx *c) {
       (void)hipEventDestroy(pt.b);
     }
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->aux) {
       (void)hipStreamSynchronize(c->aux);
       (void)hipStreamDestroy(c->aux);
@@ -904,9 +949,105 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
 }
 }  // namespace
 
-extern "C" {
+namespace {
 
-ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+void key_put(std::vector<uint8_t> &k, const void *src, size_t n) {
+  k.insert(k.end(), (const uint8_t *)src, (const uint8_t *)src + n);
+}
+
+// Argument key of a call: entry point, every option, the request and the
+// output address.
+std::vector<uint8_t> call_key(uint32_t entry, const ccut_eval_opts *eo, const void *req, size_t req_bytes,
+                              const double *out) {
+  std::vector<uint8_t> k;
+  key_put(k, &entry, 4);
+  key_put(k, &eo->seed, 8);
+  key_put(k, &eo->shots_per_variant, 8);
+  key_put(k, &eo->precision, 4);
+  key_put(k, &eo->circuit, 4);
+  key_put(k, &eo->method, 4);
+  key_put(k, &eo->reserved, 4);
+  key_put(k, &req_bytes, sizeof(req_bytes));
+  key_put(k, req, req_bytes);
+  const uintptr_t o = (uintptr_t)out;
+  key_put(k, &o, sizeof(o));
+  return k;
+}
+
+// Run a device-output call through the plan's call graphs: the first call
+// with a given key runs eagerly, the second is captured (every launch and
+// copy it enqueues, on both streams) and replayed, later ones only replay.
+// Calls with host outputs, with kernel timing on, or issued while the
+// caller's stream is itself being captured always run eagerly.  The graph's
+// scratch lives in the context's pool, which only grows, so its addresses
+// stay valid; replays and eager calls are ordered on the context's stream.
+template <class Impl>
+ccut_status graph_call(ccut_plan *p, std::vector<uint8_t> &&key, int on_device, Impl &&impl) {
+  ccut_ctx *c = p ? p->ctx : nullptr;
+  if (!c || !on_device || !c->call_graphs || c->timing || c->device < 0 || c->capturing) return impl();
+  if (hipSetDevice(c->device) != hipSuccess) return impl();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return impl();
+  CallGraph *g = nullptr;
+  for (auto &e : p->graphs)
+    if (e.key == key) g = &e;
+  if (g && g->no_graph) return impl();
+  if (g && g->exec) {
+    g->last_use = ++p->graph_tick;
+    c->cancel.store(0);
+    HIP_TRY(c, hipGraphLaunch(g->exec, c->stream));
+    return CCUT_OK;
+  }
+  if (!g) {  // first sighting: eager, remembered only if it succeeds
+    ccut_status st = impl();
+    if (st != CCUT_OK) return st;
+    if (p->graphs.size() >= ccut_plan::kMaxCallGraphs) {
+      auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
+                                  [](const CallGraph &a, const CallGraph &b) { return a.last_use < b.last_use; });
+      lru->release();
+      p->graphs.erase(lru);
+    }
+    p->graphs.emplace_back();
+    CallGraph &e = p->graphs.back();
+    e.key = std::move(key);
+    e.upload_bytes = c->call_upload_bytes;
+    e.last_use = ++p->graph_tick;
+    return CCUT_OK;
+  }
+  // second sighting: capture, instantiate, launch
+  g->last_use = ++p->graph_tick;
+  g->pin_cap = std::max<size_t>(g->upload_bytes, 256);
+  g->pin_used = 0;
+  HIP_TRY(c, hipHostMalloc((void **)&g->pin, g->pin_cap, hipHostMallocDefault));
+  // captured on a private stream (the caller's may be the legacy default
+  // stream, which cannot be captured) and launched on the caller's
+  if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  const hipStream_t caller = c->stream;
+  c->stream = c->cap_stream;
+  c->capturing = g;
+  c->arena.frozen = true;
+  ccut_status st = impl();
+  c->arena.frozen = false;
+  c->capturing = nullptr;
+  c->stream = caller;
+  hipGraph_t graph = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(c->cap_stream, &graph);
+  hipError_t e_inst = hipErrorUnknown;
+  if (st == CCUT_OK && e_end == hipSuccess && graph) e_inst = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != CCUT_OK || e_inst != hipSuccess) {
+    // stay eager for this key; the capture enqueued nothing, so run the call now
+    g->release();
+    g->no_graph = true;
+    (void)hipGetLastError();
+    return impl();
+  }
+  HIP_TRY(c, hipGraphLaunch(g->exec, c->stream));
+  return CCUT_OK;
+}
+
+ccut_status marginal_call(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
                           double *out, int on_device) {
   ccut_status st = check_eval(p, eo);
   if (st != CCUT_OK) return st;
@@ -919,7 +1060,7 @@ ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t
   return finish_out(c, res, out, (size_t)1 << nq, on_device);
 }
 
-ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t *masks, uint32_t n_strings,
+ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t *masks, uint32_t n_strings,
                          double *out, int on_device) {
   ccut_status st = check_eval(p, eo);
   if (st != CCUT_OK) return st;
@@ -1044,6 +1185,32 @@ ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
                                  res, c->cur));
   }
   return finish_out(c, res, out, n_strings, on_device);
+}
+
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                          double *out, int on_device) {
+  if (!p || !eo || !out || (nq && !qubits) || nq > 24) return marginal_call(p, eo, qubits, nq, out, on_device);
+  return graph_call(p, call_key(0, eo, qubits, (size_t)nq * 4, out), on_device,
+                    [&] { return marginal_call(p, eo, qubits, nq, out, on_device); });
+}
+
+ccut_status ccut_zexpect(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t *masks, uint32_t n_strings,
+                         double *out, int on_device) {
+  if (!p || !eo || !out || !masks || n_strings == 0)
+    return zexpect_call(p, eo, masks, n_strings, out, on_device);
+  const size_t nw = (p->pd.n + 63) / 64;
+  return graph_call(p, call_key(1, eo, masks, (size_t)n_strings * nw * 8, out), on_device,
+                    [&] { return zexpect_call(p, eo, masks, n_strings, out, on_device); });
+}
+
+ccut_status ccut_call_graphs(ccut_ctx *c, int enable) {
+  if (!c) return CCUT_E_INVALID;
+  c->call_graphs = enable != 0;
+  return CCUT_OK;
 }
 
 ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,

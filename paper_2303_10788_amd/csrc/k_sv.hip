@@ -2,10 +2,12 @@
 // exact backend for non-Clifford fragments, Sec. V-B).
 //
 // Variants of a fragment share everything but their preparations and their
-// final basis rotations, so one workgroup simulates the fragment once per
-// preparation combination (state in LDS, m <= 12 qubits: 64 KiB) and then,
-// for each basis combination, rotates a copy and writes that variant's
-// outcome distribution over the measured set.  Runs of one-qubit gates
+// final basis rotations.  A workgroup simulates the fragment for one
+// preparation combination (state in LDS, m <= 12 qubits: 64 KiB) and then
+// rotates the state into one basis combination (small grids: one workgroup
+// per preparation and basis combination) or, for large grids, into each
+// basis combination in turn on a copy, and writes that variant's outcome
+// distribution over the measured set.  Runs of one-qubit gates
 // arrive fused into single 2x2 unitaries (G_U2).  Each distribution entry is
 // reduced in a fixed order (deterministic).
 #include "common.hpp"
@@ -168,8 +170,12 @@ __device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
   }
 }
 
+// split_bc: workgroup x runs preparation combination x / 3^n_out and only
+// basis combination x mod 3^n_out (rotating its own state in place), so the
+// basis combinations run side by side; otherwise workgroup x runs
+// preparation combination x and every basis combination on a copy.
 template <int PPT, int BS>
-__global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restrict__ dist) {
+__global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
   extern __shared__ C2 smem_amp[];
   __shared__ C2 s_mats[64];
   const uint32_t m = F.m;
@@ -179,12 +185,17 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
   // preparation combination of this workgroup: digits of the input axes
   uint32_t n_out = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
-  C2 *work = n_out ? smem_amp + N : smem_amp;
+  uint32_t n_bc = 1;
+  for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
+  const uint32_t prep = split_bc ? blockIdx.x / n_bc : blockIdx.x;
+  const uint32_t bc0 = split_bc ? blockIdx.x % n_bc : 0, bc1 = split_bc ? bc0 + 1 : n_bc;
+  const bool copy = n_out && !split_bc;
+  C2 *work = copy ? smem_amp + N : smem_amp;
   for (uint32_t i = tid; i < N; i += BS) base[i] = C2{i == 0 ? 1.0 : 0.0, 0.0};
   __syncthreads();
   uint64_t vin = 0;  // variant index contribution of the input digits
   {
-    uint64_t pc = blockIdx.x, stride = 1;
+    uint64_t pc = prep, stride = 1;
     for (uint32_t j = 0; j < F.n_axes; ++j) {
       if (F.axis_side[j] == 1) {
         const uint32_t d = (uint32_t)(pc & 3u);
@@ -207,10 +218,8 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
   uint32_t mmask = 0;
   for (uint32_t j = 0; j < nm; ++j) mmask |= 1u << F.meas[j];
   const uint32_t outs = 1u << nm;
-  uint32_t n_bc = 1;
-  for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
-  for (uint32_t bc = 0; bc < n_bc; ++bc) {
-    if (n_out) {
+  for (uint32_t bc = bc0; bc < bc1; ++bc) {
+    if (copy) {
       for (uint32_t i = tid; i < N; i += BS) work[i] = base[i];
       __syncthreads();
     }
@@ -274,7 +283,14 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   if (h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
   uint32_t n_in = 0, n_out = 0;
   for (uint32_t j = 0; j < h.n_axes; ++j) (h.axis_side[j] ? n_in : n_out) += 1;
-  const size_t lds = (size_t(1) << h.m) * sizeof(C2) * (n_out ? 2 : 1);
+  // basis combinations get workgroups of their own while the grid stays
+  // within about two workgroups per compute unit (each one repeats the
+  // gate sequence, which costs nothing while the chip would idle)
+  uint64_t n_bc = 1;
+  for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
+  const uint64_t n_prep = 1ull << (2 * n_in);
+  const bool split = n_out && n_prep * n_bc <= 512;
+  const size_t lds = (size_t(1) << h.m) * sizeof(C2) * (n_out && !split ? 2 : 1);
   // one workgroup per preparation combination, sized to the state: 256
   // threads up to 9 qubits, then 512, then 1024 (several waves per SIMD
   // hide the LDS and fp64 latency); PPT amplitude pairs per thread per op
@@ -283,8 +299,8 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   const int bs = h.m <= 9 ? 256 : h.m == 10 ? 512 : 1024;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const uint64_t n_prep = 1ull << (2 * n_in);
-  hipLaunchKernelGGL(kern, dim3((unsigned)n_prep), dim3(bs), lds, s, h, dist);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(split ? n_prep * n_bc : n_prep)), dim3(bs), lds, s, h, dist,
+                     (uint32_t)split);
   return hipGetLastError();
 }
 
