@@ -221,8 +221,9 @@ T *aget(ccut_ctx *c, size_t count) {
 
 // Upload each fragment's op streams once per plan: for Clifford fragments
 // the fused forward stream and the carry-back stream, for non-Clifford ones
-// the fused stream with its matrices; padded with no-ops (identities) to a
-// multiple of 16 words so kernels can fetch ops sixteen at a time.
+// the state-vector program with its matrices; padded with no-ops
+// (identities) to a multiple of 16 words so kernels can fetch ops sixteen at
+// a time.
 ccut_status ensure_ops(ccut_plan *p) {
   ccut_ctx *c = p->ctx;
   if (!p->d_ops.empty()) return CCUT_OK;
@@ -249,8 +250,8 @@ ccut_status ensure_ops(ccut_plan *p) {
     p->d_back_layers.push_back(dbl);
     p->n_layers.push_back(f.cl_layers.empty() ? 0u : (uint32_t)f.cl_layers.size() - 1);
     p->n_back_layers.push_back(f.cl_back_layers.empty() ? 0u : (uint32_t)f.cl_back_layers.size() - 1);
-    std::vector<uint32_t> words = f.clifford ? f.cl_words : f.sv_words;
-    std::vector<double> mats = f.clifford ? std::vector<double>() : f.sv_mats;
+    std::vector<uint32_t> words = f.clifford ? f.cl_words : f.sv_prog;
+    std::vector<double> mats = f.clifford ? std::vector<double>() : f.sv_prog_mats;
     while (words.size() % 16 || words.empty()) {
       words.push_back(pack_op(G_NOP, 0, 0));
       if (!f.clifford) mats.insert(mats.end(), 8, 0.0);

@@ -10,6 +10,32 @@ namespace ccut {
 constexpr int kMaxAxes = 16;   // cut axes incident to one fragment
 constexpr int kMaxMeas = 64;   // measured qubits of one Clifford fragment (one u64 record)
 constexpr int kMaxNcQubits = 12;  // state vector of 2^12 complex doubles = 64 KiB of LDS
+
+// State-vector programs.  A non-Clifford fragment's state of 2^m amplitudes
+// is spread over registers: amplitude index bits [0, RB) select one of a
+// thread's 2^RB registers, the next min(m, 6) bits the lane of a wave and
+// the top WB bits the wave.  A program maps each logical qubit to one of
+// these bit positions; ops whose matrix mixes amplitudes (a general 2x2 or
+// a CX target) act on register or lane positions only, so they need no
+// barrier; diagonal ops, CZ and CX controls act anywhere.  SV_SWAP exchanges
+// a register or lane position with a wave position through LDS.
+enum : uint32_t {
+  SV_U2 = 0,    // general 2x2 unitary on position a (register or lane), matrix in mats
+  SV_DIAG = 1,  // diagonal unitary on position a (any): diag(m00, m11)
+  SV_CX = 2,    // control position a (any), target position b (register or lane)
+  SV_CZ = 3,    // positions a, b (any)
+  SV_SWAP = 4,  // exchange positions a (register or lane) and b (wave)
+  SV_END = 5,   // final layout: bits 4q..4q+3 of the first matrix word = position of qubit q
+};
+struct SvShape {
+  uint32_t rb, lb, wb;  // register, lane and wave bits
+};
+__host__ __device__ inline SvShape sv_shape(uint32_t m) {
+  if (m <= 6) return {0u, m, 0u};
+  if (m <= 8) return {m - 6, 6u, 0u};
+  if (m <= 10) return {2u, 6u, m - 8};
+  return {m - 8, 6u, 2u};
+}
 constexpr int kMaxTableBits = 24;
 
 enum GateKind : uint32_t {
@@ -186,6 +212,7 @@ hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nbl
                               uint64_t shots, double *dist, hipStream_t s);
 hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,
                                hipStream_t s);
+// prog: the fragment's state-vector program (words + 8 doubles per word)
 hipError_t launch_sv(const FragDev &frag, double *dist, hipStream_t s);
 hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
                                const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);

@@ -177,6 +177,25 @@ __global__ __launch_bounds__(64) void base_batch_kernel(const FragDev *__restric
 // sign) row layout.  At most 1024 rows per wave.
 constexpr uint32_t kSlicedRows = 1024;
 constexpr uint32_t kOpStage = 1024;  // op words staged in LDS (a layer has at most 512)
+constexpr uint32_t kLayStage = 256;  // layer offsets staged in LDS
+
+// Fill dst[0, CAP) from src[0, n) (zeros past n) with all loads of a lane
+// issued before its first store, so the copy costs one memory latency
+// rather than one per word (one wave).
+template <uint32_t CAP>
+__device__ inline void stage_words(uint32_t *dst, const uint32_t *src, uint32_t n, uint32_t lane) {
+  constexpr uint32_t K = (CAP + 63) / 64;
+  uint32_t t[K];
+#pragma unroll
+  for (uint32_t k = 0; k < K; ++k) {
+    const uint32_t i = lane + 64 * k;
+    t[k] = i < n && i < CAP ? src[i] : 0u;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < K; ++k)
+    if (lane + 64 * k < CAP) dst[lane + 64 * k] = t[k];
+}
+
 template <class D>
 __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                  uint32_t n_rows, uint64_t *cols) {
@@ -189,85 +208,129 @@ __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restr
   uint64_t *Xc = cols, *Zc = cols + (size_t)m * RW;
   uint32_t *sops = reinterpret_cast<uint32_t *>(Zc + (size_t)m * RW);
   const uint32_t RS = 2 * W + 1;  // row stride in words
-  for (uint32_t idx = lane; idx < m * RW; idx += 64) {
-    const uint32_t q = idx / RW, iw = idx % RW;
-    uint64_t xw = 0, zw = 0;
-    if (!in) {  // X_r for rows r < m, then Z_{r - m}
-      if (q >> 6 == iw) xw = 1ull << (q & 63);
-      if ((m + q) >> 6 == iw) zw = 1ull << ((m + q) & 63);
-    } else {
-      for (uint32_t i = 0; i < 64; ++i) {
-        const uint32_t r = 64 * iw + i;
-        if (r >= n_rows) break;
-        const uint64_t *row = in + (size_t)r * RS;
-        xw |= ((row[q >> 6] >> (q & 63)) & 1ull) << i;
-        zw |= ((row[W + (q >> 6)] >> (q & 63)) & 1ull) << i;
+  uint64_t sg = 0;  // this lane's share of sign word w
+  if (!in) {
+    for (uint32_t idx = lane; idx < m * RW; idx += 64) {  // X_r for rows r < m, then Z_{r - m}
+      const uint32_t q = idx / RW, iw = idx % RW;
+      Xc[idx] = q >> 6 == iw ? 1ull << (q & 63) : 0ull;
+      Zc[idx] = (m + q) >> 6 == iw ? 1ull << ((m + q) & 63) : 0ull;
+    }
+  } else {
+    // transpose in, 64 rows at a time: lane l loads row 64 iw + l whole,
+    // and column word (q, iw) is the ballot of bit q over the lanes
+    for (uint32_t iw = 0; iw < RW; ++iw) {
+      const uint32_t r = 64 * iw + lane;
+      const bool ok = r < n_rows;
+      const uint64_t *row = in + (size_t)(ok ? r : 0) * RS;
+      uint64_t xr[8], zr[8];
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) {
+        xr[k] = ok && k < W ? row[k] : 0ull;
+        zr[k] = ok && k < W ? row[W + k] : 0ull;
+      }
+      const uint64_t sw = __ballot(ok && (row[2 * W] & 1ull));
+      if (lane == iw) sg = sw;  // lane iw starts with sign word iw
+#pragma unroll
+      for (uint32_t k = 0; k < 8; ++k) {
+        if (k >= W) break;
+        const uint32_t nq = 64 * k < m ? min(64u, m - 64 * k) : 0u;
+        for (uint32_t i = 0; i < nq; ++i) {
+          const uint64_t cx = __ballot((xr[k] >> i) & 1ull), cz = __ballot((zr[k] >> i) & 1ull);
+          if (lane == i) {
+            Xc[(size_t)(64 * k + i) * RW + iw] = cx;
+            Zc[(size_t)(64 * k + i) * RW + iw] = cz;
+          }
+        }
       }
     }
-    Xc[idx] = xw;
-    Zc[idx] = zw;
   }
-  uint64_t sg = 0;  // this lane's share of sign word w
-  if (in && lane < RW)
-    for (uint32_t i = 0; i < 64; ++i) {
-      const uint32_t r = 64 * lane + i;
-      if (r >= n_rows) break;
-      sg |= (in[(size_t)r * RS + 2 * W] & 1ull) << i;
-    }
   const bool live = w < RW;
   __syncthreads();
-  // without layer offsets every op is a layer of its own
-  const g_u32 *lay = (const g_u32 *)F.layers;
+  // Layer offsets are staged in LDS too (without offsets every op is a
+  // layer of its own).  One layer of lookahead: the next layer's end offset
+  // and this lane's first op word of the next layer are read before the
+  // current layer's column traffic, so only the column reads wait on LDS.
+  // Op words are restaged when the next layer (at most 512 ops) might not
+  // lie inside the staged window.
+  uint32_t *slay = sops + kOpStage;
+  const uint32_t *lay = F.layers;
   const uint32_t n_layers = lay ? F.n_layers : F.n_ops;
-  uint32_t stage0 = 0xFFFFFFFFu;
-  for (uint32_t L = 0; L < n_layers; ++L) {
-    const uint32_t s0 = lay ? lay[L] : L, s1 = lay ? lay[L + 1] : L + 1;
-    if (stage0 == 0xFFFFFFFFu || s1 > stage0 + kOpStage) {
-      stage0 = s0;
-      for (uint32_t i = lane; i < kOpStage; i += 64) sops[i] = s0 + i < F.n_ops ? F.ops[s0 + i] : 0u;
+  uint32_t stage0 = 0;
+  stage_words<kOpStage>(sops, F.ops, F.n_ops, lane);
+  uint32_t s0 = 0;
+  uint32_t v_wd = sops[o];  // this lane's first op word of the current layer
+  for (uint32_t L0 = 0; L0 < n_layers; L0 += kLayStage) {
+    const uint32_t nl = min(kLayStage, n_layers - L0);
+    if (lay) {
+      stage_words<kLayStage + 1>(slay, lay + L0, nl + 1, lane);
+    } else {
+      for (uint32_t i = lane; i <= nl; i += 64) slay[i] = L0 + i;
     }
-    for (uint32_t c0 = s0 + o; c0 < s1; c0 += per) {
-      if (!live) continue;
-      const uint32_t wd = sops[c0 - stage0];
-      const uint32_t kind = op_kind(wd), a = op_q0(wd), b = op_q1(wd);
-      uint64_t *xa = Xc + (size_t)a * RW + w, *za = Zc + (size_t)a * RW + w;
-      if (kind == G_CX || kind == G_CZ) {
-        uint64_t *xb = Xc + (size_t)b * RW + w, *zb = Zc + (size_t)b * RW + w;
-        const uint64_t x1 = *xa, z1 = *za, x2 = *xb, z2 = *zb;
-        if (kind == G_CX) {
-          sg ^= x1 & z2 & ~(x2 ^ z1);
-          *xb = x2 ^ x1;
-          *za = z1 ^ z2;
+    uint32_t v_s1 = slay[1];
+    for (uint32_t L = 0; L < nl; ++L) {
+      const uint32_t s1 = __builtin_amdgcn_readfirstlane(v_s1);
+      const uint32_t wd0 = v_wd;
+      const bool keep = s1 + 512 <= stage0 + kOpStage;  // the next layer is inside the window
+      uint32_t v_s1n = 0, v_wdn = 0;
+      if (L + 2 <= nl) v_s1n = slay[L + 2];
+      if (keep) v_wdn = sops[s1 + o - stage0];
+      for (uint32_t c0 = s0 + o; c0 < s1; c0 += per) {
+        if (!live) continue;
+        const uint32_t wd = c0 == s0 + o ? wd0 : sops[c0 - stage0];
+        const uint32_t kind = op_kind(wd), a = op_q0(wd), b = op_q1(wd);
+        uint64_t *xa = Xc + (size_t)a * RW + w, *za = Zc + (size_t)a * RW + w;
+        if (kind == G_CX || kind == G_CZ) {
+          uint64_t *xb = Xc + (size_t)b * RW + w, *zb = Zc + (size_t)b * RW + w;
+          const uint64_t x1 = *xa, z1 = *za, x2 = *xb, z2 = *zb;
+          if (kind == G_CX) {
+            sg ^= x1 & z2 & ~(x2 ^ z1);
+            *xb = x2 ^ x1;
+            *za = z1 ^ z2;
+          } else {
+            sg ^= x1 & x2 & (z1 ^ z2);
+            *za = z1 ^ x2;
+            *zb = z2 ^ x1;
+          }
         } else {
-          sg ^= x1 & x2 & (z1 ^ z2);
-          *za = z1 ^ x2;
-          *zb = z2 ^ x1;
+          const C1Map g = c1_decode(b);
+          const uint64_t x = *xa, z = *za;
+          sg ^= (x & (0ull - g.al)) ^ (z & (0ull - g.be)) ^ (x & z & (0ull - g.ga));
+          *xa = (x & (0ull - g.m00)) ^ (z & (0ull - g.m01));
+          *za = (x & (0ull - g.m10)) ^ (z & (0ull - g.m11));
         }
-      } else {
-        const C1Map g = c1_decode(b);
-        const uint64_t x = *xa, z = *za;
-        sg ^= (x & (0ull - g.al)) ^ (z & (0ull - g.be)) ^ (x & z & (0ull - g.ga));
-        *xa = (x & (0ull - g.m00)) ^ (z & (0ull - g.m01));
-        *za = (x & (0ull - g.m10)) ^ (z & (0ull - g.m11));
       }
+      asm volatile("" ::: "memory");
+      if (!keep) {  // restage from the next layer's start (in issue order after this layer's reads)
+        stage0 = s1;
+        stage_words<kOpStage>(sops, F.ops + s1, F.n_ops - s1, lane);
+        v_wdn = sops[o];
+      }
+      s0 = s1;
+      v_s1 = v_s1n;
+      v_wd = v_wdn;
     }
-    asm volatile("" ::: "memory");
   }
   // sign word w: XOR of the shares of every lane on row word w (lane w ends with it)
   for (uint32_t off = RWp; off < 64; off <<= 1) sg ^= __shfl_xor(sg, off);
   __syncthreads();
-  for (uint32_t idx = lane; idx < n_rows * W; idx += 64) {
-    const uint32_t r = idx / W, wq = idx % W;
-    const uint32_t rw = r >> 6, rb = r & 63;
-    uint64_t xw = 0, zw = 0;
-    for (uint32_t i = 0; i < 64; ++i) {
-      const uint32_t q = 64 * wq + i;
-      if (q >= m) break;
-      xw |= ((Xc[(size_t)q * RW + rw] >> rb) & 1ull) << i;
-      zw |= ((Zc[(size_t)q * RW + rw] >> rb) & 1ull) << i;
+  // transpose out, 64 rows at a time: lane l gathers row 64 rw + l from the
+  // column words (each read is the same address for every lane)
+  for (uint32_t rw = 0; rw < RW; ++rw) {
+    const uint32_t r = 64 * rw + lane;
+    for (uint32_t wq = 0; wq < W; ++wq) {
+      const uint32_t nq = 64 * wq < m ? min(64u, m - 64 * wq) : 0u;
+      uint64_t xw = 0, zw = 0;
+#pragma unroll 8
+      for (uint32_t i = 0; i < nq; ++i) {
+        const size_t c = (size_t)(64 * wq + i) * RW + rw;
+        xw |= ((Xc[c] >> lane) & 1ull) << i;
+        zw |= ((Zc[c] >> lane) & 1ull) << i;
+      }
+      if (r < n_rows) {
+        out[(size_t)r * RS + wq] = xw;
+        out[(size_t)r * RS + W + wq] = zw;
+      }
     }
-    out[(size_t)r * RS + wq] = xw;
-    out[(size_t)r * RS + W + wq] = zw;
   }
   for (uint32_t rw = 0; rw < RW; ++rw) {
     const uint64_t word = __shfl(sg, rw);
@@ -447,7 +510,7 @@ hipError_t run_w(const FragDev &F, const HeisArgs &A, const uint64_t *rows_in, u
 // is turned into T[p_f][b] in place.  String mode: rows are n_str strings then
 // the output pairs; tau is [4^n_axes][n_str] = t_f[p_f][string].
 size_t rows_sliced_lds(uint32_t m, uint32_t n_rows) {
-  return (size_t)2 * m * ((n_rows + 63) / 64) * 8 + kOpStage * 4;
+  return (size_t)2 * m * ((n_rows + 63) / 64) * 8 + (kOpStage + kLayStage + 1) * 4;
 }
 
 hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,

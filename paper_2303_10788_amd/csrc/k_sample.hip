@@ -7,6 +7,8 @@
 // (c0..c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
 // key bumped by the Weyl constants between rounds.  One call yields four
 // 32-bit words: four consecutive shots x 32 measurement indices.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace ccut {
@@ -137,56 +139,80 @@ __global__ void parity_exact_kernel(const uint64_t *__restrict__ models, uint32_
   E[i] = g ? 0.0 : (c ? -1.0 : 1.0);
 }
 
-constexpr int kParityBlock = 256;
-constexpr int kParityQuads = 16;  // 64 shots per thread
+constexpr int kParityBlock = 256;  // four waves
 
-// Odd-parity counts per (variant, ext mask) over all shots.  grid (nblk_x, nv).
+// Odd-parity counts per (variant, ext mask) over all shots, bit-sliced:
+// lane l of a wave owns masks l, 64 + l, ... (G per pass) and the
+// wave draws 64 quads (256 shots) per round, one quad per lane.  For shot
+// r of every lane, bit j of the 64 random words becomes one 64-bit plane
+// (a ballot); a mask's parities over those 64 shots are the XOR of the
+// planes of the bits j set in its form g, so one wave instruction serves 64
+// shots of 64 masks.  Counts are exact integers.  grid (nblk_x, nv); wave w
+// of block x runs rounds [(4x + w) * rounds, (4x + w + 1) * rounds).
+template <int kParityGroups>
 __global__ __launch_bounds__(kParityBlock) void parity_sampled_kernel(
     const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
-    uint64_t vid0, const uint64_t *__restrict__ ext, uint32_t n_ext,
+    uint64_t vid0, const uint64_t *__restrict__ ext, uint32_t n_ext, uint32_t rounds, uint32_t use_lds,
     uint32_t *__restrict__ odd_counts) {
-  extern __shared__ uint64_t s_dyn[];
-  uint64_t *s_g = s_dyn;                                       // [n_ext]
-  uint32_t *s_c = reinterpret_cast<uint32_t *>(s_g + n_ext);    // [n_ext]
-  uint32_t *s_cnt = s_c + n_ext;                                // [n_ext]
+  extern __shared__ uint32_t s_cnt[];  // [n_ext] per workgroup when use_lds
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t v = blockIdx.y;
   const uint64_t *md = models + v * model_words(n_meas);
-  for (uint32_t s = threadIdx.x; s < n_ext; s += kParityBlock) {
-    uint32_t c;
-    uint64_t g;
-    parity_form(md, n_meas, ext[s], c, g);
-    s_g[s] = g;
-    s_c[s] = c;
-    s_cnt[s] = 0;
-  }
+  if (use_lds)
+    for (uint32_t s = threadIdx.x; s < n_ext; s += kParityBlock) s_cnt[s] = 0;
   __syncthreads();
   const uint64_t vid = vid0 + v;
   const bool wide = n_meas > 32;
   const uint64_t nquads = (shots + 3) >> 2;
-  uint64_t u[4 * kParityQuads];
-  uint32_t valid = 0;
+  const uint64_t r0 = ((uint64_t)blockIdx.x * (kParityBlock / 64) + wave) * rounds;
+  for (uint32_t p0 = 0; p0 < n_ext; p0 += 64 * kParityGroups) {
+    uint64_t gm[kParityGroups];
+    uint32_t cm[kParityGroups], cnt[kParityGroups];
+    uint64_t gall = 0;
 #pragma unroll
-  for (int q = 0; q < kParityQuads; ++q) {
-    const uint64_t quad = ((uint64_t)blockIdx.x * kParityQuads + q) * kParityBlock + threadIdx.x;
-    uint64_t w[4] = {0, 0, 0, 0};
-    if (quad < nquads) quad_bits(quad, vid, seed, wide, w);
+    for (int k = 0; k < kParityGroups; ++k) {
+      const uint32_t s = p0 + 64 * k + lane;
+      gm[k] = 0;
+      cm[k] = 0;
+      cnt[k] = 0;
+      if (s < n_ext) parity_form(md, n_meas, ext[s], cm[k], gm[k]);
+      gall |= gm[k];
+    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const bool ok = quad < nquads && quad * 4 + r < shots;
-      u[q * 4 + r] = ok ? w[r] : 0ull;
-      valid += ok ? 1u : 0u;
+    for (int off = 1; off < 64; off <<= 1) gall |= __shfl_xor(gall, off);
+    gall = __builtin_amdgcn_readfirstlane((uint32_t)gall) |
+           ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(gall >> 32)) << 32);
+    uint32_t total = 0;  // valid shots seen by this wave
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+      const uint64_t quad = (r0 + rd) * 64 + lane;
+      uint64_t w[4] = {0, 0, 0, 0};
+      if (quad < nquads) quad_bits(quad, vid, seed, wide, w);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint64_t valid = __ballot(quad < nquads && quad * 4 + r < shots);
+        if (!valid) continue;
+        total += __popcll(valid);
+        uint64_t acc[kParityGroups];
+#pragma unroll
+        for (int k = 0; k < kParityGroups; ++k) acc[k] = 0;
+        for (uint64_t rem = gall; rem; rem &= rem - 1) {
+          const uint32_t j = (uint32_t)__builtin_ctzll(rem);
+          const uint64_t plane = __ballot((w[r] >> j) & 1ull);
+#pragma unroll
+          for (int k = 0; k < kParityGroups; ++k) acc[k] ^= ((gm[k] >> j) & 1ull) ? plane : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kParityGroups; ++k) cnt[k] += __popcll(acc[k] & valid);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kParityGroups; ++k) {
+      const uint32_t s = p0 + 64 * k + lane;
+      const uint32_t odd = cm[k] ? total - cnt[k] : cnt[k];
+      if (s < n_ext && odd) atomicAdd(use_lds ? &s_cnt[s] : &odd_counts[v * n_ext + s], odd);
     }
   }
-  for (uint32_t s = 0; s < n_ext; ++s) {
-    const uint64_t g = s_g[s];
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int k = 0; k < 4 * kParityQuads; ++k) cnt += __popcll(g & u[k]) & 1u;
-    uint32_t odd = s_c[s] ? valid - cnt : cnt;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) odd += __shfl_xor(odd, off);
-    if ((threadIdx.x & 63) == 0 && odd) atomicAdd(&s_cnt[s], odd);
-  }
+  if (!use_lds) return;
   __syncthreads();
   for (uint32_t s = threadIdx.x; s < n_ext; s += kParityBlock)
     if (s_cnt[s]) atomicAdd(&odd_counts[v * n_ext + s], s_cnt[s]);
@@ -267,11 +293,27 @@ hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64
                                  uint64_t seed, uint64_t vid0, const uint64_t *ext, uint32_t n_ext,
                                  uint32_t *odd_counts, hipStream_t s) {
   if (nv == 0 || nv > 65535) return hipErrorInvalidValue;
-  const uint64_t per_block = (uint64_t)kParityBlock * kParityQuads * 4;
-  const unsigned nbx = blocks_for(shots, (unsigned)per_block);
-  const size_t lds = (size_t)n_ext * 16;
-  hipLaunchKernelGGL(parity_sampled_kernel, dim3(nbx, (unsigned)nv), dim3(kParityBlock), lds, s, models,
-                     n_meas, shots, seed, vid0, ext, n_ext, odd_counts);
+  if (shots == 0 || n_ext == 0) return hipSuccess;
+  // rounds of 256 shots per wave: enough waves for about four per SIMD
+  const uint64_t total_rounds = ((shots + 3) / 4 + 63) / 64;  // per variant
+  const uint64_t want_waves = std::max<uint64_t>(1, 4096 / nv);
+  const uint64_t rounds = std::max<uint64_t>(1, (total_rounds + want_waves - 1) / want_waves);
+  const uint64_t waves = (total_rounds + rounds - 1) / rounds;
+  const uint64_t nbx = (waves + kParityBlock / 64 - 1) / (kParityBlock / 64);
+  if (nbx > 0x7FFFFFFFull || rounds > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  // per-workgroup sums in LDS while they fit in 64 KiB, else straight to memory
+  const bool use_lds = n_ext <= 16384;
+  const size_t lds = use_lds ? (size_t)n_ext * 4 : 0;
+  const dim3 grid((unsigned)nbx, (unsigned)nv), block(kParityBlock);
+  if (n_ext <= 64)
+    hipLaunchKernelGGL(parity_sampled_kernel<1>, grid, block, lds, s, models, n_meas, shots, seed, vid0, ext, n_ext,
+                       (uint32_t)rounds, (uint32_t)use_lds, odd_counts);
+  else if (n_ext <= 128)
+    hipLaunchKernelGGL(parity_sampled_kernel<2>, grid, block, lds, s, models, n_meas, shots, seed, vid0, ext, n_ext,
+                       (uint32_t)rounds, (uint32_t)use_lds, odd_counts);
+  else
+    hipLaunchKernelGGL(parity_sampled_kernel<4>, grid, block, lds, s, models, n_meas, shots, seed, vid0, ext, n_ext,
+                       (uint32_t)rounds, (uint32_t)use_lds, odd_counts);
   return hipGetLastError();
 }
 

@@ -3,19 +3,28 @@
 //
 // Variants of a fragment share everything but their preparations and their
 // final basis rotations.  A workgroup simulates the fragment for one
-// preparation combination (state in LDS, m <= 12 qubits: 64 KiB) and then
-// rotates the state into one basis combination (small grids: one workgroup
-// per preparation and basis combination) or, for large grids, into each
-// basis combination in turn on a copy, and writes that variant's outcome
-// distribution over the measured set.  Runs of one-qubit gates
-// arrive fused into single 2x2 unitaries (G_U2).  Each distribution entry is
-// reduced in a fixed order (deterministic).
+// preparation combination and then rotates the state into one basis
+// combination (small grids: one workgroup per preparation and basis
+// combination) or, for large grids, into each basis combination in turn on
+// a copy, and writes that variant's outcome distribution over the measured
+// set.
+//
+// The state lives in registers while the gates run: amplitude index bits
+// [0, RB) pick one of a thread's 2^RB registers, the next (up to) 6 bits the
+// lane, the top bits the wave (sv_shape).  The host lays the gate stream out
+// as a program over these bit positions (runs of one-qubit gates fused into
+// one 2x2 unitary): a gate along a register bit is arithmetic on the
+// thread's own registers, one along a lane bit exchanges amplitudes with the
+// partner lane, diagonal gates, CZ and CX controls need no data movement,
+// and a qubit needed on a wave bit is first swapped in through LDS (the only
+// workgroup barrier besides program staging).  At the end the state goes to
+// LDS in logical order for the basis rotations and the outcome sums.  Each
+// distribution entry is reduced in a fixed order (deterministic).
 #include "common.hpp"
 
 namespace ccut {
 
 namespace {
-
 
 struct C2 {
   double re, im;
@@ -27,174 +36,169 @@ __device__ inline C2 cadd(C2 a, C2 b) { return C2{a.re + b.re, a.im + b.im}; }
 // insert a zero bit at position t
 __device__ inline uint32_t ins0(uint32_t k, uint32_t t) { return ((k >> t) << (t + 1)) | (k & ((1u << t) - 1)); }
 
-__device__ void apply_gate(C2 *amp, uint32_t m, uint32_t kind, uint32_t a, uint32_t b, const double *mat) {
-  const uint32_t N = 1u << m;
-  const uint32_t half = N >> 1;
-  const uint32_t ma = 1u << a;
-  switch (kind) {
-    case G_U2: {
-      const C2 m00{mat[0], mat[1]}, m01{mat[2], mat[3]}, m10{mat[4], mat[5]}, m11{mat[6], mat[7]};
-      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
-        const C2 x = amp[i0], y = amp[i1];
-        amp[i0] = cadd(cmul(m00, x), cmul(m01, y));
-        amp[i1] = cadd(cmul(m10, x), cmul(m11, y));
-      }
-      break;
-    }
-    case G_H: {
-      const double r = 0.70710678118654752440;
-      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
-        const C2 x = amp[i0], y = amp[i1];
-        amp[i0] = C2{r * (x.re + y.re), r * (x.im + y.im)};
-        amp[i1] = C2{r * (x.re - y.re), r * (x.im - y.im)};
-      }
-      break;
-    }
-    case G_X:
-      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
-        const C2 x = amp[i0];
-        amp[i0] = amp[i1];
-        amp[i1] = x;
-      }
-      break;
-    case G_S: case G_SDG: {
-      const double s = kind == G_S ? 1.0 : -1.0;
-      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const uint32_t i1 = ins0(k, a) | ma;
-        const C2 x = amp[i1];
-        amp[i1] = C2{-s * x.im, s * x.re};
-      }
-      break;
-    }
-    case G_CX: {
-      const uint32_t mb = 1u << b;
-      for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const uint32_t i0 = ins0(k, b);
-        if (!(i0 & ma)) continue;
-        const uint32_t i1 = i0 | mb;
-        const C2 x = amp[i0];
-        amp[i0] = amp[i1];
-        amp[i1] = x;
-      }
-      break;
-    }
-    case G_CZ: {
-      const uint32_t mb = 1u << b;
-      for (uint32_t i = threadIdx.x; i < N; i += blockDim.x)
-        if ((i & ma) && (i & mb)) amp[i] = C2{-amp[i].re, -amp[i].im};
-      break;
-    }
-    default:
-      break;
+// Basis rotations on the state in LDS (H, S^dagger), one barrier each.
+__device__ void lds_h(C2 *amp, uint32_t m, uint32_t a) {
+  const uint32_t half = (1u << m) >> 1, ma = 1u << a;
+  const double r = 0.70710678118654752440;
+  for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const uint32_t i0 = ins0(k, a), i1 = i0 | ma;
+    const C2 x = amp[i0], y = amp[i1];
+    amp[i0] = C2{r * (x.re + y.re), r * (x.im + y.im)};
+    amp[i1] = C2{r * (x.re - y.re), r * (x.im - y.im)};
   }
   __syncthreads();
 }
 
-// The fused op stream (U2, CX, CZ and no-ops) on the state in LDS.  Each
-// thread owns PPT amplitude pairs of every op and issues all their loads
-// (and the op's 2x2 matrix, staged in LDS once per chunk of 16 ops) before
-// any arithmetic; one barrier per op.
-template <int PPT, int BS>
-__device__ void sv_run_ops(C2 *amp, uint32_t m, const FragDev &F, C2 *s_mats) {
-  const uint32_t half = (1u << m) >> 1;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t n16 = (F.n_ops + 15) / 16;
-  for (uint32_t g16 = 0; g16 < n16; ++g16) {
-    // (the previous op's barrier has retired every read of the last chunk)
-    if (tid < 64) s_mats[tid] = C2{F.mats[(size_t)g16 * 128 + 2 * tid], F.mats[(size_t)g16 * 128 + 2 * tid + 1]};
-    __syncthreads();
-    // one rolled op loop keeps the code small; the op word is a scalar load
-    // issued when no LDS access is outstanding
-#pragma unroll 1
-    for (int t = 0; t < 16; ++t) {
-      const uint32_t w = ((const g_u32 *)F.ops)[g16 * 16 + t];
-      const uint32_t kind = op_kind(w);
-      if (kind == G_NOP) continue;
-      const uint32_t a = op_q0(w), b = op_q1(w);
-      const uint32_t ma = 1u << a;
-      if (kind == G_U2) {
-        const C2 *M = s_mats + 4 * t;
-        const C2 m00 = M[0], m01 = M[1], m10 = M[2], m11 = M[3];
-        uint32_t i0[PPT];
-        double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
+__device__ void lds_sdg(C2 *amp, uint32_t m, uint32_t a) {
+  const uint32_t half = (1u << m) >> 1, ma = 1u << a;
+  for (uint32_t k = threadIdx.x; k < half; k += blockDim.x) {
+    const uint32_t i1 = ins0(k, a) | ma;
+    const C2 x = amp[i1];
+    amp[i1] = C2{x.im, -x.re};
+  }
+  __syncthreads();
+}
+
+constexpr uint32_t kStage = 64;  // program words staged in LDS at a time
+
+// Partner-lane exchange of a thread's R amplitudes for a lane-bit op:
+// lane ^ 1 and lane ^ 2 through DPP quad permutes (no LDS round trip),
+// other masks through ds_bpermute with the byte address (lane ^ mask) * 4.
+// All 4R moves of one op are issued back to back.
+template <int MODE>
+__device__ inline int xlane32(int v, int addr) {
+  if constexpr (MODE == 0) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  else if constexpr (MODE == 1) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+  else return __builtin_amdgcn_ds_bpermute(addr, v);
+}
+
+template <int R, int MODE>
+__device__ inline void xlane_all(const double *re, const double *im, double *yr, double *yi, int addr) {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          const uint32_t k = tid + p * BS;
-          i0[p] = ins0(k < half ? k : 0, a);
-          const C2 u = amp[i0[p]], v = amp[i0[p] | ma];
-          xr[p] = u.re;
-          xi[p] = u.im;
-          yr[p] = v.re;
-          yi[p] = v.im;
-        }
+  for (int r = 0; r < R; ++r) {
+    const uint64_t a = __builtin_bit_cast(uint64_t, re[r]), b = __builtin_bit_cast(uint64_t, im[r]);
+    const uint32_t a0 = (uint32_t)xlane32<MODE>((int)(uint32_t)a, addr);
+    const uint32_t a1 = (uint32_t)xlane32<MODE>((int)(uint32_t)(a >> 32), addr);
+    const uint32_t b0 = (uint32_t)xlane32<MODE>((int)(uint32_t)b, addr);
+    const uint32_t b1 = (uint32_t)xlane32<MODE>((int)(uint32_t)(b >> 32), addr);
+    yr[r] = __builtin_bit_cast(double, ((uint64_t)a1 << 32) | a0);
+    yi[r] = __builtin_bit_cast(double, ((uint64_t)b1 << 32) | b0);
+  }
+}
+
+template <int R>
+__device__ inline void xlane(const double *re, const double *im, double *yr, double *yi, uint32_t mask, int addr) {
+  if (mask == 1)
+    xlane_all<R, 0>(re, im, yr, yi, addr);
+  else if (mask == 2)
+    xlane_all<R, 1>(re, im, yr, yi, addr);
+  else
+    xlane_all<R, 2>(re, im, yr, yi, addr);
+}
+
+// c ? y : x on the bit patterns (exact, no branch)
+__device__ inline double pick(bool c, double y, double x) {
+  const uint64_t k = 0ull - (uint64_t)c;
+  return __builtin_bit_cast(double, (__builtin_bit_cast(uint64_t, y) & k) | (__builtin_bit_cast(uint64_t, x) & ~k));
+}
+
+// A 2x2 unitary along register bit P: pairs (r, r | 2^P) of this thread.
+template <int RB, int P>
+__device__ inline void u2_reg_at(double *re, double *im, C2 m00, C2 m01, C2 m10, C2 m11) {
+  if constexpr (P < RB) {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          if (tid + p * BS < half) {
-            const C2 x{xr[p], xi[p]}, y{yr[p], yi[p]};
-            amp[i0[p]] = cadd(cmul(m00, x), cmul(m01, y));
-            amp[i0[p] | ma] = cadd(cmul(m10, x), cmul(m11, y));
-          }
-        }
-      } else if (kind == G_CX) {
-        // swap the target pair where the control bit is set
-        const uint32_t mb = 1u << b;
-        uint32_t i0[PPT];
-        double xr[PPT], xi[PPT], yr[PPT], yi[PPT];
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          const uint32_t k = tid + p * BS;
-          i0[p] = ins0(k < half ? k : 0, b);
-          const C2 u = amp[i0[p]], v = amp[i0[p] | mb];
-          xr[p] = u.re;
-          xi[p] = u.im;
-          yr[p] = v.re;
-          yi[p] = v.im;
-        }
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          if (tid + p * BS < half && (i0[p] & ma)) {
-            amp[i0[p]] = C2{yr[p], yi[p]};
-            amp[i0[p] | mb] = C2{xr[p], xi[p]};
-          }
-        }
-      } else if (kind == G_CZ) {
-        const uint32_t mb = 1u << b;
-        for (uint32_t i = tid; i < 2 * half; i += BS)
-          if ((i & ma) && (i & mb)) amp[i] = C2{-amp[i].re, -amp[i].im};
-      }
-      __syncthreads();
+    for (int r = 0; r < (1 << RB); ++r) {
+      if (r & (1 << P)) continue;
+      const int s = r | (1 << P);
+      const C2 x{re[r], im[r]}, y{re[s], im[s]};
+      const C2 u = cadd(cmul(m00, x), cmul(m01, y)), v = cadd(cmul(m10, x), cmul(m11, y));
+      re[r] = u.re;
+      im[r] = u.im;
+      re[s] = v.re;
+      im[s] = v.im;
     }
   }
 }
 
+template <int RB>
+__device__ inline void u2_reg(double *re, double *im, uint32_t p, C2 m00, C2 m01, C2 m10, C2 m11) {
+  switch (p) {
+    case 0: u2_reg_at<RB, 0>(re, im, m00, m01, m10, m11); break;
+    case 1: u2_reg_at<RB, 1>(re, im, m00, m01, m10, m11); break;
+    case 2: u2_reg_at<RB, 2>(re, im, m00, m01, m10, m11); break;
+    case 3: u2_reg_at<RB, 3>(re, im, m00, m01, m10, m11); break;
+    default: break;
+  }
+}
+
+// CX with its target on register bit P; `base` is the index of register 0.
+template <int RB, int P>
+__device__ inline void cx_reg_at(double *re, double *im, uint32_t base, uint32_t ctrl) {
+  if constexpr (P < RB) {
+#pragma unroll
+    for (int r = 0; r < (1 << RB); ++r) {
+      if (r & (1 << P)) continue;
+      const int s = r | (1 << P);
+      const bool c = ((base | (uint32_t)r) >> ctrl) & 1u;
+      const double xr = re[r], xi = im[r], yr = re[s], yi = im[s];
+      re[r] = pick(c, yr, xr);
+      im[r] = pick(c, yi, xi);
+      re[s] = pick(c, xr, yr);
+      im[s] = pick(c, xi, yi);
+    }
+  }
+}
+
+template <int RB>
+__device__ inline void cx_reg(double *re, double *im, uint32_t base, uint32_t ctrl, uint32_t p) {
+  switch (p) {
+    case 0: cx_reg_at<RB, 0>(re, im, base, ctrl); break;
+    case 1: cx_reg_at<RB, 1>(re, im, base, ctrl); break;
+    case 2: cx_reg_at<RB, 2>(re, im, base, ctrl); break;
+    case 3: cx_reg_at<RB, 3>(re, im, base, ctrl); break;
+    default: break;
+  }
+}
+
 // split_bc: workgroup x runs preparation combination x / 3^n_out and only
-// basis combination x mod 3^n_out (rotating its own state in place), so the
-// basis combinations run side by side; otherwise workgroup x runs
-// preparation combination x and every basis combination on a copy.
-template <int PPT, int BS>
-__global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
-  extern __shared__ C2 smem_amp[];
-  __shared__ C2 s_mats[64];
+// basis combination x mod 3^n_out (rotating its own state in place);
+// otherwise workgroup x runs preparation combination x and every basis
+// combination on a copy.  blockDim.x = 64 * 2^wb (sv_shape), RB register
+// bits per thread.
+template <int RB>
+__global__ __launch_bounds__(256) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
+  constexpr int R = 1 << RB;
+  extern __shared__ C2 smem[];
   const uint32_t m = F.m;
   const uint32_t N = 1u << m;
-  const uint32_t tid = threadIdx.x;
-  C2 *base = smem_amp;
-  // preparation combination of this workgroup: digits of the input axes
+  const uint32_t BS = blockDim.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  C2 *buf0 = smem, *buf1 = smem + N;
+  uint32_t *s_words = reinterpret_cast<uint32_t *>(smem + 2 * N);
+  double *s_mats = reinterpret_cast<double *>(s_words + kStage + 2);  // 8-byte aligned
+  const uint32_t base = (wave << (RB + 6)) | (lane << RB);  // index of register 0
+  const bool live = base < N;  // fewer than 64 amplitudes: the upper lanes idle
   uint32_t n_out = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
   uint32_t n_bc = 1;
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   const uint32_t prep = split_bc ? blockIdx.x / n_bc : blockIdx.x;
   const uint32_t bc0 = split_bc ? blockIdx.x % n_bc : 0, bc1 = split_bc ? bc0 + 1 : n_bc;
-  const bool copy = n_out && !split_bc;
-  C2 *work = copy ? smem_amp + N : smem_amp;
-  for (uint32_t i = tid; i < N; i += BS) base[i] = C2{i == 0 ? 1.0 : 0.0, 0.0};
-  __syncthreads();
+
+  // prepared product state: |0>, |1>, |+> = H|0> or |+i> = S H|0> on each
+  // quantum input (digit of this preparation combination), |0> elsewhere
+  double re[R], im[R];
   uint64_t vin = 0;  // variant index contribution of the input digits
   {
+    uint32_t imask = 0;
+    for (uint32_t j = 0; j < F.n_axes; ++j)
+      if (F.axis_side[j] == 1) imask |= 1u << F.axis_local[j];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      re[r] = live && !((base | (uint32_t)r) & ~imask) ? 1.0 : 0.0;
+      im[r] = 0.0;
+    }
+    const double h = 0.70710678118654752440;
     uint64_t pc = prep, stride = 1;
     for (uint32_t j = 0; j < F.n_axes; ++j) {
       if (F.axis_side[j] == 1) {
@@ -202,17 +206,168 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
         pc >>= 2;
         vin += d * stride;
         const uint32_t q = F.axis_local[j];
-        if (d == 1) {
-          apply_gate(base, m, G_X, q, 0, nullptr);
-        } else if (d >= 2) {  // |+> = H|0>, |+i> = S H|0>
-          apply_gate(base, m, G_H, q, 0, nullptr);
-          if (d == 3) apply_gate(base, m, G_S, q, 0, nullptr);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const bool b = ((base | (uint32_t)r) >> q) & 1u;
+          if (d == 0 && b) re[r] = im[r] = 0.0;
+          if (d == 1 && !b) re[r] = im[r] = 0.0;
+          if (d >= 2) {
+            const double xr = re[r] * h, xi = im[r] * h;
+            const bool rot = d == 3 && b;  // times i
+            re[r] = rot ? -xi : xr;
+            im[r] = rot ? xr : xi;
+          }
         }
       }
       stride *= F.axis_radix[j];
     }
   }
-  sv_run_ops<PPT, BS>(base, m, F, s_mats);
+
+  // the program
+  uint64_t layout = 0;
+  for (uint32_t q = 0; q < m; ++q) layout |= (uint64_t)q << (4 * q);
+  uint32_t cur = 0;  // swap buffer of the next SV_SWAP
+  for (uint32_t c0 = 0; c0 < F.n_ops; c0 += kStage) {
+    const uint32_t cn = min(kStage, F.n_ops - c0);
+    // every load of a thread is issued before its first store (one memory
+    // latency per chunk); blockDim >= 64 = kStage
+    const uint32_t wt = tid < cn ? F.ops[c0 + tid] : 0u;
+    double mt[8 * kStage / 64];
+#pragma unroll
+    for (uint32_t k = 0; k < 8 * kStage / 64; ++k) {
+      const uint32_t i = tid + k * BS;
+      mt[k] = i < 8 * cn ? F.mats[(size_t)8 * c0 + i] : 0.0;
+    }
+    __syncthreads();  // every wave is done with the previous chunk
+    if (tid < cn) s_words[tid] = wt;
+#pragma unroll
+    for (uint32_t k = 0; k < 8 * kStage / 64; ++k) {
+      const uint32_t i = tid + k * BS;
+      if (i < 8 * cn) s_mats[i] = mt[k];
+    }
+    __syncthreads();
+    // op t + 1 (word and matrix) is read from LDS while op t runs; the
+    // staging area has one spare entry for the read past the chunk's end
+    uint32_t wn = s_words[0];
+    double Mn[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Mn[e] = s_mats[e];
+#pragma unroll 1
+    for (uint32_t t = 0; t < cn; ++t) {
+      const uint32_t w = __builtin_amdgcn_readfirstlane(wn);
+      double M[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) M[e] = Mn[e];
+      wn = s_words[t + 1];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Mn[e] = s_mats[8 * (t + 1) + e];
+      const uint32_t kind = op_kind(w), a = op_q0(w), b = op_q1(w);
+      switch (kind) {
+        case SV_U2: {
+          const C2 m00{M[0], M[1]}, m01{M[2], M[3]}, m10{M[4], M[5]}, m11{M[6], M[7]};
+          if (a < (uint32_t)RB) {
+            u2_reg<RB>(re, im, a, m00, m01, m10, m11);
+          } else {
+            const uint32_t mask = 1u << (a - RB);
+            const int addr = (int)((lane ^ mask) << 2);
+            const bool hi = lane & mask;
+            const C2 k0 = hi ? m11 : m00, k1 = hi ? m10 : m01;  // own and partner coefficients
+            double yr[R], yi[R];
+            xlane<R>(re, im, yr, yi, mask, addr);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const C2 u = cadd(cmul(k0, C2{re[r], im[r]}), cmul(k1, C2{yr[r], yi[r]}));
+              re[r] = u.re;
+              im[r] = u.im;
+            }
+          }
+          break;
+        }
+        case SV_DIAG: {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const bool c = ((base | (uint32_t)r) >> a) & 1u;
+            const C2 d{pick(c, M[6], M[0]), pick(c, M[7], M[1])};
+            const C2 u = cmul(d, C2{re[r], im[r]});
+            re[r] = u.re;
+            im[r] = u.im;
+          }
+          break;
+        }
+        case SV_CX: {
+          if (b < (uint32_t)RB) {
+            cx_reg<RB>(re, im, base, a, b);
+          } else {
+            const uint32_t mask = 1u << (b - RB);
+            const int addr = (int)((lane ^ mask) << 2);
+            double yr[R], yi[R];
+            xlane<R>(re, im, yr, yi, mask, addr);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const bool c = ((base | (uint32_t)r) >> a) & 1u;
+              re[r] = pick(c, yr[r], re[r]);
+              im[r] = pick(c, yi[r], im[r]);
+            }
+          }
+          break;
+        }
+        case SV_CZ: {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const uint32_t i = base | (uint32_t)r;
+            const bool c = (i >> a) & (i >> b) & 1u;
+            re[r] = pick(c, -re[r], re[r]);
+            im[r] = pick(c, -im[r], im[r]);
+          }
+          break;
+        }
+        case SV_SWAP: {
+          // amplitude i moves to i with bits a and b exchanged
+          C2 *B = cur ? buf1 : buf0;
+          if (live) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const uint32_t i = base | (uint32_t)r;
+              const uint32_t x = ((i >> a) ^ (i >> b)) & 1u;
+              B[i ^ ((x << a) | (x << b))] = C2{re[r], im[r]};
+            }
+          }
+          __syncthreads();
+          if (live) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const C2 v = B[base | (uint32_t)r];
+              re[r] = v.re;
+              im[r] = v.im;
+            }
+          }
+          cur ^= 1u;  // the next swap writes the other buffer, so no second barrier
+          break;
+        }
+        case SV_END:
+          layout = (uint64_t)__double_as_longlong(M[0]);
+          break;
+        default:
+          break;
+      }
+    }
+  }
+  // the state to LDS in logical order: bit q of the logical index is the
+  // physical bit at position layout[q]
+  C2 *S = cur ? buf1 : buf0;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = base | (uint32_t)r;
+      uint32_t L = 0;
+      for (uint32_t q = 0; q < m; ++q) L |= ((i >> ((layout >> (4 * q)) & 15u)) & 1u) << q;
+      S[L] = C2{re[r], im[r]};
+    }
+  }
+  __syncthreads();
+  const bool copy = n_out && !split_bc;
+  C2 *work = copy ? (cur ? buf0 : buf1) : S;
+
   // outcome distribution of every basis combination
   const uint32_t nm = F.n_meas;
   uint32_t mmask = 0;
@@ -220,7 +375,7 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
   const uint32_t outs = 1u << nm;
   for (uint32_t bc = bc0; bc < bc1; ++bc) {
     if (copy) {
-      for (uint32_t i = tid; i < N; i += BS) work[i] = base[i];
+      for (uint32_t i = tid; i < N; i += BS) work[i] = S[i];
       __syncthreads();
     }
     uint64_t v = vin;
@@ -233,20 +388,21 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
           t /= 3;
           v += d * stride;
           const uint32_t q = F.axis_local[j];
-          if (d == 1) apply_gate(work, m, G_SDG, q, 0, nullptr);
-          if (d <= 1) apply_gate(work, m, G_H, q, 0, nullptr);
+          if (d == 1) lds_sdg(work, m, q);
+          if (d <= 1) lds_h(work, m, q);
         }
         stride *= F.axis_radix[j];
       }
     }
     double *out = dist + v * outs;
-    // outcome probabilities: |amp|^2 in place (reusing the work buffer as
-    // N doubles), then a pairwise sum over each unmeasured qubit in turn
-    // (fixed order, one barrier per qubit); the entry of outcome o is left
-    // at the index with o's bits on the measured qubits and zeros elsewhere
-    double pr[((1 << kMaxNcQubits) / BS)];
+    // outcome probabilities: |amp|^2 in place (the work buffer as N
+    // doubles; N = BS * R, so each thread holds at most R of them), then a
+    // pairwise sum over each unmeasured qubit in turn (fixed order, one
+    // barrier per qubit); the entry of outcome o is left at the index with
+    // o's bits on the measured qubits and zeros elsewhere
+    double pr[R];
 #pragma unroll
-    for (int j = 0; j < ((1 << kMaxNcQubits) / BS); ++j) {
+    for (int j = 0; j < R; ++j) {
       const uint32_t i = tid + j * BS;
       pr[j] = 0.0;
       if (i < N) pr[j] = work[i].re * work[i].re + work[i].im * work[i].im;
@@ -254,7 +410,7 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
     __syncthreads();
     double *P = reinterpret_cast<double *>(work);
 #pragma unroll
-    for (int j = 0; j < ((1 << kMaxNcQubits) / BS); ++j) {
+    for (int j = 0; j < R; ++j) {
       const uint32_t i = tid + j * BS;
       if (i < N) P[i] = pr[j];
     }
@@ -280,7 +436,7 @@ __global__ __launch_bounds__(BS) void sv_kernel(const FragDev F, double *__restr
 }  // namespace
 
 hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
-  if (h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
+  if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
   uint32_t n_in = 0, n_out = 0;
   for (uint32_t j = 0; j < h.n_axes; ++j) (h.axis_side[j] ? n_in : n_out) += 1;
   // basis combinations get workgroups of their own while the grid stays
@@ -290,17 +446,26 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   const uint64_t n_prep = 1ull << (2 * n_in);
   const bool split = n_out && n_prep * n_bc <= 512;
-  const size_t lds = (size_t(1) << h.m) * sizeof(C2) * (n_out && !split ? 2 : 1);
-  // one workgroup per preparation combination, sized to the state: 256
-  // threads up to 9 qubits, then 512, then 1024 (several waves per SIMD
-  // hide the LDS and fp64 latency); PPT amplitude pairs per thread per op
-  auto kern = h.m <= 9 ? sv_kernel<1, 256> : h.m == 10 ? sv_kernel<1, 512> : h.m == 11 ? sv_kernel<1, 1024>
-                                                                                   : sv_kernel<2, 1024>;
-  const int bs = h.m <= 9 ? 256 : h.m == 10 ? 512 : 1024;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const SvShape sh = sv_shape(h.m);
+  const uint32_t bs = 64u << sh.wb;
+  // two state buffers (swaps alternate between them; the copy mode uses the
+  // second for the rotated copy) and the staged program chunk
+  const size_t lds = (size_t(2) << h.m) * sizeof(C2) + (kStage + 2) * 4 + (kStage + 1) * 8 * sizeof(double);
+  const void *kern = sh.rb == 0   ? (const void *)sv_kernel<0>
+                     : sh.rb == 1 ? (const void *)sv_kernel<1>
+                     : sh.rb == 2 ? (const void *)sv_kernel<2>
+                     : sh.rb == 3 ? (const void *)sv_kernel<3>
+                                  : (const void *)sv_kernel<4>;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(split ? n_prep * n_bc : n_prep)), dim3(bs), lds, s, h, dist,
-                     (uint32_t)split);
+  const dim3 grid((unsigned)(split ? n_prep * n_bc : n_prep)), block(bs);
+  switch (sh.rb) {
+    case 0: hipLaunchKernelGGL(sv_kernel<0>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    case 1: hipLaunchKernelGGL(sv_kernel<1>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    case 2: hipLaunchKernelGGL(sv_kernel<2>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    case 3: hipLaunchKernelGGL(sv_kernel<3>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    default: hipLaunchKernelGGL(sv_kernel<4>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+  }
   return hipGetLastError();
 }
 

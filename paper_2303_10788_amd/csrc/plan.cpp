@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <set>
@@ -94,6 +96,76 @@ void fuse_one_qubit_runs(Fragment &F) {
     }
   }
   for (uint32_t q = 0; q < m; ++q) flush(q);
+}
+
+// Lay the fused stream out for the register-resident state-vector kernel
+// (positions as in sv_shape).  Qubit q starts at position q.  Before an op
+// that mixes amplitudes along a qubit that sits at a wave position, that
+// qubit swaps places with the register or lane qubit whose next such use
+// lies furthest ahead (Belady's rule), so swaps stay rare.  One-qubit
+// unitaries with zero off-diagonal entries become SV_DIAG, which runs at any
+// position.  The program ends with SV_END carrying the final layout.
+void build_sv_program(Fragment &F) {
+  const uint32_t m = F.m();
+  const SvShape sh = sv_shape(m);
+  const uint32_t inner = sh.rb + sh.lb;  // positions below this are register or lane bits
+  const size_t n = F.sv_words.size();
+  std::vector<int32_t> need(n, -1);
+  std::vector<char> diag(n, 0);
+  for (size_t g = 0; g < n; ++g) {
+    const uint32_t w = F.sv_words[g], k = op_kind(w);
+    if (k == G_U2) {
+      const double *M = &F.sv_mats[8 * g];
+      diag[g] = M[2] == 0.0 && M[3] == 0.0 && M[4] == 0.0 && M[5] == 0.0;
+      if (!diag[g]) need[g] = (int32_t)op_q0(w);
+    } else if (k == G_CX) {
+      need[g] = (int32_t)op_q1(w);  // the target
+    }
+  }
+  std::vector<std::vector<size_t>> uses(m);
+  for (size_t g = 0; g < n; ++g)
+    if (need[g] >= 0) uses[need[g]].push_back(g);
+  std::vector<size_t> next(m, 0);
+  auto next_use = [&](uint32_t q, size_t g) {  // first use after op g
+    while (next[q] < uses[q].size() && uses[q][next[q]] <= g) ++next[q];
+    return next[q] < uses[q].size() ? uses[q][next[q]] : SIZE_MAX;
+  };
+  std::vector<uint32_t> pos(m), at(m);
+  for (uint32_t q = 0; q < m; ++q) pos[q] = at[q] = q;
+  auto emit = [&](uint32_t kind, uint32_t a, uint32_t b, const double *M) {
+    F.sv_prog.push_back(pack_op(kind, a, b));
+    for (int t = 0; t < 8; ++t) F.sv_prog_mats.push_back(M ? M[t] : 0.0);
+  };
+  for (size_t g = 0; g < n; ++g) {
+    const uint32_t w = F.sv_words[g], k = op_kind(w), a = op_q0(w), b = op_q1(w);
+    if (k != G_U2 && k != G_CX && k != G_CZ) continue;
+    if (need[g] >= 0 && pos[need[g]] >= inner) {
+      const uint32_t q = (uint32_t)need[g];
+      uint32_t victim = 0;
+      size_t far = 0;
+      for (uint32_t p = 0; p < inner; ++p) {
+        const size_t u = next_use(at[p], g);
+        if (p == 0 || u > far) {
+          far = u;
+          victim = p;
+        }
+      }
+      const uint32_t pw = pos[q], qv = at[victim];
+      emit(SV_SWAP, victim, pw, nullptr);
+      std::swap(at[victim], at[pw]);
+      pos[q] = victim;
+      pos[qv] = pw;
+    }
+    if (k == G_U2)
+      emit(diag[g] ? SV_DIAG : SV_U2, pos[a], 0, &F.sv_mats[8 * g]);
+    else
+      emit(k == G_CX ? SV_CX : SV_CZ, pos[a], pos[b], nullptr);
+  }
+  uint64_t layout = 0;
+  for (uint32_t q = 0; q < m; ++q) layout |= (uint64_t)pos[q] << (4 * q);
+  double M[8] = {};
+  std::memcpy(&M[0], &layout, 8);
+  emit(SV_END, 0, 0, M);
 }
 
 // Order a Clifford stream by ASAP layer: op g goes one layer after the
@@ -309,10 +381,12 @@ int build_plan(uint32_t n, const HostOp *ops, size_t n_ops, const uint32_t *cut_
       return CCUT_E_UNSUPPORTED;
     }
     F.n_variants = nv;
-    if (!F.clifford)
+    if (!F.clifford) {
       fuse_one_qubit_runs(F);
-    else
+      if (F.m() <= (uint32_t)kMaxNcQubits) build_sv_program(F);
+    } else {
       fuse_clifford_runs(F);
+    }
     if (!F.clifford && F.m() > max_nc) {
       err = "non-Clifford fragment " + std::to_string(F.index) + " has " + std::to_string(F.m()) +
             " qubits > max_nc_qubits = " + std::to_string(max_nc);
@@ -368,7 +442,7 @@ FragRequest zstring_request(const Fragment &f, const std::vector<uint64_t> &anym
 FragDev make_frag_dev(const Fragment &f, const FragRequest &r, uint64_t vid_base) {
   FragDev d{};
   d.m = f.m();
-  d.n_ops = (uint32_t)(f.clifford ? f.cl_words.size() : f.sv_words.size());
+  d.n_ops = (uint32_t)(f.clifford ? f.cl_words.size() : f.sv_prog.size());
   d.n_axes = (uint32_t)f.axes.size();
   d.n_meas = (uint32_t)r.meas.size();
   d.n_req = (uint32_t)r.req_pos.size();

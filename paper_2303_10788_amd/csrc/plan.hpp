@@ -41,6 +41,10 @@ struct Fragment {
   // qubit fused into one 2x2 unitary (G_U2) for the state-vector kernel
   std::vector<uint32_t> sv_words;
   std::vector<double> sv_mats;              // 8 doubles per sv word
+  // the same stream laid out for the state-vector kernel (SV_* words, 8
+  // doubles per word)
+  std::vector<uint32_t> sv_prog;
+  std::vector<double> sv_prog_mats;
   bool clifford = true;
   std::vector<Axis> axes;
   std::vector<int32_t> out_local;           // per wire: local qubit if this fragment ends the wire, else -1

@@ -138,6 +138,32 @@ def test_variant_tables_random(ctx, seed):
                 assert np.abs(Tg - Te).max() <= 1e-12, (seed, f, method)
 
 
+@pytest.mark.parametrize("m,mirrored", [(m, mir) for m in (5, 6, 7, 8, 9, 10, 11, 12) for mir in (False, True)])
+def test_variant_tables_wide_nc(ctx, m, mirrored):
+    """Non-Clifford fragments of every register/lane/wave layout (5 to 12
+    qubits; from 9 qubits on some qubits sit on wave bits and are swapped
+    in), with the cut wires as quantum outputs or, mirrored, as inputs."""
+    n = m + 5
+    exits = [1, m - 1] if m > 2 else [m - 1]
+    blocks = [W.Block(list(range(m)), exits)]
+    ops, cuts = W.block_circuit(n, 30, blocks, t_c=15, p_cx=0.4, seed=700 + m, n_t=5, mirrored=mirrored)
+    qubits = [0, 2, m - 2, m, n - 1] if m > 3 else [0, m, n - 1]
+    qubits = sorted(set(q for q in qubits if q < n))
+    _log(f"wide NC m={m} mirrored={mirrored}")
+    plan = _plan(ctx, n, ops, cuts)
+    frags = C.fragment_circuit(n, ops, cuts)
+    seen = 0
+    for f, fr in enumerate(frags):
+        if fr.clifford:
+            continue
+        seen = max(seen, fr.m)
+        req = C.make_request(fr, qubits)
+        exp = C.variant_distributions(fr, req.meas)
+        got = plan.variant_tables(qubits, f)
+        assert np.abs(got - exp).max() <= 1e-12, (m, mirrored, f)
+    assert seen == m
+
+
 # ------------------------------------------------------------ marginals
 
 def test_tiny_exact_marginal(ctx):
