@@ -30,11 +30,12 @@ enum : uint32_t {
 struct SvShape {
   uint32_t rb, lb, wb;  // register, lane and wave bits
 };
+// At most 4 amplitudes per thread (more spill registers); from 9 qubits on
+// the state spreads over 2^(m - 8) waves, up to 16 (1024 threads).
 __host__ __device__ inline SvShape sv_shape(uint32_t m) {
   if (m <= 6) return {0u, m, 0u};
   if (m <= 8) return {m - 6, 6u, 0u};
-  if (m <= 10) return {2u, 6u, m - 8};
-  return {m - 8, 6u, 2u};
+  return {2u, 6u, m - 8};
 }
 constexpr int kMaxTableBits = 24;
 

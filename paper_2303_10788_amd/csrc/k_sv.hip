@@ -125,8 +125,6 @@ __device__ inline void u2_reg(double *re, double *im, uint32_t p, C2 m00, C2 m01
   switch (p) {
     case 0: u2_reg_at<RB, 0>(re, im, m00, m01, m10, m11); break;
     case 1: u2_reg_at<RB, 1>(re, im, m00, m01, m10, m11); break;
-    case 2: u2_reg_at<RB, 2>(re, im, m00, m01, m10, m11); break;
-    case 3: u2_reg_at<RB, 3>(re, im, m00, m01, m10, m11); break;
     default: break;
   }
 }
@@ -154,8 +152,6 @@ __device__ inline void cx_reg(double *re, double *im, uint32_t base, uint32_t ct
   switch (p) {
     case 0: cx_reg_at<RB, 0>(re, im, base, ctrl); break;
     case 1: cx_reg_at<RB, 1>(re, im, base, ctrl); break;
-    case 2: cx_reg_at<RB, 2>(re, im, base, ctrl); break;
-    case 3: cx_reg_at<RB, 3>(re, im, base, ctrl); break;
     default: break;
   }
 }
@@ -163,10 +159,10 @@ __device__ inline void cx_reg(double *re, double *im, uint32_t base, uint32_t ct
 // split_bc: workgroup x runs preparation combination x / 3^n_out and only
 // basis combination x mod 3^n_out (rotating its own state in place);
 // otherwise workgroup x runs preparation combination x and every basis
-// combination on a copy.  blockDim.x = 64 * 2^wb (sv_shape), RB register
-// bits per thread.
+// combination on a copy.  blockDim.x = 64 * 2^wb (sv_shape, up to 1024),
+// RB register bits per thread.
 template <int RB>
-__global__ __launch_bounds__(256) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
+__global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
   constexpr int R = 1 << RB;
   extern __shared__ C2 smem[];
   const uint32_t m = F.m;
@@ -451,20 +447,16 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   // two state buffers (swaps alternate between them; the copy mode uses the
   // second for the rotated copy) and the staged program chunk
   const size_t lds = (size_t(2) << h.m) * sizeof(C2) + (kStage + 2) * 4 + (kStage + 1) * 8 * sizeof(double);
-  const void *kern = sh.rb == 0   ? (const void *)sv_kernel<0>
+  const void *kern = sh.rb == 0 ? (const void *)sv_kernel<0>
                      : sh.rb == 1 ? (const void *)sv_kernel<1>
-                     : sh.rb == 2 ? (const void *)sv_kernel<2>
-                     : sh.rb == 3 ? (const void *)sv_kernel<3>
-                                  : (const void *)sv_kernel<4>;
+                                  : (const void *)sv_kernel<2>;
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)(split ? n_prep * n_bc : n_prep)), block(bs);
   switch (sh.rb) {
     case 0: hipLaunchKernelGGL(sv_kernel<0>, grid, block, lds, s, h, dist, (uint32_t)split); break;
     case 1: hipLaunchKernelGGL(sv_kernel<1>, grid, block, lds, s, h, dist, (uint32_t)split); break;
-    case 2: hipLaunchKernelGGL(sv_kernel<2>, grid, block, lds, s, h, dist, (uint32_t)split); break;
-    case 3: hipLaunchKernelGGL(sv_kernel<3>, grid, block, lds, s, h, dist, (uint32_t)split); break;
-    default: hipLaunchKernelGGL(sv_kernel<4>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    default: hipLaunchKernelGGL(sv_kernel<2>, grid, block, lds, s, h, dist, (uint32_t)split); break;
   }
   return hipGetLastError();
 }
