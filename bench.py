@@ -188,16 +188,8 @@ def main():
     nc = [f for f in frags if not f["clifford"]]
     cl = [f for f in frags if f["clifford"]]
     # algorithmic work per step (both calls), as stated in the design notes
-    sv_flops = 0.0
-    for f in nc:
-        n_in = sum(1 for a in f["axes"] if a[1] == 1)
-        n_out = len(f["axes"]) - n_in
-        N = 1 << f["m"]
-        # per preparation combination: 28 flops per amplitude pair of each fused
-        # 2x2 unitary; per basis combination: |a|^2 (3 flops per amplitude) and
-        # the pairwise sums over the unmeasured qubits (N/2 adds each)
-        n_meas = n_out  # the mid request measures only the quantum outputs here
-        sv_flops += 2 * (4 ** n_in) * (f["n_one"] * 14 * N + (3 ** n_out) * (3 * N + (f["m"] - n_meas) * N // 2))
+    # the marginal and the Z-string call each run the state-vector pass once
+    sv_work = sv_flops(cc, plan, frags, w.qubits) + sv_flops(cc, plan, frags, _mask_qubits(masks, w.n))
     tab_ops = 0.0
     for f in cl:
         rw = (2 * f["m"] + 1 + 63) // 64
@@ -205,7 +197,7 @@ def main():
         # (CX, CZ) 64-bit operations, i.e. 22 or 12 int32 operations
         tab_ops += 2 * f["n_variants"] * rw * (22 * f["n_one"] + 12 * f["n_two"])
     work = {
-        "sv_kernel": (sv_flops, "fp64", PEAK_FP64, "GFLOP/s"),
+        "sv_kernel": (sv_work, "fp64", PEAK_FP64, "GFLOP/s"),
         "tableau_kernel": (tab_ops, "alu", PEAK_INT32_OPS, "Gop/s"),
         # per shot: a Philox call per 4 shots and 32 measurement indices, then one
         # AND + POPCOUNT + accumulate per Z string
@@ -239,6 +231,31 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def sv_flops(cc, plan, frags, qubits):
+    """Algorithmic fp64 flops of one state-vector pass over the non-Clifford
+    fragments of a request: per preparation combination 28 flops per
+    amplitude pair of each fused one-qubit unitary; per (preparation, basis)
+    combination 3 flops per amplitude for |a|^2 and N/2 adds per unmeasured
+    qubit."""
+    total = 0.0
+    for f, fr in enumerate(frags):
+        if fr["clifford"]:
+            continue
+        n_in = sum(1 for a in fr["axes"] if a[1] == 1)
+        n_out = len(fr["axes"]) - n_in
+        N = 1 << fr["m"]
+        n_meas, _ = cc.ccut_request_info(plan.handle, qubits, f)
+        total += (4 ** n_in) * (fr["n_one"] * 14 * N + (3 ** n_out) * (3 * N + (fr["m"] - n_meas) * N // 2))
+    return total
+
+
+def _mask_qubits(masks, n):
+    """Circuit qubits that occur in any Z-string mask ([strings][words])."""
+    import numpy as np
+    anym = np.bitwise_or.reduce(np.asarray(masks, dtype=np.uint64), axis=0)
+    return [q for q in range(n) if (int(anym[q >> 6]) >> (q & 63)) & 1]
 
 
 def _kernel_pass(ctx, fn, steps):
@@ -288,7 +305,28 @@ def bench_batching(args):
     dt = _timed(lambda: batch.run(outs), args.steps, args.warmup)
     eager = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=2000, use_graph=False)
     dt_eager = _timed(lambda: eager.run(outs), args.steps, args.warmup)
+    # per-kernel times from eager runs with event timing (a graph replay records no events)
+    times = _kernel_pass(ctx, lambda: eager.run(outs), args.steps)
     n_var = sum(f["n_variants"] for p in plans for f in p.fragments() if f["clifford"])
+    sv_work = sum(sv_flops(cc, p, p.fragments(), w.qubits) for p, w in zip(plans, ws))
+    n_meas_tot = 0
+    for p, w in zip(plans, ws):
+        for f, fr in enumerate(p.fragments()):
+            if fr["clifford"]:
+                n_meas_tot += fr["n_variants"] * cc.ccut_request_info(p.handle, w.qubits, f)[0]
+    work = {
+        "sv_kernel": (sv_work, "fp64", PEAK_FP64, "GFLOP/s"),
+        # per shot: Philox share + one select-and-xor per measurement + a histogram increment
+        "sample_kernel": (shots * (n_var * (PHILOX_OPS / 4 + 1) + 3 * n_meas_tot), "alu", PEAK_INT32_OPS, "Gop/s"),
+    }
+    name, (launches, total_ms) = max(((k, v) for k, v in times.items() if k in work), key=lambda kv: kv[1][1])
+    units, bound, peak, unit = work[name]
+    per_step_launches = launches / args.steps
+    achieved = units / (total_ms / args.steps / 1e3)  # summed launch durations of one step
+    roof = {"bound": bound, "kernel": name, "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "avg_launch_us": total_ms / max(launches, 1) * 1e3,
+            "launches_per_step": per_step_launches,
+            "note": "work of all launches of one step over their summed durations (eager run, HIP events)"}
     shots_per_step = n_var * shots
     line = {
         "metric": METRIC, "value": shots_per_step / (dt / args.steps), "unit": "shots/s", "n_gpus": 1,
@@ -298,8 +336,8 @@ def bench_batching(args):
                                "1e4 shots per variant, 16-qubit marginals, one graph-captured batch",
                    "clifford_variants": n_var, "shots_per_step": shots_per_step},
         "batch": dict(info, create_s=t_create, eager_ms_per_step=1e3 * dt_eager / args.steps),
-        "roofline": {"bound": "alu", "kernel": "tableau_batch_kernel", "achieved": None, "peak": PEAK_INT32_OPS / 1e9,
-                     "unit": "Gop/s", "frac": None, "traffic": None, "avg_launch_us": info["tableau_ms"] * 1e3},
+        "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
+        "roofline": roof,
     }
     print(json.dumps(line), flush=True)
 

@@ -1356,14 +1356,15 @@ struct BatchScope {
   ccut_batch *b;
   hipStream_t saved_stream;
   bool saved_timing, saved_aux;
-  BatchScope(ccut_batch *bb) : c(bb->ctx), b(bb) {
+  // timing: keep kernel timing on (eager runs only; a capture records no events)
+  BatchScope(ccut_batch *bb, bool timing = false) : c(bb->ctx), b(bb) {
     std::swap(c->arena, b->arena);
     std::swap(c->staged, b->staged);
     saved_stream = c->stream;
     saved_timing = c->timing;
     saved_aux = c->use_aux;
     c->stream = c->cur = b->stream;
-    c->timing = false;
+    c->timing = timing && saved_timing;
     c->use_aux = false;
   }
   ~BatchScope() {
@@ -1600,7 +1601,7 @@ ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_devic
   if (b->graphed) {
     HIP_TRY(c, hipGraphLaunch(b->exec, b->stream));
   } else {
-    BatchScope scope(b);
+    BatchScope scope(b, true);
     c->replay_uploads = true;
     ccut_status st = batch_enqueue(b, false);
     if (st != CCUT_OK) return st;

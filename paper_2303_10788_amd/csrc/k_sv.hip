@@ -170,8 +170,7 @@ __global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__res
   const uint32_t BS = blockDim.x;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   C2 *buf0 = smem, *buf1 = smem + N;
-  uint32_t *s_words = reinterpret_cast<uint32_t *>(smem + 2 * N);
-  double *s_mats = reinterpret_cast<double *>(s_words + kStage + 2);  // 8-byte aligned
+  double *s_mats = reinterpret_cast<double *>(smem + 2 * N);
   const uint32_t base = (wave << (RB + 6)) | (lane << RB);  // index of register 0
   const bool live = base < N;  // fewer than 64 amplitudes: the upper lanes idle
   uint32_t n_out = 0;
@@ -225,9 +224,10 @@ __global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__res
   uint32_t cur = 0;  // swap buffer of the next SV_SWAP
   for (uint32_t c0 = 0; c0 < F.n_ops; c0 += kStage) {
     const uint32_t cn = min(kStage, F.n_ops - c0);
-    // every load of a thread is issued before its first store (one memory
-    // latency per chunk); blockDim >= 64 = kStage
-    const uint32_t wt = tid < cn ? F.ops[c0 + tid] : 0u;
+    // lane t of every wave holds op word t of the chunk (read with
+    // readlane: no LDS round trip per op); the matrices are staged in LDS
+    // with every load of a thread issued before its first store
+    const uint32_t myw = lane < cn ? F.ops[c0 + lane] : 0u;
     double mt[8 * kStage / 64];
 #pragma unroll
     for (uint32_t k = 0; k < 8 * kStage / 64; ++k) {
@@ -235,28 +235,35 @@ __global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__res
       mt[k] = i < 8 * cn ? F.mats[(size_t)8 * c0 + i] : 0.0;
     }
     __syncthreads();  // every wave is done with the previous chunk
-    if (tid < cn) s_words[tid] = wt;
 #pragma unroll
     for (uint32_t k = 0; k < 8 * kStage / 64; ++k) {
       const uint32_t i = tid + k * BS;
       if (i < 8 * cn) s_mats[i] = mt[k];
     }
     __syncthreads();
-    // op t + 1 (word and matrix) is read from LDS while op t runs; the
-    // staging area has one spare entry for the read past the chunk's end
-    uint32_t wn = s_words[0];
+    // the matrix of op t + 1 (if it has one) is read while op t runs
+    uint32_t wn = __builtin_amdgcn_readlane(myw, 0);
     double Mn[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Mn[e] = s_mats[e];
+    for (int e = 0; e < 8; ++e) Mn[e] = 0.0;
+    if (op_kind(wn) == SV_U2 || op_kind(wn) == SV_DIAG || op_kind(wn) == SV_END) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Mn[e] = s_mats[e];
+    }
 #pragma unroll 1
     for (uint32_t t = 0; t < cn; ++t) {
-      const uint32_t w = __builtin_amdgcn_readfirstlane(wn);
+      const uint32_t w = wn;
       double M[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) M[e] = Mn[e];
-      wn = s_words[t + 1];
+      if (t + 1 < cn) {
+        wn = __builtin_amdgcn_readlane(myw, t + 1);
+        const uint32_t kn = op_kind(wn);
+        if (kn == SV_U2 || kn == SV_DIAG || kn == SV_END) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) Mn[e] = s_mats[8 * (t + 1) + e];
+          for (int e = 0; e < 8; ++e) Mn[e] = s_mats[8 * (t + 1) + e];
+        }
+      }
       const uint32_t kind = op_kind(w), a = op_q0(w), b = op_q1(w);
       switch (kind) {
         case SV_U2: {
@@ -445,8 +452,8 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   const SvShape sh = sv_shape(h.m);
   const uint32_t bs = 64u << sh.wb;
   // two state buffers (swaps alternate between them; the copy mode uses the
-  // second for the rotated copy) and the staged program chunk
-  const size_t lds = (size_t(2) << h.m) * sizeof(C2) + (kStage + 2) * 4 + (kStage + 1) * 8 * sizeof(double);
+  // second for the rotated copy) and the staged matrices of a program chunk
+  const size_t lds = (size_t(2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
   const void *kern = sh.rb == 0 ? (const void *)sv_kernel<0>
                      : sh.rb == 1 ? (const void *)sv_kernel<1>
                                   : (const void *)sv_kernel<2>;

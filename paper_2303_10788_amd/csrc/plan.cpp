@@ -66,7 +66,9 @@ M2 gate_matrix(uint32_t kind, double theta) {
 // Fuse every run of one-qubit gates on a qubit (up to the next two-qubit
 // gate touching it) into one matrix; runs on different qubits commute with
 // the two-qubit gates that do not touch them, so emitting a run just before
-// the first two-qubit gate on its qubit preserves the circuit.
+// the first two-qubit gate on its qubit preserves the circuit.  A run that
+// is diagonal so far also commutes with a CZ on its qubit and with a CX it
+// controls, so it continues past them.
 void fuse_one_qubit_runs(Fragment &F) {
   const uint32_t m = F.m();
   std::vector<M2> pend(m, M2{1, 0, 0, 1});
@@ -86,8 +88,11 @@ void fuse_one_qubit_runs(Fragment &F) {
   for (size_t g = 0; g < F.op_words.size(); ++g) {
     const uint32_t w = F.op_words[g], k = op_kind(w), a = op_q0(w), b = op_q1(w);
     if (is_two_qubit(k)) {
-      flush(a);
-      flush(b);
+      // a diagonal run commutes with a CZ on its qubit and with a CX it
+      // controls, so it stays pending and merges with the next run
+      auto diag = [&](uint32_t q) { return pend[q].b == 0.0 && pend[q].c == 0.0; };
+      if (!(diag(a) && (k == G_CZ || k == G_CX))) flush(a);
+      if (!(diag(b) && k == G_CZ)) flush(b);
       F.sv_words.push_back(w);
       for (int t = 0; t < 8; ++t) F.sv_mats.push_back(0.0);
     } else {
