@@ -504,6 +504,38 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
 ccut_status pauli_passes(ccut_ctx *c, const Fragment &f, const FragRequest &r, double *data,
                          uint64_t xsize, uint64_t mode2_lo, double **out) {
   const uint32_t a = (uint32_t)f.axes.size();
+  // Small tensors (up to 3 axes, at most 27 terms per entry, at most 2^16
+  // entries out) take all passes in one launch: there the launches, not the
+  // arithmetic, are the cost; larger ones take the per-axis passes, which
+  // read each entry a bounded number of times.
+  uint64_t n_out_axes = 0;
+  for (const Axis &ax : f.axes) n_out_axes += ax.side == 0;
+  const uint64_t entries_out = (mode2_lo ? mode2_lo : xsize >> n_out_axes) << (2 * a);
+  if (a >= 2 && a <= 3 && entries_out <= (1ull << 16)) {
+    TransformAll A{};
+    A.n_axes = a;
+    A.x_in = xsize;
+    A.n_strings = mode2_lo;
+    uint64_t xo = xsize, nout = 0;
+    for (uint32_t j = 0; j < a; ++j) {
+      const bool is_out = f.axes[j].side == 0;
+      A.rad[j] = f.axes[j].radix();
+      A.mode[j] = is_out ? (mode2_lo ? 2u : 1u) : 0u;
+      A.pos[j] = is_out && !mode2_lo ? (uint32_t)r.axis_outpos[j] : 0u;
+      if (is_out) ++nout;
+    }
+    xo >>= nout;
+    if (mode2_lo) xo = mode2_lo;
+    A.x_out = xo;
+    double *nxt = aget<double>(c, xo << (2 * a));
+    if (!nxt) return fail(c, CCUT_E_OOM, "device allocation failed");
+    {
+      KTimer t(c, CCUT_K_TRANSFORM);
+      HIP_TRY(c, launch_transform_all(A, data, nxt, c->cur));
+    }
+    *out = nxt;
+    return CCUT_OK;
+  }
   std::vector<uint64_t> rad(a);
   for (uint32_t j = 0; j < a; ++j) rad[j] = f.axes[j].radix();
   std::vector<int32_t> pos(r.axis_outpos.begin(), r.axis_outpos.end());

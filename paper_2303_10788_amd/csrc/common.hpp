@@ -227,6 +227,22 @@ hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv,
 // One Pauli-basis pass over cut axis j: mode 0 = quantum input (4 -> 4),
 // mode 1 = quantum output on outcome distributions (basis x outcome -> 4),
 // mode 2 = quantum output on parity tables (basis x J-bit -> 4).
+// All Pauli-basis passes of one fragment in one launch: out[P][x_out] is
+// the sum over the per-axis coefficient terms (input axis: I = p0 + p1,
+// X = 2p+ - p0 - p1, Y = 2p+i - p0 - p1, Z = p0 - p1; output axis, per
+// outcome bit b of its basis: I = b0 + b1 (Z basis), X, Y, Z = b0 - b1;
+// Z-string selection: I picks b0 of Z, X/Y/Z pick b1 of their basis).
+// Digit j of the variant index (axis 0 fastest) has radix rad[j]; P has four
+// values per axis, axis 0 fastest; x is the fastest index.
+struct TransformAll {
+  uint32_t n_axes;
+  uint32_t mode[kMaxAxes];  // 0 quantum input, 1 output (outcome bit), 2 output (string selection)
+  uint32_t rad[kMaxAxes];
+  uint32_t pos[kMaxAxes];   // mode 1: outcome bit position in the input's x
+  uint64_t x_in, x_out;
+  uint64_t n_strings;       // mode 2: x_in = J * n_strings + x_out, bit t of J = t-th output axis
+};
+hipError_t launch_transform_all(const TransformAll &a, const double *in, double *out, hipStream_t s);
 hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, uint64_t inner_digits,
                                  uint64_t xsize_in, uint64_t lo, int mode, hipStream_t s);
 

@@ -55,6 +55,79 @@ __global__ void transform_pass_kernel(const double *__restrict__ in, double *__r
   out[i] = acc;
 }
 
+// One thread per output entry; the terms of every axis are enumerated as a
+// mixed-radix counter (at most 3 per input axis, 2 or 1 per output axis).
+__global__ void transform_all_kernel(const TransformAll A, const double *__restrict__ in, double *__restrict__ out) {
+  const uint32_t a = A.n_axes;
+  const uint64_t total = (A.x_out << (2 * a));
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t x = i % A.x_out;
+  const uint64_t P = i / A.x_out;
+  // per axis: number of terms and the term list (digit, outcome bit, coefficient)
+  uint32_t nt[kMaxAxes];
+  for (uint32_t j = 0; j < a; ++j) {
+    const uint32_t p = (uint32_t)((P >> (2 * j)) & 3ull);
+    nt[j] = A.mode[j] == 0 ? (p == 1 || p == 2 ? 3u : 2u) : A.mode[j] == 1 ? 2u : 1u;
+  }
+  // x with the consumed outcome bits (mode 1) as zeros, ascending positions
+  uint64_t xbase = x;
+  if (A.n_strings == 0) {
+    uint32_t ps[kMaxAxes], np = 0;
+    for (uint32_t j = 0; j < a; ++j)
+      if (A.mode[j] == 1) ps[np++] = A.pos[j];
+    for (uint32_t u = 1; u < np; ++u)  // insertion sort, np <= 16
+      for (uint32_t v = u; v > 0 && ps[v - 1] > ps[v]; --v) {
+        const uint32_t t = ps[v];
+        ps[v] = ps[v - 1];
+        ps[v - 1] = t;
+      }
+    for (uint32_t u = 0; u < np; ++u)
+      xbase = ((xbase >> ps[u]) << (ps[u] + 1)) | (xbase & ((1ull << ps[u]) - 1));
+  }
+  double acc = 0.0;
+  uint32_t c[kMaxAxes];
+  for (uint32_t j = 0; j < a; ++j) c[j] = 0;
+  for (;;) {
+    double coef = 1.0;
+    uint64_t v = 0, stride = 1, xin = xbase, J = 0;
+    uint32_t t_out = 0;
+    for (uint32_t j = 0; j < a; ++j) {
+      const uint32_t p = (uint32_t)((P >> (2 * j)) & 3ull);
+      uint32_t d, b = 0;
+      double w;
+      if (A.mode[j] == 0) {
+        // I: p0 + p1; X: 2p+ - p0 - p1; Y: 2p+i - p0 - p1; Z: p0 - p1
+        if (p == 0) { d = c[j]; w = 1.0; }
+        else if (p == 3) { d = c[j]; w = c[j] ? -1.0 : 1.0; }
+        else if (c[j] == 0) { d = p + 1; w = 2.0; }
+        else { d = c[j] - 1; w = -1.0; }
+      } else {
+        d = p == 1 ? 0u : p == 2 ? 1u : 2u;  // basis X, Y, Z (I reads Z)
+        if (A.mode[j] == 1) {
+          b = c[j];
+          w = (p != 0 && b) ? -1.0 : 1.0;
+        } else {
+          b = p == 0 ? 0u : 1u;
+          w = 1.0;
+        }
+        if (A.mode[j] == 1) xin |= (uint64_t)b << A.pos[j];
+        else J |= (uint64_t)b << t_out;
+        ++t_out;
+      }
+      coef *= w;
+      v += d * stride;
+      stride *= A.rad[j];
+    }
+    if (A.n_strings) xin = J * A.n_strings + x;
+    acc += coef * in[v * A.x_in + xin];
+    uint32_t j = 0;
+    while (j < a && ++c[j] == nt[j]) c[j++] = 0;
+    if (j == a) break;
+  }
+  out[i] = acc;
+}
+
 // R[b] = 2^-k sum_P prod_f T_f[p_f(P)][b_f(b)], P ascending, fragments in order.
 __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
                                       double *__restrict__ outp) {
@@ -145,6 +218,14 @@ hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, 
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(transform_pass_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, in, out, outer, R,
                      Xin, lo, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform_all(const TransformAll &a, const double *in, double *out, hipStream_t s) {
+  if (a.n_axes == 0 || a.n_axes > (uint32_t)kMaxAxes) return hipErrorInvalidValue;
+  const uint64_t total = a.x_out << (2 * a.n_axes);
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(transform_all_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, a, in, out);
   return hipGetLastError();
 }
 
