@@ -949,7 +949,8 @@ namespace {
 // sync); res receives 2^nq doubles.  pre_models[f], if given, holds the
 // already computed sample models of Clifford fragment f.
 ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
-                             double *res, const std::vector<uint64_t *> *pre_models) {
+                             double *res, const std::vector<uint64_t *> *pre_models,
+                             const std::vector<double *> *pre_dist = nullptr) {
   ccut_ctx *c = p->ctx;
   ccut_status st;
   const PlanData &pd = p->pd;
@@ -965,7 +966,8 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
       if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
     } else {
       uint64_t *pm = pre_models ? (*pre_models)[f.index] : nullptr;
-      if ((st = variant_dists(p, eo, f, r, &dist, pm)) != CCUT_OK) return st;
+      dist = pre_dist ? (*pre_dist)[f.index] : nullptr;
+      if (!dist && (st = variant_dists(p, eo, f, r, &dist, pm)) != CCUT_OK) return st;
       if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
     }
     RecombFrag &rf = args.f[f.index];
@@ -1367,6 +1369,14 @@ struct ccut_batch {
   std::vector<hipEvent_t> join_ev;
   std::vector<uint32_t> wlist[4];
   uint32_t wrows[4] = {0, 0, 0, 0};
+  // batched sampling and state vectors across plans: (plan, fragment) lists,
+  // the non-Clifford descriptors and their state-vector shapes
+  struct Ref {
+    uint32_t plan, frag, desc, n_meas;
+  };
+  std::vector<Ref> samp;  // sampled Clifford fragments (desc indexes descs)
+  std::vector<Ref> nc;    // non-Clifford fragments (desc indexes sv_descs)
+  std::vector<FragDev> sv_descs;
   uint32_t max_m = 0, block = 64, grid = 0, use_reg = 1;
   double tuned_ms = 0.0;
   ~ccut_batch() {
@@ -1496,6 +1506,102 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   }
   if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg, d_bases)) != CCUT_OK)
     return st;
+  // every plan's sampled outcome tables in one sampling launch (plus one
+  // reduction), every non-Clifford fragment in one state-vector launch per
+  // shape; the per-plan steps below start from these tables
+  std::vector<std::vector<double *>> pre_dist(b->plans.size());
+  for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+  if (!b->samp.empty()) {
+    const uint64_t shots = b->eo.shots_per_variant;
+    const uint64_t nquads = (shots + 3) / 4;
+    std::vector<SampleJob> jobs;
+    uint64_t wg = 0, t = 0, fill_words = 0;
+    size_t lds_bytes = 0;
+    for (const auto &ref : b->samp) {
+      const FragDev &h = b->descs[ref.desc];
+      const uint32_t nm = ref.n_meas, bins = 1u << nm;
+      const uint64_t nv = h.n_variants;
+      const bool lds = nm <= 14;
+      uint32_t nblk;
+      if (lds) {  // as in the per-plan sampler
+        const uint64_t per_block = std::max<uint64_t>(bins, 2048);
+        nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
+        lds_bytes = std::max<size_t>(lds_bytes, (size_t)bins * 4);
+      } else {
+        nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
+        fill_words += nv * (uint64_t)bins;
+      }
+      SampleJob J{};
+      J.models = d_models + b->model_off[ref.plan][ref.frag];
+      J.shots = shots;
+      J.seed = b->eo.seed;
+      J.vid0 = h.vid_base;
+      J.nv = nv;
+      J.n_meas = nm;
+      J.nblk = nblk;
+      J.qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
+      J.wg0 = wg;
+      J.t0 = t;
+      wg += nv * nblk;
+      t += nv * bins;
+      jobs.push_back(J);
+    }
+    // partial counts: the per-variant ones (zeroed) first, contiguous
+    uint32_t *zeroed = fill_words ? aget<uint32_t>(c, fill_words) : nullptr;
+    if (fill_words && !zeroed) return fail(c, CCUT_E_OOM, "device allocation failed");
+    uint64_t zo = 0;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      SampleJob &J = jobs[q];
+      const uint64_t bins = 1ull << J.n_meas;
+      if (J.n_meas <= 14) {
+        J.partial = aget<uint32_t>(c, J.nv * J.nblk * bins);
+      } else {
+        J.partial = zeroed + zo;
+        zo += J.nv * bins;
+      }
+      J.dist = aget<double>(c, J.nv * bins);
+      if (!J.partial || !J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+      pre_dist[b->samp[q].plan][b->samp[q].frag] = J.dist;
+    }
+    SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
+    if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
+    if (fill_words) HIP_TRY(c, launch_fill_u32(zeroed, fill_words, 0u, c->cur));
+    KTimer tm(c, CCUT_K_SAMPLE);
+    HIP_TRY(c, launch_sample_batch(d_jobs, (uint32_t)jobs.size(), wg, lds_bytes, t, c->cur));
+  }
+  if (!b->nc.empty()) {
+    FragDev *d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
+    if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
+    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+      std::vector<SvJob> jobs;
+      uint64_t wg = 0;
+      size_t lds = 0;
+      for (const auto &ref : b->nc) {
+        const FragDev &h = b->sv_descs[ref.desc];
+        if (h.m != m) continue;
+        uint64_t n_wg;
+        uint32_t bs;
+        size_t l;
+        bool split;
+        sv_launch_shape(h, n_wg, bs, l, split);
+        SvJob J{};
+        J.desc = ref.desc;
+        J.split = split ? 1u : 0u;
+        J.wg0 = wg;
+        J.dist = aget<double>(c, h.n_variants << ref.n_meas);
+        if (!J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+        pre_dist[ref.plan][ref.frag] = J.dist;
+        wg += n_wg;
+        lds = std::max(lds, l);
+        jobs.push_back(J);
+      }
+      if (jobs.empty()) continue;
+      SvJob *d_jobs = (SvJob *)upload(c, jobs.data(), jobs.size() * sizeof(SvJob));
+      if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
+      KTimer tm(c, CCUT_K_SV);
+      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
+    }
+  }
   // the plans' remaining steps are independent: plan i runs on pool stream
   // i mod P, after the shared tableau launch, and every pool stream joins
   // back before the batch stream continues
@@ -1514,7 +1620,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (b->res.size() <= i) b->res.push_back(res);
     b->res[i] = res;
     c->stream = c->cur = P ? b->pool[i % P] : b->stream;
-    st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre);
+    st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre, &pre_dist[i]);
     c->stream = c->cur = b->stream;
     if (st != CCUT_OK) return st;
   }
@@ -1552,7 +1658,15 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     b->qubits.emplace_back(qubits[i], qubits[i] + nq[i]);
     std::vector<int64_t> offs(p->pd.frags.size(), -1);
     for (const Fragment &f : p->pd.frags) {
-      if (!f.clifford || use_heisenberg(f, eo)) continue;
+      if (!f.clifford) {
+        FragRequest r = marginal_request(f, qubits[i], nq[i]);
+        if (r.meas.size() > (size_t)kMaxTableBits)
+          return fail(c, CCUT_E_UNSUPPORTED, "outcome table over more than 24 measured qubits");
+        b->nc.push_back({(uint32_t)i, f.index, (uint32_t)b->sv_descs.size(), (uint32_t)r.meas.size()});
+        b->sv_descs.push_back(frag_desc(p, f, r, (uint32_t)i));
+        continue;
+      }
+      if (use_heisenberg(f, eo)) continue;
       FragRequest r = marginal_request(f, qubits[i], nq[i]);
       const uint32_t nm = (uint32_t)r.meas.size();
       if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits");
@@ -1568,6 +1682,11 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
       const uint64_t boff = b->base_words_total;
       b->base_words_total += (uint64_t)2 * f.m() * (2 * Wb + 1);
       offs[f.index] = (int64_t)b->model_words_total;
+      if (eo->shots_per_variant) {
+        if (nm > (uint32_t)kMaxTableBits)
+          return fail(c, CCUT_E_UNSUPPORTED, "outcome table over more than 24 measured qubits");
+        b->samp.push_back({(uint32_t)i, f.index, di, nm});
+      }
       for (uint64_t v = 0; v < f.n_variants; ++v)
         b->items.push_back({di, 0u, v, b->model_words_total + v * model_words(nm), boff});
       b->model_words_total += f.n_variants * model_words(nm);

@@ -192,6 +192,28 @@ struct BatchItem {
   uint64_t base_off;  // word offset of the fragment's base tableau (when bases are given)
 };
 
+// One fragment's sampled outcome tables in a batched launch: variants
+// [0, nv) of `models`, nblk shot blocks per variant (qpt quads per thread),
+// counts in `partial` (per block when n_meas <= 14, else per variant, zeroed
+// beforehand), tables in `dist`.  wg0 / t0: the job's first workgroup of the
+// sampling launch and first thread of the reduction launch.
+struct SampleJob {
+  const uint64_t *models;
+  uint32_t *partial;
+  double *dist;
+  uint64_t shots, seed, vid0, nv;
+  uint64_t wg0, t0;
+  uint32_t n_meas, nblk, qpt, pad_;
+};
+
+// One non-Clifford fragment in a batched state-vector launch: descriptor
+// descs[desc], tables in dist, wg0 = its first workgroup.
+struct SvJob {
+  uint32_t desc, split;
+  uint64_t wg0;
+  double *dist;
+};
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
@@ -215,6 +237,18 @@ hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t
                                hipStream_t s);
 // prog: the fragment's state-vector program (words + 8 doubles per word)
 hipError_t launch_sv(const FragDev &frag, double *dist, hipStream_t s);
+// State-vector launch shape of a fragment: workgroups, threads, LDS bytes,
+// whether basis combinations get workgroups of their own.
+void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split);
+// Many non-Clifford fragments of one shape (same m class: register bits and
+// waves) in one launch; lds = the largest of theirs.
+hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_jobs, uint64_t total_wg, uint32_t m,
+                           size_t lds, hipStream_t s);
+// Batched sampling + reduction over jobs (see SampleJob); lds = the largest
+// LDS histogram among the jobs (4 * 2^n_meas bytes for n_meas <= 14, 0 if
+// none has one).
+hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
+                               uint64_t total_entries, hipStream_t s);
 hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
                                const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
 hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,

@@ -34,15 +34,16 @@ __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, boo
 constexpr int kSampleBlock = 256;
 constexpr uint32_t kLdsHistBits = 14;  // up to 2^14 u32 bins = 64 KiB per workgroup
 
-// grid: (nblk_x, nv).  Each thread handles `qpt` quads; quads are
-// interleaved across the workgroup so record writes are contiguous.
-__global__ __launch_bounds__(kSampleBlock) void sample_kernel(
-    const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
-    uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
-  extern __shared__ uint32_t s_hist[];
-  __shared__ uint64_t s_model[2 + kMaxMeas];
+// Shots of variant v, block bx of nbx: each thread handles `qpt` quads;
+// quads are interleaved across the workgroup so record writes are
+// contiguous.  With n_meas <= 14 the block's histogram lives in LDS and is
+// written to partial[v][bx][bins]; otherwise counts go straight to
+// partial[v][bins] (zeroed beforehand).
+__device__ void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
+                            uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
+                            uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
+                            uint32_t *s_hist, uint64_t *s_model) {
   const uint32_t mw = model_words(n_meas);
-  const uint64_t v = blockIdx.y;
   const uint64_t *md = models + v * mw;
   for (uint32_t i = threadIdx.x; i < mw; i += kSampleBlock) s_model[i] = md[i];
   const uint32_t bins = 1u << n_meas;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
   const bool wide = n_meas > 32;
   const uint64_t nquads = (shots + 3) >> 2;
   for (uint32_t q = 0; q < qpt; ++q) {
-    const uint64_t quad = ((uint64_t)blockIdx.x * qpt + q) * kSampleBlock + threadIdx.x;
+    const uint64_t quad = ((uint64_t)bx * qpt + q) * kSampleBlock + threadIdx.x;
     if (quad >= nquads) break;
     uint64_t u[4];
     quad_bits(quad, vid, seed, wide, u);
@@ -78,9 +79,44 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
   }
   if (lds_hist) {
     __syncthreads();
-    uint32_t *dst = partial + (v * gridDim.x + blockIdx.x) * (uint64_t)bins;
+    uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins;
     for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) dst[i] = s_hist[i];
   }
+}
+
+// grid: (nblk_x, nv)
+__global__ __launch_bounds__(kSampleBlock) void sample_kernel(
+    const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
+    uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
+  extern __shared__ uint32_t s_hist[];
+  __shared__ uint64_t s_model[2 + kMaxMeas];
+  sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_hist,
+              s_model);
+}
+
+// The job whose range [start, next start) holds idx (starts ascending, first 0).
+template <class J, class F>
+__device__ inline uint32_t find_job(const J *jobs, uint32_t n, uint64_t idx, F start) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (start(jobs[mid]) <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Many fragments' sampling in one launch: workgroup x runs block
+// (x - wg0) mod nblk of variant (x - wg0) / nblk of the job holding x.
+__global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,
+                                                                      uint32_t n_jobs) {
+  extern __shared__ uint32_t s_hist[];
+  __shared__ uint64_t s_model[2 + kMaxMeas];
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const SampleJob &J) { return J.wg0; });
+  const SampleJob &J = jobs[j];
+  const uint64_t local = blockIdx.x - J.wg0;
+  sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
+              (uint32_t)(local % J.nblk), J.nblk, s_hist, s_model);
 }
 
 // dist[v][b] = (sum over shot blocks of counts) / shots
@@ -92,6 +128,21 @@ __global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_
   uint64_t c = 0;
   for (uint32_t k = 0; k < nblk; ++k) c += partial[(v * nblk + k) * (uint64_t)bins + b];
   dist[i] = (double)c / (double)shots;
+}
+
+// The same over every job of a batch: thread t of job J handles entry
+// t - t0 of J's table.
+__global__ void hist_reduce_batch_kernel(const SampleJob *__restrict__ jobs, uint32_t n_jobs, uint64_t total) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint32_t j = find_job(jobs, n_jobs, i, [](const SampleJob &J) { return J.t0; });
+  const SampleJob &J = jobs[j];
+  const uint32_t bins = 1u << J.n_meas;
+  const uint32_t nblk = J.n_meas <= kLdsHistBits ? J.nblk : 1u;
+  const uint64_t e = i - J.t0, v = e / bins, b = e % bins;
+  uint64_t c = 0;
+  for (uint32_t k = 0; k < nblk; ++k) c += J.partial[(v * nblk + k) * (uint64_t)bins + b];
+  J.dist[e] = (double)c / (double)J.shots;
 }
 
 // Exact table: x is an outcome iff y = x ^ x0 equals the xor of the G
@@ -262,6 +313,18 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
   const size_t lds = (partial && n_meas <= kLdsHistBits) ? (size_t(1) << n_meas) * 4 : 0;
   hipLaunchKernelGGL(sample_kernel, dim3(nblk_x, (unsigned)nv), dim3(kSampleBlock), lds, s, models,
                      n_meas, shots, seed, vid0, partial, qpt, records);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
+                               uint64_t total_entries, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  if (total_wg > 0x7FFFFFFFull || lds > (size_t(4) << kLdsHistBits)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sample_batch_kernel, dim3((unsigned)total_wg), dim3(kSampleBlock), lds, s, jobs, n_jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hist_reduce_batch_kernel, dim3(blocks_for(total_entries, 256)), dim3(256), 0, s, jobs, n_jobs,
+                     total_entries);
   return hipGetLastError();
 }
 

@@ -22,6 +22,11 @@
 // distribution entry is reduced in a fixed order (deterministic).
 #include "common.hpp"
 
+// No implicit contraction: every fused multiply-add is written out, so the
+// single-fragment and the batched kernel (the same body inlined in
+// different code) round identically.
+#pragma clang fp contract(off)
+
 namespace ccut {
 
 namespace {
@@ -30,7 +35,9 @@ struct C2 {
   double re, im;
 };
 
-__device__ inline C2 cmul(C2 a, C2 b) { return C2{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline C2 cmul(C2 a, C2 b) {
+  return C2{__builtin_fma(a.re, b.re, -(a.im * b.im)), __builtin_fma(a.re, b.im, a.im * b.re)};
+}
 __device__ inline C2 cadd(C2 a, C2 b) { return C2{a.re + b.re, a.im + b.im}; }
 
 // insert a zero bit at position t
@@ -162,9 +169,8 @@ __device__ inline void cx_reg(double *re, double *im, uint32_t base, uint32_t ct
 // combination on a copy.  blockDim.x = 64 * 2^wb (sv_shape, up to 1024),
 // RB register bits per thread.
 template <int RB>
-__global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
+__device__ void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc, uint32_t blk, C2 *smem) {
   constexpr int R = 1 << RB;
-  extern __shared__ C2 smem[];
   const uint32_t m = F.m;
   const uint32_t N = 1u << m;
   const uint32_t BS = blockDim.x;
@@ -177,8 +183,8 @@ __global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__res
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
   uint32_t n_bc = 1;
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
-  const uint32_t prep = split_bc ? blockIdx.x / n_bc : blockIdx.x;
-  const uint32_t bc0 = split_bc ? blockIdx.x % n_bc : 0, bc1 = split_bc ? bc0 + 1 : n_bc;
+  const uint32_t prep = split_bc ? blk / n_bc : blk;
+  const uint32_t bc0 = split_bc ? blk % n_bc : 0, bc1 = split_bc ? bc0 + 1 : n_bc;
 
   // prepared product state: |0>, |1>, |+> = H|0> or |+i> = S H|0> on each
   // quantum input (digit of this preparation combination), |0> elsewhere
@@ -436,10 +442,31 @@ __global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__res
   }
 }
 
+template <int RB>
+__global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
+  extern __shared__ C2 smem[];
+  sv_body<RB>(F, dist, split_bc, blockIdx.x, smem);
+}
+
+// Many fragments of one shape: workgroup x runs workgroup x - wg0 of the
+// job holding x.
+template <int RB>
+__global__ __launch_bounds__(1024) void sv_batch_kernel(const FragDev *__restrict__ descs, const SvJob *__restrict__ jobs,
+                                                        uint32_t n_jobs) {
+  extern __shared__ C2 smem[];
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (jobs[mid].wg0 <= blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const SvJob &J = jobs[lo];
+  sv_body<RB>(descs[J.desc], J.dist, J.split, (uint32_t)(blockIdx.x - J.wg0), smem);
+}
+
 }  // namespace
 
-hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
-  if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
+void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split) {
   uint32_t n_in = 0, n_out = 0;
   for (uint32_t j = 0; j < h.n_axes; ++j) (h.axis_side[j] ? n_in : n_out) += 1;
   // basis combinations get workgroups of their own while the grid stays
@@ -448,18 +475,48 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   uint64_t n_bc = 1;
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   const uint64_t n_prep = 1ull << (2 * n_in);
-  const bool split = n_out && n_prep * n_bc <= 512;
-  const SvShape sh = sv_shape(h.m);
-  const uint32_t bs = 64u << sh.wb;
+  split = n_out && n_prep * n_bc <= 512;
+  n_wg = split ? n_prep * n_bc : n_prep;
+  block = 64u << sv_shape(h.m).wb;
   // two state buffers (swaps alternate between them; the copy mode uses the
   // second for the rotated copy) and the staged matrices of a program chunk
-  const size_t lds = (size_t(2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
+  lds = (size_t(2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
+}
+
+hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_jobs, uint64_t total_wg, uint32_t m,
+                           size_t lds, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  if (m == 0 || m > (uint32_t)kMaxNcQubits || total_wg > 0x7FFFFFFFull || lds > 160 * 1024)
+    return hipErrorInvalidValue;
+  const SvShape sh = sv_shape(m);
+  const dim3 grid((unsigned)total_wg), block(64u << sh.wb);
+  const void *kern = sh.rb == 0 ? (const void *)sv_batch_kernel<0>
+                     : sh.rb == 1 ? (const void *)sv_batch_kernel<1>
+                                  : (const void *)sv_batch_kernel<2>;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  switch (sh.rb) {
+    case 0: hipLaunchKernelGGL(sv_batch_kernel<0>, grid, block, lds, s, descs, jobs, n_jobs); break;
+    case 1: hipLaunchKernelGGL(sv_batch_kernel<1>, grid, block, lds, s, descs, jobs, n_jobs); break;
+    default: hipLaunchKernelGGL(sv_batch_kernel<2>, grid, block, lds, s, descs, jobs, n_jobs); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
+  if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
+  uint64_t n_wg;
+  uint32_t bs;
+  size_t lds;
+  bool split;
+  sv_launch_shape(h, n_wg, bs, lds, split);
+  const SvShape sh = sv_shape(h.m);
   const void *kern = sh.rb == 0 ? (const void *)sv_kernel<0>
                      : sh.rb == 1 ? (const void *)sv_kernel<1>
                                   : (const void *)sv_kernel<2>;
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)(split ? n_prep * n_bc : n_prep)), block(bs);
+  const dim3 grid((unsigned)n_wg), block(bs);
   switch (sh.rb) {
     case 0: hipLaunchKernelGGL(sv_kernel<0>, grid, block, lds, s, h, dist, (uint32_t)split); break;
     case 1: hipLaunchKernelGGL(sv_kernel<1>, grid, block, lds, s, h, dist, (uint32_t)split); break;
