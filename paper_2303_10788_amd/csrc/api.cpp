@@ -1541,9 +1541,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.nblk = nblk;
       J.qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
       J.wg0 = wg;
-      J.t0 = t;
+      J.rb0 = t;
       wg += nv * nblk;
-      t += nv * bins;
+      t += (nv * bins + 4095) / 4096;  // reduction workgroups
       jobs.push_back(J);
     }
     // partial counts: the per-variant ones (zeroed) first, contiguous

@@ -195,14 +195,14 @@ struct BatchItem {
 // One fragment's sampled outcome tables in a batched launch: variants
 // [0, nv) of `models`, nblk shot blocks per variant (qpt quads per thread),
 // counts in `partial` (per block when n_meas <= 14, else per variant, zeroed
-// beforehand), tables in `dist`.  wg0 / t0: the job's first workgroup of the
-// sampling launch and first thread of the reduction launch.
+// beforehand), tables in `dist`.  wg0 / rb0: the job's first workgroup of
+// the sampling launch and of the reduction launch (4096 entries each).
 struct SampleJob {
   const uint64_t *models;
   uint32_t *partial;
   double *dist;
   uint64_t shots, seed, vid0, nv;
-  uint64_t wg0, t0;
+  uint64_t wg0, rb0;
   uint32_t n_meas, nblk, qpt, pad_;
 };
 
@@ -248,7 +248,7 @@ hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_j
 // LDS histogram among the jobs (4 * 2^n_meas bytes for n_meas <= 14, 0 if
 // none has one).
 hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
-                               uint64_t total_entries, hipStream_t s);
+                               uint64_t total_reduce_blocks, hipStream_t s);
 hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
                                const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
 hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,

@@ -130,19 +130,24 @@ __global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_
   dist[i] = (double)c / (double)shots;
 }
 
-// The same over every job of a batch: thread t of job J handles entry
-// t - t0 of J's table.
-__global__ void hist_reduce_batch_kernel(const SampleJob *__restrict__ jobs, uint32_t n_jobs, uint64_t total) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const uint32_t j = find_job(jobs, n_jobs, i, [](const SampleJob &J) { return J.t0; });
+// The same over every job of a batch: workgroup x reduces entries
+// [(x - rb0) * 4096, ...) of the table of the job holding x (the job lookup
+// is done once per workgroup, with uniform loads).
+constexpr uint32_t kReduceChunk = 4096;
+__global__ __launch_bounds__(256) void hist_reduce_batch_kernel(const SampleJob *__restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const SampleJob &J) { return J.rb0; });
   const SampleJob &J = jobs[j];
   const uint32_t bins = 1u << J.n_meas;
   const uint32_t nblk = J.n_meas <= kLdsHistBits ? J.nblk : 1u;
-  const uint64_t e = i - J.t0, v = e / bins, b = e % bins;
-  uint64_t c = 0;
-  for (uint32_t k = 0; k < nblk; ++k) c += J.partial[(v * nblk + k) * (uint64_t)bins + b];
-  J.dist[e] = (double)c / (double)J.shots;
+  const uint64_t n_e = J.nv * bins;
+  const uint64_t e0 = (uint64_t)(blockIdx.x - J.rb0) * kReduceChunk;
+  const uint64_t e1 = e0 + kReduceChunk < n_e ? e0 + kReduceChunk : n_e;
+  for (uint64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const uint64_t v = e / bins, b = e % bins;
+    uint64_t c = 0;
+    for (uint32_t k = 0; k < nblk; ++k) c += J.partial[(v * nblk + k) * (uint64_t)bins + b];
+    J.dist[e] = (double)c / (double)J.shots;
+  }
 }
 
 // Exact table: x is an outcome iff y = x ^ x0 equals the xor of the G
@@ -317,14 +322,14 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
 }
 
 hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
-                               uint64_t total_entries, hipStream_t s) {
+                               uint64_t total_reduce_blocks, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   if (total_wg > 0x7FFFFFFFull || lds > (size_t(4) << kLdsHistBits)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sample_batch_kernel, dim3((unsigned)total_wg), dim3(kSampleBlock), lds, s, jobs, n_jobs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hist_reduce_batch_kernel, dim3(blocks_for(total_entries, 256)), dim3(256), 0, s, jobs, n_jobs,
-                     total_entries);
+  if (total_reduce_blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(hist_reduce_batch_kernel, dim3((unsigned)total_reduce_blocks), dim3(256), 0, s, jobs, n_jobs);
   return hipGetLastError();
 }
 
