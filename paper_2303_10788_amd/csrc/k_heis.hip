@@ -483,6 +483,22 @@ __global__ __launch_bounds__(kWht) void subset_wht_kernel(double *__restrict__ d
   for (uint32_t i = threadIdx.x; i < n; i += kWht) row[i] = ldexp(w[i], -(int)r);
 }
 
+// The same for rows of at most 64 entries: one wave per row, entry l in
+// lane l, the butterflies through lane exchanges (the same additions and
+// subtractions in the same order as the LDS version), four rows per
+// workgroup, coalesced row reads and writes.
+__global__ __launch_bounds__(256) void subset_wht_wave_kernel(double *__restrict__ data, uint32_t r, uint64_t nrows) {
+  const uint64_t row = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= nrows) return;  // whole waves leave together
+  const uint32_t l = threadIdx.x & 63, n = 1u << r;
+  double v = l < n ? data[row * n + l] : 0.0;
+  for (uint32_t s = 0; s < r; ++s) {
+    const double p = __shfl_xor(v, 1 << s);
+    v = ((l >> s) & 1u) ? p - v : v + p;  // the pair (a, b) becomes (a + b, a - b)
+  }
+  if (l < n) data[row * n + l] = ldexp(v, -(int)r);
+}
+
 __global__ void fill_zero_kernel(double *p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = 0.0;
@@ -569,6 +585,15 @@ hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32
   if (e != hipSuccess || n_str) return e;
   const uint64_t nrows = 1ull << (2 * F.n_axes);
   if (r == 0) return hipSuccess;
+  if (r <= 6) {
+    for (uint64_t r0 = 0; r0 < nrows; r0 += (1ull << 32)) {
+      const uint64_t cnt = std::min<uint64_t>(nrows - r0, 1ull << 32);
+      hipLaunchKernelGGL(subset_wht_wave_kernel, dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, s, tau + (r0 << r), r,
+                         cnt);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   for (uint64_t r0 = 0; r0 < nrows; r0 += (1ull << 30)) {
     const uint64_t cnt = std::min<uint64_t>(nrows - r0, 1ull << 30);
     hipLaunchKernelGGL(subset_wht_kernel, dim3((unsigned)cnt), dim3(kWht), (size_t(1) << r) * 8, s,

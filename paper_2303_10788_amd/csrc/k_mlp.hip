@@ -253,6 +253,41 @@ __global__ void colnorm_kernel(const double *__restrict__ T, uint32_t rows, uint
   out[p] = sqrt(s);
 }
 
+// The same for up to 64 rows per column: a wave stages 64 whole columns
+// (contiguous in memory) through LDS with coalesced loads, all issued before
+// the first store, then each lane sums its column in row order as above.
+__global__ __launch_bounds__(64) void colnorm_tile_kernel(const double *__restrict__ T, uint32_t rows, uint64_t ncols,
+                                                          double *__restrict__ out) {
+  __shared__ double tile[64 * 65];  // column c at c * 65 (padded against bank conflicts)
+  const uint64_t p0 = (uint64_t)blockIdx.x * 64;
+  const uint32_t lane = threadIdx.x;
+  const uint64_t cols = ncols - p0 < 64 ? ncols - p0 : 64;
+  const uint32_t n = (uint32_t)(cols * rows);  // <= 4096 doubles
+  const double *src = T + p0 * rows;
+  for (uint32_t i0 = 0; i0 < n; i0 += 64 * 16) {
+    double v[16];
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) {
+      const uint32_t i = i0 + 64 * k + lane;
+      v[k] = i < n ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) {
+      const uint32_t i = i0 + 64 * k + lane;
+      if (i < n) tile[(i / rows) * 65 + i % rows] = v[k];
+    }
+  }
+  __syncthreads();
+  if (lane < cols) {
+    double s = 0.0;
+    for (uint32_t b = 0; b < rows; ++b) {
+      const double t = tile[lane * 65 + b];
+      s += t * t;
+    }
+    out[p0 + lane] = sqrt(s);
+  }
+}
+
 // shares[j][d] = sum_{p: digit j of p = d} n[p]^2 / sum_p n[p]^2 for one
 // fragment: slot 4 j + d sums the 4^(a-1) columns with that digit, in
 // chunks (partials in order, then a fixed-order tree), then the chunks in
@@ -384,11 +419,20 @@ __global__ void max_partial_kernel(const float *__restrict__ x, uint64_t n, floa
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
-__global__ void max_final_kernel(const float *__restrict__ part, uint32_t np, double *__restrict__ stats) {
-  if (threadIdx.x) return;
+// final reductions: thread t takes partials t, t + 256, ... in order, then a
+// fixed tree over the 256 threads (deterministic)
+__global__ __launch_bounds__(kRedBlock) void max_final_kernel(const float *__restrict__ part, uint32_t np,
+                                                              double *__restrict__ stats) {
+  __shared__ float red[kRedBlock];
   float m = -INFINITY;
-  for (uint32_t i = 0; i < np; ++i) m = fmaxf(m, part[i]);
-  stats[0] = (double)m;
+  for (uint32_t i = threadIdx.x; i < np; i += kRedBlock) m = fmaxf(m, part[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (uint32_t w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stats[0] = (double)red[0];
 }
 __global__ void sumexp_partial_kernel(const float *__restrict__ x, uint64_t n, const double *__restrict__ stats,
                                       double *__restrict__ part) {
@@ -405,11 +449,18 @@ __global__ void sumexp_partial_kernel(const float *__restrict__ x, uint64_t n, c
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
-__global__ void sum_final_kernel(const double *__restrict__ part, uint32_t np, double *__restrict__ stats) {
-  if (threadIdx.x) return;
+__global__ __launch_bounds__(kRedBlock) void sum_final_kernel(const double *__restrict__ part, uint32_t np,
+                                                              double *__restrict__ stats) {
+  __shared__ double red[kRedBlock];
   double s = 0.0;
-  for (uint32_t i = 0; i < np; ++i) s += part[i];
-  stats[1] = s;
+  for (uint32_t i = threadIdx.x; i < np; i += kRedBlock) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (uint32_t w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stats[1] = red[0];
 }
 // q = (1 - eps) exp(x - max) / S + eps / n; uniform 1 / n without logits
 __global__ void proposal_kernel(const float *__restrict__ x, uint64_t n, const double *__restrict__ stats, double eps,
@@ -568,7 +619,10 @@ hipError_t launch_gather_rows(const uint16_t *X, const float *y, uint64_t n, uin
 }
 
 hipError_t launch_colnorm(const double *T, uint32_t rows, uint64_t ncols, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(colnorm_kernel, dim3(blocks(ncols, 256)), dim3(256), 0, s, T, rows, ncols, out);
+  if (rows <= 64)
+    hipLaunchKernelGGL(colnorm_tile_kernel, dim3(blocks(ncols, 64)), dim3(64), 0, s, T, rows, ncols, out);
+  else
+    hipLaunchKernelGGL(colnorm_kernel, dim3(blocks(ncols, 256)), dim3(256), 0, s, T, rows, ncols, out);
   return hipGetLastError();
 }
 
@@ -654,9 +708,9 @@ hipError_t launch_proposal(const float *logits, uint64_t n, double eps, float *m
   const uint32_t nb = reduce_blocks(n);
   if (logits) {
     hipLaunchKernelGGL(max_partial_kernel, dim3(nb), dim3(kRedBlock), 0, s, logits, n, mpart);
-    hipLaunchKernelGGL(max_final_kernel, dim3(1), dim3(64), 0, s, mpart, nb, stats);
+    hipLaunchKernelGGL(max_final_kernel, dim3(1), dim3(kRedBlock), 0, s, mpart, nb, stats);
     hipLaunchKernelGGL(sumexp_partial_kernel, dim3(nb), dim3(kRedBlock), 0, s, logits, n, stats, spart);
-    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(64), 0, s, spart, nb, stats);
+    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(kRedBlock), 0, s, spart, nb, stats);
   }
   hipLaunchKernelGGL(proposal_kernel, dim3(blocks(n, 256)), dim3(256), 0, s, logits, n, stats, eps, q);
   return hipGetLastError();
