@@ -479,7 +479,7 @@ def bench_learned(args):
         "train": {"rows": rows, "steps": 2000, "batch": 1024, "loss_first": float(losses[:5].mean()),
                   "loss_last": float(losses[-50:].mean()), "train_s": t_train, "dataset_s": t_data},
         "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
-        "roofline": {"bound": "mfma", "kernel": "mlp_gemm_kernel (network over all 4^10 terms)",
+        "roofline": {"bound": "mfma", "kernel": "mlp_fused_forward_kernel (network over all 4^10 terms)",
                      "achieved": flops / (mlp_ms / 1e3) / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
                      "frac": flops / (mlp_ms / 1e3) / PEAK_BF16, "traffic": None,
                      "avg_launch_us": 1e3 * mlp_ms / max(mlp_launches, 1)},

@@ -2286,6 +2286,24 @@ ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
   if (st != CCUT_OK) return st;
   if (!logits) return fail(c, CCUT_E_INVALID, "logits is NULL");
   if (M->ctx != c || M->F != L->width) return fail(c, CCUT_E_INVALID, "network input width differs from the features");
+  if (M->F == 64 && M->H == 256) {  // the whole pass in one launch, activations on chip
+    MlpFused net{};
+    net.w1 = M->pb + M->off_w1;
+    net.w2 = M->pb + M->off_w2;
+    net.w3 = M->pb + M->off_w3;
+    net.w4 = M->pb + M->off_w4;
+    net.b1 = M->p + M->off_b1;
+    net.b2 = M->p + M->off_b2;
+    net.b3 = M->p + M->off_b3;
+    net.b4 = M->p + M->off_b4;
+    net.F = M->F;
+    net.H = M->H;
+    {
+      KTimer t(c, CCUT_K_MLP);
+      HIP_TRY(c, launch_mlp_logits_fused(L->d, net, 0, L->K, kLabelScale, logits, c->cur));
+    }
+    return sync_call(c);
+  }
   const uint64_t chunk = std::min<uint64_t>(L->K, 1ull << 18);
   if ((st = mlp_ensure_work(M, std::max<uint64_t>(chunk, 64))) != CCUT_OK) return st;
   uint16_t *x = aget<uint16_t>(c, chunk * L->width);

@@ -385,6 +385,18 @@ hipError_t launch_shares(const double *norm, uint32_t n_axes, double *part, doub
 hipError_t launch_phi(const double *shares, const int64_t *src, uint32_t k, double *phi, hipStream_t s);
 hipError_t launch_features(const LearnedDev *L, const uint64_t *terms, uint64_t first, uint64_t n, uint32_t width,
                            uint16_t *X, hipStream_t s);
+// The whole forward pass over term rows [first, first + n) in one launch:
+// features from L, three ReLU layers (bf16 MFMA products, fp32
+// accumulation in the same k order as mlp_gemm, bias, ReLU, bf16), the head
+// y = scale (b4 + h3 . w4) summed as the separate head kernel does; the
+// activations never leave the workgroup.  F = 64 inputs, H = 256.
+struct MlpFused {
+  const uint16_t *w1, *w2, *w3, *w4;  // bf16 [H][F], [H][H], [H][H], [H]
+  const float *b1, *b2, *b3, *b4;
+  uint32_t F, H;
+};
+hipError_t launch_mlp_logits_fused(const LearnedDev *L, const MlpFused &net, uint64_t first, uint64_t n, float scale,
+                                   float *y, hipStream_t s);
 hipError_t launch_labels(const LearnedDev *L, const uint64_t *terms, uint64_t first, uint64_t n, float *y, int kind,
                          hipStream_t s);
 hipError_t launch_support(const LearnedDev *L, uint64_t K, uint64_t *flags, uint64_t *pos, uint64_t *scratch,

@@ -19,6 +19,7 @@ namespace {
 
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // fp32 -> bf16, round to nearest even (NaN kept quiet)
 __device__ inline uint16_t f2bf(float x) {
@@ -362,6 +363,106 @@ __global__ void features_kernel(const LearnedDev *__restrict__ L, const uint64_t
   X[i] = f2bf(v);
 }
 
+// Fused forward pass: a workgroup of 8 waves takes 128 term rows.  The
+// rows' features are built in LDS (as features_kernel does); each layer's
+// weights stream through LDS in chunks of 64 input columns; wave w
+// accumulates rows 64 (w & 1) .. + 63 by columns 64 (w >> 1) .. + 63 with
+// v_mfma_f32_16x16x16_bf16 in increasing k, adds the bias, applies the
+// ReLU and rounds to bf16 into the activation tile (in place, after a
+// barrier); the head then sums each row as head_forward_kernel does.
+constexpr uint32_t FF_TM = 128, FF_H = 256, FF_F = 64, FF_KC = 64, FF_THREADS = 512;
+constexpr uint32_t FF_AS = FF_H + 8, FF_WS = FF_KC + 8;  // padded row strides (bf16)
+
+__device__ __attribute__((always_inline)) inline void ff_layer(uint16_t *act, uint16_t *ws, const uint16_t *__restrict__ W, const float *__restrict__ b,
+                                uint32_t K, uint32_t tid) {
+  const uint32_t lane = tid & 63, wave = tid >> 6;
+  const uint32_t wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  float4v acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = float4v{0.f, 0.f, 0.f, 0.f};
+  for (uint32_t kc = 0; kc < K; kc += FF_KC) {
+    // weight chunk: ws[n][kk] = W[n][kc + kk], 256 rows of 128 B, four 16 B loads per thread
+    u32x4 v0, v1, v2, v3;
+    {
+      const uint32_t i0 = tid, i1 = tid + FF_THREADS, i2 = tid + 2 * FF_THREADS, i3 = tid + 3 * FF_THREADS;
+      v0 = *(const u32x4 *)(W + (uint64_t)(i0 >> 3) * K + kc + (i0 & 7) * 8);
+      v1 = *(const u32x4 *)(W + (uint64_t)(i1 >> 3) * K + kc + (i1 & 7) * 8);
+      v2 = *(const u32x4 *)(W + (uint64_t)(i2 >> 3) * K + kc + (i2 & 7) * 8);
+      v3 = *(const u32x4 *)(W + (uint64_t)(i3 >> 3) * K + kc + (i3 & 7) * 8);
+      __syncthreads();  // the previous chunk is consumed
+      *(u32x4 *)&ws[(i0 >> 3) * FF_WS + (i0 & 7) * 8] = v0;
+      *(u32x4 *)&ws[(i1 >> 3) * FF_WS + (i1 & 7) * 8] = v1;
+      *(u32x4 *)&ws[(i2 >> 3) * FF_WS + (i2 & 7) * 8] = v2;
+      *(u32x4 *)&ws[(i3 >> 3) * FF_WS + (i3 & 7) * 8] = v3;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t ks = 0; ks < FF_KC; ks += 16) {
+      short4v a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *(const short4v *)&act[(wm + 16 * i + (lane & 15)) * FF_AS + kc + ks + 4 * (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = *(const short4v *)&ws[(wn + 16 * j + (lane & 15)) * FF_WS + ks + 4 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave is done reading this layer's input
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t m = wm + 16 * i + 4 * (lane >> 4) + r, n = wn + 16 * j + (lane & 15);
+        act[m * FF_AS + n] = f2bf(fmaxf(acc[i][j][r] + b[n], 0.f));
+      }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(FF_THREADS) void mlp_fused_forward_kernel(const LearnedDev *__restrict__ L,
+                                                                       const MlpFused net, uint64_t first, uint64_t n,
+                                                                       float scale, float *__restrict__ y) {
+  extern __shared__ uint16_t ff_smem[];
+  uint16_t *act = ff_smem;                     // [FF_TM][FF_AS]
+  uint16_t *ws = ff_smem + FF_TM * FF_AS;      // [FF_H][FF_WS]
+  const uint32_t tid = threadIdx.x;
+  const uint64_t r0 = (uint64_t)blockIdx.x * FF_TM;
+  // features of rows r0 .. r0 + 127 (zero rows past n)
+  for (uint32_t i = tid; i < FF_TM * FF_F; i += FF_THREADS) {
+    const uint32_t t = i / FF_F, col = i % FF_F;
+    float v = 0.f;
+    if (r0 + t < n) {
+      const uint64_t P = first + r0 + t;
+      const uint32_t c = col / 6, rr = col % 6;
+      if (c < L->k) {
+        const uint32_t p = (uint32_t)((P >> (2 * c)) & 3u);
+        v = rr < 4 ? (rr == p ? 1.f : 0.f) : (float)L->phi[(c * 2 + (rr - 4)) * 4 + p];
+      }
+    }
+    act[t * FF_AS + col] = f2bf(v);
+  }
+  __syncthreads();
+  ff_layer(act, ws, net.w1, net.b1, FF_F, tid);
+  ff_layer(act, ws, net.w2, net.b2, FF_H, tid);
+  ff_layer(act, ws, net.w3, net.b3, FF_H, tid);
+  // head: 32 lanes per row, eight consecutive elements per lane, butterfly
+  const uint32_t l = tid & 31;
+  for (uint32_t t = tid >> 5; t < FF_TM; t += FF_THREADS / 32) {
+    float sacc = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sacc += bf2f(act[t * FF_AS + l * 8 + e]) * bf2f(net.w4[l * 8 + e]);
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 32);
+    if (l == 0 && r0 + t < n) y[r0 + t] = scale * (sacc + net.b4[0]);
+  }
+}
+
 // kind 0: labels y(P) = ln(2^-k prod_f n_f[P|f] + 2^-60) (fp64, stored
 // fp32); kind 2: y(P) / kLabelScale, the network's regression target;
 // kind 1: the product-of-shares log-weights sum_c 40 (phi_up + phi_dn).
@@ -566,6 +667,21 @@ hipError_t launch_mlp_gemm(const MlpGemm &g, int epi, hipStream_t s) {
     case MLP_EPI_MASK: hipLaunchKernelGGL(mlp_gemm_kernel<MLP_EPI_MASK>, grid, dim3(MG_THREADS), 0, s, g); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_logits_fused(const LearnedDev *L, const MlpFused &net, uint64_t first, uint64_t n, float scale,
+                                   float *y, hipStream_t s) {
+  if (net.F != FF_F || net.H != FF_H) return hipErrorInvalidValue;
+  if (n == 0) return hipSuccess;
+  const size_t lds = (size_t)(FF_TM * FF_AS + FF_H * FF_WS) * sizeof(uint16_t);
+  hipError_t e = hipFuncSetAttribute((const void *)mlp_fused_forward_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const uint64_t blocks_n = (n + FF_TM - 1) / FF_TM;
+  if (blocks_n > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_fused_forward_kernel, dim3((unsigned)blocks_n), dim3(FF_THREADS), lds, s, L, net, first, n,
+                     scale, y);
   return hipGetLastError();
 }
 

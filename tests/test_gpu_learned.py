@@ -194,6 +194,30 @@ def test_term_model_vs_oracle(ctx, case):
     assert np.abs(ex - R).max() <= 1e-10
 
 
+@pytest.mark.parametrize("case", CASES)
+def test_fused_logits_equal_layered_forward(ctx, case):
+    """The one-launch forward pass over every term (features built in the
+    kernel, activations on chip) equals the layer-by-layer forward of the
+    same network on the same feature rows bit for bit, times the label
+    scale, and the fp64 oracle network within the bf16 forward bound."""
+    import torch
+    ops, cuts, qubits = _small(case)
+    k = len(cuts)
+    _log(f"fused logits {case} k={k}")
+    plan = cc.Plan(ctx, 10, ops, cuts)
+    L = cc.Learned(plan, qubits)
+    net = cc.Mlp(ctx, 64, 256)
+    params = _random_net(64, 256, 11 + case[1])
+    net.set_params(cc.mlp_pack(params))
+    fused = L.logits(net).cpu().numpy()
+    X = L.features()
+    layered = net.forward(X).cpu().numpy() * np.float32(O.LABEL_SCALE)
+    assert np.array_equal(fused, layered.astype(np.float32))
+    ref, _ = O.forward(params, X.float().cpu().numpy().astype(np.float64))
+    rel = np.abs(fused / O.LABEL_SCALE - ref).max() / max(np.abs(ref).max(), 1e-30)
+    assert rel <= 2e-2
+
+
 def test_proposal_vs_oracle(ctx):
     import torch
     rng = np.random.default_rng(21)
