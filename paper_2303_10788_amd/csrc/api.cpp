@@ -683,7 +683,7 @@ ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp3
     RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
     if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
     KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_recombine_fp64(dargs, nq, res, c->cur));
+    HIP_TRY(c, launch_recombine_fp64(dargs, args.n_frags, nq, res, c->cur));
     return CCUT_OK;
   }
   GemmArgs g;
@@ -1089,10 +1089,11 @@ ccut_status marginal_call(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t
   ccut_ctx *c = p->ctx;
   if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
   if ((st = check_request(c, p->pd.n, qubits, nq)) != CCUT_OK) return st;
-  double *res = aget<double>(c, (size_t)1 << nq);
+  // a device output receives the contraction directly
+  double *res = on_device ? out : aget<double>(c, (size_t)1 << nq);
   if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
   if ((st = marginal_enqueue(p, eo, qubits, nq, res, nullptr)) != CCUT_OK) return st;
-  return finish_out(c, res, out, (size_t)1 << nq, on_device);
+  return on_device ? CCUT_OK : finish_out(c, res, out, (size_t)1 << nq, on_device);
 }
 
 ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t *masks, uint32_t n_strings,
@@ -1210,7 +1211,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   }
   if ((st = join(c)) != CCUT_OK) return st;
   RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
-  double *res = aget<double>(c, n_strings);
+  double *res = on_device ? out : aget<double>(c, n_strings);  // a device output receives the sums directly
   const uint32_t zsplits = zrecombine_splits(pd.k, n_strings);
   double *zpart = aget<double>(c, (size_t)zsplits * n_strings);
   if (!dargs || !res || !zpart) return fail(c, CCUT_E_OOM, "device allocation failed");
@@ -1219,7 +1220,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
     HIP_TRY(c, launch_zrecombine(dargs, pd.k, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM, zpart, zsplits,
                                  res, c->cur));
   }
-  return finish_out(c, res, out, n_strings, on_device);
+  return on_device ? CCUT_OK : finish_out(c, res, out, n_strings, on_device);
 }
 
 }  // namespace

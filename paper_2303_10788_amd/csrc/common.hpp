@@ -307,7 +307,8 @@ struct RecombArgs {
   uint32_t k;
   RecombFrag f[kMaxFrags];
 };
-hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *out, hipStream_t s);
+hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uint32_t nq, double *out,
+                                 hipStream_t s);
 // Z strings: fp64 products and sum, or (fp32 = true) fp32 products summed
 // in fp32 over chunks of 32 terms and in fp64 across chunks.
 uint32_t zrecombine_splits(uint32_t k, uint32_t n_strings);

@@ -155,6 +155,59 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
   outp[b] = ldexp(acc, -(int)k);
 }
 
+// The same for at most 8 fragments, with the same operations in the same
+// order: per chunk of 128 terms the column offsets p_f(P) * rows_f are
+// computed once per workgroup into LDS, each thread keeps its rows in
+// registers, and the term loop is unrolled so the gathers overlap.
+constexpr uint32_t kRcFrags = 8, kRcChunk = 128;
+__global__ __launch_bounds__(kRcChunk) void recombine_small_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
+                                                                   double *__restrict__ outp) {
+  __shared__ uint64_t s_off[kRcFrags][kRcChunk];
+  __shared__ const double *s_T[kRcFrags];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t b = (uint64_t)blockIdx.x * kRcChunk + tid;
+  const bool live = b < (1ull << nq);
+  const uint32_t nf = A->n_frags, k = A->k;
+  if (tid < nf) s_T[tid] = A->f[tid].T;
+  uint32_t row[kRcFrags];
+#pragma unroll
+  for (uint32_t f = 0; f < kRcFrags; ++f) {
+    uint32_t r = 0;
+    if (f < nf)
+      for (uint32_t i = 0; i < A->f[f].n_req; ++i) r |= (uint32_t)((b >> A->f[f].req_user[i]) & 1ull) << i;
+    row[f] = r;
+  }
+  const uint64_t nterms = 1ull << (2 * k);
+  double acc = 0.0;
+  for (uint64_t P0 = 0; P0 < nterms; P0 += kRcChunk) {
+    const uint32_t cn = (uint32_t)(nterms - P0 < kRcChunk ? nterms - P0 : kRcChunk);
+    __syncthreads();  // the previous chunk is consumed
+    if (tid < cn) {
+      const uint64_t P = P0 + tid;
+      for (uint32_t f = 0; f < nf; ++f) {
+        const RecombFrag &F = A->f[f];
+        uint32_t p = 0;
+        for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+        s_off[f][tid] = (uint64_t)p * F.rows;
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+    const double *T[kRcFrags];
+#pragma unroll
+    for (uint32_t f = 0; f < kRcFrags; ++f) T[f] = f < nf ? s_T[f] + row[f] : nullptr;
+#pragma unroll 4
+    for (uint32_t t = 0; t < cn; ++t) {
+      double term = 1.0;
+#pragma unroll
+      for (uint32_t f = 0; f < kRcFrags; ++f)
+        if (f < nf) term *= T[f][s_off[f][t]];
+      acc += term;
+    }
+  }
+  if (live) outp[b] = ldexp(acc, -(int)k);
+}
+
 // <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s].  fp64: products and sum in
 // fp64, P ascending.  fp32: every factor split into fp32 parts t = hi + lo,
 // the product taken in fp32 to first order (prod hi + sum_f lo_f prod_{g!=f}
@@ -229,9 +282,13 @@ hipError_t launch_transform_all(const TransformAll &a, const double *in, double 
   return hipGetLastError();
 }
 
-hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t nq, double *out, hipStream_t s) {
+hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uint32_t nq, double *out,
+                                 hipStream_t s) {
   const uint64_t n = 1ull << nq;
-  hipLaunchKernelGGL(recombine_fp64_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, d_args, nq, out);
+  if (n_frags <= kRcFrags)
+    hipLaunchKernelGGL(recombine_small_kernel, dim3(blocks_for(n, kRcChunk)), dim3(kRcChunk), 0, s, d_args, nq, out);
+  else
+    hipLaunchKernelGGL(recombine_fp64_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, d_args, nq, out);
   return hipGetLastError();
 }
 
