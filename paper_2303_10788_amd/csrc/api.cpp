@@ -1217,8 +1217,8 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   if (!dargs || !res || !zpart) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
     KTimer t(c, CCUT_K_ZRECOMBINE);
-    HIP_TRY(c, launch_zrecombine(dargs, pd.k, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM, zpart, zsplits,
-                                 res, c->cur));
+    HIP_TRY(c, launch_zrecombine(dargs, args.n_frags, pd.k, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM,
+                                 zpart, zsplits, res, c->cur));
   }
   return on_device ? CCUT_OK : finish_out(c, res, out, n_strings, on_device);
 }

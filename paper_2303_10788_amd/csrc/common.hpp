@@ -312,8 +312,8 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uin
 // Z strings: fp64 products and sum, or (fp32 = true) fp32 products summed
 // in fp32 over chunks of 32 terms and in fp64 across chunks.
 uint32_t zrecombine_splits(uint32_t k, uint32_t n_strings);
-hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t k, uint32_t n_strings, bool fp32, double *partial,
-                             uint32_t splits, double *out, hipStream_t s);
+hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t n_frags, uint32_t k, uint32_t n_strings, bool fp32,
+                             double *partial, uint32_t splits, double *out, hipStream_t s);
 
 // Recombination as a dense contraction A (row fragments) x B^T (column
 // fragments) over the 4^k cut terms, split along K.

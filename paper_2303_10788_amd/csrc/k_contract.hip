@@ -252,6 +252,75 @@ __global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_s
   partial[(uint64_t)blockIdx.y * n_strings + s] = acc;
 }
 
+// The same for at most 8 fragments (same operations, same order): the
+// column offsets of each chunk of 64 terms are computed once per workgroup
+// into LDS; with a single term range the result is written directly
+// (scaled by 2^-k) and no final pass is needed.
+template <bool F32>
+__global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings,
+                                                              uint64_t per_split, double *__restrict__ partial,
+                                                              double *__restrict__ direct) {
+  __shared__ uint64_t s_off[kRcFrags][64];
+  __shared__ const double *s_T[kRcFrags];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t s = blockIdx.x * 64 + tid;
+  const bool live = s < n_strings;
+  const uint32_t nf = A->n_frags, k = A->k;
+  if (tid < nf) s_T[tid] = A->f[tid].T;
+  const uint64_t nterms = 1ull << (2 * k);
+  const uint64_t P0 = (uint64_t)blockIdx.y * per_split;
+  const uint64_t P1 = P0 + per_split < nterms ? P0 + per_split : nterms;
+  double acc = 0.0;
+  float chunk = 0.f;
+  for (uint64_t C0 = P0; C0 < P1; C0 += 64) {
+    const uint32_t cn = (uint32_t)(P1 - C0 < 64 ? P1 - C0 : 64);
+    __syncthreads();  // the previous chunk is consumed
+    if (tid < cn) {
+      const uint64_t P = C0 + tid;
+      for (uint32_t f = 0; f < nf; ++f) {
+        const RecombFrag &F = A->f[f];
+        uint32_t p = 0;
+        for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+        s_off[f][tid] = (uint64_t)p * F.rows;
+      }
+    }
+    __syncthreads();
+    if (!live) continue;
+#pragma unroll 4
+    for (uint32_t t = 0; t < cn; ++t) {
+      const uint64_t P = C0 + t;
+      double term = 1.0;
+      float hi = 1.f, corr = 0.f;
+#pragma unroll
+      for (uint32_t f = 0; f < kRcFrags; ++f) {
+        if (f >= nf) continue;
+        const double v = s_T[f][s_off[f][t] + s];
+        if (F32) {
+          const float th = (float)v, tl = (float)(v - (double)th);
+          corr = corr * th + hi * tl;
+          hi *= th;
+        } else {
+          term *= v;
+        }
+      }
+      if (F32) {
+        chunk += hi + corr;
+        if ((P & 7) == 7 || P + 1 == P1) {
+          acc += (double)chunk;
+          chunk = 0.f;
+        }
+      } else {
+        acc += term;
+      }
+    }
+  }
+  if (!live) return;
+  if (direct)
+    direct[s] = ldexp(acc, -(int)k);
+  else
+    partial[(uint64_t)blockIdx.y * n_strings + s] = acc;
+}
+
 // out[s] = 2^-k sum over term ranges in order
 __global__ void zrecombine_final_kernel(const double *__restrict__ partial, uint32_t n_strings, uint32_t splits,
                                         uint32_t k, double *__restrict__ outp) {
@@ -302,12 +371,24 @@ uint32_t zrecombine_splits(uint32_t k, uint32_t n_strings) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(sp, 65535));
 }
 
-hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t k, uint32_t n_strings, bool fp32, double *partial,
-                             uint32_t splits, double *out, hipStream_t s) {
+hipError_t launch_zrecombine(const RecombArgs *d_args, uint32_t n_frags, uint32_t k, uint32_t n_strings, bool fp32,
+                             double *partial, uint32_t splits, double *out, hipStream_t s) {
   const uint64_t nterms = 1ull << (2 * k);
   uint64_t per = (nterms + splits - 1) / splits;
   per = (per + 7) & ~7ull;
   const dim3 grid(blocks_for(n_strings, 64), splits);
+  if (n_frags <= kRcFrags) {
+    double *direct = splits == 1 ? out : nullptr;
+    if (fp32)
+      hipLaunchKernelGGL(zrecombine_small_kernel<true>, grid, dim3(64), 0, s, d_args, n_strings, per, partial, direct);
+    else
+      hipLaunchKernelGGL(zrecombine_small_kernel<false>, grid, dim3(64), 0, s, d_args, n_strings, per, partial, direct);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || direct) return e;
+    hipLaunchKernelGGL(zrecombine_final_kernel, dim3(blocks_for(n_strings, 64)), dim3(64), 0, s, partial, n_strings,
+                       splits, k, out);
+    return hipGetLastError();
+  }
   if (fp32)
     hipLaunchKernelGGL((zrecombine_kernel<true>), grid, dim3(64), 0, s, d_args, n_strings, per, partial);
   else
