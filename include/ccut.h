@@ -326,6 +326,21 @@ ccut_status ccut_learned_estimate(ccut_learned *L, const double *q, uint64_t n, 
 ccut_status ccut_learned_exhaustive(ccut_learned *L, double *out, int on_device);
 void ccut_learned_destroy(ccut_learned *L);
 
+/* The whole learned path of one marginal request (Sec. V-C importance
+ * sampling with the network as proposal): fragment tensors as
+ * ccut_learned_create (eo as there), logits of `mlp` over all 4^k terms, q
+ * with eps = 0.05, n_terms (1 <= n_terms < 2^32) terms drawn with
+ * seed = eo->seed and cid = eo->circuit, and the estimate into out[2^nq]
+ * (host, or device when out_on_device).  When out_stderr_l1 (host) is not
+ * NULL it receives sum_b se_b, se_b = sqrt(max(0, M2_b - R_hat[b]^2 / N))
+ * with M2_b = (1/N^2) sum_j (w_{P_j}(b) / q(P_j))^2: the plug-in standard
+ * error of each estimated entry, summed over b (one more term-list
+ * contraction of squared operands, then a synchronization).  Temporary
+ * state lives only for the call; mlp keeps its parameters. */
+ccut_status ccut_learned_marginal(ccut_plan *plan, const ccut_eval_opts *eo, ccut_mlp *mlp, uint64_t n_terms,
+                                  const uint32_t *qubits, uint32_t nq, double *out, int out_on_device,
+                                  double *out_stderr_l1);
+
 /* q[K] (fp64) from logits[K] (fp32), or uniform when logits is NULL. */
 ccut_status ccut_proposal(ccut_ctx *ctx, const float *logits, uint64_t K, double eps, double *q);
 /* n terms drawn from q[K] as above (device u64 out[n]). */
@@ -354,6 +369,12 @@ ccut_status ccut_mlp_gradients(ccut_mlp *M, const uint16_t *x, const float *t, u
  * entries) may be NULL. */
 ccut_status ccut_mlp_train(ccut_mlp *M, const uint16_t *x, const float *t, uint64_t n, uint32_t batch,
                            uint32_t steps, float lr, uint64_t seed, float *losses);
+/* One Adam step (as ccut_mlp_train) on the whole batch x[n][F] (fp32,
+ * device; rounded to bf16 to nearest-even before the products), t[n] (fp32,
+ * device), rows in order; n % 64 == 0, n <= 2^24.  loss (host, may be
+ * NULL) receives the batch's mean squared error before the step.  Equals
+ * ccut_mlp_train(batch = n, steps = 1) on the bf16-rounded rows. */
+ccut_status ccut_mlp_train_step(ccut_mlp *M, const float *x, const float *t, uint64_t n, float lr, float *loss);
 void ccut_mlp_destroy(ccut_mlp *M);
 
 /* ---------------------------------------------------------------- timing */

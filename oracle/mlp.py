@@ -139,6 +139,21 @@ def is_estimate(term_weight, terms, q):
     return acc / len(terms)
 
 
+def is_stderr_l1(term_weight, terms, q):
+    """Summed plug-in standard error of R_hat: with Y_j = w_{P_j} / q(P_j),
+    se[b] = sqrt(max(0, (1/N^2) sum_j Y_j[b]^2 - R_hat[b]^2 / N)), the
+    square root of the population variance of the Y_j[b] over N; returns
+    sum_b se[b]."""
+    N = len(terms)
+    s1 = s2 = None
+    for P in terms:
+        v = term_weight(int(P)) / q[P]
+        s1 = v if s1 is None else s1 + v
+        s2 = v * v if s2 is None else s2 + v * v
+    est = s1 / N
+    return float(np.sum(np.sqrt(np.maximum(0.0, s2 / (N * N) - est * est / N))))
+
+
 # ------------------------------------------------------ term model inputs
 
 FEATURE_FLOOR = -40.0

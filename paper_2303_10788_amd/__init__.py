@@ -116,6 +116,8 @@ SIGNATURES = {
     "ccut_learned_estimate": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, _P, ctypes.c_int, _P], ctypes.c_int),
     "ccut_learned_exhaustive": ([_P, _P, ctypes.c_int], ctypes.c_int),
     "ccut_learned_destroy": ([_P], None),
+    "ccut_learned_marginal": ([_P, ctypes.POINTER(ccut_eval_opts), _P, ctypes.c_uint64, _U32P, ctypes.c_uint32, _P,
+                               ctypes.c_int, _DP], ctypes.c_int),
     "ccut_proposal": ([_P, _P, ctypes.c_uint64, ctypes.c_double, _P], ctypes.c_int),
     "ccut_sample_terms": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _P],
                           ctypes.c_int),
@@ -126,6 +128,8 @@ SIGNATURES = {
     "ccut_mlp_gradients": ([_P, _P, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float), _DP], ctypes.c_int),
     "ccut_mlp_train": ([_P, _P, _P, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
                         ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)], ctypes.c_int),
+    "ccut_mlp_train_step": ([_P, _P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.POINTER(ctypes.c_float)],
+                            ctypes.c_int),
     "ccut_mlp_destroy": ([_P], None),
 }
 
@@ -461,6 +465,16 @@ class Plan:
         ccut_marginal(self.handle, self.ctx.handle, eo, qubits, out)
         return out
 
+    def learned_marginal(self, mlp, qubits, n_terms, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO,
+                         out=None):
+        """Importance-sampled marginal with `mlp` as the term proposal:
+        (estimate, summed standard error of its entries)."""
+        eo = _eval_opts(shots, seed, CCUT_FP64, circuit, method)
+        if out is None:
+            out = np.zeros(1 << len(qubits), dtype=np.float64)
+        se = ccut_learned_marginal(self.handle, self.ctx.handle, eo, mlp.handle, n_terms, qubits, out)
+        return out, se
+
     def zexpect(self, masks, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,
                 out=None):
         masks = np.asarray(masks, dtype=np.uint64)
@@ -586,6 +600,15 @@ def ccut_learned_destroy(L) -> None:
     lib().ccut_learned_destroy(L)
 
 
+def ccut_learned_marginal(plan, ctx, eo, mlp, n_terms, qubits, out, want_stderr=True):
+    q, qp = _u32(qubits)
+    p, dev = _out_ptr(out)
+    se = ctypes.c_double()
+    _check(lib().ccut_learned_marginal(plan, ctypes.byref(eo), mlp, n_terms, qp, len(q), p, dev,
+                                       ctypes.byref(se) if want_stderr else None), ctx)
+    return se.value if want_stderr else None
+
+
 def ccut_proposal(ctx, logits, K, eps, q):
     _check(lib().ccut_proposal(ctx, _dptr(logits), K, eps, _dptr(q)), ctx)
 
@@ -629,6 +652,12 @@ def ccut_mlp_train(M, ctx, x, t, n, batch, steps, lr, seed):
     _check(lib().ccut_mlp_train(M, _dptr(x), _dptr(t), n, batch, steps, lr, int(seed) & 0xFFFFFFFFFFFFFFFF,
                                 losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), ctx)
     return losses[:steps]
+
+
+def ccut_mlp_train_step(M, ctx, x, t, n, lr):
+    loss = ctypes.c_float()
+    _check(lib().ccut_mlp_train_step(M, _dptr(x), _dptr(t), n, lr, ctypes.byref(loss)), ctx)
+    return loss.value
 
 
 def ccut_mlp_destroy(M) -> None:
@@ -680,6 +709,10 @@ class Mlp:
 
     def train(self, x, t, *, batch, steps, lr=1e-3, seed=0):
         return ccut_mlp_train(self.handle, self.ctx.handle, x, t, x.shape[0], batch, steps, lr, seed)
+
+    def train_step(self, x, t, lr=1e-3):
+        """One Adam step on the whole batch x (fp32 [n][F], rounded to bf16), t [n]."""
+        return ccut_mlp_train_step(self.handle, self.ctx.handle, x, t, x.shape[0], lr)
 
     def close(self):
         if getattr(self, "handle", None):

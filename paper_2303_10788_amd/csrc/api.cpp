@@ -2280,11 +2280,14 @@ ccut_status ccut_learned_support(ccut_learned *L, uint64_t cap, uint64_t *terms,
   return sync_call(c);
 }
 
-ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
-  if (!L || !M) return CCUT_E_INVALID;
+}  // extern "C"
+
+namespace {
+// The network's logits over every term of L, enqueued on the context's
+// stream (no synchronization).
+ccut_status learned_logits_enqueue(ccut_learned *L, ccut_mlp *M, float *logits) {
   ccut_ctx *c = L->ctx;
-  ccut_status st = begin_call(c);
-  if (st != CCUT_OK) return st;
+  ccut_status st;
   if (!logits) return fail(c, CCUT_E_INVALID, "logits is NULL");
   if (M->ctx != c || M->F != L->width) return fail(c, CCUT_E_INVALID, "network input width differs from the features");
   if (M->F == 64 && M->H == 256) {  // the whole pass in one launch, activations on chip
@@ -2303,7 +2306,7 @@ ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
       KTimer t(c, CCUT_K_MLP);
       HIP_TRY(c, launch_mlp_logits_fused(L->d, net, 0, L->K, kLabelScale, logits, c->cur));
     }
-    return sync_call(c);
+    return CCUT_OK;
   }
   const uint64_t chunk = std::min<uint64_t>(L->K, 1ull << 18);
   if ((st = mlp_ensure_work(M, std::max<uint64_t>(chunk, 64))) != CCUT_OK) return st;
@@ -2317,6 +2320,19 @@ ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
     }
     if ((st = mlp_forward_rows(M, x, rows, logits + first, kLabelScale)) != CCUT_OK) return st;
   }
+  return CCUT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *M, float *logits) {
+  if (!L || !M) return CCUT_E_INVALID;
+  ccut_ctx *c = L->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if ((st = learned_logits_enqueue(L, M, logits)) != CCUT_OK) return st;
   return sync_call(c);
 }
 
@@ -2404,6 +2420,92 @@ void ccut_learned_destroy(ccut_learned *L) {
   ccut_ctx *c = L->ctx;
   delete L;
   ctx_release(c);
+}
+
+ccut_status ccut_learned_marginal(ccut_plan *p, const ccut_eval_opts *eo, ccut_mlp *net, uint64_t n_terms,
+                                  const uint32_t *qubits, uint32_t nq, double *out, int out_on_device,
+                                  double *out_stderr_l1) {
+  if (!p || !eo || !net) return CCUT_E_INVALID;
+  ccut_ctx *c = p->ctx;
+  if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
+  if (n_terms == 0 || n_terms > 0xFFFFFFFFull) return fail(c, CCUT_E_INVALID, "n_terms must be in [1, 2^32)");
+  ccut_learned *L = nullptr;
+  ccut_status st = ccut_learned_create(p, eo, qubits, nq, &L);
+  if (st != CCUT_OK) return st;
+  std::unique_ptr<ccut_learned, void (*)(ccut_learned *)> hold(L, ccut_learned_destroy);
+  if ((st = begin_call(c)) != CCUT_OK) return st;
+  const uint64_t K = L->K, bins = 1ull << L->nq;
+  const uint32_t nb = reduce_blocks(K);
+  float *logits = aget<float>(c, K), *mpart = aget<float>(c, nb);
+  double *q = aget<double>(c, K), *spart = aget<double>(c, nb), *stats = aget<double>(c, 2);
+  uint64_t *terms = aget<uint64_t>(c, n_terms);
+  double *scale = aget<double>(c, n_terms), *res = aget<double>(c, bins);
+  double *res2 = out_stderr_l1 ? aget<double>(c, bins) : nullptr;
+  if (!logits || !mpart || !q || !spart || !stats || !terms || !scale || !res || (out_stderr_l1 && !res2))
+    return fail(c, CCUT_E_OOM, "device allocation failed");
+  if ((st = learned_logits_enqueue(L, net, logits)) != CCUT_OK) return st;
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_proposal(logits, K, 0.05, mpart, spart, stats, q, c->cur));
+  }
+  if ((st = draw_terms(c, q, K, n_terms, eo->seed, L->circuit, terms)) != CCUT_OK) return st;
+  {
+    KTimer t(c, CCUT_K_TERMS);
+    HIP_TRY(c, launch_is_scale(terms, q, n_terms, scale, c->cur));
+  }
+  GemmArgs g;
+  make_gemm_args(L->args, g);
+  g.terms = terms;
+  g.tscale = scale;
+  g.K = n_terms;
+  if ((st = run_gemm(c, g, false, res)) != CCUT_OK) return st;
+  if (out_stderr_l1) {
+    // second moment: res2 = 2^-k sum_j (w_j / (N q_j))^2 2^2k, so with
+    // Y_j the j-th term of the estimate, sum_j Y_j^2 = 2^-k res2 and the
+    // standard error of entry b is sqrt(sum_j Y_j^2 - est_b^2 / N)
+    g.square = 1;
+    if ((st = run_gemm(c, g, false, res2)) != CCUT_OK) return st;
+    std::vector<double> e(bins), e2(bins);
+    HIP_TRY(c, hipMemcpyAsync(e.data(), res, bins * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(e2.data(), res2, bins * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double l1 = 0.0;
+    for (uint64_t b = 0; b < bins; ++b)
+      l1 += std::sqrt(std::max(0.0, std::ldexp(e2[b], -(int)L->k) - e[b] * e[b] / (double)n_terms));
+    *out_stderr_l1 = l1;
+  }
+  return finish_out(c, res, out, bins, out_on_device);
+}
+
+ccut_status ccut_mlp_train_step(ccut_mlp *M, const float *x, const float *t, uint64_t n, float lr, float *loss) {
+  if (!M) return CCUT_E_INVALID;
+  ccut_ctx *c = M->ctx;
+  ccut_status st = begin_call(c);
+  if (st != CCUT_OK) return st;
+  if (!x || !t) return fail(c, CCUT_E_INVALID, "NULL argument");
+  if (n == 0 || n % 64 || n > (1u << 24)) return fail(c, CCUT_E_INVALID, "n must be a positive multiple of 64, at most 2^24");
+  if ((st = mlp_ensure_work(M, n)) != CCUT_OK) return st;
+  float *lsum = aget<float>(c, 1);
+  if (!lsum) return fail(c, CCUT_E_OOM, "device allocation failed");
+  // the batch is every row, in order: features rounded to bf16, targets as given
+  HIP_TRY(c, launch_to_bf16(x, M->xb, n * M->F, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(M->tb, t, n * 4, hipMemcpyDeviceToDevice, c->stream));
+  if ((st = mlp_forward_rows(M, M->xb, n, M->y)) != CCUT_OK) return st;
+  if ((st = mlp_backward_rows(M, M->xb, M->tb, n, lsum)) != CCUT_OK) return st;
+  M->t += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)M->t));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)M->t));
+  {
+    KTimer tm(c, CCUT_K_MLP);
+    HIP_TRY(c, launch_adam(M->p, M->g, M->m, M->v, M->pb, M->n_params, lr, 0.9f, 0.999f, c1, c2, 1e-8f, c->stream));
+  }
+  if (loss) {
+    HIP_TRY(c, hipMemcpyAsync(loss, lsum, 4, hipMemcpyDeviceToHost, c->stream));
+    if ((st = sync_call(c)) != CCUT_OK) return st;
+    *loss /= (float)n;
+    return CCUT_OK;
+  }
+  return sync_call(c);
 }
 
 }  // extern "C"

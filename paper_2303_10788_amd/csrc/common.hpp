@@ -330,6 +330,7 @@ struct GemmArgs {
   // term's row-side value is multiplied by tscale[kk] when set
   const uint64_t *terms;
   const double *tscale;
+  uint32_t square;  // 1: every operand value squared (second moment of the sampled estimate)
   GemmSide L, R;
   uint32_t ident[kMaxFrags];  // 1 if the fragment's axes are cuts 0..k-1 in order (p_f(P) = P)
   RecombFrag f[kMaxFrags];

@@ -16,7 +16,9 @@
 //  - FP64 MFMA (v_mfma_f64_16x16x4_f64) end to end (reference path).
 // Split-K partials are summed in fp64 in split order by a second kernel.
 // With a term list the K index runs over sampled terms P_j, each row-side
-// value scaled by its importance weight (the estimator of the same sum).
+// value scaled by its importance weight (the estimator of the same sum);
+// with `square` every operand value is squared first, which gives the sum
+// of the squared sampled terms (the estimator's second moment).
 #include <algorithm>
 
 #include "common.hpp"
@@ -85,6 +87,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
       if (m < M && j < k1) {
         a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
         if (G->tscale) a *= G->tscale[j];
+        if (G->square) a *= a;
       }
       As[kk][mm] = (TS)a;
       if constexpr (F32) Al[kk][mm] = (float)(a - (double)(float)a);
@@ -93,7 +96,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
       const uint32_t kk = e / NT, nn = e % NT;
       const uint32_t n = tn * NT + nn;
       const uint64_t j = kb + kk;
-      const double b = (n < N && j < k1) ? side_value(G, G->R, n, G->terms ? G->terms[j] : j) : 0.0;
+      double b = (n < N && j < k1) ? side_value(G, G->R, n, G->terms ? G->terms[j] : j) : 0.0;
+      if (G->square) b *= b;
       Bs[kk][nn] = (TS)b;
       if constexpr (F32) Bl[kk][nn] = (float)(b - (double)(float)b);
     }

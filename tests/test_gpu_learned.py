@@ -261,6 +261,64 @@ def test_is_estimate_vs_oracle(ctx, case):
     assert abs(est.sum() - 1.0) < 0.5  # an unbiased estimate of a distribution
 
 
+@pytest.mark.parametrize("case", CASES[:2])
+def test_learned_marginal_vs_oracle(ctx, case):
+    """One call through the whole learned path: network logits, q, the
+    draw and the contraction.  The oracle takes the same q (from the
+    kernel's logits; the network itself is checked against the oracle
+    elsewhere), draws the same terms and forms the estimate and its
+    standard error in fp64."""
+    import torch
+    ops, cuts, qubits = _small(case)
+    k = len(cuts)
+    _log(f"learned marginal {case} k={k}")
+    R, parts = C.marginal(10, ops, cuts, qubits, return_parts=True)
+    plan = cc.Plan(ctx, 10, ops, cuts)
+    net = cc.Mlp(ctx, 64, 256)
+    # a damped head keeps the logits' spread a few units (an untrained
+    # network at full scale puts nearly all mass on one term, and a draw can
+    # then miss the whole support)
+    params = _random_net(64, 256, 5 + case[1])
+    params[-1] = (params[-1][0] * 0.02, params[-1][1] * 0.0)
+    net.set_params(cc.mlp_pack(params))
+    n, s = 2000, 31
+    est, se = plan.learned_marginal(net, qubits, n, seed=s, circuit=9)
+    L = cc.Learned(plan, qubits, seed=s, circuit=9)
+    logits = L.logits(net).cpu().numpy().astype(np.float64)
+    q = O.proposal(logits)
+    tref = O.sample_terms(O.integer_cdf(q), n, seed=s, cid=9)
+    tw = lambda P: O.term_vector(parts["frags"], parts["reqs"], parts["tensors"], k, P, len(qubits))
+    ref = O.is_estimate(tw, tref, q)
+    ref_se = O.is_stderr_l1(tw, tref, q)
+    assert np.abs(est - ref).max() <= 1e-10
+    assert abs(se - ref_se) <= 1e-9 * max(ref_se, 1.0)
+    # device output: the same values
+    out = torch.empty(1 << len(qubits), dtype=torch.float64, device="cuda")
+    _, se2 = plan.learned_marginal(net, qubits, n, seed=s, circuit=9, out=out)
+    assert np.array_equal(out.cpu().numpy(), est) and se2 == se
+    # the estimate is within a few standard errors of the exact marginal
+    assert se > 0 and np.abs(est - R).sum() <= 6 * se
+
+
+def test_train_step_equals_one_train_step(ctx):
+    import torch
+    F, H, n = 64, 128, 256
+    rng = np.random.default_rng(8)
+    x = torch.tensor(rng.integers(0, 2, size=(n, F)).astype(np.float32)).cuda()
+    t = torch.tensor(rng.normal(size=n).astype(np.float32)).cuda()
+    p0 = cc.mlp_pack(_random_net(F, H, 4))
+    a, b = cc.Mlp(ctx, F, H), cc.Mlp(ctx, F, H)
+    a.set_params(p0)
+    b.set_params(p0)
+    for step in range(3):
+        la = a.train_step(x, t, lr=1e-3)
+        lb = b.train(x.to(torch.bfloat16), t, batch=n, steps=1, lr=1e-3)[0]
+        assert la == lb, step
+        assert np.array_equal(a.get_params(), b.get_params()), step
+    with pytest.raises(cc.CcutError):
+        a.train_step(x[:100], t[:100])
+
+
 # ------------------------------------------------------------ the gain
 
 def _dataset(ctx, seeds, n_support=1024, n_shares=2048, n_uniform=1024):

@@ -97,6 +97,38 @@ def test_exact_proposal_gives_zero_variance_estimator():
     assert np.isclose(est[0], w.sum())
 
 
+def test_is_stderr_matches_population_std():
+    # the summed standard error is sum_b std_pop(Y[:, b]) / sqrt(N) with
+    # Y_j = w_{P_j} / q(P_j): numpy's standard deviation of the same draws
+    rng = np.random.default_rng(12)
+    K, nb = 64, 8
+    w = rng.normal(size=(K, nb)) * (rng.random(K) < 0.5)[:, None]
+    q = mlp.proposal(rng.normal(size=K))
+    terms = mlp.sample_terms(mlp.integer_cdf(q), 500, seed=4, cid=2)
+    Y = np.array([w[P] / q[P] for P in terms])
+    ref = np.sum(Y.std(axis=0) / np.sqrt(len(terms)))
+    assert np.isclose(mlp.is_stderr_l1(lambda P: w[P], terms, q), ref, rtol=1e-10)
+
+
+def test_is_stderr_predicts_spread_and_vanishes_for_exact_proposal():
+    rng = np.random.default_rng(13)
+    K, nb = 64, 4
+    w = rng.normal(size=(K, nb))
+    q = mlp.proposal(rng.normal(size=K))
+    cdf = mlp.integer_cdf(q)
+    ests, ses = [], []
+    for s in range(80):
+        t = mlp.sample_terms(cdf, 300, seed=s, cid=0)
+        ests.append(mlp.is_estimate(lambda P: w[P], t, q))
+        ses.append(mlp.is_stderr_l1(lambda P: w[P], t, q))
+    spread = np.sum(np.std(ests, axis=0, ddof=1))
+    assert 0.7 < np.mean(ses) / spread < 1.3
+    # zero-variance proposal (q proportional to |w|, one output, one sign)
+    w1 = np.array([0.0, 2.0, 0.0, 1.0, 1.0])
+    q1 = w1 / w1.sum()
+    assert mlp.is_stderr_l1(lambda P: np.array([w1[P]]), [1, 3, 4, 1], q1) < 1e-12
+
+
 # ---------------------------------------------------------- term model inputs
 
 def _small_cut_parts(seed=3):
