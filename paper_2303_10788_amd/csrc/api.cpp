@@ -501,17 +501,90 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
 // Per-axis Pauli-basis passes: data[v][x] -> T[p_f][rest], where rest is
 // the x part with the output bits removed (mode 1) or the J part consumed
 // (mode 2, parity tables laid out [v][J][string]).
+// Tile plan of a fragment's marginal-mode transform (variant data in, T out):
+// false when the fragment has no axes, more than kMaxTileAxes, or variant
+// data per x_out entry beyond kTileElems.
+bool tile_job(const Fragment &f, const FragRequest &r, const double *in, uint64_t xsize, double *out, TileJob &J) {
+  const uint32_t a = (uint32_t)f.axes.size();
+  if (a == 0 || a > (uint32_t)kMaxTileAxes) return false;
+  J = TileJob{};
+  uint64_t V = 1;
+  uint32_t n_out = 0;
+  std::vector<uint32_t> outpos;
+  for (uint32_t j = 0; j < a; ++j) {
+    const bool is_out = f.axes[j].side == 0;
+    J.rad[j] = is_out ? 3u : 4u;
+    V *= J.rad[j];
+    if (is_out) {
+      ++n_out;
+      outpos.push_back((uint32_t)r.axis_outpos[j]);
+    }
+  }
+  if ((V << n_out) > kTileElems) return false;
+  uint32_t xb = 0;  // log2 of x_in
+  while ((1ull << xb) < xsize) ++xb;
+  const uint32_t xo_bits = xb - n_out;
+  uint32_t t = std::min<uint32_t>(xo_bits, kTileMaxT);
+  while ((V << (n_out + t)) > kTileElems) --t;
+  std::sort(outpos.begin(), outpos.end());
+  auto is_out_pos = [&](uint32_t p) { return std::binary_search(outpos.begin(), outpos.end(), p); };
+  uint32_t p = 0, cnt = 0;
+  while (cnt < t) {
+    if (!is_out_pos(p)) J.xpos[cnt++] = p;
+    ++p;
+  }
+  const uint32_t thr = p;
+  uint32_t nh = 0;
+  for (uint32_t q : outpos)
+    if (q >= thr) J.hpos[nh++] = q;
+  for (uint32_t j = 0; j < a; ++j) {
+    if (J.rad[j] != 3) continue;
+    const uint32_t q = (uint32_t)r.axis_outpos[j];
+    uint32_t lp = q;
+    if (q >= thr) {
+      lp = thr;
+      while (J.hpos[lp - thr] != q) ++lp;
+    }
+    J.lpos[j] = lp;
+  }
+  J.in = in;
+  J.out = out;
+  J.x_in = xsize;
+  J.x_out = xsize >> n_out;
+  J.tiles = (uint32_t)(J.x_out >> t);
+  J.n_axes = a;
+  J.v_count = (uint32_t)V;
+  J.t = t;
+  J.thr = thr;
+  J.nh = nh;
+  J.lbits = thr + nh;
+  return true;
+}
+
 ccut_status pauli_passes(ccut_ctx *c, const Fragment &f, const FragRequest &r, double *data,
                          uint64_t xsize, uint64_t mode2_lo, double **out) {
   const uint32_t a = (uint32_t)f.axes.size();
-  // Small tensors (up to 3 axes, at most 27 terms per entry, at most 2^16
-  // entries out) take all passes in one launch: there the launches, not the
-  // arithmetic, are the cost; larger ones take the per-axis passes, which
-  // read each entry a bounded number of times.
+  if (!mode2_lo && a) {
+    // every axis in one launch, through LDS tiles (the passes' arithmetic)
+    TileJob J;
+    if (tile_job(f, r, data, xsize, nullptr, J)) {
+      J.out = aget<double>(c, J.x_out << (2 * a));
+      TileJob *dj = J.out ? (TileJob *)upload(c, &J, sizeof(J)) : nullptr;
+      if (!dj) return fail(c, CCUT_E_OOM, "device allocation failed");
+      KTimer t(c, CCUT_K_TRANSFORM);
+      HIP_TRY(c, launch_transform_tiled(dj, 1, J.tiles, c->cur));
+      *out = J.out;
+      return CCUT_OK;
+    }
+  }
+  // String-selection tables that are small (up to 3 axes, at most 27 terms
+  // per entry, at most 2^16 entries out) take all axes in one launch: there
+  // the launches, not the arithmetic, are the cost; the rest take the
+  // per-axis passes, which read each entry a bounded number of times.
   uint64_t n_out_axes = 0;
   for (const Axis &ax : f.axes) n_out_axes += ax.side == 0;
   const uint64_t entries_out = (mode2_lo ? mode2_lo : xsize >> n_out_axes) << (2 * a);
-  if (a >= 2 && a <= 3 && entries_out <= (1ull << 16)) {
+  if (mode2_lo && a >= 2 && a <= 3 && entries_out <= (1ull << 16)) {
     TransformAll A{};
     A.n_axes = a;
     A.x_in = xsize;
@@ -664,13 +737,16 @@ void make_gemm_args(const RecombArgs &args, GemmArgs &g) {
   g.N = 1u << args.f[rf].n_req;
 }
 
-ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res) {
-  const uint32_t splits = gemm_splits(g);
+// allow_skinny: exhaustive contractions with at most 32 rows take the
+// skinny kernel (term-list estimates always take the MFMA tiles)
+ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res, bool allow_skinny = false) {
+  const bool skinny = allow_skinny && contraction_skinny(g, fp32);
+  const uint32_t splits = contraction_splits(g, skinny);
   GemmArgs *dg = (GemmArgs *)upload(c, &g, sizeof(g));
   double *partial = aget<double>(c, (size_t)splits * g.M * g.N);
   if (!dg || !partial) return fail(c, CCUT_E_OOM, "device allocation failed");
   KTimer t(c, CCUT_K_RECOMBINE);
-  HIP_TRY(c, launch_recombine_gemm(g, dg, fp32, partial, splits, res, c->cur));
+  HIP_TRY(c, launch_recombine_gemm(g, dg, fp32, partial, splits, res, c->cur, skinny));
   return CCUT_OK;
 }
 
@@ -688,7 +764,7 @@ ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp3
   }
   GemmArgs g;
   make_gemm_args(args, g);
-  return run_gemm(c, g, fp32, res);
+  return run_gemm(c, g, fp32, res, true);
 }
 
 bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo) {
@@ -1366,7 +1442,7 @@ struct ccut_batch {
   // independent per-plan steps run on a pool of streams (default priority),
   // forked from and joined back into the batch stream
   std::vector<hipStream_t> pool;
-  hipEvent_t fork_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, sv_ev = nullptr;
   std::vector<hipEvent_t> join_ev;
   std::vector<uint32_t> wlist[4];
   uint32_t wrows[4] = {0, 0, 0, 0};
@@ -1386,6 +1462,7 @@ struct ccut_batch {
     for (auto ps : pool) (void)hipStreamDestroy(ps);
     for (auto e : join_ev) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (sv_ev) (void)hipEventDestroy(sv_ev);
     if (stream) (void)hipStreamDestroy(stream);
     arena.release();
   }
@@ -1512,6 +1589,12 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   // shape; the per-plan steps below start from these tables
   std::vector<std::vector<double *>> pre_dist(b->plans.size());
   for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+  // the state vectors (pool stream 0) run beside the sampling (batch stream)
+  const bool sv_side = !b->nc.empty() && !b->pool.empty();
+  if (sv_side) {
+    HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+    HIP_TRY(c, hipStreamWaitEvent(b->pool[0], b->fork_ev, 0));
+  }
   if (!b->samp.empty()) {
     const uint64_t shots = b->eo.shots_per_variant;
     const uint64_t nquads = (shots + 3) / 4;
@@ -1571,6 +1654,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     HIP_TRY(c, launch_sample_batch(d_jobs, (uint32_t)jobs.size(), wg, lds_bytes, t, c->cur));
   }
   if (!b->nc.empty()) {
+    if (sv_side) c->cur = b->pool[0];
     FragDev *d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
     if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
     for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
@@ -1602,33 +1686,157 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       KTimer tm(c, CCUT_K_SV);
       HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
     }
+    c->cur = b->stream;
+    if (sv_side) {
+      HIP_TRY(c, hipEventRecord(b->sv_ev, b->pool[0]));
+      HIP_TRY(c, hipStreamWaitEvent(b->stream, b->sv_ev, 0));
+    }
   }
-  // the plans' remaining steps are independent: plan i runs on pool stream
-  // i mod P, after the shared tableau launch, and every pool stream joins
-  // back before the batch stream continues
-  const size_t P = b->pool.size();
+  // The plans' remaining steps.  Work that the batched launches below do
+  // not cover (Heisenberg tensors, tables outside the pre-pass, transforms
+  // too large to tile, contractions of more than 8 fragments) runs per plan,
+  // plan i on pool stream i mod P; then, on the batch stream, one tiled
+  // transform launch for every other fragment, one plain and one MFMA
+  // contraction launch for all plans.  Each plan takes the same transform
+  // and contraction as a call of its own, so the results are the same bits.
+  const size_t P = b->pool.size(), np = b->plans.size();
   HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
   for (size_t k = 0; k < P; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
-  for (size_t i = 0; i < b->plans.size(); ++i) {
+  const bool fp32 = b->eo.precision == CCUT_FP32_MFMA_FP64SUM;
+  std::vector<TileJob> tjobs;
+  std::vector<RecombArgs> rargs(np);
+  std::vector<uint8_t> kind(np);  // 0 plain (batched), 1 plain (own launch), 2 MFMA
+  for (size_t i = 0; i < np; ++i) {
     ccut_plan *p = b->plans[i];
+    const PlanData &pd = p->pd;
+    if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
     ccut_eval_opts eo = b->eo;
     eo.circuit = (uint32_t)i;
-    std::vector<uint64_t *> pre(p->pd.frags.size(), nullptr);
-    for (size_t f = 0; f < pre.size(); ++f)
-      if (b->model_off[i][f] >= 0) pre[f] = d_models + b->model_off[i][f];
-    double *res = aget<double>(c, (size_t)1 << b->qubits[i].size());
+    const uint32_t *qubits = b->qubits[i].data();
+    const uint32_t nq = (uint32_t)b->qubits[i].size();
+    double *res = aget<double>(c, (size_t)1 << nq);
     if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (b->res.size() <= i) b->res.push_back(res);
     b->res[i] = res;
+    RecombArgs &args = rargs[i];
+    args = RecombArgs{};
+    args.n_frags = (uint32_t)pd.frags.size();
+    args.k = pd.k;
     c->stream = c->cur = P ? b->pool[i % P] : b->stream;
-    st = marginal_enqueue(p, &eo, b->qubits[i].data(), (uint32_t)b->qubits[i].size(), res, &pre, &pre_dist[i]);
+    for (const Fragment &f : pd.frags) {
+      FragRequest r = marginal_request(f, qubits, nq);
+      double *T = nullptr;
+      if (use_heisenberg(f, &eo)) {
+        st = heis_tensor(p, f, r, eo.circuit, nullptr, &T);
+      } else {
+        double *dist = pre_dist[i][f.index];
+        uint64_t *pm = b->model_off[i][f.index] >= 0 ? d_models + b->model_off[i][f.index] : nullptr;
+        st = dist ? CCUT_OK : variant_dists(p, &eo, f, r, &dist, pm);
+        const uint64_t xsize = 1ull << r.meas.size();
+        TileJob J;
+        if (st == CCUT_OK && !f.axes.empty() && tile_job(f, r, dist, xsize, nullptr, J)) {
+          J.out = T = aget<double>(c, J.x_out << (2 * f.axes.size()));
+          if (!T) st = fail(c, CCUT_E_OOM, "device allocation failed");
+          tjobs.push_back(J);
+        } else if (st == CCUT_OK) {
+          st = pauli_passes(c, f, r, dist, xsize, 0, &T);
+        }
+      }
+      if (st != CCUT_OK) break;
+      RecombFrag &rf = args.f[f.index];
+      rf.T = T;
+      rf.n_axes = (uint32_t)f.axes.size();
+      rf.rows = 1u << r.req_pos.size();
+      rf.n_req = (uint32_t)r.req_pos.size();
+      for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
+      for (size_t q = 0; q < r.req_user.size(); ++q) rf.req_user[q] = r.req_user[q];
+    }
     c->stream = c->cur = b->stream;
     if (st != CCUT_OK) return st;
+    // the contraction recombine() would take
+    const uint64_t K = 1ull << (2 * pd.k);
+    kind[i] = (!fp32 && (K << nq) <= (1ull << 20)) ? (args.n_frags <= 8 ? 0 : 1) : 2;
   }
   for (size_t k = 0; k < P; ++k) {
     HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
     HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
   }
+  if (!tjobs.empty()) {
+    uint64_t wg = 0;
+    for (TileJob &J : tjobs) {
+      J.wg0 = wg;
+      wg += J.tiles;
+    }
+    TileJob *d_t = (TileJob *)upload(c, tjobs.data(), tjobs.size() * sizeof(TileJob));
+    if (!d_t) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_TRANSFORM);
+    HIP_TRY(c, launch_transform_tiled(d_t, (uint32_t)tjobs.size(), wg, c->cur));
+  }
+  // contractions: the plain ones' arguments in one upload, the MFMA ones'
+  // operand descriptions in another
+  std::vector<RecombArgs> plain;
+  std::vector<size_t> plain_of(np, 0);
+  std::vector<GemmArgs> gargs;
+  for (size_t i = 0; i < np; ++i) {
+    if (kind[i] < 2) {
+      plain_of[i] = plain.size();
+      plain.push_back(rargs[i]);
+    } else {
+      gargs.emplace_back();
+      make_gemm_args(rargs[i], gargs.back());
+    }
+  }
+  RecombArgs *d_plain = plain.empty() ? nullptr : (RecombArgs *)upload(c, plain.data(), plain.size() * sizeof(RecombArgs));
+  GemmArgs *d_gargs = gargs.empty() ? nullptr : (GemmArgs *)upload(c, gargs.data(), gargs.size() * sizeof(GemmArgs));
+  if ((!plain.empty() && !d_plain) || (!gargs.empty() && !d_gargs)) return fail(c, CCUT_E_OOM, "device allocation failed");
+  std::vector<RcJob> rjobs;
+  std::vector<GemmJob> gjobs[2];  // MFMA tiles, skinny
+  uint64_t rwg = 0, gwg[2] = {0, 0}, grwg[2] = {0, 0};
+  for (size_t i = 0, g = 0; i < np; ++i) {
+    const uint32_t nq = (uint32_t)b->qubits[i].size();
+    if (kind[i] == 0) {
+      RcJob J{};
+      J.args = d_plain + plain_of[i];
+      J.out = b->res[i];
+      J.nq = nq;
+      J.wg0 = rwg;
+      rwg += ((1ull << nq) + kRcChunkOut - 1) / kRcChunkOut;
+      rjobs.push_back(J);
+    } else if (kind[i] == 2) {
+      const GemmArgs &h = gargs[g];
+      const bool sk = contraction_skinny(h, fp32);
+      GemmJob J{};
+      J.args = d_gargs + g;
+      J.splits = contraction_splits(h, sk);
+      J.tiles = gemm_tiles(h, sk);
+      J.k_per_split = gemm_k_per_split(h, J.splits, sk);
+      J.partial = aget<double>(c, (size_t)J.splits * h.M * h.N);
+      if (!J.partial) return fail(c, CCUT_E_OOM, "device allocation failed");
+      J.out = b->res[i];
+      J.wg0 = gwg[sk];
+      J.rwg0 = grwg[sk];
+      gwg[sk] += (uint64_t)J.tiles * J.splits;
+      grwg[sk] += ((uint64_t)h.M * h.N + 255) / 256;
+      gjobs[sk].push_back(J);
+      ++g;
+    }
+  }
+  KTimer t(c, CCUT_K_RECOMBINE);
+  if (!rjobs.empty()) {
+    RcJob *d_r = (RcJob *)upload(c, rjobs.data(), rjobs.size() * sizeof(RcJob));
+    if (!d_r) return fail(c, CCUT_E_OOM, "device allocation failed");
+    HIP_TRY(c, launch_recombine_batch(d_r, (uint32_t)rjobs.size(), rwg, c->cur));
+  }
+  for (int sk = 0; sk < 2; ++sk) {
+    if (gjobs[sk].empty()) continue;
+    GemmJob *d_g = (GemmJob *)upload(c, gjobs[sk].data(), gjobs[sk].size() * sizeof(GemmJob));
+    if (!d_g) return fail(c, CCUT_E_OOM, "device allocation failed");
+    HIP_TRY(c, launch_gemm_batch(d_g, (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32, sk == 1, c->cur));
+  }
+  for (size_t i = 0; i < np; ++i)
+    if (kind[i] == 1)
+      HIP_TRY(c, launch_recombine_fp64(d_plain + plain_of[i], rargs[i].n_frags, (uint32_t)b->qubits[i].size(),
+                                       b->res[i], c->cur));
   return CCUT_OK;
 }
 
@@ -1702,6 +1910,7 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
   });
   HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&b->sv_ev, hipEventDisableTiming));
   for (size_t k = 0; k < std::min<size_t>(n, 8); ++k) {
     hipStream_t ps = nullptr;
     hipEvent_t je = nullptr;

@@ -214,6 +214,18 @@ struct SvJob {
   double *dist;
 };
 
+// The job whose range [start, next start) holds idx (starts ascending, first 0).
+template <class J, class F>
+__device__ inline uint32_t find_job(const J *jobs, uint32_t n, uint64_t idx, F start) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (start(jobs[mid]) <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
@@ -277,6 +289,29 @@ struct TransformAll {
   uint64_t n_strings;       // mode 2: x_in = J * n_strings + x_out, bit t of J = t-th output axis
 };
 hipError_t launch_transform_all(const TransformAll &a, const double *in, double *out, hipStream_t s);
+
+// Pauli transform of one fragment's variant tables, tiled through LDS: the
+// per-axis passes (same operations, same axis order as the pass kernel) on
+// a tile of 2^t output entries at a time, all axes in one launch.  The
+// variant data of a tile (v_count x 2^lbits doubles, the outcome bits of the
+// output axes inside) must fit kTileElems.  Layout of a tile's x: the x_in
+// bits below thr, then the outcome bits at x_in positions hpos[0..nh).
+constexpr int kMaxTileAxes = 8;
+constexpr uint32_t kTileElems = 8192, kTileMaxT = 8;
+struct TileJob {
+  const double *in;
+  double *out;
+  uint64_t x_in, x_out;
+  uint64_t wg0;                 // first workgroup of the job in a batched launch
+  uint32_t tiles;               // x_out >> t
+  uint32_t n_axes, v_count, t, thr, nh, lbits, pad_;
+  uint32_t rad[kMaxTileAxes];   // 4 quantum input, 3 quantum output
+  uint32_t lpos[kMaxTileAxes];  // output axis: its outcome bit's position in the tile's x
+  uint32_t hpos[kMaxTileAxes];  // x_in positions of the outcome bits at or above thr, ascending
+  uint32_t xpos[kTileMaxT];     // the t positions below thr that carry the tile's x_out bits, ascending
+};
+hipError_t launch_transform_tiled(const TileJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s);
+
 hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, uint64_t inner_digits,
                                  uint64_t xsize_in, uint64_t lo, int mode, hipStream_t s);
 
@@ -309,6 +344,16 @@ struct RecombArgs {
 };
 hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uint32_t nq, double *out,
                                  hipStream_t s);
+// Batched plain fp64 recombination (at most 8 fragments per job): job j's
+// workgroups [wg0, next wg0) cover its 2^nq outputs, 128 per workgroup.
+struct RcJob {
+  const RecombArgs *args;
+  double *out;
+  uint64_t wg0;
+  uint32_t nq, pad_;
+};
+hipError_t launch_recombine_batch(const RcJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s);
+constexpr uint32_t kRcChunkOut = 128;  // outputs per workgroup of the plain recombination
 // Z strings: fp64 products and sum, or (fp32 = true) fp32 products summed
 // in fp32 over chunks of 32 terms and in fp64 across chunks.
 uint32_t zrecombine_splits(uint32_t k, uint32_t n_strings);
@@ -336,8 +381,28 @@ struct GemmArgs {
   RecombFrag f[kMaxFrags];
 };
 uint32_t gemm_splits(const GemmArgs &h);
+// fp64 contractions with at most 32 rows take the skinny kernel (one
+// column per thread, products summed in ascending term order) instead of
+// 64 x 64 MFMA tiles; tiles, splits and the K range per split of either
+bool contraction_skinny(const GemmArgs &h, bool fp32);
+uint32_t gemm_tiles(const GemmArgs &h, bool skinny);
+uint32_t contraction_splits(const GemmArgs &h, bool skinny);
+uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny);
+// Batched contractions (one precision per launch): job j's workgroups
+// [wg0, next wg0) are tiles x splits of its product, its reduction
+// workgroups (256 outputs each) [rwg0, next rwg0).
+struct GemmJob {
+  const GemmArgs *args;
+  double *partial;
+  double *out;
+  uint64_t wg0, rwg0, k_per_split;
+  uint32_t tiles, splits;
+};
+hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
+                             bool skinny, hipStream_t s);
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
-                                 uint32_t splits, double *out, hipStream_t s);
+                                 uint32_t splits, double *out, hipStream_t s,
+                                 bool skinny = false);
 
 
 // ------------------------------------------------- learned term proposal

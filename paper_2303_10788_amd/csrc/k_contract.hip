@@ -13,6 +13,10 @@
 
 #include "common.hpp"
 
+// products and sums exactly as written (no contraction into fma), so every
+// kernel that shares a body computes the same bits
+#pragma clang fp contract(off)
+
 namespace ccut {
 
 namespace {
@@ -128,6 +132,102 @@ __global__ void transform_all_kernel(const TransformAll A, const double *__restr
   out[i] = acc;
 }
 
+// The per-axis passes on LDS tiles.  Workgroup = one tile of 2^t output
+// entries x of one job.  The tile's variant data (every variant digit,
+// every outcome bit of the output axes) is staged in LDS as
+// s[v][l], v mixed radix over the axes (axis 0 fastest), l the tile's x
+// (x_in bits below thr, then the high outcome bits).  Each pass rewrites its
+// axis in place, group by group, with the operations of the pass kernel:
+// an input axis keeps its four slots (I, X, Y, Z); an output axis reads its
+// six (basis X, Y, Z x outcome 0, 1) and leaves I, X, Y in the outcome-0
+// slots of bases X, Y, Z and Z in the outcome-1 slot of basis X.
+constexpr uint32_t kTileThreads = 256;
+__global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const TileJob *__restrict__ jobs,
+                                                                       uint32_t n_jobs) {
+  __shared__ double s[kTileElems];
+  __shared__ uint32_t s_xdep[1u << kTileMaxT];
+  const uint32_t jb = find_job(jobs, n_jobs, blockIdx.x, [](const TileJob &J) { return J.wg0; });
+  const TileJob &J = jobs[jb];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t u = blockIdx.x - J.wg0;  // tile index: the x_out bits above t
+  const uint32_t a = J.n_axes, V = J.v_count, lb = J.lbits, t = J.t, thr = J.thr, nh = J.nh;
+  const uint32_t XL = 1u << lb, XT = 1u << t;
+  // the tile's fixed x_in bits: u deposited into the non-outcome positions from thr up
+  uint64_t base = 0;
+  {
+    uint64_t rest = u;
+    uint32_t hi = 0;
+    for (uint32_t p = thr; rest; ++p) {
+      if (hi < nh && J.hpos[hi] == p) {
+        ++hi;
+        continue;
+      }
+      base |= (rest & 1ull) << p;
+      rest >>= 1;
+    }
+  }
+  for (uint32_t xo = tid; xo < XT; xo += kTileThreads) {
+    uint32_t l = 0;
+    for (uint32_t i = 0; i < t; ++i) l |= ((xo >> i) & 1u) << J.xpos[i];
+    s_xdep[xo] = l;
+  }
+  const uint32_t lowmask = (1u << thr) - 1u;
+  const uint32_t n_el = V << lb;
+  for (uint32_t e = tid; e < n_el; e += kTileThreads) {
+    const uint32_t v = e >> lb, l = e & (XL - 1u);
+    uint64_t x = base | (l & lowmask);
+    for (uint32_t i = 0; i < nh; ++i) x |= (uint64_t)((l >> (thr + i)) & 1u) << J.hpos[i];
+    s[e] = J.in[(uint64_t)v * J.x_in + x];
+  }
+  __syncthreads();
+  uint32_t R = 1;  // product of the radices of the axes below j
+  for (uint32_t j = 0; j < a; ++j) {
+    const uint32_t S = R << lb;  // slot stride of axis j's digit
+    if (J.rad[j] == 4) {
+      for (uint32_t g = tid; g < (n_el >> 2); g += kTileThreads) {
+        const uint32_t b = (g / S) * 4 * S + g % S;
+        const double p0 = s[b], p1 = s[b + S], pp = s[b + 2 * S], pi = s[b + 3 * S];
+        s[b] = p0 + p1;
+        s[b + S] = 2.0 * pp - p0 - p1;
+        s[b + 2 * S] = 2.0 * pi - p0 - p1;
+        s[b + 3 * S] = p0 - p1;
+      }
+    } else {
+      const uint32_t lp = J.lpos[j], half = XL >> 1, o1 = 1u << lp;
+      for (uint32_t g = tid; g < (V / 3) * half; g += kTileThreads) {
+        const uint32_t li = g % half, vg = g / half;
+        const uint32_t l = ((li >> lp) << (lp + 1)) | (li & (o1 - 1u));
+        const uint32_t b = (((vg / R) * 3 * R + vg % R) << lb) | l;
+        const double x0 = s[b], x1 = s[b + o1], y0 = s[b + S], y1 = s[b + S + o1];
+        const double z0 = s[b + 2 * S], z1 = s[b + 2 * S + o1];
+        s[b] = z0 + z1;
+        s[b + S] = x0 - x1;
+        s[b + 2 * S] = y0 - y1;
+        s[b + o1] = z0 - z1;
+      }
+    }
+    R *= J.rad[j];
+    __syncthreads();
+  }
+  // out[P][x_out], P base 4 (axis 0 fastest), x_out = u 2^t + xo
+  const uint32_t n_out = XT << (2 * a);
+  for (uint32_t e = tid; e < n_out; e += kTileThreads) {
+    const uint32_t xo = e & (XT - 1u), P = e >> t;
+    uint32_t v = 0, l = s_xdep[xo], Rj = 1;
+    for (uint32_t j = 0; j < a; ++j) {
+      const uint32_t p = (P >> (2 * j)) & 3u;
+      if (J.rad[j] == 4) {
+        v += p * Rj;
+      } else {
+        v += (p == 3 ? 0u : p) * Rj;
+        if (p == 3) l |= 1u << J.lpos[j];
+      }
+      Rj *= J.rad[j];
+    }
+    J.out[(uint64_t)P * J.x_out + (u << t) + xo] = s[(v << lb) | l];
+  }
+}
+
 // R[b] = 2^-k sum_P prod_f T_f[p_f(P)][b_f(b)], P ascending, fragments in order.
 __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
                                       double *__restrict__ outp) {
@@ -159,13 +259,13 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
 // order: per chunk of 128 terms the column offsets p_f(P) * rows_f are
 // computed once per workgroup into LDS, each thread keeps its rows in
 // registers, and the term loop is unrolled so the gathers overlap.
-constexpr uint32_t kRcFrags = 8, kRcChunk = 128;
-__global__ __launch_bounds__(kRcChunk) void recombine_small_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
-                                                                   double *__restrict__ outp) {
+constexpr uint32_t kRcFrags = 8, kRcChunk = kRcChunkOut;
+__device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, uint32_t nq,
+                                            double *__restrict__ outp, uint64_t blk) {
   __shared__ uint64_t s_off[kRcFrags][kRcChunk];
   __shared__ const double *s_T[kRcFrags];
   const uint32_t tid = threadIdx.x;
-  const uint64_t b = (uint64_t)blockIdx.x * kRcChunk + tid;
+  const uint64_t b = blk * kRcChunk + tid;
   const bool live = b < (1ull << nq);
   const uint32_t nf = A->n_frags, k = A->k;
   if (tid < nf) s_T[tid] = A->f[tid].T;
@@ -206,6 +306,17 @@ __global__ __launch_bounds__(kRcChunk) void recombine_small_kernel(const RecombA
     }
   }
   if (live) outp[b] = ldexp(acc, -(int)k);
+}
+
+__global__ __launch_bounds__(kRcChunk) void recombine_small_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
+                                                                   double *__restrict__ outp) {
+  recombine_small_body(A, nq, outp, blockIdx.x);
+}
+
+// Many plans' plain recombinations in one launch.
+__global__ __launch_bounds__(kRcChunk) void recombine_batch_kernel(const RcJob *__restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const RcJob &J) { return J.wg0; });
+  recombine_small_body(jobs[j].args, jobs[j].nq, jobs[j].out, blockIdx.x - jobs[j].wg0);
 }
 
 // <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s].  fp64: products and sum in
@@ -358,6 +469,20 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uin
     hipLaunchKernelGGL(recombine_small_kernel, dim3(blocks_for(n, kRcChunk)), dim3(kRcChunk), 0, s, d_args, nq, out);
   else
     hipLaunchKernelGGL(recombine_fp64_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, d_args, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_recombine_batch(const RcJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s) {
+  if (n_jobs == 0 || total_wg == 0) return hipSuccess;
+  if (total_wg > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(recombine_batch_kernel, dim3((unsigned)total_wg), dim3(kRcChunk), 0, s, d_jobs, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform_tiled(const TileJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s) {
+  if (n_jobs == 0 || total_wg == 0) return hipSuccess;
+  if (total_wg > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transform_tiled_kernel, dim3((unsigned)total_wg), dim3(kTileThreads), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
 }
 

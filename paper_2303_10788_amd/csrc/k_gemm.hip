@@ -23,6 +23,8 @@
 
 #include "common.hpp"
 
+#pragma clang fp contract(off)
+
 namespace ccut {
 
 namespace {
@@ -50,9 +52,11 @@ __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSi
   return v;
 }
 
+// One 64 x 64 output tile (tile index `tile`, M tiles fastest) over the
+// K range of split `split`, into partial[split][M][N].
 template <bool F32>
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
-                                                            double *__restrict__ partial) {
+__device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
+                                 uint32_t tile, uint32_t split) {
   typedef typename std::conditional<F32, float, double>::type TS;
   __shared__ TS As[KC][MT + 1];
   __shared__ TS Bs[KC][NT + 1];
@@ -61,8 +65,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
   const uint32_t M = G->M, N = G->N;
   const uint64_t K = G->K;
   const uint32_t tilesM = (M + MT - 1) / MT;
-  const uint32_t tm = blockIdx.x % tilesM, tn = blockIdx.x / tilesM;
-  const uint64_t k0 = (uint64_t)blockIdx.y * k_per_split;
+  const uint32_t tm = tile % tilesM, tn = tile / tilesM;
+  const uint64_t k0 = (uint64_t)split * k_per_split;
   const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
     }
     __syncthreads();
   }
-  double *dst = partial + (uint64_t)blockIdx.y * M * N;
+  double *dst = partial + (uint64_t)split * M * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -159,10 +163,82 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
       }
 }
 
+template <bool F32>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
+                                                            double *__restrict__ partial) {
+  gemm_body<F32>(G, k_per_split, partial, blockIdx.x, blockIdx.y);
+}
+
+// Many contractions in one launch: workgroup x runs tile (x - wg0) mod
+// tiles, split (x - wg0) / tiles of the job holding x.
+template <bool F32>
+__global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
+  const GemmJob &J = jobs[j];
+  const uint64_t local = blockIdx.x - J.wg0;
+  gemm_body<F32>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles));
+}
+
+// Skinny contraction (M <= SK_M rows, fp64): one output column n per
+// thread with all M rows in registers; the row-side values of a K chunk are
+// staged in LDS.  partial[split][m][n] = sum over the split's terms, in
+// ascending order, of a(m, P) * b(n, P) (each product rounded, then added).
+constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
+__device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
+                                   uint32_t tile, uint32_t split) {
+  __shared__ double As[SK_KC][SK_M];
+  const uint32_t M = G->M, N = G->N, tid = threadIdx.x;
+  const uint64_t K = G->K;
+  const uint32_t n = tile * SK_N + tid;
+  const uint64_t k0 = (uint64_t)split * k_per_split;
+  const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
+  double acc[SK_M];
+#pragma unroll
+  for (uint32_t m = 0; m < SK_M; ++m) acc[m] = 0.0;
+  for (uint64_t kb = k0; kb < k1; kb += SK_KC) {
+    const uint32_t kn = (uint32_t)std::min<uint64_t>(SK_KC, k1 - kb);
+    __syncthreads();  // the previous chunk is consumed
+    for (uint32_t e = tid; e < kn * M; e += SK_N) {
+      const uint32_t kk = e / M, m = e % M;
+      const uint64_t j = kb + kk;
+      double a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+      if (G->tscale) a *= G->tscale[j];
+      if (G->square) a *= a;
+      As[kk][m] = a;
+    }
+    __syncthreads();
+    if (n >= N) continue;
+    for (uint32_t kk = 0; kk < kn; ++kk) {
+      const uint64_t j = kb + kk;
+      double b = side_value(G, G->R, n, G->terms ? G->terms[j] : j);
+      if (G->square) b *= b;
+#pragma unroll
+      for (uint32_t m = 0; m < SK_M; ++m)
+        if (m < M) acc[m] += As[kk][m] * b;
+    }
+  }
+  if (n >= N) return;
+  double *dst = partial + (uint64_t)split * M * N;
+#pragma unroll
+  for (uint32_t m = 0; m < SK_M; ++m)
+    if (m < M) dst[(uint64_t)m * N + n] = acc[m];
+}
+
+__global__ __launch_bounds__(SK_N) void skinny_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
+                                                      double *__restrict__ partial) {
+  skinny_body(G, k_per_split, partial, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(SK_N) void skinny_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
+  const GemmJob &J = jobs[j];
+  const uint64_t local = blockIdx.x - J.wg0;
+  skinny_body(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles));
+}
+
 // out[b(m, n)] = 2^-k sum_split partial[split][m][n], splits in order
-__global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
-                                   uint32_t splits, double *__restrict__ out) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void gemm_reduce_body(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
+                                        uint32_t splits, double *__restrict__ out, uint64_t i) {
   const uint64_t MN = (uint64_t)G->M * G->N;
   if (i >= MN) return;
   double s = 0.0;
@@ -182,6 +258,17 @@ __global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double 
   out[b] = ldexp(s, -(int)G->k);
 }
 
+__global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
+                                   uint32_t splits, double *__restrict__ out) {
+  gemm_reduce_body(G, partial, splits, out, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ void gemm_reduce_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
+  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.rwg0; });
+  const GemmJob &J = jobs[j];
+  gemm_reduce_body(J.args, J.partial, J.splits, J.out, (blockIdx.x - J.rwg0) * 256ull + threadIdx.x);
+}
+
 }  // namespace
 
 uint32_t gemm_splits(const GemmArgs &h) {
@@ -192,12 +279,51 @@ uint32_t gemm_splits(const GemmArgs &h) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
 }
 
+bool contraction_skinny(const GemmArgs &h, bool fp32) { return !fp32 && h.M <= SK_M; }
+
+uint32_t gemm_tiles(const GemmArgs &h, bool skinny) {
+  if (skinny) return (h.N + SK_N - 1) / SK_N;
+  return ((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
+}
+
+uint32_t contraction_splits(const GemmArgs &h, bool skinny) {
+  if (!skinny) return gemm_splits(h);
+  const uint64_t tiles = gemm_tiles(h, true);
+  const uint64_t kchunks = (h.K + SK_KC - 1) / SK_KC;
+  uint64_t s = std::max<uint64_t>(1, 1024 / std::max<uint64_t>(tiles, 1));
+  s = std::min<uint64_t>(s, kchunks);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
+}
+
+uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny) {
+  const uint64_t kc = skinny ? SK_KC : KC;
+  const uint64_t kchunks = (h.K + kc - 1) / kc;
+  return ((kchunks + splits - 1) / splits) * kc;
+}
+
+hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
+                             bool skinny, hipStream_t s) {
+  if (n_jobs == 0 || total_wg == 0) return hipSuccess;
+  if (total_wg > 0x7FFFFFFFull || total_rwg > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  if (skinny)
+    hipLaunchKernelGGL(skinny_batch_kernel, dim3((unsigned)total_wg), dim3(SK_N), 0, s, d_jobs, n_jobs);
+  else if (fp32)
+    hipLaunchKernelGGL((gemm_batch_kernel<true>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
+  else
+    hipLaunchKernelGGL((gemm_batch_kernel<false>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gemm_reduce_batch_kernel, dim3((unsigned)total_rwg), dim3(256), 0, s, d_jobs, n_jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
-                                 uint32_t splits, double *out, hipStream_t s) {
-  const uint32_t tiles = ((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
-  const uint64_t kchunks = (h.K + KC - 1) / KC;
-  const uint64_t k_per_split = ((kchunks + splits - 1) / splits) * KC;
-  if (fp32)
+                                 uint32_t splits, double *out, hipStream_t s, bool skinny) {
+  const uint32_t tiles = gemm_tiles(h, skinny);
+  const uint64_t k_per_split = gemm_k_per_split(h, splits, skinny);
+  if (skinny)
+    hipLaunchKernelGGL(skinny_kernel, dim3(tiles, splits), dim3(SK_N), 0, s, d_args, k_per_split, partial);
+  else if (fp32)
     hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
                        partial);
   else

@@ -94,18 +94,6 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
               s_model);
 }
 
-// The job whose range [start, next start) holds idx (starts ascending, first 0).
-template <class J, class F>
-__device__ inline uint32_t find_job(const J *jobs, uint32_t n, uint64_t idx, F start) {
-  uint32_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (start(jobs[mid]) <= idx) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // Many fragments' sampling in one launch: workgroup x runs block
 // (x - wg0) mod nblk of variant (x - wg0) / nblk of the job holding x.
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,

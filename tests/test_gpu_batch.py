@@ -5,7 +5,7 @@ import pytest
 
 import paper_2303_10788_amd as cc
 import workloads as W
-from oracle import cutting as C
+from oracle import cutting as C, statevector as SV
 
 pytestmark = pytest.mark.gpu
 
@@ -75,3 +75,21 @@ def test_run_batch_one_shot(ctx):
     cc.ccut_run_batch(ctx.handle, plans, cc._eval_opts(0, 0), [w.qubits for w in ws], outs)
     for i, (p, w) in enumerate(zip(plans, ws)):
         assert np.abs(outs[i] - p.marginal(w.qubits, circuit=i)).max() <= 1e-12
+
+
+def test_skinny_contraction_vs_uncut_state_vector(ctx):
+    """A 20-qubit circuit of the batching shape with 3 cuts and its 16-qubit
+    marginal: 4^3 terms x 2^16 outputs with 8 rows on the non-Clifford side
+    take the skinny fp64 contraction, per plan and in a batch; the uncut
+    brute-force state vector is the reference."""
+    w = W.batching_circuit(230, shots=0)
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    k, nq = len(w.cuts), len(w.qubits)
+    reqs = [cc.ccut_request_info(plan.handle, w.qubits, f)[1] for f in range(len(plan.fragments()))]
+    assert (4 ** k) << nq > (1 << 20) and 1 << (sum(reqs) - max(reqs)) <= 32
+    print(f"skinny contraction: n={w.n} k={k} requested bits {reqs}", flush=True)
+    ref = SV.uncut_marginal(w.n, w.ops, w.qubits)
+    got = plan.marginal(w.qubits)
+    assert np.abs(got - ref).max() <= 1e-10
+    out = cc.Batch(ctx, [plan], [w.qubits]).run()[0]
+    assert np.array_equal(out, got)
