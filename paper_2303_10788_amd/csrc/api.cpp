@@ -547,6 +547,11 @@ bool tile_job(const Fragment &f, const FragRequest &r, const double *in, uint64_
     }
     J.lpos[j] = lp;
   }
+  uint64_t Rj = 1;
+  for (uint32_t j = 0; j < a; ++j) {
+    J.rmag[j] = Rj == 1 ? 0u : (uint32_t)((1ull << 32) / Rj + 1);
+    Rj *= J.rad[j];
+  }
   J.in = in;
   J.out = out;
   J.x_in = xsize;

@@ -297,7 +297,7 @@ hipError_t launch_transform_all(const TransformAll &a, const double *in, double 
 // output axes inside) must fit kTileElems.  Layout of a tile's x: the x_in
 // bits below thr, then the outcome bits at x_in positions hpos[0..nh).
 constexpr int kMaxTileAxes = 8;
-constexpr uint32_t kTileElems = 8192, kTileMaxT = 8;
+constexpr uint32_t kTileElems = 4096, kTileMaxT = 8;
 struct TileJob {
   const double *in;
   double *out;
@@ -309,6 +309,7 @@ struct TileJob {
   uint32_t lpos[kMaxTileAxes];  // output axis: its outcome bit's position in the tile's x
   uint32_t hpos[kMaxTileAxes];  // x_in positions of the outcome bits at or above thr, ascending
   uint32_t xpos[kTileMaxT];     // the t positions below thr that carry the tile's x_out bits, ascending
+  uint32_t rmag[kMaxTileAxes];  // floor(2^32 / R_j) + 1, R_j the product of the radices below axis j (0: R_j = 1)
 };
 hipError_t launch_transform_tiled(const TileJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s);
 

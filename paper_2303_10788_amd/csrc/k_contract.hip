@@ -173,19 +173,40 @@ __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const Til
   }
   const uint32_t lowmask = (1u << thr) - 1u;
   const uint32_t n_el = V << lb;
-  for (uint32_t e = tid; e < n_el; e += kTileThreads) {
-    const uint32_t v = e >> lb, l = e & (XL - 1u);
-    uint64_t x = base | (l & lowmask);
-    for (uint32_t i = 0; i < nh; ++i) x |= (uint64_t)((l >> (thr + i)) & 1u) << J.hpos[i];
-    s[e] = J.in[(uint64_t)v * J.x_in + x];
+  // every load of a thread issued before its first LDS store
+  constexpr uint32_t kPer = kTileElems / kTileThreads;
+  double vals[kPer];
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t e = tid + i * kTileThreads;
+    if (e < n_el) {
+      const uint32_t v = e >> lb, l = e & (XL - 1u);
+      uint64_t x = base | (l & lowmask);
+      for (uint32_t h = 0; h < nh; ++h) x |= (uint64_t)((l >> (thr + h)) & 1u) << J.hpos[h];
+      vals[i] = J.in[(uint64_t)v * J.x_in + x];
+    }
+  }
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t e = tid + i * kTileThreads;
+    if (e < n_el) s[e] = vals[i];
   }
   __syncthreads();
   uint32_t R = 1;  // product of the radices of the axes below j
   for (uint32_t j = 0; j < a; ++j) {
     const uint32_t S = R << lb;  // slot stride of axis j's digit
+    const uint32_t mag = J.rmag[j];
+    // g = q S + r: q = (g >> lb) / R by multiply-high (exact for g < 2^19)
+    auto split = [&](uint32_t g, uint32_t &q, uint32_t &r) {
+      const uint32_t gh = g >> lb;
+      q = mag ? __umulhi(gh, mag) : gh;
+      r = ((gh - q * R) << lb) | (g & (XL - 1u));
+    };
     if (J.rad[j] == 4) {
       for (uint32_t g = tid; g < (n_el >> 2); g += kTileThreads) {
-        const uint32_t b = (g / S) * 4 * S + g % S;
+        uint32_t q, r;
+        split(g, q, r);
+        const uint32_t b = q * 4 * S + r;
         const double p0 = s[b], p1 = s[b + S], pp = s[b + 2 * S], pi = s[b + 3 * S];
         s[b] = p0 + p1;
         s[b + S] = 2.0 * pp - p0 - p1;
@@ -195,9 +216,10 @@ __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const Til
     } else {
       const uint32_t lp = J.lpos[j], half = XL >> 1, o1 = 1u << lp;
       for (uint32_t g = tid; g < (V / 3) * half; g += kTileThreads) {
-        const uint32_t li = g % half, vg = g / half;
+        const uint32_t li = g & (half - 1u), vg = g >> (lb - 1);
         const uint32_t l = ((li >> lp) << (lp + 1)) | (li & (o1 - 1u));
-        const uint32_t b = (((vg / R) * 3 * R + vg % R) << lb) | l;
+        const uint32_t vq = mag ? __umulhi(vg, mag) : vg;
+        const uint32_t b = ((vq * 3 * R + (vg - vq * R)) << lb) | l;
         const double x0 = s[b], x1 = s[b + o1], y0 = s[b + S], y1 = s[b + S + o1];
         const double z0 = s[b + 2 * S], z1 = s[b + 2 * S + o1];
         s[b] = z0 + z1;

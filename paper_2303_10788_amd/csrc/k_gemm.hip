@@ -184,20 +184,41 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob 
 // staged in LDS.  partial[split][m][n] = sum over the split's terms, in
 // ascending order, of a(m, P) * b(n, P) (each product rounded, then added).
 constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
+template <uint32_t MC>
+__device__ inline void skinny_rows(const double (*__restrict__ As)[SK_M], const uint64_t *__restrict__ s_boff,
+                                   const double *__restrict__ Tn, uint32_t kn, bool square, double *acc) {
+#pragma unroll 4
+  for (uint32_t kk = 0; kk < kn; ++kk) {
+    double b = Tn[s_boff[kk]];
+    if (square) b *= b;
+#pragma unroll
+    for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+  }
+}
+
 __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
                                    uint32_t tile, uint32_t split) {
   __shared__ double As[SK_KC][SK_M];
+  __shared__ uint64_t s_boff[SK_KC];
   const uint32_t M = G->M, N = G->N, tid = threadIdx.x;
   const uint64_t K = G->K;
   const uint32_t n = tile * SK_N + tid;
   const uint64_t k0 = (uint64_t)split * k_per_split;
   const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
+  // the column side is one fragment whose rows are the column index
+  const uint32_t rf = G->R.frag[0];
+  const double *Tn = G->f[rf].T + n;
+  const uint64_t rows = G->f[rf].rows;
   double acc[SK_M];
 #pragma unroll
   for (uint32_t m = 0; m < SK_M; ++m) acc[m] = 0.0;
   for (uint64_t kb = k0; kb < k1; kb += SK_KC) {
     const uint32_t kn = (uint32_t)std::min<uint64_t>(SK_KC, k1 - kb);
     __syncthreads();  // the previous chunk is consumed
+    if (tid < kn) {
+      const uint64_t j = kb + tid;
+      s_boff[tid] = frag_p(G, rf, G->terms ? G->terms[j] : j) * rows;
+    }
     for (uint32_t e = tid; e < kn * M; e += SK_N) {
       const uint32_t kk = e / M, m = e % M;
       const uint64_t j = kb + kk;
@@ -208,13 +229,14 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
     }
     __syncthreads();
     if (n >= N) continue;
-    for (uint32_t kk = 0; kk < kn; ++kk) {
-      const uint64_t j = kb + kk;
-      double b = side_value(G, G->R, n, G->terms ? G->terms[j] : j);
-      if (G->square) b *= b;
-#pragma unroll
-      for (uint32_t m = 0; m < SK_M; ++m)
-        if (m < M) acc[m] += As[kk][m] * b;
+    const bool sq = G->square != 0;
+    switch (M) {
+      case 1: skinny_rows<1>(As, s_boff, Tn, kn, sq, acc); break;
+      case 2: skinny_rows<2>(As, s_boff, Tn, kn, sq, acc); break;
+      case 4: skinny_rows<4>(As, s_boff, Tn, kn, sq, acc); break;
+      case 8: skinny_rows<8>(As, s_boff, Tn, kn, sq, acc); break;
+      case 16: skinny_rows<16>(As, s_boff, Tn, kn, sq, acc); break;
+      default: skinny_rows<32>(As, s_boff, Tn, kn, sq, acc); break;
     }
   }
   if (n >= N) return;
@@ -279,7 +301,10 @@ uint32_t gemm_splits(const GemmArgs &h) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
 }
 
-bool contraction_skinny(const GemmArgs &h, bool fp32) { return !fp32 && h.M <= SK_M; }
+// rows a power of two up to 32 (the row side's requested bits), one column fragment
+bool contraction_skinny(const GemmArgs &h, bool fp32) {
+  return !fp32 && h.M <= SK_M && (h.M & (h.M - 1)) == 0 && h.R.n == 1 && h.R.shift[0] == 0;
+}
 
 uint32_t gemm_tiles(const GemmArgs &h, bool skinny) {
   if (skinny) return (h.N + SK_N - 1) / SK_N;

@@ -168,10 +168,22 @@ __device__ inline void cx_reg(double *re, double *im, uint32_t base, uint32_t ct
 // otherwise workgroup x runs preparation combination x and every basis
 // combination on a copy.  blockDim.x = 64 * 2^wb (sv_shape, up to 1024),
 // RB register bits per thread.
+template <class T>
+__device__ inline const T *uniform_ptr(const T *p) {
+  const uint64_t u = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (const T *)(((uint64_t)hi << 32) | lo);
+}
+
 template <int RB>
-__device__ void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc, uint32_t blk, C2 *smem) {
+__device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc, uint32_t blk, C2 *smem) {
   constexpr int R = 1 << RB;
-  const uint32_t m = F.m;
+  // the descriptor's scalars in scalar registers (uniform across the
+  // workgroup; read from memory they would hold vector registers)
+  const uint32_t m = __builtin_amdgcn_readfirstlane(F.m);
+  const uint32_t n_ops = __builtin_amdgcn_readfirstlane(F.n_ops);
+  const uint32_t *ops = uniform_ptr(F.ops);
+  const double *mats = uniform_ptr(F.mats);
   const uint32_t N = 1u << m;
   const uint32_t BS = blockDim.x;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -228,17 +240,17 @@ __device__ void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t sp
   uint64_t layout = 0;
   for (uint32_t q = 0; q < m; ++q) layout |= (uint64_t)q << (4 * q);
   uint32_t cur = 0;  // swap buffer of the next SV_SWAP
-  for (uint32_t c0 = 0; c0 < F.n_ops; c0 += kStage) {
-    const uint32_t cn = min(kStage, F.n_ops - c0);
+  for (uint32_t c0 = 0; c0 < n_ops; c0 += kStage) {
+    const uint32_t cn = min(kStage, n_ops - c0);
     // lane t of every wave holds op word t of the chunk (read with
     // readlane: no LDS round trip per op); the matrices are staged in LDS
     // with every load of a thread issued before its first store
-    const uint32_t myw = lane < cn ? F.ops[c0 + lane] : 0u;
+    const uint32_t myw = lane < cn ? ops[c0 + lane] : 0u;
     double mt[8 * kStage / 64];
 #pragma unroll
     for (uint32_t k = 0; k < 8 * kStage / 64; ++k) {
       const uint32_t i = tid + k * BS;
-      mt[k] = i < 8 * cn ? F.mats[(size_t)8 * c0 + i] : 0.0;
+      mt[k] = i < 8 * cn ? mats[(size_t)8 * c0 + i] : 0.0;
     }
     __syncthreads();  // every wave is done with the previous chunk
 #pragma unroll
@@ -460,8 +472,12 @@ __global__ __launch_bounds__(1024) void sv_batch_kernel(const FragDev *__restric
     if (jobs[mid].wg0 <= blockIdx.x) lo = mid;
     else hi = mid;
   }
-  const SvJob &J = jobs[lo];
-  sv_body<RB>(descs[J.desc], J.dist, J.split, (uint32_t)(blockIdx.x - J.wg0), smem);
+  // the job's fields are workgroup-uniform: keep them in scalar registers
+  const SvJob &J = jobs[__builtin_amdgcn_readfirstlane(lo)];
+  const uint32_t desc = __builtin_amdgcn_readfirstlane(J.desc), split = __builtin_amdgcn_readfirstlane(J.split);
+  const uint32_t blk = __builtin_amdgcn_readfirstlane((uint32_t)(blockIdx.x - J.wg0));
+  double *dist = const_cast<double *>(uniform_ptr(J.dist));
+  sv_body<RB>(descs[desc], dist, split, blk, smem);
 }
 
 }  // namespace
