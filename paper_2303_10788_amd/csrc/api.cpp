@@ -1447,7 +1447,7 @@ struct ccut_batch {
   // independent per-plan steps run on a pool of streams (default priority),
   // forked from and joined back into the batch stream
   std::vector<hipStream_t> pool;
-  hipEvent_t fork_ev = nullptr, sv_ev = nullptr;
+  hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> join_ev;
   std::vector<uint32_t> wlist[4];
   uint32_t wrows[4] = {0, 0, 0, 0};
@@ -1467,7 +1467,6 @@ struct ccut_batch {
     for (auto ps : pool) (void)hipStreamDestroy(ps);
     for (auto e : join_ev) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
-    if (sv_ev) (void)hipEventDestroy(sv_ev);
     if (stream) (void)hipStreamDestroy(stream);
     arena.release();
   }
@@ -1594,11 +1593,17 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   // shape; the per-plan steps below start from these tables
   std::vector<std::vector<double *>> pre_dist(b->plans.size());
   for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
-  // the state vectors (pool stream 0) run beside the sampling (batch stream)
+  // the state vectors run beside the sampling (batch stream), each shape
+  // class on a pool stream of its own
+  FragDev *d_sv = nullptr;
+  if (!b->nc.empty()) {
+    d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
+    if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
+  }
   const bool sv_side = !b->nc.empty() && !b->pool.empty();
   if (sv_side) {
     HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
-    HIP_TRY(c, hipStreamWaitEvent(b->pool[0], b->fork_ev, 0));
+    for (hipStream_t ps : b->pool) HIP_TRY(c, hipStreamWaitEvent(ps, b->fork_ev, 0));
   }
   if (!b->samp.empty()) {
     const uint64_t shots = b->eo.shots_per_variant;
@@ -1615,11 +1620,11 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       if (lds) {  // as in the per-plan sampler
         const uint64_t per_block = std::max<uint64_t>(bins, 2048);
         nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
-        lds_bytes = std::max<size_t>(lds_bytes, (size_t)bins * 4);
       } else {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         fill_words += nv * (uint64_t)bins;
       }
+      lds_bytes = std::max<size_t>(lds_bytes, sample_lds_bytes(nm, true));
       SampleJob J{};
       J.models = d_models + b->model_off[ref.plan][ref.frag];
       J.shots = shots;
@@ -1659,9 +1664,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     HIP_TRY(c, launch_sample_batch(d_jobs, (uint32_t)jobs.size(), wg, lds_bytes, t, c->cur));
   }
   if (!b->nc.empty()) {
-    if (sv_side) c->cur = b->pool[0];
-    FragDev *d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
-    if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
+    std::vector<uint8_t> used(b->pool.size(), 0);
+    uint32_t ci = 0;  // shape classes so far
     for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
       std::vector<SvJob> jobs;
       uint64_t wg = 0;
@@ -1686,16 +1690,23 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         jobs.push_back(J);
       }
       if (jobs.empty()) continue;
+      if (sv_side) {
+        const size_t k = ci % b->pool.size();
+        c->cur = b->pool[k];
+        used[k] = 1;
+      }
+      ++ci;
       SvJob *d_jobs = (SvJob *)upload(c, jobs.data(), jobs.size() * sizeof(SvJob));
       if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
       KTimer tm(c, CCUT_K_SV);
       HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
     }
     c->cur = b->stream;
-    if (sv_side) {
-      HIP_TRY(c, hipEventRecord(b->sv_ev, b->pool[0]));
-      HIP_TRY(c, hipStreamWaitEvent(b->stream, b->sv_ev, 0));
-    }
+    for (size_t k = 0; k < used.size(); ++k)
+      if (used[k]) {
+        HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
+        HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
+      }
   }
   // The plans' remaining steps.  Work that the batched launches below do
   // not cover (Heisenberg tensors, tables outside the pre-pass, transforms
@@ -1915,7 +1926,6 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
   });
   HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
-  HIP_TRY(c, hipEventCreateWithFlags(&b->sv_ev, hipEventDisableTiming));
   for (size_t k = 0; k < std::min<size_t>(n, 8); ++k) {
     hipStream_t ps = nullptr;
     hipEvent_t je = nullptr;

@@ -206,6 +206,14 @@ struct SampleJob {
   uint32_t n_meas, nblk, qpt, pad_;
 };
 
+// Sampling LDS: the shot xor's byte tables (256 u64 per 8 measurement
+// indices) and, for n_meas <= kLdsHistBits, the workgroup's u32 histogram.
+constexpr uint32_t kLdsHistBits = 14;
+__host__ __device__ inline uint32_t sample_tab_groups(uint32_t n_meas) { return (n_meas + 7) / 8; }
+inline size_t sample_lds_bytes(uint32_t n_meas, bool hist) {
+  return (size_t)sample_tab_groups(n_meas) * 256 * 8 + ((hist && n_meas <= kLdsHistBits) ? (size_t(4) << n_meas) : 0);
+}
+
 // One non-Clifford fragment in a batched state-vector launch: descriptor
 // descs[desc], tables in dist, wg0 = its first workgroup.
 struct SvJob {

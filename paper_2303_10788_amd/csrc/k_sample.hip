@@ -32,26 +32,42 @@ __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, boo
 }
 
 constexpr int kSampleBlock = 256;
-constexpr uint32_t kLdsHistBits = 14;  // up to 2^14 u32 bins = 64 KiB per workgroup
 
 // Shots of variant v, block bx of nbx: each thread handles `qpt` quads;
 // quads are interleaved across the workgroup so record writes are
 // contiguous.  With n_meas <= 14 the block's histogram lives in LDS and is
 // written to partial[v][bx][bins]; otherwise counts go straight to
 // partial[v][bins] (zeroed beforehand).
-__device__ void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
+//
+// The xor over random measurements goes by bytes of the Philox word: table
+// T[g][b] (LDS, 256 entries per group of 8 measurement indices) holds the
+// xor of Gcol[8 g + i] over the bits i of b whose measurement is random, so
+// a shot takes ceil(n_meas / 8) lookups.  Dynamic LDS: the tables, then the
+// histogram.
+__device__ __attribute__((always_inline)) void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
                             uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
                             uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
-                            uint32_t *s_hist, uint64_t *s_model) {
+                            uint64_t *s_dyn) {
   const uint32_t mw = model_words(n_meas);
   const uint64_t *md = models + v * mw;
-  for (uint32_t i = threadIdx.x; i < mw; i += kSampleBlock) s_model[i] = md[i];
+  const uint32_t groups = sample_tab_groups(n_meas);
+  uint64_t *s_tab = s_dyn;
+  uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_dyn + groups * 256);
+  const uint64_t x0 = md[0], rmask = md[1];
+  for (uint32_t e = threadIdx.x; e < groups * 256; e += kSampleBlock) {
+    const uint32_t g = e >> 8, b = e & 255u;
+    uint64_t t = 0;
+    for (uint32_t i = 0; i < 8; ++i) {
+      const uint32_t a = 8 * g + i;
+      if (((b >> i) & 1u) && a < n_meas && ((rmask >> a) & 1ull)) t ^= md[2 + a];
+    }
+    s_tab[e] = t;
+  }
   const uint32_t bins = 1u << n_meas;
   const bool lds_hist = partial != nullptr && n_meas <= kLdsHistBits;
   if (lds_hist)
     for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) s_hist[i] = 0;
   __syncthreads();
-  const uint64_t x0 = s_model[0], rmask = s_model[1];
   const uint64_t vid = vid0 + v;
   const bool wide = n_meas > 32;
   const uint64_t nquads = (shots + 3) >> 2;
@@ -64,12 +80,8 @@ __device__ void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas
     for (int r = 0; r < 4; ++r) {
       const uint64_t s = quad * 4 + r;
       if (s >= shots) break;
-      const uint64_t ur = u[r] & rmask;
       uint64_t x = x0;
-      for (uint64_t mm = rmask; mm; mm &= mm - 1) {
-        const int a = __ffsll((unsigned long long)mm) - 1;
-        x ^= s_model[2 + a] & (0ull - ((ur >> a) & 1ull));
-      }
+      for (uint32_t g = 0; g < groups; ++g) x ^= s_tab[(g << 8) | (uint32_t)((u[r] >> (8 * g)) & 255u)];
       if (records) records[v * shots + s] = x;
       if (lds_hist)
         atomicAdd(&s_hist[x], 1u);
@@ -88,23 +100,20 @@ __device__ void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas
 __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
     const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
     uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
-  extern __shared__ uint32_t s_hist[];
-  __shared__ uint64_t s_model[2 + kMaxMeas];
-  sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_hist,
-              s_model);
+  extern __shared__ uint64_t s_dyn[];
+  sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn);
 }
 
 // Many fragments' sampling in one launch: workgroup x runs block
 // (x - wg0) mod nblk of variant (x - wg0) / nblk of the job holding x.
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,
                                                                       uint32_t n_jobs) {
-  extern __shared__ uint32_t s_hist[];
-  __shared__ uint64_t s_model[2 + kMaxMeas];
+  extern __shared__ uint64_t s_dyn[];
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const SampleJob &J) { return J.wg0; });
   const SampleJob &J = jobs[j];
   const uint64_t local = blockIdx.x - J.wg0;
   sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
-              (uint32_t)(local % J.nblk), J.nblk, s_hist, s_model);
+              (uint32_t)(local % J.nblk), J.nblk, s_dyn);
 }
 
 // dist[v][b] = (sum over shot blocks of counts) / shots
@@ -303,7 +312,9 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
                               uint32_t qpt, uint64_t *records, hipStream_t s) {
   if (n_meas > (uint32_t)kMaxMeas || nv == 0 || nv > 65535) return hipErrorInvalidValue;
-  const size_t lds = (partial && n_meas <= kLdsHistBits) ? (size_t(1) << n_meas) * 4 : 0;
+  const size_t lds = sample_lds_bytes(n_meas, partial != nullptr);
+  hipError_t e = hipFuncSetAttribute((const void *)sample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sample_kernel, dim3(nblk_x, (unsigned)nv), dim3(kSampleBlock), lds, s, models,
                      n_meas, shots, seed, vid0, partial, qpt, records);
   return hipGetLastError();
@@ -312,9 +323,12 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
 hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
                                uint64_t total_reduce_blocks, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
-  if (total_wg > 0x7FFFFFFFull || lds > (size_t(4) << kLdsHistBits)) return hipErrorInvalidValue;
+  if (total_wg > 0x7FFFFFFFull || lds > sample_lds_bytes(kLdsHistBits, true)) return hipErrorInvalidValue;
+  hipError_t e =
+      hipFuncSetAttribute((const void *)sample_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sample_batch_kernel, dim3((unsigned)total_wg), dim3(kSampleBlock), lds, s, jobs, n_jobs);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (total_reduce_blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hist_reduce_batch_kernel, dim3((unsigned)total_reduce_blocks), dim3(256), 0, s, jobs, n_jobs);
