@@ -1547,6 +1547,68 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   uint32_t *d_counter = aget<uint32_t>(c, 64);
   uint64_t *d_models = aget<uint64_t>(c, std::max<uint64_t>(b->model_words_total, 1));
   if (!d_descs || !d_items || !d_counter || !d_models) return fail(c, CCUT_E_OOM, "device allocation failed");
+  // every plan's sampled outcome tables come from one pass of sampling
+  // launches (plus one reduction), every non-Clifford fragment's from one
+  // state-vector launch per shape; the per-plan steps below start from these
+  // tables.  The state vectors need no tableau: they start at once, each
+  // shape class on a pool stream of its own (at most 3 of them: HIP maps a
+  // process's streams onto 4 hardware queues, the batch stream holds one),
+  // and join before the per-plan steps.
+  std::vector<std::vector<double *>> pre_dist(b->plans.size());
+  for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+  const size_t n_sv_streams = std::min<size_t>(b->pool.size(), 3);
+  std::vector<uint8_t> sv_used(n_sv_streams, 0);
+  if (!b->nc.empty()) {
+    FragDev *d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
+    if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
+    if (n_sv_streams) {
+      HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+      for (size_t k = 0; k < n_sv_streams; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
+    }
+    uint32_t ci = 0;  // shape classes so far
+    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+      std::vector<SvJob> jobs;
+      uint64_t wg = 0;
+      size_t lds = 0;
+      for (const auto &ref : b->nc) {
+        const FragDev &h = b->sv_descs[ref.desc];
+        if (h.m != m) continue;
+        uint64_t n_wg;
+        uint32_t bs;
+        size_t l;
+        bool split;
+        sv_launch_shape(h, n_wg, bs, l, split);
+        SvJob J{};
+        J.desc = ref.desc;
+        J.split = split ? 1u : 0u;
+        J.wg0 = wg;
+        J.dist = aget<double>(c, h.n_variants << ref.n_meas);
+        if (!J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+        pre_dist[ref.plan][ref.frag] = J.dist;
+        wg += n_wg;
+        lds = std::max(lds, l);
+        jobs.push_back(J);
+      }
+      if (jobs.empty()) continue;
+      if (n_sv_streams) {
+        const size_t k = ci % n_sv_streams;
+        c->cur = b->pool[k];
+        sv_used[k] = 1;
+      }
+      ++ci;
+      SvJob *d_jobs = (SvJob *)upload(c, jobs.data(), jobs.size() * sizeof(SvJob));
+      if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
+      KTimer tm(c, CCUT_K_SV);
+      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
+    }
+    c->cur = b->stream;
+    for (size_t k = 0; k < n_sv_streams; ++k)
+      if (sv_used[k]) {
+        HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
+        // the autotuner below times the tableau launch alone
+        if (tune) HIP_TRY(c, hipStreamSynchronize(b->pool[k]));
+      }
+  }
   uint64_t *d_bases = nullptr;
   if ((st = batch_bases(b, d_descs, &d_bases)) != CCUT_OK) return st;
   if (tune && !b->items.empty()) {
@@ -1588,34 +1650,26 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   }
   if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg, d_bases)) != CCUT_OK)
     return st;
-  // every plan's sampled outcome tables in one sampling launch (plus one
-  // reduction), every non-Clifford fragment in one state-vector launch per
-  // shape; the per-plan steps below start from these tables
-  std::vector<std::vector<double *>> pre_dist(b->plans.size());
-  for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
-  // the state vectors run beside the sampling (batch stream), each shape
-  // class on a pool stream of its own
-  FragDev *d_sv = nullptr;
-  if (!b->nc.empty()) {
-    d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
-    if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
-  }
-  const bool sv_side = !b->nc.empty() && !b->pool.empty();
-  if (sv_side) {
-    HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
-    for (hipStream_t ps : b->pool) HIP_TRY(c, hipStreamWaitEvent(ps, b->fork_ev, 0));
-  }
   if (!b->samp.empty()) {
+    // jobs in LDS classes (one launch each, so a launch's workgroups reserve
+    // only their class's histogram): up to 8, 20, 36 and 68 KiB
     const uint64_t shots = b->eo.shots_per_variant;
     const uint64_t nquads = (shots + 3) / 4;
+    auto lds_class = [](size_t l) { return l <= (8u << 10) ? 0 : l <= (20u << 10) ? 1 : l <= (36u << 10) ? 2 : 3; };
+    std::vector<size_t> order;
+    for (int cls = 0; cls < 4; ++cls)
+      for (size_t q = 0; q < b->samp.size(); ++q)
+        if (lds_class(sample_lds_bytes(b->samp[q].n_meas, true)) == cls) order.push_back(q);
     std::vector<SampleJob> jobs;
-    uint64_t wg = 0, t = 0, fill_words = 0;
-    size_t lds_bytes = 0;
-    for (const auto &ref : b->samp) {
+    uint64_t t = 0, fill_words = 0;
+    uint64_t cls_units[4] = {0, 0, 0, 0};
+    size_t cls_lds[4] = {0, 0, 0, 0}, cls_first[4] = {0, 0, 0, 0}, cls_count[4] = {0, 0, 0, 0};
+    for (size_t q : order) {
+      const auto &ref = b->samp[q];
       const FragDev &h = b->descs[ref.desc];
       const uint32_t nm = ref.n_meas, bins = 1u << nm;
       const uint64_t nv = h.n_variants;
-      const bool lds = nm <= 14;
+      const bool lds = nm <= kLdsHistBits;
       uint32_t nblk;
       if (lds) {  // as in the per-plan sampler
         const uint64_t per_block = std::max<uint64_t>(bins, 2048);
@@ -1624,7 +1678,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         fill_words += nv * (uint64_t)bins;
       }
-      lds_bytes = std::max<size_t>(lds_bytes, sample_lds_bytes(nm, true));
+      const int cls = lds_class(sample_lds_bytes(nm, true));
+      if (cls_count[cls]++ == 0) cls_first[cls] = jobs.size();
+      cls_lds[cls] = std::max<size_t>(cls_lds[cls], sample_lds_bytes(nm, true));
       SampleJob J{};
       J.models = d_models + b->model_off[ref.plan][ref.frag];
       J.shots = shots;
@@ -1634,9 +1690,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.n_meas = nm;
       J.nblk = nblk;
       J.qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
-      J.wg0 = wg;
+      J.wg0 = cls_units[cls];
       J.rb0 = t;
-      wg += nv * nblk;
+      cls_units[cls] += nv * nblk;
       t += (nv * bins + 4095) / 4096;  // reduction workgroups
       jobs.push_back(J);
     }
@@ -1647,7 +1703,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     for (size_t q = 0; q < jobs.size(); ++q) {
       SampleJob &J = jobs[q];
       const uint64_t bins = 1ull << J.n_meas;
-      if (J.n_meas <= 14) {
+      if (J.n_meas <= kLdsHistBits) {
         J.partial = aget<uint32_t>(c, J.nv * J.nblk * bins);
       } else {
         J.partial = zeroed + zo;
@@ -1655,59 +1711,20 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       }
       J.dist = aget<double>(c, J.nv * bins);
       if (!J.partial || !J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
-      pre_dist[b->samp[q].plan][b->samp[q].frag] = J.dist;
+      pre_dist[b->samp[order[q]].plan][b->samp[order[q]].frag] = J.dist;
     }
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
     if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (fill_words) HIP_TRY(c, launch_fill_u32(zeroed, fill_words, 0u, c->cur));
     KTimer tm(c, CCUT_K_SAMPLE);
-    HIP_TRY(c, launch_sample_batch(d_jobs, (uint32_t)jobs.size(), wg, lds_bytes, t, c->cur));
+    for (int cls = 0; cls < 4; ++cls)
+      if (cls_count[cls])
+        HIP_TRY(c, launch_sample_batch(d_jobs + cls_first[cls], (uint32_t)cls_count[cls], cls_units[cls],
+                                       cls_lds[cls], c->cur));
+    HIP_TRY(c, launch_hist_reduce_batch(d_jobs, (uint32_t)jobs.size(), t, c->cur));
   }
-  if (!b->nc.empty()) {
-    std::vector<uint8_t> used(b->pool.size(), 0);
-    uint32_t ci = 0;  // shape classes so far
-    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
-      std::vector<SvJob> jobs;
-      uint64_t wg = 0;
-      size_t lds = 0;
-      for (const auto &ref : b->nc) {
-        const FragDev &h = b->sv_descs[ref.desc];
-        if (h.m != m) continue;
-        uint64_t n_wg;
-        uint32_t bs;
-        size_t l;
-        bool split;
-        sv_launch_shape(h, n_wg, bs, l, split);
-        SvJob J{};
-        J.desc = ref.desc;
-        J.split = split ? 1u : 0u;
-        J.wg0 = wg;
-        J.dist = aget<double>(c, h.n_variants << ref.n_meas);
-        if (!J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
-        pre_dist[ref.plan][ref.frag] = J.dist;
-        wg += n_wg;
-        lds = std::max(lds, l);
-        jobs.push_back(J);
-      }
-      if (jobs.empty()) continue;
-      if (sv_side) {
-        const size_t k = ci % b->pool.size();
-        c->cur = b->pool[k];
-        used[k] = 1;
-      }
-      ++ci;
-      SvJob *d_jobs = (SvJob *)upload(c, jobs.data(), jobs.size() * sizeof(SvJob));
-      if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
-      KTimer tm(c, CCUT_K_SV);
-      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
-    }
-    c->cur = b->stream;
-    for (size_t k = 0; k < used.size(); ++k)
-      if (used[k]) {
-        HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
-        HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
-      }
-  }
+  for (size_t k = 0; k < n_sv_streams; ++k)
+    if (sv_used[k]) HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
   // The plans' remaining steps.  Work that the batched launches below do
   // not cover (Heisenberg tensors, tables outside the pre-pass, transforms
   // too large to tile, contractions of more than 8 fragments) runs per plan,

@@ -264,11 +264,13 @@ void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &
 // waves) in one launch; lds = the largest of theirs.
 hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_jobs, uint64_t total_wg, uint32_t m,
                            size_t lds, hipStream_t s);
-// Batched sampling + reduction over jobs (see SampleJob); lds = the largest
-// LDS histogram among the jobs (4 * 2^n_meas bytes for n_meas <= 14, 0 if
-// none has one).
-hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
-                               uint64_t total_reduce_blocks, hipStream_t s);
+// Batched sampling over jobs (see SampleJob; wg0 numbers the units of this
+// launch's jobs from 0); lds = the largest sample_lds_bytes among them.  The
+// reduction runs over all jobs of a batch (rb0 numbering) in one launch.
+hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_units, size_t lds,
+                               hipStream_t s);
+hipError_t launch_hist_reduce_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_reduce_blocks,
+                                    hipStream_t s);
 hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t nv,
                                const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
 hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,

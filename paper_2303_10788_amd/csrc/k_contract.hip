@@ -141,15 +141,28 @@ __global__ void transform_all_kernel(const TransformAll A, const double *__restr
 // an input axis keeps its four slots (I, X, Y, Z); an output axis reads its
 // six (basis X, Y, Z x outcome 0, 1) and leaves I, X, Y in the outcome-0
 // slots of bases X, Y, Z and Z in the outcome-1 slot of basis X.
+// A workgroup takes `per_wg` consecutive tiles of the launch in turn (fewer,
+// longer workgroups: the dispatcher, not the tiles, limits short ones).
 constexpr uint32_t kTileThreads = 256;
+__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep);
+
 __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const TileJob *__restrict__ jobs,
-                                                                       uint32_t n_jobs) {
+                                                                       uint32_t n_jobs, uint64_t total,
+                                                                       uint32_t per_wg) {
   __shared__ double s[kTileElems];
   __shared__ uint32_t s_xdep[1u << kTileMaxT];
-  const uint32_t jb = find_job(jobs, n_jobs, blockIdx.x, [](const TileJob &J) { return J.wg0; });
-  const TileJob &J = jobs[jb];
+  const uint64_t g0 = (uint64_t)blockIdx.x * per_wg;
+  const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
+  uint32_t jb = find_job(jobs, n_jobs, g0, [](const TileJob &J) { return J.wg0; });
+  for (uint64_t g = g0; g < g1; ++g) {
+    while (jb + 1 < n_jobs && jobs[jb + 1].wg0 <= g) ++jb;
+    if (g > g0) __syncthreads();  // the previous tile's LDS is consumed
+    tile_body(jobs[jb], g - jobs[jb].wg0, s, s_xdep);
+  }
+}
+
+__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep) {
   const uint32_t tid = threadIdx.x;
-  const uint64_t u = blockIdx.x - J.wg0;  // tile index: the x_out bits above t
   const uint32_t a = J.n_axes, V = J.v_count, lb = J.lbits, t = J.t, thr = J.thr, nh = J.nh;
   const uint32_t XL = 1u << lb, XT = 1u << t;
   // the tile's fixed x_in bits: u deposited into the non-outcome positions from thr up
@@ -501,10 +514,14 @@ hipError_t launch_recombine_batch(const RcJob *d_jobs, uint32_t n_jobs, uint64_t
   return hipGetLastError();
 }
 
-hipError_t launch_transform_tiled(const TileJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s) {
-  if (n_jobs == 0 || total_wg == 0) return hipSuccess;
-  if (total_wg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(transform_tiled_kernel, dim3((unsigned)total_wg), dim3(kTileThreads), 0, s, d_jobs, n_jobs);
+hipError_t launch_transform_tiled(const TileJob *d_jobs, uint32_t n_jobs, uint64_t total_tiles, hipStream_t s) {
+  if (n_jobs == 0 || total_tiles == 0) return hipSuccess;
+  // about 4096 workgroups, at most 16 tiles each
+  const uint32_t per_wg = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, total_tiles / 4096));
+  const uint64_t wgs = (total_tiles + per_wg - 1) / per_wg;
+  if (wgs > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transform_tiled_kernel, dim3((unsigned)wgs), dim3(kTileThreads), 0, s, d_jobs, n_jobs,
+                     total_tiles, per_wg);
   return hipGetLastError();
 }
 

@@ -104,16 +104,24 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
   sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn);
 }
 
-// Many fragments' sampling in one launch: workgroup x runs block
-// (x - wg0) mod nblk of variant (x - wg0) / nblk of the job holding x.
+// Many fragments' sampling in one launch: unit g runs block
+// (g - wg0) mod nblk of variant (g - wg0) / nblk of the job holding g, and
+// a workgroup takes `per_wg` consecutive units in turn.
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,
-                                                                      uint32_t n_jobs) {
+                                                                      uint32_t n_jobs, uint64_t total,
+                                                                      uint32_t per_wg) {
   extern __shared__ uint64_t s_dyn[];
-  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const SampleJob &J) { return J.wg0; });
-  const SampleJob &J = jobs[j];
-  const uint64_t local = blockIdx.x - J.wg0;
-  sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
-              (uint32_t)(local % J.nblk), J.nblk, s_dyn);
+  const uint64_t g0 = (uint64_t)blockIdx.x * per_wg;
+  const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
+  uint32_t j = find_job(jobs, n_jobs, g0, [](const SampleJob &J) { return J.wg0; });
+  for (uint64_t g = g0; g < g1; ++g) {
+    while (j + 1 < n_jobs && jobs[j + 1].wg0 <= g) ++j;
+    if (g > g0) __syncthreads();  // the previous unit's tables and histogram are consumed
+    const SampleJob &J = jobs[j];
+    const uint64_t local = g - J.wg0;
+    sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
+                (uint32_t)(local % J.nblk), J.nblk, s_dyn);
+  }
 }
 
 // dist[v][b] = (sum over shot blocks of counts) / shots
@@ -320,16 +328,25 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
   return hipGetLastError();
 }
 
-hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_wg, size_t lds,
-                               uint64_t total_reduce_blocks, hipStream_t s) {
-  if (n_jobs == 0) return hipSuccess;
-  if (total_wg > 0x7FFFFFFFull || lds > sample_lds_bytes(kLdsHistBits, true)) return hipErrorInvalidValue;
+hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_units, size_t lds,
+                               hipStream_t s) {
+  if (n_jobs == 0 || total_units == 0) return hipSuccess;
+  if (lds > sample_lds_bytes(kLdsHistBits, true)) return hipErrorInvalidValue;
+  // about 8192 workgroups, at most 8 units each
+  const uint32_t per_wg = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, total_units / 8192));
+  const uint64_t wgs = (total_units + per_wg - 1) / per_wg;
+  if (wgs > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipError_t e =
       hipFuncSetAttribute((const void *)sample_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sample_batch_kernel, dim3((unsigned)total_wg), dim3(kSampleBlock), lds, s, jobs, n_jobs);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sample_batch_kernel, dim3((unsigned)wgs), dim3(kSampleBlock), lds, s, jobs, n_jobs, total_units,
+                     per_wg);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_reduce_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_reduce_blocks,
+                                    hipStream_t s) {
+  if (n_jobs == 0 || total_reduce_blocks == 0) return hipSuccess;
   if (total_reduce_blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hist_reduce_batch_kernel, dim3((unsigned)total_reduce_blocks), dim3(256), 0, s, jobs, n_jobs);
   return hipGetLastError();
