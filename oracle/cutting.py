@@ -320,10 +320,20 @@ def pauli_tensor(frag: Fragment, req: Request, dists: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(t).reshape(1 << len(req.req_pos), 4 ** a)
 
 
+def support(frags: Sequence[Fragment], tensors, k: int) -> List[int]:
+    """Cut terms P whose column T_f[:, P|f] is nonzero in every fragment,
+    ascending: the terms that can contribute to the recombination sum
+    (Sec. IX, fewer stitching calculations: for Clifford fragments most
+    Pauli expectations vanish)."""
+    nz = [np.any(T != 0.0, axis=0) for T in tensors]
+    return [P for P in range(4 ** k) if all(z[f.p_index(P)] for f, z in zip(frags, nz))]
+
+
 def recombine(frags: Sequence[Fragment], reqs: Sequence[Request], tensors, k: int,
-              nq: int) -> np.ndarray:
+              nq: int, sparse: bool = False) -> np.ndarray:
     """R[b] = 2^-k sum_P prod_f T_f[b_f; P|f], summed over P in ascending
-    order (the contraction of Sec. V-C, written out)."""
+    order (the contraction of Sec. V-C, written out).  sparse: only the
+    terms of ``support`` are summed (the skipped terms are exact zeros)."""
     b = np.arange(1 << nq, dtype=np.int64)
     bidx = []
     for req in reqs:
@@ -332,7 +342,7 @@ def recombine(frags: Sequence[Fragment], reqs: Sequence[Request], tensors, k: in
             bi |= ((b >> u) & 1) << i
         bidx.append(bi)
     R = np.zeros(1 << nq, dtype=np.float64)
-    for P in range(4 ** k):
+    for P in (support(frags, tensors, k) if sparse else range(4 ** k)):
         term = np.ones(1 << nq, dtype=np.float64)
         for f, T, bi in zip(frags, tensors, bidx):
             term = term * T[bi, f.p_index(P)]
@@ -384,7 +394,7 @@ def recombine_matmul(frags: Sequence[Fragment], reqs: Sequence[Request], tensors
 # ------------------------------------------------------------------ end to end
 
 def marginal(n: int, ops, cuts, qubits, *, shots: int = 0, seed: int = 0, circuit: int = 0,
-             exact_method: str = "branch", return_parts: bool = False):
+             exact_method: str = "branch", return_parts: bool = False, sparse: bool = False):
     """Reconstructed output marginal over ``qubits`` (bit i = qubits[i])."""
     qubits = list(qubits)
     if len(set(qubits)) != len(qubits) or any(not (0 <= q < n) for q in qubits):
@@ -394,7 +404,7 @@ def marginal(n: int, ops, cuts, qubits, *, shots: int = 0, seed: int = 0, circui
     dists = [variant_distributions(f, r.meas, shots=shots, seed=seed, circuit=circuit,
                                    exact_method=exact_method) for f, r in zip(frags, reqs)]
     tensors = [pauli_tensor(f, r, d) for f, r, d in zip(frags, reqs, dists)]
-    R = recombine(frags, reqs, tensors, len(cuts), len(qubits))
+    R = recombine(frags, reqs, tensors, len(cuts), len(qubits), sparse=sparse)
     if return_parts:
         return R, dict(frags=frags, reqs=reqs, dists=dists, tensors=tensors)
     return R
@@ -428,8 +438,11 @@ def _variant_state(frag, v, meas, *, shots, seed, circuit):
     return ("shots", t.sample(meas, seed, vid, 0, shots).astype(np.int64))
 
 
-def _parity_expectation(state, meas, mk):
-    """E_v[(-1)^{mask . x}] for one mask (bitmask over measured positions)."""
+def _parity_expectation(state, meas, mk, settle=False):
+    """E_v[(-1)^{mask . x}] for one mask (bitmask over measured positions).
+    settle (sampled Clifford variants, Sec. IX fewer shots): the expectation
+    of a Pauli on a stabilizer state is -1, 0 or +1, so shots that show both
+    parities give 0 and shots that agree give their common sign."""
     kind, data = state
     sel = [j for j in range(len(meas)) if (mk >> j) & 1]
     if kind == "dist":
@@ -442,10 +455,13 @@ def _parity_expectation(state, meas, mk):
         xs, zs, rs = data
         return float(_stab.z_expectation(xs, zs, rs, [meas[j] for j in sel]))
     par = data[:, sel].sum(axis=1) % 2 if sel else np.zeros(data.shape[0], np.int64)
+    if settle:
+        odd = int(np.sum(par))
+        return 1.0 if odd == 0 else -1.0 if odd == data.shape[0] else 0.0
     return float(np.sum(1 - 2 * par)) / data.shape[0]
 
 
-def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=0, circuit=0):
+def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=0, circuit=0, settle=False):
     """t_f[z][p_f] = sum over the contributing variants of the coefficient
     times the variant's expectation of (-1)^(z_f.b + sum of the quantum-output
     bits of the axes with P != I)."""
@@ -468,7 +484,7 @@ def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=
         if key not in cache:
             if v not in states:
                 states[v] = _variant_state(frag, v, meas, shots=shots, seed=seed, circuit=circuit)
-            cache[key] = [_parity_expectation(states[v], meas, z | extra) for z in zloc]
+            cache[key] = [_parity_expectation(states[v], meas, z | extra, settle) for z in zloc]
         return cache[key]
 
     t = np.zeros((len(masks), 4 ** a))
@@ -492,7 +508,7 @@ def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=
 
 
 def zexpect(n: int, ops, cuts, masks: Sequence[int], *, shots: int = 0, seed: int = 0,
-            circuit: int = 0, return_parts: bool = False):
+            circuit: int = 0, return_parts: bool = False, settle: bool = False):
     """<Z_z> for every mask z (bit q = qubit q):
     2^-k sum_P prod_f t_f[z; P|f]."""
     frags = fragment_circuit(n, ops, cuts)
@@ -500,7 +516,7 @@ def zexpect(n: int, ops, cuts, masks: Sequence[int], *, shots: int = 0, seed: in
     tens = []
     for f in frags:
         meas = zstring_measured_set(f, masks)
-        tens.append(zstring_tensor(f, meas, masks, shots=shots, seed=seed, circuit=circuit))
+        tens.append(zstring_tensor(f, meas, masks, shots=shots, seed=seed, circuit=circuit, settle=settle))
     out = np.zeros(len(masks))
     for P in range(4 ** k):
         term = np.ones(len(masks))

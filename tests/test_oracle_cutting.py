@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import chp, cutting as C, statevector as sv
+from oracle import chp, cutting as C, mlp as M, statevector as sv
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "textbook_cuts.txt")
 
@@ -188,6 +188,64 @@ def test_sampled_z_strings_unbiased():
     runs = np.array([C.zexpect(w.n, w.ops, w.cuts, w.zmasks, shots=300, seed=s) for s in range(40)])
     se = runs.std(axis=0, ddof=1) / np.sqrt(len(runs))
     assert np.all(np.abs(runs.mean(axis=0) - exact) <= 4 * se + 1e-12)
+
+
+# ------------------------------------------- Clifford-specific optimisations
+
+def test_support_terms_are_the_nonzero_terms_and_sparse_sum_equals_dense():
+    # brute force: every term outside the support is an all-zero vector, and
+    # the support sum equals the full ascending sum bit for bit (the skipped
+    # terms are exact zeros)
+    for seed in range(8):
+        rng = np.random.default_rng(100 + seed)
+        n = int(rng.integers(3, 7))
+        kinds = W.CLIFFORD_KINDS if seed % 2 else W.ALL_KINDS
+        ops = W.random_circuit(n, int(rng.integers(10, 30)), seed, kinds=kinds)
+        cuts = W.random_cuts(n, ops, int(rng.integers(1, 4)), seed)
+        qubits = list(range(n))
+        R, parts = C.marginal(n, ops, cuts, qubits, return_parts=True)
+        frags, reqs, tens, k = parts["frags"], parts["reqs"], parts["tensors"], len(cuts)
+        sup = set(C.support(frags, tens, k))
+        for P in range(4 ** k):
+            tv = M.term_vector(frags, parts["reqs"], tens, k, P, n)
+            assert (P in sup) == bool(np.any(tv != 0.0)), P
+        Rs = C.marginal(n, ops, cuts, qubits, sparse=True)
+        assert np.array_equal(Rs, R)
+        assert np.abs(Rs - sv.uncut_marginal(n, ops, qubits)).max() <= 1e-12
+
+
+def test_stabilizer_state_on_a_cut_vanishes_in_two_paulis():
+    # H, cut, H on one wire: the cut carries |+>, so <Y> = <Z> = 0 upstream
+    # (a one-qubit stabilizer state sits on a vertex of the Bloch
+    # octahedron), and downstream H maps the Y and Z preparations to
+    # uniform outcomes; the support keeps only I and X of the 4 terms
+    ops = [("H", 0, -1, 0.0), ("H", 0, -1, 0.0)]
+    cuts = [(0, 0)]
+    R, parts = C.marginal(1, ops, cuts, [0], return_parts=True)
+    up, dn = parts["tensors"]
+    assert np.allclose(up, [[1.0, 1.0, 0.0, 0.0]]) and np.allclose(dn[:, 2:], 0.0)
+    assert C.support(parts["frags"], parts["tensors"], 1) == [0, 1]  # I, X
+    assert np.abs(R - np.array([1.0, 0.0])).max() <= 1e-12
+
+
+def test_settled_shots_give_exact_clifford_expectations():
+    # all-Clifford circuits: with settlement a few dozen shots per variant
+    # reproduce the exact expectations (a string with a random parity shows
+    # both values unless all 48 shots agree, probability 2^-47), without it
+    # the estimate carries sampling noise
+    for seed in range(4):
+        rng = np.random.default_rng(200 + seed)
+        n = int(rng.integers(3, 7))
+        ops = W.random_circuit(n, int(rng.integers(12, 30)), seed, kinds=W.CLIFFORD_KINDS)
+        cuts = W.random_cuts(n, ops, 2, seed)
+        masks = [int(m) for m in rng.integers(1, 1 << n, size=8)]
+        exact = C.zexpect(n, ops, cuts, masks)
+        settled = C.zexpect(n, ops, cuts, masks, shots=48, seed=seed, settle=True)
+        assert np.array_equal(settled, exact)
+        zr = [sv.z_expectation(sv.probabilities(sv.run(n, ops)), n, m) for m in masks]
+        assert np.abs(settled - zr).max() <= 1e-12
+    raw = C.zexpect(n, ops, cuts, masks, shots=48, seed=1)
+    assert not np.allclose(raw, exact, atol=1e-3) or np.all(np.abs(exact) == 1)
 
 
 def test_validation_errors():
