@@ -128,8 +128,24 @@ typedef struct {
   int32_t precision;          /* CCUT_FP64, or CCUT_FP32_MFMA_FP64SUM for the recombination */
   uint32_t circuit;           /* circuit index in variant ids (batch position) */
   uint32_t method;            /* CCUT_METHOD_*, exact mode only */
-  uint32_t reserved;          /* must be 0 */
+  uint32_t flags;             /* CCUT_FLAG_* (0: none) */
 } ccut_eval_opts;
+
+/* Clifford-specific cutting optimisations (Sec. IX):
+ *  CCUT_FLAG_SPARSE (ccut_marginal only): the contraction sums only the cut
+ *    terms P whose column T_f[.; P|f] is nonzero in every fragment (the
+ *    others are exact zeros; for Clifford fragments most Pauli
+ *    expectations vanish).  The support is found on the device and its size
+ *    read back, so the call synchronizes and is never captured in a call
+ *    graph.  With the plain fp64 sum the result equals the dense sum bit for
+ *    bit; the matrix-core paths differ from it by rounding only.
+ *  CCUT_FLAG_SETTLE (ccut_zexpect in sampled mode only): each sampled
+ *    Clifford variant's string expectation, which is -1, 0 or +1 on a
+ *    stabilizer state, is settled from its shots: 0 if both parities
+ *    occurred, else the common sign.
+ * A flag outside its call's scope, or in a batch, is CCUT_E_UNSUPPORTED;
+ * unknown bits are CCUT_E_INVALID. */
+enum { CCUT_FLAG_SPARSE = 1, CCUT_FLAG_SETTLE = 2 };
 
 /* ---------------------------------------------------------------- context */
 

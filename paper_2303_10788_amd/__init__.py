@@ -25,6 +25,7 @@ CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
 CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
 CCUT_FP64, CCUT_FP32_MFMA_FP64SUM = 0, 1
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
+CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE = 1, 2
 KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
            "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
            "heisenberg_kernels", "mlp_kernels", "term_kernels")
@@ -55,7 +56,7 @@ class ccut_opts(ctypes.Structure):
 class ccut_eval_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("shots_per_variant", ctypes.c_uint64),
                 ("precision", ctypes.c_int32), ("circuit", ctypes.c_uint32), ("method", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32)]
 
 
 class CcutError(RuntimeError):
@@ -234,8 +235,9 @@ def ccut_fragment_axes(plan, f: int):
     return [(c[j], s[j], l[j]) for j in range(na)]
 
 
-def _eval_opts(shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO):
-    return ccut_eval_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(shots), int(precision), int(circuit), int(method), 0)
+def _eval_opts(shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO, flags=0):
+    return ccut_eval_opts(int(seed) & 0xFFFFFFFFFFFFFFFF, int(shots), int(precision), int(circuit), int(method),
+                          int(flags))
 
 
 def _u32(a):
@@ -458,8 +460,8 @@ class Plan:
         return out
 
     def marginal(self, qubits, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,
-                 out=None):
-        eo = _eval_opts(shots, seed, precision, circuit, method)
+                 out=None, flags=0):
+        eo = _eval_opts(shots, seed, precision, circuit, method, flags)
         if out is None:
             out = np.zeros(1 << len(qubits), dtype=np.float64)
         ccut_marginal(self.handle, self.ctx.handle, eo, qubits, out)
@@ -476,13 +478,14 @@ class Plan:
         return out, se
 
     def zexpect(self, masks, *, shots=0, seed=0, precision=CCUT_FP64, circuit=0, method=CCUT_METHOD_AUTO,
-                out=None):
+                out=None, flags=0):
         masks = np.asarray(masks, dtype=np.uint64)
         if masks.ndim == 1:
             masks = masks[:, None]
         if out is None:
             out = np.zeros(masks.shape[0], dtype=np.float64)
-        ccut_zexpect(self.handle, self.ctx.handle, _eval_opts(shots, seed, precision, circuit, method), masks, out)
+        ccut_zexpect(self.handle, self.ctx.handle, _eval_opts(shots, seed, precision, circuit, method, flags), masks,
+                     out)
         return out
 
     def shot_records(self, qubits, fragment, v_begin, v_end, *, shots, seed=0, circuit=0):

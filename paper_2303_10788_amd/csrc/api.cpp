@@ -278,8 +278,9 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   if (eo->precision != CCUT_FP64 && eo->precision != CCUT_FP32_MFMA_FP64SUM)
     return fail(c, CCUT_E_INVALID, "unknown precision mode");
   HIP_TRY(c, hipSetDevice(c->device));
-  if (eo->method > CCUT_METHOD_HEISENBERG || eo->reserved != 0)
-    return fail(c, CCUT_E_INVALID, "unknown evaluation method");
+  if (eo->method > CCUT_METHOD_HEISENBERG) return fail(c, CCUT_E_INVALID, "unknown evaluation method");
+  if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE))
+    return fail(c, CCUT_E_INVALID, "unknown evaluation flag");
   c->cancel.store(0);
   c->arena.reset();
   c->staged.clear();
@@ -755,10 +756,55 @@ ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res, boo
   return CCUT_OK;
 }
 
+// The sparse contraction: the support (cut terms whose column is nonzero in
+// every fragment) is found on the device, its size read back, and only its
+// terms are summed: the plain sum in ascending order when it is small (the
+// same operations as the dense plain sum minus its zero terms), else the
+// term-list contraction.
+ccut_status recombine_sparse(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
+  const uint64_t K = 1ull << (2 * args.k);
+  SupportArgs sa{};
+  uint64_t cols_total = 0;
+  for (uint32_t f = 0; f < args.n_frags; ++f) {
+    sa.off[f] = cols_total;
+    cols_total += 1ull << (2 * args.f[f].n_axes);
+  }
+  RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
+  uint8_t *nz = aget<uint8_t>(c, cols_total);
+  uint64_t *pos = aget<uint64_t>(c, K), *scratch = aget<uint64_t>(c, scan_scratch_words(K));
+  uint64_t *terms = aget<uint64_t>(c, K);
+  if (!dargs || !nz || !pos || !scratch || !terms) return fail(c, CCUT_E_OOM, "device allocation failed");
+  uint64_t count = 0;
+  {
+    KTimer t(c, CCUT_K_RECOMBINE);
+    for (uint32_t f = 0; f < args.n_frags; ++f)
+      HIP_TRY(c, launch_colnz(args.f[f].T, args.f[f].rows, 1ull << (2 * args.f[f].n_axes), nz + sa.off[f], c->cur));
+    HIP_TRY(c, launch_support_terms(dargs, sa, nz, K, pos, scratch, terms, c->cur));
+  }
+  HIP_TRY(c, hipMemcpyAsync(&count, pos + K - 1, 8, hipMemcpyDeviceToHost, c->cur));
+  HIP_TRY(c, hipStreamSynchronize(c->cur));
+  if (count == 0) {  // every term vanishes
+    HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(res), 2ull << nq, 0u, c->cur));  // +0.0
+    return CCUT_OK;
+  }
+  if (!fp32 && (count << nq) <= (1ull << 20) && args.n_frags <= 8) {
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_recombine_terms(dargs, nq, terms, count, res, c->cur));
+    return CCUT_OK;
+  }
+  GemmArgs g;
+  make_gemm_args(args, g);
+  g.terms = terms;
+  g.K = count;
+  return run_gemm(c, g, fp32, res, true);
+}
+
 // Contract the fragment tensors into out[2^nq].  fp64 with at most 2^20
 // term-outputs: the plain ascending sum; otherwise the K-split MFMA contraction
 // (fp32 products with fp64 across K-chunks, or fp64 MFMA).
-ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
+ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res,
+                      bool sparse = false) {
+  if (sparse) return recombine_sparse(c, args, nq, fp32, res);
   const uint64_t K = 1ull << (2 * args.k);
   if (!fp32 && (K << nq) <= (1ull << 20)) {
     RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
@@ -1061,7 +1107,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
     if ((st = cancelled(c)) != CCUT_OK) return st;
   }
   if ((st = join(c)) != CCUT_OK) return st;
-  return recombine(c, args, nq, eo->precision == CCUT_FP32_MFMA_FP64SUM, res);
+  return recombine(c, args, nq, eo->precision == CCUT_FP32_MFMA_FP64SUM, res, (eo->flags & CCUT_FLAG_SPARSE) != 0);
 }
 }  // namespace
 
@@ -1082,7 +1128,7 @@ std::vector<uint8_t> call_key(uint32_t entry, const ccut_eval_opts *eo, const vo
   key_put(k, &eo->precision, 4);
   key_put(k, &eo->circuit, 4);
   key_put(k, &eo->method, 4);
-  key_put(k, &eo->reserved, 4);
+  key_put(k, &eo->flags, 4);
   key_put(k, &req_bytes, sizeof(req_bytes));
   key_put(k, req, req_bytes);
   const uintptr_t o = (uintptr_t)out;
@@ -1169,6 +1215,7 @@ ccut_status marginal_call(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t
   if (st != CCUT_OK) return st;
   ccut_ctx *c = p->ctx;
   if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
+  if (eo->flags & CCUT_FLAG_SETTLE) return fail(c, CCUT_E_UNSUPPORTED, "settlement applies to Z-string expectations");
   if ((st = check_request(c, p->pd.n, qubits, nq)) != CCUT_OK) return st;
   // a device output receives the contraction directly
   double *res = on_device ? out : aget<double>(c, (size_t)1 << nq);
@@ -1183,6 +1230,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   if (st != CCUT_OK) return st;
   ccut_ctx *c = p->ctx;
   if (!out || (n_strings && !masks)) return fail(c, CCUT_E_INVALID, "NULL argument");
+  if (eo->flags & CCUT_FLAG_SPARSE) return fail(c, CCUT_E_UNSUPPORTED, "the sparse contraction applies to marginals");
   if (n_strings == 0) return CCUT_OK;
   const PlanData &pd = p->pd;
   if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
@@ -1277,7 +1325,8 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
                                            eo->seed, h.vid_base + v0, d_ext, n_ext, odd + v0 * n_ext,
                                            c->cur));
         }
-        HIP_TRY(c, launch_parity_finish(odd, nv * n_ext, eo->shots_per_variant, E, c->cur));
+        HIP_TRY(c, launch_parity_finish(odd, nv * n_ext, eo->shots_per_variant, (eo->flags & CCUT_FLAG_SETTLE) != 0,
+                                        E, c->cur));
       }
     }
     double *T = nullptr;
@@ -1310,7 +1359,9 @@ extern "C" {
 
 ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
                           double *out, int on_device) {
-  if (!p || !eo || !out || (nq && !qubits) || nq > 24) return marginal_call(p, eo, qubits, nq, out, on_device);
+  // a sparse contraction reads its support size back: never captured
+  if (!p || !eo || !out || (nq && !qubits) || nq > 24 || (eo->flags & CCUT_FLAG_SPARSE))
+    return marginal_call(p, eo, qubits, nq, out, on_device);
   return graph_call(p, call_key(0, eo, qubits, (size_t)nq * 4, out), on_device,
                     [&] { return marginal_call(p, eo, qubits, nq, out, on_device); });
 }
@@ -1671,8 +1722,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       const uint64_t nv = h.n_variants;
       const bool lds = nm <= kLdsHistBits;
       uint32_t nblk;
-      if (lds) {  // as in the per-plan sampler
-        const uint64_t per_block = std::max<uint64_t>(bins, 2048);
+      if (lds) {  // up to 16384 shots per block: a batch has workgroups enough without splitting further
+        const uint64_t per_block = std::max<uint64_t>(bins, 16384);
         nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
       } else {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
@@ -1883,6 +1934,7 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
   *out = nullptr;
   if (c->device < 0) return fail(c, CCUT_E_DEVICE, "host-only context: evaluation needs a device");
   if (n == 0 || n > 65535) return fail(c, CCUT_E_INVALID, "batch size must be in [1, 65535]");
+  if (eo->flags) return fail(c, CCUT_E_UNSUPPORTED, "evaluation flags apply to single calls");
   std::unique_ptr<ccut_batch> b(new (std::nothrow) ccut_batch());
   if (!b) return fail(c, CCUT_E_OOM, "host allocation failed");
   b->ctx = c;

@@ -276,7 +276,7 @@ hipError_t launch_parity_exact(const uint64_t *models, uint32_t n_meas, uint64_t
 hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                                  uint64_t seed, uint64_t vid0, const uint64_t *ext_masks,
                                  uint32_t n_ext, uint32_t *odd_counts, hipStream_t s);
-hipError_t launch_parity_finish(const uint32_t *odd_counts, uint64_t n, uint64_t shots, double *E,
+hipError_t launch_parity_finish(const uint32_t *odd_counts, uint64_t n, uint64_t shots, bool settle, double *E,
                                 hipStream_t s);
 hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv,
                               const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
@@ -364,6 +364,20 @@ struct RcJob {
   uint32_t nq, pad_;
 };
 hipError_t launch_recombine_batch(const RcJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, hipStream_t s);
+// The plain fp64 sum over a term list (ascending cut terms; at most 8
+// fragments): the same operations as the full sum without its zero terms.
+hipError_t launch_recombine_terms(const RecombArgs *d_args, uint32_t nq, const uint64_t *terms, uint64_t n_terms,
+                                  double *out, hipStream_t s);
+// Sparse support of a contraction: nz[off_f + p] = 1 if column p of
+// fragment f's tensor has a nonzero entry; then the cut terms P with every
+// fragment's column nonzero, ascending, into terms[0 .. count) and the
+// count into *count (device).  pos: K words, scratch: scan_scratch_words(K).
+struct SupportArgs {
+  uint64_t off[kMaxFrags];
+};
+hipError_t launch_colnz(const double *T, uint32_t rows, uint64_t cols, uint8_t *nz, hipStream_t s);
+hipError_t launch_support_terms(const RecombArgs *d_args, const SupportArgs &sa, const uint8_t *nz, uint64_t K,
+                                uint64_t *pos, uint64_t *scratch, uint64_t *terms, hipStream_t s);
 constexpr uint32_t kRcChunkOut = 128;  // outputs per workgroup of the plain recombination
 // Z strings: fp64 products and sum, or (fp32 = true) fp32 products summed
 // in fp32 over chunks of 32 terms and in fp64 across chunks.

@@ -295,8 +295,10 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
 // computed once per workgroup into LDS, each thread keeps its rows in
 // registers, and the term loop is unrolled so the gathers overlap.
 constexpr uint32_t kRcFrags = 8, kRcChunk = kRcChunkOut;
+// terms: the cut terms to sum (ascending), or null for all 4^k.
 __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, uint32_t nq,
-                                            double *__restrict__ outp, uint64_t blk) {
+                                            double *__restrict__ outp, uint64_t blk,
+                                            const uint64_t *__restrict__ terms = nullptr, uint64_t n_terms = 0) {
   __shared__ uint64_t s_off[kRcFrags][kRcChunk];
   __shared__ const double *s_T[kRcFrags];
   const uint32_t tid = threadIdx.x;
@@ -312,13 +314,13 @@ __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, ui
       for (uint32_t i = 0; i < A->f[f].n_req; ++i) r |= (uint32_t)((b >> A->f[f].req_user[i]) & 1ull) << i;
     row[f] = r;
   }
-  const uint64_t nterms = 1ull << (2 * k);
+  const uint64_t nterms = terms ? n_terms : 1ull << (2 * k);
   double acc = 0.0;
   for (uint64_t P0 = 0; P0 < nterms; P0 += kRcChunk) {
     const uint32_t cn = (uint32_t)(nterms - P0 < kRcChunk ? nterms - P0 : kRcChunk);
     __syncthreads();  // the previous chunk is consumed
     if (tid < cn) {
-      const uint64_t P = P0 + tid;
+      const uint64_t P = terms ? terms[P0 + tid] : P0 + tid;
       for (uint32_t f = 0; f < nf; ++f) {
         const RecombFrag &F = A->f[f];
         uint32_t p = 0;
@@ -346,6 +348,49 @@ __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, ui
 __global__ __launch_bounds__(kRcChunk) void recombine_small_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
                                                                    double *__restrict__ outp) {
   recombine_small_body(A, nq, outp, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kRcChunk) void recombine_terms_kernel(const RecombArgs *__restrict__ A, uint32_t nq,
+                                                                   const uint64_t *__restrict__ terms,
+                                                                   uint64_t n_terms, double *__restrict__ outp) {
+  recombine_small_body(A, nq, outp, blockIdx.x, terms, n_terms);
+}
+
+// nz[c] = 1 if column c (rows contiguous) holds a nonzero: one wave per column.
+__global__ __launch_bounds__(256) void colnz_kernel(const double *__restrict__ T, uint32_t rows, uint64_t cols,
+                                                    uint8_t *__restrict__ nz) {
+  const uint64_t col = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (col >= cols) return;
+  const double *c = T + col * rows;
+  bool any = false;
+  for (uint32_t r = lane; r < rows; r += 64) any |= c[r] != 0.0;
+  const uint64_t b = __ballot(any);
+  if (lane == 0) nz[col] = b ? 1 : 0;
+}
+
+// pos[P] = 1 if every fragment's column p_f(P) is nonzero, else 0.
+__global__ void support_flags_kernel(const RecombArgs *__restrict__ A, const SupportArgs sa,
+                                     const uint8_t *__restrict__ nz, uint64_t K, uint64_t *__restrict__ pos) {
+  const uint64_t P = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= K) return;
+  uint64_t f = 1;
+  for (uint32_t i = 0; i < A->n_frags && f; ++i) {
+    const RecombFrag &F = A->f[i];
+    uint64_t p = 0;
+    for (uint32_t j = 0; j < F.n_axes; ++j) p |= ((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
+    f = nz[sa.off[i] + p];
+  }
+  pos[P] = f;
+}
+
+// after the inclusive scan: term P with flag 1 goes to terms[pos[P] - 1]
+__global__ void support_scatter_terms_kernel(const uint64_t *__restrict__ pos, uint64_t K,
+                                             uint64_t *__restrict__ terms) {
+  const uint64_t P = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= K) return;
+  const uint64_t prev = P ? pos[P - 1] : 0;
+  if (pos[P] != prev) terms[prev] = P;
 }
 
 // Many plans' plain recombinations in one launch.
@@ -504,6 +549,31 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uin
     hipLaunchKernelGGL(recombine_small_kernel, dim3(blocks_for(n, kRcChunk)), dim3(kRcChunk), 0, s, d_args, nq, out);
   else
     hipLaunchKernelGGL(recombine_fp64_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, s, d_args, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_recombine_terms(const RecombArgs *d_args, uint32_t nq, const uint64_t *terms, uint64_t n_terms,
+                                  double *out, hipStream_t s) {
+  const uint64_t n = 1ull << nq;
+  hipLaunchKernelGGL(recombine_terms_kernel, dim3(blocks_for(n, kRcChunk)), dim3(kRcChunk), 0, s, d_args, nq, terms,
+                     n_terms, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colnz(const double *T, uint32_t rows, uint64_t cols, uint8_t *nz, hipStream_t s) {
+  if (cols == 0) return hipSuccess;
+  if ((cols + 3) / 4 > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(colnz_kernel, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, s, T, rows, cols, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_support_terms(const RecombArgs *d_args, const SupportArgs &sa, const uint8_t *nz, uint64_t K,
+                                uint64_t *pos, uint64_t *scratch, uint64_t *terms, hipStream_t s) {
+  hipLaunchKernelGGL(support_flags_kernel, dim3(blocks_for(K, 256)), dim3(256), 0, s, d_args, sa, nz, K, pos);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_scan_u64(pos, K, scratch, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(support_scatter_terms_kernel, dim3(blocks_for(K, 256)), dim3(256), 0, s, pos, K, terms);
   return hipGetLastError();
 }
 

@@ -47,19 +47,23 @@ constexpr int kSampleBlock = 256;
 __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
                             uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
                             uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
-                            uint64_t *s_dyn) {
+                            uint64_t *s_dyn, uint64_t *s_model) {
   const uint32_t mw = model_words(n_meas);
   const uint64_t *md = models + v * mw;
   const uint32_t groups = sample_tab_groups(n_meas);
   uint64_t *s_tab = s_dyn;
   uint32_t *s_hist = reinterpret_cast<uint32_t *>(s_dyn + groups * 256);
-  const uint64_t x0 = md[0], rmask = md[1];
+  // the model to LDS in one coalesced load, then the tables from LDS
+  if (threadIdx.x < mw) s_model[threadIdx.x] = md[threadIdx.x];
+  __syncthreads();
+  const uint64_t x0 = s_model[0], rmask = s_model[1];
   for (uint32_t e = threadIdx.x; e < groups * 256; e += kSampleBlock) {
     const uint32_t g = e >> 8, b = e & 255u;
     uint64_t t = 0;
+#pragma unroll
     for (uint32_t i = 0; i < 8; ++i) {
       const uint32_t a = 8 * g + i;
-      if (((b >> i) & 1u) && a < n_meas && ((rmask >> a) & 1ull)) t ^= md[2 + a];
+      if (((b >> i) & 1u) && a < n_meas && ((rmask >> a) & 1ull)) t ^= s_model[2 + a];
     }
     s_tab[e] = t;
   }
@@ -71,22 +75,39 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   const uint64_t vid = vid0 + v;
   const bool wide = n_meas > 32;
   const uint64_t nquads = (shots + 3) >> 2;
+  // With few random bits the shots of a wave land on few bins: lanes with
+  // equal outcomes then add their count once (one atomic per distinct
+  // outcome in the wave instead of up to 64 on one address).
+  const bool combine = partial != nullptr && __popcll(rmask) <= 6;
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t *hist = lds_hist ? s_hist : (partial ? partial + v * (uint64_t)bins : nullptr);
   for (uint32_t q = 0; q < qpt; ++q) {
     const uint64_t quad = ((uint64_t)bx * qpt + q) * kSampleBlock + threadIdx.x;
-    if (quad >= nquads) break;
+    if (!combine && quad >= nquads) break;
+    if (combine && ((uint64_t)bx * qpt + q) * kSampleBlock >= nquads) break;  // the whole workgroup is done
     uint64_t u[4];
     quad_bits(quad, vid, seed, wide, u);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint64_t s = quad * 4 + r;
-      if (s >= shots) break;
+      const bool valid = quad < nquads && s < shots;
+      if (!combine && !valid) break;
       uint64_t x = x0;
       for (uint32_t g = 0; g < groups; ++g) x ^= s_tab[(g << 8) | (uint32_t)((u[r] >> (8 * g)) & 255u)];
-      if (records) records[v * shots + s] = x;
-      if (lds_hist)
-        atomicAdd(&s_hist[x], 1u);
-      else if (partial)
-        atomicAdd(&partial[v * (uint64_t)bins + x], 1u);
+      if (records && valid) records[v * shots + s] = x;
+      if (combine) {
+        // every lane of the wave is here (no early exit on this path)
+        uint64_t todo = __ballot(valid);
+        while (todo) {
+          const uint32_t leader = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
+          const uint32_t xl = __builtin_amdgcn_readlane((uint32_t)x, leader);
+          const uint64_t same = __ballot(valid && (uint32_t)x == xl) & todo;
+          if (lane == leader) atomicAdd(&hist[xl], (uint32_t)__popcll(same));
+          todo &= ~same;
+        }
+      } else if (hist) {
+        atomicAdd(&hist[x], 1u);
+      }
     }
   }
   if (lds_hist) {
@@ -101,7 +122,9 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
     const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
     uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
   extern __shared__ uint64_t s_dyn[];
-  sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn);
+  __shared__ uint64_t s_model[2 + kMaxMeas];
+  sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn,
+              s_model);
 }
 
 // Many fragments' sampling in one launch: unit g runs block
@@ -111,6 +134,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const Sample
                                                                       uint32_t n_jobs, uint64_t total,
                                                                       uint32_t per_wg) {
   extern __shared__ uint64_t s_dyn[];
+  __shared__ uint64_t s_model[2 + kMaxMeas];
   const uint64_t g0 = (uint64_t)blockIdx.x * per_wg;
   const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
   uint32_t j = find_job(jobs, n_jobs, g0, [](const SampleJob &J) { return J.wg0; });
@@ -120,7 +144,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const Sample
     const SampleJob &J = jobs[j];
     const uint64_t local = g - J.wg0;
     sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
-                (uint32_t)(local % J.nblk), J.nblk, s_dyn);
+                (uint32_t)(local % J.nblk), J.nblk, s_dyn, s_model);
   }
 }
 
@@ -279,11 +303,16 @@ __global__ __launch_bounds__(kParityBlock) void parity_sampled_kernel(
     if (s_cnt[s]) atomicAdd(&odd_counts[v * n_ext + s], s_cnt[s]);
 }
 
-__global__ void parity_finish_kernel(const uint32_t *__restrict__ odd, uint64_t n, uint64_t shots,
+// settle: a Pauli expectation on a stabilizer state is -1, 0 or +1, so
+// shots showing both parities give 0 and shots that agree their sign.
+__global__ void parity_finish_kernel(const uint32_t *__restrict__ odd, uint64_t n, uint64_t shots, int settle,
                                      double *__restrict__ E) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  E[i] = ((double)shots - 2.0 * (double)odd[i]) / (double)shots;
+  if (settle)
+    E[i] = odd[i] == 0 ? 1.0 : (uint64_t)odd[i] == shots ? -1.0 : 0.0;
+  else
+    E[i] = ((double)shots - 2.0 * (double)odd[i]) / (double)shots;
 }
 
 // <(-1)^{z.x}> for every mask z from an outcome distribution over n_meas
@@ -404,8 +433,10 @@ hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64
   return hipGetLastError();
 }
 
-hipError_t launch_parity_finish(const uint32_t *odd, uint64_t n, uint64_t shots, double *E, hipStream_t s) {
-  hipLaunchKernelGGL(parity_finish_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, odd, n, shots, E);
+hipError_t launch_parity_finish(const uint32_t *odd, uint64_t n, uint64_t shots, bool settle, double *E,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(parity_finish_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, odd, n, shots, settle ? 1 : 0,
+                     E);
   return hipGetLastError();
 }
 

@@ -1,0 +1,102 @@
+"""Clifford-specific cutting optimisations (Sec. IX) on the GPU against the
+oracle: the sparse contraction over the nonzero cut terms, and few-shot
+settlement of sampled Clifford string expectations."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2303_10788_amd as cc
+import workloads as W
+from oracle import cutting as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return cc.Context()
+
+
+def _case(seed, clifford_only):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(4, 9))
+    kinds = W.CLIFFORD_KINDS if clifford_only else W.ALL_KINDS
+    ops = W.random_circuit(n, int(rng.integers(15, 40)), seed, kinds=kinds)
+    cuts = W.random_cuts(n, ops, int(rng.integers(1, 4)), seed)
+    return n, ops, cuts, rng
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sparse_marginal_equals_dense_and_oracle(ctx, seed):
+    n, ops, cuts, rng = _case(seed, seed % 2 == 0)
+    qubits = [int(q) for q in rng.permutation(n)[: int(rng.integers(1, n + 1))]]
+    _log(f"sparse marginal: seed={seed} n={n} k={len(cuts)} nq={len(qubits)}")
+    plan = cc.Plan(ctx, n, ops, cuts)
+    for shots in (0, 500):
+        dense = plan.marginal(qubits, shots=shots, seed=seed)
+        sparse = plan.marginal(qubits, shots=shots, seed=seed, flags=cc.CCUT_FLAG_SPARSE)
+        # plain ascending sum with the zero terms left out: the same bits
+        assert np.array_equal(sparse, dense), shots
+        ref = C.marginal(n, ops, cuts, qubits, shots=shots, seed=seed, sparse=True)
+        assert np.abs(sparse - ref).max() <= 1e-10, shots
+
+
+def test_sparse_matrix_core_paths(ctx):
+    """Large contractions (the skinny and the MFMA term-list paths) over the
+    support against the dense contraction."""
+    import torch
+    for w in (W.precision(), W.learned_circuit(200001)):
+        plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+        _log(f"sparse contraction: {w.name} k={len(w.cuts)}")
+        dense = plan.marginal(w.qubits)
+        sparse = plan.marginal(w.qubits, flags=cc.CCUT_FLAG_SPARSE)
+        assert np.abs(sparse - dense).max() <= 1e-12
+        out = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
+        for _ in range(2):  # device output, repeated: eager every time
+            out.zero_()
+            plan.marginal(w.qubits, flags=cc.CCUT_FLAG_SPARSE, out=out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), sparse)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_settled_zexpect_vs_oracle_and_exact(ctx, seed):
+    n, ops, cuts, rng = _case(seed, True)
+    masks = [int(m) for m in rng.integers(1, 1 << n, size=12)]
+    words = np.array([[m] for m in masks], dtype=np.uint64)
+    _log(f"settled z strings: seed={seed} n={n} k={len(cuts)}")
+    plan = cc.Plan(ctx, n, ops, cuts)
+    got = plan.zexpect(words, shots=64, seed=seed, flags=cc.CCUT_FLAG_SETTLE)
+    ref = C.zexpect(n, ops, cuts, masks, shots=64, seed=seed, settle=True)
+    assert np.abs(got - ref).max() <= 1e-12
+    exact = plan.zexpect(words)
+    assert np.abs(got - exact).max() <= 1e-12
+    raw = plan.zexpect(words, shots=64, seed=seed)
+    assert np.abs(raw - C.zexpect(n, ops, cuts, masks, shots=64, seed=seed)).max() <= 1e-10
+
+
+def test_flag_scope_errors(ctx):
+    w = W.tiny()
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    words = np.array([[1], [3]], dtype=np.uint64)
+    with pytest.raises(cc.CcutError) as e:
+        plan.marginal(w.qubits, flags=cc.CCUT_FLAG_SETTLE)
+    assert e.value.status == cc.CCUT_E_UNSUPPORTED
+    with pytest.raises(cc.CcutError) as e:
+        plan.zexpect(words, flags=cc.CCUT_FLAG_SPARSE)
+    assert e.value.status == cc.CCUT_E_UNSUPPORTED
+    with pytest.raises(cc.CcutError) as e:
+        plan.marginal(w.qubits, flags=8)
+    assert e.value.status == cc.CCUT_E_INVALID
+    eo = cc._eval_opts(0, 0, flags=cc.CCUT_FLAG_SPARSE)
+    with pytest.raises(cc.CcutError) as e:
+        cc.ccut_batch_create(ctx.handle, [plan], eo, [w.qubits])
+    assert e.value.status == cc.CCUT_E_UNSUPPORTED

@@ -315,7 +315,7 @@ def test_planted_mistakes_are_caught(monkeypatch, mutation):
         monkeypatch.setattr(C, "BASIS_Z", C.BASIS_X)   # I and Z terms from the X variant
     elif mutation == "cut_scale":
         orig = C.recombine
-        monkeypatch.setattr(C, "recombine", lambda *a: orig(*a) * 2.0)
+        monkeypatch.setattr(C, "recombine", lambda *a, **kw: orig(*a, **kw) * 2.0)
     elif mutation == "p_index":
         monkeypatch.setattr(C.Fragment, "p_index",
                             lambda self, P: sum(((P >> (2 * a.cut)) & 3) << (2 * (len(self.axes) - 1 - j))
