@@ -460,8 +460,17 @@ def bench_learned(args):
         L.estimate(q, n_samples, 9, out=out_le)
         L.close()
 
+    out_sp = torch.empty_like(out_ex)
+
+    def sparse_exhaustive():  # Sec. IX: only the cut terms whose columns are all nonzero
+        plan.marginal(w.qubits, out=out_sp, flags=cc.CCUT_FLAG_SPARSE)
+
     dt_ex = _timed(exhaustive, args.steps, args.warmup)
+    dt_sp = _timed(sparse_exhaustive, args.steps, args.warmup)
     dt_le = _timed(learned, args.steps, args.warmup)
+    Ls = cc.Learned(plan, w.qubits)
+    _, n_support = Ls.support(cap=0)
+    Ls.close()
     times = _kernel_pass(ctx, learned, args.steps)
     ex = out_ex.cpu().numpy()
     le = out_le.cpu().numpy()
@@ -481,6 +490,8 @@ def bench_learned(args):
                                "network trained on 16 circuits of the family, evaluated on a held-out one",
                    "samples": n_samples, "cut_terms": K},
         "exhaustive_ms": ms_ex, "learned_ms": ms_le, "tvd_learned_vs_exhaustive": tvd,
+        "sparse_exhaustive_ms": 1e3 * dt_sp / args.steps, "support_terms": int(n_support),
+        "sparse_max_abs_diff": float(np.abs(out_sp.cpu().numpy() - ex).max()),
         "train": {"rows": rows, "steps": 2000, "batch": 1024, "loss_first": float(losses[:5].mean()),
                   "loss_last": float(losses[-50:].mean()), "train_s": t_train, "dataset_s": t_data},
         "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
