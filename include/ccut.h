@@ -94,6 +94,18 @@ typedef struct {
   uint32_t after_op;
 } ccut_cut;
 
+/* Automatic cut placement (the circuit cutter of Sec. V-A; no context or
+ * device needed).  Chooses cut locations such that every fragment holding
+ * a non-Clifford op (T, TDG, RZ) has at most max_width qubits, aiming at few
+ * cuts (the recombination costs 4^k): a greedy search from one region per non-Clifford
+ * op that merges regions, or stretches one to a wire's first or last op,
+ * while the total cut count drops.  Never more than 2 cuts per non-Clifford
+ * op (Sec. III-B's bound).  Writes min(k, cap) cuts, ascending by
+ * (after_op, qubit), and k to *k (host).  CCUT_E_INVALID: malformed
+ * circuit, max_width = 0; CCUT_E_TOO_MANY_CUTS: k > cap (*k still set). */
+ccut_status ccut_find_cuts(uint32_t n_qubits, const ccut_op *ops, size_t n_ops, uint32_t max_width,
+                           ccut_cut *cuts, size_t cap, size_t *k);
+
 /* Optional device allocator (for example a framework's caching allocator).
  * alloc returns NULL on failure, which the library reports as CCUT_E_OOM. */
 typedef void *(*ccut_alloc_fn)(size_t bytes, void *user);

@@ -132,6 +132,8 @@ SIGNATURES = {
     "ccut_mlp_train_step": ([_P, _P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.POINTER(ctypes.c_float)],
                             ctypes.c_int),
     "ccut_mlp_destroy": ([_P], None),
+    "ccut_find_cuts": ([ctypes.c_uint32, ctypes.POINTER(ccut_op), ctypes.c_size_t, ctypes.c_uint32,
+                        ctypes.POINTER(ccut_cut), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
 }
 
 _lib = None
@@ -192,6 +194,20 @@ def _cuts_array(cuts):
     for i, (q, a) in enumerate(cuts):
         arr[i] = ccut_cut(int(q), int(a))
     return arr
+
+
+def ccut_find_cuts(n_qubits: int, ops, max_width: int = 12):
+    """Cut locations [(qubit, after_op)] that put every non-Clifford op in
+    a fragment of at most max_width qubits, with few cuts."""
+    arr = _ops_array(ops)
+    k = ctypes.c_size_t()
+    cap = max(2 * len(ops), 1)
+    out = (ccut_cut * cap)()
+    _check(lib().ccut_find_cuts(n_qubits, arr, len(ops), max_width, out, cap, ctypes.byref(k)), None)
+    return [(out[i].qubit, out[i].after_op) for i in range(k.value)]
+
+
+find_cuts = ccut_find_cuts
 
 
 def ccut_plan_create(ctx, n_qubits: int, ops, cuts):

@@ -100,3 +100,21 @@ def test_flag_scope_errors(ctx):
     with pytest.raises(cc.CcutError) as e:
         cc.ccut_batch_create(ctx.handle, [plan], eo, [w.qubits])
     assert e.value.status == cc.CCUT_E_UNSUPPORTED
+
+
+def test_found_cuts_end_to_end(ctx):
+    """Cut lists from the automatic cutter drive the GPU path: the tiny
+    circuit against its uncut state vector, the 32-qubit circuit (exact
+    mode) against the same marginal with its hand-placed block cuts."""
+    from oracle import statevector as sv
+    w = W.tiny()
+    cuts = cc.find_cuts(w.n, w.ops, 4)
+    _log(f"found cuts: tiny {cuts}")
+    got = cc.Plan(ctx, w.n, w.ops, cuts).marginal(w.qubits)
+    assert np.abs(got - sv.uncut_marginal(w.n, w.ops, w.qubits)).max() <= 1e-10
+    w = W.mid()
+    cuts = cc.find_cuts(w.n, w.ops, 12)
+    _log(f"found cuts: mid {cuts}")
+    a = cc.Plan(ctx, w.n, w.ops, cuts).marginal(w.qubits)
+    b = cc.Plan(ctx, w.n, w.ops, w.cuts).marginal(w.qubits)
+    assert np.abs(a - b).max() <= 1e-10
