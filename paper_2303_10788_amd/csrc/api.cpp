@@ -818,8 +818,14 @@ ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp3
   return run_gemm(c, g, fp32, res, true);
 }
 
-bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo) {
-  return f.clifford && eo->shots_per_variant == 0 && eo->method != CCUT_METHOD_VARIANTS;
+// Exact-mode Clifford fragments take the Heisenberg picture unless told
+// otherwise; a marginal request of more than 14 bits on the fragment
+// (req_bits) takes the variant path, since the transform to the Pauli basis
+// runs one LDS block of 2^req_bits entries per row (Z strings: req_bits 0).
+constexpr uint32_t kHeisMaxReqBits = 14;
+bool use_heisenberg(const Fragment &f, const ccut_eval_opts *eo, size_t req_bits) {
+  return f.clifford && eo->shots_per_variant == 0 && eo->method != CCUT_METHOD_VARIANTS &&
+         req_bits <= kHeisMaxReqBits;
 }
 
 // Results to the caller: into host memory with a final synchronization, or
@@ -1059,7 +1065,7 @@ ccut_status ccut_fragment_tensor(ccut_plan *p, const ccut_eval_opts *eo, const u
   const Fragment &f = p->pd.frags[fragment];
   FragRequest r = marginal_request(f, qubits, nq);
   double *dist = nullptr, *T = nullptr;
-  if (use_heisenberg(f, eo)) {
+  if (use_heisenberg(f, eo, r.req_pos.size())) {
     if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
   } else {
     if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;
@@ -1089,7 +1095,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
     route(c, f);
     FragRequest r = marginal_request(f, qubits, nq);
     double *dist = nullptr, *T = nullptr;
-    if (use_heisenberg(f, eo)) {
+    if (use_heisenberg(f, eo, r.req_pos.size())) {
       if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
     } else {
       uint64_t *pm = pre_models ? (*pre_models)[f.index] : nullptr;
@@ -1248,7 +1254,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
     FragRequest r = zstring_request(f, anymask);
     const uint32_t nm = (uint32_t)r.meas.size();
     const uint64_t nv = f.n_variants;
-    if (use_heisenberg(f, eo)) {
+    if (use_heisenberg(f, eo, 0)) {
       const uint32_t W = row_words(f.m());
       if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
       std::vector<std::vector<uint64_t>> zs(n_strings, std::vector<uint64_t>(W, 0));
@@ -1810,7 +1816,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     for (const Fragment &f : pd.frags) {
       FragRequest r = marginal_request(f, qubits, nq);
       double *T = nullptr;
-      if (use_heisenberg(f, &eo)) {
+      if (use_heisenberg(f, &eo, r.req_pos.size())) {
         st = heis_tensor(p, f, r, eo.circuit, nullptr, &T);
       } else {
         double *dist = pre_dist[i][f.index];
@@ -1960,8 +1966,8 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
         b->sv_descs.push_back(frag_desc(p, f, r, (uint32_t)i));
         continue;
       }
-      if (use_heisenberg(f, eo)) continue;
       FragRequest r = marginal_request(f, qubits[i], nq[i]);
+      if (use_heisenberg(f, eo, r.req_pos.size())) continue;
       const uint32_t nm = (uint32_t)r.meas.size();
       if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits");
       if (f.m() > 512) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
@@ -2474,7 +2480,7 @@ ccut_status ccut_learned_create(ccut_plan *p, const ccut_eval_opts *eo, const ui
     for (const Fragment &f : pd.frags) {
       FragRequest r = marginal_request(f, qubits, nq);
       double *dist = nullptr, *T = nullptr;
-      if (use_heisenberg(f, eo)) {
+      if (use_heisenberg(f, eo, r.req_pos.size())) {
         if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
       } else {
         if ((st = variant_dists(p, eo, f, r, &dist)) != CCUT_OK) return st;

@@ -118,3 +118,38 @@ def test_found_cuts_end_to_end(ctx):
     a = cc.Plan(ctx, w.n, w.ops, cuts).marginal(w.qubits)
     b = cc.Plan(ctx, w.n, w.ops, w.cuts).marginal(w.qubits)
     assert np.abs(a - b).max() <= 1e-10
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_paper_workloads_with_found_cuts(ctx, seed):
+    """The paper's workload families end to end on the GPU (automatic cuts,
+    exact mode) against the uncut state vector."""
+    from oracle import statevector as sv
+    for w in (W.hwea(12, seed=seed), W.qaoa_sk(10, seed=seed), W.phase_code(7, seed=seed)):
+        cuts = cc.find_cuts(w.n, w.ops, 4)
+        _log(f"paper workload {w.name}: cuts {cuts}")
+        plan = cc.Plan(ctx, w.n, w.ops, cuts)
+        if w.zmasks:
+            got = plan.zexpect(w.zmask_words())
+            p = sv.probabilities(sv.run(w.n, w.ops))
+            ref = np.array([sv.z_expectation(p, w.n, m) for m in w.zmasks])
+        else:
+            got = plan.marginal(w.qubits)
+            ref = sv.uncut_marginal(w.n, w.ops, w.qubits)
+        assert np.abs(got - ref).max() <= 1e-10, w.name
+
+
+def test_wide_exact_request_takes_variant_path(ctx):
+    """An exact marginal with more than 14 requested bits on a Clifford
+    fragment goes through the per-variant exact tables (the Heisenberg
+    transform is limited to 14): against the uncut state vector."""
+    from oracle import statevector as sv
+    w = W.hwea(18, rounds=2, seed=3)
+    cuts = cc.find_cuts(w.n, w.ops, 4)
+    qubits = list(range(16))
+    plan = cc.Plan(ctx, w.n, w.ops, cuts)
+    reqs = [cc.ccut_request_info(plan.handle, qubits, f)[1] for f in range(len(plan.fragments()))]
+    assert max(reqs) > 14, reqs
+    _log(f"wide exact request: cuts {cuts}, requested bits {reqs}")
+    got = plan.marginal(qubits)
+    assert np.abs(got - sv.uncut_marginal(w.n, w.ops, qubits)).max() <= 1e-10

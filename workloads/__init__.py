@@ -367,3 +367,90 @@ def random_cuts(n: int, ops: Sequence[Op], k: int, seed: int) -> List[Cut]:
         raise ValueError("not enough cut locations")
     idx = rng.choice(len(cand), size=k, replace=False)
     return sorted((cand[i] for i in idx), key=lambda c: (c[1], c[0]))
+
+
+# ------------------------------------------- the paper's workloads (Sec. VI-B)
+# Written from the paper's descriptions (no benchmark-suite code): each
+# circuit is Clifford with `n_t` T gates injected at random op positions;
+# its cuts are left to the automatic cutter (cuts = []).
+
+# Clifford angles of the ansatz rotations: RZ(k pi/2) is I, S, Z, S^dag
+_RZ_CLIFFORD = {0: [], 1: ["S"], 2: ["Z"], 3: ["SDG"]}
+
+
+def _clifford_rz(rng, q: int) -> List[Op]:
+    return [(g, q, -1, 0.0) for g in _RZ_CLIFFORD[int(rng.integers(4))]]
+
+
+def _clifford_ry(rng, q: int) -> List[Op]:
+    # RY(k pi/2) up to a global phase: S^dag H RZ(k pi/2) H S
+    body = _clifford_rz(rng, q)
+    if not body:
+        return []
+    return [("SDG", q, -1, 0.0), ("H", q, -1, 0.0)] + body + [("H", q, -1, 0.0), ("S", q, -1, 0.0)]
+
+
+def _inject_t(rng, ops: List[Op], n_t: int, n: int) -> List[Op]:
+    """Insert n_t T gates on random wires at random positions of the op list."""
+    out = list(ops)
+    for _ in range(n_t):
+        pos = int(rng.integers(len(out) + 1))
+        out.insert(pos, ("T", int(rng.integers(n)), -1, 0.0))
+    return out
+
+
+def hwea(n: int, rounds: int = 5, seed: int = 0, n_t: int = 1) -> Workload:
+    """Near-Clifford hardware-efficient ansatz (Sec. VI-B): per round a layer
+    of single-qubit rotations (RY then RZ at Clifford angles), a linear
+    chain of CX entanglers, and a final single-qubit rotation layer."""
+    rng = np.random.default_rng([seed, 31, n])
+    ops: List[Op] = []
+    for _ in range(rounds):
+        for q in range(n):
+            ops += _clifford_ry(rng, q) + _clifford_rz(rng, q)
+        for q in range(n - 1):
+            ops.append(("CX", q, q + 1, 0.0))
+        for q in range(n):
+            ops += _clifford_ry(rng, q) + _clifford_rz(rng, q)
+    ops = _inject_t(rng, ops, n_t, n)
+    return Workload(f"hwea{n}", n, ops, [], list(range(n)), [1 << q for q in range(n)], seed=seed, depth=rounds)
+
+
+def qaoa_sk(n: int, seed: int = 0, n_t: int = 1) -> Workload:
+    """One round of MaxCut QAOA on the Sherrington-Kirkpatrick model
+    (complete graph, weights +-1; Sec. IV / VI-B) at Clifford angles: H on
+    every qubit, exp(-i gamma w_ij Z_i Z_j) for every pair as CX, RZ, CX with
+    gamma w_ij a multiple of pi/4 (RZ(2 gamma w) a Clifford), then the
+    mixer RX(2 beta) = H RZ(2 beta) H."""
+    rng = np.random.default_rng([seed, 37, n])
+    g = int(rng.integers(1, 4))   # 2 gamma = g pi/2
+    b = int(rng.integers(1, 4))   # 2 beta = b pi/2
+    ops: List[Op] = [("H", q, -1, 0.0) for q in range(n)]
+    for i in range(n):
+        for j in range(i + 1, n):
+            w = 1 if rng.random() < 0.5 else -1
+            k = (g * w) % 4
+            ops.append(("CX", i, j, 0.0))
+            ops += [(gate, j, -1, 0.0) for gate in _RZ_CLIFFORD[k]]
+            ops.append(("CX", i, j, 0.0))
+    for q in range(n):
+        ops += [("H", q, -1, 0.0)] + [(gate, q, -1, 0.0) for gate in _RZ_CLIFFORD[b]] + [("H", q, -1, 0.0)]
+    ops = _inject_t(rng, ops, n_t, n)
+    return Workload(f"qaoa{n}", n, ops, [], list(range(n)), [1 << q for q in range(n)], seed=seed, depth=1)
+
+
+def phase_code(n_data: int, seed: int = 0, n_t: int = 1) -> Workload:
+    """One round of the phase-flip repetition code (Sec. VI-B): data qubits
+    0..d-1 prepared in |+>, ancilla d+i measures X_i X_{i+1} (H, CX from
+    the ancilla to both data qubits, H), data measured in the X basis.  The
+    request is the syndrome (the ancillas), a sparse distribution."""
+    rng = np.random.default_rng([seed, 41, n_data])
+    d = n_data
+    n = 2 * d - 1
+    ops: List[Op] = [("H", q, -1, 0.0) for q in range(d)]
+    for i in range(d - 1):
+        a = d + i
+        ops += [("H", a, -1, 0.0), ("CX", a, i, 0.0), ("CX", a, i + 1, 0.0), ("H", a, -1, 0.0)]
+    ops += [("H", q, -1, 0.0) for q in range(d)]
+    ops = _inject_t(rng, ops, n_t, n)
+    return Workload(f"phase{d}", n, ops, [], list(range(d, n)), [], seed=seed, depth=1)
