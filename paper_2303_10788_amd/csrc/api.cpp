@@ -1709,14 +1709,17 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     return st;
   if (!b->samp.empty()) {
     // jobs in LDS classes (one launch each, so a launch's workgroups reserve
-    // only their class's histogram): up to 8, 20, 36 and 68 KiB
+    // only their class's histogram): up to 8, 20, 38 and 80 KiB
     const uint64_t shots = b->eo.shots_per_variant;
     const uint64_t nquads = (shots + 3) / 4;
-    auto lds_class = [](size_t l) { return l <= (8u << 10) ? 0 : l <= (20u << 10) ? 1 : l <= (36u << 10) ? 2 : 3; };
+    auto lds_class = [](size_t l) { return l <= (8u << 10) ? 0 : l <= (20u << 10) ? 1 : l <= (38u << 10) ? 2 : 3; };
     std::vector<size_t> order;
     for (int cls = 0; cls < 4; ++cls)
       for (size_t q = 0; q < b->samp.size(); ++q)
-        if (lds_class(sample_lds_bytes(b->samp[q].n_meas, true)) == cls) order.push_back(q);
+        if (lds_class(sample_lds_bytes(b->samp[q].n_meas, true,
+                                       b->samp[q].n_meas > kLdsHistBits && b->samp[q].n_meas <= kLdsHistBits + 3)) ==
+            cls)
+          order.push_back(q);
     std::vector<SampleJob> jobs;
     uint64_t t = 0, fill_words = 0;
     uint64_t cls_units[4] = {0, 0, 0, 0};
@@ -1726,18 +1729,22 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       const FragDev &h = b->descs[ref.desc];
       const uint32_t nm = ref.n_meas, bins = 1u << nm;
       const uint64_t nv = h.n_variants;
-      const bool lds = nm <= kLdsHistBits;
+      // up to 3 bits above the LDS histogram: one workgroup per 2^14-bin
+      // slice, each replaying the shots (no global atomics, no zero fill)
+      const uint32_t nslice = nm > kLdsHistBits && nm <= kLdsHistBits + 3 ? 1u << (nm - kLdsHistBits) : 1u;
+      const bool lds = nm <= kLdsHistBits || nslice > 1;
       uint32_t nblk;
       if (lds) {  // up to 16384 shots per block: a batch has workgroups enough without splitting further
-        const uint64_t per_block = std::max<uint64_t>(bins, 16384);
+        const uint64_t per_block = std::max<uint64_t>(std::min<uint64_t>(bins, 1u << kLdsHistBits), 16384);
         nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
       } else {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         fill_words += nv * (uint64_t)bins;
       }
-      const int cls = lds_class(sample_lds_bytes(nm, true));
+      const size_t lds_need = sample_lds_bytes(nm, true, nslice > 1);
+      const int cls = lds_class(lds_need);
       if (cls_count[cls]++ == 0) cls_first[cls] = jobs.size();
-      cls_lds[cls] = std::max<size_t>(cls_lds[cls], sample_lds_bytes(nm, true));
+      cls_lds[cls] = std::max<size_t>(cls_lds[cls], lds_need);
       SampleJob J{};
       J.models = d_models + b->model_off[ref.plan][ref.frag];
       J.shots = shots;
@@ -1747,10 +1754,13 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.n_meas = nm;
       J.nblk = nblk;
       J.qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
+      J.nslice = nslice;
       J.wg0 = cls_units[cls];
       J.rb0 = t;
-      cls_units[cls] += nv * nblk;
-      t += (nv * bins + 4095) / 4096;  // reduction workgroups
+      cls_units[cls] += nv * nblk * nslice;
+      // one shot block in LDS: the sampling workgroups write the table
+      // themselves; otherwise partial counts and a reduction
+      if (!(lds && nblk == 1)) t += (nv * bins + 4095) / 4096;  // reduction workgroups
       jobs.push_back(J);
     }
     // partial counts: the per-variant ones (zeroed) first, contiguous
@@ -1760,14 +1770,16 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     for (size_t q = 0; q < jobs.size(); ++q) {
       SampleJob &J = jobs[q];
       const uint64_t bins = 1ull << J.n_meas;
-      if (J.n_meas <= kLdsHistBits) {
+      if ((J.n_meas <= kLdsHistBits || J.nslice > 1) && J.nblk == 1) {
+        J.partial = nullptr;  // written directly as the table
+      } else if (J.n_meas <= kLdsHistBits || J.nslice > 1) {
         J.partial = aget<uint32_t>(c, J.nv * J.nblk * bins);
       } else {
         J.partial = zeroed + zo;
         zo += J.nv * bins;
       }
       J.dist = aget<double>(c, J.nv * bins);
-      if (!J.partial || !J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+      if ((!J.partial && J.nblk != 1) || !J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
       pre_dist[b->samp[order[q]].plan][b->samp[order[q]].frag] = J.dist;
     }
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));

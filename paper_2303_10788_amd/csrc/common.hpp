@@ -194,8 +194,8 @@ struct BatchItem {
 
 // One fragment's sampled outcome tables in a batched launch: variants
 // [0, nv) of `models`, nblk shot blocks per variant (qpt quads per thread),
-// counts in `partial` (per block when n_meas <= 14, else per variant, zeroed
-// beforehand), tables in `dist`.  wg0 / rb0: the job's first workgroup of
+// counts in `partial` (per block when n_meas <= 14 or sliced, else per
+// variant, zeroed beforehand), tables in `dist`.  wg0 / rb0: the job's first workgroup of
 // the sampling launch and of the reduction launch (4096 entries each).
 struct SampleJob {
   const uint64_t *models;
@@ -203,16 +203,21 @@ struct SampleJob {
   double *dist;
   uint64_t shots, seed, vid0, nv;
   uint64_t wg0, rb0;
-  uint32_t n_meas, nblk, qpt, pad_;
+  uint32_t n_meas, nblk, qpt;
+  uint32_t nslice;  // > 1: n_meas > kLdsHistBits counted in LDS slices of 2^kLdsHistBits bins
 };
 
 // Sampling LDS: the shot xor's byte tables (256 u64 per 8 measurement
 // indices) and, for n_meas <= kLdsHistBits, the workgroup's u32 histogram.
 constexpr uint32_t kLdsHistBits = 14;
 __host__ __device__ inline uint32_t sample_tab_groups(uint32_t n_meas) { return (n_meas + 7) / 8; }
-inline size_t sample_lds_bytes(uint32_t n_meas, bool hist) {
-  return (size_t)sample_tab_groups(n_meas) * 256 * 8 + ((hist && n_meas <= kLdsHistBits) ? (size_t(4) << n_meas) : 0);
+inline size_t sample_lds_bytes(uint32_t n_meas, bool hist, bool sliced = false) {
+  const size_t tab = (size_t)sample_tab_groups(n_meas) * 256 * 8;
+  if (!hist) return tab;
+  if (sliced) return tab + (size_t(4) << kLdsHistBits);
+  return tab + (n_meas <= kLdsHistBits ? (size_t(4) << n_meas) : 0);
 }
+constexpr size_t kSampleLdsMax = 8 * 256 * 8 + (size_t(4) << kLdsHistBits);
 
 // One non-Clifford fragment in a batched state-vector launch: descriptor
 // descs[desc], tables in dist, wg0 = its first workgroup.

@@ -47,7 +47,8 @@ constexpr int kSampleBlock = 256;
 __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
                             uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
                             uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
-                            uint64_t *s_dyn, uint64_t *s_model) {
+                            uint64_t *s_dyn, uint64_t *s_model, uint32_t slice = 0, uint32_t nslice = 1,
+                            double *__restrict__ dist = nullptr) {
   const uint32_t mw = model_words(n_meas);
   const uint64_t *md = models + v * mw;
   const uint32_t groups = sample_tab_groups(n_meas);
@@ -68,9 +69,14 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
     s_tab[e] = t;
   }
   const uint32_t bins = 1u << n_meas;
-  const bool lds_hist = partial != nullptr && n_meas <= kLdsHistBits;
+  // sliced (nslice > 1): this workgroup counts the outcomes whose top bits
+  // equal `slice` into an LDS histogram of 2^kLdsHistBits bins
+  const bool sliced = nslice > 1;
+  // dist (one shot block): the workgroup writes the table itself, count / shots
+  const bool lds_hist = (partial != nullptr || dist != nullptr) && (n_meas <= kLdsHistBits || sliced);
+  const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
   if (lds_hist)
-    for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) s_hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) s_hist[i] = 0;
   __syncthreads();
   const uint64_t vid = vid0 + v;
   const bool wide = n_meas > 32;
@@ -78,7 +84,7 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   // With few random bits the shots of a wave land on few bins: lanes with
   // equal outcomes then add their count once (one atomic per distinct
   // outcome in the wave instead of up to 64 on one address).
-  const bool combine = partial != nullptr && __popcll(rmask) <= 6;
+  const bool combine = (lds_hist || partial != nullptr) && __popcll(rmask) <= 6;
   const uint32_t lane = threadIdx.x & 63u;
   uint32_t *hist = lds_hist ? s_hist : (partial ? partial + v * (uint64_t)bins : nullptr);
   for (uint32_t q = 0; q < qpt; ++q) {
@@ -90,11 +96,16 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint64_t s = quad * 4 + r;
-      const bool valid = quad < nquads && s < shots;
+      bool valid = quad < nquads && s < shots;
       if (!combine && !valid) break;
       uint64_t x = x0;
       for (uint32_t g = 0; g < groups; ++g) x ^= s_tab[(g << 8) | (uint32_t)((u[r] >> (8 * g)) & 255u)];
       if (records && valid) records[v * shots + s] = x;
+      if (sliced) {
+        if ((uint32_t)(x >> kLdsHistBits) != slice) valid = false;
+        x &= (1u << kLdsHistBits) - 1u;
+        if (!combine && !valid) continue;
+      }
       if (combine) {
         // every lane of the wave is here (no early exit on this path)
         uint64_t todo = __ballot(valid);
@@ -112,8 +123,13 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   }
   if (lds_hist) {
     __syncthreads();
-    uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins;
-    for (uint32_t i = threadIdx.x; i < bins; i += kSampleBlock) dst[i] = s_hist[i];
+    if (dist) {
+      double *dd = dist + v * (uint64_t)bins + (uint64_t)slice * lbins;
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)s_hist[i] / (double)shots;
+    } else {
+      uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins + (uint64_t)slice * lbins;
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = s_hist[i];
+    }
   }
 }
 
@@ -127,9 +143,9 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
               s_model);
 }
 
-// Many fragments' sampling in one launch: unit g runs block
-// (g - wg0) mod nblk of variant (g - wg0) / nblk of the job holding g, and
-// a workgroup takes `per_wg` consecutive units in turn.
+// Many fragments' sampling in one launch: unit g of the job holding it is
+// ((variant x nblk + block) x nslice + slice) = g - wg0, and a workgroup
+// takes `per_wg` consecutive units in turn.
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,
                                                                       uint32_t n_jobs, uint64_t total,
                                                                       uint32_t per_wg) {
@@ -143,8 +159,11 @@ __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const Sample
     if (g > g0) __syncthreads();  // the previous unit's tables and histogram are consumed
     const SampleJob &J = jobs[j];
     const uint64_t local = g - J.wg0;
-    sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / J.nblk,
-                (uint32_t)(local % J.nblk), J.nblk, s_dyn, s_model);
+    const uint32_t ns = J.nslice > 1 ? J.nslice : 1u;
+    const uint64_t per_v = (uint64_t)J.nblk * ns, rem = local % per_v;
+    sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / per_v,
+                (uint32_t)(rem / ns), J.nblk, s_dyn, s_model, (uint32_t)(rem % ns), ns,
+                J.partial ? nullptr : J.dist);
   }
 }
 
@@ -167,7 +186,7 @@ __global__ __launch_bounds__(256) void hist_reduce_batch_kernel(const SampleJob 
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const SampleJob &J) { return J.rb0; });
   const SampleJob &J = jobs[j];
   const uint32_t bins = 1u << J.n_meas;
-  const uint32_t nblk = J.n_meas <= kLdsHistBits ? J.nblk : 1u;
+  const uint32_t nblk = (J.n_meas <= kLdsHistBits || J.nslice > 1) ? J.nblk : 1u;
   const uint64_t n_e = J.nv * bins;
   const uint64_t e0 = (uint64_t)(blockIdx.x - J.rb0) * kReduceChunk;
   const uint64_t e1 = e0 + kReduceChunk < n_e ? e0 + kReduceChunk : n_e;
@@ -360,7 +379,7 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
 hipError_t launch_sample_batch(const SampleJob *jobs, uint32_t n_jobs, uint64_t total_units, size_t lds,
                                hipStream_t s) {
   if (n_jobs == 0 || total_units == 0) return hipSuccess;
-  if (lds > sample_lds_bytes(kLdsHistBits, true)) return hipErrorInvalidValue;
+  if (lds > kSampleLdsMax) return hipErrorInvalidValue;
   // about 8192 workgroups, at most 8 units each
   const uint32_t per_wg = (uint32_t)std::min<uint64_t>(8, std::max<uint64_t>(1, total_units / 8192));
   const uint64_t wgs = (total_units + per_wg - 1) / per_wg;
