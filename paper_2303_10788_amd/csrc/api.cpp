@@ -1892,8 +1892,10 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   GemmArgs *d_gargs = gargs.empty() ? nullptr : (GemmArgs *)upload(c, gargs.data(), gargs.size() * sizeof(GemmArgs));
   if ((!plain.empty() && !d_plain) || (!gargs.empty() && !d_gargs)) return fail(c, CCUT_E_OOM, "device allocation failed");
   std::vector<RcJob> rjobs;
-  std::vector<GemmJob> gjobs[2];  // MFMA tiles, skinny
-  uint64_t rwg = 0, gwg[2] = {0, 0}, grwg[2] = {0, 0};
+  // launch classes: 0 the MFMA tiles, 1 + log2(M) the skinny kernel for M rows
+  constexpr int kGemmClasses = 7;
+  std::vector<GemmJob> gjobs[kGemmClasses];
+  uint64_t rwg = 0, gwg[kGemmClasses] = {}, grwg[kGemmClasses] = {};
   for (size_t i = 0, g = 0; i < np; ++i) {
     const uint32_t nq = (uint32_t)b->qubits[i].size();
     if (kind[i] == 0) {
@@ -1906,19 +1908,24 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       rjobs.push_back(J);
     } else if (kind[i] == 2) {
       const GemmArgs &h = gargs[g];
-      const bool sk = contraction_skinny(h, fp32);
+      const bool skinny = contraction_skinny(h, fp32);
+      int sk = 0;
+      if (skinny)
+        while ((1u << (sk)) < h.M) ++sk;
+      if (skinny) ++sk;  // class 1 + log2(M)
       GemmJob J{};
       J.args = d_gargs + g;
-      J.splits = contraction_splits(h, sk);
-      J.tiles = gemm_tiles(h, sk);
-      J.k_per_split = gemm_k_per_split(h, J.splits, sk);
-      J.partial = aget<double>(c, (size_t)J.splits * h.M * h.N);
-      if (!J.partial) return fail(c, CCUT_E_OOM, "device allocation failed");
+      J.splits = contraction_splits(h, skinny);
+      J.tiles = gemm_tiles(h, skinny);
+      J.k_per_split = gemm_k_per_split(h, J.splits, skinny);
+      const bool direct = skinny && J.splits == 1;  // the skinny kernel writes the outputs itself
+      J.partial = direct ? nullptr : aget<double>(c, (size_t)J.splits * h.M * h.N);
+      if (!direct && !J.partial) return fail(c, CCUT_E_OOM, "device allocation failed");
       J.out = b->res[i];
       J.wg0 = gwg[sk];
       J.rwg0 = grwg[sk];
       gwg[sk] += (uint64_t)J.tiles * J.splits;
-      grwg[sk] += ((uint64_t)h.M * h.N + 255) / 256;
+      if (!direct) grwg[sk] += ((uint64_t)h.M * h.N + 255) / 256;
       gjobs[sk].push_back(J);
       ++g;
     }
@@ -1929,11 +1936,12 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (!d_r) return fail(c, CCUT_E_OOM, "device allocation failed");
     HIP_TRY(c, launch_recombine_batch(d_r, (uint32_t)rjobs.size(), rwg, c->cur));
   }
-  for (int sk = 0; sk < 2; ++sk) {
+  for (int sk = 0; sk < kGemmClasses; ++sk) {
     if (gjobs[sk].empty()) continue;
     GemmJob *d_g = (GemmJob *)upload(c, gjobs[sk].data(), gjobs[sk].size() * sizeof(GemmJob));
     if (!d_g) return fail(c, CCUT_E_OOM, "device allocation failed");
-    HIP_TRY(c, launch_gemm_batch(d_g, (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32, sk == 1, c->cur));
+    HIP_TRY(c, launch_gemm_batch(d_g, (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32, sk ? 1u << (sk - 1) : 0u,
+                                 c->cur));
   }
   for (size_t i = 0; i < np; ++i)
     if (kind[i] == 1)

@@ -428,8 +428,10 @@ struct GemmJob {
   uint64_t wg0, rwg0, k_per_split;
   uint32_t tiles, splits;
 };
+// skinny_rows: 0 for the MFMA tiles, else the row count M (1, 2, 4, ..., 32)
+// every job of the list shares
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             bool skinny, hipStream_t s);
+                             uint32_t skinny_rows, hipStream_t s);
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
                                  uint32_t splits, double *out, hipStream_t s,
                                  bool skinny = false);

@@ -183,24 +183,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob 
 // thread with all M rows in registers; the row-side values of a K chunk are
 // staged in LDS.  partial[split][m][n] = sum over the split's terms, in
 // ascending order, of a(m, P) * b(n, P) (each product rounded, then added).
-constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
-template <uint32_t MC>
-__device__ inline void skinny_rows(const double (*__restrict__ As)[SK_M], const uint64_t *__restrict__ s_boff,
-                                   const double *__restrict__ Tn, uint32_t kn, bool square, double *acc) {
-#pragma unroll 4
-  for (uint32_t kk = 0; kk < kn; ++kk) {
-    double b = Tn[s_boff[kk]];
-    if (square) b *= b;
-#pragma unroll
-    for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
-  }
-}
+__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n);
 
+constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
+// One instantiation per row count MC (1, 2, ..., 32): the accumulators of
+// one kernel stay in registers only when the kernel holds exactly its own.
+template <uint32_t MC>
 __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
-                                   uint32_t tile, uint32_t split) {
-  __shared__ double As[SK_KC][SK_M];
+                                   uint32_t tile, uint32_t split, double *__restrict__ out) {
+  __shared__ double As[SK_KC][MC];
   __shared__ uint64_t s_boff[SK_KC];
-  const uint32_t M = G->M, N = G->N, tid = threadIdx.x;
+  const uint32_t N = G->N, tid = threadIdx.x;
   const uint64_t K = G->K;
   const uint32_t n = tile * SK_N + tid;
   const uint64_t k0 = (uint64_t)split * k_per_split;
@@ -209,9 +202,10 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
   const uint32_t rf = G->R.frag[0];
   const double *Tn = G->f[rf].T + n;
   const uint64_t rows = G->f[rf].rows;
-  double acc[SK_M];
+  const bool square = G->square != 0;
+  double acc[MC];
 #pragma unroll
-  for (uint32_t m = 0; m < SK_M; ++m) acc[m] = 0.0;
+  for (uint32_t m = 0; m < MC; ++m) acc[m] = 0.0;
   for (uint64_t kb = k0; kb < k1; kb += SK_KC) {
     const uint32_t kn = (uint32_t)std::min<uint64_t>(SK_KC, k1 - kb);
     __syncthreads();  // the previous chunk is consumed
@@ -219,53 +213,57 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
       const uint64_t j = kb + tid;
       s_boff[tid] = frag_p(G, rf, G->terms ? G->terms[j] : j) * rows;
     }
-    for (uint32_t e = tid; e < kn * M; e += SK_N) {
-      const uint32_t kk = e / M, m = e % M;
+    for (uint32_t e = tid; e < kn * MC; e += SK_N) {
+      const uint32_t kk = e / MC, m = e % MC;
       const uint64_t j = kb + kk;
       double a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
       if (G->tscale) a *= G->tscale[j];
-      if (G->square) a *= a;
+      if (square) a *= a;
       As[kk][m] = a;
     }
     __syncthreads();
     if (n >= N) continue;
-    const bool sq = G->square != 0;
-    switch (M) {
-      case 1: skinny_rows<1>(As, s_boff, Tn, kn, sq, acc); break;
-      case 2: skinny_rows<2>(As, s_boff, Tn, kn, sq, acc); break;
-      case 4: skinny_rows<4>(As, s_boff, Tn, kn, sq, acc); break;
-      case 8: skinny_rows<8>(As, s_boff, Tn, kn, sq, acc); break;
-      case 16: skinny_rows<16>(As, s_boff, Tn, kn, sq, acc); break;
-      default: skinny_rows<32>(As, s_boff, Tn, kn, sq, acc); break;
+    // several column loads in flight per thread (fewer for many rows, whose
+    // row values would crowd the registers): the kernel streams the column
+    // tensor once
+    constexpr uint32_t kUnroll = MC <= 8 ? 8 : 2;
+#pragma unroll kUnroll
+    for (uint32_t kk = 0; kk < kn; ++kk) {
+      double b = Tn[s_boff[kk]];
+      if (square) b *= b;
+#pragma unroll
+      for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
     }
   }
   if (n >= N) return;
-  double *dst = partial + (uint64_t)split * M * N;
+  if (out) {
 #pragma unroll
-  for (uint32_t m = 0; m < SK_M; ++m)
-    if (m < M) dst[(uint64_t)m * N + n] = acc[m];
+    for (uint32_t m = 0; m < MC; ++m) out[out_index(G, m, n)] = ldexp(0.0 + acc[m], -(int)G->k);
+    return;
+  }
+  double *dst = partial + (uint64_t)split * MC * N;
+#pragma unroll
+  for (uint32_t m = 0; m < MC; ++m) dst[(uint64_t)m * N + n] = acc[m];
 }
 
+template <uint32_t MC>
 __global__ __launch_bounds__(SK_N) void skinny_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
-                                                      double *__restrict__ partial) {
-  skinny_body(G, k_per_split, partial, blockIdx.x, blockIdx.y);
+                                                      double *__restrict__ partial, double *__restrict__ out) {
+  skinny_body<MC>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
 }
 
+// Jobs of one row count MC.
+template <uint32_t MC>
 __global__ __launch_bounds__(SK_N) void skinny_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];
   const uint64_t local = blockIdx.x - J.wg0;
-  skinny_body(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles));
+  skinny_body<MC>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
+                  J.splits == 1 ? J.out : nullptr);
 }
 
 // out[b(m, n)] = 2^-k sum_split partial[split][m][n], splits in order
-__device__ inline void gemm_reduce_body(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
-                                        uint32_t splits, double *__restrict__ out, uint64_t i) {
-  const uint64_t MN = (uint64_t)G->M * G->N;
-  if (i >= MN) return;
-  double s = 0.0;
-  for (uint32_t sp = 0; sp < splits; ++sp) s += partial[sp * MN + i];
-  const uint32_t m = (uint32_t)(i / G->N), n = (uint32_t)(i % G->N);
+__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n) {
   uint64_t b = 0;
   for (uint32_t t = 0; t < G->L.n; ++t) {
     const RecombFrag &F = G->f[G->L.frag[t]];
@@ -277,7 +275,16 @@ __device__ inline void gemm_reduce_body(const GemmArgs *__restrict__ G, const do
     const uint32_t r = (n >> G->R.shift[t]) & ((1u << G->R.bits[t]) - 1u);
     for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
   }
-  out[b] = ldexp(s, -(int)G->k);
+  return b;
+}
+
+__device__ inline void gemm_reduce_body(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
+                                        uint32_t splits, double *__restrict__ out, uint64_t i) {
+  const uint64_t MN = (uint64_t)G->M * G->N;
+  if (i >= MN) return;
+  double s = 0.0;
+  for (uint32_t sp = 0; sp < splits; ++sp) s += partial[sp * MN + i];
+  out[out_index(G, (uint32_t)(i / G->N), (uint32_t)(i % G->N))] = ldexp(s, -(int)G->k);
 }
 
 __global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
@@ -313,9 +320,11 @@ uint32_t gemm_tiles(const GemmArgs &h, bool skinny) {
 
 uint32_t contraction_splits(const GemmArgs &h, bool skinny) {
   if (!skinny) return gemm_splits(h);
+  // about 256 workgroups: a column tile per thread block carries enough work
+  // that more splits only add partial traffic
   const uint64_t tiles = gemm_tiles(h, true);
   const uint64_t kchunks = (h.K + SK_KC - 1) / SK_KC;
-  uint64_t s = std::max<uint64_t>(1, 1024 / std::max<uint64_t>(tiles, 1));
+  uint64_t s = std::max<uint64_t>(1, 256 / std::max<uint64_t>(tiles, 1));
   s = std::min<uint64_t>(s, kchunks);
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
 }
@@ -327,17 +336,26 @@ uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny) {
 }
 
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             bool skinny, hipStream_t s) {
+                             uint32_t skinny_rows, hipStream_t s) {
   if (n_jobs == 0 || total_wg == 0) return hipSuccess;
   if (total_wg > 0x7FFFFFFFull || total_rwg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  if (skinny)
-    hipLaunchKernelGGL(skinny_batch_kernel, dim3((unsigned)total_wg), dim3(SK_N), 0, s, d_jobs, n_jobs);
-  else if (fp32)
+  const dim3 g((unsigned)total_wg), b(SK_N);
+  if (skinny_rows) {
+    switch (skinny_rows) {
+      case 1: hipLaunchKernelGGL(skinny_batch_kernel<1>, g, b, 0, s, d_jobs, n_jobs); break;
+      case 2: hipLaunchKernelGGL(skinny_batch_kernel<2>, g, b, 0, s, d_jobs, n_jobs); break;
+      case 4: hipLaunchKernelGGL(skinny_batch_kernel<4>, g, b, 0, s, d_jobs, n_jobs); break;
+      case 8: hipLaunchKernelGGL(skinny_batch_kernel<8>, g, b, 0, s, d_jobs, n_jobs); break;
+      case 16: hipLaunchKernelGGL(skinny_batch_kernel<16>, g, b, 0, s, d_jobs, n_jobs); break;
+      case 32: hipLaunchKernelGGL(skinny_batch_kernel<32>, g, b, 0, s, d_jobs, n_jobs); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (fp32)
     hipLaunchKernelGGL((gemm_batch_kernel<true>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
   else
     hipLaunchKernelGGL((gemm_batch_kernel<false>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || total_rwg == 0) return e;  // (one-split skinny jobs wrote their outputs)
   hipLaunchKernelGGL(gemm_reduce_batch_kernel, dim3((unsigned)total_rwg), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
 }
@@ -346,9 +364,20 @@ hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool
                                  uint32_t splits, double *out, hipStream_t s, bool skinny) {
   const uint32_t tiles = gemm_tiles(h, skinny);
   const uint64_t k_per_split = gemm_k_per_split(h, splits, skinny);
-  if (skinny)
-    hipLaunchKernelGGL(skinny_kernel, dim3(tiles, splits), dim3(SK_N), 0, s, d_args, k_per_split, partial);
-  else if (fp32)
+  if (skinny) {
+    const dim3 g(tiles, splits), b(SK_N);
+    double *o = splits == 1 ? out : nullptr;
+    switch (h.M) {
+      case 1: hipLaunchKernelGGL(skinny_kernel<1>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      case 2: hipLaunchKernelGGL(skinny_kernel<2>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      case 4: hipLaunchKernelGGL(skinny_kernel<4>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      case 8: hipLaunchKernelGGL(skinny_kernel<8>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      case 16: hipLaunchKernelGGL(skinny_kernel<16>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      case 32: hipLaunchKernelGGL(skinny_kernel<32>, g, b, 0, s, d_args, k_per_split, partial, o); break;
+      default: return hipErrorInvalidValue;
+    }
+    if (splits == 1) return hipGetLastError();
+  } else if (fp32)
     hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
                        partial);
   else
