@@ -135,7 +135,7 @@ def main():
     if args.traffic:
         return traffic_from_counters(args)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batching":
         return bench_batching(args)
