@@ -143,7 +143,7 @@ __global__ void transform_all_kernel(const TransformAll A, const double *__restr
 // slots of bases X, Y, Z and Z in the outcome-1 slot of basis X.
 // A workgroup takes `per_wg` consecutive tiles of the launch in turn (fewer,
 // longer workgroups: the dispatcher, not the tiles, limits short ones).
-constexpr uint32_t kTileThreads = 256;
+constexpr uint32_t kTileThreads = 512;
 __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep);
 
 __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const TileJob *__restrict__ jobs,
