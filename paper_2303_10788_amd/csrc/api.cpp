@@ -112,29 +112,33 @@ struct ccut_ctx {
   PinSlot pin[kPinSlots];
   int pin_cur = -1;
   // Call graphs: a device-output call repeated with identical arguments is
-  // captured once and then replayed.  While a capture is open, uploads are
-  // staged in the captured call's own pinned block (its copy nodes read it on
-  // every replay).
+  // captured once and then replayed.  While a capture is open, uploads go to
+  // the captured call's own device block, filled once from its pinned block
+  // before the first launch; the graph itself holds kernels only.
   bool call_graphs = true;
   hipStream_t cap_stream = nullptr;  // capture stream of call graphs
   struct CallGraph *capturing = nullptr;
   size_t call_upload_bytes = 0;  // staged bytes of the current call
 };
 
-// One captured call: its argument key, the executable graph and the pinned
-// block its host-to-device copy nodes read.
+// One captured call: its argument key, the executable graph, and the
+// device block holding the call's uploads (with the pinned block they are
+// copied from once).
 struct CallGraph {
   std::vector<uint8_t> key;
   hipGraphExec_t exec = nullptr;
   char *pin = nullptr;
+  char *dev = nullptr;
   size_t pin_cap = 0, pin_used = 0, upload_bytes = 0;
   bool no_graph = false;  // capture failed once: stay eager
   uint64_t last_use = 0;
   void release() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (pin) (void)hipHostFree(pin);
+    if (dev) (void)hipFree(dev);
     exec = nullptr;
     pin = nullptr;
+    dev = nullptr;
   }
 };
 
@@ -151,7 +155,7 @@ struct ccut_plan {
   uint64_t graph_tick = 0;
   static constexpr size_t kMaxCallGraphs = 8;
   ~ccut_plan() {
-    // a replay may still be reading the graphs' pinned blocks
+    // a replay may still be reading the graphs' upload blocks
     if (!graphs.empty() && ctx && ctx->device >= 0) (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : graphs) g.release();
     for (auto p : d_ops)
@@ -343,19 +347,21 @@ hipError_t pin_begin(ccut_ctx *c) {
 // the call's pinned slot.  A null source (an empty host vector) gets the
 // allocation without a copy.
 void *upload(ccut_ctx *c, const void *src, size_t bytes) {
+  const size_t need = (bytes + 255) & ~size_t(255);
+  if (CallGraph *g = c->capturing; g && src && bytes) {
+    // kept for good in the captured call's device block; its one copy is
+    // enqueued after the capture ends, ahead of the first launch
+    if (g->pin_used + need > g->pin_cap) return nullptr;
+    std::memcpy(g->pin + g->pin_used, src, bytes);
+    void *d = g->dev + g->pin_used;
+    g->pin_used += need;
+    c->call_upload_bytes += need;
+    return d;
+  }
   void *d = c->arena.get(bytes);
   if (!d) return nullptr;
   if (c->replay_uploads || !src || bytes == 0) return d;  // replay: the bytes are already there
-  const size_t need = (bytes + 255) & ~size_t(255);
   c->call_upload_bytes += need;
-  if (CallGraph *g = c->capturing) {  // staged for good in the captured call's block
-    if (g->pin_used + need > g->pin_cap) return nullptr;
-    char *stage = g->pin + g->pin_used;
-    g->pin_used += need;
-    std::memcpy(stage, src, bytes);
-    if (hipMemcpyAsync(d, stage, bytes, hipMemcpyHostToDevice, c->cur) != hipSuccess) return nullptr;
-    return d;
-  }
   if (c->pin_cur < 0 && pin_begin(c) != hipSuccess) return nullptr;
   ccut_ctx::PinSlot &sl = c->pin[c->pin_cur];
   while (sl.chunk < sl.chunks.size() && sl.used + need > sl.chunks[sl.chunk].second) {
@@ -1172,6 +1178,7 @@ ccut_status graph_call(ccut_plan *p, std::vector<uint8_t> &&key, int on_device, 
     if (p->graphs.size() >= ccut_plan::kMaxCallGraphs) {
       auto lru = std::min_element(p->graphs.begin(), p->graphs.end(),
                                   [](const CallGraph &a, const CallGraph &b) { return a.last_use < b.last_use; });
+      (void)hipStreamSynchronize(c->stream);  // a replay of it may still be running
       lru->release();
       p->graphs.erase(lru);
     }
@@ -1187,6 +1194,7 @@ ccut_status graph_call(ccut_plan *p, std::vector<uint8_t> &&key, int on_device, 
   g->pin_cap = std::max<size_t>(g->upload_bytes, 256);
   g->pin_used = 0;
   HIP_TRY(c, hipHostMalloc((void **)&g->pin, g->pin_cap, hipHostMallocDefault));
+  HIP_TRY(c, hipMalloc((void **)&g->dev, g->pin_cap));
   // captured on a private stream (the caller's may be the legacy default
   // stream, which cannot be captured) and launched on the caller's
   if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1211,6 +1219,7 @@ ccut_status graph_call(ccut_plan *p, std::vector<uint8_t> &&key, int on_device, 
     (void)hipGetLastError();
     return impl();
   }
+  if (g->pin_used) HIP_TRY(c, hipMemcpyAsync(g->dev, g->pin, g->pin_used, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipGraphLaunch(g->exec, c->stream));
   return CCUT_OK;
 }
