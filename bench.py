@@ -34,8 +34,9 @@ PHILOX_OPS = 100                        # 10 rounds x (2 mul_lo + 2 mul_hi + 4 x
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 2000 for mid, whose step takes about 0.1 ms; 50 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 200 for mid, 10 otherwise)")
     ap.add_argument("--shots", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -51,7 +52,13 @@ def parse():
                          "graph-captured batch; precision: the 400-qubit, 6-cut workload with FP32-MFMA "
                          "recombination; learned: the 300-qubit, 10-cut workload, learned term proposal against "
                          "exhaustive recombination; scan: the paper's workload families with automatic cuts")
-    return ap.parse_args()
+    args = ap.parse_args()
+    short = args.workload == "mid"
+    if args.steps is None:
+        args.steps = 2000 if short else 50
+    if args.warmup is None:
+        args.warmup = 200 if short else 10
+    return args
 
 
 def cpu_baseline(w, target_s: float):
