@@ -287,7 +287,11 @@ typedef struct ccut_batch ccut_batch;
 ccut_status ccut_batch_create(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,
                               const uint32_t *const *qubits, const uint32_t *nq, int use_graph, ccut_batch **out);
 /* Evaluate the batch again (graph replay when captured); outs[i] receives
- * plan i's 2^nq[i] marginal, on the device if outs_on_device. */
+ * plan i's 2^nq[i] marginal, on the device if outs_on_device.  Host
+ * outputs: returns once they are written.  Device outputs: one copy launch
+ * writes them all, and the context's stream is ordered after it; the call
+ * returns without waiting (work queued later on that stream sees the
+ * results).  Runs of one batch are ordered among themselves. */
 ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_device);
 /* Work items of the persistent launch, the chosen workgroup size, grid,
  * register-tableau use, whether a graph was captured, and the best tuned

@@ -1527,7 +1527,16 @@ struct ccut_batch {
   std::vector<FragDev> sv_descs;
   uint32_t max_m = 0, block = 64, grid = 0, use_reg = 1;
   double tuned_ms = 0.0;
+  // device outputs: the copy list of the last run (pinned and on the
+  // device), reused while the caller passes the same output addresses, and
+  // the event the caller's stream waits on
+  std::vector<double *> last_outs;
+  OutCopy *h_copy = nullptr, *d_copy = nullptr;
+  hipEvent_t done_ev = nullptr;
   ~ccut_batch() {
+    if (h_copy) (void)hipHostFree(h_copy);
+    if (d_copy) (void)hipFree(d_copy);
+    if (done_ev) (void)hipEventDestroy(done_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto ps : pool) (void)hipStreamDestroy(ps);
@@ -1577,8 +1586,9 @@ ccut_status batch_tableau(ccut_batch *b, FragDev *d_descs, BatchItem *d_items, u
   return CCUT_OK;
 }
 
-// The shared base tableau of every Clifford descriptor: one launch per
-// row-width class, one row per lane.
+// The shared base tableau of every Clifford descriptor: one launch, one
+// workgroup per descriptor, the widest row classes first (they take
+// longest), one row per lane.
 ccut_status batch_bases(ccut_batch *b, FragDev *d_descs, uint64_t **d_bases_out) {
   ccut_ctx *c = b->ctx;
   *d_bases_out = nullptr;
@@ -1586,14 +1596,15 @@ ccut_status batch_bases(ccut_batch *b, FragDev *d_descs, uint64_t **d_bases_out)
   uint64_t *d_bases = aget<uint64_t>(c, std::max<uint64_t>(b->base_words_total, 1));
   uint64_t *d_off = (uint64_t *)upload(c, b->base_off.data(), b->base_off.size() * 8);
   if (!d_bases || !d_off) return fail(c, CCUT_E_OOM, "device allocation failed");
-  static const uint32_t kW[4] = {1, 2, 4, 8};
-  for (int k = 0; k < 4; ++k) {
-    if (b->wlist[k].empty()) continue;
-    uint32_t *d_list = (uint32_t *)upload(c, b->wlist[k].data(), b->wlist[k].size() * 4);
-    if (!d_list) return fail(c, CCUT_E_OOM, "device allocation failed");
-    HIP_TRY(c, launch_base_batch(d_descs, kW[k], d_list, (uint32_t)b->wlist[k].size(), b->wrows[k], d_off, d_bases,
-                                 c->cur));
+  std::vector<uint32_t> list;
+  uint32_t max_rows = 0;
+  for (int k = 3; k >= 0; --k) {  // class k: 2^k words per row half
+    for (uint32_t d : b->wlist[k]) list.push_back(d | (uint32_t)k << 28);
+    max_rows = std::max(max_rows, b->wrows[k]);
   }
+  uint32_t *d_list = (uint32_t *)upload(c, list.data(), list.size() * 4);
+  if (!d_list) return fail(c, CCUT_E_OOM, "device allocation failed");
+  HIP_TRY(c, launch_base_batch(d_descs, d_list, (uint32_t)list.size(), max_rows, d_off, d_bases, c->cur));
   *d_bases_out = d_bases;
   return CCUT_OK;
 }
@@ -1631,11 +1642,23 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
       for (size_t k = 0; k < n_sv_streams; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
     }
-    uint32_t ci = 0;  // shape classes so far
-    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+    // one launch per shape class; the classes go to the streams longest
+    // first, each to the stream with the least work so far (work: amplitudes
+    // times program length, summed over workgroups)
+    struct SvClass {
+      uint32_t m;
       std::vector<SvJob> jobs;
       uint64_t wg = 0;
       size_t lds = 0;
+      double cost = 0.0;
+    };
+    std::vector<SvClass> classes;
+    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+      SvClass C;
+      C.m = m;
+      std::vector<SvJob> &jobs = C.jobs;
+      uint64_t &wg = C.wg;
+      size_t &lds = C.lds;
       for (const auto &ref : b->nc) {
         const FragDev &h = b->sv_descs[ref.desc];
         if (h.m != m) continue;
@@ -1653,19 +1676,25 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         pre_dist[ref.plan][ref.frag] = J.dist;
         wg += n_wg;
         lds = std::max(lds, l);
+        C.cost += (double)n_wg * (double)(1u << m) * (double)h.n_ops;
         jobs.push_back(J);
       }
-      if (jobs.empty()) continue;
+      if (!jobs.empty()) classes.push_back(std::move(C));
+    }
+    std::stable_sort(classes.begin(), classes.end(),
+                     [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
+    std::vector<double> load(n_sv_streams, 0.0);
+    for (const SvClass &C : classes) {
       if (n_sv_streams) {
-        const size_t k = ci % n_sv_streams;
+        const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += C.cost;
         c->cur = b->pool[k];
         sv_used[k] = 1;
       }
-      ++ci;
-      SvJob *d_jobs = (SvJob *)upload(c, jobs.data(), jobs.size() * sizeof(SvJob));
+      SvJob *d_jobs = (SvJob *)upload(c, C.jobs.data(), C.jobs.size() * sizeof(SvJob));
       if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
       KTimer tm(c, CCUT_K_SV);
-      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)jobs.size(), wg, m, lds, c->cur));
+      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs.size(), C.wg, C.m, C.lds, c->cur));
     }
     c->cur = b->stream;
     for (size_t k = 0; k < n_sv_streams; ++k)
@@ -1939,19 +1968,43 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       ++g;
     }
   }
-  KTimer t(c, CCUT_K_RECOMBINE);
+  // every job list goes up on the batch stream first; then the launch
+  // classes (they write disjoint outputs and partial sums) spread over the
+  // batch stream and up to three pool streams, which are idle by now, so the
+  // small skinny classes run beside the large plain and MFMA launches
+  RcJob *d_r = nullptr;
+  if (!rjobs.empty() && !(d_r = (RcJob *)upload(c, rjobs.data(), rjobs.size() * sizeof(RcJob))))
+    return fail(c, CCUT_E_OOM, "device allocation failed");
+  GemmJob *d_g[kGemmClasses] = {};
+  for (int sk = 0; sk < kGemmClasses; ++sk)
+    if (!gjobs[sk].empty() &&
+        !(d_g[sk] = (GemmJob *)upload(c, gjobs[sk].data(), gjobs[sk].size() * sizeof(GemmJob))))
+      return fail(c, CCUT_E_OOM, "device allocation failed");
+  const size_t n_side = std::min<size_t>(P, 3);
+  if (n_side) {
+    HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+    for (size_t k = 0; k < n_side; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
+  }
+  size_t next = 0;  // launch classes in order, round-robin over the streams
+  auto pick = [&]() { c->cur = (next % (n_side + 1)) ? b->pool[next % (n_side + 1) - 1] : b->stream; ++next; };
   if (!rjobs.empty()) {
-    RcJob *d_r = (RcJob *)upload(c, rjobs.data(), rjobs.size() * sizeof(RcJob));
-    if (!d_r) return fail(c, CCUT_E_OOM, "device allocation failed");
+    pick();
+    KTimer t(c, CCUT_K_RECOMBINE);
     HIP_TRY(c, launch_recombine_batch(d_r, (uint32_t)rjobs.size(), rwg, c->cur));
   }
   for (int sk = 0; sk < kGemmClasses; ++sk) {
     if (gjobs[sk].empty()) continue;
-    GemmJob *d_g = (GemmJob *)upload(c, gjobs[sk].data(), gjobs[sk].size() * sizeof(GemmJob));
-    if (!d_g) return fail(c, CCUT_E_OOM, "device allocation failed");
-    HIP_TRY(c, launch_gemm_batch(d_g, (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32, sk ? 1u << (sk - 1) : 0u,
-                                 c->cur));
+    pick();
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32,
+                                 sk ? 1u << (sk - 1) : 0u, c->cur));
   }
+  c->cur = b->stream;
+  for (size_t k = 0; k < n_side; ++k) {
+    HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
+    HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
+  }
+  KTimer t(c, CCUT_K_RECOMBINE);
   for (size_t i = 0; i < np; ++i)
     if (kind[i] == 1)
       HIP_TRY(c, launch_recombine_fp64(d_plain + plain_of[i], rargs[i].n_frags, (uint32_t)b->qubits[i].size(),
@@ -2002,6 +2055,7 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
       if (f.m() > 512) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
       FragDev h = frag_desc(p, f, r, (uint32_t)i);
       const uint32_t di = (uint32_t)b->descs.size();
+      if (di >= (1u << 28)) return fail(c, CCUT_E_UNSUPPORTED, "too many Clifford fragments in one batch");
       b->descs.push_back(h);
       const uint32_t Wb = row_words(f.m());
       const int wk = Wb == 1 ? 0 : Wb == 2 ? 1 : Wb == 4 ? 2 : 3;
@@ -2086,10 +2140,35 @@ ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_devic
     ccut_status st = batch_enqueue(b, false);
     if (st != CCUT_OK) return st;
   }
-  for (size_t i = 0; i < b->plans.size(); ++i)
-    HIP_TRY(c, hipMemcpyAsync(outs[i], b->res[i], sizeof(double) << b->qubits[i].size(),
-                              outs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, b->stream));
-  HIP_TRY(c, hipStreamSynchronize(b->stream));
+  const size_t n = b->plans.size();
+  if (!outs_on_device) {
+    for (size_t i = 0; i < n; ++i)
+      HIP_TRY(c, hipMemcpyAsync(outs[i], b->res[i], sizeof(double) << b->qubits[i].size(), hipMemcpyDeviceToHost,
+                                b->stream));
+    HIP_TRY(c, hipStreamSynchronize(b->stream));
+    return CCUT_OK;
+  }
+  // device outputs: one gather launch, then the caller's stream waits for it
+  // (no host synchronization)
+  if (n == 0) return CCUT_OK;
+  if (!b->d_copy) {
+    HIP_TRY(c, hipHostMalloc((void **)&b->h_copy, n * sizeof(OutCopy), hipHostMallocDefault));
+    HIP_TRY(c, hipMalloc((void **)&b->d_copy, n * sizeof(OutCopy)));
+    HIP_TRY(c, hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming));
+  }
+  uint64_t max_n = 0;
+  for (size_t i = 0; i < n; ++i) max_n = std::max<uint64_t>(max_n, uint64_t(1) << b->qubits[i].size());
+  if (!std::equal(outs, outs + n, b->last_outs.begin(), b->last_outs.end())) {
+    // the previous run's gather may still read both copies of the list
+    HIP_TRY(c, hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < n; ++i) b->h_copy[i] = OutCopy{b->res[i], outs[i], uint64_t(1) << b->qubits[i].size()};
+    HIP_TRY(c, hipMemcpyAsync(b->d_copy, b->h_copy, n * sizeof(OutCopy), hipMemcpyHostToDevice, b->stream));
+    b->last_outs.assign(outs, outs + n);
+  }
+  for (size_t i0 = 0; i0 < n; i0 += 65535)
+    HIP_TRY(c, launch_gather_f64(b->d_copy + i0, (uint32_t)std::min<size_t>(65535, n - i0), max_n, b->stream));
+  HIP_TRY(c, hipEventRecord(b->done_ev, b->stream));
+  HIP_TRY(c, hipStreamWaitEvent(c->stream, b->done_ev, 0));
   return CCUT_OK;
 }
 

@@ -338,8 +338,11 @@ hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, 
 // (x[W], z[W], sign) u64 each.
 hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
                        hipStream_t s);
-hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
-                             uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s);
+// The base tableaux of many Clifford descriptors in one launch, one
+// workgroup each: list entries are descriptor index | log2(row words) << 28;
+// max_rows = the most rows (2m) of any of them (it sizes the LDS).
+hipError_t launch_base_batch(const FragDev *descs, const uint32_t *list, uint32_t n_list, uint32_t max_rows,
+                             const uint64_t *base_off, uint64_t *base, hipStream_t s);
 hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
                              uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
                              uint32_t n_rows, double *tau, hipStream_t s);
@@ -381,6 +384,15 @@ struct SupportArgs {
   uint64_t off[kMaxFrags];
 };
 hipError_t launch_colnz(const double *T, uint32_t rows, uint64_t cols, uint8_t *nz, hipStream_t s);
+
+// One result vector to copy: n doubles from src to dst (device memory).
+struct OutCopy {
+  const double *src;
+  double *dst;
+  uint64_t n;
+};
+// All copies in one launch (at most 65535 of them; max_n = the longest n).
+hipError_t launch_gather_f64(const OutCopy *d_jobs, uint32_t n_jobs, uint64_t max_n, hipStream_t s);
 hipError_t launch_support_terms(const RecombArgs *d_args, const SupportArgs &sa, const uint8_t *nz, uint64_t K,
                                 uint64_t *pos, uint64_t *scratch, uint64_t *terms, hipStream_t s);
 constexpr uint32_t kRcChunkOut = 128;  // outputs per workgroup of the plain recombination

@@ -393,6 +393,28 @@ __global__ void support_scatter_terms_kernel(const uint64_t *__restrict__ pos, u
   if (pos[P] != prev) terms[prev] = P;
 }
 
+// Copies of many result vectors in one launch: workgroup (x, y) moves
+// elements [x * kGatherChunk, (x + 1) * kGatherChunk) of copy y.
+constexpr uint32_t kGatherPer = 4, kGatherChunk = 256 * kGatherPer;
+__global__ __launch_bounds__(256) void gather_f64_kernel(const OutCopy *__restrict__ jobs) {
+  const OutCopy &J = jobs[blockIdx.y];
+  const uint64_t n = J.n, base = (uint64_t)blockIdx.x * kGatherChunk;
+  if (base >= n) return;
+  const double *src = J.src;
+  double *dst = J.dst;
+  double v[kGatherPer];
+#pragma unroll
+  for (uint32_t k = 0; k < kGatherPer; ++k) {
+    const uint64_t i = base + k * 256 + threadIdx.x;
+    v[k] = i < n ? src[i] : 0.0;
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kGatherPer; ++k) {
+    const uint64_t i = base + k * 256 + threadIdx.x;
+    if (i < n) dst[i] = v[k];
+  }
+}
+
 // Many plans' plain recombinations in one launch.
 __global__ __launch_bounds__(kRcChunk) void recombine_batch_kernel(const RcJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const RcJob &J) { return J.wg0; });
@@ -564,6 +586,14 @@ hipError_t launch_colnz(const double *T, uint32_t rows, uint64_t cols, uint8_t *
   if (cols == 0) return hipSuccess;
   if ((cols + 3) / 4 > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(colnz_kernel, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, s, T, rows, cols, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f64(const OutCopy *d_jobs, uint32_t n_jobs, uint64_t max_n, hipStream_t s) {
+  if (n_jobs == 0 || max_n == 0) return hipSuccess;
+  const uint64_t gx = (max_n + kGatherChunk - 1) / kGatherChunk;
+  if (n_jobs > 65535u || gx > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_f64_kernel, dim3((unsigned)gx, n_jobs), dim3(256), 0, s, d_jobs);
   return hipGetLastError();
 }
 

@@ -351,11 +351,14 @@ __global__ __launch_bounds__(64) void rows_sliced_kernel(const FragDev F, uint32
 // Shared tableau passes of many fragments: block y runs fragment list[y]
 // (2m rows, row width W = row_words(m)) into base + base_off[list[y]].
 __global__ __launch_bounds__(64) void rows_sliced_batch_kernel(const FragDev *__restrict__ descs,
-                                                                const uint32_t *__restrict__ list, uint32_t W,
+                                                                const uint32_t *__restrict__ list,
                                                                 const uint64_t *__restrict__ base_off,
                                                                 uint64_t *__restrict__ base) {
   extern __shared__ uint64_t cols[];
-  const uint32_t d = list[blockIdx.x];
+  // list entry: descriptor index in the low 28 bits, log2 of the row width
+  // in words above
+  const uint32_t e = list[blockIdx.x];
+  const uint32_t d = e & 0x0FFFFFFFu, W = 1u << (e >> 28);
   const g_FragDevH &F = ((const g_FragDevH *)descs)[d];
   rows_sliced_body(F, W, nullptr, base + base_off[d], 2 * F.m, cols);
 }
@@ -544,8 +547,8 @@ hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_
   return hipGetLastError();
 }
 
-hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *list, uint32_t n_list,
-                             uint32_t max_rows, const uint64_t *base_off, uint64_t *base, hipStream_t s) {
+hipError_t launch_base_batch(const FragDev *descs, const uint32_t *list, uint32_t n_list, uint32_t max_rows,
+                             const uint64_t *base_off, uint64_t *base, hipStream_t s) {
   if (n_list == 0) return hipSuccess;
   if (max_rows > kSlicedRows) return hipErrorInvalidValue;
   const size_t lds = rows_sliced_lds(max_rows / 2, max_rows);
@@ -553,7 +556,7 @@ hipError_t launch_base_batch(const FragDev *descs, uint32_t W, const uint32_t *l
   hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_batch_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rows_sliced_batch_kernel, dim3(n_list), dim3(64), lds, s, descs, list, W, base_off, base);
+  hipLaunchKernelGGL(rows_sliced_batch_kernel, dim3(n_list), dim3(64), lds, s, descs, list, base_off, base);
   return hipGetLastError();
 }
 
