@@ -175,6 +175,12 @@ __device__ inline const T *uniform_ptr(const T *p) {
   return (const T *)(((uint64_t)hi << 32) | lo);
 }
 
+// One state buffer in LDS instead of two: when no basis-combination copy
+// needs the second one and the state is large enough that halving the LDS
+// lets more workgroups share a compute unit.  Swaps then take a second
+// barrier (their writes must wait for the previous swap's reads).
+__host__ __device__ inline bool sv_single_buffer(uint32_t m, bool copy) { return !copy && m >= 11; }
+
 template <int RB>
 __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc, uint32_t blk, C2 *smem) {
   constexpr int R = 1 << RB;
@@ -187,12 +193,14 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
   const uint32_t N = 1u << m;
   const uint32_t BS = blockDim.x;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  C2 *buf0 = smem, *buf1 = smem + N;
-  double *s_mats = reinterpret_cast<double *>(smem + 2 * N);
   const uint32_t base = (wave << (RB + 6)) | (lane << RB);  // index of register 0
   const bool live = base < N;  // fewer than 64 amplitudes: the upper lanes idle
   uint32_t n_out = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
+  const bool copy = n_out && !split_bc;
+  const bool single = sv_single_buffer(m, copy);
+  C2 *buf0 = smem, *buf1 = single ? smem : smem + N;
+  double *s_mats = reinterpret_cast<double *>(smem + (single ? 1 : 2) * N);
   uint32_t n_bc = 1;
   for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
   const uint32_t prep = split_bc ? blk / n_bc : blk;
@@ -345,6 +353,7 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
         case SV_SWAP: {
           // amplitude i moves to i with bits a and b exchanged
           C2 *B = cur ? buf1 : buf0;
+          if (single) __syncthreads();  // every read of the previous swap is done
           if (live) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -376,6 +385,7 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
   // the state to LDS in logical order: bit q of the logical index is the
   // physical bit at position layout[q]
   C2 *S = cur ? buf1 : buf0;
+  if (single) __syncthreads();  // the last swap's reads are done
   if (live) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -386,7 +396,6 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
     }
   }
   __syncthreads();
-  const bool copy = n_out && !split_bc;
   C2 *work = copy ? (cur ? buf0 : buf1) : S;
 
   // outcome distribution of every basis combination
@@ -495,8 +504,10 @@ void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &
   n_wg = split ? n_prep * n_bc : n_prep;
   block = 64u << sv_shape(h.m).wb;
   // two state buffers (swaps alternate between them; the copy mode uses the
-  // second for the rotated copy) and the staged matrices of a program chunk
-  lds = (size_t(2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
+  // second for the rotated copy), or one, and the staged matrices of a
+  // program chunk
+  const bool copy = n_out && !split;
+  lds = (size_t(sv_single_buffer(h.m, copy) ? 1 : 2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
 }
 
 hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_jobs, uint64_t total_wg, uint32_t m,
