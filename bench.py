@@ -1,16 +1,23 @@
 """Benchmark of the Clifford-based circuit-cutting hot path on one MI355X.
 
-One step = the whole hot path over the 32-qubit workload (40 random
-Clifford layers, CX density 0.3, 4 T gates on qubits 0-9, 2 cuts leaving a
-10-qubit non-Clifford and a 24-qubit Clifford fragment, 1e5 shots per
-Clifford variant): the 12-qubit marginal over qubits 20-31 and the 64 random
-Z-string expectations, each rebuilt from all fragment variants (tableau
-pass, Philox shots, state vectors, Pauli transform, 4^k recombination).
+Default workload (the largest single-GPU configuration): 256 near-Clifford
+circuits of uneven shape (width 20-200, depth 20-60, 1-6 T gates in one
+block of at most 12 wires, 1-4 cuts, half of them mirrored in time), 1e4
+shots per Clifford fragment variant, a 16-qubit marginal per circuit.  One
+step = one replay of the captured batch: every fragment variant of every
+circuit (tableau pass, Philox shots, state vectors), the Pauli transforms
+and the 4^k recombinations.
 
 Prints one JSON line.  value = fragment-variant shots per second of the
-whole step; recombination term-products per second and the dominant
-kernel's roofline sit beside it; the CPU oracle, timed on this host on a
-bounded sample of the same workload, is reported as cpu_baseline.
+whole step; recombination term-products per second sit beside it, with the
+dominant kernel's roofline (work per launch over its HIP-event-timed
+launches), the fractions of the other modelled kernels, and the CPU oracle
+timed on this host (single-threaded and on all cores) on a bounded sample
+of the same circuits as cpu_baseline.
+
+Other workloads (--workload): mid (32 qubits, 2 cuts, 1e5 shots), precision
+(400 qubits, 6 cuts, fp32 matrix-core products), learned (300 qubits, 10
+cuts, learned term proposal), scan (the paper's workload families).
 """
 from __future__ import annotations
 
@@ -35,9 +42,12 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default: 2000 for mid, whose step takes about 0.1 ms; 50 otherwise)")
-    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 200 for mid, 10 otherwise)")
-    ap.add_argument("--shots", type=int, default=100_000)
+                    help="timed steps (default: 2000 for mid, whose step takes about 0.1 ms; 20 for batching; "
+                         "50 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default: 200 for mid, 5 for batching, 10 otherwise)")
+    ap.add_argument("--shots", type=int, default=None,
+                    help="shots per Clifford variant (default: 1e5 for mid, 1e4 for batching)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 64 MiB elementwise copy first (the known-size kernel that scales the HBM "
@@ -47,17 +57,20 @@ def parse():
                          "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy run into profiles/<workload>_traffic.json")
     ap.add_argument("--traffic-kernel", default="sv_kernel")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["mid", "batching", "precision", "learned", "scan"], default="mid",
-                    help="mid (default): the 32-qubit, 2-cut workload; batching: 256 uneven circuits in one "
-                         "graph-captured batch; precision: the 400-qubit, 6-cut workload with FP32-MFMA "
+    ap.add_argument("--workload", choices=["mid", "batching", "precision", "learned", "scan"], default="batching",
+                    help="batching (default): 256 uneven circuits in one graph-captured batch; mid: the 32-qubit, "
+                         "2-cut workload; precision: the 400-qubit, 6-cut workload with FP32-MFMA "
                          "recombination; learned: the 300-qubit, 10-cut workload, learned term proposal against "
                          "exhaustive recombination; scan: the paper's workload families with automatic cuts")
     args = ap.parse_args()
     short = args.workload == "mid"
+    batch = args.workload == "batching"
     if args.steps is None:
-        args.steps = 2000 if short else 50
+        args.steps = 2000 if short else 20 if batch else 50
     if args.warmup is None:
-        args.warmup = 200 if short else 10
+        args.warmup = 200 if short else 5 if batch else 10
+    if args.shots is None:
+        args.shots = 10_000 if batch else 100_000
     return args
 
 
@@ -308,6 +321,189 @@ def _timed(fn, steps, warmup):
     return time.perf_counter() - t0
 
 
+def host_info():
+    """Host CPU: usable cores, nproc and the model name (as lscpu reports it)."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cores": cores, "model": model}
+
+
+def _oracle_fragment_task(task):
+    """One pool task of the all-core oracle run: the variant distributions of
+    variants [v0, v1) of fragment f of batch circuit i (the oracle's own
+    per-variant functions, as oracle.cutting.variant_distributions calls them)."""
+    import numpy as np
+    import workloads as W
+    from oracle import cutting as C
+    from oracle import philox as Ph
+    i, f, v0, v1, shots, seed = task
+    w = W.batching_circuit(i, shots=shots)
+    frag = C.fragment_circuit(w.n, w.ops, w.cuts)[f]
+    meas = C.make_request(frag, w.qubits).meas
+    out = np.zeros((v1 - v0, 1 << len(meas)))
+    for v in range(v0, v1):
+        if not frag.clifford:
+            out[v - v0] = C.nc_distribution(frag, v, meas)
+        else:
+            out[v - v0] = C.clifford_sampled(frag, v, meas, seed, Ph.variant_id(i, frag.index, v), shots)
+    return i, f, v0, out
+
+
+def _oracle_batch_sample(idx, shots, seed, pool=None):
+    """The oracle's sampled marginals of batch circuits idx (circuit index =
+    batch position, as the GPU batch numbers its variant ids).  pool: a
+    process pool that evaluates the fragment variants in parallel; the
+    transform and recombination run in this process as in
+    oracle.cutting.marginal."""
+    import numpy as np
+    import workloads as W
+    from oracle import cutting as C
+    res, n_shots = {}, 0
+    if pool is None:
+        for i in idx:
+            w = W.batching_circuit(i, shots=shots)
+            res[i] = C.marginal(w.n, w.ops, w.cuts, w.qubits, shots=shots, seed=seed, circuit=i)
+            n_shots += shots * sum(f.n_variants for f in C.fragment_circuit(w.n, w.ops, w.cuts) if f.clifford)
+        return res, n_shots
+    tasks, parts = [], {}
+    for i in idx:
+        w = W.batching_circuit(i, shots=shots)
+        frags = C.fragment_circuit(w.n, w.ops, w.cuts)
+        for f in frags:
+            step = max(1, f.n_variants // 16)
+            for v0 in range(0, f.n_variants, step):
+                tasks.append((i, f.index, v0, min(f.n_variants, v0 + step), shots, seed))
+            if f.clifford:
+                n_shots += shots * f.n_variants
+    for i, f, v0, d in pool.imap_unordered(_oracle_fragment_task, tasks, chunksize=1):
+        parts[(i, f, v0)] = d
+    for i in idx:
+        w = W.batching_circuit(i, shots=shots)
+        frags = C.fragment_circuit(w.n, w.ops, w.cuts)
+        reqs = [C.make_request(f, w.qubits) for f in frags]
+        dists = [np.concatenate([parts[key] for key in sorted(k for k in parts if k[0] == i and k[1] == f.index)])
+                 for f in frags]
+        tensors = [C.pauli_tensor(f, r, d) for f, r, d in zip(frags, reqs, dists)]
+        res[i] = C.recombine(frags, reqs, tensors, len(w.cuts), len(w.qubits))
+    return res, n_shots
+
+
+def cpu_baseline_batching(target_s: float, full_shots: int, seed: int):
+    """The oracle (literal per-shot CHP tableau, fp64 state vectors, plain
+    transform and ascending recombination) on a bounded sample of the batch:
+    4 of its 256 circuits (every 64th), timed single-threaded and with the
+    fragment variants spread over every usable host core, each at two shot
+    counts.  The oracle's time is a per-variant part (building each
+    variant's tableau gate by gate) plus a per-shot part (one literal
+    tableau measurement sequence per shot), so the two timings give both,
+    and the rate at the batch's own shots per variant follows; shots/s."""
+    import multiprocessing as mp
+
+    import numpy as np
+    idx = list(range(0, 256, 64))
+    lo = 8
+    t0 = time.perf_counter()
+    single_lo, n_lo = _oracle_batch_sample(idx, lo, seed)
+    t1_lo = time.perf_counter() - t0
+    # the larger sample: as many shots as fit the time target
+    hi = lo
+    while True:
+        hi = int(max(2 * hi, min(full_shots, hi * target_s / max(t1_lo, 1e-3))))
+        t0 = time.perf_counter()
+        single_hi, n_hi = _oracle_batch_sample(idx, hi, seed)
+        t1_hi = time.perf_counter() - t0
+        if t1_hi >= 0.5 * target_s or hi >= full_shots:
+            break
+    n_var = n_lo // lo
+    host = host_info()
+    workers = max(1, min(16, host["usable_cores"]))
+    ctx = mp.get_context("spawn")  # this process holds a GPU context: no fork
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_fragment_task, [(0, 0, 0, 1, 1, seed)] * workers)  # workers up and imported
+        t0 = time.perf_counter()
+        par_lo, _ = _oracle_batch_sample(idx, lo, seed, pool)
+        tn_lo = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        par_hi, _ = _oracle_batch_sample(idx, hi, seed, pool)
+        tn_hi = time.perf_counter() - t0
+    same = all(np.array_equal(single_lo[i], par_lo[i]) and np.array_equal(single_hi[i], par_hi[i]) for i in idx)
+
+    def at_full(t_lo, t_hi):
+        per_shot = max(t_hi - t_lo, 0.0) / (n_var * (hi - lo))
+        per_var = max(t_lo - per_shot * n_var * lo, 0.0) / n_var
+        return n_var * full_shots / (n_var * (per_var + per_shot * full_shots)), per_shot, per_var
+
+    rate_n, shot_n, var_n = at_full(tn_lo, tn_hi)
+    rate_1, shot_1, var_1 = at_full(t1_lo, t1_hi)
+    sample = (f"batch circuits {idx} (4 of 256, {n_var} Clifford variants) timed at {lo} and {hi} shots per "
+              f"variant; value = the rate at the batch's {full_shots} shots per variant from the per-variant "
+              f"and per-shot times of those two runs (all-core: variants over a process pool of {workers}; "
+              f"results equal to the single-threaded ones: {same})")
+    return {"value": rate_n, "unit": "shots/s", "cores": workers, "kind": "oracle", "sample": sample,
+            "measured": {"shots_lo": lo, "shots_hi": hi, "s_lo": tn_lo, "s_hi": tn_hi,
+                         "rate_lo": n_lo / tn_lo, "rate_hi": n_hi / tn_hi,
+                         "per_shot_us": shot_n * 1e6, "per_variant_ms": var_n * 1e3},
+            "single_core": {"value": rate_1, "cores": 1, "s_lo": t1_lo, "s_hi": t1_hi, "rate_lo": n_lo / t1_lo,
+                            "rate_hi": n_hi / t1_hi, "per_shot_us": shot_1 * 1e6, "per_variant_ms": var_1 * 1e3},
+            "host": host}
+
+
+def batching_work(cc, plans, ws, shots):
+    """Algorithmic work of one batch step per modelled kernel class:
+    {kernel: (amount, kind)} with kind 'int' (int32 ops), 'fp64' (flops) or
+    'bytes' (HBM bytes), as stated in the design notes."""
+    sv = 0.0
+    samp_ops = samp_bytes = 0.0
+    tab_ops = base_ops = 0.0
+    tr_bytes = 0.0
+    rc_flops = rc_bytes = 0.0
+    for p, w in zip(plans, ws):
+        frags = p.fragments()
+        sv += sv_flops(cc, p, frags, w.qubits)
+        k = len(w.cuts)
+        K = 4 ** k
+        rows = []
+        for f, fr in enumerate(frags):
+            nm, nr = cc.ccut_request_info(p.handle, w.qubits, f)
+            nv = fr["n_variants"]
+            rows.append(nr)
+            tr_bytes += 8.0 * (nv << nm) + 8.0 * ((4 ** len(fr["axes"])) << nr)
+            if not fr["clifford"]:
+                continue
+            W_ = (fr["m"] + 63) // 64
+            rw = (2 * fr["m"] + 63) // 64
+            # base tableau (once per fragment): per gate and 64 rows 22 (one-qubit
+            # map) or 12 (CX, CZ) int32 operations
+            base_ops += rw * (22 * fr["n_one"] + 12 * fr["n_two"])
+            # per variant and measurement: 2m rows x W words x 12 int32 operations
+            # (pivot search and rowsums)
+            tab_ops += nv * nm * 2 * fr["m"] * W_ * 12
+            # per shot: Philox share (100 per 4 shots and 32 indices), one
+            # select-and-xor (3 ops) per measurement, one histogram increment;
+            # the variant's fp64 table written once
+            samp_ops += nv * shots * (PHILOX_OPS / 4 * ((nm + 31) // 32) + 3 * nm + 1)
+            samp_bytes += 8.0 * (nv << nm)
+        M = 1 << min(rows) if len(rows) > 1 else 1
+        N = 1 << max(rows)
+        rc_flops += 2.0 * M * N * K
+        rc_bytes += 8.0 * K * (M + N) + 8.0 * M * N
+    return {"sv_kernel": (sv, "fp64"), "tableau_kernel": (tab_ops, "int"), "base_tableau_kernel": (base_ops, "int"),
+            "sample_kernel": (samp_ops, "int"), "sample_kernel:bytes": (samp_bytes, "bytes"),
+            "transform_pass_kernel": (tr_bytes, "bytes"), "recombine_fp64_kernel": (rc_flops, "fp64"),
+            "recombine_fp64_kernel:bytes": (rc_bytes, "bytes")}
+
+
+PEAKS = {"int": (PEAK_INT32_OPS, "alu", "Gop/s"), "fp64": (PEAK_FP64, "fp64", "GFLOP/s"),
+         "bytes": (PEAK_HBM, "hbm", "GB/s")}
+
+
 def bench_batching(args):
     """256 circuits (width 20-200, depth 20-60, 1-4 cuts), 1e4 shots per
     variant, 16-qubit marginals; one step = one replay of the captured batch."""
@@ -317,57 +513,63 @@ def bench_batching(args):
     import workloads as W
 
     torch.cuda.set_device(0)
-    shots = min(args.shots, 10_000)
+    shots = args.shots
+    seed = 2000
     ws = W.batching(256, shots=shots)
     ctx = cc.Context(0)
     plans = [cc.Plan(ctx, w.n, w.ops, w.cuts) for w in ws]
+    if args.calibrate_copy:
+        a = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = a + 0.0
+        torch.cuda.synchronize()
+        del a, b
     t0 = time.perf_counter()
-    batch = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=2000, use_graph=True)
+    batch = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=seed, use_graph=True)
     t_create = time.perf_counter() - t0
     info = batch.info()
     outs = [torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda") for w in ws]
     dt = _timed(lambda: batch.run(outs), args.steps, args.warmup)
-    eager = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=2000, use_graph=False)
+    eager = cc.Batch(ctx, plans, [w.qubits for w in ws], shots=shots, seed=seed, use_graph=False)
     dt_eager = _timed(lambda: eager.run(outs), args.steps, args.warmup)
-    # per-kernel times from eager runs with event timing (a graph replay records no events)
+    # per-kernel times from eager runs of the same launches with HIP events
+    # on each launch's own stream (a graph replay records no events)
     times = _kernel_pass(ctx, lambda: eager.run(outs), args.steps)
+    work = batching_work(cc, plans, ws, shots)
+    fracs = {}
+    for key, (amount, kind) in work.items():
+        name = key.split(":")[0]
+        launches, total_ms = times.get(name, (0, 0.0))
+        if not launches:
+            continue
+        peak, bound, unit = PEAKS[kind]
+        per_launch = amount / (launches / args.steps)
+        avg_s = total_ms / launches / 1e3
+        fracs[key] = {"bound": bound, "achieved": per_launch / avg_s / 1e9, "peak": peak / 1e9, "unit": unit,
+                      "frac": per_launch / avg_s / peak, "avg_launch_us": avg_s * 1e6,
+                      "launches_per_step": launches / args.steps, "work_per_launch": per_launch}
+    # the dominant kernel: the modelled kernel class with the largest summed
+    # launch time per step
+    dom = max((k for k in fracs if ":" not in k), key=lambda k: times[k][1])
+    roof = dict(fracs[dom], kernel=dom, traffic=traffic_for("batching", dom))
     n_var = sum(f["n_variants"] for p in plans for f in p.fragments() if f["clifford"])
-    sv_work = sum(sv_flops(cc, p, p.fragments(), w.qubits) for p, w in zip(plans, ws))
-    n_meas_tot = 0
-    for p, w in zip(plans, ws):
-        for f, fr in enumerate(p.fragments()):
-            if fr["clifford"]:
-                n_meas_tot += fr["n_variants"] * cc.ccut_request_info(p.handle, w.qubits, f)[0]
-    work = {
-        "sv_kernel": (sv_work, "fp64", PEAK_FP64, "GFLOP/s"),
-        # per shot: Philox share + one select-and-xor per measurement + a histogram increment
-        "sample_kernel": (shots * (n_var * (PHILOX_OPS / 4 + 1) + 3 * n_meas_tot), "alu", PEAK_INT32_OPS, "Gop/s"),
-    }
-    # the metric's kernel (shots: the sampling launches, which run one after
-    # another on the batch stream); the state-vector launches overlap each
-    # other and the sampling, so their summed durations overstate their share
-    name = "sample_kernel"
-    launches, total_ms = times[name]
-    units, bound, peak, unit = work[name]
-    per_step_launches = launches / args.steps
-    achieved = units / (total_ms / args.steps / 1e3)  # summed launch durations of one step
-    roof = {"bound": bound, "kernel": name, "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "avg_launch_us": total_ms / max(launches, 1) * 1e3,
-            "launches_per_step": per_step_launches,
-            "note": "work of the sampling launches of one step over their time including the histogram "
-                    "reduction (eager run, HIP events)"}
     shots_per_step = n_var * shots
+    terms = sum((4 ** len(w.cuts)) << len(w.qubits) for w in ws)
     line = {
         "metric": METRIC, "value": shots_per_step / (dt / args.steps), "unit": "shots/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "batching: 256 near-Clifford circuits, width 20-200, depth 20-60, 1-6 T, 1-4 cuts, "
-                               "1e4 shots per variant, 16-qubit marginals, one graph-captured batch",
-                   "clifford_variants": n_var, "shots_per_step": shots_per_step},
+        "config": {"workload": "batching: 256 near-Clifford circuits, width 20-200, depth 20-60, 1-6 T in one block "
+                               "of at most 12 wires, 1-4 cuts (half mirrored in time), 1e4 shots per variant, "
+                               "16-qubit marginals, one graph-captured batch per step",
+                   "clifford_variants": n_var, "shots_per_step": shots_per_step, "circuits": len(ws)},
+        "recombination_terms_per_s": terms / (dt / args.steps),
         "batch": dict(info, create_s=t_create, eager_ms_per_step=1e3 * dt_eager / args.steps),
         "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
         "roofline": roof,
+        "kernel_fractions": fracs,
     }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_batching(args.cpu_seconds, shots, seed)
     print(json.dumps(line), flush=True)
 
 

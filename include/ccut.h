@@ -428,7 +428,8 @@ enum {
   CCUT_K_HEISENBERG = 9,
   CCUT_K_MLP = 10,
   CCUT_K_TERMS = 11,
-  CCUT_K_COUNT = 12
+  CCUT_K_BASE = 12, /* shared base tableaux of a batch's Clifford fragments */
+  CCUT_K_COUNT = 13
 };
 ccut_status ccut_timing_enable(ccut_ctx *ctx, int enable);
 ccut_status ccut_timing_reset(ccut_ctx *ctx);

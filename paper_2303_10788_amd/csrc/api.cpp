@@ -1478,7 +1478,7 @@ const char *ccut_kernel_name(uint32_t kid) {
                                             "exact_kernel", "sv_kernel", "parity_kernel",
                                             "transform_pass_kernel", "recombine_fp64_kernel",
                                             "zrecombine_fp64_kernel", "heisenberg_kernels",
-                                            "mlp_kernels", "term_kernels"};
+                                            "mlp_kernels", "term_kernels", "base_tableau_kernel"};
   return kid < CCUT_K_COUNT ? names[kid] : "";
 }
 
@@ -1581,6 +1581,7 @@ ccut_status batch_tableau(ccut_batch *b, FragDev *d_descs, BatchItem *d_items, u
                           const uint64_t *d_bases) {
   ccut_ctx *c = b->ctx;
   if (b->items.empty()) return CCUT_OK;
+  KTimer t(c, CCUT_K_TABLEAU);
   HIP_TRY(c, launch_tableau_batch(d_descs, d_items, (uint32_t)b->items.size(), d_counter, d_models, b->max_m, block,
                                   grid, use_reg, d_bases, c->cur));
   return CCUT_OK;
@@ -1604,7 +1605,10 @@ ccut_status batch_bases(ccut_batch *b, FragDev *d_descs, uint64_t **d_bases_out)
   }
   uint32_t *d_list = (uint32_t *)upload(c, list.data(), list.size() * 4);
   if (!d_list) return fail(c, CCUT_E_OOM, "device allocation failed");
-  HIP_TRY(c, launch_base_batch(d_descs, d_list, (uint32_t)list.size(), max_rows, d_off, d_bases, c->cur));
+  {
+    KTimer t(c, CCUT_K_BASE);
+    HIP_TRY(c, launch_base_batch(d_descs, d_list, (uint32_t)list.size(), max_rows, d_off, d_bases, c->cur));
+  }
   *d_bases_out = d_bases;
   return CCUT_OK;
 }
@@ -1823,12 +1827,16 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
     if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (fill_words) HIP_TRY(c, launch_fill_u32(zeroed, fill_words, 0u, c->cur));
-    KTimer tm(c, CCUT_K_SAMPLE);
     for (int cls = 0; cls < 4; ++cls)
-      if (cls_count[cls])
+      if (cls_count[cls]) {
+        KTimer tm(c, CCUT_K_SAMPLE);
         HIP_TRY(c, launch_sample_batch(d_jobs + cls_first[cls], (uint32_t)cls_count[cls], cls_units[cls],
                                        cls_lds[cls], c->cur));
-    HIP_TRY(c, launch_hist_reduce_batch(d_jobs, (uint32_t)jobs.size(), t, c->cur));
+      }
+    if (t) {
+      KTimer tm(c, CCUT_K_HIST_REDUCE);
+      HIP_TRY(c, launch_hist_reduce_batch(d_jobs, (uint32_t)jobs.size(), t, c->cur));
+    }
   }
   for (size_t k = 0; k < n_sv_streams; ++k)
     if (sv_used[k]) HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
