@@ -168,7 +168,8 @@ ccut_status ccut_ctx_create(const ccut_opts *opts, ccut_ctx **out);
 void ccut_ctx_destroy(ccut_ctx *ctx);
 
 /* Text of the last error on this context (valid until the next call on
- * it); "" if none.  ctx may be NULL for errors of ccut_ctx_create. */
+ * it); "" if none.  ctx may be NULL for errors of ccut_ctx_create and
+ * ccut_sample_terms_noalloc (per host thread). */
 const char *ccut_last_error(const ccut_ctx *ctx);
 
 /* Ask a running evaluation on this context to stop; it returns
@@ -378,6 +379,24 @@ ccut_status ccut_proposal(ccut_ctx *ctx, const float *logits, uint64_t K, double
 /* n terms drawn from q[K] as above (device u64 out[n]). */
 ccut_status ccut_sample_terms(ccut_ctx *ctx, const double *q, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
                               uint64_t *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the draw
+ * of ccut_sample_terms (same terms for the same q, n, seed, cid) without a
+ * context and without any allocation.  The integer CDF and the scan
+ * partials live in one fixed device array of the library, 8 MiB + 16 KiB on
+ * each device it runs on, held until the process ends; so K <= 2^20 (the
+ * 4^10 terms of ten cuts), larger K is CCUT_E_UNSUPPORTED.  Runs on the
+ * current HIP device, enqueued on hip_stream (hipStream_t, NULL = null
+ * stream); returns without waiting: out (device u64[n]) is valid in stream
+ * order.  q (device fp64 [K]) and out are caller-owned.  Every call on one
+ * device shares that array: calls that overlap on a device (other streams,
+ * other host threads) race and must be ordered by the caller.  Errors
+ * (text in ccut_last_error(NULL)): CCUT_E_INVALID (NULL q, NULL out with
+ * n > 0, K = 0, n >= 2^32), CCUT_E_UNSUPPORTED (K > 2^20), CCUT_E_DEVICE (no
+ * current device, symbol lookup or launch failure). */
+ccut_status ccut_sample_terms_noalloc(void *hip_stream, const double *q, uint64_t K, uint64_t n, uint64_t seed,
+                                      uint64_t cid, uint64_t *out);
 
 /* Network with F inputs (F % 64 == 0) and width H (H % 64 == 0, H <= 256).
  * Parameters, flat fp32 in this order: W1[H][F], b1[H], W2[H][H], b2[H],

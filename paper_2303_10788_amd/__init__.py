@@ -122,6 +122,8 @@ SIGNATURES = {
     "ccut_proposal": ([_P, _P, ctypes.c_uint64, ctypes.c_double, _P], ctypes.c_int),
     "ccut_sample_terms": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _P],
                           ctypes.c_int),
+    "ccut_sample_terms_noalloc": ([_P, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                   _P], ctypes.c_int),
     "ccut_mlp_create": ([_P, ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(_P)], ctypes.c_int),
     "ccut_mlp_set_params": ([_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t], ctypes.c_int),
     "ccut_mlp_get_params": ([_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t], ctypes.c_int),
@@ -635,6 +637,15 @@ def ccut_proposal(ctx, logits, K, eps, q):
 def ccut_sample_terms(ctx, q, K, n, seed, cid, out):
     _check(lib().ccut_sample_terms(ctx, _dptr(q), K, n, int(seed) & 0xFFFFFFFFFFFFFFFF,
                                    int(cid) & 0xFFFFFFFFFFFFFFFF, _dptr(out)), ctx)
+
+
+def ccut_sample_terms_noalloc(stream, q, K, n, seed, cid, out):
+    """The allocation-free term draw on the current device, enqueued on
+    `stream` (a torch stream, a raw hipStream_t, or None for the null
+    stream); out is valid in stream order."""
+    raw = getattr(stream, "cuda_stream", stream)
+    _check(lib().ccut_sample_terms_noalloc(raw, _dptr(q), K, n, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                           int(cid) & 0xFFFFFFFFFFFFFFFF, _dptr(out)), None)
 
 
 def ccut_mlp_create(ctx, F, H):

@@ -173,6 +173,10 @@ struct ccut_plan {
 
 static thread_local std::string g_create_err;
 
+namespace ccut {
+void set_call_error(const char *msg) { g_create_err = msg; }
+}  // namespace ccut
+
 namespace {
 
 ccut_status fail(ccut_ctx *ctx, ccut_status st, const std::string &msg) {

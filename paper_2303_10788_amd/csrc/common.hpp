@@ -517,6 +517,8 @@ hipError_t launch_scan_u64(uint64_t *x, uint64_t n, uint64_t *scratch, hipStream
 uint32_t reduce_blocks(uint64_t n);
 hipError_t launch_proposal(const float *logits, uint64_t n, double eps, float *mpart, double *spart, double *stats,
                            double *q, hipStream_t s);
+// The error text of a call without a context (ccut_last_error(NULL)).
+void set_call_error(const char *msg);
 hipError_t launch_int_cdf(const double *q, uint64_t n, uint64_t *cdf, uint64_t *scratch, hipStream_t s);
 hipError_t launch_sample_terms(const uint64_t *cdf, uint64_t K, uint64_t n, uint64_t seed, uint64_t cid,
                                uint64_t *out, hipStream_t s);

@@ -10,7 +10,9 @@
 // supplies A[row l % 16][k 4 (l / 16) + i] and B[k 4 (l / 16) + i][col l % 16]
 // for i < 4; accumulator register g holds D[row 4 (l / 16) + g][col l % 16].
 #include <cmath>
+#include <mutex>
 
+#include "ccut.h"
 #include "common.hpp"
 
 namespace ccut {
@@ -852,3 +854,70 @@ hipError_t launch_is_scale(const uint64_t *terms, const double *q, uint64_t n, d
 }
 
 }  // namespace ccut
+
+// ------------------------------------------------ term draws without allocation
+// ccut_sample_terms_noalloc keeps the integer CDF and the scan partials of a
+// draw in one fixed device array instead of allocating them: up to
+// kNoAllocMaxTerms cut terms (4^10, the ten-cut recombination) plus the scan
+// partials of that size, 8 MiB + 16 KiB on each device the library runs on,
+// held until the process ends.  Host code never uses the array's name as an
+// address: its device address is looked up once per device with
+// hipGetSymbolAddress (with that device current) and kept.
+namespace {
+
+constexpr uint64_t kNoAllocMaxTerms = 1ull << 20;
+constexpr uint64_t kNoAllocScanWords = 2048;  // scan partials for up to kNoAllocMaxTerms entries (1025 words)
+constexpr uint64_t kNoAllocWords = kNoAllocMaxTerms + kNoAllocScanWords;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) uint64_t noalloc_scratch[kNoAllocWords];
+
+std::mutex g_noalloc_mu;
+uint64_t *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+extern "C" ccut_status ccut_sample_terms_noalloc(void *hip_stream, const double *q, uint64_t K, uint64_t n,
+                                                 uint64_t seed, uint64_t cid, uint64_t *out) {
+  using namespace ccut;
+  if (!q || K == 0 || (n && !out)) {
+    set_call_error("ccut_sample_terms_noalloc: NULL argument or K = 0");
+    return CCUT_E_INVALID;
+  }
+  if (n > 0xFFFFFFFFull) {
+    set_call_error("ccut_sample_terms_noalloc: at most 2^32 - 1 terms per draw");
+    return CCUT_E_INVALID;
+  }
+  if (K > kNoAllocMaxTerms || scan_scratch_words(K) > kNoAllocScanWords) {
+    set_call_error("ccut_sample_terms_noalloc: K above 2^20, the size of the fixed term buffer");
+    return CCUT_E_UNSUPPORTED;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) {
+    set_call_error("ccut_sample_terms_noalloc: no current HIP device");
+    return CCUT_E_DEVICE;
+  }
+  uint64_t *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+      void *ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !ptr) {
+        set_call_error("ccut_sample_terms_noalloc: hipGetSymbolAddress of the term buffer failed");
+        return CCUT_E_DEVICE;
+      }
+      g_noalloc_ptr[dev] = static_cast<uint64_t *>(ptr);
+    }
+    base = g_noalloc_ptr[dev];
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // every CDF entry and scan partial is written before it is read: nothing
+  // left by an earlier call is used
+  uint64_t *cdf = base, *partials = base + K;
+  if (launch_int_cdf(q, K, cdf, partials, s) != hipSuccess ||
+      launch_sample_terms(cdf, K, n, seed, cid, out, s) != hipSuccess) {
+    set_call_error("ccut_sample_terms_noalloc: kernel launch failed");
+    return CCUT_E_DEVICE;
+  }
+  return CCUT_OK;
+}
