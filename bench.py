@@ -265,10 +265,12 @@ def main():
 
 def sv_flops(cc, plan, frags, qubits):
     """Algorithmic fp64 flops of one state-vector pass over the non-Clifford
-    fragments of a request: per preparation combination 28 flops per
-    amplitude pair of each fused one-qubit unitary; per (preparation, basis)
-    combination 3 flops per amplitude for |a|^2 and N/2 adds per unmeasured
-    qubit."""
+    fragments of a request: the gate program runs once per computational-
+    basis input (2^n_in runs; 28 flops per amplitude pair of each fused
+    one-qubit unitary); each of the 4^n_in preparation states is a sum of
+    the run states it superposes (6^n_in terms over all preparations, 2 flops
+    per amplitude each); per (preparation, basis) combination 3 flops per
+    amplitude for |a|^2 and N/2 adds per unmeasured qubit."""
     total = 0.0
     for f, fr in enumerate(frags):
         if fr["clifford"]:
@@ -277,7 +279,10 @@ def sv_flops(cc, plan, frags, qubits):
         n_out = len(fr["axes"]) - n_in
         N = 1 << fr["m"]
         n_meas, _ = cc.ccut_request_info(plan.handle, qubits, f)
-        total += (4 ** n_in) * (fr["n_one"] * 14 * N + (3 ** n_out) * (3 * N + (fr["m"] - n_meas) * N // 2))
+        runs = 1 << n_in
+        combine = 2 * N * (6 ** n_in) if n_in else 0
+        total += runs * fr["n_one"] * 14 * N + combine + \
+            (4 ** n_in) * (3 ** n_out) * (3 * N + (fr["m"] - n_meas) * N // 2)
     return total
 
 

@@ -457,8 +457,11 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
   double *dist = aget<double>(c, nv << nm);
   if (!dist) return fail(c, CCUT_E_OOM, "device allocation failed");
   if (!f.clifford) {
+    const size_t sb = sv_states_bytes(h);
+    double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
+    if (sb && !states) return fail(c, CCUT_E_OOM, "device allocation failed");
     KTimer t(c, CCUT_K_SV);
-    HIP_TRY(c, launch_sv(h, dist, c->cur));
+    HIP_TRY(c, launch_sv(h, dist, states, c->cur));
   } else {
     uint64_t *models = pre_models;
     if (!models) {
@@ -1316,10 +1319,12 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
     const FragDev h = frag_desc(p, f, r, eo->circuit);
     if (!f.clifford) {
       double *dist = aget<double>(c, nv << nm);
-      if (!dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+      const size_t sb = sv_states_bytes(h);
+      double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
+      if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
         KTimer t(c, CCUT_K_SV);
-        HIP_TRY(c, launch_sv(h, dist, c->cur));
+        HIP_TRY(c, launch_sv(h, dist, states, c->cur));
       }
       KTimer t(c, CCUT_K_PARITY);
       HIP_TRY(c, launch_dist_parity(dist, nm, nv, d_ext, n_ext, E, c->cur));
@@ -1650,44 +1655,52 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
       for (size_t k = 0; k < n_sv_streams; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
     }
-    // one launch per shape class; the classes go to the streams longest
-    // first, each to the stream with the least work so far (work: amplitudes
-    // times program length, summed over workgroups)
+    // two launches per shape class: the first runs fragments without
+    // quantum inputs in full and evolves the computational-basis inputs of
+    // the others, the second combines those into their preparations; the
+    // classes go to the streams longest first, each to the stream with the
+    // least work so far (work: amplitudes times program length, summed over
+    // workgroups)
     struct SvClass {
       uint32_t m;
-      std::vector<SvJob> jobs;
-      uint64_t wg = 0;
-      size_t lds = 0;
+      std::vector<SvJob> jobs[2];
+      uint64_t wg[2] = {0, 0};
+      size_t lds[2] = {0, 0};
       double cost = 0.0;
     };
     std::vector<SvClass> classes;
     for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
       SvClass C;
       C.m = m;
-      std::vector<SvJob> &jobs = C.jobs;
-      uint64_t &wg = C.wg;
-      size_t &lds = C.lds;
       for (const auto &ref : b->nc) {
         const FragDev &h = b->sv_descs[ref.desc];
         if (h.m != m) continue;
-        uint64_t n_wg;
-        uint32_t bs;
-        size_t l;
-        bool split;
-        sv_launch_shape(h, n_wg, bs, l, split);
-        SvJob J{};
-        J.desc = ref.desc;
-        J.split = split ? 1u : 0u;
-        J.wg0 = wg;
-        J.dist = aget<double>(c, h.n_variants << ref.n_meas);
-        if (!J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
-        pre_dist[ref.plan][ref.frag] = J.dist;
-        wg += n_wg;
-        lds = std::max(lds, l);
-        C.cost += (double)n_wg * (double)(1u << m) * (double)h.n_ops;
-        jobs.push_back(J);
+        double *dist = aget<double>(c, h.n_variants << ref.n_meas);
+        const size_t sb = sv_states_bytes(h);
+        double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
+        if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
+        pre_dist[ref.plan][ref.frag] = dist;
+        const uint32_t passes[2] = {sb ? 1u : 0u, 2u};
+        for (int k = 0; k < (sb ? 2 : 1); ++k) {
+          uint64_t n_wg;
+          uint32_t bs;
+          size_t l;
+          bool split;
+          sv_pass_shape(h, passes[k], n_wg, bs, l, split);
+          SvJob J{};
+          J.desc = ref.desc;
+          J.split = split ? 1u : 0u;
+          J.wg0 = C.wg[k];
+          J.dist = dist;
+          J.mode = passes[k];
+          J.states = states;
+          C.wg[k] += n_wg;
+          C.lds[k] = std::max(C.lds[k], l);
+          C.cost += (double)n_wg * (double)(1u << m) * (passes[k] == 2 ? 8.0 : (double)h.n_ops);
+          C.jobs[k].push_back(J);
+        }
       }
-      if (!jobs.empty()) classes.push_back(std::move(C));
+      if (!C.jobs[0].empty()) classes.push_back(std::move(C));
     }
     std::stable_sort(classes.begin(), classes.end(),
                      [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
@@ -1699,10 +1712,13 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         c->cur = b->pool[k];
         sv_used[k] = 1;
       }
-      SvJob *d_jobs = (SvJob *)upload(c, C.jobs.data(), C.jobs.size() * sizeof(SvJob));
-      if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
-      KTimer tm(c, CCUT_K_SV);
-      HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs.size(), C.wg, C.m, C.lds, c->cur));
+      for (int k = 0; k < 2; ++k) {
+        if (C.jobs[k].empty()) continue;
+        SvJob *d_jobs = (SvJob *)upload(c, C.jobs[k].data(), C.jobs[k].size() * sizeof(SvJob));
+        if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
+        KTimer tm(c, CCUT_K_SV);
+        HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs[k].size(), C.wg[k], C.m, C.lds[k], c->cur));
+      }
     }
     c->cur = b->stream;
     for (size_t k = 0; k < n_sv_streams; ++k)

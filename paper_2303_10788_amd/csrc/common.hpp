@@ -221,10 +221,16 @@ constexpr size_t kSampleLdsMax = 8 * 256 * 8 + (size_t(4) << kLdsHistBits);
 
 // One non-Clifford fragment in a batched state-vector launch: descriptor
 // descs[desc], tables in dist, wg0 = its first workgroup.
+// One fragment's pass of a batched state-vector launch: mode 0 runs every
+// preparation combination in full (fragments without quantum inputs),
+// mode 1 evolves the computational-basis inputs into `states`, mode 2
+// combines them into the preparation combinations' tables.
 struct SvJob {
   uint32_t desc, split;
   uint64_t wg0;
   double *dist;
+  uint32_t mode, pad_;
+  double *states;  // [2^n_in][2^m] complex amplitudes (modes 1 and 2)
 };
 
 // The job whose range [start, next start) holds idx (starts ascending, first 0).
@@ -261,7 +267,12 @@ hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nbl
 hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,
                                hipStream_t s);
 // prog: the fragment's state-vector program (words + 8 doubles per word)
-hipError_t launch_sv(const FragDev &frag, double *dist, hipStream_t s);
+// states: scratch of sv_states_bytes(frag) (may be NULL when it is 0).
+hipError_t launch_sv(const FragDev &frag, double *dist, void *states, hipStream_t s);
+uint32_t sv_inputs(const FragDev &h);
+size_t sv_states_bytes(const FragDev &h);
+// Launch shape of one pass (0 full, 1 evolve, 2 combine) of a fragment.
+void sv_pass_shape(const FragDev &h, uint32_t pass, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split);
 // State-vector launch shape of a fragment: workgroups, threads, LDS bytes,
 // whether basis combinations get workgroups of their own.
 void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split);

@@ -9,6 +9,13 @@
 // a copy, and writes that variant's outcome distribution over the measured
 // set.
 //
+// The fragment is linear in its input state, and |+> = (|0> + |1>)/sqrt2,
+// |+i> = (|0> + i|1>)/sqrt2.  So a fragment with quantum inputs is run only
+// on the 2^n_in computational-basis inputs (evolve pass, final states to
+// HBM), and the state of each of the 4^n_in preparation combinations is
+// their linear combination (combine pass, which then rotates and sums the
+// outcomes as above): 2^n_in instead of 4^n_in runs of the gate program.
+//
 // The state lives in registers while the gates run: amplitude index bits
 // [0, RB) pick one of a thread's 2^RB registers, the next (up to) 6 bits the
 // lane, the top bits the wave (sv_shape).  The host lays the gate stream out
@@ -181,8 +188,21 @@ __device__ inline const T *uniform_ptr(const T *p) {
 // barrier (their writes must wait for the previous swap's reads).
 __host__ __device__ inline bool sv_single_buffer(uint32_t m, bool copy) { return !copy && m >= 11; }
 
+// Passes of sv_body: the whole variant (fragments without quantum inputs),
+// the evolve pass (computational-basis inputs, final state to `states`) and
+// the combine pass (no gate program: a preparation combination's state from
+// `states`, then the basis rotations and outcome sums).
+enum : uint32_t { SV_FULL = 0, SV_EVOLVE = 1, SV_COMBINE = 2 };
+
+// The basis rotations and outcome distributions of one preparation
+// combination whose state is in S (logical order); vin = the variant-index
+// contribution of its input digits.
+__device__ void sv_outcomes(const FragDev &F, C2 *S, C2 *work, bool copy, uint32_t bc0, uint32_t bc1, uint64_t vin,
+                            double *__restrict__ dist, uint32_t R);
+
 template <int RB>
-__device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc, uint32_t blk, C2 *smem) {
+__device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double *__restrict__ dist, uint32_t split_bc,
+                                                       uint32_t blk, C2 *smem, uint32_t mode, C2 *__restrict__ states) {
   constexpr int R = 1 << RB;
   // the descriptor's scalars in scalar registers (uniform across the
   // workgroup; read from memory they would hold vector registers)
@@ -197,7 +217,7 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
   const bool live = base < N;  // fewer than 64 amplitudes: the upper lanes idle
   uint32_t n_out = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) n_out += F.axis_side[j] == 0;
-  const bool copy = n_out && !split_bc;
+  const bool copy = mode != SV_EVOLVE && n_out && !split_bc;
   const bool single = sv_single_buffer(m, copy);
   C2 *buf0 = smem, *buf1 = single ? smem : smem + N;
   double *s_mats = reinterpret_cast<double *>(smem + (single ? 1 : 2) * N);
@@ -206,8 +226,57 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
   const uint32_t prep = split_bc ? blk / n_bc : blk;
   const uint32_t bc0 = split_bc ? blk % n_bc : 0, bc1 = split_bc ? bc0 + 1 : n_bc;
 
+  if (mode == SV_COMBINE) {
+    // the preparation combination's state from the basis-input states:
+    // psi_s = h^(#superposed inputs) sum_b phase(s, b) psi_b over the inputs b
+    // compatible with s (digit 0 or 1: that bit; + or +i: both, the second
+    // times 1 or i), summed in ascending b
+    uint32_t n_in = 0, fixed = 0, sup = 0, imul = 0;
+    uint64_t vin = 0, stride = 1;
+    {
+      uint64_t pc = prep;
+      for (uint32_t j = 0; j < F.n_axes; ++j) {
+        if (F.axis_side[j] == 1) {
+          const uint32_t d = (uint32_t)(pc & 3u);
+          pc >>= 2;
+          vin += d * stride;
+          if (d == 1) fixed |= 1u << n_in;
+          if (d >= 2) sup |= 1u << n_in;
+          if (d == 3) imul |= 1u << n_in;
+          ++n_in;
+        }
+        stride *= F.axis_radix[j];
+      }
+    }
+    double scale = 1.0;
+    for (uint32_t j = 0; j < n_in; ++j)
+      if ((sup >> j) & 1u) scale *= 0.70710678118654752440;
+    for (uint32_t i = tid; i < N; i += BS) {
+      double ar = 0.0, ai = 0.0;
+      // enumerate the subsets of `sup` in ascending order of b = fixed | sub
+      uint32_t sub = 0;
+      do {
+        const uint32_t b = fixed | sub;
+        const C2 v = states[(size_t)b * N + i];
+        // the number of +i digits whose input bit is 1 sets the phase i^k
+        const uint32_t k = __popc(sub & imul) & 3u;
+        const double vr = k == 0 ? v.re : k == 1 ? -v.im : k == 2 ? -v.re : v.im;
+        const double vi = k == 0 ? v.im : k == 1 ? v.re : k == 2 ? -v.im : -v.re;
+        ar += vr;
+        ai += vi;
+        sub = (sub - sup) & sup;
+      } while (sub);
+      buf0[i] = C2{ar * scale, ai * scale};
+    }
+    __syncthreads();
+    sv_outcomes(F, buf0, copy ? buf1 : buf0, copy, bc0, bc1, vin, dist, R);
+    return;
+  }
+
   // prepared product state: |0>, |1>, |+> = H|0> or |+i> = S H|0> on each
-  // quantum input (digit of this preparation combination), |0> elsewhere
+  // quantum input (digit of this preparation combination; in the evolve
+  // pass bit j of the workgroup index is input j's computational-basis
+  // value), |0> elsewhere
   double re[R], im[R];
   uint64_t vin = 0;  // variant index contribution of the input digits
   {
@@ -223,8 +292,8 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
     uint64_t pc = prep, stride = 1;
     for (uint32_t j = 0; j < F.n_axes; ++j) {
       if (F.axis_side[j] == 1) {
-        const uint32_t d = (uint32_t)(pc & 3u);
-        pc >>= 2;
+        const uint32_t d = mode == SV_EVOLVE ? (uint32_t)(pc & 1u) : (uint32_t)(pc & 3u);
+        pc >>= mode == SV_EVOLVE ? 1 : 2;
         vin += d * stride;
         const uint32_t q = F.axis_local[j];
 #pragma unroll
@@ -382,8 +451,21 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
       }
     }
   }
-  // the state to LDS in logical order: bit q of the logical index is the
-  // physical bit at position layout[q]
+  // the state in logical order: bit q of the logical index is the physical
+  // bit at position layout[q]; the evolve pass writes it to HBM
+  if (mode == SV_EVOLVE) {
+    if (live) {
+      C2 *dst = states + (size_t)blk * N;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t i = base | (uint32_t)r;
+        uint32_t L = 0;
+        for (uint32_t q = 0; q < m; ++q) L |= ((i >> ((layout >> (4 * q)) & 15u)) & 1u) << q;
+        dst[L] = C2{re[r], im[r]};
+      }
+    }
+    return;
+  }
   C2 *S = cur ? buf1 : buf0;
   if (single) __syncthreads();  // the last swap's reads are done
   if (live) {
@@ -396,8 +478,12 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
     }
   }
   __syncthreads();
-  C2 *work = copy ? (cur ? buf0 : buf1) : S;
+  sv_outcomes(F, S, copy ? (cur ? buf0 : buf1) : S, copy, bc0, bc1, vin, dist, R);
+}
 
+__device__ void sv_outcomes(const FragDev &F, C2 *S, C2 *work, bool copy, uint32_t bc0, uint32_t bc1, uint64_t vin,
+                            double *__restrict__ dist, uint32_t R) {
+  const uint32_t m = F.m, N = 1u << m, BS = blockDim.x, tid = threadIdx.x;
   // outcome distribution of every basis combination
   const uint32_t nm = F.n_meas;
   uint32_t mmask = 0;
@@ -430,19 +516,19 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
     // pairwise sum over each unmeasured qubit in turn (fixed order, one
     // barrier per qubit); the entry of outcome o is left at the index with
     // o's bits on the measured qubits and zeros elsewhere
-    double pr[R];
+    double pr[4];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
+    for (uint32_t j = 0; j < 4; ++j) {
       const uint32_t i = tid + j * BS;
       pr[j] = 0.0;
-      if (i < N) pr[j] = work[i].re * work[i].re + work[i].im * work[i].im;
+      if (j < R && i < N) pr[j] = work[i].re * work[i].re + work[i].im * work[i].im;
     }
     __syncthreads();
     double *P = reinterpret_cast<double *>(work);
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
+    for (uint32_t j = 0; j < 4; ++j) {
       const uint32_t i = tid + j * BS;
-      if (i < N) P[i] = pr[j];
+      if (j < R && i < N) P[i] = pr[j];
     }
     __syncthreads();
     for (uint32_t q = 0; q < m; ++q) {
@@ -464,9 +550,10 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
 }
 
 template <int RB>
-__global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc) {
+__global__ __launch_bounds__(1024) void sv_kernel(const FragDev F, double *__restrict__ dist, uint32_t split_bc,
+                                                  uint32_t mode, C2 *__restrict__ states) {
   extern __shared__ C2 smem[];
-  sv_body<RB>(F, dist, split_bc, blockIdx.x, smem);
+  sv_body<RB>(F, dist, split_bc, blockIdx.x, smem, mode, states);
 }
 
 // Many fragments of one shape: workgroup x runs workgroup x - wg0 of the
@@ -484,12 +571,43 @@ __global__ __launch_bounds__(1024) void sv_batch_kernel(const FragDev *__restric
   // the job's fields are workgroup-uniform: keep them in scalar registers
   const SvJob &J = jobs[__builtin_amdgcn_readfirstlane(lo)];
   const uint32_t desc = __builtin_amdgcn_readfirstlane(J.desc), split = __builtin_amdgcn_readfirstlane(J.split);
+  const uint32_t mode = __builtin_amdgcn_readfirstlane(J.mode);
   const uint32_t blk = __builtin_amdgcn_readfirstlane((uint32_t)(blockIdx.x - J.wg0));
   double *dist = const_cast<double *>(uniform_ptr(J.dist));
-  sv_body<RB>(descs[desc], dist, split, blk, smem);
+  C2 *states = reinterpret_cast<C2 *>(const_cast<double *>(uniform_ptr(J.states)));
+  sv_body<RB>(descs[desc], dist, split, blk, smem, mode, states);
 }
 
 }  // namespace
+
+uint32_t sv_inputs(const FragDev &h) {
+  uint32_t n_in = 0;
+  for (uint32_t j = 0; j < h.n_axes; ++j) n_in += h.axis_side[j] == 1;
+  return n_in;
+}
+
+size_t sv_states_bytes(const FragDev &h) {
+  const uint32_t n_in = sv_inputs(h);
+  return n_in ? ((size_t)1 << (n_in + h.m)) * sizeof(C2) : 0;
+}
+
+void sv_pass_shape(const FragDev &h, uint32_t pass, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split) {
+  if (pass == SV_EVOLVE) {
+    // one workgroup per computational-basis input; the gate program needs
+    // the swap buffers and the staged matrices, no basis-rotation copy
+    n_wg = 1ull << sv_inputs(h);
+    block = 64u << sv_shape(h.m).wb;
+    split = false;
+    lds = (size_t(sv_single_buffer(h.m, false) ? 1 : 2) << h.m) * sizeof(C2) + kStage * 8 * sizeof(double);
+    return;
+  }
+  sv_launch_shape(h, n_wg, block, lds, split);
+  if (pass == SV_COMBINE) {
+    // no gate program: one state buffer, and a second for the rotated copy
+    const bool copy = h.n_axes != sv_inputs(h) && !split;
+    lds = (size_t(copy ? 2 : 1) << h.m) * sizeof(C2);
+  }
+}
 
 void sv_launch_shape(const FragDev &h, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split) {
   uint32_t n_in = 0, n_out = 0;
@@ -530,13 +648,13 @@ hipError_t launch_sv_batch(const FragDev *descs, const SvJob *jobs, uint32_t n_j
   return hipGetLastError();
 }
 
-hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
-  if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
+static hipError_t launch_sv_pass(const FragDev &h, double *dist, uint32_t pass, C2 *states, hipStream_t s) {
   uint64_t n_wg;
   uint32_t bs;
   size_t lds;
   bool split;
-  sv_launch_shape(h, n_wg, bs, lds, split);
+  sv_pass_shape(h, pass, n_wg, bs, lds, split);
+  if (lds > 160 * 1024 || n_wg > 0x7FFFFFFFull) return hipErrorInvalidValue;
   const SvShape sh = sv_shape(h.m);
   const void *kern = sh.rb == 0 ? (const void *)sv_kernel<0>
                      : sh.rb == 1 ? (const void *)sv_kernel<1>
@@ -545,11 +663,20 @@ hipError_t launch_sv(const FragDev &h, double *dist, hipStream_t s) {
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)n_wg), block(bs);
   switch (sh.rb) {
-    case 0: hipLaunchKernelGGL(sv_kernel<0>, grid, block, lds, s, h, dist, (uint32_t)split); break;
-    case 1: hipLaunchKernelGGL(sv_kernel<1>, grid, block, lds, s, h, dist, (uint32_t)split); break;
-    default: hipLaunchKernelGGL(sv_kernel<2>, grid, block, lds, s, h, dist, (uint32_t)split); break;
+    case 0: hipLaunchKernelGGL(sv_kernel<0>, grid, block, lds, s, h, dist, (uint32_t)split, pass, states); break;
+    case 1: hipLaunchKernelGGL(sv_kernel<1>, grid, block, lds, s, h, dist, (uint32_t)split, pass, states); break;
+    default: hipLaunchKernelGGL(sv_kernel<2>, grid, block, lds, s, h, dist, (uint32_t)split, pass, states); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_sv(const FragDev &h, double *dist, void *states, hipStream_t s) {
+  if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
+  if (sv_inputs(h) == 0) return launch_sv_pass(h, dist, SV_FULL, nullptr, s);
+  if (!states) return hipErrorInvalidValue;
+  hipError_t e = launch_sv_pass(h, dist, SV_EVOLVE, static_cast<C2 *>(states), s);
+  if (e != hipSuccess) return e;
+  return launch_sv_pass(h, dist, SV_COMBINE, static_cast<C2 *>(states), s);
 }
 
 }  // namespace ccut
