@@ -418,26 +418,50 @@ FragDev frag_desc(ccut_plan *p, const Fragment &f, const FragRequest &r, uint32_
   return h;
 }
 
-// Affine sample models of variants [v0, v0 + nv) of a Clifford fragment.
-// With more than one variant, the fragment's gates run once on the identity
-// tableau (the layered bit-sliced row pass) and every variant starts from
-// that shared tableau with its preparations as row substitutions; a single
-// variant replays the gates itself.
-constexpr uint64_t kBaseMinVariants = 1;
-ccut_status tableau_models(ccut_ctx *c, const Fragment &f, const FragDev &h, uint64_t v0, uint64_t nv,
-                           uint64_t *models) {
-  const uint64_t *base = nullptr;
-  if (nv > kBaseMinVariants) {
-    const uint32_t W = row_words(f.m());
-    if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
-    uint64_t *b = aget<uint64_t>(c, (size_t)2 * f.m() * (2 * W + 1));
-    if (!b) return fail(c, CCUT_E_OOM, "device allocation failed");
-    KTimer t(c, CCUT_K_TABLEAU);
-    HIP_TRY(c, launch_rows(h, W, nullptr, b, 2 * f.m(), c->cur));
-    base = b;
+// The measured Paulis of a Clifford fragment before the pull-back through
+// its gates, in measured order: a requested output's Z, a quantum output's X
+// then Z (its basis Pauli is X, Z or i X Z); rows x[W], z[W], sign word.
+std::vector<uint64_t> measured_rows(const FragDev &h, uint32_t W) {
+  const uint32_t RW = 2 * W + 1;
+  std::vector<uint64_t> rows;
+  auto add = [&](bool xpart, uint32_t q) {
+    std::vector<uint64_t> row(RW, 0);
+    row[(xpart ? 0 : W) + (q >> 6)] = 1ull << (q & 63);
+    rows.insert(rows.end(), row.begin(), row.end());
+  };
+  for (uint32_t j = 0; j < h.n_meas; ++j) {
+    const uint32_t q = h.meas[j];
+    bool out = false;
+    for (uint32_t a = 0; a < h.n_axes; ++a) out |= h.axis_side[a] == 0 && h.axis_local[a] == q;
+    if (out) add(true, q);
+    add(false, q);
   }
+  return rows;
+}
+
+// Affine sample models of variants [v0, v0 + nv) of a Clifford fragment:
+// its measured Paulis are carried back through the fragment once (the
+// reversed stream of inverse gates), then one wave per variant eliminates
+// them against the variant's prepared product state (Heisenberg picture).
+ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, uint64_t v0, uint64_t nv,
+                           uint64_t *models) {
+  ccut_ctx *c = p->ctx;
+  const uint32_t W = row_words(f.m());
+  if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
+  std::vector<uint64_t> rows = measured_rows(h, W);
+  const uint32_t n_rows = (uint32_t)(rows.size() / (2 * W + 1));
+  if (rows.empty()) rows.assign(2 * W + 1, 0);  // nothing measured: a valid buffer all the same
+  uint64_t *d_in = (uint64_t *)upload(c, rows.data(), rows.size() * 8);
+  uint64_t *d_out = aget<uint64_t>(c, rows.size());
+  if (!d_in || !d_out) return fail(c, CCUT_E_OOM, "device allocation failed");
+  FragDev hb = h;
+  hb.ops = p->d_back[f.index];
+  hb.n_ops = p->n_back[f.index];
+  hb.layers = p->d_back_layers[f.index];
+  hb.n_layers = p->n_back_layers[f.index];
   KTimer t(c, CCUT_K_TABLEAU);
-  HIP_TRY(c, launch_tableau(h, v0, nv, models, c->cur, base));
+  HIP_TRY(c, launch_rows(hb, W, d_in, d_out, n_rows, c->cur));
+  HIP_TRY(c, launch_affine(h, W, d_out, v0, nv, models, c->cur));
   return CCUT_OK;
 }
 
@@ -467,7 +491,7 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     if (!models) {
       models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
-      ccut_status st2 = tableau_models(c, f, h, 0, nv, models);
+      ccut_status st2 = tableau_models(p, f, h, 0, nv, models);
       if (st2 != CCUT_OK) return st2;
     }
     if (eo->shots_per_variant == 0) {
@@ -1332,7 +1356,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
       uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
-        ccut_status st2 = tableau_models(c, f, h, 0, nv, models);
+        ccut_status st2 = tableau_models(p, f, h, 0, nv, models);
         if (st2 != CCUT_OK) return st2;
       }
       if (eo->shots_per_variant == 0) {
@@ -1427,7 +1451,7 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   const uint64_t shots = eo->shots_per_variant;
   uint64_t *rec = aget<uint64_t>(c, nv * shots);
   if (!models || !rec) return fail(c, CCUT_E_OOM, "device allocation failed");
-  if ((st = tableau_models(c, f, h, v_begin, nv, models)) != CCUT_OK) return st;
+  if ((st = tableau_models(p, f, h, v_begin, nv, models)) != CCUT_OK) return st;
   const uint64_t nquads = (shots + 3) / 4;
   for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
     const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
@@ -1515,17 +1539,19 @@ struct ccut_batch {
   std::vector<BatchItem> items;
   std::vector<std::vector<int64_t>> model_off;  // per plan, per fragment: word offset or -1
   uint64_t model_words_total = 0;
-  // shared base tableaux: word offset per descriptor, and the descriptors
-  // of each row-width class (1, 2, 4, 8 words per half) with its most rows
-  std::vector<uint64_t> base_off;
-  uint64_t base_words_total = 0;
+  // the measured Paulis of every Clifford descriptor (host rows, all
+  // descriptors back to back), their carry-back jobs, the descriptors with
+  // the carry-back stream, and each descriptor's row width
+  std::vector<uint64_t> carry_rows;
+  std::vector<CarryJob> carry_jobs;
+  std::vector<FragDev> back_descs;
+  std::vector<uint32_t> desc_w;
+  uint32_t max_rows = 0;
   // independent per-plan steps run on a pool of streams (default priority),
   // forked from and joined back into the batch stream
   std::vector<hipStream_t> pool;
   hipEvent_t fork_ev = nullptr;
   std::vector<hipEvent_t> join_ev;
-  std::vector<uint32_t> wlist[4];
-  uint32_t wrows[4] = {0, 0, 0, 0};
   // batched sampling and state vectors across plans: (plan, fragment) lists,
   // the non-Clifford descriptors and their state-vector shapes
   struct Ref {
@@ -1534,7 +1560,7 @@ struct ccut_batch {
   std::vector<Ref> samp;  // sampled Clifford fragments (desc indexes descs)
   std::vector<Ref> nc;    // non-Clifford fragments (desc indexes sv_descs)
   std::vector<FragDev> sv_descs;
-  uint32_t max_m = 0, block = 64, grid = 0, use_reg = 1;
+  uint32_t max_m = 0, block = 64, grid = 0, use_reg = 0;
   double tuned_ms = 0.0;
   // device outputs: the copy list of the last run (pinned and on the
   // device), reused while the caller passes the same output addresses, and
@@ -1585,40 +1611,36 @@ struct BatchScope {
   }
 };
 
-ccut_status batch_tableau(ccut_batch *b, FragDev *d_descs, BatchItem *d_items, uint32_t *d_counter,
-                          uint64_t *d_models, uint32_t block, uint32_t grid, uint32_t use_reg,
-                          const uint64_t *d_bases) {
+// The affine sample models of every Clifford variant of the batch: one
+// wave per item (grid-stride over the cost-sorted items) from the carried-back
+// measured Paulis.
+ccut_status batch_models(ccut_batch *b, FragDev *d_descs, const uint32_t *d_w, BatchItem *d_items,
+                         const uint64_t *d_rows, uint64_t *d_models, uint32_t block, uint32_t grid) {
   ccut_ctx *c = b->ctx;
   if (b->items.empty()) return CCUT_OK;
   KTimer t(c, CCUT_K_TABLEAU);
-  HIP_TRY(c, launch_tableau_batch(d_descs, d_items, (uint32_t)b->items.size(), d_counter, d_models, b->max_m, block,
-                                  grid, use_reg, d_bases, c->cur));
+  HIP_TRY(c, launch_affine_batch(d_descs, d_w, d_items, (uint32_t)b->items.size(), d_rows, d_models, block, grid,
+                                 c->cur));
   return CCUT_OK;
 }
 
-// The shared base tableau of every Clifford descriptor: one launch, one
-// workgroup per descriptor, the widest row classes first (they take
-// longest), one row per lane.
-ccut_status batch_bases(ccut_batch *b, FragDev *d_descs, uint64_t **d_bases_out) {
+// Every Clifford descriptor's measured Paulis carried back through its
+// fragment: one launch, one wave per descriptor.
+ccut_status batch_carry(ccut_batch *b, uint64_t **d_rows_out) {
   ccut_ctx *c = b->ctx;
-  *d_bases_out = nullptr;
+  *d_rows_out = nullptr;
   if (b->descs.empty()) return CCUT_OK;
-  uint64_t *d_bases = aget<uint64_t>(c, std::max<uint64_t>(b->base_words_total, 1));
-  uint64_t *d_off = (uint64_t *)upload(c, b->base_off.data(), b->base_off.size() * 8);
-  if (!d_bases || !d_off) return fail(c, CCUT_E_OOM, "device allocation failed");
-  std::vector<uint32_t> list;
-  uint32_t max_rows = 0;
-  for (int k = 3; k >= 0; --k) {  // class k: 2^k words per row half
-    for (uint32_t d : b->wlist[k]) list.push_back(d | (uint32_t)k << 28);
-    max_rows = std::max(max_rows, b->wrows[k]);
-  }
-  uint32_t *d_list = (uint32_t *)upload(c, list.data(), list.size() * 4);
-  if (!d_list) return fail(c, CCUT_E_OOM, "device allocation failed");
+  uint64_t *d_in = (uint64_t *)upload(c, b->carry_rows.data(), std::max<size_t>(b->carry_rows.size(), 1) * 8);
+  uint64_t *d_out = aget<uint64_t>(c, std::max<size_t>(b->carry_rows.size(), 1));
+  FragDev *d_back = (FragDev *)upload(c, b->back_descs.data(), b->back_descs.size() * sizeof(FragDev));
+  CarryJob *d_jobs = (CarryJob *)upload(c, b->carry_jobs.data(), b->carry_jobs.size() * sizeof(CarryJob));
+  if (!d_in || !d_out || !d_back || !d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
     KTimer t(c, CCUT_K_BASE);
-    HIP_TRY(c, launch_base_batch(d_descs, d_list, (uint32_t)list.size(), max_rows, d_off, d_bases, c->cur));
+    HIP_TRY(c, launch_carry_batch(d_back, d_jobs, (uint32_t)b->carry_jobs.size(), b->max_m, b->max_rows, d_in, d_out,
+                                  c->cur));
   }
-  *d_bases_out = d_bases;
+  *d_rows_out = d_out;
   return CCUT_OK;
 }
 
@@ -1634,9 +1656,10 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
                                        std::max<size_t>(b->descs.size(), 1) * sizeof(FragDev));
   BatchItem *d_items = (BatchItem *)upload(c, b->items.empty() ? nullptr : b->items.data(),
                                            std::max<size_t>(b->items.size(), 1) * sizeof(BatchItem));
-  uint32_t *d_counter = aget<uint32_t>(c, 64);
+  uint32_t *d_w = (uint32_t *)upload(c, b->desc_w.empty() ? nullptr : b->desc_w.data(),
+                                     std::max<size_t>(b->desc_w.size(), 1) * sizeof(uint32_t));
   uint64_t *d_models = aget<uint64_t>(c, std::max<uint64_t>(b->model_words_total, 1));
-  if (!d_descs || !d_items || !d_counter || !d_models) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if (!d_descs || !d_items || !d_w || !d_models) return fail(c, CCUT_E_OOM, "device allocation failed");
   // every plan's sampled outcome tables come from one pass of sampling
   // launches (plus one reduction), every non-Clifford fragment's from one
   // state-vector launch per shape; the per-plan steps below start from these
@@ -1728,47 +1751,43 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         if (tune) HIP_TRY(c, hipStreamSynchronize(b->pool[k]));
       }
   }
-  uint64_t *d_bases = nullptr;
-  if ((st = batch_bases(b, d_descs, &d_bases)) != CCUT_OK) return st;
+  uint64_t *d_rows = nullptr;
+  if ((st = batch_carry(b, &d_rows)) != CCUT_OK) return st;
   if (tune && !b->items.empty()) {
-    // autotune the persistent launch: workgroup size x workgroups per CU
+    // autotune the model launch: waves per workgroup x workgroups per
+    // compute unit (a grid-stride loop covers whatever the grid leaves)
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
     double best = 1e30;
-    for (uint32_t block : {64u, 128u, 256u}) {
-      const size_t lds = tableau_batch_lds(b->max_m, block);
-      if (lds > 160 * 1024) continue;
-      for (uint32_t per_cu : {1u, 2u, 4u, 8u}) {
-        if (lds * per_cu > 160 * 1024) continue;
-        for (uint32_t reg : {0u, 1u}) {
-          if (reg && block != 64) continue;
-          const uint32_t grid = (uint32_t)cus * per_cu;
-          // warm once, then time
-          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg, d_bases)) != CCUT_OK) return st;
-          HIP_TRY(c, hipEventRecord(e0, c->cur));
-          if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, block, grid, reg, d_bases)) != CCUT_OK) return st;
-          HIP_TRY(c, hipEventRecord(e1, c->cur));
-          HIP_TRY(c, hipEventSynchronize(e1));
-          float ms = 0.f;
-          HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
-          if (ms < best) {
-            best = ms;
-            b->block = block;
-            b->grid = grid;
-            b->use_reg = reg;
-          }
+    const uint64_t n_items = b->items.size();
+    for (uint32_t block : {64u, 256u, 1024u}) {
+      const uint64_t full = (n_items * 64 + block - 1) / block;
+      for (uint32_t per_cu : {1u, 2u, 4u, 8u, 32u}) {
+        const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(full, (uint64_t)cus * per_cu));
+        // warm once, then time
+        if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, block, grid)) != CCUT_OK) return st;
+        HIP_TRY(c, hipEventRecord(e0, c->cur));
+        if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, block, grid)) != CCUT_OK) return st;
+        HIP_TRY(c, hipEventRecord(e1, c->cur));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          b->block = block;
+          b->grid = grid;
         }
+        if (grid == full) break;
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->tuned_ms = best;
   }
-  if ((st = batch_tableau(b, d_descs, d_items, d_counter, d_models, b->block, b->grid, b->use_reg, d_bases)) != CCUT_OK)
-    return st;
+  if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, b->block, b->grid)) != CCUT_OK) return st;
   if (!b->samp.empty()) {
     // jobs in LDS classes (one launch each, so a launch's workgroups reserve
     // only their class's histogram): up to 8, 20, 38 and 80 KiB
@@ -2086,12 +2105,19 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
       if (di >= (1u << 28)) return fail(c, CCUT_E_UNSUPPORTED, "too many Clifford fragments in one batch");
       b->descs.push_back(h);
       const uint32_t Wb = row_words(f.m());
-      const int wk = Wb == 1 ? 0 : Wb == 2 ? 1 : Wb == 4 ? 2 : 3;
-      b->base_off.push_back(b->base_words_total);
-      b->wlist[wk].push_back(di);
-      b->wrows[wk] = std::max(b->wrows[wk], 2 * f.m());
-      const uint64_t boff = b->base_words_total;
-      b->base_words_total += (uint64_t)2 * f.m() * (2 * Wb + 1);
+      const std::vector<uint64_t> rows = measured_rows(h, Wb);
+      const uint64_t boff = b->carry_rows.size();
+      const uint32_t n_rows = (uint32_t)(rows.size() / (2 * Wb + 1));
+      b->carry_rows.insert(b->carry_rows.end(), rows.begin(), rows.end());
+      b->carry_jobs.push_back({di, Wb, n_rows, 0u, boff, boff});
+      FragDev hb = h;
+      hb.ops = p->d_back[f.index];
+      hb.n_ops = p->n_back[f.index];
+      hb.layers = p->d_back_layers[f.index];
+      hb.n_layers = p->n_back_layers[f.index];
+      b->back_descs.push_back(hb);
+      b->desc_w.push_back(Wb);
+      b->max_rows = std::max(b->max_rows, n_rows);
       offs[f.index] = (int64_t)b->model_words_total;
       if (eo->shots_per_variant) {
         if (nm > (uint32_t)kMaxTableBits)
@@ -2105,10 +2131,10 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     }
     b->model_off.push_back(offs);
   }
-  // longest items first: cost ~ width x gate count
+  // longest items first: the elimination costs ~ measurements^2 x row width
   std::stable_sort(b->items.begin(), b->items.end(), [&](const BatchItem &x, const BatchItem &y) {
     const FragDev &a = b->descs[x.desc], &d = b->descs[y.desc];
-    return (uint64_t)a.m * (a.n_ops + a.n_meas * a.m) > (uint64_t)d.m * (d.n_ops + d.n_meas * d.m);
+    return (uint64_t)a.n_meas * a.n_meas * b->desc_w[x.desc] > (uint64_t)d.n_meas * d.n_meas * b->desc_w[y.desc];
   });
   HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));

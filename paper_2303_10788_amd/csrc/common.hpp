@@ -182,14 +182,14 @@ struct FragDev {
 // Philox bit is 1).  Layout per variant: [x0, randmask, Gcol[0..n_meas)].
 __host__ __device__ inline uint32_t model_words(uint32_t n_meas) { return 2u + n_meas; }
 
-// One unit of the batched tableau launch: variant `variant` of descriptor
+// One unit of the batched model launch: variant `variant` of descriptor
 // `desc`, its model written at word offset `model_off`.
 struct BatchItem {
   uint32_t desc;
   uint32_t pad;
   uint64_t variant;
   uint64_t model_off;
-  uint64_t base_off;  // word offset of the fragment's base tableau (when bases are given)
+  uint64_t base_off;  // word offset of the fragment's carried-back measured rows
 };
 
 // One fragment's sampled outcome tables in a batched launch: variants
@@ -248,16 +248,6 @@ __device__ inline uint32_t find_job(const J *jobs, uint32_t n, uint64_t idx, F s
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
-// Per-variant tableau passes; with `base` (the fragment's evolved identity
-// tableau from launch_rows on its forward stream: 2m rows of
-// row_words(m) words per half) the gate replay is replaced by row
-// substitutions for the preparations.
-hipError_t launch_tableau(const FragDev &frag, uint64_t v0, uint64_t nv, uint64_t *models, hipStream_t s,
-                          const uint64_t *base = nullptr);
-size_t tableau_batch_lds(uint32_t max_m, uint32_t block);
-hipError_t launch_tableau_batch(const FragDev *descs, const BatchItem *items, uint32_t n_items, uint32_t *counter,
-                                uint64_t *models, uint32_t max_m, uint32_t block, uint32_t grid, uint32_t use_reg,
-                                const uint64_t *bases, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
@@ -344,16 +334,28 @@ hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, 
 
 // Exact Pauli-basis tensor of a Clifford fragment without enumerating
 // variants (Heisenberg picture); see k_heis.hip for the row layout.
-// Rows carried through F.ops (F.n_ops words) one per lane: rows_in null
-// starts from the identity tableau (X_r for r < m, then Z_{r-m}); rows are
-// (x[W], z[W], sign) u64 each.
+// Rows carried through F.ops (F.n_ops words), column-sliced (k_heis.hip):
+// rows_in null starts from the identity tableau (X_r for r < m, then
+// Z_{r-m}); rows are (x[W], z[W], sign) u64 each.
 hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_t *out, uint32_t n_rows,
                        hipStream_t s);
-// The base tableaux of many Clifford descriptors in one launch, one
-// workgroup each: list entries are descriptor index | log2(row words) << 28;
-// max_rows = the most rows (2m) of any of them (it sizes the LDS).
-hipError_t launch_base_batch(const FragDev *descs, const uint32_t *list, uint32_t n_list, uint32_t max_rows,
-                             const uint64_t *base_off, uint64_t *base, hipStream_t s);
+// One fragment's carry-back in a batched launch: n_rows rows of width W
+// words per half at in + in_off, carried through the descriptor's stream
+// into out + out_off.
+struct CarryJob {
+  uint32_t desc, W, n_rows, pad_;
+  uint64_t in_off, out_off;
+};
+hipError_t launch_carry_batch(const FragDev *descs, const CarryJob *jobs, uint32_t n_jobs, uint32_t max_m,
+                              uint32_t max_rows, const uint64_t *in, uint64_t *out, hipStream_t s);
+// Affine sample models from carried-back measured Paulis (one wave per
+// variant): rows as built by measured_rows on the host, W words per half.
+hipError_t launch_affine(const FragDev &F, uint32_t W, const uint64_t *rows, uint64_t v0, uint64_t nv,
+                         uint64_t *models, hipStream_t s);
+// desc_w[d]: row width of descriptor d; BatchItem::base_off: word offset of
+// the item's fragment rows; block threads (a multiple of 64), grid blocks.
+hipError_t launch_affine_batch(const FragDev *descs, const uint32_t *desc_w, const BatchItem *items, uint32_t n_items,
+                               const uint64_t *rows, uint64_t *models, uint32_t block, uint32_t grid, hipStream_t s);
 hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32_t n_out, uint32_t r,
                              uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
                              uint32_t n_rows, double *tau, hipStream_t s);

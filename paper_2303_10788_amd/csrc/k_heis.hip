@@ -21,146 +21,11 @@ namespace ccut {
 
 namespace {
 
-// row layout in memory: x[W], z[W], sign word (bit 0)
-template <int W>
-struct PRow {
-  uint64_t x[W], z[W];
-  uint32_t s;
-};
-
-// conjugation P -> G P G^dag of one Hermitian Pauli row by gate `kind`:
-// CX, CZ or a fused one-qubit Clifford (G_C1 parameters in b)
-template <int W>
-__device__ inline void conj_gate(PRow<W> &r, uint32_t kind, uint32_t a, uint32_t b) {
-  const uint32_t wa = a >> 6, sa = a & 63;
-  uint64_t xa_w = r.x[0], za_w = r.z[0];
-#pragma unroll
-  for (int w = 1; w < W; ++w)
-    if (wa == (uint32_t)w) {
-      xa_w = r.x[w];
-      za_w = r.z[w];
-    }
-  const uint32_t xa = (uint32_t)(xa_w >> sa) & 1u, za = (uint32_t)(za_w >> sa) & 1u;
-  if (kind == G_CX || kind == G_CZ) {
-    const uint32_t wb = b >> 6;
-    const uint64_t ma = 1ull << sa, mb = 1ull << (b & 63);
-    uint64_t nxa = xa_w, nza = za_w;
-    uint64_t xb_w = r.x[0], zb_w = r.z[0];
-#pragma unroll
-    for (int w = 1; w < W; ++w)
-      if (wb == (uint32_t)w) {
-        xb_w = r.x[w];
-        zb_w = r.z[w];
-      }
-    const uint32_t xb = (xb_w & mb) != 0, zb = (zb_w & mb) != 0;
-    uint64_t flip_xb = 0, flip_zb = 0;
-    if (kind == G_CX) {
-      r.s ^= xa & zb & (xb ^ za ^ 1u);
-      if (xa) flip_xb = mb;
-      if (zb) nza ^= ma;
-    } else {
-      r.s ^= xa & xb & (za ^ zb);
-      if (xb) nza ^= ma;
-      if (xa) flip_zb = mb;
-    }
-    // write qubit-a word first, then apply the qubit-b flips to the
-    // (possibly same) word
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-      if (wa == (uint32_t)w) {
-        r.x[w] = nxa;
-        r.z[w] = nza;
-      }
-#pragma unroll
-    for (int w = 0; w < W; ++w)
-      if (wb == (uint32_t)w) {
-        r.x[w] ^= flip_xb;
-        r.z[w] ^= flip_zb;
-      }
-    return;
-  }
-  const C1Map g = c1_decode(b);
-  r.s ^= (g.al & xa) ^ (g.be & za) ^ (g.ga & xa & za);
-  const uint32_t nx = (g.m00 & xa) ^ (g.m01 & za), nz = (g.m10 & xa) ^ (g.m11 & za);
-  const uint64_t dx = (uint64_t)(xa ^ nx) << sa, dz = (uint64_t)(za ^ nz) << sa;
-#pragma unroll
-  for (int w = 0; w < W; ++w)
-    if (wa == (uint32_t)w) {
-      r.x[w] ^= dx;
-      r.z[w] ^= dz;
-    }
-}
-
-// One Pauli row per lane carried through an op stream with the tableau
-// rule P -> G P G^dag (rows never interact, so there is no barrier).  Two
-// uses: the Heisenberg carry-back O = U^dag P U (F.ops is the reversed
-// stream of inverse gates built on the host), and the shared tableau pass
-// of a Clifford fragment (F.ops is the forward stream and the rows start as
-// the identity tableau: X_r for r < m, Z_{r-m} after, when `in` is null).
-template <int W, class D>
-__device__ inline void row_pass_body(const D &F, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
-                                     uint32_t n_rows, uint32_t row) {
-  const bool ok = row < n_rows;
-  PRow<W> r;
-  if (in) {
-    const uint64_t *src = in + (size_t)(ok ? row : 0) * (2 * W + 1);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      r.x[w] = ok ? src[w] : 0;
-      r.z[w] = ok ? src[W + w] : 0;
-    }
-    r.s = ok ? (uint32_t)src[2 * W] & 1u : 0u;
-  } else {
-    const uint32_t m = F.m;
-    const uint32_t q = row < m ? row : row - m;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const uint64_t bit = (ok && (q >> 6) == (uint32_t)w) ? (1ull << (q & 63)) : 0ull;
-      r.x[w] = row < m ? bit : 0ull;
-      r.z[w] = row < m ? 0ull : bit;
-    }
-    r.s = 0;
-  }
-  const uint32_t n16 = (F.n_ops + 15) / 16;
-  for (uint32_t g16 = 0; g16 < n16; ++g16) {
-    const Ops16 o = load_ops16(F.ops, g16);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) conj_gate<W>(r, op_kind(o.w[t]), op_q0(o.w[t]), op_q1(o.w[t]));
-  }
-  if (ok) {
-    uint64_t *dst = out + (size_t)row * (2 * W + 1);
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      dst[w] = r.x[w];
-      dst[W + w] = r.z[w];
-    }
-    dst[2 * W] = r.s;
-  }
-}
-
-template <int W>
-__global__ __launch_bounds__(64) void backprop_kernel(const FragDev F, const uint64_t *__restrict__ in,
-                                                      uint64_t *__restrict__ out, uint32_t n_rows) {
-  row_pass_body<W>(F, in, out, n_rows, blockIdx.x * 64 + threadIdx.x);
-}
-
-// Shared tableau passes of many fragments at once (one row width class):
-// grid (row blocks, fragments in the class); fragment list[y] writes its 2m
-// rows at base + base_off[list[y]].
+// Shared pass of many fragments' rows: the descriptor array in the global
+// address space, read through a reference.
 typedef __attribute__((address_space(1))) const FragDev g_FragDevH;
-template <int W>
-__global__ __launch_bounds__(64) void base_batch_kernel(const FragDev *__restrict__ descs,
-                                                        const uint32_t *__restrict__ list,
-                                                        const uint64_t *__restrict__ base_off,
-                                                        uint64_t *__restrict__ base) {
-  const uint32_t d = list[blockIdx.y];
-  const g_FragDevH &F = ((const g_FragDevH *)descs)[d];
-  const uint32_t n_rows = 2 * F.m;
-  if (blockIdx.x * 64 >= n_rows) return;
-  row_pass_body<W>(F, nullptr, base + base_off[d], n_rows, blockIdx.x * 64 + threadIdx.x);
-}
 
-// The same row pass bit-sliced: column q of the x (z) parts holds bit q of
+// The row pass bit-sliced: column q of the x (z) parts holds bit q of
 // 64 rows per word, so a gate reads and writes only its qubits' column
 // words and applies its rule to 64 rows with a few 64-bit operations.  The
 // stream comes in layers of ops on disjoint qubits.  Lane l works on row
@@ -348,19 +213,15 @@ __global__ __launch_bounds__(64) void rows_sliced_kernel(const FragDev F, uint32
   rows_sliced_body(F, W, in ? in + r0 * RS : nullptr, out + r0 * RS, min(kSlicedRows, n_rows - r0), cols);
 }
 
-// Shared tableau passes of many fragments: block y runs fragment list[y]
-// (2m rows, row width W = row_words(m)) into base + base_off[list[y]].
-__global__ __launch_bounds__(64) void rows_sliced_batch_kernel(const FragDev *__restrict__ descs,
-                                                                const uint32_t *__restrict__ list,
-                                                                const uint64_t *__restrict__ base_off,
-                                                                uint64_t *__restrict__ base) {
+// Carry-back of many fragments' rows: block x carries job x's n_rows input
+// rows (row width W words per half) through its descriptor's stream.
+__global__ __launch_bounds__(64) void carry_batch_kernel(const FragDev *__restrict__ descs,
+                                                          const CarryJob *__restrict__ jobs,
+                                                          const uint64_t *__restrict__ in, uint64_t *__restrict__ out) {
   extern __shared__ uint64_t cols[];
-  // list entry: descriptor index in the low 28 bits, log2 of the row width
-  // in words above
-  const uint32_t e = list[blockIdx.x];
-  const uint32_t d = e & 0x0FFFFFFFu, W = 1u << (e >> 28);
-  const g_FragDevH &F = ((const g_FragDevH *)descs)[d];
-  rows_sliced_body(F, W, nullptr, base + base_off[d], 2 * F.m, cols);
+  const CarryJob &J = jobs[blockIdx.x];
+  const g_FragDevH &F = ((const g_FragDevH *)descs)[J.desc];
+  rows_sliced_body(F, J.W, in + J.in_off, out + J.out_off, J.n_rows, cols);
 }
 
 struct HeisArgs {
@@ -547,16 +408,16 @@ hipError_t launch_rows(const FragDev &F, uint32_t W, const uint64_t *in, uint64_
   return hipGetLastError();
 }
 
-hipError_t launch_base_batch(const FragDev *descs, const uint32_t *list, uint32_t n_list, uint32_t max_rows,
-                             const uint64_t *base_off, uint64_t *base, hipStream_t s) {
-  if (n_list == 0) return hipSuccess;
+hipError_t launch_carry_batch(const FragDev *descs, const CarryJob *jobs, uint32_t n_jobs, uint32_t max_m,
+                              uint32_t max_rows, const uint64_t *in, uint64_t *out, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
   if (max_rows > kSlicedRows) return hipErrorInvalidValue;
-  const size_t lds = rows_sliced_lds(max_rows / 2, max_rows);
+  const size_t lds = rows_sliced_lds(max_m, max_rows);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)rows_sliced_batch_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void *)carry_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(rows_sliced_batch_kernel, dim3(n_list), dim3(64), lds, s, descs, list, base_off, base);
+  hipLaunchKernelGGL(carry_batch_kernel, dim3(n_jobs), dim3(64), lds, s, descs, jobs, in, out);
   return hipGetLastError();
 }
 

@@ -473,4 +473,18 @@ hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv, 
   return hipSuccess;
 }
 
+namespace {
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t value) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<uint64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, p, n, value);
+  return hipGetLastError();
+}
+
 }  // namespace ccut
