@@ -150,7 +150,11 @@ typedef struct {
  *    expectations vanish).  The support is found on the device and its size
  *    read back, so the call synchronizes and is never captured in a call
  *    graph.  With the plain fp64 sum the result equals the dense sum bit for
- *    bit; the matrix-core paths differ from it by rounding only.
+ *    bit; the matrix-core paths differ from it by rounding only.  (When the
+ *    fragment with the most requested outputs has only quantum inputs and
+ *    its tensor would come from variant tables, its tables stand in for the
+ *    tensor with the input coefficients moved onto the upstream fragments'
+ *    tensors; that fragment's columns are then indexed by preparations.)
  *  CCUT_FLAG_SETTLE (ccut_zexpect in sampled mode only): each sampled
  *    Clifford variant's string expectation, which is -1, 0 or +1 on a
  *    stabilizer state, is settled from its shots: 0 if both parities

@@ -1118,6 +1118,47 @@ namespace {
 // Enqueue the whole marginal evaluation of one plan (no final copy, no
 // sync); res receives 2^nq doubles.  pre_models[f], if given, holds the
 // already computed sample models of Clifford fragment f.
+// The fragment whose variant tables stand in for its Pauli-basis tensor:
+// the fragment with the most requested outputs (the contraction's column
+// side, the largest tensor) when every cut axis of it is a quantum input
+// and its tensor would come from variant tables.  Its preparation
+// coefficients then move across the sum over each cut's Pauli onto the
+// upstream fragment (fold_jobs), and its own transform is skipped (the
+// sparse contraction then reads its support over these folded terms: a
+// skipped term is still an exact zero).  -1: none.
+int fold_target(const PlanData &pd, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq) {
+  int best = -1;
+  size_t best_bits = 0;
+  for (const Fragment &f : pd.frags) {
+    const size_t bits = marginal_request(f, qubits, nq).req_pos.size();
+    if (best < 0 || bits > best_bits) {
+      best = (int)f.index;
+      best_bits = bits;
+    }
+  }
+  if (best < 0) return -1;
+  const Fragment &g = pd.frags[best];
+  if (g.axes.empty() || use_heisenberg(g, eo, best_bits)) return -1;
+  for (const Axis &a : g.axes)
+    if (a.side != 1) return -1;
+  return best;
+}
+
+// The fold jobs of the other fragments: every axis on a cut of fragment g.
+void fold_jobs(const PlanData &pd, int g, const RecombArgs &args, std::vector<FoldJob> &jobs) {
+  if (g < 0) return;
+  std::vector<char> gcut(pd.k, 0);
+  for (const Axis &a : pd.frags[g].axes) gcut[a.cut] = 1;
+  for (const Fragment &f : pd.frags) {
+    if ((int)f.index == g) continue;
+    uint32_t mask = 0;
+    for (size_t j = 0; j < f.axes.size(); ++j)
+      if (gcut[f.axes[j].cut]) mask |= 1u << j;
+    const RecombFrag &rf = args.f[f.index];
+    if (mask) jobs.push_back({const_cast<double *>(rf.T), rf.rows, rf.n_axes, mask});
+  }
+}
+
 ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
                              double *res, const std::vector<uint64_t *> *pre_models,
                              const std::vector<double *> *pre_dist = nullptr) {
@@ -1128,6 +1169,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
   RecombArgs args{};
   args.n_frags = (uint32_t)pd.frags.size();
   args.k = pd.k;
+  const int g = fold_target(pd, eo, qubits, nq);
   for (const Fragment &f : pd.frags) {
     route(c, f);
     FragRequest r = marginal_request(f, qubits, nq);
@@ -1138,7 +1180,10 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
       uint64_t *pm = pre_models ? (*pre_models)[f.index] : nullptr;
       dist = pre_dist ? (*pre_dist)[f.index] : nullptr;
       if (!dist && (st = variant_dists(p, eo, f, r, &dist, pm)) != CCUT_OK) return st;
-      if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+      if ((int)f.index == g)
+        T = dist;  // tables [preparations][outcomes]: the tensor's layout, preparation digits for Paulis
+      else if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK)
+        return st;
     }
     RecombFrag &rf = args.f[f.index];
     rf.T = T;
@@ -1150,6 +1195,14 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
     if ((st = cancelled(c)) != CCUT_OK) return st;
   }
   if ((st = join(c)) != CCUT_OK) return st;
+  std::vector<FoldJob> fj;
+  fold_jobs(pd, g, args, fj);
+  if (!fj.empty()) {
+    FoldJob *d_fj = (FoldJob *)upload(c, fj.data(), fj.size() * sizeof(FoldJob));
+    if (!d_fj) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_TRANSFORM);
+    HIP_TRY(c, launch_fold(d_fj, (uint32_t)fj.size(), c->cur));
+  }
   return recombine(c, args, nq, eo->precision == CCUT_FP32_MFMA_FP64SUM, res, (eo->flags & CCUT_FLAG_SPARSE) != 0);
 }
 }  // namespace
@@ -1891,6 +1944,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   for (size_t k = 0; k < P; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
   const bool fp32 = b->eo.precision == CCUT_FP32_MFMA_FP64SUM;
   std::vector<TileJob> tjobs;
+  std::vector<FoldJob> fjobs;
   std::vector<RecombArgs> rargs(np);
   std::vector<uint8_t> kind(np);  // 0 plain (batched), 1 plain (own launch), 2 MFMA
   for (size_t i = 0; i < np; ++i) {
@@ -1910,6 +1964,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     args.n_frags = (uint32_t)pd.frags.size();
     args.k = pd.k;
     c->stream = c->cur = P ? b->pool[i % P] : b->stream;
+    const int g = fold_target(pd, &eo, qubits, nq);
     for (const Fragment &f : pd.frags) {
       FragRequest r = marginal_request(f, qubits, nq);
       double *T = nullptr;
@@ -1921,7 +1976,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         st = dist ? CCUT_OK : variant_dists(p, &eo, f, r, &dist, pm);
         const uint64_t xsize = 1ull << r.meas.size();
         TileJob J;
-        if (st == CCUT_OK && !f.axes.empty() && tile_job(f, r, dist, xsize, nullptr, J)) {
+        if (st == CCUT_OK && (int)f.index == g) {
+          T = dist;  // tables [preparations][outcomes] stand in for the tensor (fold_target)
+        } else if (st == CCUT_OK && !f.axes.empty() && tile_job(f, r, dist, xsize, nullptr, J)) {
           J.out = T = aget<double>(c, J.x_out << (2 * f.axes.size()));
           if (!T) st = fail(c, CCUT_E_OOM, "device allocation failed");
           tjobs.push_back(J);
@@ -1940,6 +1997,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     }
     c->stream = c->cur = b->stream;
     if (st != CCUT_OK) return st;
+    fold_jobs(pd, g, args, fjobs);
     // the contraction recombine() would take
     const uint64_t K = 1ull << (2 * pd.k);
     kind[i] = (!fp32 && (K << nq) <= (1ull << 20)) ? (args.n_frags <= 8 ? 0 : 1) : 2;
@@ -1958,6 +2016,12 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (!d_t) return fail(c, CCUT_E_OOM, "device allocation failed");
     KTimer t(c, CCUT_K_TRANSFORM);
     HIP_TRY(c, launch_transform_tiled(d_t, (uint32_t)tjobs.size(), wg, c->cur));
+  }
+  if (!fjobs.empty()) {
+    FoldJob *d_fj = (FoldJob *)upload(c, fjobs.data(), fjobs.size() * sizeof(FoldJob));
+    if (!d_fj) return fail(c, CCUT_E_OOM, "device allocation failed");
+    KTimer t(c, CCUT_K_TRANSFORM);
+    HIP_TRY(c, launch_fold(d_fj, (uint32_t)fjobs.size(), c->cur));
   }
   // contractions: the plain ones' arguments in one upload, the MFMA ones'
   // operand descriptions in another

@@ -360,6 +360,15 @@ hipError_t launch_heisenberg(const FragDev &F, uint32_t W, uint32_t n_in, uint32
                              uint32_t n_str, const uint64_t *cin_mask, const uint64_t *rows_in, uint64_t *rows_out,
                              uint32_t n_rows, double *tau, hipStream_t s);
 
+// A fragment tensor to be rewritten along cut axes `mask` (bit j = axis j)
+// into the preparation basis of the fragments downstream (launch_fold).
+struct FoldJob {
+  double *T;
+  uint64_t rows;
+  uint32_t n_axes, mask;
+};
+hipError_t launch_fold(const FoldJob *d_jobs, uint32_t n_jobs, hipStream_t s);
+
 struct RecombFrag {
   const double *T;          // T_f[p_f][row], row count `rows`
   uint32_t n_axes;

@@ -546,6 +546,41 @@ __global__ void zrecombine_final_kernel(const double *__restrict__ partial, uint
 
 }  // namespace
 
+namespace {
+// A fragment tensor T[p_f][row] rewritten in place along the marked cut
+// axes from the Pauli basis to the preparation basis (0, 1, +, +i) of the
+// fragment downstream of that cut: new[s] = sum_P c(P, s) T[P] with the
+// input coefficients c (I = p0 + p1, Z = p0 - p1, X = 2p+ - p0 - p1,
+// Y = 2p+i - p0 - p1), i.e. s=0: I - X - Y + Z, s=1: I - X - Y - Z,
+// s=+: 2X, s=+i: 2Y.  Moving the input coefficients across the sum over
+// the cut's Pauli lets the downstream fragment's variant tables stand in
+// for its Pauli-basis tensor.  One workgroup per tensor, axis by axis.
+__global__ __launch_bounds__(1024) void fold_kernel(const FoldJob *__restrict__ jobs) {
+  const FoldJob J = jobs[blockIdx.x];
+  const uint64_t fibers = (J.rows << (2 * J.n_axes)) / 4;
+  for (uint32_t j = 0; j < J.n_axes; ++j) {
+    if (!((J.mask >> j) & 1u)) continue;
+    const uint64_t stride = J.rows << (2 * j);  // distance between the P digits of axis j
+    for (uint64_t t = threadIdx.x; t < fibers; t += blockDim.x) {
+      const uint64_t lo = t % stride, hi = t / stride;
+      double *q = J.T + hi * 4 * stride + lo;
+      const double vI = q[0], vX = q[stride], vY = q[2 * stride], vZ = q[3 * stride];
+      q[0] = ((vI - vX) - vY) + vZ;
+      q[stride] = ((vI - vX) - vY) - vZ;
+      q[2 * stride] = 2.0 * vX;
+      q[3 * stride] = 2.0 * vY;
+    }
+    __syncthreads();  // the next axis reads what this one wrote
+  }
+}
+}  // namespace
+
+hipError_t launch_fold(const FoldJob *d_jobs, uint32_t n_jobs, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(fold_kernel, dim3(n_jobs), dim3(1024), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_transform_pass(const double *in, double *out, uint64_t outer, uint64_t R, uint64_t Xin,
                                  uint64_t lo, int mode, hipStream_t s) {
   const uint64_t Xout = mode == 0 ? Xin : Xin / 2;
