@@ -2067,7 +2067,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.splits = contraction_splits(h, skinny);
       J.tiles = gemm_tiles(h, skinny);
       J.k_per_split = gemm_k_per_split(h, J.splits, skinny);
-      const bool direct = skinny && J.splits == 1;  // the skinny kernel writes the outputs itself
+      const bool direct = J.splits == 1;  // one split: the kernel writes the outputs itself
       J.partial = direct ? nullptr : aget<double>(c, (size_t)J.splits * h.M * h.N);
       if (!direct && !J.partial) return fail(c, CCUT_E_OOM, "device allocation failed");
       J.out = b->res[i];

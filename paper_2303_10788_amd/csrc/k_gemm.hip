@@ -52,11 +52,26 @@ __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSi
   return v;
 }
 
+__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n);
+__device__ inline uint64_t side_bits(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t idx);
+
+// A side that is one fragment whose axes are the cuts in order, with K
+// running over every term: its operand is the fragment tensor itself
+// (T[P][row], P-major), read with plain strided loads instead of
+// side_value.  Returns the tensor (rows in `rows`), or null.
+__device__ inline const double *direct_side(const GemmArgs *__restrict__ G, const GemmSide &S, uint64_t &rows) {
+  if (S.n != 1 || G->terms || S.shift[0] != 0) return nullptr;
+  const uint32_t f = S.frag[0];
+  if (!G->ident[f]) return nullptr;
+  rows = G->f[f].rows;
+  return G->f[f].T;
+}
+
 // One 64 x 64 output tile (tile index `tile`, M tiles fastest) over the
 // K range of split `split`, into partial[split][M][N].
 template <bool F32>
 __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
-                                 uint32_t tile, uint32_t split) {
+                                 uint32_t tile, uint32_t split, double *__restrict__ out = nullptr) {
   typedef typename std::conditional<F32, float, double>::type TS;
   __shared__ TS As[KC][MT + 1];
   __shared__ TS Bs[KC][NT + 1];
@@ -82,6 +97,16 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
 #pragma unroll
       for (int g = 0; g < 4; ++g) acc64[i][j][g] = 0.0;
     }
+  uint64_t rowsA = 0, rowsB = 0;
+  const double *TA = direct_side(G, G->L, rowsA), *TB = direct_side(G, G->R, rowsB);
+  // output index bits of the tile's rows and columns (written with the
+  // outputs directly when there is one split)
+  __shared__ uint64_t s_obits[MT + NT];
+  if (out) {
+    if (tid < MT) s_obits[tid] = tm * MT + tid < M ? side_bits(G, G->L, tm * MT + tid) : 0;
+    else if (tid < MT + NT) s_obits[tid] = tn * NT + tid - MT < N ? side_bits(G, G->R, tn * NT + tid - MT) : 0;
+    __syncthreads();
+  }
   for (uint64_t kb = k0; kb < k1; kb += KC) {
     for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
       const uint32_t kk = e / MT, mm = e % MT;
@@ -89,7 +114,7 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       const uint64_t j = kb + kk;
       double a = 0.0;
       if (m < M && j < k1) {
-        a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+        a = TA ? TA[j * rowsA + m] : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
         if (G->tscale) a *= G->tscale[j];
         if (G->square) a *= a;
       }
@@ -100,7 +125,8 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       const uint32_t kk = e / NT, nn = e % NT;
       const uint32_t n = tn * NT + nn;
       const uint64_t j = kb + kk;
-      double b = (n < N && j < k1) ? side_value(G, G->R, n, G->terms ? G->terms[j] : j) : 0.0;
+      double b = 0.0;
+      if (n < N && j < k1) b = TB ? TB[j * rowsB + n] : side_value(G, G->R, n, G->terms ? G->terms[j] : j);
       if (G->square) b *= b;
       Bs[kk][nn] = (TS)b;
       if constexpr (F32) Bl[kk][nn] = (float)(b - (double)(float)b);
@@ -159,14 +185,18 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
         const uint32_t r = F32 ? 4 * (lane / 16) + g : lane / 16 + 4 * g;
         const uint32_t m = tm * MT + wm + 16 * i + r;
         const uint32_t n = tn * NT + wn + 16 * j + lane % 16;
-        if (m < M && n < N) dst[(uint64_t)m * N + n] = F32 ? acc64[i][j][g] : accd[i][j][g];
+        if (m >= M || n >= N) continue;
+        const double v = F32 ? acc64[i][j][g] : accd[i][j][g];
+        // one split: the output itself (as the reduction would write it)
+        if (out) out[s_obits[m - tm * MT] | s_obits[MT + n - tn * NT]] = ldexp(0.0 + v, -(int)G->k);
+        else dst[(uint64_t)m * N + n] = v;
       }
 }
 
 template <bool F32>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
-                                                            double *__restrict__ partial) {
-  gemm_body<F32>(G, k_per_split, partial, blockIdx.x, blockIdx.y);
+                                                            double *__restrict__ partial, double *__restrict__ out) {
+  gemm_body<F32>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
 }
 
 // Many contractions in one launch: workgroup x runs tile (x - wg0) mod
@@ -176,15 +206,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob 
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];
   const uint64_t local = blockIdx.x - J.wg0;
-  gemm_body<F32>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles));
+  gemm_body<F32>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
+                 J.splits == 1 ? J.out : nullptr);
 }
 
 // Skinny contraction (M <= SK_M rows, fp64): one output column n per
 // thread with all M rows in registers; the row-side values of a K chunk are
 // staged in LDS.  partial[split][m][n] = sum over the split's terms, in
 // ascending order, of a(m, P) * b(n, P) (each product rounded, then added).
-__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n);
-
 constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
 // One instantiation per row count MC (1, 2, ..., 32): the accumulators of
 // one kernel stay in registers only when the kernel holds exactly its own.
@@ -203,6 +232,13 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
   const double *Tn = G->f[rf].T + n;
   const uint64_t rows = G->f[rf].rows;
   const bool square = G->square != 0;
+  uint64_t rowsA = 0;
+  const double *TA = direct_side(G, G->L, rowsA);
+  __shared__ uint64_t s_mbits[MC];  // output index bits of the rows
+  if (out) {
+    if (tid < MC) s_mbits[tid] = side_bits(G, G->L, tid);
+    __syncthreads();
+  }
   double acc[MC];
 #pragma unroll
   for (uint32_t m = 0; m < MC; ++m) acc[m] = 0.0;
@@ -216,7 +252,7 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
     for (uint32_t e = tid; e < kn * MC; e += SK_N) {
       const uint32_t kk = e / MC, m = e % MC;
       const uint64_t j = kb + kk;
-      double a = side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+      double a = TA ? TA[j * rowsA + m] : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
       if (G->tscale) a *= G->tscale[j];
       if (square) a *= a;
       As[kk][m] = a;
@@ -237,8 +273,9 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
   }
   if (n >= N) return;
   if (out) {
+    const uint64_t nb = side_bits(G, G->R, n);
 #pragma unroll
-    for (uint32_t m = 0; m < MC; ++m) out[out_index(G, m, n)] = ldexp(0.0 + acc[m], -(int)G->k);
+    for (uint32_t m = 0; m < MC; ++m) out[s_mbits[m] | nb] = ldexp(0.0 + acc[m], -(int)G->k);
     return;
   }
   double *dst = partial + (uint64_t)split * MC * N;
@@ -262,20 +299,21 @@ __global__ __launch_bounds__(SK_N) void skinny_batch_kernel(const GemmJob *__res
                   J.splits == 1 ? J.out : nullptr);
 }
 
-// out[b(m, n)] = 2^-k sum_split partial[split][m][n], splits in order
-__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n) {
+// The output index bits of row (or column) idx of side S: each of its
+// fragments' requested bits at its user position.
+__device__ inline uint64_t side_bits(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t idx) {
   uint64_t b = 0;
-  for (uint32_t t = 0; t < G->L.n; ++t) {
-    const RecombFrag &F = G->f[G->L.frag[t]];
-    const uint32_t r = (m >> G->L.shift[t]) & ((1u << G->L.bits[t]) - 1u);
-    for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
-  }
-  for (uint32_t t = 0; t < G->R.n; ++t) {
-    const RecombFrag &F = G->f[G->R.frag[t]];
-    const uint32_t r = (n >> G->R.shift[t]) & ((1u << G->R.bits[t]) - 1u);
+  for (uint32_t t = 0; t < S.n; ++t) {
+    const RecombFrag &F = G->f[S.frag[t]];
+    const uint32_t r = (idx >> S.shift[t]) & ((1u << S.bits[t]) - 1u);
     for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
   }
   return b;
+}
+
+// out[b(m, n)] = 2^-k sum_split partial[split][m][n], splits in order
+__device__ inline uint64_t out_index(const GemmArgs *__restrict__ G, uint32_t m, uint32_t n) {
+  return side_bits(G, G->L, m) | side_bits(G, G->R, n);
 }
 
 __device__ inline void gemm_reduce_body(const GemmArgs *__restrict__ G, const double *__restrict__ partial,
@@ -300,11 +338,14 @@ __global__ void gemm_reduce_batch_kernel(const GemmJob *__restrict__ jobs, uint3
 
 }  // namespace
 
+// K splits: about 1024 workgroups, each split at least 8 K chunks (256
+// terms), so short contractions take one split and write their outputs
+// directly (no partial sums, no reduction pass).
 uint32_t gemm_splits(const GemmArgs &h) {
   const uint64_t tiles = (uint64_t)((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
   const uint64_t kchunks = (h.K + KC - 1) / KC;
   uint64_t s = std::max<uint64_t>(1, 1024 / std::max<uint64_t>(tiles, 1));
-  s = std::min<uint64_t>(s, kchunks);
+  s = std::min<uint64_t>(s, kchunks / 8);
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, 65535));
 }
 
@@ -379,12 +420,12 @@ hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool
     if (splits == 1) return hipGetLastError();
   } else if (fp32)
     hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
-                       partial);
+                       partial, splits == 1 ? out : nullptr);
   else
     hipLaunchKernelGGL((gemm_kernel<false>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
-                       partial);
+                       partial, splits == 1 ? out : nullptr);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || splits == 1) return e;
   const uint64_t MN = (uint64_t)h.M * h.N;
   hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, d_args, partial,
                      splits, out);

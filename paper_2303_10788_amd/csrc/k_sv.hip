@@ -586,9 +586,13 @@ uint32_t sv_inputs(const FragDev &h) {
   return n_in;
 }
 
+// A fragment with cut axes runs in two passes: the gate program once per
+// computational-basis input (the only run without inputs), then one
+// workgroup per preparation and basis combination from the stored states
+// (no workgroup repeats the program for a basis combination).  Fragments
+// without axes run in one pass.
 size_t sv_states_bytes(const FragDev &h) {
-  const uint32_t n_in = sv_inputs(h);
-  return n_in ? ((size_t)1 << (n_in + h.m)) * sizeof(C2) : 0;
+  return h.n_axes ? ((size_t)1 << (sv_inputs(h) + h.m)) * sizeof(C2) : 0;
 }
 
 void sv_pass_shape(const FragDev &h, uint32_t pass, uint64_t &n_wg, uint32_t &block, size_t &lds, bool &split) {
@@ -603,9 +607,14 @@ void sv_pass_shape(const FragDev &h, uint32_t pass, uint64_t &n_wg, uint32_t &bl
   }
   sv_launch_shape(h, n_wg, block, lds, split);
   if (pass == SV_COMBINE) {
-    // no gate program: one state buffer, and a second for the rotated copy
-    const bool copy = h.n_axes != sv_inputs(h) && !split;
-    lds = (size_t(copy ? 2 : 1) << h.m) * sizeof(C2);
+    // no gate program: one workgroup per preparation and basis combination,
+    // one state buffer each
+    const uint32_t n_in = sv_inputs(h), n_out = h.n_axes - n_in;
+    uint64_t n_bc = 1;
+    for (uint32_t j = 0; j < n_out; ++j) n_bc *= 3;
+    split = n_out != 0;
+    n_wg = (1ull << (2 * n_in)) * n_bc;
+    lds = ((size_t)1 << h.m) * sizeof(C2);
   }
 }
 
@@ -672,7 +681,7 @@ static hipError_t launch_sv_pass(const FragDev &h, double *dist, uint32_t pass, 
 
 hipError_t launch_sv(const FragDev &h, double *dist, void *states, hipStream_t s) {
   if (h.m == 0 || h.m > (uint32_t)kMaxNcQubits || h.n_meas > h.m) return hipErrorInvalidValue;
-  if (sv_inputs(h) == 0) return launch_sv_pass(h, dist, SV_FULL, nullptr, s);
+  if (h.n_axes == 0) return launch_sv_pass(h, dist, SV_FULL, nullptr, s);
   if (!states) return hipErrorInvalidValue;
   hipError_t e = launch_sv_pass(h, dist, SV_EVOLVE, static_cast<C2 *>(states), s);
   if (e != hipSuccess) return e;
