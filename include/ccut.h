@@ -121,7 +121,16 @@ typedef struct {
   uint32_t max_cuts;      /* 0 = default 12: exhaustive recombination sums 4^k terms */
 } ccut_opts;
 
-enum { CCUT_FP64 = 0, CCUT_FP32_MFMA_FP64SUM = 1 };
+/* Precision of the recombination (Sec. V-C's contraction):
+ *  CCUT_FP64: fp64 products and sums (fp64 matrix cores or fp64 VALU);
+ *  CCUT_FP32_MFMA_FP64SUM: operands rounded to fp32, fp32 matrix-core
+ *    products summed in fp32 over 8 cut terms, those partial sums added in
+ *    fp64 (an output's error is about 2^-23 times the summed magnitude of its
+ *    terms);
+ *  CCUT_FP32X3_MFMA_FP64SUM: as above with every operand split into fp32
+ *    hi + lo parts and three products (hi hi + hi lo + lo hi) per term: near
+ *    fp64 products, still fp32 sums over 8 terms. */
+enum { CCUT_FP64 = 0, CCUT_FP32_MFMA_FP64SUM = 1, CCUT_FP32X3_MFMA_FP64SUM = 2 };
 
 /* How exact-mode Clifford fragments are evaluated (sampled mode always
  * evaluates every variant on the tableau):
@@ -136,8 +145,8 @@ enum { CCUT_METHOD_AUTO = 0, CCUT_METHOD_VARIANTS = 1, CCUT_METHOD_HEISENBERG = 
 
 typedef struct {
   uint64_t seed;              /* Philox key */
-  uint64_t shots_per_variant; /* 0 = exact ("strong simulation", Sec. V-C) Clifford tables */
-  int32_t precision;          /* CCUT_FP64, or CCUT_FP32_MFMA_FP64SUM for the recombination */
+  uint64_t shots_per_variant; /* 0 = exact ("strong simulation", Sec. V-C) Clifford tables; < 2^32 */
+  int32_t precision;          /* CCUT_FP64, CCUT_FP32_MFMA_FP64SUM or CCUT_FP32X3_MFMA_FP64SUM */
   uint32_t circuit;           /* circuit index in variant ids (batch position) */
   uint32_t method;            /* CCUT_METHOD_*, exact mode only */
   uint32_t flags;             /* CCUT_FLAG_* (0: none) */

@@ -461,11 +461,9 @@ def _parity_expectation(state, meas, mk, settle=False):
     return float(np.sum(1 - 2 * par)) / data.shape[0]
 
 
-def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=0, circuit=0, settle=False):
-    """t_f[z][p_f] = sum over the contributing variants of the coefficient
-    times the variant's expectation of (-1)^(z_f.b + sum of the quantum-output
-    bits of the axes with P != I)."""
-    a = len(frag.axes)
+def zstring_local_masks(frag: Fragment, meas, masks: Sequence[int]) -> List[int]:
+    """Each mask restricted to the fragment's circuit outputs, as a bitmask
+    over measured positions."""
     pos = {l: j for j, l in enumerate(meas)}
     zloc = []
     for mk in masks:
@@ -474,10 +472,32 @@ def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=
             if (mk >> q) & 1:
                 bits |= 1 << pos[l]
         zloc.append(bits)
+    return zloc
+
+
+def zstring_variant_expectations(frag: Fragment, meas, masks: Sequence[int], v: int, extras: Sequence[int], *,
+                                 shots=0, seed=0, circuit=0, settle=False):
+    """{extra: [E_v[(-1)^(z_f.b + extra.b)] for each mask z]} for variant v
+    (extra: a bitmask of quantum-output positions)."""
+    state = _variant_state(frag, v, meas, shots=shots, seed=seed, circuit=circuit)
+    zloc = zstring_local_masks(frag, meas, masks)
+    return {e: [_parity_expectation(state, meas, z | e, settle) for z in zloc] for e in extras}
+
+
+def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=0, circuit=0, settle=False,
+                   expect=None):
+    """t_f[z][p_f] = sum over the contributing variants of the coefficient
+    times the variant's expectation of (-1)^(z_f.b + sum of the quantum-output
+    bits of the axes with P != I).  expect: optional precomputed
+    {(v, extra): expectations} (zstring_variant_expectations) used in place
+    of evaluating variants here."""
+    a = len(frag.axes)
+    pos = {l: j for j, l in enumerate(meas)}
+    zloc = zstring_local_masks(frag, meas, masks)
     # all (variant, extra-mask) pairs that can be needed
     out_bit = {j: 1 << pos[ax.local] for j, ax in enumerate(frag.axes) if ax.side == 0}
     states = {}
-    cache = {}
+    cache = {} if expect is None else expect
 
     def E(v, extra):
         key = (v, extra)
@@ -508,15 +528,17 @@ def zstring_tensor(frag: Fragment, meas, masks: Sequence[int], *, shots=0, seed=
 
 
 def zexpect(n: int, ops, cuts, masks: Sequence[int], *, shots: int = 0, seed: int = 0,
-            circuit: int = 0, return_parts: bool = False, settle: bool = False):
+            circuit: int = 0, return_parts: bool = False, settle: bool = False, expect=None):
     """<Z_z> for every mask z (bit q = qubit q):
-    2^-k sum_P prod_f t_f[z; P|f]."""
+    2^-k sum_P prod_f t_f[z; P|f].  expect: optional per-fragment
+    precomputed variant expectations (see zstring_tensor)."""
     frags = fragment_circuit(n, ops, cuts)
     k = len(cuts)
     tens = []
     for f in frags:
         meas = zstring_measured_set(f, masks)
-        tens.append(zstring_tensor(f, meas, masks, shots=shots, seed=seed, circuit=circuit, settle=settle))
+        tens.append(zstring_tensor(f, meas, masks, shots=shots, seed=seed, circuit=circuit, settle=settle,
+                                   expect=None if expect is None else expect.get(f.index)))
     out = np.zeros(len(masks))
     for P in range(4 ** k):
         term = np.ones(len(masks))

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libccut.so")
 GATES = {"H": 0, "S": 1, "SDG": 2, "X": 3, "Y": 4, "Z": 5, "CX": 6, "CZ": 7, "T": 8, "TDG": 9, "RZ": 10}
 CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
 CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
-CCUT_FP64, CCUT_FP32_MFMA_FP64SUM = 0, 1
+CCUT_FP64, CCUT_FP32_MFMA_FP64SUM, CCUT_FP32X3_MFMA_FP64SUM = 0, 1, 2
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
 CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE = 1, 2
 KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",

@@ -282,13 +282,17 @@ hipError_t pin_begin(ccut_ctx *c);
 ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
   if (!p || !eo) return CCUT_E_INVALID;
   ccut_ctx *c = p->ctx;
-  if (c->device < 0) return fail(c, CCUT_E_DEVICE, "host-only context: evaluation needs a device");
-  if (eo->precision != CCUT_FP64 && eo->precision != CCUT_FP32_MFMA_FP64SUM)
+  if (eo->precision != CCUT_FP64 && eo->precision != CCUT_FP32_MFMA_FP64SUM &&
+      eo->precision != CCUT_FP32X3_MFMA_FP64SUM)
     return fail(c, CCUT_E_INVALID, "unknown precision mode");
-  HIP_TRY(c, hipSetDevice(c->device));
   if (eo->method > CCUT_METHOD_HEISENBERG) return fail(c, CCUT_E_INVALID, "unknown evaluation method");
   if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE))
     return fail(c, CCUT_E_INVALID, "unknown evaluation flag");
+  // shot counters and histogram counts are 32-bit per variant
+  if (eo->shots_per_variant > 0xFFFFFFFFull)
+    return fail(c, CCUT_E_INVALID, "shots_per_variant must be below 2^32");
+  if (c->device < 0) return fail(c, CCUT_E_DEVICE, "host-only context: evaluation needs a device");
+  HIP_TRY(c, hipSetDevice(c->device));
   c->cancel.store(0);
   c->arena.reset();
   c->staged.clear();
@@ -759,6 +763,7 @@ void make_gemm_args(const RecombArgs &args, GemmArgs &g) {
   g = GemmArgs{};
   g.k = args.k;
   g.K = 1ull << (2 * args.k);
+  g.lo_parts = args.lo_parts;
   uint32_t rf = 0;
   for (uint32_t f = 1; f < args.n_frags; ++f)
     if (args.f[f].n_req > args.f[rf].n_req) rf = f;
@@ -839,11 +844,20 @@ ccut_status recombine_sparse(ccut_ctx *c, const RecombArgs &args, uint32_t nq, b
 // Contract the fragment tensors into out[2^nq].  fp64 with at most 2^20
 // term-outputs: the plain ascending sum; otherwise the K-split MFMA contraction
 // (fp32 products with fp64 across K-chunks, or fp64 MFMA).
+// The plain fp64 sum (per output, every term's product, ascending) for
+// small contractions of more than two fragments; two fragments always take
+// the matrix paths (the skinny kernel's ascending sum of products is the
+// plain sum's arithmetic, and it streams the column tensor).
+bool plain_contraction(const RecombArgs &args, uint32_t nq, bool fp32) {
+  const uint64_t K = 1ull << (2 * args.k);
+  return !fp32 && args.n_frags > 2 && (K << nq) <= (1ull << 20);
+}
+
 ccut_status recombine(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res,
                       bool sparse = false) {
   if (sparse) return recombine_sparse(c, args, nq, fp32, res);
   const uint64_t K = 1ull << (2 * args.k);
-  if (!fp32 && (K << nq) <= (1ull << 20)) {
+  if (plain_contraction(args, nq, fp32)) {
     RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
     if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
     KTimer t(c, CCUT_K_RECOMBINE);
@@ -1169,6 +1183,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
   RecombArgs args{};
   args.n_frags = (uint32_t)pd.frags.size();
   args.k = pd.k;
+  args.lo_parts = eo->precision == CCUT_FP32X3_MFMA_FP64SUM;
   const int g = fold_target(pd, eo, qubits, nq);
   for (const Fragment &f : pd.frags) {
     route(c, f);
@@ -1203,7 +1218,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
     KTimer t(c, CCUT_K_TRANSFORM);
     HIP_TRY(c, launch_fold(d_fj, (uint32_t)fj.size(), c->cur));
   }
-  return recombine(c, args, nq, eo->precision == CCUT_FP32_MFMA_FP64SUM, res, (eo->flags & CCUT_FLAG_SPARSE) != 0);
+  return recombine(c, args, nq, eo->precision != CCUT_FP64, res, (eo->flags & CCUT_FLAG_SPARSE) != 0);
 }
 }  // namespace
 
@@ -1342,6 +1357,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   RecombArgs args{};
   args.n_frags = (uint32_t)pd.frags.size();
   args.k = pd.k;
+  args.lo_parts = eo->precision == CCUT_FP32X3_MFMA_FP64SUM;
   for (const Fragment &f : pd.frags) {
     route(c, f);
     FragRequest r = zstring_request(f, anymask);
@@ -1448,7 +1464,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   if (!dargs || !res || !zpart) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
     KTimer t(c, CCUT_K_ZRECOMBINE);
-    HIP_TRY(c, launch_zrecombine(dargs, args.n_frags, pd.k, n_strings, eo->precision == CCUT_FP32_MFMA_FP64SUM,
+    HIP_TRY(c, launch_zrecombine(dargs, args.n_frags, pd.k, n_strings, eo->precision != CCUT_FP64,
                                  zpart, zsplits, res, c->cur));
   }
   return on_device ? CCUT_OK : finish_out(c, res, out, n_strings, on_device);
@@ -1942,7 +1958,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   const size_t P = b->pool.size(), np = b->plans.size();
   HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
   for (size_t k = 0; k < P; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
-  const bool fp32 = b->eo.precision == CCUT_FP32_MFMA_FP64SUM;
+  const bool fp32 = b->eo.precision != CCUT_FP64;
   std::vector<TileJob> tjobs;
   std::vector<FoldJob> fjobs;
   std::vector<RecombArgs> rargs(np);
@@ -1963,6 +1979,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     args = RecombArgs{};
     args.n_frags = (uint32_t)pd.frags.size();
     args.k = pd.k;
+    args.lo_parts = b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM;
     c->stream = c->cur = P ? b->pool[i % P] : b->stream;
     const int g = fold_target(pd, &eo, qubits, nq);
     for (const Fragment &f : pd.frags) {
@@ -2000,7 +2017,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     fold_jobs(pd, g, args, fjobs);
     // the contraction recombine() would take
     const uint64_t K = 1ull << (2 * pd.k);
-    kind[i] = (!fp32 && (K << nq) <= (1ull << 20)) ? (args.n_frags <= 8 ? 0 : 1) : 2;
+    kind[i] = plain_contraction(args, nq, fp32) ? (args.n_frags <= 8 ? 0 : 1) : 2;
   }
   for (size_t k = 0; k < P; ++k) {
     HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));

@@ -381,6 +381,7 @@ constexpr int kMaxFrags = 64;
 struct RecombArgs {
   uint32_t n_frags;
   uint32_t k;
+  uint32_t lo_parts;  // fp32 modes: 1 = hi/lo split operands (three products), 0 = fp32 operands
   RecombFrag f[kMaxFrags];
 };
 hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uint32_t nq, double *out,
@@ -440,6 +441,7 @@ struct GemmArgs {
   const uint64_t *terms;
   const double *tscale;
   uint32_t square;  // 1: every operand value squared (second moment of the sampled estimate)
+  uint32_t lo_parts;  // fp32 mode: 1 = operands split hi + lo, three MFMA products; 0 = one fp32 product
   GemmSide L, R;
   uint32_t ident[kMaxFrags];  // 1 if the fragment's axes are cuts 0..k-1 in order (p_f(P) = P)
   RecombFrag f[kMaxFrags];

@@ -422,9 +422,10 @@ __global__ __launch_bounds__(kRcChunk) void recombine_batch_kernel(const RcJob *
 }
 
 // <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s].  fp64: products and sum in
-// fp64, P ascending.  fp32: every factor split into fp32 parts t = hi + lo,
-// the product taken in fp32 to first order (prod hi + sum_f lo_f prod_{g!=f}
-// hi_g), summed in fp32 over 8 consecutive terms, those sums added in fp64.
+// fp64, P ascending.  fp32: factors rounded to fp32 and multiplied in fp32
+// (with lo_parts: every factor split into fp32 parts t = hi + lo and the
+// product taken to first order, prod hi + sum_f lo_f prod_{g!=f} hi_g),
+// summed in fp32 over 8 consecutive terms, those sums added in fp64.
 template <bool F32>
 __global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_strings, uint64_t per_split,
                                   double *__restrict__ partial) {
@@ -445,7 +446,7 @@ __global__ void zrecombine_kernel(const RecombArgs *__restrict__ A, uint32_t n_s
       for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
       const double t = F.T[(uint64_t)p * F.rows + s];
       if (F32) {
-        const float th = (float)t, tl = (float)(t - (double)th);
+        const float th = (float)t, tl = A->lo_parts ? (float)(t - (double)th) : 0.f;
         corr = corr * th + hi * tl;
         hi *= th;
       } else {
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *
   const uint32_t tid = threadIdx.x;
   const uint32_t s = blockIdx.x * 64 + tid;
   const bool live = s < n_strings;
-  const uint32_t nf = A->n_frags, k = A->k;
+  const uint32_t nf = A->n_frags, k = A->k, lo_parts = A->lo_parts;
   if (tid < nf) s_T[tid] = A->f[tid].T;
   const uint64_t nterms = 1ull << (2 * k);
   const uint64_t P0 = (uint64_t)blockIdx.y * per_split;
@@ -509,7 +510,7 @@ __global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *
         if (f >= nf) continue;
         const double v = s_T[f][s_off[f][t] + s];
         if (F32) {
-          const float th = (float)v, tl = (float)(v - (double)th);
+          const float th = (float)v, tl = lo_parts ? (float)(v - (double)th) : 0.f;
           corr = corr * th + hi * tl;
           hi *= th;
         } else {

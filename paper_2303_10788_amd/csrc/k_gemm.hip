@@ -7,12 +7,18 @@
 // materialised: for 10 cuts the row operand alone would be 2^10 x 4^10).
 //
 // Precision modes:
-//  - FP32 MFMA with FP64 across K tiles: each fp64 operand is split into
-//    fp32 parts a = a_hi + a_lo; every group of 4 terms is multiplied by
-//    three v_mfma_f32_16x16x4_f32 (a_hi b_hi + a_hi b_lo + a_lo b_hi, the
-//    dropped a_lo b_lo is 2^-48 relative), summed in fp32 over 8 terms, and
-//    those partial sums are added into fp64 accumulators (the signed sum over
-//    cut terms cancels heavily, so it is kept in fp64);
+//  - FP32 MFMA with FP64 across K tiles (the default fp32 mode): operands
+//    rounded to fp32, one v_mfma_f32_16x16x4_f32 per 4 terms, products summed
+//    in fp32 over 8 terms, those partial sums added into fp64 accumulators
+//    (the signed sum over cut terms cancels heavily, so it is kept in fp64).
+//    Each partial sum carries about 2^-23 relative error from the operand
+//    rounding and the fp32 products and sums, so an output's error is about
+//    2^-23 times the sum of its terms' magnitudes;
+//  - the same with hi/lo split operands (a = a_hi + a_lo in fp32, three
+//    MFMAs a_hi b_hi + a_hi b_lo + a_lo b_hi per 4 terms): the products are
+//    then near fp64, but the fp32 sums over 8 terms still round at 2^-24
+//    relative of the partial sum, so this gains a small constant factor at
+//    three times the matrix-core work;
 //  - FP64 MFMA (v_mfma_f64_16x16x4_f64) end to end (reference path).
 // Split-K partials are summed in fp64 in split order by a second kernel.
 // With a term list the K index runs over sampled terms P_j, each row-side
@@ -99,6 +105,7 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
     }
   uint64_t rowsA = 0, rowsB = 0;
   const double *TA = direct_side(G, G->L, rowsA), *TB = direct_side(G, G->R, rowsB);
+  const bool lo = F32 && G->lo_parts != 0;
   // output index bits of the tile's rows and columns (written with the
   // outputs directly when there is one split)
   __shared__ uint64_t s_obits[MT + NT];
@@ -119,7 +126,8 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
         if (G->square) a *= a;
       }
       As[kk][mm] = (TS)a;
-      if constexpr (F32) Al[kk][mm] = (float)(a - (double)(float)a);
+      if constexpr (F32)
+        if (lo) Al[kk][mm] = (float)(a - (double)(float)a);
     }
     for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
       const uint32_t kk = e / NT, nn = e % NT;
@@ -129,7 +137,8 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       if (n < N && j < k1) b = TB ? TB[j * rowsB + n] : side_value(G, G->R, n, G->terms ? G->terms[j] : j);
       if (G->square) b *= b;
       Bs[kk][nn] = (TS)b;
-      if constexpr (F32) Bl[kk][nn] = (float)(b - (double)(float)b);
+      if constexpr (F32)
+        if (lo) Bl[kk][nn] = (float)(b - (double)(float)b);
     }
     __syncthreads();
 #pragma unroll
@@ -140,19 +149,25 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lane / 16][wn + 16 * j + lane % 16];
       if constexpr (F32) {
-        float al[2], bl[2];
+        if (lo) {
+          float al[2], bl[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) al[i] = Al[kk + lane / 16][wm + 16 * i + lane % 16];
+          for (int i = 0; i < 2; ++i) al[i] = Al[kk + lane / 16][wm + 16 * i + lane % 16];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bl[j] = Bl[kk + lane / 16][wn + 16 * j + lane % 16];
+          for (int j = 0; j < 2; ++j) bl[j] = Bl[kk + lane / 16][wn + 16 * j + lane % 16];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], bl[j], acc32[i][j], 0, 0, 0);
+              acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[i], (float)b[j], acc32[i][j], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], bl[j], acc32[i][j], 0, 0, 0);
-            acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[i], (float)b[j], acc32[i][j], 0, 0, 0);
+          for (int j = 0; j < 2; ++j)
             acc32[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[i], (float)b[j], acc32[i][j], 0, 0, 0);
-          }
         if (kk & 4) {  // fold every 8 terms into fp64
 #pragma unroll
           for (int i = 0; i < 2; ++i)

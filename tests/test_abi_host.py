@@ -107,6 +107,20 @@ def test_host_only_context_refuses_evaluation():
     assert e.value.status == cc.CCUT_E_DEVICE
 
 
+def test_shot_count_limit():
+    """Shot counters and histogram counts are 32-bit per variant: 2^32 shots
+    or more is refused before anything reaches a device."""
+    ctx = _host_ctx()
+    w = W.tiny()
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    with pytest.raises(cc.CcutError) as e:
+        plan.marginal(w.qubits, shots=1 << 32)
+    assert e.value.status == cc.CCUT_E_INVALID and "2^32" in str(e.value)
+    with pytest.raises(cc.CcutError) as e:
+        plan.marginal(w.qubits, shots=(1 << 32) - 1)  # valid: only the host-only context refuses
+    assert e.value.status == cc.CCUT_E_DEVICE
+
+
 def test_plan_outlives_destroyed_context():
     """Destroying a context while a plan made from it is alive defers the
     context's release to the plan's destruction."""

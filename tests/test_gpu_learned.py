@@ -115,6 +115,31 @@ def test_mlp_first_adam_step(ctx):
     assert np.allclose(np.abs(delta[big]), lr, rtol=2e-2)
 
 
+def test_mlp_adam_steps_two_and_three(ctx):
+    """Adam at t = 1, 2, 3 on the GPU against the oracle's Adam applied to
+    the same gradients (the network's own, read back before each step):
+    the moment updates and the bias corrections of later steps."""
+    import torch
+    F, H, B = 64, 128, 256
+    params = _random_net(F, H, 13)
+    X, y = _inputs(B, F, 14)
+    net = cc.Mlp(ctx, F, H)
+    net.set_params(cc.mlp_pack(params))
+    Xd, yd = _dev(X, torch.bfloat16), _dev(y, torch.float32)
+    lr = 1e-3
+    state = O.adam_state(cc.mlp_unpack(cc.mlp_pack(params).astype(np.float64), F, H))
+    for t in range(1, 4):
+        before = net.get_params().astype(np.float64)
+        g, _ = net.gradients(Xd, yd)
+        net.train(Xd, yd, batch=B, steps=1, lr=lr)
+        got = net.get_params().astype(np.float64)
+        exp_struct, state = O.adam_step(cc.mlp_unpack(before, F, H), cc.mlp_unpack(g.astype(np.float64), F, H),
+                                        state, lr)
+        exp = np.concatenate([np.ravel(a) for W_, b_ in exp_struct for a in (W_, b_)])
+        err = np.abs(got - exp)
+        assert np.all(err <= 1e-3 * lr + 2e-7 * np.abs(exp)), (t, float(err.max()))
+
+
 def test_mlp_training_reduces_loss(ctx):
     import torch
     F, H, n = 64, 256, 4096

@@ -57,6 +57,46 @@ def test_adam_matches_definition_on_quadratic():
     assert np.isclose(new[0][0][0, 0], 3.0 - 0.1, atol=1e-7)
 
 
+def test_adam_constant_gradient_moves_lr_every_step():
+    """Bias correction at every step: with a constant gradient g the
+    corrected moments are exactly g and g^2 at every t, so every step (not
+    only the first) moves each coordinate by lr g / (|g| + eps).  A missing or
+    wrong bias correction, or a moment update without its (1 - beta)
+    factor, moves by a different amount from t = 2 on."""
+    p0 = [(np.array([[3.0, -1.0]]), np.array([0.5]))]
+    g = [(np.array([[6.0, -0.25]]), np.array([1e-3]))]
+    st = mlp.adam_state(p0)
+    params = p0
+    lr = 0.01
+    for t in range(1, 6):
+        prev = params
+        params, st = mlp.adam_step(params, g, st, lr)
+        assert st[2] == t
+        for (W1, b1), (W0, b0), (gW, gb) in zip(params, prev, g):
+            assert np.allclose(W1 - W0, -lr * gW / (np.abs(gW) + 1e-8), rtol=1e-12, atol=0)
+            assert np.allclose(b1 - b0, -lr * gb / (np.abs(gb) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients g then -g: after two steps the first moment is
+    (1 - b1)(b1 g - g) = -g (1 - b1)^2, corrected -g (1 - b1) / (1 + b1); the
+    second moment (1 - b2)(b2 + 1) g^2, corrected g^2; so the second step moves
+    by +lr (1 - b1) / (1 + b1) sign(g) (= lr / 19 for b1 = 0.9).  At t = 3
+    with g again: m_hat = g (b1^2 - b1 + 1)(1 - b1) / (1 - b1^3), v_hat = g^2."""
+    g = 4.0
+    lr = 0.1
+    p = [(np.array([[1.0]]), np.array([0.0]))]
+    st = mlp.adam_state(p)
+    p1, st = mlp.adam_step(p, [(np.array([[g]]), np.array([0.0]))], st, lr)
+    p2, st = mlp.adam_step(p1, [(np.array([[-g]]), np.array([0.0]))], st, lr)
+    step2 = p2[0][0][0, 0] - p1[0][0][0, 0]
+    assert np.isclose(step2, lr / 19.0 * g / (g + 1e-8), rtol=1e-12)
+    p3, st = mlp.adam_step(p2, [(np.array([[g]]), np.array([0.0]))], st, lr)
+    step3 = p3[0][0][0, 0] - p2[0][0][0, 0]
+    mhat = g * (0.81 - 0.9 + 1.0) * 0.1 / (1 - 0.729)
+    assert np.isclose(step3, -lr * mhat / (g + 1e-8), rtol=1e-12)
+
+
 def test_proposal_and_cdf():
     rng = np.random.default_rng(5)
     logits = rng.normal(size=1000) * 3
