@@ -470,8 +470,11 @@ ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, ui
 }
 
 // Per-variant outcome distributions dist[v][x] over the measured set.
+// cnt_out (sampled Clifford fragments, fewer than 2^16 shots): the tables
+// as 16-bit shot counts into *cnt_out instead (*dist_out null).
 ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment &f,
-                          const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr) {
+                          const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr,
+                          uint16_t **cnt_out = nullptr) {
   ccut_ctx *c = p->ctx;
   const uint32_t nm = (uint32_t)r.meas.size();
   const uint64_t nv = f.n_variants;
@@ -482,8 +485,11 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
   if ((nv << nm) > (uint64_t(1) << 34))
     return fail(c, CCUT_E_UNSUPPORTED, "variant tables exceed 2^34 entries");
   const FragDev h = frag_desc(p, f, r, eo->circuit);
-  double *dist = aget<double>(c, nv << nm);
-  if (!dist) return fail(c, CCUT_E_OOM, "device allocation failed");
+  const bool want16 = cnt_out && f.clifford && eo->shots_per_variant > 0 && eo->shots_per_variant <= 0xFFFFull;
+  uint16_t *cnt16 = want16 ? aget<uint16_t>(c, nv << nm) : nullptr;
+  double *dist = want16 ? nullptr : aget<double>(c, nv << nm);
+  if (!dist && !cnt16) return fail(c, CCUT_E_OOM, "device allocation failed");
+  if (cnt_out) *cnt_out = cnt16;
   if (!f.clifford) {
     const size_t sb = sv_states_bytes(h);
     double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
@@ -530,8 +536,8 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
         }
         {
           KTimer t(c, CCUT_K_HIST_REDUCE);
-          HIP_TRY(c, launch_hist_reduce(partial, cnv, lds ? nblk : 1, bins, shots, dist + (v0 << nm),
-                                        c->cur));
+          HIP_TRY(c, launch_hist_reduce(partial, cnv, lds ? nblk : 1, bins, shots, dist ? dist + (v0 << nm) : nullptr,
+                                        c->cur, cnt16 ? cnt16 + (v0 << nm) : nullptr));
         }
       }
     }
@@ -1158,6 +1164,16 @@ int fold_target(const PlanData &pd, const ccut_eval_opts *eo, const uint32_t *qu
   return best;
 }
 
+// Whether the fold target's tensor may stay 16-bit shot counts: sampled
+// (fewer than 2^16 shots), read by the matrix contraction paths (not the
+// plain sum, not the sparse support search).
+bool counts_contraction(const PlanData &pd, const ccut_eval_opts *eo, uint32_t nq) {
+  if (eo->shots_per_variant == 0 || eo->shots_per_variant > 0xFFFFull || (eo->flags & CCUT_FLAG_SPARSE)) return false;
+  const uint64_t K = 1ull << (2 * pd.k);
+  const bool fp32 = eo->precision != CCUT_FP64;
+  return !(!fp32 && pd.frags.size() > 2 && (K << nq) <= (1ull << 20));
+}
+
 // The fold jobs of the other fragments: every axis on a cut of fragment g.
 void fold_jobs(const PlanData &pd, int g, const RecombArgs &args, std::vector<FoldJob> &jobs) {
   if (g < 0) return;
@@ -1185,6 +1201,7 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
   args.k = pd.k;
   args.lo_parts = eo->precision == CCUT_FP32X3_MFMA_FP64SUM;
   const int g = fold_target(pd, eo, qubits, nq);
+  const bool counts_ok = counts_contraction(pd, eo, nq);
   for (const Fragment &f : pd.frags) {
     route(c, f);
     FragRequest r = marginal_request(f, qubits, nq);
@@ -1194,11 +1211,17 @@ ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint3
     } else {
       uint64_t *pm = pre_models ? (*pre_models)[f.index] : nullptr;
       dist = pre_dist ? (*pre_dist)[f.index] : nullptr;
-      if (!dist && (st = variant_dists(p, eo, f, r, &dist, pm)) != CCUT_OK) return st;
+      uint16_t *cnt = nullptr;
+      const bool counts = (int)f.index == g && counts_ok;
+      if (!dist && (st = variant_dists(p, eo, f, r, &dist, pm, counts ? &cnt : nullptr)) != CCUT_OK) return st;
       if ((int)f.index == g)
-        T = dist;  // tables [preparations][outcomes]: the tensor's layout, preparation digits for Paulis
+        T = cnt ? reinterpret_cast<double *>(cnt) : dist;  // tables [preparations][outcomes]: the tensor's layout
       else if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK)
         return st;
+      if (cnt) {
+        args.f[f.index].cnt16 = 1;
+        args.f[f.index].shots = (double)eo->shots_per_variant;
+      }
     }
     RecombFrag &rf = args.f[f.index];
     rf.T = T;
@@ -1737,7 +1760,11 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   // process's streams onto 4 hardware queues, the batch stream holds one),
   // and join before the per-plan steps.
   std::vector<std::vector<double *>> pre_dist(b->plans.size());
-  for (size_t i = 0; i < b->plans.size(); ++i) pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+  std::vector<std::vector<uint16_t *>> pre_cnt(b->plans.size());  // sampled tables kept as 16-bit counts
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    pre_dist[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+    pre_cnt[i].assign(b->plans[i]->pd.frags.size(), nullptr);
+  }
   const size_t n_sv_streams = std::min<size_t>(b->pool.size(), 3);
   std::vector<uint8_t> sv_used(n_sv_streams, 0);
   if (!b->nc.empty()) {
@@ -1928,9 +1955,34 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         J.partial = zeroed + zo;
         zo += J.nv * bins;
       }
-      J.dist = aget<double>(c, J.nv * bins);
-      if ((!J.partial && J.nblk != 1) || !J.dist) return fail(c, CCUT_E_OOM, "device allocation failed");
-      pre_dist[b->samp[order[q]].plan][b->samp[order[q]].frag] = J.dist;
+      // 16-bit shot counts where the consumer reads them: the fold target of
+      // a matrix-path contraction, or a fragment that goes through the tiled
+      // transform
+      const auto &ref = b->samp[order[q]];
+      bool c16 = false;
+      if (J.shots <= 0xFFFFull) {
+        ccut_plan *pp = b->plans[ref.plan];
+        const uint32_t *qb = b->qubits[ref.plan].data();
+        const uint32_t nqb = (uint32_t)b->qubits[ref.plan].size();
+        const Fragment &fr = pp->pd.frags[ref.frag];
+        ccut_eval_opts eo_i = b->eo;
+        if (fold_target(pp->pd, &eo_i, qb, nqb) == (int)ref.frag) {
+          c16 = counts_contraction(pp->pd, &eo_i, nqb);
+        } else {
+          const FragRequest rr = marginal_request(fr, qb, nqb);
+          TileJob probe;
+          c16 = !fr.axes.empty() && tile_job(fr, rr, nullptr, 1ull << rr.meas.size(), nullptr, probe);
+        }
+      }
+      if (c16) {
+        J.cnt16 = aget<uint16_t>(c, J.nv * bins);
+        J.dist = nullptr;
+      } else {
+        J.dist = aget<double>(c, J.nv * bins);
+      }
+      if ((!J.partial && J.nblk != 1) || (!J.dist && !J.cnt16)) return fail(c, CCUT_E_OOM, "device allocation failed");
+      pre_dist[ref.plan][ref.frag] = J.dist;
+      pre_cnt[ref.plan][ref.frag] = J.cnt16;
     }
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
     if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
@@ -1989,13 +2041,21 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         st = heis_tensor(p, f, r, eo.circuit, nullptr, &T);
       } else {
         double *dist = pre_dist[i][f.index];
+        uint16_t *cnt = pre_cnt[i][f.index];
         uint64_t *pm = b->model_off[i][f.index] >= 0 ? d_models + b->model_off[i][f.index] : nullptr;
-        st = dist ? CCUT_OK : variant_dists(p, &eo, f, r, &dist, pm);
+        st = (dist || cnt) ? CCUT_OK : variant_dists(p, &eo, f, r, &dist, pm);
         const uint64_t xsize = 1ull << r.meas.size();
         TileJob J;
         if (st == CCUT_OK && (int)f.index == g) {
-          T = dist;  // tables [preparations][outcomes] stand in for the tensor (fold_target)
+          // tables [preparations][outcomes] stand in for the tensor (fold_target)
+          T = cnt ? reinterpret_cast<double *>(cnt) : dist;
+          if (cnt) {
+            args.f[f.index].cnt16 = 1;
+            args.f[f.index].shots = (double)eo.shots_per_variant;
+          }
         } else if (st == CCUT_OK && !f.axes.empty() && tile_job(f, r, dist, xsize, nullptr, J)) {
+          J.in16 = cnt;
+          J.shots = (double)eo.shots_per_variant;
           J.out = T = aget<double>(c, J.x_out << (2 * f.axes.size()));
           if (!T) st = fail(c, CCUT_E_OOM, "device allocation failed");
           tjobs.push_back(J);

@@ -201,6 +201,7 @@ struct SampleJob {
   const uint64_t *models;
   uint32_t *partial;
   double *dist;
+  uint16_t *cnt16;  // when set: the tables as 16-bit shot counts (shots < 2^16) instead of dist
   uint64_t shots, seed, vid0, nv;
   uint64_t wg0, rb0;
   uint32_t n_meas, nblk, qpt;
@@ -253,7 +254,7 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
                               uint32_t quads_per_thread, uint64_t *records, hipStream_t s);
 hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nblk_x, uint32_t bins,
-                              uint64_t shots, double *dist, hipStream_t s);
+                              uint64_t shots, double *dist, hipStream_t s, uint16_t *cnt16 = nullptr);
 hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,
                                hipStream_t s);
 // prog: the fragment's state-vector program (words + 8 doubles per word)
@@ -317,6 +318,8 @@ constexpr uint32_t kTileElems = 4096, kTileMaxT = 8;
 struct TileJob {
   const double *in;
   double *out;
+  const uint16_t *in16;  // when set: the variant data as 16-bit shot counts, value = count / shots
+  double shots;
   uint64_t x_in, x_out;
   uint64_t wg0;                 // first workgroup of the job in a batched launch
   uint32_t tiles;               // x_out >> t
@@ -371,6 +374,9 @@ hipError_t launch_fold(const FoldJob *d_jobs, uint32_t n_jobs, hipStream_t s);
 
 struct RecombFrag {
   const double *T;          // T_f[p_f][row], row count `rows`
+  uint32_t cnt16;           // 1: T holds 16-bit shot counts, the value is count / shots
+  uint32_t pad_;
+  double shots;
   uint32_t n_axes;
   uint32_t rows;
   uint32_t n_req;

@@ -196,7 +196,8 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
       const uint32_t v = e >> lb, l = e & (XL - 1u);
       uint64_t x = base | (l & lowmask);
       for (uint32_t h = 0; h < nh; ++h) x |= (uint64_t)((l >> (thr + h)) & 1u) << J.hpos[h];
-      vals[i] = J.in[(uint64_t)v * J.x_in + x];
+      const uint64_t idx = (uint64_t)v * J.x_in + x;
+      vals[i] = J.in16 ? (double)J.in16[idx] / J.shots : J.in[idx];
     }
   }
 #pragma unroll

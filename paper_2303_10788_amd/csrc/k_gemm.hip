@@ -48,12 +48,18 @@ __device__ inline uint64_t frag_p(const GemmArgs *__restrict__ G, uint32_t f, ui
   return p;
 }
 
+// A fragment tensor entry: fp64, or a 16-bit shot count divided by the
+// shots (the value the fp64 table would hold).
+__device__ inline double tval(const RecombFrag &F, uint64_t i) {
+  return F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[i] / F.shots : F.T[i];
+}
+
 __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t row, uint64_t P) {
   double v = 1.0;
   for (uint32_t i = 0; i < S.n; ++i) {
     const uint32_t f = S.frag[i];
     const uint32_t r = (row >> S.shift[i]) & ((1u << S.bits[i]) - 1u);
-    v *= G->f[f].T[frag_p(G, f, P) * G->f[f].rows + r];
+    v *= tval(G->f[f], frag_p(G, f, P) * G->f[f].rows + r);
   }
   return v;
 }
@@ -64,13 +70,12 @@ __device__ inline uint64_t side_bits(const GemmArgs *__restrict__ G, const GemmS
 // A side that is one fragment whose axes are the cuts in order, with K
 // running over every term: its operand is the fragment tensor itself
 // (T[P][row], P-major), read with plain strided loads instead of
-// side_value.  Returns the tensor (rows in `rows`), or null.
-__device__ inline const double *direct_side(const GemmArgs *__restrict__ G, const GemmSide &S, uint64_t &rows) {
+// side_value.  Returns the fragment, or null.
+__device__ inline const RecombFrag *direct_side(const GemmArgs *__restrict__ G, const GemmSide &S) {
   if (S.n != 1 || G->terms || S.shift[0] != 0) return nullptr;
   const uint32_t f = S.frag[0];
   if (!G->ident[f]) return nullptr;
-  rows = G->f[f].rows;
-  return G->f[f].T;
+  return &G->f[f];
 }
 
 // One 64 x 64 output tile (tile index `tile`, M tiles fastest) over the
@@ -103,8 +108,8 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
 #pragma unroll
       for (int g = 0; g < 4; ++g) acc64[i][j][g] = 0.0;
     }
-  uint64_t rowsA = 0, rowsB = 0;
-  const double *TA = direct_side(G, G->L, rowsA), *TB = direct_side(G, G->R, rowsB);
+  const RecombFrag *FA = direct_side(G, G->L), *FB = direct_side(G, G->R);
+  const uint64_t rowsA = FA ? FA->rows : 0, rowsB = FB ? FB->rows : 0;
   const bool lo = F32 && G->lo_parts != 0;
   // output index bits of the tile's rows and columns (written with the
   // outputs directly when there is one split)
@@ -121,7 +126,7 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       const uint64_t j = kb + kk;
       double a = 0.0;
       if (m < M && j < k1) {
-        a = TA ? TA[j * rowsA + m] : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+        a = FA ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
         if (G->tscale) a *= G->tscale[j];
         if (G->square) a *= a;
       }
@@ -134,7 +139,7 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       const uint32_t n = tn * NT + nn;
       const uint64_t j = kb + kk;
       double b = 0.0;
-      if (n < N && j < k1) b = TB ? TB[j * rowsB + n] : side_value(G, G->R, n, G->terms ? G->terms[j] : j);
+      if (n < N && j < k1) b = FB ? tval(*FB, j * rowsB + n) : side_value(G, G->R, n, G->terms ? G->terms[j] : j);
       if (G->square) b *= b;
       Bs[kk][nn] = (TS)b;
       if constexpr (F32)
@@ -245,10 +250,13 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
   // the column side is one fragment whose rows are the column index
   const uint32_t rf = G->R.frag[0];
   const double *Tn = G->f[rf].T + n;
+  const uint16_t *Cn = reinterpret_cast<const uint16_t *>(G->f[rf].T) + n;
+  const bool cnt16 = G->f[rf].cnt16 != 0;
+  const double shots = G->f[rf].shots;
   const uint64_t rows = G->f[rf].rows;
   const bool square = G->square != 0;
-  uint64_t rowsA = 0;
-  const double *TA = direct_side(G, G->L, rowsA);
+  const RecombFrag *FA = direct_side(G, G->L);
+  const uint64_t rowsA = FA ? FA->rows : 0;
   __shared__ uint64_t s_mbits[MC];  // output index bits of the rows
   if (out) {
     if (tid < MC) s_mbits[tid] = side_bits(G, G->L, tid);
@@ -267,7 +275,7 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
     for (uint32_t e = tid; e < kn * MC; e += SK_N) {
       const uint32_t kk = e / MC, m = e % MC;
       const uint64_t j = kb + kk;
-      double a = TA ? TA[j * rowsA + m] : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+      double a = FA ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
       if (G->tscale) a *= G->tscale[j];
       if (square) a *= a;
       As[kk][m] = a;
@@ -278,12 +286,22 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
     // row values would crowd the registers): the kernel streams the column
     // tensor once
     constexpr uint32_t kUnroll = MC <= 8 ? 8 : 2;
+    if (cnt16) {  // 16-bit shot counts: a quarter of the bytes, the same values
 #pragma unroll kUnroll
-    for (uint32_t kk = 0; kk < kn; ++kk) {
-      double b = Tn[s_boff[kk]];
-      if (square) b *= b;
+      for (uint32_t kk = 0; kk < kn; ++kk) {
+        double b = (double)Cn[s_boff[kk]] / shots;
+        if (square) b *= b;
 #pragma unroll
-      for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+        for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+      }
+    } else {
+#pragma unroll kUnroll
+      for (uint32_t kk = 0; kk < kn; ++kk) {
+        double b = Tn[s_boff[kk]];
+        if (square) b *= b;
+#pragma unroll
+        for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+      }
     }
   }
   if (n >= N) return;

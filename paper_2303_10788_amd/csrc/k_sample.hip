@@ -48,7 +48,7 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
                             uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
                             uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
                             uint64_t *s_dyn, uint64_t *s_model, uint32_t slice = 0, uint32_t nslice = 1,
-                            double *__restrict__ dist = nullptr) {
+                            double *__restrict__ dist = nullptr, uint16_t *__restrict__ cnt16 = nullptr) {
   const uint32_t mw = model_words(n_meas);
   const uint64_t *md = models + v * mw;
   const uint32_t groups = sample_tab_groups(n_meas);
@@ -73,7 +73,7 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   // equal `slice` into an LDS histogram of 2^kLdsHistBits bins
   const bool sliced = nslice > 1;
   // dist (one shot block): the workgroup writes the table itself, count / shots
-  const bool lds_hist = (partial != nullptr || dist != nullptr) && (n_meas <= kLdsHistBits || sliced);
+  const bool lds_hist = (partial != nullptr || dist != nullptr || cnt16 != nullptr) && (n_meas <= kLdsHistBits || sliced);
   const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
   if (lds_hist)
     for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) s_hist[i] = 0;
@@ -123,7 +123,10 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   }
   if (lds_hist) {
     __syncthreads();
-    if (dist) {
+    if (cnt16) {
+      uint16_t *dd = cnt16 + v * (uint64_t)bins + (uint64_t)slice * lbins;
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (uint16_t)s_hist[i];
+    } else if (dist) {
       double *dd = dist + v * (uint64_t)bins + (uint64_t)slice * lbins;
       for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)s_hist[i] / (double)shots;
     } else {
@@ -163,19 +166,23 @@ __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const Sample
     const uint64_t per_v = (uint64_t)J.nblk * ns, rem = local % per_v;
     sample_body(J.models, J.n_meas, J.shots, J.seed, J.vid0, J.partial, J.qpt, nullptr, local / per_v,
                 (uint32_t)(rem / ns), J.nblk, s_dyn, s_model, (uint32_t)(rem % ns), ns,
-                J.partial ? nullptr : J.dist);
+                J.partial || J.cnt16 ? nullptr : J.dist, J.partial ? nullptr : J.cnt16);
   }
 }
 
 // dist[v][b] = (sum over shot blocks of counts) / shots
 __global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_t nv, uint32_t nblk,
-                                   uint32_t bins, uint64_t shots, double *__restrict__ dist) {
+                                   uint32_t bins, uint64_t shots, double *__restrict__ dist,
+                                   uint16_t *__restrict__ cnt16) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv * bins) return;
   const uint64_t v = i / bins, b = i % bins;
   uint64_t c = 0;
   for (uint32_t k = 0; k < nblk; ++k) c += partial[(v * nblk + k) * (uint64_t)bins + b];
-  dist[i] = (double)c / (double)shots;
+  if (cnt16)
+    cnt16[i] = (uint16_t)c;
+  else
+    dist[i] = (double)c / (double)shots;
 }
 
 // The same over every job of a batch: workgroup x reduces entries
@@ -194,7 +201,10 @@ __global__ __launch_bounds__(256) void hist_reduce_batch_kernel(const SampleJob 
     const uint64_t v = e / bins, b = e % bins;
     uint64_t c = 0;
     for (uint32_t k = 0; k < nblk; ++k) c += J.partial[(v * nblk + k) * (uint64_t)bins + b];
-    J.dist[e] = (double)c / (double)J.shots;
+    if (J.cnt16)
+      J.cnt16[e] = (uint16_t)c;
+    else
+      J.dist[e] = (double)c / (double)J.shots;
   }
 }
 
@@ -401,10 +411,11 @@ hipError_t launch_hist_reduce_batch(const SampleJob *jobs, uint32_t n_jobs, uint
 }
 
 hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nblk, uint32_t bins,
-                              uint64_t shots, double *dist, hipStream_t s) {
+                              uint64_t shots, double *dist, hipStream_t s, uint16_t *cnt16) {
   const uint64_t n = nv * bins;
+  if (cnt16 && shots > 0xFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hist_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, partial, nv, nblk,
-                     bins, shots, dist);
+                     bins, shots, dist, cnt16);
   return hipGetLastError();
 }
 
