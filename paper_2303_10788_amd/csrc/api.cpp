@@ -513,14 +513,16 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
       const uint64_t nquads = (shots + 3) / 4;
       for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
         const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
-        const bool lds = nm <= 14;
+        const bool lds = nm <= kLdsHistBits;
         uint32_t nblk = 1;
         if (lds) {
-          // enough shots per workgroup that its partial histogram is not mostly empty
+          // enough shots per workgroup that its partial histogram is not mostly
+          // empty, few enough for its 16-bit LDS counts
           const uint64_t per_block = std::max<uint64_t>(bins, 2048);
           uint64_t want = (shots + per_block - 1) / per_block;
           uint64_t maxb = (nquads + 255) / 256;
           nblk = (uint32_t)std::max<uint64_t>(1, std::min(want, maxb));
+          nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * 256 - 1) / (kMaxUnitQpt * 256));
         } else {
           nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         }
@@ -1886,21 +1888,23 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, b->block, b->grid)) != CCUT_OK) return st;
   if (!b->samp.empty()) {
     // jobs in LDS classes (one launch each, so a launch's workgroups reserve
-    // only their class's histogram): up to 8, 20, 38 and 80 KiB
+    // only their class's histogram): up to 8, 24, 40, 72 and 136 KiB
+    constexpr int kClasses = 5;
     const uint64_t shots = b->eo.shots_per_variant;
     const uint64_t nquads = (shots + 3) / 4;
-    auto lds_class = [](size_t l) { return l <= (8u << 10) ? 0 : l <= (20u << 10) ? 1 : l <= (38u << 10) ? 2 : 3; };
+    auto lds_class = [](size_t l) {
+      return l <= (8u << 10) ? 0 : l <= (24u << 10) ? 1 : l <= (40u << 10) ? 2 : l <= (72u << 10) ? 3 : 4;
+    };
+    auto sliced_bits = [](uint32_t nm) { return nm > kLdsHistBits && nm <= kLdsHistBits + kMaxSliceBits; };
     std::vector<size_t> order;
-    for (int cls = 0; cls < 4; ++cls)
+    for (int cls = 0; cls < kClasses; ++cls)
       for (size_t q = 0; q < b->samp.size(); ++q)
-        if (lds_class(sample_lds_bytes(b->samp[q].n_meas, true,
-                                       b->samp[q].n_meas > kLdsHistBits && b->samp[q].n_meas <= kLdsHistBits + 3)) ==
-            cls)
+        if (lds_class(sample_lds_bytes(b->samp[q].n_meas, true, sliced_bits(b->samp[q].n_meas))) == cls)
           order.push_back(q);
     std::vector<SampleJob> jobs;
     uint64_t t = 0, fill_words = 0;
-    uint64_t cls_units[4] = {0, 0, 0, 0};
-    size_t cls_lds[4] = {0, 0, 0, 0}, cls_first[4] = {0, 0, 0, 0}, cls_count[4] = {0, 0, 0, 0};
+    uint64_t cls_units[kClasses] = {};
+    size_t cls_lds[kClasses] = {}, cls_first[kClasses] = {}, cls_count[kClasses] = {};
     for (size_t q : order) {
       const auto &ref = b->samp[q];
       const FragDev &h = b->descs[ref.desc];
@@ -1908,12 +1912,14 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       const uint64_t nv = h.n_variants;
       // up to 3 bits above the LDS histogram: one workgroup per 2^14-bin
       // slice, each replaying the shots (no global atomics, no zero fill)
-      const uint32_t nslice = nm > kLdsHistBits && nm <= kLdsHistBits + 3 ? 1u << (nm - kLdsHistBits) : 1u;
+      const uint32_t nslice = sliced_bits(nm) ? 1u << (nm - kLdsHistBits) : 1u;
       const bool lds = nm <= kLdsHistBits || nslice > 1;
       uint32_t nblk;
-      if (lds) {  // up to 16384 shots per block: a batch has workgroups enough without splitting further
+      if (lds) {  // 16384 shots or more per block: a batch has workgroups enough without splitting further
         const uint64_t per_block = std::max<uint64_t>(std::min<uint64_t>(bins, 1u << kLdsHistBits), 16384);
         nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
+        // and few enough for the 16-bit LDS counts
+        nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * 256 - 1) / (kMaxUnitQpt * 256));
       } else {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         fill_words += nv * (uint64_t)bins;
@@ -1987,7 +1993,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
     if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (fill_words) HIP_TRY(c, launch_fill_u32(zeroed, fill_words, 0u, c->cur));
-    for (int cls = 0; cls < 4; ++cls)
+    for (int cls = 0; cls < kClasses; ++cls)
       if (cls_count[cls]) {
         KTimer tm(c, CCUT_K_SAMPLE);
         HIP_TRY(c, launch_sample_batch(d_jobs + cls_first[cls], (uint32_t)cls_count[cls], cls_units[cls],

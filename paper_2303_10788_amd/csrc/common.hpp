@@ -209,16 +209,24 @@ struct SampleJob {
 };
 
 // Sampling LDS: the shot xor's byte tables (256 u64 per 8 measurement
-// indices) and, for n_meas <= kLdsHistBits, the workgroup's u32 histogram.
-constexpr uint32_t kLdsHistBits = 14;
+// indices) and the workgroup's histogram of up to 2^kLdsHistBits bins,
+// 16-bit counts packed two to a 32-bit word.  A workgroup counts at most
+// kMaxUnitShots shots (at most kMaxUnitQpt quads per thread), so no count
+// carries into its neighbour.  Wider outcome tables are counted in
+// 2^kLdsHistBits-bin slices (up to kMaxSliceBits more bits), each slice
+// replaying the shots.
+constexpr uint32_t kLdsHistBits = 16;
+constexpr uint32_t kMaxSliceBits = 3;
+constexpr uint32_t kMaxUnitQpt = 63;  // 63 quads x 256 threads x 4 shots = 64512 < 2^16
 __host__ __device__ inline uint32_t sample_tab_groups(uint32_t n_meas) { return (n_meas + 7) / 8; }
 inline size_t sample_lds_bytes(uint32_t n_meas, bool hist, bool sliced = false) {
   const size_t tab = (size_t)sample_tab_groups(n_meas) * 256 * 8;
   if (!hist) return tab;
-  if (sliced) return tab + (size_t(4) << kLdsHistBits);
-  return tab + (n_meas <= kLdsHistBits ? (size_t(4) << n_meas) : 0);
+  const uint32_t lb = sliced ? kLdsHistBits : n_meas;
+  if (lb > kLdsHistBits) return tab;
+  return tab + 4 * (((size_t(1) << lb) + 1) / 2);
 }
-constexpr size_t kSampleLdsMax = 8 * 256 * 8 + (size_t(4) << kLdsHistBits);
+constexpr size_t kSampleLdsMax = 8 * 256 * 8 + (size_t(2) << kLdsHistBits);
 
 // One non-Clifford fragment in a batched state-vector launch: descriptor
 // descs[desc], tables in dist, wg0 = its first workgroup.

@@ -35,9 +35,10 @@ constexpr int kSampleBlock = 256;
 
 // Shots of variant v, block bx of nbx: each thread handles `qpt` quads;
 // quads are interleaved across the workgroup so record writes are
-// contiguous.  With n_meas <= 14 the block's histogram lives in LDS and is
-// written to partial[v][bx][bins]; otherwise counts go straight to
-// partial[v][bins] (zeroed beforehand).
+// contiguous.  With n_meas <= kLdsHistBits (or a slice of the bins) the
+// block's histogram lives in LDS as packed 16-bit counts (qpt <= kMaxUnitQpt)
+// and is written to partial[v][bx][bins], or straight to the table;
+// otherwise counts go to partial[v][bins] (zeroed beforehand).
 //
 // The xor over random measurements goes by bytes of the Philox word: table
 // T[g][b] (LDS, 256 entries per group of 8 measurement indices) holds the
@@ -75,8 +76,9 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   // dist (one shot block): the workgroup writes the table itself, count / shots
   const bool lds_hist = (partial != nullptr || dist != nullptr || cnt16 != nullptr) && (n_meas <= kLdsHistBits || sliced);
   const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
+  const uint32_t lwords = (lbins + 1) / 2;  // two 16-bit counts per word
   if (lds_hist)
-    for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) s_hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) s_hist[i] = 0;
   __syncthreads();
   const uint64_t vid = vid0 + v;
   const bool wide = n_meas > 32;
@@ -113,9 +115,16 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
           const uint32_t leader = (uint32_t)__ffsll((unsigned long long)todo) - 1u;
           const uint32_t xl = __builtin_amdgcn_readlane((uint32_t)x, leader);
           const uint64_t same = __ballot(valid && (uint32_t)x == xl) & todo;
-          if (lane == leader) atomicAdd(&hist[xl], (uint32_t)__popcll(same));
+          if (lane == leader) {
+            if (lds_hist)
+              atomicAdd(&hist[xl >> 1], (uint32_t)__popcll(same) << (16 * (xl & 1u)));
+            else
+              atomicAdd(&hist[xl], (uint32_t)__popcll(same));
+          }
           todo &= ~same;
         }
+      } else if (lds_hist) {
+        atomicAdd(&hist[(uint32_t)x >> 1], 1u << (16 * ((uint32_t)x & 1u)));
       } else if (hist) {
         atomicAdd(&hist[x], 1u);
       }
@@ -123,15 +132,21 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   }
   if (lds_hist) {
     __syncthreads();
+    auto count = [&](uint32_t i) { return (s_hist[i >> 1] >> (16 * (i & 1u))) & 0xFFFFu; };
     if (cnt16) {
       uint16_t *dd = cnt16 + v * (uint64_t)bins + (uint64_t)slice * lbins;
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (uint16_t)s_hist[i];
+      if (lbins >= 2) {  // the packed words are the table's layout (little-endian pairs)
+        uint32_t *dw = reinterpret_cast<uint32_t *>(dd);
+        for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) dw[i] = s_hist[i];
+      } else if (threadIdx.x == 0) {
+        dd[0] = (uint16_t)count(0);
+      }
     } else if (dist) {
       double *dd = dist + v * (uint64_t)bins + (uint64_t)slice * lbins;
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)s_hist[i] / (double)shots;
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)count(i) / (double)shots;
     } else {
       uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins + (uint64_t)slice * lbins;
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = s_hist[i];
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = count(i);
     }
   }
 }
@@ -378,6 +393,7 @@ hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t 
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
                               uint32_t qpt, uint64_t *records, hipStream_t s) {
   if (n_meas > (uint32_t)kMaxMeas || nv == 0 || nv > 65535) return hipErrorInvalidValue;
+  if (partial && n_meas <= kLdsHistBits && qpt > kMaxUnitQpt) return hipErrorInvalidValue;  // 16-bit LDS counts
   const size_t lds = sample_lds_bytes(n_meas, partial != nullptr);
   hipError_t e = hipFuncSetAttribute((const void *)sample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
