@@ -1176,16 +1176,24 @@ bool counts_contraction(const PlanData &pd, const ccut_eval_opts *eo, uint32_t n
   return !(!fp32 && pd.frags.size() > 2 && (K << nq) <= (1ull << 20));
 }
 
+// The axes of fragment f on a cut of fragment g (bit j: axis j).
+uint32_t fold_mask(const PlanData &pd, int g, const Fragment &f) {
+  if (g < 0 || (int)f.index == g) return 0;
+  uint32_t mask = 0;
+  for (size_t j = 0; j < f.axes.size(); ++j)
+    for (const Axis &a : pd.frags[g].axes)
+      if (a.cut == f.axes[j].cut) mask |= 1u << j;
+  return mask;
+}
+
 // The fold jobs of the other fragments: every axis on a cut of fragment g.
-void fold_jobs(const PlanData &pd, int g, const RecombArgs &args, std::vector<FoldJob> &jobs) {
+// folded[f] set: fragment f's tensor was folded where it was produced.
+void fold_jobs(const PlanData &pd, int g, const RecombArgs &args, std::vector<FoldJob> &jobs,
+               const std::vector<char> *folded = nullptr) {
   if (g < 0) return;
-  std::vector<char> gcut(pd.k, 0);
-  for (const Axis &a : pd.frags[g].axes) gcut[a.cut] = 1;
   for (const Fragment &f : pd.frags) {
-    if ((int)f.index == g) continue;
-    uint32_t mask = 0;
-    for (size_t j = 0; j < f.axes.size(); ++j)
-      if (gcut[f.axes[j].cut]) mask |= 1u << j;
+    if (folded && (*folded)[f.index]) continue;
+    const uint32_t mask = fold_mask(pd, g, f);
     const RecombFrag &rf = args.f[f.index];
     if (mask) jobs.push_back({const_cast<double *>(rf.T), rf.rows, rf.n_axes, mask});
   }
@@ -2040,6 +2048,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     args.lo_parts = b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM;
     c->stream = c->cur = P ? b->pool[i % P] : b->stream;
     const int g = fold_target(pd, &eo, qubits, nq);
+    std::vector<char> folded(pd.frags.size(), 0);
     for (const Fragment &f : pd.frags) {
       FragRequest r = marginal_request(f, qubits, nq);
       double *T = nullptr;
@@ -2062,6 +2071,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
         } else if (st == CCUT_OK && !f.axes.empty() && tile_job(f, r, dist, xsize, nullptr, J)) {
           J.in16 = cnt;
           J.shots = (double)eo.shots_per_variant;
+          J.fold = fold_mask(pd, g, f);  // the fold of fold_jobs, applied in the tile
+          folded[f.index] = 1;
           J.out = T = aget<double>(c, J.x_out << (2 * f.axes.size()));
           if (!T) st = fail(c, CCUT_E_OOM, "device allocation failed");
           tjobs.push_back(J);
@@ -2080,7 +2091,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     }
     c->stream = c->cur = b->stream;
     if (st != CCUT_OK) return st;
-    fold_jobs(pd, g, args, fjobs);
+    fold_jobs(pd, g, args, fjobs, &folded);
     // the contraction recombine() would take
     const uint64_t K = 1ull << (2 * pd.k);
     kind[i] = plain_contraction(args, nq, fp32) ? (args.n_frags <= 8 ? 0 : 1) : 2;
@@ -2124,8 +2135,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   GemmArgs *d_gargs = gargs.empty() ? nullptr : (GemmArgs *)upload(c, gargs.data(), gargs.size() * sizeof(GemmArgs));
   if ((!plain.empty() && !d_plain) || (!gargs.empty() && !d_gargs)) return fail(c, CCUT_E_OOM, "device allocation failed");
   std::vector<RcJob> rjobs;
-  // launch classes: 0 the MFMA tiles, 1 + log2(M) the skinny kernel for M rows
-  constexpr int kGemmClasses = 7;
+  // launch classes: 0 the MFMA tiles, 1 + 3 log2(M) + log2(CPT) the skinny
+  // kernel for M rows and CPT columns per thread
+  constexpr int kGemmClasses = 19;
   std::vector<GemmJob> gjobs[kGemmClasses];
   uint64_t rwg = 0, gwg[kGemmClasses] = {}, grwg[kGemmClasses] = {};
   for (size_t i = 0, g = 0; i < np; ++i) {
@@ -2142,9 +2154,12 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       const GemmArgs &h = gargs[g];
       const bool skinny = contraction_skinny(h, fp32);
       int sk = 0;
-      if (skinny)
-        while ((1u << (sk)) < h.M) ++sk;
-      if (skinny) ++sk;  // class 1 + log2(M)
+      if (skinny) {
+        int lm = 0, lc = 0;
+        while ((1u << lm) < h.M) ++lm;
+        while ((1u << lc) < skinny_cols(h)) ++lc;
+        sk = 1 + 3 * lm + lc;
+      }
       GemmJob J{};
       J.args = d_gargs + g;
       J.splits = contraction_splits(h, skinny);
@@ -2191,7 +2206,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     pick();
     KTimer t(c, CCUT_K_RECOMBINE);
     HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32,
-                                 sk ? 1u << (sk - 1) : 0u, c->cur));
+                                 sk ? 1u << ((sk - 1) / 3) : 0u, sk ? 1u << ((sk - 1) % 3) : 0u, c->cur));
   }
   c->cur = b->stream;
   for (size_t k = 0; k < n_side; ++k) {

@@ -254,6 +254,18 @@ __device__ inline uint32_t find_job(const J *jobs, uint32_t n, uint64_t idx, F s
   return lo;
 }
 
+// The dispatcher hands consecutive workgroups of a launch to the chip's 8
+// XCDs in turn, and each XCD has an L2 of its own.  xcd_block renumbers
+// workgroup `bid` of `n` so that each XCD runs one contiguous range of
+// logical blocks: neighbouring tiles, which share cache lines, then meet in
+// one L2 instead of being fetched from HBM once per XCD.  A bijection of
+// [0, n) for any n.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_block(uint32_t bid, uint32_t n) {
+  const uint32_t x = bid % kXcds, local = bid / kXcds, per = n / kXcds, rem = n % kXcds;
+  return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 // ---------------------------------------------------------------- launchers
 // All return hipSuccess or the launch error.
 
@@ -331,7 +343,8 @@ struct TileJob {
   uint64_t x_in, x_out;
   uint64_t wg0;                 // first workgroup of the job in a batched launch
   uint32_t tiles;               // x_out >> t
-  uint32_t n_axes, v_count, t, thr, nh, lbits, pad_;
+  uint32_t n_axes, v_count, t, thr, nh, lbits;
+  uint32_t fold;                // axes (bit j) rewritten into the downstream preparation basis (launch_fold's map)
   uint32_t rad[kMaxTileAxes];   // 4 quantum input, 3 quantum output
   uint32_t lpos[kMaxTileAxes];  // output axis: its outcome bit's position in the tile's x
   uint32_t hpos[kMaxTileAxes];  // x_in positions of the outcome bits at or above thr, ascending
@@ -465,6 +478,7 @@ uint32_t gemm_splits(const GemmArgs &h);
 // column per thread, products summed in ascending term order) instead of
 // 64 x 64 MFMA tiles; tiles, splits and the K range per split of either
 bool contraction_skinny(const GemmArgs &h, bool fp32);
+uint32_t skinny_cols(const GemmArgs &h);  // skinny kernel columns per thread (1, 2 or 4)
 uint32_t gemm_tiles(const GemmArgs &h, bool skinny);
 uint32_t contraction_splits(const GemmArgs &h, bool skinny);
 uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny);
@@ -479,9 +493,9 @@ struct GemmJob {
   uint32_t tiles, splits;
 };
 // skinny_rows: 0 for the MFMA tiles, else the row count M (1, 2, 4, ..., 32)
-// every job of the list shares
+// and skinny_cpt the columns per thread (skinny_cols) every job of the list shares
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             uint32_t skinny_rows, hipStream_t s);
+                             uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s);
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
                                  uint32_t splits, double *out, hipStream_t s,
                                  bool skinny = false);

@@ -142,7 +142,9 @@ __global__ void transform_all_kernel(const TransformAll A, const double *__restr
 // six (basis X, Y, Z x outcome 0, 1) and leaves I, X, Y in the outcome-0
 // slots of bases X, Y, Z and Z in the outcome-1 slot of basis X.
 // A workgroup takes `per_wg` consecutive tiles of the launch in turn (fewer,
-// longer workgroups: the dispatcher, not the tiles, limits short ones).
+// longer workgroups: the dispatcher, not the tiles, limits short ones), and
+// the workgroups of one XCD take consecutive ranges (xcd_block): the tiles
+// of a variant row share its cache lines.
 constexpr uint32_t kTileThreads = 512;
 __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep);
 
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const Til
                                                                        uint32_t per_wg) {
   __shared__ double s[kTileElems];
   __shared__ uint32_t s_xdep[1u << kTileMaxT];
-  const uint64_t g0 = (uint64_t)blockIdx.x * per_wg;
+  const uint64_t g0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * per_wg;
   const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
   uint32_t jb = find_job(jobs, n_jobs, g0, [](const TileJob &J) { return J.wg0; });
   for (uint64_t g = g0; g < g1; ++g) {
@@ -244,6 +246,40 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
     }
     R *= J.rad[j];
     __syncthreads();
+  }
+  // folded axes: the four Pauli slots of the axis rewritten into the
+  // preparation basis of the fragment downstream of its cut (the map of
+  // launch_fold: s=0: I - X - Y + Z, s=1: I - X - Y - Z, s=+: 2X, s=+i: 2Y)
+  if (J.fold) {
+    R = 1;
+    for (uint32_t j = 0; j < a; ++j) {
+      if ((J.fold >> j) & 1u) {
+        const uint32_t S = R << lb, mag = J.rmag[j];
+        const uint32_t ngroups = J.rad[j] == 4 ? (n_el >> 2) : (V / 3) * (XL >> 1);
+        for (uint32_t g = tid; g < ngroups; g += kTileThreads) {
+          uint32_t b, s1, s2, s3;
+          if (J.rad[j] == 4) {
+            const uint32_t gh = g >> lb, q = mag ? __umulhi(gh, mag) : gh;
+            b = q * 4 * S + (((gh - q * R) << lb) | (g & (XL - 1u)));
+            s1 = b + S, s2 = b + 2 * S, s3 = b + 3 * S;
+          } else {
+            const uint32_t lp = J.lpos[j], half = XL >> 1, o1 = 1u << lp;
+            const uint32_t li = g & (half - 1u), vg = g >> (lb - 1);
+            const uint32_t l = ((li >> lp) << (lp + 1)) | (li & (o1 - 1u));
+            const uint32_t vq = mag ? __umulhi(vg, mag) : vg;
+            b = ((vq * 3 * R + (vg - vq * R)) << lb) | l;
+            s1 = b + S, s2 = b + 2 * S, s3 = b + o1;
+          }
+          const double vI = s[b], vX = s[s1], vY = s[s2], vZ = s[s3];
+          s[b] = ((vI - vX) - vY) + vZ;
+          s[s1] = ((vI - vX) - vY) - vZ;
+          s[s2] = 2.0 * vX;
+          s[s3] = 2.0 * vY;
+        }
+        __syncthreads();
+      }
+      R *= J.rad[j];
+    }
   }
   // out[P][x_out], P base 4 (axis 0 fastest), x_out = u 2^t + xo
   const uint32_t n_out = XT << (2 * a);

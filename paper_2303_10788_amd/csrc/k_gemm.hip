@@ -223,38 +223,80 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
 // tiles, split (x - wg0) / tiles of the job holding x.
 template <bool F32>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
-  const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
+  const uint32_t bid = xcd_block(blockIdx.x, gridDim.x);  // the tiles of a job share one XCD's L2
+  const uint32_t j = find_job(jobs, n_jobs, bid, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];
-  const uint64_t local = blockIdx.x - J.wg0;
+  const uint64_t local = bid - J.wg0;
   gemm_body<F32>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
                  J.splits == 1 ? J.out : nullptr);
 }
 
-// Skinny contraction (M <= SK_M rows, fp64): one output column n per
-// thread with all M rows in registers; the row-side values of a K chunk are
-// staged in LDS.  partial[split][m][n] = sum over the split's terms, in
+// Skinny contraction (M <= SK_M rows, fp64): CPT adjacent output columns
+// per thread with all M rows in registers; the row-side values of a K chunk
+// are staged in LDS.  partial[split][m][n] = sum over the split's terms, in
 // ascending order, of a(m, P) * b(n, P) (each product rounded, then added).
+// A thread's CPT columns come in one vector load per term (CPT 16-bit shot
+// counts in 8 bytes, or CPT doubles), so a wave moves 512 bytes or more per
+// load instruction.
 constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
-// One instantiation per row count MC (1, 2, ..., 32): the accumulators of
-// one kernel stay in registers only when the kernel holds exactly its own.
-template <uint32_t MC>
+
+template <uint32_t CPT>
+struct ColLoad;
+template <>
+struct ColLoad<1> {
+  __device__ static void cnt(const uint16_t *p, double shots, double *b) { b[0] = (double)p[0] / shots; }
+  __device__ static void f64(const double *p, double *b) { b[0] = p[0]; }
+};
+template <>
+struct ColLoad<2> {
+  __device__ static void cnt(const uint16_t *p, double shots, double *b) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+    b[0] = (double)(w & 0xFFFFu) / shots;
+    b[1] = (double)(w >> 16) / shots;
+  }
+  __device__ static void f64(const double *p, double *b) {
+    const double2 v = *reinterpret_cast<const double2 *>(p);
+    b[0] = v.x, b[1] = v.y;
+  }
+};
+template <>
+struct ColLoad<4> {
+  __device__ static void cnt(const uint16_t *p, double shots, double *b) {
+    const uint2 w = *reinterpret_cast<const uint2 *>(p);
+    b[0] = (double)(w.x & 0xFFFFu) / shots;
+    b[1] = (double)(w.x >> 16) / shots;
+    b[2] = (double)(w.y & 0xFFFFu) / shots;
+    b[3] = (double)(w.y >> 16) / shots;
+  }
+  __device__ static void f64(const double *p, double *b) {
+    const double2 v0 = reinterpret_cast<const double2 *>(p)[0], v1 = reinterpret_cast<const double2 *>(p)[1];
+    b[0] = v0.x, b[1] = v0.y, b[2] = v1.x, b[3] = v1.y;
+  }
+};
+
+// One instantiation per row count MC (1, 2, ..., 32) and column count CPT:
+// the accumulators of one kernel stay in registers only when the kernel
+// holds exactly its own.
+template <uint32_t MC, uint32_t CPT>
 __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
                                    uint32_t tile, uint32_t split, double *__restrict__ out) {
   __shared__ double As[SK_KC][MC];
   __shared__ uint64_t s_boff[SK_KC];
   const uint32_t N = G->N, tid = threadIdx.x;
   const uint64_t K = G->K;
-  const uint32_t n = tile * SK_N + tid;
+  const uint32_t n = (tile * SK_N + tid) * CPT;  // the thread's first column (N is a multiple of CPT)
   const uint64_t k0 = (uint64_t)split * k_per_split;
   const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
   // the column side is one fragment whose rows are the column index
   const uint32_t rf = G->R.frag[0];
-  const double *Tn = G->f[rf].T + n;
-  const uint16_t *Cn = reinterpret_cast<const uint16_t *>(G->f[rf].T) + n;
-  const bool cnt16 = G->f[rf].cnt16 != 0;
-  const double shots = G->f[rf].shots;
-  const uint64_t rows = G->f[rf].rows;
+  const RecombFrag &FR = G->f[rf];
+  const double *Tn = FR.T + n;
+  const uint16_t *Cn = reinterpret_cast<const uint16_t *>(FR.T) + n;
+  const bool cnt16 = FR.cnt16 != 0;
+  const double shots = FR.shots;
+  const uint64_t rows = FR.rows;
   const bool square = G->square != 0;
+  const double *tscale = G->tscale;
   const RecombFrag *FA = direct_side(G, G->L);
   const uint64_t rowsA = FA ? FA->rows : 0;
   __shared__ uint64_t s_mbits[MC];  // output index bits of the rows
@@ -262,9 +304,11 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
     if (tid < MC) s_mbits[tid] = side_bits(G, G->L, tid);
     __syncthreads();
   }
-  double acc[MC];
+  double acc[MC][CPT];
 #pragma unroll
-  for (uint32_t m = 0; m < MC; ++m) acc[m] = 0.0;
+  for (uint32_t m = 0; m < MC; ++m)
+#pragma unroll
+    for (uint32_t c = 0; c < CPT; ++c) acc[m][c] = 0.0;
   for (uint64_t kb = k0; kb < k1; kb += SK_KC) {
     const uint32_t kn = (uint32_t)std::min<uint64_t>(SK_KC, k1 - kb);
     __syncthreads();  // the previous chunk is consumed
@@ -276,60 +320,115 @@ __device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_pe
       const uint32_t kk = e / MC, m = e % MC;
       const uint64_t j = kb + kk;
       double a = FA ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
-      if (G->tscale) a *= G->tscale[j];
+      if (tscale) a *= tscale[j];
       if (square) a *= a;
       As[kk][m] = a;
     }
     __syncthreads();
     if (n >= N) continue;
-    // several column loads in flight per thread (fewer for many rows, whose
-    // row values would crowd the registers): the kernel streams the column
-    // tensor once
-    constexpr uint32_t kUnroll = MC <= 8 ? 8 : 2;
+    // several column loads in flight per thread (fewer for many
+    // accumulators, which would crowd the registers): the kernel streams the
+    // column tensor once
+    constexpr uint32_t kUnroll = MC * CPT <= 8 ? 8 : 4;
     if (cnt16) {  // 16-bit shot counts: a quarter of the bytes, the same values
 #pragma unroll kUnroll
       for (uint32_t kk = 0; kk < kn; ++kk) {
-        double b = (double)Cn[s_boff[kk]] / shots;
-        if (square) b *= b;
+        double b[CPT];
+        ColLoad<CPT>::cnt(Cn + s_boff[kk], shots, b);
 #pragma unroll
-        for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+        for (uint32_t c = 0; c < CPT; ++c) {
+          if (square) b[c] *= b[c];
+#pragma unroll
+          for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[kk][m] * b[c];
+        }
       }
     } else {
 #pragma unroll kUnroll
       for (uint32_t kk = 0; kk < kn; ++kk) {
-        double b = Tn[s_boff[kk]];
-        if (square) b *= b;
+        double b[CPT];
+        ColLoad<CPT>::f64(Tn + s_boff[kk], b);
 #pragma unroll
-        for (uint32_t m = 0; m < MC; ++m) acc[m] += As[kk][m] * b;
+        for (uint32_t c = 0; c < CPT; ++c) {
+          if (square) b[c] *= b[c];
+#pragma unroll
+          for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[kk][m] * b[c];
+        }
       }
     }
   }
   if (n >= N) return;
   if (out) {
-    const uint64_t nb = side_bits(G, G->R, n);
 #pragma unroll
-    for (uint32_t m = 0; m < MC; ++m) out[s_mbits[m] | nb] = ldexp(0.0 + acc[m], -(int)G->k);
+    for (uint32_t c = 0; c < CPT; ++c) {
+      const uint64_t nb = side_bits(G, G->R, n + c);
+#pragma unroll
+      for (uint32_t m = 0; m < MC; ++m) out[s_mbits[m] | nb] = ldexp(0.0 + acc[m][c], -(int)G->k);
+    }
     return;
   }
   double *dst = partial + (uint64_t)split * MC * N;
 #pragma unroll
-  for (uint32_t m = 0; m < MC; ++m) dst[(uint64_t)m * N + n] = acc[m];
+  for (uint32_t m = 0; m < MC; ++m)
+#pragma unroll
+    for (uint32_t c = 0; c < CPT; ++c) dst[(uint64_t)m * N + n + c] = acc[m][c];
 }
 
-template <uint32_t MC>
+template <uint32_t MC, uint32_t CPT>
 __global__ __launch_bounds__(SK_N) void skinny_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
                                                       double *__restrict__ partial, double *__restrict__ out) {
-  skinny_body<MC>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
+  skinny_body<MC, CPT>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
 }
 
-// Jobs of one row count MC.
-template <uint32_t MC>
+// Jobs of one row count MC and column count CPT.
+template <uint32_t MC, uint32_t CPT>
 __global__ __launch_bounds__(SK_N) void skinny_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];
   const uint64_t local = blockIdx.x - J.wg0;
-  skinny_body<MC>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
-                  J.splits == 1 ? J.out : nullptr);
+  skinny_body<MC, CPT>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
+                       J.splits == 1 ? J.out : nullptr);
+}
+
+// The skinny kernel for M rows and CPT columns per thread, one launch.
+// batch: the job list (grid total_wg), else one contraction (grid tiles x splits).
+template <uint32_t MC, uint32_t CPT>
+void skinny_launch(dim3 g, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs, const GemmArgs *args,
+                   uint64_t k_per_split, double *partial, double *out) {
+  if (jobs)
+    hipLaunchKernelGGL((skinny_batch_kernel<MC, CPT>), g, dim3(SK_N), 0, s, jobs, n_jobs);
+  else
+    hipLaunchKernelGGL((skinny_kernel<MC, CPT>), g, dim3(SK_N), 0, s, args, k_per_split, partial, out);
+}
+
+template <uint32_t MC>
+hipError_t skinny_cols_launch(uint32_t cpt, dim3 g, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs,
+                              const GemmArgs *args, uint64_t k_per_split, double *partial, double *out) {
+  switch (cpt) {
+    case 1: skinny_launch<MC, 1>(g, s, jobs, n_jobs, args, k_per_split, partial, out); break;
+    case 2: skinny_launch<MC, 2>(g, s, jobs, n_jobs, args, k_per_split, partial, out); break;
+    case 4:
+      if constexpr (MC <= 4) {
+        skinny_launch<MC, 4>(g, s, jobs, n_jobs, args, k_per_split, partial, out);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t skinny_dispatch(uint32_t rows, uint32_t cpt, dim3 g, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs,
+                           const GemmArgs *args, uint64_t k_per_split, double *partial, double *out) {
+  switch (rows) {
+    case 1: return skinny_cols_launch<1>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out);
+    case 2: return skinny_cols_launch<2>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out);
+    case 4: return skinny_cols_launch<4>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out);
+    case 8: return skinny_cols_launch<8>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out);
+    case 16: return skinny_cols_launch<16>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out);
+    case 32: return cpt == 1 ? skinny_cols_launch<32>(cpt, g, s, jobs, n_jobs, args, k_per_split, partial, out)
+                             : hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // The output index bits of row (or column) idx of side S: each of its
@@ -387,8 +486,16 @@ bool contraction_skinny(const GemmArgs &h, bool fp32) {
   return !fp32 && h.M <= SK_M && (h.M & (h.M - 1)) == 0 && h.R.n == 1 && h.R.shift[0] == 0;
 }
 
+// Columns per thread of the skinny kernel: 4 for at most 4 rows, 2 for 8
+// and 16, 1 for 32 (at most 32 accumulators), and never more than N (a
+// power of two: the rows of the one column fragment).
+uint32_t skinny_cols(const GemmArgs &h) {
+  const uint32_t cap = h.M <= 4 ? 4 : h.M <= 16 ? 2 : 1;
+  return std::min<uint32_t>(cap, h.N);
+}
+
 uint32_t gemm_tiles(const GemmArgs &h, bool skinny) {
-  if (skinny) return (h.N + SK_N - 1) / SK_N;
+  if (skinny) return (h.N + SK_N * skinny_cols(h) - 1) / (SK_N * skinny_cols(h));
   return ((h.M + MT - 1) / MT) * ((h.N + NT - 1) / NT);
 }
 
@@ -410,26 +517,22 @@ uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny) {
 }
 
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             uint32_t skinny_rows, hipStream_t s) {
+                             uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s) {
   if (n_jobs == 0 || total_wg == 0) return hipSuccess;
   if (total_wg > 0x7FFFFFFFull || total_rwg > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  const dim3 g((unsigned)total_wg), b(SK_N);
-  if (skinny_rows) {
-    switch (skinny_rows) {
-      case 1: hipLaunchKernelGGL(skinny_batch_kernel<1>, g, b, 0, s, d_jobs, n_jobs); break;
-      case 2: hipLaunchKernelGGL(skinny_batch_kernel<2>, g, b, 0, s, d_jobs, n_jobs); break;
-      case 4: hipLaunchKernelGGL(skinny_batch_kernel<4>, g, b, 0, s, d_jobs, n_jobs); break;
-      case 8: hipLaunchKernelGGL(skinny_batch_kernel<8>, g, b, 0, s, d_jobs, n_jobs); break;
-      case 16: hipLaunchKernelGGL(skinny_batch_kernel<16>, g, b, 0, s, d_jobs, n_jobs); break;
-      case 32: hipLaunchKernelGGL(skinny_batch_kernel<32>, g, b, 0, s, d_jobs, n_jobs); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else if (fp32)
-    hipLaunchKernelGGL((gemm_batch_kernel<true>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
-  else
-    hipLaunchKernelGGL((gemm_batch_kernel<false>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || total_rwg == 0) return e;  // (one-split skinny jobs wrote their outputs)
+  hipError_t e;
+  if (skinny_rows)
+    e = skinny_dispatch(skinny_rows, skinny_cpt, dim3((unsigned)total_wg), s, d_jobs, n_jobs, nullptr, 0, nullptr,
+                        nullptr);
+  else {
+    if (fp32)
+      hipLaunchKernelGGL((gemm_batch_kernel<true>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
+    else
+      hipLaunchKernelGGL((gemm_batch_kernel<false>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs,
+                         n_jobs);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess || total_rwg == 0) return e;  // (one-split jobs wrote their outputs)
   hipLaunchKernelGGL(gemm_reduce_batch_kernel, dim3((unsigned)total_rwg), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
 }
@@ -439,18 +542,9 @@ hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool
   const uint32_t tiles = gemm_tiles(h, skinny);
   const uint64_t k_per_split = gemm_k_per_split(h, splits, skinny);
   if (skinny) {
-    const dim3 g(tiles, splits), b(SK_N);
-    double *o = splits == 1 ? out : nullptr;
-    switch (h.M) {
-      case 1: hipLaunchKernelGGL(skinny_kernel<1>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      case 2: hipLaunchKernelGGL(skinny_kernel<2>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      case 4: hipLaunchKernelGGL(skinny_kernel<4>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      case 8: hipLaunchKernelGGL(skinny_kernel<8>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      case 16: hipLaunchKernelGGL(skinny_kernel<16>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      case 32: hipLaunchKernelGGL(skinny_kernel<32>, g, b, 0, s, d_args, k_per_split, partial, o); break;
-      default: return hipErrorInvalidValue;
-    }
-    if (splits == 1) return hipGetLastError();
+    const hipError_t e = skinny_dispatch(h.M, skinny_cols(h), dim3(tiles, splits), s, nullptr, 0, d_args,
+                                         k_per_split, partial, splits == 1 ? out : nullptr);
+    if (e != hipSuccess || splits == 1) return e;
   } else if (fp32)
     hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
                        partial, splits == 1 ? out : nullptr);
