@@ -1777,86 +1777,91 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   }
   const size_t n_sv_streams = std::min<size_t>(b->pool.size(), 3);
   std::vector<uint8_t> sv_used(n_sv_streams, 0);
+  // (enqueued after the sampling chain below: a graph replay starts its
+  // nodes in capture order, and the chain is the longer of the two)
+  // the descriptors' copy goes on the batch stream ahead of the fork point
+  // the state-vector streams wait for
+  FragDev *d_sv = nullptr;
   if (!b->nc.empty()) {
-    FragDev *d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
+    d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
     if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
-    if (n_sv_streams) {
-      HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+    if (n_sv_streams) HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
+  }
+  auto sv_pass = [&]() -> ccut_status {
+    if (!b->nc.empty()) {
+      // (the fork point was recorded before the sampling chain)
       for (size_t k = 0; k < n_sv_streams; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
-    }
-    // two launches per shape class: the first runs fragments without
-    // quantum inputs in full and evolves the computational-basis inputs of
-    // the others, the second combines those into their preparations; the
-    // classes go to the streams longest first, each to the stream with the
-    // least work so far (work: amplitudes times program length, summed over
-    // workgroups)
-    struct SvClass {
-      uint32_t m;
-      std::vector<SvJob> jobs[2];
-      uint64_t wg[2] = {0, 0};
-      size_t lds[2] = {0, 0};
-      double cost = 0.0;
-    };
-    std::vector<SvClass> classes;
-    for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
-      SvClass C;
-      C.m = m;
-      for (const auto &ref : b->nc) {
-        const FragDev &h = b->sv_descs[ref.desc];
-        if (h.m != m) continue;
-        double *dist = aget<double>(c, h.n_variants << ref.n_meas);
-        const size_t sb = sv_states_bytes(h);
-        double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
-        if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
-        pre_dist[ref.plan][ref.frag] = dist;
-        const uint32_t passes[2] = {sb ? 1u : 0u, 2u};
-        for (int k = 0; k < (sb ? 2 : 1); ++k) {
-          uint64_t n_wg;
-          uint32_t bs;
-          size_t l;
-          bool split;
-          sv_pass_shape(h, passes[k], n_wg, bs, l, split);
-          SvJob J{};
-          J.desc = ref.desc;
-          J.split = split ? 1u : 0u;
-          J.wg0 = C.wg[k];
-          J.dist = dist;
-          J.mode = passes[k];
-          J.states = states;
-          C.wg[k] += n_wg;
-          C.lds[k] = std::max(C.lds[k], l);
-          C.cost += (double)n_wg * (double)(1u << m) * (passes[k] == 2 ? 8.0 : (double)h.n_ops);
-          C.jobs[k].push_back(J);
+      // two launches per shape class: the first runs fragments without
+      // quantum inputs in full and evolves the computational-basis inputs of
+      // the others, the second combines those into their preparations; the
+      // classes go to the streams longest first, each to the stream with the
+      // least work so far (work: amplitudes times program length, summed over
+      // workgroups)
+      struct SvClass {
+        uint32_t m;
+        std::vector<SvJob> jobs[2];
+        uint64_t wg[2] = {0, 0};
+        size_t lds[2] = {0, 0};
+        double cost = 0.0;
+      };
+      std::vector<SvClass> classes;
+      for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+        SvClass C;
+        C.m = m;
+        for (const auto &ref : b->nc) {
+          const FragDev &h = b->sv_descs[ref.desc];
+          if (h.m != m) continue;
+          double *dist = aget<double>(c, h.n_variants << ref.n_meas);
+          const size_t sb = sv_states_bytes(h);
+          double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
+          if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
+          pre_dist[ref.plan][ref.frag] = dist;
+          const uint32_t passes[2] = {sb ? 1u : 0u, 2u};
+          for (int k = 0; k < (sb ? 2 : 1); ++k) {
+            uint64_t n_wg;
+            uint32_t bs;
+            size_t l;
+            bool split;
+            sv_pass_shape(h, passes[k], n_wg, bs, l, split);
+            SvJob J{};
+            J.desc = ref.desc;
+            J.split = split ? 1u : 0u;
+            J.wg0 = C.wg[k];
+            J.dist = dist;
+            J.mode = passes[k];
+            J.states = states;
+            C.wg[k] += n_wg;
+            C.lds[k] = std::max(C.lds[k], l);
+            C.cost += (double)n_wg * (double)(1u << m) * (passes[k] == 2 ? 8.0 : (double)h.n_ops);
+            C.jobs[k].push_back(J);
+          }
+        }
+        if (!C.jobs[0].empty()) classes.push_back(std::move(C));
+      }
+      std::stable_sort(classes.begin(), classes.end(),
+                       [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
+      std::vector<double> load(n_sv_streams, 0.0);
+      for (const SvClass &C : classes) {
+        if (n_sv_streams) {
+          const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+          load[k] += C.cost;
+          c->cur = b->pool[k];
+          sv_used[k] = 1;
+        }
+        for (int k = 0; k < 2; ++k) {
+          if (C.jobs[k].empty()) continue;
+          SvJob *d_jobs = (SvJob *)upload(c, C.jobs[k].data(), C.jobs[k].size() * sizeof(SvJob));
+          if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
+          KTimer tm(c, CCUT_K_SV);
+          HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs[k].size(), C.wg[k], C.m, C.lds[k], c->cur));
         }
       }
-      if (!C.jobs[0].empty()) classes.push_back(std::move(C));
+      c->cur = b->stream;
+      for (size_t k = 0; k < n_sv_streams; ++k)
+        if (sv_used[k]) HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
     }
-    std::stable_sort(classes.begin(), classes.end(),
-                     [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
-    std::vector<double> load(n_sv_streams, 0.0);
-    for (const SvClass &C : classes) {
-      if (n_sv_streams) {
-        const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += C.cost;
-        c->cur = b->pool[k];
-        sv_used[k] = 1;
-      }
-      for (int k = 0; k < 2; ++k) {
-        if (C.jobs[k].empty()) continue;
-        SvJob *d_jobs = (SvJob *)upload(c, C.jobs[k].data(), C.jobs[k].size() * sizeof(SvJob));
-        if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
-        KTimer tm(c, CCUT_K_SV);
-        HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs[k].size(), C.wg[k], C.m, C.lds[k], c->cur));
-      }
-    }
-    c->cur = b->stream;
-    for (size_t k = 0; k < n_sv_streams; ++k)
-      if (sv_used[k]) {
-        HIP_TRY(c, hipEventRecord(b->join_ev[k], b->pool[k]));
-        // the autotuner below times the tableau launch alone
-        if (tune) HIP_TRY(c, hipStreamSynchronize(b->pool[k]));
-      }
-  }
+    return CCUT_OK;
+  };
   uint64_t *d_rows = nullptr;
   if ((st = batch_carry(b, &d_rows)) != CCUT_OK) return st;
   if (tune && !b->items.empty()) {
@@ -2012,6 +2017,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       HIP_TRY(c, launch_hist_reduce_batch(d_jobs, (uint32_t)jobs.size(), t, c->cur));
     }
   }
+  if ((st = sv_pass()) != CCUT_OK) return st;
   for (size_t k = 0; k < n_sv_streams; ++k)
     if (sv_used[k]) HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
   // The plans' remaining steps.  Work that the batched launches below do
