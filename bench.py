@@ -475,11 +475,27 @@ def batching_work(cc, plans, ws, shots):
         k = len(w.cuts)
         K = 4 ** k
         rows = []
+        info = [cc.ccut_request_info(p.handle, w.qubits, f) for f in range(len(frags))]
+        # the fold target (the fragment with the most requested bits, first
+        # of equals, when all its cut axes are inputs) is read as its tables
+        # and has no transform; sampled tables are read as 16-bit counts
+        g = max(range(len(frags)), key=lambda f: (info[f][1], -f))
+        if not frags[g]["axes"] or any(a[1] != 1 for a in frags[g]["axes"]):
+            g = -1
+        # sampled tables kept as 16-bit counts: the fold target's when a
+        # matrix path contracts it, and every tiled fragment's
+        plain = len(frags) > 2 and (K << len(w.qubits)) <= (1 << 20)
+        c16 = set()
+        if shots <= 0xFFFF:
+            c16 = {f for f, fr in enumerate(frags)
+                   if fr["clifford"] and ((f == g and not plain) or (f != g and fr["axes"]))}
         for f, fr in enumerate(frags):
-            nm, nr = cc.ccut_request_info(p.handle, w.qubits, f)
+            nm, nr = info[f]
             nv = fr["n_variants"]
             rows.append(nr)
-            tr_bytes += 8.0 * (nv << nm) + 8.0 * ((4 ** len(fr["axes"])) << nr)
+            if fr["axes"] and f != g:
+                in_b = 2.0 if fr["clifford"] and shots <= 0xFFFF else 8.0
+                tr_bytes += in_b * (nv << nm) + 8.0 * ((4 ** len(fr["axes"])) << nr)
             if not fr["clifford"]:
                 continue
             W_ = (fr["m"] + 63) // 64
@@ -494,11 +510,11 @@ def batching_work(cc, plans, ws, shots):
             # select-and-xor (3 ops) per measurement, one histogram increment;
             # the variant's fp64 table written once
             samp_ops += nv * shots * (PHILOX_OPS / 4 * ((nm + 31) // 32) + 3 * nm + 1)
-            samp_bytes += 8.0 * (nv << nm)
+            samp_bytes += (2.0 if f in c16 else 8.0) * (nv << nm)
         M = 1 << min(rows) if len(rows) > 1 else 1
         N = 1 << max(rows)
         rc_flops += 2.0 * M * N * K
-        rc_bytes += 8.0 * K * (M + N) + 8.0 * M * N
+        rc_bytes += 8.0 * K * M + (2.0 if g in c16 else 8.0) * K * N + 8.0 * M * N
     return {"sv_kernel": (sv, "fp64"), "tableau_kernel": (tab_ops, "int"), "base_tableau_kernel": (base_ops, "int"),
             "sample_kernel": (samp_ops, "int"), "sample_kernel:bytes": (samp_bytes, "bytes"),
             "transform_pass_kernel": (tr_bytes, "bytes"), "recombine_fp64_kernel": (rc_flops, "fp64"),

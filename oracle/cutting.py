@@ -17,7 +17,8 @@ Readings where the paper is silent (its Fig. 2 is not available):
   the four prepared states);
 * a quantum output contributes  I = Z0 + Z1 (the I term comes from the
   Z-basis variant),  Z = Z0 - Z1,  X = X0 - X1,  Y = Y0 - Y1;
-* no maximum-likelihood correction: raw (possibly negative) estimates;
+* by default no maximum-likelihood correction: raw (possibly negative)
+  estimates (the correction is ``mlcorrect``, ml=True);
 * non-Clifford fragments are evaluated exactly, Clifford fragments either
   exactly ("strong simulation", Sec. V-C) or by sampling shots;
 * variant index: mixed radix over the fragment's incident cut axes in
@@ -394,8 +395,11 @@ def recombine_matmul(frags: Sequence[Fragment], reqs: Sequence[Request], tensors
 # ------------------------------------------------------------------ end to end
 
 def marginal(n: int, ops, cuts, qubits, *, shots: int = 0, seed: int = 0, circuit: int = 0,
-             exact_method: str = "branch", return_parts: bool = False, sparse: bool = False):
-    """Reconstructed output marginal over ``qubits`` (bit i = qubits[i])."""
+             exact_method: str = "branch", return_parts: bool = False, sparse: bool = False,
+             ml: bool = False):
+    """Reconstructed output marginal over ``qubits`` (bit i = qubits[i]).
+    ml: the variant tables first go through the maximum-likelihood fragment
+    correction (``mlcorrect``)."""
     qubits = list(qubits)
     if len(set(qubits)) != len(qubits) or any(not (0 <= q < n) for q in qubits):
         raise CutError("bad qubit request")
@@ -403,6 +407,9 @@ def marginal(n: int, ops, cuts, qubits, *, shots: int = 0, seed: int = 0, circui
     reqs = [make_request(f, qubits) for f in frags]
     dists = [variant_distributions(f, r.meas, shots=shots, seed=seed, circuit=circuit,
                                    exact_method=exact_method) for f, r in zip(frags, reqs)]
+    if ml:
+        from . import mlcorrect
+        dists = [mlcorrect.correct_tables(f, r, d) for f, r, d in zip(frags, reqs, dists)]
     tensors = [pauli_tensor(f, r, d) for f, r, d in zip(frags, reqs, dists)]
     R = recombine(frags, reqs, tensors, len(cuts), len(qubits), sparse=sparse)
     if return_parts:
