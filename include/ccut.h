@@ -168,9 +168,27 @@ typedef struct {
  *    Clifford variant's string expectation, which is -1, 0 or +1 on a
  *    stabilizer state, is settled from its shots: 0 if both parities
  *    occurred, else the common sign.
+ * Maximum-likelihood fragment correction (Sec. V-C, distribution builder:
+ * self-consistent fragment models before the contraction):
+ *  CCUT_FLAG_ML (ccut_marginal, ccut_variant_tables, ccut_fragment_tensor):
+ *    the variant tables of every fragment with quantum outputs are replaced
+ *    by those of the physical model nearest the data.  Per preparation
+ *    combination s of the quantum inputs, the model is the set of
+ *    conditional states rho_x of the quantum outputs jointly with outcome x
+ *    of the requested outputs; the data give rho_x by least-squares
+ *    inversion (each Pauli coefficient the mean over the basis combinations
+ *    that measure it); the correction projects the joint spectrum of the
+ *    rho_x onto the probability simplex (every rho_x positive
+ *    semidefinite, sum_x Tr rho_x = 1; the nearest such model in the
+ *    Frobenius norm, the maximum-likelihood one under Gaussian noise) and
+ *    writes back p(o, x | s, b) = Tr(Pi_{b,o} rho_x).  Exact data are left
+ *    unchanged up to rounding.  At most 2 quantum outputs and 8 quantum
+ *    inputs per corrected fragment (else CCUT_E_UNSUPPORTED); fragments
+ *    whose tensors come from the Heisenberg picture (exact mode) have no
+ *    tables and are exact already.
  * A flag outside its call's scope, or in a batch, is CCUT_E_UNSUPPORTED;
  * unknown bits are CCUT_E_INVALID. */
-enum { CCUT_FLAG_SPARSE = 1, CCUT_FLAG_SETTLE = 2 };
+enum { CCUT_FLAG_SPARSE = 1, CCUT_FLAG_SETTLE = 2, CCUT_FLAG_ML = 4 };
 
 /* ---------------------------------------------------------------- context */
 

@@ -25,7 +25,7 @@ CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
 CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
 CCUT_FP64, CCUT_FP32_MFMA_FP64SUM, CCUT_FP32X3_MFMA_FP64SUM = 0, 1, 2
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
-CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE = 1, 2
+CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE, CCUT_FLAG_ML = 1, 2, 4
 KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
            "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
            "heisenberg_kernels", "mlp_kernels", "term_kernels", "base_tableau_kernel")
@@ -512,19 +512,19 @@ class Plan:
                           v_begin, v_end, out)
         return out.reshape(v_end - v_begin, shots)
 
-    def variant_tables(self, qubits, fragment, *, shots=0, seed=0, circuit=0):
+    def variant_tables(self, qubits, fragment, *, shots=0, seed=0, circuit=0, flags=0):
         nm, _ = ccut_request_info(self.handle, qubits, fragment)
         nv = ccut_fragment_info(self.handle, fragment)[3]
         out = np.zeros(nv << nm, dtype=np.float64)
-        ccut_variant_tables(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits, fragment,
-                            out)
+        ccut_variant_tables(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, flags=flags), qubits,
+                            fragment, out)
         return out.reshape(nv, 1 << nm)
 
-    def fragment_tensor(self, qubits, fragment, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO):
+    def fragment_tensor(self, qubits, fragment, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO, flags=0):
         _, nr = ccut_request_info(self.handle, qubits, fragment)
         na = ccut_fragment_info(self.handle, fragment)[2]
         out = np.zeros((4 ** na) << nr, dtype=np.float64)
-        ccut_fragment_tensor(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, method), qubits,
+        ccut_fragment_tensor(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, method, flags), qubits,
                              fragment, out)
         return out.reshape(4 ** na, 1 << nr)
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libccut.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = ["plan.cpp", "cutfind.cpp", "api.cpp", "k_sample.hip", "k_sv.hip", "k_contract.hip", "k_heis.hip",
-           "k_gemm.hip", "k_mlp.hip", "k_affine.hip"]
+           "k_gemm.hip", "k_mlp.hip", "k_mlc.hip", "k_affine.hip"]
 ARCH = os.environ.get("CCUT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -286,7 +286,7 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
       eo->precision != CCUT_FP32X3_MFMA_FP64SUM)
     return fail(c, CCUT_E_INVALID, "unknown precision mode");
   if (eo->method > CCUT_METHOD_HEISENBERG) return fail(c, CCUT_E_INVALID, "unknown evaluation method");
-  if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE))
+  if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE | CCUT_FLAG_ML))
     return fail(c, CCUT_E_INVALID, "unknown evaluation flag");
   // shot counters and histogram counts are 32-bit per variant
   if (eo->shots_per_variant > 0xFFFFFFFFull)
@@ -472,6 +472,41 @@ ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, ui
 // Per-variant outcome distributions dist[v][x] over the measured set.
 // cnt_out (sampled Clifford fragments, fewer than 2^16 shots): the tables
 // as 16-bit shot counts into *cnt_out instead (*dist_out null).
+// Maximum-likelihood correction of a fragment's variant tables, in place
+// (Sec. V-C, distribution builder; launch_ml_correct).  Fragments without
+// quantum outputs keep their tables: sampled histograms already are
+// physical models.
+ccut_status ml_correct(ccut_ctx *c, const Fragment &f, const FragRequest &r, double *dist) {
+  MlJob J{};
+  uint64_t stride = 1;
+  for (size_t j = 0; j < f.axes.size(); ++j) {
+    if (f.axes[j].side == 0) {
+      if (J.n_out == kMlMaxOut)
+        return fail(c, CCUT_E_UNSUPPORTED, "maximum-likelihood correction of more than 2 quantum outputs");
+      J.opos[J.n_out] = (uint32_t)r.axis_outpos[j];
+      J.ostride[J.n_out++] = (uint32_t)stride;
+    } else {
+      J.istride[J.n_in++] = (uint32_t)stride;
+    }
+    stride *= f.axes[j].radix();
+  }
+  if (J.n_out == 0) return CCUT_OK;
+  if (J.n_in > 8) return fail(c, CCUT_E_UNSUPPORTED, "maximum-likelihood correction of more than 8 quantum inputs");
+  J.n_req = (uint32_t)r.req_pos.size();
+  for (uint32_t i = 0; i < J.n_req; ++i) J.xpos[i] = r.req_pos[i];
+  J.dist = dist;
+  J.nx = 1ull << J.n_req;
+  J.row_len = 1ull << r.meas.size();
+  J.n_prep = 1u << (2 * J.n_in);
+  J.eig = aget<double>(c, (size_t)J.n_prep * J.nx << J.n_out);
+  J.tau = aget<double>(c, J.n_prep);
+  MlJob *d = (MlJob *)upload(c, &J, sizeof(MlJob));
+  if (!J.eig || !J.tau || !d) return fail(c, CCUT_E_OOM, "device allocation failed");
+  KTimer t(c, CCUT_K_TRANSFORM);
+  HIP_TRY(c, launch_ml_correct(J, d, c->cur));
+  return CCUT_OK;
+}
+
 ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment &f,
                           const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr,
                           uint16_t **cnt_out = nullptr) {
@@ -545,6 +580,10 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     }
   }
   *dist_out = dist;
+  if ((eo->flags & CCUT_FLAG_ML) && dist) {
+    ccut_status st = ml_correct(c, f, r, dist);
+    if (st != CCUT_OK) return st;
+  }
   return cancelled(c);
 }
 
@@ -1378,6 +1417,7 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   ccut_ctx *c = p->ctx;
   if (!out || (n_strings && !masks)) return fail(c, CCUT_E_INVALID, "NULL argument");
   if (eo->flags & CCUT_FLAG_SPARSE) return fail(c, CCUT_E_UNSUPPORTED, "the sparse contraction applies to marginals");
+  if (eo->flags & CCUT_FLAG_ML) return fail(c, CCUT_E_UNSUPPORTED, "the maximum-likelihood correction applies to outcome tables");
   if (n_strings == 0) return CCUT_OK;
   const PlanData &pd = p->pd;
   if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
@@ -1541,6 +1581,7 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   if ((st = check_request(c, p->pd.n, qubits, nq, p->pd.n)) != CCUT_OK) return st;
   const Fragment &f = p->pd.frags[fragment];
   if (!f.clifford) return fail(c, CCUT_E_INVALID, "shot records exist only for Clifford fragments");
+  if (eo->flags) return fail(c, CCUT_E_UNSUPPORTED, "evaluation flags do not apply to shot records");
   if (eo->shots_per_variant == 0) return fail(c, CCUT_E_INVALID, "shot records need shots > 0");
   if (v_begin > v_end || v_end > f.n_variants) return fail(c, CCUT_E_INVALID, "bad variant range");
   const uint64_t nv = v_end - v_begin;
@@ -2778,6 +2819,7 @@ ccut_status ccut_learned_create(ccut_plan *p, const ccut_eval_opts *eo, const ui
   const PlanData &pd = p->pd;
   if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
   if (pd.k == 0 || pd.k > 12) return fail(c, CCUT_E_UNSUPPORTED, "the term model needs 1 to 12 cuts");
+  if (eo->flags & CCUT_FLAG_ML) return fail(c, CCUT_E_UNSUPPORTED, "the maximum-likelihood correction applies to marginals");
   std::unique_ptr<ccut_learned> L(new (std::nothrow) ccut_learned());
   if (!L) return fail(c, CCUT_E_OOM, "host allocation failed");
   L->ctx = c;

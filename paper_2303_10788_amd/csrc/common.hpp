@@ -393,6 +393,24 @@ struct FoldJob {
 };
 hipError_t launch_fold(const FoldJob *d_jobs, uint32_t n_jobs, hipStream_t s);
 
+// Maximum-likelihood correction of one fragment's variant tables (in
+// place): n_out (1 or 2) quantum outputs, n_in inputs.
+constexpr uint32_t kMlMaxOut = 2;
+struct MlJob {
+  double *dist;       // [n_variants][row_len] tables, corrected in place
+  double *eig;        // scratch: [n_prep][nx][2^n_out] eigenvalues
+  double *tau;        // scratch: [n_prep] simplex shifts
+  uint64_t nx;        // 2^n_req outcomes of the requested outputs
+  uint64_t row_len;   // 2^(measured bits)
+  uint32_t n_prep;    // 4^n_in
+  uint32_t n_out, n_in, n_req;
+  uint32_t opos[kMlMaxOut];     // outcome bit of each quantum output (axis order)
+  uint32_t ostride[kMlMaxOut];  // its variant-index stride
+  uint32_t istride[kMaxAxes];   // variant-index stride of each quantum input (axis order)
+  uint32_t xpos[32];            // outcome bit of each requested output
+};
+hipError_t launch_ml_correct(const MlJob &h, const MlJob *d_job, hipStream_t s);
+
 struct RecombFrag {
   const double *T;          // T_f[p_f][row], row count `rows`
   uint32_t cnt16;           // 1: T holds 16-bit shot counts, the value is count / shots
