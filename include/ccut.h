@@ -247,16 +247,17 @@ ccut_status ccut_fragment_axes(const ccut_plan *plan, uint32_t f, uint32_t *cut,
  * bit i of b = outcome of qubits[i].  out has 2^nq doubles, caller-owned,
  * on the device if out_on_device else on the host.  nq <= 24.
  * Errors: CCUT_E_INVALID (repeated or out-of-range qubit, nq > 24),
- * CCUT_E_DEVICE (host-only context), CCUT_E_UNSUPPORTED (a Clifford
- * fragment with more than 64 measured qubits, or an exact table over
- * more than 24 measured qubits), CCUT_E_CANCELLED, CCUT_E_OOM. */
+ * CCUT_E_DEVICE (host-only context), CCUT_E_UNSUPPORTED (an outcome
+ * table over more than 24 measured qubits), CCUT_E_CANCELLED, CCUT_E_OOM. */
 ccut_status ccut_marginal(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
                           uint32_t nq, double *out, int out_on_device);
 
 /* <Z_z> for n_strings masks; masks is a host array [n_strings][ceil(n/64)]
  * of uint64 words (bit q of the mask = qubit q).  out has n_strings doubles.
  * Each fragment measures its circuit outputs that occur in any mask plus
- * its quantum outputs (at most 64 for a sampled Clifford fragment).
+ * its quantum outputs (at most 1024 for a Clifford fragment evaluated
+ * from its variants: sampled, or exact with CCUT_METHOD_VARIANTS; beyond
+ * 64 its sample models span several words per outcome vector).
  * In exact mode each Clifford variant gives -1, 0 or +1 (Sec. IX). */
 ccut_status ccut_zexpect(ccut_plan *plan, const ccut_eval_opts *eo, const uint64_t *masks,
                          uint32_t n_strings, double *out, int out_on_device);
@@ -275,8 +276,10 @@ ccut_status ccut_call_graphs(ccut_ctx *ctx, int enable);
 
 /* Parity hook: the sampled shot records of Clifford fragment `fragment`
  * for variants [v_begin, v_end) under the marginal request qubits[0..nq):
- * out[(v - v_begin) * shots + s] holds the outcome bits of shot s (bit j =
- * measurement j of the measured set, at most 64).  Needs shots > 0. */
+ * with RW = 1 for at most 64 measured qubits, else ceil(n_meas / 64),
+ * out[((v - v_begin) * shots + s) * RW + w] holds outcome bits 64 w ..
+ * 64 w + 63 of shot s (bit j = measurement j of the measured set, at most
+ * 1024).  Needs shots > 0. */
 ccut_status ccut_shot_records(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
                               uint32_t nq, uint32_t fragment, uint64_t v_begin, uint64_t v_end,
                               uint64_t *out, int out_on_device);

@@ -507,10 +507,15 @@ class Plan:
         return out
 
     def shot_records(self, qubits, fragment, v_begin, v_end, *, shots, seed=0, circuit=0):
-        out = np.zeros((v_end - v_begin) * shots, dtype=np.uint64)
+        """uint64 records [variant][shot] (at most 64 measurements), else
+        [variant][shot][ceil(n_meas / 64)] (bit j of word w = measurement
+        64 w + j)."""
+        nm, _ = ccut_request_info(self.handle, qubits, fragment)
+        rw = (nm + 63) // 64 if nm > 64 else 1
+        out = np.zeros((v_end - v_begin) * shots * rw, dtype=np.uint64)
         ccut_shot_records(self.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit), qubits, fragment,
                           v_begin, v_end, out)
-        return out.reshape(v_end - v_begin, shots)
+        return out.reshape(v_end - v_begin, shots) if rw == 1 else out.reshape(v_end - v_begin, shots, rw)
 
     def variant_tables(self, qubits, fragment, *, shots=0, seed=0, circuit=0, flags=0):
         nm, _ = ccut_request_info(self.handle, qubits, fragment)

@@ -447,12 +447,40 @@ std::vector<uint64_t> measured_rows(const FragDev &h, uint32_t W) {
 // its measured Paulis are carried back through the fragment once (the
 // reversed stream of inverse gates), then one wave per variant eliminates
 // them against the variant's prepared product state (Heisenberg picture).
-ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, uint64_t v0, uint64_t nv,
-                           uint64_t *models) {
+// The same rows for a measured set of any size (meas: local qubits in
+// measured order); row_of[j] = the first row of measurement j, meas_axis[j]
+// = the axis of a quantum output, else -1.
+std::vector<uint64_t> measured_rows(const Fragment &f, const std::vector<uint32_t> &meas, uint32_t W,
+                                    std::vector<uint16_t> *row_of = nullptr, std::vector<int8_t> *meas_axis = nullptr) {
+  const uint32_t RW = 2 * W + 1;
+  std::vector<uint64_t> rows;
+  auto add = [&](bool xpart, uint32_t q) {
+    std::vector<uint64_t> row(RW, 0);
+    row[(xpart ? 0 : W) + (q >> 6)] = 1ull << (q & 63);
+    rows.insert(rows.end(), row.begin(), row.end());
+  };
+  for (uint32_t q : meas) {
+    int axis = -1;
+    for (size_t a = 0; a < f.axes.size(); ++a)
+      if (f.axes[a].side == 0 && f.axes[a].local == q) axis = (int)a;
+    if (row_of) row_of->push_back((uint16_t)(rows.size() / RW));
+    if (meas_axis) meas_axis->push_back((int8_t)axis);
+    if (axis >= 0) add(true, q);
+    add(false, q);
+  }
+  return rows;
+}
+
+ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, const FragRequest &r, uint64_t v0,
+                           uint64_t nv, uint64_t *models) {
   ccut_ctx *c = p->ctx;
   const uint32_t W = row_words(f.m());
   if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
-  std::vector<uint64_t> rows = measured_rows(h, W);
+  const uint32_t nm = (uint32_t)r.meas.size();
+  if (nm > (uint32_t)kMaxMeasWide) return fail(c, CCUT_E_UNSUPPORTED, "more than 1024 measured qubits in a fragment");
+  std::vector<uint16_t> row_of;
+  std::vector<int8_t> meas_axis;
+  std::vector<uint64_t> rows = measured_rows(f, r.meas, W, &row_of, &meas_axis);
   const uint32_t n_rows = (uint32_t)(rows.size() / (2 * W + 1));
   if (rows.empty()) rows.assign(2 * W + 1, 0);  // nothing measured: a valid buffer all the same
   uint64_t *d_in = (uint64_t *)upload(c, rows.data(), rows.size() * 8);
@@ -463,9 +491,19 @@ ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, ui
   hb.n_ops = p->n_back[f.index];
   hb.layers = p->d_back_layers[f.index];
   hb.n_layers = p->n_back_layers[f.index];
+  int8_t *d_axis = nullptr;
+  uint16_t *d_row = nullptr;
+  if (nm > (uint32_t)kMaxMeas) {
+    d_axis = (int8_t *)upload(c, meas_axis.data(), meas_axis.size());
+    d_row = (uint16_t *)upload(c, row_of.data(), row_of.size() * 2);
+    if (!d_axis || !d_row) return fail(c, CCUT_E_OOM, "device allocation failed");
+  }
   KTimer t(c, CCUT_K_TABLEAU);
   HIP_TRY(c, launch_rows(hb, W, d_in, d_out, n_rows, c->cur));
-  HIP_TRY(c, launch_affine(h, W, d_out, v0, nv, models, c->cur));
+  if (nm > (uint32_t)kMaxMeas)
+    HIP_TRY(c, launch_affine_wide(h, W, d_axis, d_row, nm, d_out, v0, nv, models, c->cur));
+  else
+    HIP_TRY(c, launch_affine(h, W, d_out, v0, nv, models, c->cur));
   return CCUT_OK;
 }
 
@@ -536,7 +574,7 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     if (!models) {
       models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
-      ccut_status st2 = tableau_models(p, f, h, 0, nv, models);
+      ccut_status st2 = tableau_models(p, f, h, r, 0, nv, models);
       if (st2 != CCUT_OK) return st2;
     }
     if (eo->shots_per_variant == 0) {
@@ -1456,30 +1494,36 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
       for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
       continue;
     }
-    if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits in a fragment");
-    // extended masks [J][string] over measured positions
+    // a non-Clifford fragment's tables, or a Clifford fragment's models
+    // (one outcome vector of MW words; more than 64 measurements: wide)
+    if (!f.clifford && nm > (uint32_t)kMaxTableBits)
+      return fail(c, CCUT_E_UNSUPPORTED, "outcome table over more than 24 measured qubits");
+    if (nm > (uint32_t)kMaxMeasWide) return fail(c, CCUT_E_UNSUPPORTED, "more than 1024 measured qubits in a fragment");
+    const bool wide = nm > (uint32_t)kMaxMeas;
+    const uint32_t MW = model_mw(nm);
+    // extended masks [J][string][MW words] over measured positions
     std::vector<uint32_t> outpos;
     for (size_t j = 0; j < f.axes.size(); ++j)
       if (f.axes[j].side == 0) outpos.push_back((uint32_t)r.axis_outpos[j]);
     const uint32_t n_out = (uint32_t)outpos.size();
     if (n_out > 12) return fail(c, CCUT_E_UNSUPPORTED, "more than 12 quantum outputs in a fragment");
     const uint32_t n_ext = n_strings << n_out;
-    std::vector<uint64_t> ext(n_ext);
+    std::vector<uint64_t> ext((size_t)n_ext * MW, 0);
     for (uint32_t s = 0; s < n_strings; ++s) {
-      uint64_t z = 0;
+      std::vector<uint64_t> z(MW, 0);
       for (uint32_t jpos = 0; jpos < nm; ++jpos) {
         const uint32_t wire = f.wires[r.meas[jpos]];
         const bool is_cout = f.out_local[wire] == (int32_t)r.meas[jpos];
-        if (is_cout && ((masks[(size_t)s * nw + (wire >> 6)] >> (wire & 63)) & 1ull)) z |= 1ull << jpos;
+        if (is_cout && ((masks[(size_t)s * nw + (wire >> 6)] >> (wire & 63)) & 1ull)) z[jpos >> 6] |= 1ull << (jpos & 63);
       }
       for (uint32_t J = 0; J < (1u << n_out); ++J) {
-        uint64_t e = z;
+        uint64_t *e = &ext[((size_t)J * n_strings + s) * MW];
+        for (uint32_t w = 0; w < MW; ++w) e[w] = z[w];
         for (uint32_t i = 0; i < n_out; ++i)
-          if ((J >> i) & 1u) e |= 1ull << outpos[i];
-        ext[(size_t)J * n_strings + s] = e;
+          if ((J >> i) & 1u) e[outpos[i] >> 6] |= 1ull << (outpos[i] & 63);
       }
     }
-    uint64_t *d_ext = (uint64_t *)upload(c, ext.data(), n_ext * 8);
+    uint64_t *d_ext = (uint64_t *)upload(c, ext.data(), ext.size() * 8);
     double *E = aget<double>(c, nv * n_ext);
     if (!d_ext || !E) return fail(c, CCUT_E_OOM, "device allocation failed");
     const FragDev h = frag_desc(p, f, r, eo->circuit);
@@ -1498,12 +1542,15 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
       uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
       {
-        ccut_status st2 = tableau_models(p, f, h, 0, nv, models);
+        ccut_status st2 = tableau_models(p, f, h, r, 0, nv, models);
         if (st2 != CCUT_OK) return st2;
       }
       if (eo->shots_per_variant == 0) {
         KTimer t(c, CCUT_K_PARITY);
-        HIP_TRY(c, launch_parity_exact(models, nm, nv, d_ext, n_ext, E, c->cur));
+        if (wide)
+          HIP_TRY(c, launch_parity_exact_wide(models, nm, nv, d_ext, n_ext, E, c->cur));
+        else
+          HIP_TRY(c, launch_parity_exact(models, nm, nv, d_ext, n_ext, E, c->cur));
       } else {
         uint32_t *odd = aget<uint32_t>(c, nv * n_ext);
         if (!odd) return fail(c, CCUT_E_OOM, "device allocation failed");
@@ -1511,9 +1558,14 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
         for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
           const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
           KTimer t(c, CCUT_K_PARITY);
-          HIP_TRY(c, launch_parity_sampled(models + v0 * model_words(nm), nm, cnv, eo->shots_per_variant,
-                                           eo->seed, h.vid_base + v0, d_ext, n_ext, odd + v0 * n_ext,
-                                           c->cur));
+          if (wide)
+            HIP_TRY(c, launch_parity_sampled_wide(models + v0 * model_words(nm), nm, cnv, eo->shots_per_variant,
+                                                  eo->seed, h.vid_base + v0, d_ext, n_ext, odd + v0 * n_ext,
+                                                  c->cur));
+          else
+            HIP_TRY(c, launch_parity_sampled(models + v0 * model_words(nm), nm, cnv, eo->shots_per_variant,
+                                             eo->seed, h.vid_base + v0, d_ext, n_ext, odd + v0 * n_ext,
+                                             c->cur));
         }
         HIP_TRY(c, launch_parity_finish(odd, nv * n_ext, eo->shots_per_variant, (eo->flags & CCUT_FLAG_SETTLE) != 0,
                                         E, c->cur));
@@ -1588,24 +1640,30 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   if (nv == 0) return CCUT_OK;
   FragRequest r = marginal_request(f, qubits, nq);
   const uint32_t nm = (uint32_t)r.meas.size();
-  if (nm > (uint32_t)kMaxMeas) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 measured qubits");
+  if (nm > (uint32_t)kMaxMeasWide) return fail(c, CCUT_E_UNSUPPORTED, "more than 1024 measured qubits");
+  const bool wide = nm > (uint32_t)kMaxMeas;
+  const uint32_t RW = wide ? (nm + 63) / 64 : 1;  // record words
   const FragDev h = frag_desc(p, f, r, eo->circuit);
   uint64_t *models = aget<uint64_t>(c, nv * model_words(nm));
   const uint64_t shots = eo->shots_per_variant;
-  uint64_t *rec = aget<uint64_t>(c, nv * shots);
+  uint64_t *rec = aget<uint64_t>(c, nv * shots * RW);
   if (!models || !rec) return fail(c, CCUT_E_OOM, "device allocation failed");
-  if ((st = tableau_models(p, f, h, v_begin, nv, models)) != CCUT_OK) return st;
+  if ((st = tableau_models(p, f, h, r, v_begin, nv, models)) != CCUT_OK) return st;
   const uint64_t nquads = (shots + 3) / 4;
   for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
     const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
     const uint32_t nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 255) / 256, 4096));
     const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
     KTimer t(c, CCUT_K_SAMPLE);
-    HIP_TRY(c, launch_sample_hist(models + v0 * model_words(nm), nm, cnv, shots, eo->seed,
-                                  h.vid_base + v_begin + v0, nullptr, nblk, qpt, rec + v0 * shots, c->cur));
+    if (wide)
+      HIP_TRY(c, launch_records_wide(models + v0 * model_words(nm), nm, cnv, shots, eo->seed, h.vid_base + v_begin + v0,
+                                     rec + v0 * shots * RW, c->cur));
+    else
+      HIP_TRY(c, launch_sample_hist(models + v0 * model_words(nm), nm, cnv, shots, eo->seed,
+                                    h.vid_base + v_begin + v0, nullptr, nblk, qpt, rec + v0 * shots, c->cur));
   }
-  HIP_TRY(c, hipMemcpyAsync(out, rec, nv * shots * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                            c->cur));
+  HIP_TRY(c, hipMemcpyAsync(out, rec, nv * shots * RW * 8,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->cur));
   HIP_TRY(c, hipStreamSynchronize(c->cur));
   return CCUT_OK;
 }

@@ -180,7 +180,16 @@ struct FragDev {
 // Per-variant affine sample model of a Clifford variant: a shot's outcome
 // bits are x = x0 ^ (xor of G[:, a] over the random measurements a whose
 // Philox bit is 1).  Layout per variant: [x0, randmask, Gcol[0..n_meas)].
-__host__ __device__ inline uint32_t model_words(uint32_t n_meas) { return 2u + n_meas; }
+// Words of one outcome vector in a model: 1 up to 64 measurements, else
+// the power of two at or above ceil(n / 64) (at most 16: kMaxMeasWide).
+// Model: x0, randmask, then G[a] for each measurement a, each that many
+// words.
+constexpr int kMaxMeasWide = 1024;
+__host__ __device__ inline uint32_t model_mw(uint32_t n_meas) {
+  const uint32_t w = (n_meas + 63) / 64;
+  return w <= 1 ? 1u : w <= 2 ? 2u : w <= 4 ? 4u : w <= 8 ? 8u : 16u;
+}
+__host__ __device__ inline uint32_t model_words(uint32_t n_meas) { return model_mw(n_meas) * (2u + n_meas); }
 
 // One unit of the batched model launch: variant `variant` of descriptor
 // `desc`, its model written at word offset `model_off`.
@@ -305,6 +314,16 @@ hipError_t launch_parity_sampled(const uint64_t *models, uint32_t n_meas, uint64
                                  uint32_t n_ext, uint32_t *odd_counts, hipStream_t s);
 hipError_t launch_parity_finish(const uint32_t *odd_counts, uint64_t n, uint64_t shots, bool settle, double *E,
                                 hipStream_t s);
+// The same over more than 64 measurements (wide models, model_mw words per
+// vector): ext_masks [n_ext][model_mw], odd_counts zeroed by the caller;
+// shot records [nv][shots][ceil(n_meas / 64)].
+hipError_t launch_parity_exact_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, const uint64_t *ext_masks,
+                                    uint32_t n_ext, double *E, hipStream_t s);
+hipError_t launch_parity_sampled_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
+                                      uint64_t seed, uint64_t vid0, const uint64_t *ext_masks, uint32_t n_ext,
+                                      uint32_t *odd_counts, hipStream_t s);
+hipError_t launch_records_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots, uint64_t seed,
+                               uint64_t vid0, uint64_t *records, hipStream_t s);
 hipError_t launch_dist_parity(const double *dist, uint32_t n_meas, uint64_t nv,
                               const uint64_t *ext_masks, uint32_t n_ext, double *E, hipStream_t s);
 // One Pauli-basis pass over cut axis j: mode 0 = quantum input (4 -> 4),
@@ -376,6 +395,12 @@ hipError_t launch_carry_batch(const FragDev *descs, const CarryJob *jobs, uint32
 // variant): rows as built by measured_rows on the host, W words per half.
 hipError_t launch_affine(const FragDev &F, uint32_t W, const uint64_t *rows, uint64_t v0, uint64_t nv,
                          uint64_t *models, hipStream_t s);
+// More than 64 measurements (up to kMaxMeasWide): one workgroup per
+// variant; meas_axis[j] = the axis of measurement j if it is a quantum
+// output, else -1; row_of[j] = its first row in `rows`.
+hipError_t launch_affine_wide(const FragDev &F, uint32_t W, const int8_t *meas_axis, const uint16_t *row_of,
+                              uint32_t n_meas, const uint64_t *rows, uint64_t v0, uint64_t nv, uint64_t *models,
+                              hipStream_t s);
 // desc_w[d]: row width of descriptor d; BatchItem::base_off: word offset of
 // the item's fragment rows; block threads (a multiple of 64), grid blocks.
 hipError_t launch_affine_batch(const FragDev *descs, const uint32_t *desc_w, const BatchItem *items, uint32_t n_items,

@@ -248,7 +248,212 @@ __global__ __launch_bounds__(1024) void affine_batch_kernel(const FragDev *__res
   }
 }
 
+// More than 64 measurements: one workgroup per variant, wave t's lane l
+// holding measurement 64 t + l (meas_axis[j]: the axis of a quantum output,
+// else -1; row_of[j]: its first carried-back row).  The elimination is the
+// same, each step's pivot measurement broadcast through LDS (double
+// buffered: one barrier per step).  The combination of a deterministic
+// measurement holds itself and random measurements only (only pivots are
+// ever folded into another vector), so its outcome is its sign plus the
+// random outcomes of the rest of its combination: G[a] (the outcomes that
+// random bit a flips) is a itself plus every deterministic j whose
+// combination holds a.  Model: x0[MW], rmask[MW], G[a][MW] for a < n.
+template <int W, int MW>
+__global__ __launch_bounds__(1024) void affine_wide_kernel(const FragDev F, const int8_t *__restrict__ meas_axis,
+                                                           const uint16_t *__restrict__ row_of, uint32_t n,
+                                                           const uint64_t *__restrict__ rows, uint64_t v0,
+                                                           uint64_t *__restrict__ models) {
+  struct Bcast {
+    uint64_t c[W], x[W], z[W], rec[MW];
+    uint32_t a;
+  };
+  __shared__ Bcast s_b[2];
+  const uint32_t me = threadIdx.x, lane = me & 63u, wave = me >> 6;
+  const bool live = me < n;
+  const uint64_t v = v0 + blockIdx.x;
+  uint64_t *out = models + blockIdx.x * (uint64_t)model_words(n);
+  uint64_t one[W], px[W], py[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) one[w] = px[w] = py[w] = 0;
+  const int my_axis = live ? (int)meas_axis[me] : -1;
+  bool is_out = my_axis >= 0;
+  uint32_t bdig = 2;
+  {
+    uint64_t t = v;
+    for (uint32_t j = 0; j < F.n_axes; ++j) {
+      const uint32_t radix = F.axis_radix[j];
+      const uint32_t d = (uint32_t)(t % radix);
+      t /= radix;
+      const uint32_t q = F.axis_local[j];
+      if (F.axis_side[j] == 1) {
+        const uint64_t bit = 1ull << (q & 63);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if ((q >> 6) == (uint32_t)w) {
+            if (d == 1) one[w] |= bit;
+            if (d == 2) px[w] |= bit;
+            if (d == 3) py[w] |= bit;
+          }
+      } else if ((int)j == my_axis) {
+        bdig = d;  // X 0, Y 1, Z 2
+      }
+    }
+  }
+  constexpr uint32_t RS = 2 * W + 1;
+  uint64_t x[W], z[W];
+  uint32_t a = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) x[w] = z[w] = 0;
+  if (live) {
+    const uint64_t *R = rows + (size_t)row_of[me] * RS;
+    const uint64_t *Q = (is_out && bdig == 2) ? R + RS : R;  // a quantum output in Z: its Z row
+    uint32_t pr = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      x[w] = Q[w];
+      z[w] = Q[W + w];
+      pr += __popcll(x[w] & z[w]);
+    }
+    a = (2u * ((uint32_t)Q[2 * W] & 1u) + pr) & 3u;
+    if (is_out && bdig == 1) {  // Y = i X Z from the X and Z rows
+      const uint64_t *Z = R + RS;
+      uint32_t cross = 0, pq = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        cross += __popcll(z[w] & Z[w]);
+        pq += __popcll(Z[w] & Z[W + w]);
+      }
+      a = (a + 1u + 2u * ((uint32_t)Z[2 * W] & 1u) + pq + 2u * cross) & 3u;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        x[w] ^= Z[w];
+        z[w] ^= Z[W + w];
+      }
+    }
+  }
+  uint64_t col[W], rec[MW];
+#pragma unroll
+  for (int w = 0; w < W; ++w) col[w] = (x[w] & ~(px[w] | py[w])) | (z[w] & px[w]) | ((x[w] ^ z[w]) & py[w]);
+#pragma unroll
+  for (int w = 0; w < MW; ++w) rec[w] = (live && (me >> 6) == (uint32_t)w) ? 1ull << lane : 0ull;
+  bool det = false;
+  for (uint32_t j = 0; j < n; ++j) {
+    Bcast &B = s_b[j & 1];
+    if (me == j) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        B.c[w] = col[w];
+        B.x[w] = x[w];
+        B.z[w] = z[w];
+      }
+#pragma unroll
+      for (int w = 0; w < MW; ++w) B.rec[w] = rec[w];
+      B.a = a;
+    }
+    __syncthreads();
+    uint64_t c[W], nz = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      c[w] = B.c[w];
+      nz |= c[w];
+    }
+    if (nz == 0) {  // uniform: measurement j is deterministic
+      det |= me == j;
+      continue;
+    }
+    uint32_t pw = 0;
+    uint64_t pb = 0;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w)
+      if (c[w]) {
+        pw = (uint32_t)w;
+        pb = c[w] & (0ull - c[w]);
+      }
+    uint64_t cw = col[0];
+#pragma unroll
+    for (int w = 1; w < W; ++w)
+      if (pw == (uint32_t)w) cw = col[w];
+    if (live && me > j && (cw & pb)) {
+      uint32_t cross = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) cross += __popcll(z[w] & B.x[w]);
+      a = (a + B.a + 2u * cross) & 3u;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        col[w] ^= c[w];
+        x[w] ^= B.x[w];
+        z[w] ^= B.z[w];
+      }
+#pragma unroll
+      for (int w = 0; w < MW; ++w) rec[w] ^= B.rec[w];
+    }
+  }
+  uint32_t cst = 0;
+  if (det) {
+    uint32_t ny = 0, n1 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      ny += __popcll(x[w] & z[w] & py[w]);
+      n1 += __popcll(z[w] & one[w]);
+    }
+    cst = ((a + 3u * ny + 2u * n1) & 3u) >> 1;
+  }
+  // wave t writes word t of every model vector
+  const uint64_t x0 = __ballot(live && det && cst);
+  const uint64_t rmask = __ballot(live && !det);
+  if (lane == 0 && wave < (uint32_t)MW) {
+    out[wave] = x0;
+    out[MW + wave] = rmask;
+  }
+  for (uint32_t aa = 0; aa < n; ++aa) {
+    uint64_t rw = rec[0];
+#pragma unroll
+    for (int w = 1; w < MW; ++w)
+      if ((aa >> 6) == (uint32_t)w) rw = rec[w];
+    const bool bit = live && (me == aa ? !det : (det && ((rw >> (aa & 63)) & 1ull)));
+    const uint64_t g = __ballot(bit);
+    if (lane == 0 && wave < (uint32_t)MW) out[2 * MW + (uint64_t)aa * MW + wave] = g;
+  }
+  // words of waves beyond the measurements (MW rounded up): zero
+  if (lane == 0)
+    for (uint32_t w = (n + 63) / 64 + wave; w < (uint32_t)MW; w += blockDim.x / 64) {
+      out[w] = 0;
+      out[MW + w] = 0;
+      for (uint32_t aa = 0; aa < n; ++aa) out[2 * MW + (uint64_t)aa * MW + w] = 0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_affine_wide(const FragDev &F, uint32_t W, const int8_t *meas_axis, const uint16_t *row_of,
+                              uint32_t n_meas, const uint64_t *rows, uint64_t v0, uint64_t nv, uint64_t *models,
+                              hipStream_t s) {
+  if (nv == 0) return hipSuccess;
+  const uint32_t MW = model_mw(n_meas);
+  if (n_meas > (uint32_t)kMaxMeasWide || (W != 1 && W != 2 && W != 4 && W != 8) || F.m > 64 * W ||
+      nv > 0x7FFFFFFFull)
+    return hipErrorInvalidValue;
+  const dim3 g((unsigned)nv), b(64 * ((n_meas + 63) / 64));
+#define CCUT_AFFINE_WIDE(WW, MM) \
+  hipLaunchKernelGGL((affine_wide_kernel<WW, MM>), g, b, 0, s, F, meas_axis, row_of, n_meas, rows, v0, models)
+#define CCUT_AFFINE_WIDE_W(MM)          \
+  switch (W) {                          \
+    case 1: CCUT_AFFINE_WIDE(1, MM); break; \
+    case 2: CCUT_AFFINE_WIDE(2, MM); break; \
+    case 4: CCUT_AFFINE_WIDE(4, MM); break; \
+    default: CCUT_AFFINE_WIDE(8, MM); break; \
+  }
+  switch (MW) {
+    case 1: CCUT_AFFINE_WIDE_W(1); break;
+    case 2: CCUT_AFFINE_WIDE_W(2); break;
+    case 4: CCUT_AFFINE_WIDE_W(4); break;
+    case 8: CCUT_AFFINE_WIDE_W(8); break;
+    default: CCUT_AFFINE_WIDE_W(16); break;
+  }
+#undef CCUT_AFFINE_WIDE_W
+#undef CCUT_AFFINE_WIDE
+  return hipGetLastError();
+}
 
 hipError_t launch_affine(const FragDev &F, uint32_t W, const uint64_t *rows, uint64_t v0, uint64_t nv,
                          uint64_t *models, hipStream_t s) {

@@ -387,7 +387,234 @@ __global__ __launch_bounds__(kWhtBlock) void dist_parity_kernel(const double *__
 
 inline unsigned blocks_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// ------------------------------------------------ more than 64 measurements
+// Models of MW words per outcome vector (model_mw): x0[MW], rmask[MW],
+// G[a][MW].  Shot bits: measurement index a takes bit a & 31 of Philox
+// call a >> 5 (the same draw as below 64).
+
+// The shot words of one quad: u[r][w] = bits 64 w .. 64 w + 63 of shot r.
+template <int MW>
+__device__ inline void quad_words(uint64_t quad, uint64_t vid, uint64_t seed, uint32_t n_meas, uint64_t (&u)[4][MW]) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int w = 0; w < MW; ++w)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r][w] = 0;
+#pragma unroll
+  for (int cidx = 0; cidx < 2 * MW; ++cidx) {
+    if ((uint32_t)cidx * 32 >= n_meas) break;
+    const U4 o = philox10((uint32_t)cidx, (uint32_t)quad, (uint32_t)vid, (uint32_t)(vid >> 32), k0, k1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r][cidx >> 1] |= (uint64_t)o.w[r] << (32 * (cidx & 1));
+  }
+}
+
+// For a mask z over the measured set: z.x = z.x0 ^ g.u, g_a = z.G[a].
+template <int MW>
+__device__ inline void parity_form_wide(const uint64_t *md, uint32_t n_meas, const uint64_t *z, uint32_t &c,
+                                        uint64_t (&g)[MW]) {
+  uint32_t p = 0;
+#pragma unroll
+  for (int w = 0; w < MW; ++w) {
+    p += __popcll(z[w] & md[w]);
+    g[w] = 0;
+  }
+  c = p & 1u;
+  for (uint32_t a = 0; a < n_meas; ++a) {
+    const uint64_t *G = md + 2 * MW + (uint64_t)a * MW;
+    uint32_t q = 0;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) q += __popcll(z[w] & G[w]);
+#pragma unroll
+    for (int w = 0; w < MW; ++w)
+      if ((a >> 6) == (uint32_t)w) g[w] |= (uint64_t)(q & 1u) << (a & 63);
+  }
+}
+
+// Exact <(-1)^{z.x}>: (-1)^c if g = 0, else 0.  ext: [n_ext][MW].
+template <int MW>
+__global__ void parity_exact_wide_kernel(const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t nv,
+                                         const uint64_t *__restrict__ ext, uint32_t n_ext, double *__restrict__ E) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * n_ext) return;
+  const uint64_t v = i / n_ext;
+  const uint32_t s = (uint32_t)(i % n_ext);
+  uint32_t c;
+  uint64_t g[MW], any = 0;
+  parity_form_wide<MW>(models + v * model_words(n_meas), n_meas, ext + (uint64_t)s * MW, c, g);
+#pragma unroll
+  for (int w = 0; w < MW; ++w) any |= g[w];
+  E[i] = any ? 0.0 : (c ? -1.0 : 1.0);
+}
+
+// Odd-parity counts, bit-sliced as parity_sampled_kernel: lane l owns mask
+// l of each group of 64, a wave draws 64 quads per round; for shot r the
+// planes of the random bits in any form are ballots, a mask's parities
+// over 64 shots the xor of the planes its form selects.  grid (nblk_x, nv).
+template <int MW>
+__global__ __launch_bounds__(kParityBlock) void parity_sampled_wide_kernel(
+    const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed, uint64_t vid0,
+    const uint64_t *__restrict__ ext, uint32_t n_ext, uint32_t rounds, uint32_t *__restrict__ odd_counts) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t v = blockIdx.y;
+  const uint64_t *md = models + v * model_words(n_meas);
+  const uint64_t vid = vid0 + v;
+  const uint64_t nquads = (shots + 3) >> 2;
+  const uint64_t r0 = ((uint64_t)blockIdx.x * (kParityBlock / 64) + wave) * rounds;
+  for (uint32_t p0 = 0; p0 < n_ext; p0 += 64) {
+    const uint32_t s = p0 + lane;
+    uint64_t g[MW], gall[MW];
+    uint32_t cm = 0, cnt = 0;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) g[w] = 0;
+    if (s < n_ext) parity_form_wide<MW>(md, n_meas, ext + (uint64_t)s * MW, cm, g);
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+      uint64_t t = g[w];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) t |= __shfl_xor(t, off);
+      gall[w] = __builtin_amdgcn_readfirstlane((uint32_t)t) |
+                ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t >> 32)) << 32);
+    }
+    uint32_t total = 0;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+      const uint64_t quad = (r0 + rd) * 64 + lane;
+      uint64_t u[4][MW];
+      if (quad < nquads) {
+        quad_words<MW>(quad, vid, seed, n_meas, u);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int w = 0; w < MW; ++w) u[r][w] = 0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint64_t valid = __ballot(quad < nquads && quad * 4 + r < shots);
+        if (!valid) continue;
+        total += __popcll(valid);
+        uint64_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < MW; ++w)
+          for (uint64_t rem = gall[w]; rem; rem &= rem - 1) {
+            const uint32_t j = (uint32_t)__builtin_ctzll(rem);
+            const uint64_t plane = __ballot((u[r][w] >> j) & 1ull);
+            acc ^= ((g[w] >> j) & 1ull) ? plane : 0ull;
+          }
+        cnt += __popcll(acc & valid);
+      }
+    }
+    const uint32_t odd = cm ? total - cnt : cnt;
+    if (s < n_ext && odd) atomicAdd(&odd_counts[v * n_ext + s], odd);
+  }
+}
+
+// Shot records: records[v][shot][rw] (rw = ceil(n_meas / 64) words) =
+// x0 ^ (xor of G[a] over the random a whose shot bit is set); one thread
+// per shot, the model in LDS.
+template <int MW>
+__global__ __launch_bounds__(256) void records_wide_kernel(const uint64_t *__restrict__ models, uint32_t n_meas,
+                                                           uint64_t shots, uint64_t seed, uint64_t vid0,
+                                                           uint32_t rw, uint64_t *__restrict__ records) {
+  extern __shared__ uint64_t s_md[];
+  const uint64_t v = blockIdx.y;
+  const uint32_t mw = model_words(n_meas);
+  const uint64_t *md = models + v * mw;
+  for (uint32_t i = threadIdx.x; i < mw; i += blockDim.x) s_md[i] = md[i];
+  __syncthreads();
+  const uint64_t shot = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (shot >= shots) return;
+  uint64_t u[4][MW];
+  quad_words<MW>(shot >> 2, vid0 + v, seed, n_meas, u);
+  uint64_t x[MW], bits[MW];
+#pragma unroll
+  for (int w = 0; w < MW; ++w) {
+    x[w] = s_md[w];
+    bits[w] = s_md[MW + w];  // random measurements
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if ((shot & 3) == (uint64_t)r) bits[w] &= u[r][w];
+  }
+#pragma unroll
+  for (int w = 0; w < MW; ++w)
+    for (uint64_t rem = bits[w]; rem; rem &= rem - 1) {
+      const uint32_t a = 64u * w + (uint32_t)__builtin_ctzll(rem);
+      const uint64_t *G = s_md + 2 * MW + (uint64_t)a * MW;
+#pragma unroll
+      for (int k = 0; k < MW; ++k) x[k] ^= G[k];
+    }
+  uint64_t *dst = records + (v * shots + shot) * rw;
+#pragma unroll
+  for (int w = 0; w < MW; ++w)
+    if ((uint32_t)w < rw) dst[w] = x[w];
+}
+
 }  // namespace
+
+#define CCUT_MW_SWITCH(MW_, CALL) \
+  switch (MW_) {                  \
+    case 2: CALL(2); break;       \
+    case 4: CALL(4); break;       \
+    case 8: CALL(8); break;       \
+    default: CALL(16); break;     \
+  }
+
+hipError_t launch_parity_exact_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, const uint64_t *ext,
+                                    uint32_t n_ext, double *E, hipStream_t s) {
+  if (n_meas <= (uint32_t)kMaxMeas || n_meas > (uint32_t)kMaxMeasWide) return hipErrorInvalidValue;
+  const uint64_t n = nv * n_ext;
+  if (n == 0) return hipSuccess;
+  const dim3 g(blocks_for(n, 256)), b(256);
+#define CCUT_PEW(M) hipLaunchKernelGGL(parity_exact_wide_kernel<M>, g, b, 0, s, models, n_meas, nv, ext, n_ext, E)
+  CCUT_MW_SWITCH(model_mw(n_meas), CCUT_PEW)
+#undef CCUT_PEW
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_sampled_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
+                                      uint64_t seed, uint64_t vid0, const uint64_t *ext, uint32_t n_ext,
+                                      uint32_t *odd_counts, hipStream_t s) {
+  if (n_meas <= (uint32_t)kMaxMeas || n_meas > (uint32_t)kMaxMeasWide || nv == 0 || nv > 65535)
+    return hipErrorInvalidValue;
+  if (shots == 0 || n_ext == 0) return hipSuccess;
+  const uint64_t total_rounds = ((shots + 3) / 4 + 63) / 64;
+  const uint64_t want_waves = std::max<uint64_t>(1, 4096 / nv);
+  const uint64_t rounds = std::max<uint64_t>(1, (total_rounds + want_waves - 1) / want_waves);
+  const uint64_t waves = (total_rounds + rounds - 1) / rounds;
+  const uint64_t nbx = (waves + kParityBlock / 64 - 1) / (kParityBlock / 64);
+  if (nbx > 0x7FFFFFFFull || rounds > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nbx, (unsigned)nv), block(kParityBlock);
+#define CCUT_PSW(M)                                                                                            \
+  hipLaunchKernelGGL(parity_sampled_wide_kernel<M>, grid, block, 0, s, models, n_meas, shots, seed, vid0, ext, \
+                     n_ext, (uint32_t)rounds, odd_counts)
+  CCUT_MW_SWITCH(model_mw(n_meas), CCUT_PSW)
+#undef CCUT_PSW
+  return hipGetLastError();
+}
+
+hipError_t launch_records_wide(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots, uint64_t seed,
+                               uint64_t vid0, uint64_t *records, hipStream_t s) {
+  if (n_meas <= (uint32_t)kMaxMeas || n_meas > (uint32_t)kMaxMeasWide || nv == 0 || nv > 65535)
+    return hipErrorInvalidValue;
+  if (shots == 0) return hipSuccess;
+  const uint64_t nb = (shots + 255) / 256;
+  if (nb > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  const size_t lds = (size_t)model_words(n_meas) * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nb, (unsigned)nv), block(256);
+#define CCUT_RW(M)                                                                                         \
+  do {                                                                                                     \
+    hipError_t e = hipFuncSetAttribute((const void *)records_wide_kernel<M>,                               \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);              \
+    if (e != hipSuccess) return e;                                                                         \
+    hipLaunchKernelGGL(records_wide_kernel<M>, grid, block, lds, s, models, n_meas, shots, seed, vid0,     \
+                       (n_meas + 63) / 64, records);                                                      \
+  } while (0)
+  CCUT_MW_SWITCH(model_mw(n_meas), CCUT_RW)
+#undef CCUT_RW
+  return hipGetLastError();
+}
+#undef CCUT_MW_SWITCH
 
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
