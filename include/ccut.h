@@ -389,7 +389,8 @@ ccut_status ccut_learned_logits(ccut_learned *L, ccut_mlp *mlp, float *logits);
  * terms_out (device, n entries) may be NULL. */
 ccut_status ccut_learned_estimate(ccut_learned *L, const double *q, uint64_t n, uint64_t seed, double *out,
                                   int on_device, uint64_t *terms_out);
-/* The exhaustive contraction of the kept tensors (equals ccut_marginal). */
+/* The exhaustive contraction of the kept tensors in eo->precision of the
+ * create call (equals ccut_marginal with that precision). */
 ccut_status ccut_learned_exhaustive(ccut_learned *L, double *out, int on_device);
 void ccut_learned_destroy(ccut_learned *L);
 

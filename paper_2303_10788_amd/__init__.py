@@ -765,11 +765,12 @@ class Learned:
     """Per-circuit term model: fragment tensors, column norms and share
     tables of one marginal request, kept on the device."""
 
-    def __init__(self, plan: Plan, qubits, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO):
+    def __init__(self, plan: Plan, qubits, *, shots=0, seed=0, circuit=0, method=CCUT_METHOD_AUTO,
+                 precision=CCUT_FP64):
         self.plan, self.ctx = plan, plan.ctx
         self.nq = len(qubits)
-        self.handle = ccut_learned_create(plan.handle, self.ctx.handle, _eval_opts(shots, seed, 0, circuit, method),
-                                          qubits)
+        self.handle = ccut_learned_create(plan.handle, self.ctx.handle,
+                                          _eval_opts(shots, seed, precision, circuit, method), qubits)
         self.k, self.K, self.width = ccut_learned_info(self.handle)
 
     def features(self, terms=None, first=0, n=None):

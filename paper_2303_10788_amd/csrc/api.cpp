@@ -2245,6 +2245,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   constexpr int kGemmClasses = 19;
   std::vector<GemmJob> gjobs[kGemmClasses];
   uint64_t rwg = 0, gwg[kGemmClasses] = {}, grwg[kGemmClasses] = {};
+  bool ggen[kGemmClasses] = {};
   for (size_t i = 0, g = 0; i < np; ++i) {
     const uint32_t nq = (uint32_t)b->qubits[i].size();
     if (kind[i] == 0) {
@@ -2277,6 +2278,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.wg0 = gwg[sk];
       J.rwg0 = grwg[sk];
       gwg[sk] += (uint64_t)J.tiles * J.splits;
+      if (!skinny) ggen[sk] = ggen[sk] || gemm_general(h);
       if (!direct) grwg[sk] += ((uint64_t)h.M * h.N + 255) / 256;
       gjobs[sk].push_back(J);
       ++g;
@@ -2310,7 +2312,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (gjobs[sk].empty()) continue;
     pick();
     KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], fp32,
+    const int mode = fp32 ? (b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM ? 2 : 1) : 0;
+    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], mode, ggen[sk],
                                  sk ? 1u << ((sk - 1) / 3) : 0u, sk ? 1u << ((sk - 1) % 3) : 0u, c->cur));
   }
   c->cur = b->stream;
@@ -2557,6 +2560,7 @@ struct ccut_learned {
   ccut_ctx *ctx = nullptr;
   ccut_plan *plan = nullptr;
   uint32_t k = 0, nq = 0, width = 64, circuit = 0;
+  int32_t precision = CCUT_FP64;  // of the exhaustive contraction
   uint64_t K = 0;
   Arena arena;  // fragment tensors, norms, share tables
   std::vector<std::vector<char>> staged;
@@ -2886,6 +2890,7 @@ ccut_status ccut_learned_create(ccut_plan *p, const ccut_eval_opts *eo, const ui
   L->K = 1ull << (2 * pd.k);
   L->nq = nq;
   L->circuit = eo->circuit;
+  L->precision = eo->precision;
   L->width = (uint32_t)((6 * pd.k + 63) / 64 * 64);
   L->arena.alloc = c->arena.alloc;
   L->arena.free_fn = c->arena.free_fn;
@@ -3140,7 +3145,9 @@ ccut_status ccut_learned_exhaustive(ccut_learned *L, double *out, int on_device)
   if (!out) return fail(c, CCUT_E_INVALID, "out is NULL");
   double *res = aget<double>(c, (size_t)1 << L->nq);
   if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
-  if ((st = recombine(c, L->args, L->nq, false, res)) != CCUT_OK) return st;
+  RecombArgs args = L->args;
+  args.lo_parts = L->precision == CCUT_FP32X3_MFMA_FP64SUM;
+  if ((st = recombine(c, args, L->nq, L->precision != CCUT_FP64, res)) != CCUT_OK) return st;
   return finish_out(c, res, out, (size_t)1 << L->nq, on_device);
 }
 

@@ -537,8 +537,13 @@ struct GemmJob {
 };
 // skinny_rows: 0 for the MFMA tiles, else the row count M (1, 2, 4, ..., 32)
 // and skinny_cpt the columns per thread (skinny_cols) every job of the list shares
-hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s);
+// mode: 0 fp64, 1 fp32, 2 fp32 hi/lo (the MFMA tiles)
+// gen: some contraction of the list has a side that is not one fragment
+// read directly (gemm_general)
+hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, int mode,
+                             bool gen, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s);
+bool gemm_general(const GemmArgs &h);
+
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
                                  uint32_t splits, double *out, hipStream_t s,
                                  bool skinny = false);

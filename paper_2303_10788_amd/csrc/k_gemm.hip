@@ -40,9 +40,18 @@ constexpr int MT = 64, NT = 64, KC = 32, GEMM_THREADS = 256;
 typedef float float4v __attribute__((ext_vector_type(4)));
 typedef double double4v __attribute__((ext_vector_type(4)));
 
+// The contraction's arguments as read-only (constant address space) data:
+// read with a uniform index they compile to scalar loads, so operand
+// formation keeps the descriptors out of the vector memory path.
+typedef __attribute__((address_space(4))) const GemmArgs c_GemmArgs;
+typedef __attribute__((address_space(4))) const RecombFrag c_RecombFrag;
+__device__ inline c_GemmArgs *cargs(const GemmArgs *G) { return (c_GemmArgs *)(uint64_t)G; }
+
+// p_f(P): the digits of P on fragment f's cuts
 __device__ inline uint64_t frag_p(const GemmArgs *__restrict__ G, uint32_t f, uint64_t P) {
-  const RecombFrag &F = G->f[f];
-  if (G->ident[f]) return P;
+  c_GemmArgs *C = cargs(G);
+  c_RecombFrag &F = C->f[f];
+  if (C->ident[f]) return P;
   uint64_t p = 0;
   for (uint32_t j = 0; j < F.n_axes; ++j) p |= ((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
   return p;
@@ -55,11 +64,17 @@ __device__ inline double tval(const RecombFrag &F, uint64_t i) {
 }
 
 __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t row, uint64_t P) {
+  c_GemmArgs *C = cargs(G);
+  const bool left = &S == &G->L;
   double v = 1.0;
-  for (uint32_t i = 0; i < S.n; ++i) {
-    const uint32_t f = S.frag[i];
-    const uint32_t r = (row >> S.shift[i]) & ((1u << S.bits[i]) - 1u);
-    v *= tval(G->f[f], frag_p(G, f, P) * G->f[f].rows + r);
+  const uint32_t n = left ? C->L.n : C->R.n;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t f = left ? C->L.frag[i] : C->R.frag[i];
+    const uint32_t sh = left ? C->L.shift[i] : C->R.shift[i], bits = left ? C->L.bits[i] : C->R.bits[i];
+    const uint32_t r = (row >> sh) & ((1u << bits) - 1u);
+    c_RecombFrag &F = C->f[f];
+    const uint64_t idx = frag_p(G, f, P) * F.rows + r;
+    v *= F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] / F.shots : F.T[idx];
   }
   return v;
 }
@@ -79,15 +94,21 @@ __device__ inline const RecombFrag *direct_side(const GemmArgs *__restrict__ G, 
 }
 
 // One 64 x 64 output tile (tile index `tile`, M tiles fastest) over the
-// K range of split `split`, into partial[split][M][N].
-template <bool F32>
-__device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
+// K range of split `split`, into partial[split][M][N].  MODE 0: fp64
+// MFMA; 1: fp32 operands, one fp32 MFMA product per term; 2: hi/lo split
+// fp32 operands, three products.  GEN false: both sides are one fragment
+// read directly (direct_side); true: any side, a side that is not direct
+// formed per entry (side_value).
+template <int MODE, bool GEN>
+__device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_split,
+                                                               double *__restrict__ partial,
                                  uint32_t tile, uint32_t split, double *__restrict__ out = nullptr) {
+  constexpr bool F32 = MODE != 0, LO = MODE == 2;
   typedef typename std::conditional<F32, float, double>::type TS;
   __shared__ TS As[KC][MT + 1];
   __shared__ TS Bs[KC][NT + 1];
-  __shared__ TS Al[F32 ? KC : 1][MT + 1];  // fp32 mode: low parts of the split operands
-  __shared__ TS Bl[F32 ? KC : 1][NT + 1];
+  __shared__ TS Al[LO ? KC : 1][MT + 1];  // hi/lo mode: low parts of the split operands
+  __shared__ TS Bl[LO ? KC : 1][NT + 1];
   const uint32_t M = G->M, N = G->N;
   const uint64_t K = G->K;
   const uint32_t tilesM = (M + MT - 1) / MT;
@@ -110,7 +131,10 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
     }
   const RecombFrag *FA = direct_side(G, G->L), *FB = direct_side(G, G->R);
   const uint64_t rowsA = FA ? FA->rows : 0, rowsB = FB ? FB->rows : 0;
-  const bool lo = F32 && G->lo_parts != 0;
+  // the arguments read once (uniform), not per operand entry
+  const double *tscale = G->tscale;
+  const uint64_t *terms = G->terms;
+  const bool square = G->square != 0;
   // output index bits of the tile's rows and columns (written with the
   // outputs directly when there is one split)
   __shared__ uint64_t s_obits[MT + NT];
@@ -126,24 +150,22 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       const uint64_t j = kb + kk;
       double a = 0.0;
       if (m < M && j < k1) {
-        a = FA ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
-        if (G->tscale) a *= G->tscale[j];
-        if (G->square) a *= a;
+        a = (!GEN || FA) ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, terms ? terms[j] : j);
+        if (tscale) a *= tscale[j];
+        if (square) a *= a;
       }
       As[kk][mm] = (TS)a;
-      if constexpr (F32)
-        if (lo) Al[kk][mm] = (float)(a - (double)(float)a);
+      if constexpr (LO) Al[kk][mm] = (float)(a - (double)(float)a);
     }
     for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
       const uint32_t kk = e / NT, nn = e % NT;
       const uint32_t n = tn * NT + nn;
       const uint64_t j = kb + kk;
       double b = 0.0;
-      if (n < N && j < k1) b = FB ? tval(*FB, j * rowsB + n) : side_value(G, G->R, n, G->terms ? G->terms[j] : j);
-      if (G->square) b *= b;
+      if (n < N && j < k1) b = (!GEN || FB) ? tval(*FB, j * rowsB + n) : side_value(G, G->R, n, terms ? terms[j] : j);
+      if (square) b *= b;
       Bs[kk][nn] = (TS)b;
-      if constexpr (F32)
-        if (lo) Bl[kk][nn] = (float)(b - (double)(float)b);
+      if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
     }
     __syncthreads();
 #pragma unroll
@@ -154,7 +176,7 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lane / 16][wn + 16 * j + lane % 16];
       if constexpr (F32) {
-        if (lo) {
+        if constexpr (LO) {
           float al[2], bl[2];
 #pragma unroll
           for (int i = 0; i < 2; ++i) al[i] = Al[kk + lane / 16][wm + 16 * i + lane % 16];
@@ -213,22 +235,22 @@ __device__ inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_
       }
 }
 
-template <bool F32>
+template <int MODE, bool GEN>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
                                                             double *__restrict__ partial, double *__restrict__ out) {
-  gemm_body<F32>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
+  gemm_body<MODE, GEN>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
 }
 
 // Many contractions in one launch: workgroup x runs tile (x - wg0) mod
 // tiles, split (x - wg0) / tiles of the job holding x.
-template <bool F32>
+template <int MODE, bool GEN>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t bid = xcd_block(blockIdx.x, gridDim.x);  // the tiles of a job share one XCD's L2
   const uint32_t j = find_job(jobs, n_jobs, bid, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];
   const uint64_t local = bid - J.wg0;
-  gemm_body<F32>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
-                 J.splits == 1 ? J.out : nullptr);
+  gemm_body<MODE, GEN>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
+                       J.splits == 1 ? J.out : nullptr);
 }
 
 // Skinny contraction (M <= SK_M rows, fp64): CPT adjacent output columns
@@ -278,7 +300,7 @@ struct ColLoad<4> {
 // the accumulators of one kernel stay in registers only when the kernel
 // holds exactly its own.
 template <uint32_t MC, uint32_t CPT>
-__device__ inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
+__device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs *__restrict__ G, uint64_t k_per_split, double *__restrict__ partial,
                                    uint32_t tile, uint32_t split, double *__restrict__ out) {
   __shared__ double As[SK_KC][MC];
   __shared__ uint64_t s_boff[SK_KC];
@@ -516,22 +538,47 @@ uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny) {
   return ((kchunks + splits - 1) / splits) * kc;
 }
 
-hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, bool fp32,
-                             uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s) {
+// The MFMA tile kernel of precision mode `mode` (0 fp64, 1 fp32, 2 fp32
+// hi/lo) with `lds` bytes of factor tables; batch: the job list, else one
+// contraction.
+hipError_t gemm_launch(int mode, bool gen, dim3 g, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs,
+                       const GemmArgs *args, uint64_t k_per_split, double *partial, double *out) {
+#define CCUT_GEMM(M_, G_)                                                                                   \
+  do {                                                                                                      \
+    if (jobs)                                                                                               \
+      hipLaunchKernelGGL((gemm_batch_kernel<M_, G_>), g, dim3(GEMM_THREADS), 0, s, jobs, n_jobs);          \
+    else                                                                                                    \
+      hipLaunchKernelGGL((gemm_kernel<M_, G_>), g, dim3(GEMM_THREADS), 0, s, args, k_per_split, partial, out); \
+  } while (0)
+  switch (mode * 2 + (gen ? 1 : 0)) {
+    case 0: CCUT_GEMM(0, false); break;
+    case 1: CCUT_GEMM(0, true); break;
+    case 2: CCUT_GEMM(1, false); break;
+    case 3: CCUT_GEMM(1, true); break;
+    case 4: CCUT_GEMM(2, false); break;
+    default: CCUT_GEMM(2, true); break;
+  }
+#undef CCUT_GEMM
+  return hipGetLastError();
+}
+
+// Whether contraction h needs the general tile kernel (a side that is not
+// one fragment read directly).
+bool gemm_general(const GemmArgs &h) {
+  auto direct = [&](const GemmSide &S) { return S.n == 1 && !h.terms && S.shift[0] == 0 && h.ident[S.frag[0]]; };
+  return !direct(h.L) || !direct(h.R);
+}
+
+hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, int mode,
+                             bool gen, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s) {
   if (n_jobs == 0 || total_wg == 0) return hipSuccess;
   if (total_wg > 0x7FFFFFFFull || total_rwg > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipError_t e;
   if (skinny_rows)
     e = skinny_dispatch(skinny_rows, skinny_cpt, dim3((unsigned)total_wg), s, d_jobs, n_jobs, nullptr, 0, nullptr,
                         nullptr);
-  else {
-    if (fp32)
-      hipLaunchKernelGGL((gemm_batch_kernel<true>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs, n_jobs);
-    else
-      hipLaunchKernelGGL((gemm_batch_kernel<false>), dim3((unsigned)total_wg), dim3(GEMM_THREADS), 0, s, d_jobs,
-                         n_jobs);
-    e = hipGetLastError();
-  }
+  else
+    e = gemm_launch(mode, gen, dim3((unsigned)total_wg), s, d_jobs, n_jobs, nullptr, 0, nullptr, nullptr);
   if (e != hipSuccess || total_rwg == 0) return e;  // (one-split jobs wrote their outputs)
   hipLaunchKernelGGL(gemm_reduce_batch_kernel, dim3((unsigned)total_rwg), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
@@ -545,14 +592,11 @@ hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool
     const hipError_t e = skinny_dispatch(h.M, skinny_cols(h), dim3(tiles, splits), s, nullptr, 0, d_args,
                                          k_per_split, partial, splits == 1 ? out : nullptr);
     if (e != hipSuccess || splits == 1) return e;
-  } else if (fp32)
-    hipLaunchKernelGGL((gemm_kernel<true>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
-                       partial, splits == 1 ? out : nullptr);
-  else
-    hipLaunchKernelGGL((gemm_kernel<false>), dim3(tiles, splits), dim3(GEMM_THREADS), 0, s, d_args, k_per_split,
-                       partial, splits == 1 ? out : nullptr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || splits == 1) return e;
+  } else {
+    const hipError_t e = gemm_launch(fp32 ? (h.lo_parts ? 2 : 1) : 0, gemm_general(h), dim3(tiles, splits), s,
+                                     nullptr, 0, d_args, k_per_split, partial, splits == 1 ? out : nullptr);
+    if (e != hipSuccess || splits == 1) return e;
+  }
   const uint64_t MN = (uint64_t)h.M * h.N;
   hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, d_args, partial,
                      splits, out);

@@ -320,21 +320,28 @@ def precision(shots: int = 0) -> Workload:
                     shots=shots, nc_output_wires=nc_out, depth=30)
 
 
-def learned_circuit(seed: int) -> Workload:
-    """300 qubits, 50 layers (CX density 0.3), four 5-qubit blocks at
+def learned_circuit(seed: int, tail: int = 25, near_exits: bool = False) -> Workload:
+    """300 qubits, 25 + tail layers (CX density 0.3), four 5-qubit blocks at
     30 + 75 i with 3 T gates each and (3, 3, 2, 2) exit wires: 10 cuts,
-    4^10 cut terms; 16-qubit marginal (10 block outputs + 6 Clifford qubits)."""
+    4^10 cut terms; 16-qubit marginal (10 block outputs + 6 Clifford qubits).
+    near_exits: the marginal is over the first 6 block outputs and the 10
+    exit wires themselves (measured tail layers after their cut), so the
+    Clifford fragment's outputs sit in the cuts' light cone."""
     exit_counts = (3, 3, 2, 2)
     blocks = []
     for i, c in enumerate(exit_counts):
         wires = list(range(30 + 75 * i, 35 + 75 * i))
         blocks.append(Block(wires, wires[5 - c:]))
-    ops, cuts = block_circuit(300, 50, blocks, t_c=25, p_cx=0.3, seed=seed, n_t=12)
+    depth = 25 + tail
+    ops, cuts = block_circuit(300, depth, blocks, t_c=25, p_cx=0.3, seed=seed, n_t=12)
     nc_out = [q for b in blocks for q in b.wires if q not in b.exits]
-    cl = [q for q in range(300) if q not in nc_out and not any(q in b.wires and q not in b.exits for b in blocks)]
-    req = sorted(nc_out + _nearest(cl, [b.wires[0] for b in blocks], 6))
-    return Workload(f"learned{seed}", 300, ops, cuts, req, [], seed=seed, shots=0,
-                    nc_output_wires=nc_out, depth=50)
+    if near_exits:
+        req = sorted(nc_out[:6] + [q for b in blocks for q in b.exits])
+    else:
+        cl = [q for q in range(300) if q not in nc_out and not any(q in b.wires and q not in b.exits for b in blocks)]
+        req = sorted(nc_out + _nearest(cl, [b.wires[0] for b in blocks], 6))
+    name = f"learned{seed}" if (tail, near_exits) == (25, False) else f"learned{seed}_t{tail}{'e' if near_exits else ''}"
+    return Workload(name, 300, ops, cuts, req, [], seed=seed, shots=0, nc_output_wires=nc_out, depth=depth)
 
 
 def random_circuit(n: int, n_ops: int, seed: int, *, kinds: Sequence[str] = ALL_KINDS,
