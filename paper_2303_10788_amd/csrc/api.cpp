@@ -2246,6 +2246,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   std::vector<GemmJob> gjobs[kGemmClasses];
   uint64_t rwg = 0, gwg[kGemmClasses] = {}, grwg[kGemmClasses] = {};
   bool ggen[kGemmClasses] = {};
+  size_t glds[kGemmClasses] = {};
   for (size_t i = 0, g = 0; i < np; ++i) {
     const uint32_t nq = (uint32_t)b->qubits[i].size();
     if (kind[i] == 0) {
@@ -2278,7 +2279,10 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.wg0 = gwg[sk];
       J.rwg0 = grwg[sk];
       gwg[sk] += (uint64_t)J.tiles * J.splits;
-      if (!skinny) ggen[sk] = ggen[sk] || gemm_general(h);
+      if (!skinny) {
+        ggen[sk] = ggen[sk] || gemm_general(h);
+        glds[sk] = std::max(glds[sk], gemm_fac_lds(h));
+      }
       if (!direct) grwg[sk] += ((uint64_t)h.M * h.N + 255) / 256;
       gjobs[sk].push_back(J);
       ++g;
@@ -2313,7 +2317,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     pick();
     KTimer t(c, CCUT_K_RECOMBINE);
     const int mode = fp32 ? (b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM ? 2 : 1) : 0;
-    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], mode, ggen[sk],
+    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], mode, ggen[sk], glds[sk],
                                  sk ? 1u << ((sk - 1) / 3) : 0u, sk ? 1u << ((sk - 1) % 3) : 0u, c->cur));
   }
   c->cur = b->stream;

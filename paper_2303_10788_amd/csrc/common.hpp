@@ -540,9 +540,13 @@ struct GemmJob {
 // mode: 0 fp64, 1 fp32, 2 fp32 hi/lo (the MFMA tiles)
 // gen: some contraction of the list has a side that is not one fragment
 // read directly (gemm_general)
+// (gen: lds = the largest gemm_fac_lds of the list)
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, int mode,
-                             bool gen, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s);
+                             bool gen, size_t lds, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s);
 bool gemm_general(const GemmArgs &h);
+// Bytes of LDS the general tiles of contraction h take for operand factor
+// tables.
+size_t gemm_fac_lds(const GemmArgs &h);
 
 hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool fp32, double *partial,
                                  uint32_t splits, double *out, hipStream_t s,

@@ -93,12 +93,80 @@ __device__ inline const RecombFrag *direct_side(const GemmArgs *__restrict__ G, 
   return &G->f[f];
 }
 
+// Operand factors of a side that is not one direct fragment: the tile's
+// 64 rows (or columns) take only 2^vb distinct row values of fragment t
+// (vb = its row bits below bit 6 of the side index; the 64 indices share
+// every higher bit), so per K chunk fragment t's factors
+// F_t[kk][r] = T_t[p_t(P_kk)][fixed_t | r] are gathered once into LDS and
+// each operand entry is their product in fragment order (the product
+// side_value forms, the same roundings).  Layout per side: fragment t at
+// word offset KC (cnt_0 + ... + cnt_{t-1}), [kk][r].  At most kFacFrags
+// fragments per side (more: side_value per entry).
+constexpr uint32_t kFacFrags = 8;
+
+__host__ __device__ inline uint32_t fac_vb(uint32_t shift, uint32_t bits) {
+  return shift >= 6 ? 0u : (bits < 6 - shift ? bits : 6 - shift);
+}
+
+// Doubles of LDS the factor tables of side S take (0: no tables).
+__host__ __device__ inline uint32_t fac_words(const GemmArgs &h, const GemmSide &S) {
+  if (S.n > kFacFrags || (S.n == 1 && !h.terms && S.shift[0] == 0 && h.ident[S.frag[0]])) return 0;
+  uint32_t w = 0;
+  for (uint32_t t = 0; t < S.n; ++t) w += KC << fac_vb(S.shift[t], S.bits[t]);
+  return w;
+}
+
+// Fill side S's factor tables for the tile whose first index is base:
+// fragment by fragment (uniform), one gather per entry.
+__device__ inline void fac_fill(const GemmArgs *__restrict__ G, bool left, uint32_t base, uint64_t kb, uint64_t k1,
+                                double *__restrict__ fac) {
+  c_GemmArgs *C = cargs(G);
+  const uint32_t n = left ? C->L.n : C->R.n;
+  uint32_t off = 0;
+  for (uint32_t t = 0; t < n; ++t) {
+    const uint32_t f = left ? C->L.frag[t] : C->R.frag[t];
+    const uint32_t sh = left ? C->L.shift[t] : C->R.shift[t], bits = left ? C->L.bits[t] : C->R.bits[t];
+    const uint32_t vb = fac_vb(sh, bits), cnt = 1u << vb;
+    const uint32_t fixed = (base >> sh) & ((1u << bits) - 1u);
+    c_RecombFrag &F = C->f[f];
+    for (uint32_t e = threadIdx.x; e < KC * cnt; e += GEMM_THREADS) {
+      const uint32_t kk = e >> vb, r = e & (cnt - 1u);
+      const uint64_t j = kb + kk;
+      double v = 0.0;
+      if (j < k1) {
+        const uint64_t idx = frag_p(G, f, C->terms ? C->terms[j] : j) * F.rows + (fixed | r);
+        v = F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] / F.shots : F.T[idx];
+      }
+      fac[off + e] = v;
+    }
+    off += KC * cnt;
+  }
+}
+
+// Entry (kk, local) of a factored side: the product of its fragments'
+// factors in fragment order.
+__device__ inline double fac_value(const GemmArgs *__restrict__ G, bool left, const double *__restrict__ fac,
+                                   uint32_t kk, uint32_t local) {
+  c_GemmArgs *C = cargs(G);
+  const uint32_t n = left ? C->L.n : C->R.n;
+  double v = 1.0;
+  uint32_t off = 0;
+  for (uint32_t t = 0; t < n; ++t) {
+    const uint32_t sh = left ? C->L.shift[t] : C->R.shift[t], bits = left ? C->L.bits[t] : C->R.bits[t];
+    const uint32_t vb = fac_vb(sh, bits);
+    v *= fac[off + (kk << vb) + ((local >> sh) & ((1u << vb) - 1u))];
+    off += KC << vb;
+  }
+  return v;
+}
+
 // One 64 x 64 output tile (tile index `tile`, M tiles fastest) over the
 // K range of split `split`, into partial[split][M][N].  MODE 0: fp64
 // MFMA; 1: fp32 operands, one fp32 MFMA product per term; 2: hi/lo split
 // fp32 operands, three products.  GEN false: both sides are one fragment
 // read directly (direct_side); true: any side, a side that is not direct
-// formed per entry (side_value).
+// formed from factor tables (dynamic LDS: the row side's, then the column
+// side's, fac_words each) or, beyond kFacFrags fragments, per entry.
 template <int MODE, bool GEN>
 __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *__restrict__ G, uint64_t k_per_split,
                                                                double *__restrict__ partial,
@@ -131,6 +199,13 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
     }
   const RecombFrag *FA = direct_side(G, G->L), *FB = direct_side(G, G->R);
   const uint64_t rowsA = FA ? FA->rows : 0, rowsB = FB ? FB->rows : 0;
+  extern __shared__ double s_fac[];
+  uint32_t wA = 0, wB = 0;
+  if constexpr (GEN) {
+    wA = fac_words(*G, G->L);
+    wB = fac_words(*G, G->R);
+  }
+  double *facA = s_fac, *facB = s_fac + wA;
   // the arguments read once (uniform), not per operand entry
   const double *tscale = G->tscale;
   const uint64_t *terms = G->terms;
@@ -144,13 +219,22 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
     __syncthreads();
   }
   for (uint64_t kb = k0; kb < k1; kb += KC) {
+    if constexpr (GEN) {
+      if (wA || wB) {
+        if (wA) fac_fill(G, true, tm * MT, kb, k1, facA);
+        if (wB) fac_fill(G, false, tn * NT, kb, k1, facB);
+        __syncthreads();
+      }
+    }
     for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
       const uint32_t kk = e / MT, mm = e % MT;
       const uint32_t m = tm * MT + mm;
       const uint64_t j = kb + kk;
       double a = 0.0;
       if (m < M && j < k1) {
-        a = (!GEN || FA) ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, terms ? terms[j] : j);
+        a = (!GEN || FA) ? tval(*FA, j * rowsA + m)
+            : wA         ? fac_value(G, true, facA, kk, mm)
+                         : side_value(G, G->L, m, terms ? terms[j] : j);
         if (tscale) a *= tscale[j];
         if (square) a *= a;
       }
@@ -162,7 +246,10 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
       const uint32_t n = tn * NT + nn;
       const uint64_t j = kb + kk;
       double b = 0.0;
-      if (n < N && j < k1) b = (!GEN || FB) ? tval(*FB, j * rowsB + n) : side_value(G, G->R, n, terms ? terms[j] : j);
+      if (n < N && j < k1)
+        b = (!GEN || FB) ? tval(*FB, j * rowsB + n)
+            : wB         ? fac_value(G, false, facB, kk, nn)
+                         : side_value(G, G->R, n, terms ? terms[j] : j);
       if (square) b *= b;
       Bs[kk][nn] = (TS)b;
       if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
@@ -541,14 +628,20 @@ uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny) {
 // The MFMA tile kernel of precision mode `mode` (0 fp64, 1 fp32, 2 fp32
 // hi/lo) with `lds` bytes of factor tables; batch: the job list, else one
 // contraction.
-hipError_t gemm_launch(int mode, bool gen, dim3 g, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs,
+hipError_t gemm_launch(int mode, bool gen, dim3 g, size_t lds, hipStream_t s, const GemmJob *jobs, uint32_t n_jobs,
                        const GemmArgs *args, uint64_t k_per_split, double *partial, double *out) {
-#define CCUT_GEMM(M_, G_)                                                                                   \
-  do {                                                                                                      \
-    if (jobs)                                                                                               \
-      hipLaunchKernelGGL((gemm_batch_kernel<M_, G_>), g, dim3(GEMM_THREADS), 0, s, jobs, n_jobs);          \
-    else                                                                                                    \
-      hipLaunchKernelGGL((gemm_kernel<M_, G_>), g, dim3(GEMM_THREADS), 0, s, args, k_per_split, partial, out); \
+  if (lds > 96 * 1024) return hipErrorInvalidValue;
+#define CCUT_GEMM(M_, G_)                                                                                     \
+  do {                                                                                                        \
+    const void *fn = jobs ? (const void *)gemm_batch_kernel<M_, G_> : (const void *)gemm_kernel<M_, G_>;     \
+    if (lds) {                                                                                                \
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);           \
+      if (e != hipSuccess) return e;                                                                          \
+    }                                                                                                         \
+    if (jobs)                                                                                                 \
+      hipLaunchKernelGGL((gemm_batch_kernel<M_, G_>), g, dim3(GEMM_THREADS), lds, s, jobs, n_jobs);          \
+    else                                                                                                      \
+      hipLaunchKernelGGL((gemm_kernel<M_, G_>), g, dim3(GEMM_THREADS), lds, s, args, k_per_split, partial, out); \
   } while (0)
   switch (mode * 2 + (gen ? 1 : 0)) {
     case 0: CCUT_GEMM(0, false); break;
@@ -562,6 +655,8 @@ hipError_t gemm_launch(int mode, bool gen, dim3 g, hipStream_t s, const GemmJob 
   return hipGetLastError();
 }
 
+size_t gemm_fac_lds(const GemmArgs &h) { return (size_t)(fac_words(h, h.L) + fac_words(h, h.R)) * sizeof(double); }
+
 // Whether contraction h needs the general tile kernel (a side that is not
 // one fragment read directly).
 bool gemm_general(const GemmArgs &h) {
@@ -570,7 +665,7 @@ bool gemm_general(const GemmArgs &h) {
 }
 
 hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t total_wg, uint64_t total_rwg, int mode,
-                             bool gen, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s) {
+                             bool gen, size_t lds, uint32_t skinny_rows, uint32_t skinny_cpt, hipStream_t s) {
   if (n_jobs == 0 || total_wg == 0) return hipSuccess;
   if (total_wg > 0x7FFFFFFFull || total_rwg > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipError_t e;
@@ -578,7 +673,8 @@ hipError_t launch_gemm_batch(const GemmJob *d_jobs, uint32_t n_jobs, uint64_t to
     e = skinny_dispatch(skinny_rows, skinny_cpt, dim3((unsigned)total_wg), s, d_jobs, n_jobs, nullptr, 0, nullptr,
                         nullptr);
   else
-    e = gemm_launch(mode, gen, dim3((unsigned)total_wg), s, d_jobs, n_jobs, nullptr, 0, nullptr, nullptr);
+    e = gemm_launch(mode, gen, dim3((unsigned)total_wg), gen ? lds : 0, s, d_jobs, n_jobs, nullptr, 0, nullptr,
+                    nullptr);
   if (e != hipSuccess || total_rwg == 0) return e;  // (one-split jobs wrote their outputs)
   hipLaunchKernelGGL(gemm_reduce_batch_kernel, dim3((unsigned)total_rwg), dim3(256), 0, s, d_jobs, n_jobs);
   return hipGetLastError();
@@ -593,8 +689,10 @@ hipError_t launch_recombine_gemm(const GemmArgs &h, const GemmArgs *d_args, bool
                                          k_per_split, partial, splits == 1 ? out : nullptr);
     if (e != hipSuccess || splits == 1) return e;
   } else {
-    const hipError_t e = gemm_launch(fp32 ? (h.lo_parts ? 2 : 1) : 0, gemm_general(h), dim3(tiles, splits), s,
-                                     nullptr, 0, d_args, k_per_split, partial, splits == 1 ? out : nullptr);
+    const bool gen = gemm_general(h);
+    const hipError_t e = gemm_launch(fp32 ? (h.lo_parts ? 2 : 1) : 0, gen, dim3(tiles, splits),
+                                     gen ? gemm_fac_lds(h) : 0, s, nullptr, 0, d_args, k_per_split, partial,
+                                     splits == 1 ? out : nullptr);
     if (e != hipSuccess || splits == 1) return e;
   }
   const uint64_t MN = (uint64_t)h.M * h.N;
