@@ -56,6 +56,9 @@ def parse():
                     help="instead of benchmarking: turn two rocprofv3 --pmc counter_collection.csv files "
                          "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy run into profiles/<workload>_traffic.json")
     ap.add_argument("--traffic-kernel", default="sv_kernel")
+    ap.add_argument("--contraction-only", action="store_true",
+                    help="learned workload: only the held-out circuit's dense exhaustive contraction, fp64 and "
+                         "fp32 (no training, few dispatches: for counter runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", choices=["mid", "batching", "precision", "learned", "scan"], default="batching",
                     help="batching (default): 256 uneven circuits in one graph-captured batch; mid: the 32-qubit, "
@@ -113,15 +116,30 @@ def _source_hash(kernel):
     return None
 
 
+def _kernel_base(name):
+    """The kernel's own name: no return type, namespaces, template
+    arguments or parameter list."""
+    name = name.replace("void ", "").replace("(anonymous namespace)::", "")
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):  # the first '<' or '(' outside any bracket ends the qualified name
+        if ch in "<(" and depth == 0:
+            cut = i
+            break
+    return name[:cut].split("::")[-1]
+
+
 def traffic_from_counters(args):
     """HBM bytes per launch of one kernel from a FETCH_SIZE and a WRITE_SIZE
     counter run, each scaled by the same counter on the 64 MiB copy
     (elementwise kernel reading and writing CALIB_BYTES)."""
     import csv
     out = {"workload": args.workload, "kernel": args.traffic_kernel, "source_sha": _source_hash(args.traffic_kernel)}
+    # the batched launches of a kernel class count as its launches
+    names = {"sv_kernel": ("sv_kernel", "sv_batch_kernel"), "sample_kernel": ("sample_kernel", "sample_batch_kernel")}
+    names = names.get(args.traffic_kernel, (args.traffic_kernel,))
     for path, counter in zip(args.traffic, ("FETCH_SIZE", "WRITE_SIZE")):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
-        kern = [float(r["Counter_Value"]) for r in rows if args.traffic_kernel in r["Kernel_Name"]]
+        kern = [float(r["Counter_Value"]) for r in rows if _kernel_base(r["Kernel_Name"]) in names]
         calib = [float(r["Counter_Value"]) for r in rows if "elementwise" in r["Kernel_Name"]]
         calib = max(calib)  # the 64 MiB copy is the largest elementwise dispatch
         factor = (CALIB_BYTES / 1024.0) / calib
@@ -503,9 +521,11 @@ def batching_work(cc, plans, ws, shots):
             # base tableau (once per fragment): per gate and 64 rows 22 (one-qubit
             # map) or 12 (CX, CZ) int32 operations
             base_ops += rw * (22 * fr["n_one"] + 12 * fr["n_two"])
-            # per variant and measurement: 2m rows x W words x 12 int32 operations
-            # (pivot search and rowsums)
-            tab_ops += nv * nm * 2 * fr["m"] * W_ * 12
+            # the affine models (Heisenberg picture): per variant, elimination
+            # step j and later measurement k > j, W words of the constraint
+            # vector, x and z (three 64-bit xors = 6 int32 operations) and the
+            # cross-term popcount (2): 8 int32 operations per word
+            tab_ops += nv * (nm * (nm - 1) // 2) * 8 * W_
             # per shot: Philox share (100 per 4 shots and 32 indices), one
             # select-and-xor (3 ops) per measurement, one histogram increment;
             # the variant's fp64 table written once
@@ -668,15 +688,24 @@ def bench_precision(args):
 PEAK_BF16 = 2.5e15
 
 
+PEAK_FP32_MFMA = 157.3e12
+
+
 def bench_learned(args):
     """300 qubits, 50 layers, four 5-qubit non-Clifford blocks, 10 cuts
     (4^10 terms), exact fragment tensors, 16-qubit marginal.  The network
-    (64 -> 256 -> 256 -> 256 -> 1) is trained first on 16 other circuits of
-    the same family (not timed in the steps).  One step = the whole learned
-    path on the held-out circuit: fragment tensors, network logits over all
-    4^10 terms, proposal, 16384 sampled terms contracted; against it, the
-    exhaustive path (fragment tensors + contraction of all 4^10 terms).
-    value = exhaustive time / learned time at the stated TVD."""
+    (64 -> 256 -> 256 -> 256 -> 1) is trained first on 64 other circuits of
+    the same family (not timed in the steps; the TVD at 16 and 32 training
+    circuits is reported too).  One step = the whole learned path on the
+    held-out circuit: fragment tensors, network logits over all 4^10 terms,
+    proposal, 16384 sampled terms contracted; against it the dense
+    exhaustive path (fp64 and fp32 MFMA) and the Sec. IX sparse exhaustive
+    path, and the network-free proposals on the same tensors: uniform,
+    product of per-cut shares (the network's inputs) and the product of the
+    fragments' column norms (the network's training labels, exact).  A
+    second held-out circuit measures its exit wires after one Clifford layer
+    (the Clifford fragment's outputs in the cuts' light cone).
+    value = dense exhaustive time / learned time at the stated TVD."""
     import numpy as np
     import torch
 
@@ -685,10 +714,22 @@ def bench_learned(args):
 
     torch.cuda.set_device(0)
     ctx = cc.Context(0)
+    if args.contraction_only:
+        w = W.learned_circuit(200000)
+        plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+        buf = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
+        res = {}
+        for name, prec in (("fp64", cc.CCUT_FP64), ("fp32", cc.CCUT_FP32_MFMA_FP64SUM)):
+            L = cc.Learned(plan, w.qubits, precision=prec)
+            res[name] = 1e3 * _timed(lambda: L.exhaustive(out=buf), args.steps, args.warmup) / args.steps
+            L.close()
+        print(json.dumps({"workload": "learned contraction", "exhaustive_ms": res}), flush=True)
+        return
     n_samples = 16384
+    n_train = 64
     t0 = time.perf_counter()
     xs, ys = [], []
-    for s in range(100000, 100016):
+    for s in range(100000, 100000 + n_train):
         w = W.learned_circuit(s)
         plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
         L = cc.Learned(plan, w.qubits)
@@ -700,70 +741,94 @@ def bench_learned(args):
         ys.append(L.log_weights(terms, kind=2))
         L.close()
         plan.close()
-    X = torch.cat(xs).contiguous()
-    y = torch.cat(ys).contiguous()
-    rows = (X.shape[0] // 64) * 64
-    X, y = X[:rows].contiguous(), y[:rows].contiguous()
     t_data = time.perf_counter() - t0
-    net = cc.Mlp(ctx, 64, 256)
-    t0 = time.perf_counter()
-    losses = net.train(X, y, batch=1024, steps=2000, lr=1e-3, seed=1)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    nets, train = {}, {}
+    for n in (16, 32, n_train):
+        X = torch.cat(xs[:n]).contiguous()
+        y = torch.cat(ys[:n]).contiguous()
+        rows = (X.shape[0] // 64) * 64
+        net = cc.Mlp(ctx, 64, 256)
+        t0 = time.perf_counter()
+        losses = net.train(X[:rows].contiguous(), y[:rows].contiguous(), batch=1024, steps=2000, lr=1e-3, seed=1)
+        torch.cuda.synchronize()
+        nets[n] = net
+        train[n] = {"rows": rows, "loss_first": float(losses[:5].mean()), "loss_last": float(losses[-50:].mean()),
+                    "train_s": time.perf_counter() - t0}
+    net = nets[n_train]
 
-    w = W.learned_circuit(200000)
-    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
-    out_ex = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
-    out_le = torch.empty_like(out_ex)
+    def tvd(a, b):
+        return 0.5 * float(np.abs(a - b).sum())
 
-    def exhaustive():
-        plan.marginal(w.qubits, out=out_ex)
-
-    def learned():
+    def evaluate(w, timed):
+        plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
         L = cc.Learned(plan, w.qubits)
-        q = cc.proposal(ctx, L.logits(net))
-        L.estimate(q, n_samples, 9, out=out_le)
+        exact = L.exhaustive()
+        _, n_support = L.support(cap=0)
+        props = {"uniform": cc.proposal(ctx, None, K=L.K), "shares": cc.proposal(ctx, L.log_weights(kind=1)),
+                 "norm_product": cc.proposal(ctx, L.log_weights(kind=0))}
+        for n, nt in nets.items():
+            props[f"learned_{n}"] = cc.proposal(ctx, L.logits(nt))
+        tv = {k: tvd(L.estimate(q, n_samples, 9), exact) for k, q in props.items()}
+        out = {"circuit": w.name, "support_terms": int(n_support), "tvd_at_16384_samples": tv}
+        if timed:
+            L32 = cc.Learned(plan, w.qubits, precision=cc.CCUT_FP32_MFMA_FP64SUM)
+            buf = torch.empty(1 << len(w.qubits), dtype=torch.float64, device="cuda")
+
+            def learned():
+                Lx = cc.Learned(plan, w.qubits)
+                Lx.estimate(cc.proposal(ctx, Lx.logits(net)), n_samples, 9, out=buf)
+                Lx.close()
+
+            fns = {"exhaustive_fp64": lambda: plan.marginal(w.qubits, out=buf),
+                   "exhaustive_fp32": lambda: plan.marginal(w.qubits, out=buf, precision=cc.CCUT_FP32_MFMA_FP64SUM),
+                   "sparse_exhaustive": lambda: plan.marginal(w.qubits, out=buf, flags=cc.CCUT_FLAG_SPARSE),
+                   "learned": learned}
+            out["ms"] = {k: 1e3 * _timed(f, args.steps, args.warmup) / args.steps for k, f in fns.items()}
+            # the contraction alone (tensors kept), with its kernel time
+            con = {}
+            for name, Lk in (("fp64", L), ("fp32", L32)):
+                times = _kernel_pass(ctx, lambda: Lk.exhaustive(out=buf), args.steps)
+                n_l, ms_l = times["recombine_fp64_kernel"]
+                con[name] = ms_l / args.steps
+            out["contraction_kernel_ms"] = con
+            out["fp32_max_abs_err"] = float(np.abs(L32.exhaustive() - exact).max())
+            L32.close()
         L.close()
+        plan.close()
+        return out
 
-    out_sp = torch.empty_like(out_ex)
-
-    def sparse_exhaustive():  # Sec. IX: only the cut terms whose columns are all nonzero
-        plan.marginal(w.qubits, out=out_sp, flags=cc.CCUT_FLAG_SPARSE)
-
-    dt_ex = _timed(exhaustive, args.steps, args.warmup)
-    dt_sp = _timed(sparse_exhaustive, args.steps, args.warmup)
-    dt_le = _timed(learned, args.steps, args.warmup)
-    Ls = cc.Learned(plan, w.qubits)
-    _, n_support = Ls.support(cap=0)
-    Ls.close()
-    times = _kernel_pass(ctx, learned, args.steps)
-    ex = out_ex.cpu().numpy()
-    le = out_le.cpu().numpy()
-    tvd = 0.5 * float(np.abs(le - ex).sum())
-    K = 4 ** len(w.cuts)
-    H, F = 256, 64
-    mlp_launches, mlp_ms = times["mlp_kernels"]
-    flops = 2.0 * K * (F * H + 2 * H * H + H) * args.steps
-    ms_le = 1e3 * dt_le / args.steps
-    ms_ex = 1e3 * dt_ex / args.steps
+    held = [evaluate(W.learned_circuit(200000), True),
+            evaluate(W.learned_circuit(200001, tail=1, near_exits=True), True)]
+    main_ = held[0]
+    ms = main_["ms"]
+    w0 = W.learned_circuit(200000)
+    p0 = cc.Plan(ctx, w0.n, w0.ops, w0.cuts)
+    rbits = [cc.ccut_request_info(p0.handle, w0.qubits, f)[1] for f in range(p0.info()[0])]
+    p0.close()
+    K = 4 ** len(w0.cuts)
+    N = 1 << max(rbits)                 # the column side: the fragment with the most requested bits
+    M = 1 << (sum(rbits) - max(rbits))  # the row side: every other fragment
+    flops = 2.0 * M * N * K
+    c32 = main_["contraction_kernel_ms"]["fp32"]
+    c64 = main_["contraction_kernel_ms"]["fp64"]
     line = {
-        "metric": METRIC, "value": ms_ex / ms_le, "unit": "x (exhaustive time / learned time, TVD<=1e-2)",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_le, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/f64", "data": "synthetic",
+        "metric": METRIC, "value": ms["exhaustive_fp64"] / ms["learned"],
+        "unit": "x (dense exhaustive time / learned time, TVD<=1e-2)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms["learned"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/f64",
+        "data": "synthetic",
         "config": {"workload": "learned: 300 qubits, 50 layers (CX density 0.3), four 5-qubit blocks x 3 T, "
                                "exits (3,3,2,2) -> 10 cuts (4^10 terms), exact tensors, 16-qubit marginal; "
-                               "network trained on 16 circuits of the family, evaluated on a held-out one",
+                               f"network trained on {n_train} circuits of the family, evaluated on held-out ones",
                    "samples": n_samples, "cut_terms": K},
-        "exhaustive_ms": ms_ex, "learned_ms": ms_le, "tvd_learned_vs_exhaustive": tvd,
-        "sparse_exhaustive_ms": 1e3 * dt_sp / args.steps, "support_terms": int(n_support),
-        "sparse_max_abs_diff": float(np.abs(out_sp.cpu().numpy() - ex).max()),
-        "train": {"rows": rows, "steps": 2000, "batch": 1024, "loss_first": float(losses[:5].mean()),
-                  "loss_last": float(losses[-50:].mean()), "train_s": t_train, "dataset_s": t_data},
-        "kernels_ms_per_step": {k: round(ms / args.steps, 5) for k, (n, ms) in times.items() if n},
-        "roofline": {"bound": "mfma", "kernel": "mlp_fused_forward_kernel (network over all 4^10 terms)",
-                     "achieved": flops / (mlp_ms / 1e3) / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
-                     "frac": flops / (mlp_ms / 1e3) / PEAK_BF16, "traffic": None,
-                     "avg_launch_us": 1e3 * mlp_ms / max(mlp_launches, 1)},
+        "held_out": held,
+        "learned_vs_sparse_exhaustive_time": ms["learned"] / ms["sparse_exhaustive"],
+        "train": {str(k): v for k, v in train.items()}, "dataset_s": t_data,
+        "roofline": {"bound": "mfma", "kernel": f"gemm_kernel (dense exhaustive contraction, {M} x {N} x {K}, fp32)",
+                     "achieved": flops / (c32 / 1e3) / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": flops / (c32 / 1e3) / PEAK_FP32_MFMA, "traffic": None, "avg_launch_us": 1e3 * c32},
+        "contraction_fp64": {"achieved_tflops": flops / (c64 / 1e3) / 1e12, "peak_tflops": PEAK_FP64 / 1e12,
+                             "frac": flops / (c64 / 1e3) / PEAK_FP64, "kernel_ms": c64},
     }
     print(json.dumps(line), flush=True)
 
