@@ -5,7 +5,7 @@ circuits of uneven shape (width 20-200, depth 20-60, 1-6 T gates in one
 block of at most 12 wires, 1-4 cuts, half of them mirrored in time), 1e4
 shots per Clifford fragment variant, a 16-qubit marginal per circuit.  One
 step = one replay of the captured batch: every fragment variant of every
-circuit (tableau pass, Philox shots, state vectors), the Pauli transforms
+circuit (affine sample models, Philox shots, state vectors), the Pauli transforms
 and the 4^k recombinations.
 
 Prints one JSON line.  value = fragment-variant shots per second of the
@@ -102,8 +102,8 @@ def cpu_baseline(w, target_s: float):
 
 
 # kernel name -> the source file whose contents its traffic figure belongs to
-KERNEL_SOURCES = {"sv_kernel": "k_sv.hip", "tableau": "k_tableau.hip", "parity": "k_sample.hip",
-                  "sample_kernel": "k_sample.hip"}
+KERNEL_SOURCES = {"sv_kernel": "k_sv.hip", "affine_kernel": "k_affine.hip", "carry_kernel": "k_heis.hip",
+                  "parity": "k_sample.hip", "sample_kernel": "k_sample.hip"}
 CALIB_BYTES = 64 << 20
 
 
@@ -227,7 +227,7 @@ def main():
     value = shots_per_step / (dt / args.steps)
 
     # dominant kernel (among those with an algorithmic work model: the state
-    # vector, the tableau pass, the sampler and the parity kernel) and its
+    # vector, the affine models, the sampler and the parity kernel) and its
     # algorithmic work per launch
     overall = max(times.items(), key=lambda kv: kv[1][1])[0]
     n_meas_z = 24
@@ -237,15 +237,15 @@ def main():
     # algorithmic work per step (both calls), as stated in the design notes
     # the marginal and the Z-string call each run the state-vector pass once
     sv_work = sv_flops(cc, plan, frags, w.qubits) + sv_flops(cc, plan, frags, _mask_qubits(masks, w.n))
-    tab_ops = 0.0
-    for f in cl:
-        rw = (2 * f["m"] + 1 + 63) // 64
-        # column-sliced rule per gate and 64 rows: 11 (one-qubit map) or 6
-        # (CX, CZ) 64-bit operations, i.e. 22 or 12 int32 operations
-        tab_ops += 2 * f["n_variants"] * rw * (22 * f["n_one"] + 12 * f["n_two"])
+    carry_ops = model_ops = 0.0
+    for qs in (w.qubits, _mask_qubits(masks, w.n)):
+        c_, m_ = affine_work(cc, plan, frags, qs)
+        carry_ops += c_
+        model_ops += m_
     work = {
         "sv_kernel": (sv_work, "fp64", PEAK_FP64, "GFLOP/s"),
-        "tableau_kernel": (tab_ops, "alu", PEAK_INT32_OPS, "Gop/s"),
+        # one timer covers both: the carry-back and the per-variant elimination
+        "affine_kernel": (carry_ops + model_ops, "alu", PEAK_INT32_OPS, "Gop/s"),
         # per shot: a Philox call per 4 shots and 32 measurement indices, then one
         # AND + POPCOUNT + accumulate per Z string
         "parity_kernel": (n_cliff_var * w.shots * (PHILOX_OPS / 4 * ((n_meas_z + 31) // 32) + 3 * n_ext),
@@ -478,6 +478,26 @@ def cpu_baseline_batching(target_s: float, full_shots: int, seed: int):
             "host": host}
 
 
+def affine_work(cc, plan, frags, qubits):
+    """Algorithmic int32 work of the affine sample models of a request's
+    Clifford fragments, as (carry-back, elimination): the carry-back takes
+    22 (fused one-qubit map) or 12 (CX, CZ) int32 operations per gate and 64
+    carried rows (bit-sliced over rows; one row per requested output, two
+    per quantum output); the elimination, per variant, step j and later
+    measurement k > j, W = ceil(m/64) words of the constraint vector: three
+    64-bit xors (6 int32 operations) and the cross-term popcount (2)."""
+    carry = model = 0.0
+    for f, fr in enumerate(frags):
+        if not fr["clifford"]:
+            continue
+        nm, _ = cc.ccut_request_info(plan.handle, qubits, f)
+        n_qout = sum(1 for a in fr["axes"] if a[1] == 0)
+        rw = (nm + n_qout + 63) // 64
+        carry += rw * (22 * fr["n_one"] + 12 * fr["n_two"])
+        model += fr["n_variants"] * (nm * (nm - 1) // 2) * 8 * ((fr["m"] + 63) // 64)
+    return carry, model
+
+
 def batching_work(cc, plans, ws, shots):
     """Algorithmic work of one batch step per modelled kernel class:
     {kernel: (amount, kind)} with kind 'int' (int32 ops), 'fp64' (flops) or
@@ -507,6 +527,9 @@ def batching_work(cc, plans, ws, shots):
         if shots <= 0xFFFF:
             c16 = {f for f, fr in enumerate(frags)
                    if fr["clifford"] and ((f == g and not plain) or (f != g and fr["axes"]))}
+        c_, m_ = affine_work(cc, p, frags, w.qubits)
+        base_ops += c_
+        tab_ops += m_
         for f, fr in enumerate(frags):
             nm, nr = info[f]
             nv = fr["n_variants"]
@@ -516,16 +539,6 @@ def batching_work(cc, plans, ws, shots):
                 tr_bytes += in_b * (nv << nm) + 8.0 * ((4 ** len(fr["axes"])) << nr)
             if not fr["clifford"]:
                 continue
-            W_ = (fr["m"] + 63) // 64
-            rw = (2 * fr["m"] + 63) // 64
-            # base tableau (once per fragment): per gate and 64 rows 22 (one-qubit
-            # map) or 12 (CX, CZ) int32 operations
-            base_ops += rw * (22 * fr["n_one"] + 12 * fr["n_two"])
-            # the affine models (Heisenberg picture): per variant, elimination
-            # step j and later measurement k > j, W words of the constraint
-            # vector, x and z (three 64-bit xors = 6 int32 operations) and the
-            # cross-term popcount (2): 8 int32 operations per word
-            tab_ops += nv * (nm * (nm - 1) // 2) * 8 * W_
             # per shot: Philox share (100 per 4 shots and 32 indices), one
             # select-and-xor (3 ops) per measurement, one histogram increment;
             # the variant's fp64 table written once
@@ -535,7 +548,7 @@ def batching_work(cc, plans, ws, shots):
         N = 1 << max(rows)
         rc_flops += 2.0 * M * N * K
         rc_bytes += 8.0 * K * M + (2.0 if g in c16 else 8.0) * K * N + 8.0 * M * N
-    return {"sv_kernel": (sv, "fp64"), "tableau_kernel": (tab_ops, "int"), "base_tableau_kernel": (base_ops, "int"),
+    return {"sv_kernel": (sv, "fp64"), "affine_kernel": (tab_ops, "int"), "carry_kernel": (base_ops, "int"),
             "sample_kernel": (samp_ops, "int"), "sample_kernel:bytes": (samp_bytes, "bytes"),
             "transform_pass_kernel": (tr_bytes, "bytes"), "recombine_fp64_kernel": (rc_flops, "fp64"),
             "recombine_fp64_kernel:bytes": (rc_bytes, "bytes")}

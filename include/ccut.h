@@ -26,8 +26,9 @@
  *  - results are a pure function of (ops, cuts, request, seed, shots, mode):
  *    every random bit is Philox4x32-10 keyed by seed and counted by
  *    (variant id, shot, measurement index);
- *  - estimates are raw quasi-probabilities (no maximum-likelihood
- *    correction): sampled marginals can be slightly negative.
+ *  - estimates are raw quasi-probabilities unless CCUT_FLAG_ML asks for
+ *    the maximum-likelihood fragment correction: raw sampled marginals can
+ *    be slightly negative.
  *
  * Readings of the method where the paper is silent:
  *  - quantum inputs are prepared in {|0>, |1>, |+>, |+i>}, quantum outputs
@@ -470,7 +471,7 @@ void ccut_mlp_destroy(ccut_mlp *M);
  * `kid` the number of launches and their summed duration in ms since the
  * last reset. */
 enum {
-  CCUT_K_TABLEAU = 0,
+  CCUT_K_AFFINE = 0, /* affine sample models (carry-back + per-variant elimination) */
   CCUT_K_SAMPLE = 1,
   CCUT_K_HIST_REDUCE = 2,
   CCUT_K_EXACT = 3,
@@ -482,7 +483,7 @@ enum {
   CCUT_K_HEISENBERG = 9,
   CCUT_K_MLP = 10,
   CCUT_K_TERMS = 11,
-  CCUT_K_BASE = 12, /* shared base tableaux of a batch's Clifford fragments */
+  CCUT_K_CARRY = 12, /* a batch's carry-back of the measured Paulis, all Clifford fragments */
   CCUT_K_COUNT = 13
 };
 ccut_status ccut_timing_enable(ccut_ctx *ctx, int enable);

@@ -26,9 +26,9 @@ CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED =
 CCUT_FP64, CCUT_FP32_MFMA_FP64SUM, CCUT_FP32X3_MFMA_FP64SUM = 0, 1, 2
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
 CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE, CCUT_FLAG_ML = 1, 2, 4
-KERNELS = ("tableau_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
+KERNELS = ("affine_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
            "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
-           "heisenberg_kernels", "mlp_kernels", "term_kernels", "base_tableau_kernel")
+           "heisenberg_kernels", "mlp_kernels", "term_kernels", "carry_kernel")
 STATUS_NAMES = {0: "CCUT_OK", -1: "CCUT_E_INVALID", -2: "CCUT_E_OOM", -3: "CCUT_E_DEVICE",
                 -4: "CCUT_E_NC_TOO_WIDE", -5: "CCUT_E_TOO_MANY_CUTS", -6: "CCUT_E_CANCELLED",
                 -7: "CCUT_E_UNSUPPORTED"}

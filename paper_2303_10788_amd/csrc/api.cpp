@@ -498,7 +498,7 @@ ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, co
     d_row = (uint16_t *)upload(c, row_of.data(), row_of.size() * 2);
     if (!d_axis || !d_row) return fail(c, CCUT_E_OOM, "device allocation failed");
   }
-  KTimer t(c, CCUT_K_TABLEAU);
+  KTimer t(c, CCUT_K_AFFINE);
   HIP_TRY(c, launch_rows(hb, W, d_in, d_out, n_rows, c->cur));
   if (nm > (uint32_t)kMaxMeas)
     HIP_TRY(c, launch_affine_wide(h, W, d_axis, d_row, nm, d_out, v0, nv, models, c->cur));
@@ -1708,11 +1708,11 @@ ccut_status ccut_timing_read(ccut_ctx *c, uint32_t kid, uint64_t *launches, doub
 }
 
 const char *ccut_kernel_name(uint32_t kid) {
-  static const char *names[CCUT_K_COUNT] = {"tableau_kernel", "sample_kernel", "hist_reduce_kernel",
+  static const char *names[CCUT_K_COUNT] = {"affine_kernel", "sample_kernel", "hist_reduce_kernel",
                                             "exact_kernel", "sv_kernel", "parity_kernel",
                                             "transform_pass_kernel", "recombine_fp64_kernel",
                                             "zrecombine_fp64_kernel", "heisenberg_kernels",
-                                            "mlp_kernels", "term_kernels", "base_tableau_kernel"};
+                                            "mlp_kernels", "term_kernels", "carry_kernel"};
   return kid < CCUT_K_COUNT ? names[kid] : "";
 }
 
@@ -1819,7 +1819,7 @@ ccut_status batch_models(ccut_batch *b, FragDev *d_descs, const uint32_t *d_w, B
                          const uint64_t *d_rows, uint64_t *d_models, uint32_t block, uint32_t grid) {
   ccut_ctx *c = b->ctx;
   if (b->items.empty()) return CCUT_OK;
-  KTimer t(c, CCUT_K_TABLEAU);
+  KTimer t(c, CCUT_K_AFFINE);
   HIP_TRY(c, launch_affine_batch(d_descs, d_w, d_items, (uint32_t)b->items.size(), d_rows, d_models, block, grid,
                                  c->cur));
   return CCUT_OK;
@@ -1837,7 +1837,7 @@ ccut_status batch_carry(ccut_batch *b, uint64_t **d_rows_out) {
   CarryJob *d_jobs = (CarryJob *)upload(c, b->carry_jobs.data(), b->carry_jobs.size() * sizeof(CarryJob));
   if (!d_in || !d_out || !d_back || !d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
   {
-    KTimer t(c, CCUT_K_BASE);
+    KTimer t(c, CCUT_K_CARRY);
     HIP_TRY(c, launch_carry_batch(d_back, d_jobs, (uint32_t)b->carry_jobs.size(), b->max_m, b->max_rows, d_in, d_out,
                                   c->cur));
   }
