@@ -311,11 +311,15 @@ ccut_status ccut_request_info(ccut_plan *plan, const uint32_t *qubits, uint32_t 
 
 /* Many circuits at once (each plan is one circuit; its variant ids use its
  * position i in the batch as the circuit index, eo->circuit is ignored).
- * All Clifford fragment variants of all plans run in one persistent,
- * work-queue tableau launch whose workgroup size and workgroups per CU are
- * picked by timing the candidates on this batch at creation; the remaining
- * per-plan steps follow, and with use_graph != 0 the whole evaluation is
- * captured once as a HIP graph and replayed by ccut_batch_run.
+ * The affine sample models of all Clifford fragment variants of all plans
+ * come from one work-queue launch whose workgroup size and workgroups per
+ * CU are picked by timing the candidates at creation.  The choice is kept
+ * for the process, keyed by the device and the batch's model work (item
+ * count and elimination cost, bucketed), and, when the environment variable
+ * CCUT_TUNE_CACHE names a file, read from and appended to that file so
+ * later processes skip the timing.  The remaining steps follow, and with
+ * use_graph != 0 the whole evaluation is captured once as a HIP graph and
+ * replayed by ccut_batch_run.
  * qubits[i] / nq[i] are each plan's marginal request (nq[i] <= 24).  The
  * batch owns its device memory; plans must outlive it.  Creating a batch
  * runs one full evaluation.  Errors: as ccut_marginal. */
@@ -324,16 +328,21 @@ ccut_status ccut_batch_create(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, 
                               const uint32_t *const *qubits, const uint32_t *nq, int use_graph, ccut_batch **out);
 /* Evaluate the batch again (graph replay when captured); outs[i] receives
  * plan i's 2^nq[i] marginal, on the device if outs_on_device.  Host
- * outputs: returns once they are written.  Device outputs: one copy launch
- * writes them all, and the context's stream is ordered after it; the call
- * returns without waiting (work queued later on that stream sees the
- * results).  Runs of one batch are ordered among themselves. */
+ * outputs: returns once they are written.  Device outputs: a replay's
+ * contractions write them in place (an eager run, or a plan whose
+ * contraction has a launch of its own, goes through one copy launch), and
+ * the context's stream is ordered after the batch; the call returns without
+ * waiting (work queued later on that stream sees the results).  Runs of one
+ * batch are ordered among themselves; a run with other output addresses
+ * than the previous one first waits for the previous one. */
 ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_device);
-/* Work items of the persistent launch, the chosen workgroup size, grid,
- * register-tableau use, whether a graph was captured, and the best tuned
- * time of the tableau launch in ms. */
+/* Work items of the affine-model launch, the chosen workgroup size and
+ * grid, whether that choice came from the tuning cache (1) or from timing
+ * at creation (0), whether a graph was captured, and the best tuned time of
+ * the model launch in ms (the cached one on a cache hit).  Any pointer may
+ * be NULL. */
 ccut_status ccut_batch_info(const ccut_batch *b, uint64_t *n_items, uint32_t *block, uint32_t *grid,
-                            int32_t *use_reg, int32_t *graphed, double *tableau_ms);
+                            int32_t *tune_cached, int32_t *graphed, double *models_ms);
 void ccut_batch_destroy(ccut_batch *b);
 /* One-shot convenience: create (no graph), run into host buffers, destroy. */
 ccut_status ccut_run_batch(ccut_ctx *ctx, ccut_plan *const *plans, size_t n, const ccut_eval_opts *eo,

@@ -341,8 +341,8 @@ def ccut_batch_info(batch):
                                   ctypes.c_int32(), ctypes.c_double())
     _check(lib().ccut_batch_info(batch, ctypes.byref(n), ctypes.byref(blk), ctypes.byref(grid), ctypes.byref(reg),
                                  ctypes.byref(gr), ctypes.byref(ms)), None)
-    return dict(n_items=n.value, block=blk.value, grid=grid.value, use_reg=bool(reg.value), graphed=bool(gr.value),
-                tableau_ms=ms.value)
+    return dict(n_items=n.value, block=blk.value, grid=grid.value, tune_cached=bool(reg.value),
+                graphed=bool(gr.value), models_ms=ms.value)
 
 
 def ccut_batch_destroy(batch) -> None:

@@ -9,6 +9,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -1761,7 +1765,7 @@ struct ccut_batch {
   std::vector<Ref> samp;  // sampled Clifford fragments (desc indexes descs)
   std::vector<Ref> nc;    // non-Clifford fragments (desc indexes sv_descs)
   std::vector<FragDev> sv_descs;
-  uint32_t max_m = 0, block = 64, grid = 0, use_reg = 0;
+  uint32_t max_m = 0, block = 64, grid = 0, tune_cached = 0;
   double tuned_ms = 0.0;
   // device outputs: the copy list of the last run (pinned and on the
   // device), reused while the caller passes the same output addresses, and
@@ -1769,9 +1773,20 @@ struct ccut_batch {
   std::vector<double *> last_outs;
   OutCopy *h_copy = nullptr, *d_copy = nullptr;
   hipEvent_t done_ev = nullptr;
+  // the contraction jobs read their output address from out_tab[i] when
+  // they run: res[i] while enqueuing eagerly; in a replay of the captured
+  // graph the caller's device output itself, so no gather copies it
+  // (job_out[i]: plan i's result comes from such a job, else from a launch
+  // of its own into res[i])
+  double **d_out_tab = nullptr, **h_out_tab = nullptr;
+  std::vector<double *> cur_tab;
+  std::vector<uint8_t> job_out;
+  bool capturing = false;
   ~ccut_batch() {
     if (h_copy) (void)hipHostFree(h_copy);
     if (d_copy) (void)hipFree(d_copy);
+    if (h_out_tab) (void)hipHostFree(h_out_tab);
+    if (d_out_tab) (void)hipFree(d_out_tab);
     if (done_ev) (void)hipEventDestroy(done_ev);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1845,8 +1860,71 @@ ccut_status batch_carry(ccut_batch *b, uint64_t **d_rows_out) {
   return CCUT_OK;
 }
 
+// Launch shapes of the affine-model launch chosen by timing, kept for the
+// process (and, when CCUT_TUNE_CACHE names a file, across processes: one
+// "key block per_cu ms" line per entry, read at the first lookup, appended
+// when a new shape is tuned).  The key is the device (architecture, compute
+// units) and the batch's model work: its item count and total elimination
+// cost (sum of measurements^2 x row words), each bucketed by half octaves.
+struct TuneEntry {
+  uint32_t block, per_cu;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(ccut_ctx *c, const ccut_batch *b);
+bool tune_lookup(const std::string &key, TuneEntry &e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!g_tune_loaded) {
+    g_tune_loaded = true;
+    if (const char *path = std::getenv("CCUT_TUNE_CACHE")) {
+      if (FILE *f = std::fopen(path, "r")) {
+        char k[256];
+        unsigned blk = 0, pc = 0;
+        double ms = 0.0;
+        while (std::fscanf(f, "%255s %u %u %lf", k, &blk, &pc, &ms) == 4)
+          if (blk && pc) g_tune[k] = TuneEntry{blk, pc, ms};
+        std::fclose(f);
+      }
+    }
+  }
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  e = it->second;
+  return true;
+}
+void tune_store(const std::string &key, const TuneEntry &e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = e;
+  if (const char *path = std::getenv("CCUT_TUNE_CACHE")) {
+    if (FILE *f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %u %u %.6f\n", key.c_str(), e.block, e.per_cu, e.ms);
+      std::fclose(f);
+    }
+  }
+}
+
 // Enqueue one whole batch evaluation on the batch stream (inside a
 // BatchScope).  Allocation order is fixed, so a replay reuses the same memory.
+std::string tune_key(ccut_ctx *c, const ccut_batch *b) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, c->device);
+  double cost = 0.0;
+  for (const BatchItem &it : b->items) {
+    const double nm = b->descs[it.desc].n_meas;
+    cost += nm * nm * b->desc_w[it.desc];
+  }
+  auto bucket = [](double x) { return x > 0 ? (int)std::floor(2.0 * std::log2(x)) : -1; };
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s:%d:%d:%d", prop.gcnArchName, prop.multiProcessorCount,
+                bucket((double)b->items.size()), bucket(cost));
+  for (char *p = buf; *p; ++p)
+    if (*p == ' ') *p = '_';
+  return buf;
+}
+
 ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   ccut_ctx *c = b->ctx;
   ccut_status st;
@@ -1963,11 +2041,27 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   };
   uint64_t *d_rows = nullptr;
   if ((st = batch_carry(b, &d_rows)) != CCUT_OK) return st;
+  TuneEntry cached{};
+  std::string tkey;
+  if (tune && !b->items.empty()) {
+    tkey = tune_key(c, b);
+    if (tune_lookup(tkey, cached)) {
+      int cus = 256;
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+      const uint64_t full = (b->items.size() * 64 + cached.block - 1) / cached.block;
+      b->block = cached.block;
+      b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(full, (uint64_t)cus * cached.per_cu));
+      b->tuned_ms = cached.ms;
+      b->tune_cached = 1;
+      tune = false;
+    }
+  }
   if (tune && !b->items.empty()) {
     // autotune the model launch: waves per workgroup x workgroups per
     // compute unit (a grid-stride loop covers whatever the grid leaves)
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    uint32_t best_pc = 1;
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
@@ -1989,6 +2083,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
           best = ms;
           b->block = block;
           b->grid = grid;
+          best_pc = per_cu;
         }
         if (grid == full) break;
       }
@@ -1996,6 +2091,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->tuned_ms = best;
+    tune_store(tkey, TuneEntry{b->block, best_pc, best});
   }
   if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, b->block, b->grid)) != CCUT_OK) return st;
   if (!b->samp.empty()) {
@@ -2222,6 +2318,16 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     KTimer t(c, CCUT_K_TRANSFORM);
     HIP_TRY(c, launch_fold(d_fj, (uint32_t)fjobs.size(), c->cur));
   }
+  // the output table: res while enqueuing eagerly; a captured graph reads
+  // whatever the run call has put there
+  b->job_out.assign(np, 0);
+  for (size_t i = 0; i < np; ++i) b->job_out[i] = kind[i] != 1;
+  if (!b->capturing && b->cur_tab != b->res) {
+    HIP_TRY(c, hipStreamSynchronize(b->stream));  // an earlier copy may still read the pinned table
+    for (size_t i = 0; i < np; ++i) b->h_out_tab[i] = b->res[i];
+    HIP_TRY(c, hipMemcpyAsync(b->d_out_tab, b->h_out_tab, np * sizeof(double *), hipMemcpyHostToDevice, b->stream));
+    b->cur_tab = b->res;
+  }
   // contractions: the plain ones' arguments in one upload, the MFMA ones'
   // operand descriptions in another
   std::vector<RecombArgs> plain;
@@ -2252,7 +2358,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     if (kind[i] == 0) {
       RcJob J{};
       J.args = d_plain + plain_of[i];
-      J.out = b->res[i];
+      J.out = b->d_out_tab + i;
       J.nq = nq;
       J.wg0 = rwg;
       rwg += ((1ull << nq) + kRcChunkOut - 1) / kRcChunkOut;
@@ -2275,7 +2381,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       const bool direct = J.splits == 1;  // one split: the kernel writes the outputs itself
       J.partial = direct ? nullptr : aget<double>(c, (size_t)J.splits * h.M * h.N);
       if (!direct && !J.partial) return fail(c, CCUT_E_OOM, "device allocation failed");
-      J.out = b->res[i];
+      J.out = b->d_out_tab + i;
       J.wg0 = gwg[sk];
       J.rwg0 = grwg[sk];
       gwg[sk] += (uint64_t)J.tiles * J.splits;
@@ -2412,6 +2518,8 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
   });
   HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   HIP_TRY(c, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  HIP_TRY(c, hipMalloc((void **)&b->d_out_tab, std::max<size_t>(n, 1) * sizeof(double *)));
+  HIP_TRY(c, hipHostMalloc((void **)&b->h_out_tab, std::max<size_t>(n, 1) * sizeof(double *), hipHostMallocDefault));
   for (size_t k = 0; k < std::min<size_t>(n, 8); ++k) {
     hipStream_t ps = nullptr;
     hipEvent_t je = nullptr;
@@ -2430,7 +2538,9 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     c->replay_uploads = true;
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+      b->capturing = true;
       st = batch_enqueue(b.get(), false);
+      b->capturing = false;
       hipGraph_t g = nullptr;
       e = hipStreamEndCapture(b->stream, &g);
       if (st == CCUT_OK && e == hipSuccess && g) {
@@ -2460,7 +2570,17 @@ ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_devic
   }
   HIP_TRY(c, hipEventRecord(c->fork_ev, c->stream));
   HIP_TRY(c, hipStreamWaitEvent(b->stream, c->fork_ev, 0));
+  const size_t n = b->plans.size();
   if (b->graphed) {
+    // the captured contractions write the caller's device outputs directly
+    std::vector<double *> want(n);
+    for (size_t i = 0; i < n; ++i) want[i] = outs_on_device && b->job_out[i] ? outs[i] : b->res[i];
+    if (want != b->cur_tab) {
+      HIP_TRY(c, hipStreamSynchronize(b->stream));  // the previous copy may still read the pinned table
+      for (size_t i = 0; i < n; ++i) b->h_out_tab[i] = want[i];
+      HIP_TRY(c, hipMemcpyAsync(b->d_out_tab, b->h_out_tab, n * sizeof(double *), hipMemcpyHostToDevice, b->stream));
+      b->cur_tab = want;
+    }
     HIP_TRY(c, hipGraphLaunch(b->exec, b->stream));
   } else {
     BatchScope scope(b, true);
@@ -2468,7 +2588,6 @@ ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_devic
     ccut_status st = batch_enqueue(b, false);
     if (st != CCUT_OK) return st;
   }
-  const size_t n = b->plans.size();
   if (!outs_on_device) {
     for (size_t i = 0; i < n; ++i)
       HIP_TRY(c, hipMemcpyAsync(outs[i], b->res[i], sizeof(double) << b->qubits[i].size(), hipMemcpyDeviceToHost,
@@ -2476,39 +2595,50 @@ ccut_status ccut_batch_run(ccut_batch *b, double *const *outs, int outs_on_devic
     HIP_TRY(c, hipStreamSynchronize(b->stream));
     return CCUT_OK;
   }
-  // device outputs: one gather launch, then the caller's stream waits for it
-  // (no host synchronization)
+  // device outputs not written in place (an eager run, or a plan whose
+  // contraction has a launch of its own): one gather launch; then the
+  // caller's stream waits for the batch (no host synchronization)
   if (n == 0) return CCUT_OK;
   if (!b->d_copy) {
     HIP_TRY(c, hipHostMalloc((void **)&b->h_copy, n * sizeof(OutCopy), hipHostMallocDefault));
     HIP_TRY(c, hipMalloc((void **)&b->d_copy, n * sizeof(OutCopy)));
     HIP_TRY(c, hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming));
   }
+  std::vector<double *> key(outs, outs + n);
+  key.push_back(b->graphed ? (double *)1 : nullptr);  // the copy list depends on the mode too
+  size_t n_copy = 0;
   uint64_t max_n = 0;
-  for (size_t i = 0; i < n; ++i) max_n = std::max<uint64_t>(max_n, uint64_t(1) << b->qubits[i].size());
-  if (!std::equal(outs, outs + n, b->last_outs.begin(), b->last_outs.end())) {
+  for (size_t i = 0; i < n; ++i)
+    if (!b->graphed || !b->job_out[i]) {
+      ++n_copy;
+      max_n = std::max<uint64_t>(max_n, uint64_t(1) << b->qubits[i].size());
+    }
+  if (key != b->last_outs) {
     // the previous run's gather may still read both copies of the list
     HIP_TRY(c, hipStreamSynchronize(b->stream));
-    for (size_t i = 0; i < n; ++i) b->h_copy[i] = OutCopy{b->res[i], outs[i], uint64_t(1) << b->qubits[i].size()};
-    HIP_TRY(c, hipMemcpyAsync(b->d_copy, b->h_copy, n * sizeof(OutCopy), hipMemcpyHostToDevice, b->stream));
-    b->last_outs.assign(outs, outs + n);
+    size_t k = 0;
+    for (size_t i = 0; i < n; ++i)
+      if (!b->graphed || !b->job_out[i]) b->h_copy[k++] = OutCopy{b->res[i], outs[i], uint64_t(1) << b->qubits[i].size()};
+    if (n_copy)
+      HIP_TRY(c, hipMemcpyAsync(b->d_copy, b->h_copy, n_copy * sizeof(OutCopy), hipMemcpyHostToDevice, b->stream));
+    b->last_outs = key;
   }
-  for (size_t i0 = 0; i0 < n; i0 += 65535)
-    HIP_TRY(c, launch_gather_f64(b->d_copy + i0, (uint32_t)std::min<size_t>(65535, n - i0), max_n, b->stream));
+  for (size_t i0 = 0; i0 < n_copy; i0 += 65535)
+    HIP_TRY(c, launch_gather_f64(b->d_copy + i0, (uint32_t)std::min<size_t>(65535, n_copy - i0), max_n, b->stream));
   HIP_TRY(c, hipEventRecord(b->done_ev, b->stream));
   HIP_TRY(c, hipStreamWaitEvent(c->stream, b->done_ev, 0));
   return CCUT_OK;
 }
 
 ccut_status ccut_batch_info(const ccut_batch *b, uint64_t *n_items, uint32_t *block, uint32_t *grid,
-                            int32_t *use_reg, int32_t *graphed, double *tableau_ms) {
+                            int32_t *tune_cached, int32_t *graphed, double *models_ms) {
   if (!b) return CCUT_E_INVALID;
   if (n_items) *n_items = b->items.size();
   if (block) *block = b->block;
   if (grid) *grid = b->grid;
-  if (use_reg) *use_reg = (int32_t)b->use_reg;
+  if (tune_cached) *tune_cached = (int32_t)b->tune_cached;
   if (graphed) *graphed = b->graphed ? 1 : 0;
-  if (tableau_ms) *tableau_ms = b->tuned_ms;
+  if (models_ms) *models_ms = b->tuned_ms;
   return CCUT_OK;
 }
 

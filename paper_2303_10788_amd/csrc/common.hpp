@@ -460,7 +460,7 @@ hipError_t launch_recombine_fp64(const RecombArgs *d_args, uint32_t n_frags, uin
 // workgroups [wg0, next wg0) cover its 2^nq outputs, 128 per workgroup.
 struct RcJob {
   const RecombArgs *args;
-  double *out;
+  double *const *out;  // slot holding the output address (read when the job runs)
   uint64_t wg0;
   uint32_t nq, pad_;
 };
@@ -531,7 +531,7 @@ uint64_t gemm_k_per_split(const GemmArgs &h, uint32_t splits, bool skinny);
 struct GemmJob {
   const GemmArgs *args;
   double *partial;
-  double *out;
+  double *const *out;  // slot holding the output address (read when the job runs)
   uint64_t wg0, rwg0, k_per_split;
   uint32_t tiles, splits;
 };

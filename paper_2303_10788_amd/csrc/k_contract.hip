@@ -145,77 +145,147 @@ __global__ void transform_all_kernel(const TransformAll A, const double *__restr
 // longer workgroups: the dispatcher, not the tiles, limits short ones), and
 // the workgroups of one XCD take consecutive ranges (xcd_block): the tiles
 // of a variant row share its cache lines.
-constexpr uint32_t kTileThreads = 512;
-__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep);
+constexpr uint32_t kTileThreads = 256;
+__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep,
+                                                         uint32_t (*s_pv)[256]);
 
 __global__ __launch_bounds__(kTileThreads) void transform_tiled_kernel(const TileJob *__restrict__ jobs,
                                                                        uint32_t n_jobs, uint64_t total,
                                                                        uint32_t per_wg) {
   __shared__ double s[kTileElems];
   __shared__ uint32_t s_xdep[1u << kTileMaxT];
+  __shared__ uint32_t s_pv[2][256];
   const uint64_t g0 = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * per_wg;
   const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
   uint32_t jb = find_job(jobs, n_jobs, g0, [](const TileJob &J) { return J.wg0; });
   for (uint64_t g = g0; g < g1; ++g) {
     while (jb + 1 < n_jobs && jobs[jb + 1].wg0 <= g) ++jb;
     if (g > g0) __syncthreads();  // the previous tile's LDS is consumed
-    tile_body(jobs[jb], g - jobs[jb].wg0, s, s_xdep);
+    tile_body(jobs[jb], g - jobs[jb].wg0, s, s_xdep, s_pv);
   }
 }
 
-__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep) {
+// The slot offset of the term digits in one byte of P (axes 4 hi .. 4 hi + 3):
+// v part (mixed radix, an output axis' Z on its Z-basis slot) shifted by
+// lb, or'ed with the outcome bits the output axes' Z set.  Offsets of the
+// two bytes add (their v parts add, their outcome bits are disjoint).
+template <uint32_t HI>
+__device__ inline uint32_t pv_byte(uint32_t pb, const uint32_t *Rv, const uint32_t *o3, const uint32_t *lq,
+                                   uint32_t lb) {
+  uint32_t v = 0, l = 0;
+#pragma unroll
+  for (uint32_t jj = 0; jj < 4; ++jj) {
+    const uint32_t j = 4 * HI + jj;
+    const uint32_t p = (pb >> (2 * jj)) & 3u;
+    const uint32_t z = o3[j] & ((p + 1u) >> 2);  // 1 iff p = 3 on an output axis
+    v += (p - 3u * z) * Rv[j];
+    l |= z << lq[j];
+  }
+  return (v << lb) | l;
+}
+
+__device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint64_t u, double *s, uint32_t *s_xdep,
+                                                         uint32_t (*s_pv)[256]) {
+  static_assert(kTileThreads == 256, "one byte of P per thread in the offset tables");
   const uint32_t tid = threadIdx.x;
   const uint32_t a = J.n_axes, V = J.v_count, lb = J.lbits, t = J.t, thr = J.thr, nh = J.nh;
   const uint32_t XL = 1u << lb, XT = 1u << t;
-  // the tile's fixed x_in bits: u deposited into the non-outcome positions from thr up
-  uint64_t base = 0;
-  {
-    uint64_t rest = u;
-    uint32_t hi = 0;
-    for (uint32_t p = thr; rest; ++p) {
-      if (hi < nh && J.hpos[hi] == p) {
-        ++hi;
-        continue;
-      }
-      base |= (rest & 1ull) << p;
-      rest >>= 1;
-    }
-  }
+  // the job's per-axis positions in registers, read once (uniform).  Slots
+  // past the job's axes hold 0 and are never selected: the bits and digits
+  // they would place are 0, so the index arithmetic below needs no guards.
+  uint32_t hp[kMaxTileAxes], xp[kTileMaxT];
+#pragma unroll
+  for (uint32_t h = 0; h < (uint32_t)kMaxTileAxes; ++h) hp[h] = J.hpos[h];
+#pragma unroll
+  for (uint32_t i = 0; i < kTileMaxT; ++i) xp[i] = J.xpos[i];
+  // the tile's fixed x_in bits: u's bits in the non-outcome positions from
+  // thr up, i.e. u << thr with a zero inserted at each outcome position at
+  // or above thr (ascending)
+  uint64_t base = (uint64_t)u << thr;
+#pragma unroll
+  for (uint32_t h = 0; h < (uint32_t)kMaxTileAxes; ++h)
+    if (h < nh) base = ((base >> hp[h]) << (hp[h] + 1)) | (base & ((1ull << hp[h]) - 1ull));
   for (uint32_t xo = tid; xo < XT; xo += kTileThreads) {
     uint32_t l = 0;
-    for (uint32_t i = 0; i < t; ++i) l |= ((xo >> i) & 1u) << J.xpos[i];
+#pragma unroll
+    for (uint32_t i = 0; i < kTileMaxT; ++i) l |= ((xo >> i) & 1u) << xp[i];
     s_xdep[xo] = l;
+  }
+  // per-axis radix products, output flags and outcome positions (slots past
+  // the axes: radix 0 -> flag 0, digit always 0), then the two byte tables
+  {
+    uint32_t Rv[kMaxTileAxes], o3[kMaxTileAxes], lq[kMaxTileAxes];
+    uint32_t Rj = 1;
+#pragma unroll
+    for (uint32_t j = 0; j < (uint32_t)kMaxTileAxes; ++j) {
+      Rv[j] = Rj;
+      o3[j] = J.rad[j] == 3 ? 1u : 0u;
+      lq[j] = J.lpos[j];
+      Rj *= J.rad[j] ? J.rad[j] : 1u;
+    }
+    s_pv[0][tid] = pv_byte<0>(tid, Rv, o3, lq, lb);
+    s_pv[1][tid] = pv_byte<1>(tid, Rv, o3, lq, lb);
   }
   const uint32_t lowmask = (1u << thr) - 1u;
   const uint32_t n_el = V << lb;
-  // every load of a thread issued before its first LDS store
+  // x_in bits of a tile-local index l: bits below thr in place, bit thr + h
+  // at the outcome position hp[h] (a bit permutation, so the deposit of
+  // disjoint bit sets or's)
+  auto dep = [&](uint32_t l) {
+    uint64_t x = l & lowmask;
+#pragma unroll
+    for (uint32_t h = 0; h < (uint32_t)kMaxTileAxes; ++h) x |= (((uint64_t)l >> (thr + h)) & 1ull) << hp[h];
+    return x;
+  };
+  // element e = tid + 256 i has l = (tid mod XL) | ((256 i) mod XL) with
+  // disjoint bits: this thread's part is deposited once, the second part
+  // (nonzero only when XL > 256) is uniform
+  const uint64_t xt = base | dep(tid & (XL - 1u));
+  // every element's table index first, then all loads, then the
+  // conversions: no load waits on the one before it
   constexpr uint32_t kPer = kTileElems / kTileThreads;
-  double vals[kPer];
+  uint64_t idx[kPer];
 #pragma unroll
   for (uint32_t i = 0; i < kPer; ++i) {
     const uint32_t e = tid + i * kTileThreads;
-    if (e < n_el) {
-      const uint32_t v = e >> lb, l = e & (XL - 1u);
-      uint64_t x = base | (l & lowmask);
-      for (uint32_t h = 0; h < nh; ++h) x |= (uint64_t)((l >> (thr + h)) & 1u) << J.hpos[h];
-      const uint64_t idx = (uint64_t)v * J.x_in + x;
-      vals[i] = J.in16 ? (double)J.in16[idx] / J.shots : J.in[idx];
-    }
+    const uint32_t v = e >> lb;
+    uint64_t x = xt;
+    if (XL > kTileThreads) x |= dep((i * kTileThreads) & (XL - 1u));
+    idx[i] = e < n_el ? (uint64_t)v * J.x_in + x : 0;  // entry 0 stands in for the lanes past the tile
   }
+  if (J.in16) {
+    const __attribute__((address_space(1))) uint16_t *in16 =
+        (const __attribute__((address_space(1))) uint16_t *)J.in16;
+    const double shots = J.shots;
+    uint32_t c[kPer];
 #pragma unroll
-  for (uint32_t i = 0; i < kPer; ++i) {
-    const uint32_t e = tid + i * kTileThreads;
-    if (e < n_el) s[e] = vals[i];
+    for (uint32_t i = 0; i < kPer; ++i) c[i] = in16[idx[i]];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) {
+      const uint32_t e = tid + i * kTileThreads;
+      if (e < n_el) s[e] = (double)c[i] / shots;
+    }
+  } else {
+    const __attribute__((address_space(1))) double *in = (const __attribute__((address_space(1))) double *)J.in;
+    double d[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) d[i] = in[idx[i]];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; ++i) {
+      const uint32_t e = tid + i * kTileThreads;
+      if (e < n_el) s[e] = d[i];
+    }
   }
   __syncthreads();
   uint32_t R = 1;  // product of the radices of the axes below j
   for (uint32_t j = 0; j < a; ++j) {
     const uint32_t S = R << lb;  // slot stride of axis j's digit
     const uint32_t mag = J.rmag[j];
+    const uint32_t m1 = mag ? 0u : ~0u;  // R_j = 1 (mag 0): the quotient is the value itself, no branch
     // g = q S + r: q = (g >> lb) / R by multiply-high (exact for g < 2^19)
     auto split = [&](uint32_t g, uint32_t &q, uint32_t &r) {
       const uint32_t gh = g >> lb;
-      q = mag ? __umulhi(gh, mag) : gh;
+      q = __umulhi(gh, mag) + (gh & m1);
       r = ((gh - q * R) << lb) | (g & (XL - 1u));
     };
     if (J.rad[j] == 4) {
@@ -234,7 +304,7 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
       for (uint32_t g = tid; g < (V / 3) * half; g += kTileThreads) {
         const uint32_t li = g & (half - 1u), vg = g >> (lb - 1);
         const uint32_t l = ((li >> lp) << (lp + 1)) | (li & (o1 - 1u));
-        const uint32_t vq = mag ? __umulhi(vg, mag) : vg;
+        const uint32_t vq = __umulhi(vg, mag) + (vg & m1);
         const uint32_t b = ((vq * 3 * R + (vg - vq * R)) << lb) | l;
         const double x0 = s[b], x1 = s[b + o1], y0 = s[b + S], y1 = s[b + S + o1];
         const double z0 = s[b + 2 * S], z1 = s[b + 2 * S + o1];
@@ -255,18 +325,19 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
     for (uint32_t j = 0; j < a; ++j) {
       if ((J.fold >> j) & 1u) {
         const uint32_t S = R << lb, mag = J.rmag[j];
+        const uint32_t m1 = mag ? 0u : ~0u;
         const uint32_t ngroups = J.rad[j] == 4 ? (n_el >> 2) : (V / 3) * (XL >> 1);
         for (uint32_t g = tid; g < ngroups; g += kTileThreads) {
           uint32_t b, s1, s2, s3;
           if (J.rad[j] == 4) {
-            const uint32_t gh = g >> lb, q = mag ? __umulhi(gh, mag) : gh;
+            const uint32_t gh = g >> lb, q = __umulhi(gh, mag) + (gh & m1);
             b = q * 4 * S + (((gh - q * R) << lb) | (g & (XL - 1u)));
             s1 = b + S, s2 = b + 2 * S, s3 = b + 3 * S;
           } else {
             const uint32_t lp = J.lpos[j], half = XL >> 1, o1 = 1u << lp;
             const uint32_t li = g & (half - 1u), vg = g >> (lb - 1);
             const uint32_t l = ((li >> lp) << (lp + 1)) | (li & (o1 - 1u));
-            const uint32_t vq = mag ? __umulhi(vg, mag) : vg;
+            const uint32_t vq = __umulhi(vg, mag) + (vg & m1);
             b = ((vq * 3 * R + (vg - vq * R)) << lb) | l;
             s1 = b + S, s2 = b + 2 * S, s3 = b + o1;
           }
@@ -281,22 +352,15 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
       R *= J.rad[j];
     }
   }
-  // out[P][x_out], P base 4 (axis 0 fastest), x_out = u 2^t + xo
+  // out[P][x_out], P base 4 (axis 0 fastest), x_out = u 2^t + xo: the
+  // source slot from the two byte tables (P < 4^a <= 4096) and s_xdep
+  double *out = J.out;
+  const uint64_t x_out = J.x_out, ob = (uint64_t)u << t;
   const uint32_t n_out = XT << (2 * a);
   for (uint32_t e = tid; e < n_out; e += kTileThreads) {
     const uint32_t xo = e & (XT - 1u), P = e >> t;
-    uint32_t v = 0, l = s_xdep[xo], Rj = 1;
-    for (uint32_t j = 0; j < a; ++j) {
-      const uint32_t p = (P >> (2 * j)) & 3u;
-      if (J.rad[j] == 4) {
-        v += p * Rj;
-      } else {
-        v += (p == 3 ? 0u : p) * Rj;
-        if (p == 3) l |= 1u << J.lpos[j];
-      }
-      Rj *= J.rad[j];
-    }
-    J.out[(uint64_t)P * J.x_out + (u << t) + xo] = s[(v << lb) | l];
+    const uint32_t off = s_pv[0][P & 255u] + s_pv[1][P >> 8] + s_xdep[xo];
+    out[(uint64_t)P * x_out + ob + xo] = s[off];
   }
 }
 
@@ -332,25 +396,31 @@ __global__ void recombine_fp64_kernel(const RecombArgs *__restrict__ A, uint32_t
 // computed once per workgroup into LDS, each thread keeps its rows in
 // registers, and the term loop is unrolled so the gathers overlap.
 constexpr uint32_t kRcFrags = 8, kRcChunk = kRcChunkOut;
+typedef const __attribute__((address_space(4))) RecombFrag c_RecombFragK;
 // terms: the cut terms to sum (ascending), or null for all 4^k.
 __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, uint32_t nq,
                                             double *__restrict__ outp, uint64_t blk,
                                             const uint64_t *__restrict__ terms = nullptr, uint64_t n_terms = 0) {
   __shared__ uint64_t s_off[kRcFrags][kRcChunk];
-  __shared__ const double *s_T[kRcFrags];
+  typedef const __attribute__((address_space(4))) RecombArgs c_Args;
+  typedef const __attribute__((address_space(1))) double g_f64;
+  c_Args *C = (c_Args *)(uint64_t)A;  // uniform descriptors: scalar loads
   const uint32_t tid = threadIdx.x;
   const uint64_t b = blk * kRcChunk + tid;
   const bool live = b < (1ull << nq);
-  const uint32_t nf = A->n_frags, k = A->k;
-  if (tid < nf) s_T[tid] = A->f[tid].T;
+  const uint32_t nf = C->n_frags, k = C->k;
   uint32_t row[kRcFrags];
 #pragma unroll
   for (uint32_t f = 0; f < kRcFrags; ++f) {
     uint32_t r = 0;
     if (f < nf)
-      for (uint32_t i = 0; i < A->f[f].n_req; ++i) r |= (uint32_t)((b >> A->f[f].req_user[i]) & 1ull) << i;
+      for (uint32_t i = 0; i < C->f[f].n_req; ++i) r |= (uint32_t)((b >> C->f[f].req_user[i]) & 1ull) << i;
     row[f] = r;
   }
+  // global pointers: the gathers never wait behind the LDS offset reads
+  g_f64 *T[kRcFrags];
+#pragma unroll
+  for (uint32_t f = 0; f < kRcFrags; ++f) T[f] = f < nf ? (g_f64 *)(uint64_t)C->f[f].T + row[f] : nullptr;
   const uint64_t nterms = terms ? n_terms : 1ull << (2 * k);
   double acc = 0.0;
   for (uint64_t P0 = 0; P0 < nterms; P0 += kRcChunk) {
@@ -359,7 +429,7 @@ __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, ui
     if (tid < cn) {
       const uint64_t P = terms ? terms[P0 + tid] : P0 + tid;
       for (uint32_t f = 0; f < nf; ++f) {
-        const RecombFrag &F = A->f[f];
+        c_RecombFragK &F = C->f[f];
         uint32_t p = 0;
         for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
         s_off[f][tid] = (uint64_t)p * F.rows;
@@ -367,16 +437,29 @@ __device__ inline void recombine_small_body(const RecombArgs *__restrict__ A, ui
     }
     __syncthreads();
     if (!live) continue;
-    const double *T[kRcFrags];
+    // batches of U terms: every gather of the batch issued before the
+    // first product (the products and the sum in the same order as one
+    // term at a time)
+    constexpr uint32_t U = 4;
+    for (uint32_t t0 = 0; t0 < cn; t0 += U) {
+      double v[U][kRcFrags];
 #pragma unroll
-    for (uint32_t f = 0; f < kRcFrags; ++f) T[f] = f < nf ? s_T[f] + row[f] : nullptr;
-#pragma unroll 4
-    for (uint32_t t = 0; t < cn; ++t) {
-      double term = 1.0;
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t t = t0 + u < cn ? t0 + u : t0;
 #pragma unroll
-      for (uint32_t f = 0; f < kRcFrags; ++f)
-        if (f < nf) term *= T[f][s_off[f][t]];
-      acc += term;
+        for (uint32_t f = 0; f < kRcFrags; ++f)
+          if (f < nf) v[u][f] = T[f][s_off[f][t]];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the gathers stay ahead of their uses
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        if (t0 + u >= cn) break;
+        double term = 1.0;
+#pragma unroll
+        for (uint32_t f = 0; f < kRcFrags; ++f)
+          if (f < nf) term *= v[u][f];
+        acc += term;
+      }
     }
   }
   if (live) outp[b] = ldexp(acc, -(int)k);
@@ -455,7 +538,7 @@ __global__ __launch_bounds__(256) void gather_f64_kernel(const OutCopy *__restri
 // Many plans' plain recombinations in one launch.
 __global__ __launch_bounds__(kRcChunk) void recombine_batch_kernel(const RcJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const RcJob &J) { return J.wg0; });
-  recombine_small_body(jobs[j].args, jobs[j].nq, jobs[j].out, blockIdx.x - jobs[j].wg0);
+  recombine_small_body(jobs[j].args, jobs[j].nq, *jobs[j].out, blockIdx.x - jobs[j].wg0);
 }
 
 // <Z_z>[s] = 2^-k sum_P prod_f t_f[p_f(P)][s].  fp64: products and sum in
@@ -512,12 +595,16 @@ __global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *
                                                               uint64_t per_split, double *__restrict__ partial,
                                                               double *__restrict__ direct) {
   __shared__ uint64_t s_off[kRcFrags][64];
-  __shared__ const double *s_T[kRcFrags];
+  typedef const __attribute__((address_space(4))) RecombArgs c_Args;
+  typedef const __attribute__((address_space(1))) double g_f64;
+  c_Args *C = (c_Args *)(uint64_t)A;  // uniform descriptors: scalar loads
   const uint32_t tid = threadIdx.x;
   const uint32_t s = blockIdx.x * 64 + tid;
   const bool live = s < n_strings;
-  const uint32_t nf = A->n_frags, k = A->k, lo_parts = A->lo_parts;
-  if (tid < nf) s_T[tid] = A->f[tid].T;
+  const uint32_t nf = C->n_frags, k = C->k, lo_parts = C->lo_parts;
+  g_f64 *T[kRcFrags];
+#pragma unroll
+  for (uint32_t f = 0; f < kRcFrags; ++f) T[f] = f < nf ? (g_f64 *)(uint64_t)C->f[f].T + s : nullptr;
   const uint64_t nterms = 1ull << (2 * k);
   const uint64_t P0 = (uint64_t)blockIdx.y * per_split;
   const uint64_t P1 = P0 + per_split < nterms ? P0 + per_split : nterms;
@@ -529,7 +616,7 @@ __global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *
     if (tid < cn) {
       const uint64_t P = C0 + tid;
       for (uint32_t f = 0; f < nf; ++f) {
-        const RecombFrag &F = A->f[f];
+        c_RecombFragK &F = C->f[f];
         uint32_t p = 0;
         for (uint32_t j = 0; j < F.n_axes; ++j) p |= (uint32_t)((P >> (2 * F.axis_cut[j])) & 3ull) << (2 * j);
         s_off[f][tid] = (uint64_t)p * F.rows;
@@ -537,31 +624,44 @@ __global__ __launch_bounds__(64) void zrecombine_small_kernel(const RecombArgs *
     }
     __syncthreads();
     if (!live) continue;
-#pragma unroll 4
-    for (uint32_t t = 0; t < cn; ++t) {
-      const uint64_t P = C0 + t;
-      double term = 1.0;
-      float hi = 1.f, corr = 0.f;
+    constexpr uint32_t U = 4;
+    for (uint32_t t0 = 0; t0 < cn; t0 += U) {
+      double v[U][kRcFrags];
 #pragma unroll
-      for (uint32_t f = 0; f < kRcFrags; ++f) {
-        if (f >= nf) continue;
-        const double v = s_T[f][s_off[f][t] + s];
-        if (F32) {
-          const float th = (float)v, tl = lo_parts ? (float)(v - (double)th) : 0.f;
-          corr = corr * th + hi * tl;
-          hi *= th;
-        } else {
-          term *= v;
-        }
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t t = t0 + u < cn ? t0 + u : t0;
+#pragma unroll
+        for (uint32_t f = 0; f < kRcFrags; ++f)
+          if (f < nf) v[u][f] = T[f][s_off[f][t]];
       }
-      if (F32) {
-        chunk += hi + corr;
-        if ((P & 7) == 7 || P + 1 == P1) {
-          acc += (double)chunk;
-          chunk = 0.f;
+      __builtin_amdgcn_sched_barrier(0);  // the gathers stay ahead of their uses
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        if (t0 + u >= cn) break;
+        const uint64_t P = C0 + t0 + u;
+        double term = 1.0;
+        float hi = 1.f, corr = 0.f;
+#pragma unroll
+        for (uint32_t f = 0; f < kRcFrags; ++f) {
+          if (f >= nf) continue;
+          const double x = v[u][f];
+          if (F32) {
+            const float th = (float)x, tl = lo_parts ? (float)(x - (double)th) : 0.f;
+            corr = corr * th + hi * tl;
+            hi *= th;
+          } else {
+            term *= x;
+          }
         }
-      } else {
-        acc += term;
+        if (F32) {
+          chunk += hi + corr;
+          if ((P & 7) == 7 || P + 1 == P1) {
+            acc += (double)chunk;
+            chunk = 0.f;
+          }
+        } else {
+          acc += term;
+        }
       }
     }
   }

@@ -87,10 +87,67 @@ __device__ inline uint64_t side_bits(const GemmArgs *__restrict__ G, const GemmS
 // (T[P][row], P-major), read with plain strided loads instead of
 // side_value.  Returns the fragment, or null.
 __device__ inline const RecombFrag *direct_side(const GemmArgs *__restrict__ G, const GemmSide &S) {
-  if (S.n != 1 || G->terms || S.shift[0] != 0) return nullptr;
-  const uint32_t f = S.frag[0];
-  if (!G->ident[f]) return nullptr;
+  c_GemmArgs *C = cargs(G);
+  const bool left = &S == &G->L;
+  const uint32_t n = left ? C->L.n : C->R.n;
+  const uint32_t sh = left ? C->L.shift[0] : C->R.shift[0];
+  if (n != 1 || C->terms || sh != 0) return nullptr;
+  const uint32_t f = left ? C->L.frag[0] : C->R.frag[0];
+  if (!C->ident[f]) return nullptr;
   return &G->f[f];
+}
+
+// A direct side's tensor as loop-invariant registers: read once through
+// the constant address space (scalar loads), the entries through global
+// pointers, so LDS stores of the operand tiles cannot be taken to alias
+// them and no descriptor is reloaded per entry.
+struct DirOp {
+  const __attribute__((address_space(1))) double *T64;
+  const __attribute__((address_space(1))) uint16_t *T16;
+  double shots;
+  uint64_t rows;
+  bool c16;
+};
+
+__device__ inline DirOp dir_op(const RecombFrag *F) {
+  DirOp D{};
+  if (!F) return D;
+  c_RecombFrag &C = *(c_RecombFrag *)(uint64_t)F;
+  D.T64 = (const __attribute__((address_space(1))) double *)(uint64_t)C.T;
+  D.T16 = (const __attribute__((address_space(1))) uint16_t *)(uint64_t)C.T;
+  D.shots = C.shots;
+  D.rows = C.rows;
+  D.c16 = C.cnt16 != 0;
+  return D;
+}
+
+// Entries (term kb + kk0 + STEP i, row col) of a direct side, i < NPER;
+// 0 past the K range or the side's extent.  Every load is issued before
+// the first is used (the value is tval's: count / shots, or the fp64 entry).
+template <uint32_t NPER, uint32_t STEP>
+__device__ __attribute__((always_inline)) inline void direct_gather(const DirOp &D, uint64_t kb, uint64_t k1,
+                                                                    uint32_t kk0, uint32_t col, bool col_ok,
+                                                                    double *v) {
+  uint64_t ix[NPER];
+  bool ok[NPER];
+#pragma unroll
+  for (uint32_t i = 0; i < NPER; ++i) {
+    const uint64_t j = kb + kk0 + STEP * i;
+    ok[i] = col_ok && j < k1;
+    ix[i] = ok[i] ? j * D.rows + col : 0;  // entry 0 stands in for the lanes past the range
+  }
+  if (D.c16) {
+    uint32_t c[NPER];
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) c[i] = D.T16[ix[i]];
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) v[i] = ok[i] ? (double)c[i] / D.shots : 0.0;
+  } else {
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) v[i] = D.T64[ix[i]];
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) v[i] = ok[i] ? v[i] : 0.0;
+  }
 }
 
 // Operand factors of a side that is not one direct fragment: the tile's
@@ -198,7 +255,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
       for (int g = 0; g < 4; ++g) acc64[i][j][g] = 0.0;
     }
   const RecombFrag *FA = direct_side(G, G->L), *FB = direct_side(G, G->R);
-  const uint64_t rowsA = FA ? FA->rows : 0, rowsB = FB ? FB->rows : 0;
+  const DirOp DA = dir_op(FA), DB = dir_op(FB);
   extern __shared__ double s_fac[];
   uint32_t wA = 0, wB = 0;
   if constexpr (GEN) {
@@ -208,6 +265,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
   double *facA = s_fac, *facB = s_fac + wA;
   // the arguments read once (uniform), not per operand entry
   const double *tscale = G->tscale;
+  const __attribute__((address_space(1))) double *tscale_g = (const __attribute__((address_space(1))) double *)tscale;
   const uint64_t *terms = G->terms;
   const bool square = G->square != 0;
   // output index bits of the tile's rows and columns (written with the
@@ -226,33 +284,64 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
         __syncthreads();
       }
     }
-    for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
-      const uint32_t kk = e / MT, mm = e % MT;
-      const uint32_t m = tm * MT + mm;
-      const uint64_t j = kb + kk;
-      double a = 0.0;
-      if (m < M && j < k1) {
-        a = (!GEN || FA) ? tval(*FA, j * rowsA + m)
-            : wA         ? fac_value(G, true, facA, kk, mm)
-                         : side_value(G, G->L, m, terms ? terms[j] : j);
-        if (tscale) a *= tscale[j];
-        if (square) a *= a;
+    if (!GEN || FA) {
+      // one fragment read directly: a thread's entries share its row
+      constexpr uint32_t NPA = KC * MT / GEMM_THREADS, STA = GEMM_THREADS / MT;
+      const uint32_t mm = tid % MT, kk0 = tid / MT, m = tm * MT + mm;
+      double a[NPA];
+      direct_gather<NPA, STA>(DA, kb, k1, kk0, m, m < M, a);
+      double ts[NPA];
+#pragma unroll
+      for (uint32_t i = 0; i < NPA; ++i) {
+        const uint64_t j = kb + kk0 + STA * i;
+        ts[i] = (tscale && m < M && j < k1) ? tscale_g[j] : 1.0;
       }
-      As[kk][mm] = (TS)a;
-      if constexpr (LO) Al[kk][mm] = (float)(a - (double)(float)a);
+#pragma unroll
+      for (uint32_t i = 0; i < NPA; ++i) {
+        double x = a[i];
+        if (tscale) x *= ts[i];
+        if (square) x *= x;
+        As[kk0 + STA * i][mm] = (TS)x;
+        if constexpr (LO) Al[kk0 + STA * i][mm] = (float)(x - (double)(float)x);
+      }
+    } else {
+      for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
+        const uint32_t kk = e / MT, mm = e % MT;
+        const uint32_t m = tm * MT + mm;
+        const uint64_t j = kb + kk;
+        double a = 0.0;
+        if (m < M && j < k1) {
+          a = wA ? fac_value(G, true, facA, kk, mm) : side_value(G, G->L, m, terms ? terms[j] : j);
+          if (tscale) a *= tscale[j];
+          if (square) a *= a;
+        }
+        As[kk][mm] = (TS)a;
+        if constexpr (LO) Al[kk][mm] = (float)(a - (double)(float)a);
+      }
     }
-    for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
-      const uint32_t kk = e / NT, nn = e % NT;
-      const uint32_t n = tn * NT + nn;
-      const uint64_t j = kb + kk;
-      double b = 0.0;
-      if (n < N && j < k1)
-        b = (!GEN || FB) ? tval(*FB, j * rowsB + n)
-            : wB         ? fac_value(G, false, facB, kk, nn)
-                         : side_value(G, G->R, n, terms ? terms[j] : j);
-      if (square) b *= b;
-      Bs[kk][nn] = (TS)b;
-      if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
+    if (!GEN || FB) {
+      constexpr uint32_t NPB = KC * NT / GEMM_THREADS, STB = GEMM_THREADS / NT;
+      const uint32_t nn = tid % NT, kk0 = tid / NT, n = tn * NT + nn;
+      double b[NPB];
+      direct_gather<NPB, STB>(DB, kb, k1, kk0, n, n < N, b);
+#pragma unroll
+      for (uint32_t i = 0; i < NPB; ++i) {
+        double x = b[i];
+        if (square) x *= x;
+        Bs[kk0 + STB * i][nn] = (TS)x;
+        if constexpr (LO) Bl[kk0 + STB * i][nn] = (float)(x - (double)(float)x);
+      }
+    } else {
+      for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
+        const uint32_t kk = e / NT, nn = e % NT;
+        const uint32_t n = tn * NT + nn;
+        const uint64_t j = kb + kk;
+        double b = 0.0;
+        if (n < N && j < k1) b = wB ? fac_value(G, false, facB, kk, nn) : side_value(G, G->R, n, terms ? terms[j] : j);
+        if (square) b *= b;
+        Bs[kk][nn] = (TS)b;
+        if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -337,7 +426,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob 
   const GemmJob &J = jobs[j];
   const uint64_t local = bid - J.wg0;
   gemm_body<MODE, GEN>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
-                       J.splits == 1 ? J.out : nullptr);
+                       J.splits == 1 ? *J.out : nullptr);
 }
 
 // Skinny contraction (M <= SK_M rows, fp64): CPT adjacent output columns
@@ -349,38 +438,54 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob 
 // load instruction.
 constexpr uint32_t SK_N = 256, SK_M = 32, SK_KC = 64;
 
+// Column loads through global pointers: vector-memory loads only, so the
+// LDS reads of the loop never wait for them.
+typedef const __attribute__((address_space(1))) uint16_t g_u16;
+typedef const __attribute__((address_space(1))) double g_f64;
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
 template <uint32_t CPT>
 struct ColLoad;
 template <>
 struct ColLoad<1> {
-  __device__ static void cnt(const uint16_t *p, double shots, double *b) { b[0] = (double)p[0] / shots; }
-  __device__ static void f64(const double *p, double *b) { b[0] = p[0]; }
+  typedef uint32_t Raw16;
+  typedef double Raw64;
+  __device__ static Raw16 cnt(g_u16 *p) { return p[0]; }
+  __device__ static void cnt_val(Raw16 w, double shots, double *b) { b[0] = (double)w / shots; }
+  __device__ static Raw64 f64(g_f64 *p) { return p[0]; }
+  __device__ static void f64_val(Raw64 v, double *b) { b[0] = v; }
 };
 template <>
 struct ColLoad<2> {
-  __device__ static void cnt(const uint16_t *p, double shots, double *b) {
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+  typedef uint32_t Raw16;
+  typedef d2v Raw64;
+  __device__ static Raw16 cnt(g_u16 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(p); }
+  __device__ static void cnt_val(Raw16 w, double shots, double *b) {
     b[0] = (double)(w & 0xFFFFu) / shots;
     b[1] = (double)(w >> 16) / shots;
   }
-  __device__ static void f64(const double *p, double *b) {
-    const double2 v = *reinterpret_cast<const double2 *>(p);
-    b[0] = v.x, b[1] = v.y;
-  }
+  __device__ static Raw64 f64(g_f64 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) d2v *>(p); }
+  __device__ static void f64_val(Raw64 v, double *b) { b[0] = v.x, b[1] = v.y; }
 };
 template <>
 struct ColLoad<4> {
-  __device__ static void cnt(const uint16_t *p, double shots, double *b) {
-    const uint2 w = *reinterpret_cast<const uint2 *>(p);
+  typedef u2v Raw16;
+  struct Raw64 {
+    d2v a, b;
+  };
+  __device__ static Raw16 cnt(g_u16 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) u2v *>(p); }
+  __device__ static void cnt_val(Raw16 w, double shots, double *b) {
     b[0] = (double)(w.x & 0xFFFFu) / shots;
     b[1] = (double)(w.x >> 16) / shots;
     b[2] = (double)(w.y & 0xFFFFu) / shots;
     b[3] = (double)(w.y >> 16) / shots;
   }
-  __device__ static void f64(const double *p, double *b) {
-    const double2 v0 = reinterpret_cast<const double2 *>(p)[0], v1 = reinterpret_cast<const double2 *>(p)[1];
-    b[0] = v0.x, b[1] = v0.y, b[2] = v1.x, b[3] = v1.y;
+  __device__ static Raw64 f64(g_f64 *p) {
+    const __attribute__((address_space(1))) d2v *q = reinterpret_cast<const __attribute__((address_space(1))) d2v *>(p);
+    return Raw64{q[0], q[1]};
   }
+  __device__ static void f64_val(Raw64 v, double *b) { b[0] = v.a.x, b[1] = v.a.y, b[2] = v.b.x, b[3] = v.b.y; }
 };
 
 // One instantiation per row count MC (1, 2, ..., 32) and column count CPT:
@@ -398,16 +503,17 @@ __device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs
   const uint64_t k1 = std::min<uint64_t>(K, k0 + k_per_split);
   // the column side is one fragment whose rows are the column index
   const uint32_t rf = G->R.frag[0];
-  const RecombFrag &FR = G->f[rf];
-  const double *Tn = FR.T + n;
-  const uint16_t *Cn = reinterpret_cast<const uint16_t *>(FR.T) + n;
+  c_RecombFrag &FR = cargs(G)->f[rf];
+  g_f64 *Tn = (g_f64 *)(uint64_t)FR.T + n;
+  g_u16 *Cn = (g_u16 *)(uint64_t)FR.T + n;
   const bool cnt16 = FR.cnt16 != 0;
   const double shots = FR.shots;
   const uint64_t rows = FR.rows;
   const bool square = G->square != 0;
-  const double *tscale = G->tscale;
+  g_f64 *tscale = (g_f64 *)(uint64_t)cargs(G)->tscale;
+  const uint64_t *terms = cargs(G)->terms;
   const RecombFrag *FA = direct_side(G, G->L);
-  const uint64_t rowsA = FA ? FA->rows : 0;
+  const DirOp DA = dir_op(FA);
   __shared__ uint64_t s_mbits[MC];  // output index bits of the rows
   if (out) {
     if (tid < MC) s_mbits[tid] = side_bits(G, G->L, tid);
@@ -423,44 +529,64 @@ __device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs
     __syncthreads();  // the previous chunk is consumed
     if (tid < kn) {
       const uint64_t j = kb + tid;
-      s_boff[tid] = frag_p(G, rf, G->terms ? G->terms[j] : j) * rows;
+      s_boff[tid] = frag_p(G, rf, terms ? terms[j] : j) * rows;
     }
     for (uint32_t e = tid; e < kn * MC; e += SK_N) {
       const uint32_t kk = e / MC, m = e % MC;
       const uint64_t j = kb + kk;
-      double a = FA ? tval(*FA, j * rowsA + m) : side_value(G, G->L, m, G->terms ? G->terms[j] : j);
+      double a;
+      if (FA) {
+        const uint64_t ix = j * DA.rows + m;
+        a = DA.c16 ? (double)DA.T16[ix] / DA.shots : DA.T64[ix];
+      } else {
+        a = side_value(G, G->L, m, terms ? terms[j] : j);
+      }
       if (tscale) a *= tscale[j];
       if (square) a *= a;
       As[kk][m] = a;
     }
     __syncthreads();
     if (n >= N) continue;
-    // several column loads in flight per thread (fewer for many
-    // accumulators, which would crowd the registers): the kernel streams the
-    // column tensor once
-    constexpr uint32_t kUnroll = MC * CPT <= 8 ? 8 : 4;
+    // the column tensor streamed once: a batch of U terms' loads issued
+    // before the first is used (fewer for many accumulators, which would
+    // crowd the registers)
+    constexpr uint32_t U = MC * CPT <= 8 ? 8 : 4;
     if (cnt16) {  // 16-bit shot counts: a quarter of the bytes, the same values
-#pragma unroll kUnroll
-      for (uint32_t kk = 0; kk < kn; ++kk) {
-        double b[CPT];
-        ColLoad<CPT>::cnt(Cn + s_boff[kk], shots, b);
+      for (uint32_t k2 = 0; k2 < kn; k2 += U) {
+        typename ColLoad<CPT>::Raw16 w[U];
 #pragma unroll
-        for (uint32_t c = 0; c < CPT; ++c) {
-          if (square) b[c] *= b[c];
+        for (uint32_t u = 0; u < U; ++u) w[u] = ColLoad<CPT>::cnt(Cn + s_boff[k2 + u < kn ? k2 + u : k2]);
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of their uses
 #pragma unroll
-          for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[kk][m] * b[c];
+        for (uint32_t u = 0; u < U; ++u) {
+          if (k2 + u >= kn) break;
+          double b[CPT];
+          ColLoad<CPT>::cnt_val(w[u], shots, b);
+#pragma unroll
+          for (uint32_t c = 0; c < CPT; ++c) {
+            if (square) b[c] *= b[c];
+#pragma unroll
+            for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[k2 + u][m] * b[c];
+          }
         }
       }
     } else {
-#pragma unroll kUnroll
-      for (uint32_t kk = 0; kk < kn; ++kk) {
-        double b[CPT];
-        ColLoad<CPT>::f64(Tn + s_boff[kk], b);
+      for (uint32_t k2 = 0; k2 < kn; k2 += U) {
+        typename ColLoad<CPT>::Raw64 w[U];
 #pragma unroll
-        for (uint32_t c = 0; c < CPT; ++c) {
-          if (square) b[c] *= b[c];
+        for (uint32_t u = 0; u < U; ++u) w[u] = ColLoad<CPT>::f64(Tn + s_boff[k2 + u < kn ? k2 + u : k2]);
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of their uses
 #pragma unroll
-          for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[kk][m] * b[c];
+        for (uint32_t u = 0; u < U; ++u) {
+          if (k2 + u >= kn) break;
+          double b[CPT];
+          ColLoad<CPT>::f64_val(w[u], b);
+#pragma unroll
+          for (uint32_t c = 0; c < CPT; ++c) {
+            if (square) b[c] *= b[c];
+#pragma unroll
+            for (uint32_t m = 0; m < MC; ++m) acc[m][c] += As[k2 + u][m] * b[c];
+          }
         }
       }
     }
@@ -495,7 +621,7 @@ __global__ __launch_bounds__(SK_N) void skinny_batch_kernel(const GemmJob *__res
   const GemmJob &J = jobs[j];
   const uint64_t local = blockIdx.x - J.wg0;
   skinny_body<MC, CPT>(J.args, J.k_per_split, J.partial, (uint32_t)(local % J.tiles), (uint32_t)(local / J.tiles),
-                       J.splits == 1 ? J.out : nullptr);
+                       J.splits == 1 ? *J.out : nullptr);
 }
 
 // The skinny kernel for M rows and CPT columns per thread, one launch.
@@ -543,10 +669,16 @@ hipError_t skinny_dispatch(uint32_t rows, uint32_t cpt, dim3 g, hipStream_t s, c
 // The output index bits of row (or column) idx of side S: each of its
 // fragments' requested bits at its user position.
 __device__ inline uint64_t side_bits(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t idx) {
+  // the descriptors are uniform: scalar loads through the constant space
+  c_GemmArgs *C = cargs(G);
+  const bool left = &S == &G->L;
+  const uint32_t n = left ? C->L.n : C->R.n;
   uint64_t b = 0;
-  for (uint32_t t = 0; t < S.n; ++t) {
-    const RecombFrag &F = G->f[S.frag[t]];
-    const uint32_t r = (idx >> S.shift[t]) & ((1u << S.bits[t]) - 1u);
+  for (uint32_t t = 0; t < n; ++t) {
+    const uint32_t f = left ? C->L.frag[t] : C->R.frag[t];
+    const uint32_t sh = left ? C->L.shift[t] : C->R.shift[t], bits = left ? C->L.bits[t] : C->R.bits[t];
+    c_RecombFrag &F = C->f[f];
+    const uint32_t r = (idx >> sh) & ((1u << bits) - 1u);
     for (uint32_t q = 0; q < F.n_req; ++q) b |= (uint64_t)((r >> q) & 1u) << F.req_user[q];
   }
   return b;
@@ -574,7 +706,7 @@ __global__ void gemm_reduce_kernel(const GemmArgs *__restrict__ G, const double 
 __global__ void gemm_reduce_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t j = find_job(jobs, n_jobs, blockIdx.x, [](const GemmJob &J) { return J.rwg0; });
   const GemmJob &J = jobs[j];
-  gemm_reduce_body(J.args, J.partial, J.splits, J.out, (blockIdx.x - J.rwg0) * 256ull + threadIdx.x);
+  gemm_reduce_body(J.args, J.partial, J.splits, *J.out, (blockIdx.x - J.rwg0) * 256ull + threadIdx.x);
 }
 
 }  // namespace

@@ -1,5 +1,6 @@
-"""Batched evaluation (persistent autotuned tableau launch + HIP graph)
-against per-plan evaluation and the oracle, and graph replays."""
+"""Batched evaluation (autotuned affine-model launch + HIP graph) against
+per-plan evaluation and the oracle, graph replays, device outputs written
+in place by a replay, and the tuning cache."""
 import numpy as np
 import pytest
 
@@ -89,6 +90,38 @@ def test_device_outputs_match_host(ctx, use_graph):
             assert np.array_equal(got[i], host[i]), (rep, i)
         x = torch.randn(1 << 16, device="cuda")
         assert float(x.abs().sum()) > 0
+    # back to host outputs after device ones (a replay's output table
+    # points at the batch's own results again)
+    again = b.run()
+    for i in range(len(ws)):
+        assert np.array_equal(again[i], host[i]), i
+
+
+def test_tuning_cache(ctx, tmp_path, monkeypatch):
+    """The model launch's shape is timed once per batch shape: a second
+    batch of the same plans takes it from the process cache (same block and
+    grid, same results); with CCUT_TUNE_CACHE set, a timed shape is appended
+    to that file as 'key block per_cu ms'."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("CCUT_TUNE_CACHE", str(path))
+    ws = [W.batching_circuit(i, shots=500) for i in range(40, 47)]
+    plans = _plans(ctx, ws)
+    qs = [w.qubits for w in ws]
+    a = cc.Batch(ctx, plans, qs, shots=500, seed=4, use_graph=False)
+    ia = a.info()
+    b = cc.Batch(ctx, plans, qs, shots=500, seed=4, use_graph=False)
+    ib = b.info()
+    assert ib["tune_cached"]
+    assert (ib["block"], ib["grid"]) == (ia["block"], ia["grid"])
+    assert ib["models_ms"] == pytest.approx(ia["models_ms"])
+    ra, rb = a.run(), b.run()
+    for i in range(len(ws)):
+        assert np.array_equal(ra[i], rb[i]), i
+    if not ia["tune_cached"]:  # timed here: written to the file
+        lines = path.read_text().split("\n")
+        rows = [l.split() for l in lines if l.strip()]
+        assert any(int(r[1]) == ia["block"] and float(r[3]) == pytest.approx(ia["models_ms"], rel=1e-5) for r in rows)
+        assert all(len(r) == 4 and int(r[2]) >= 1 for r in rows)
 
 
 def test_run_batch_one_shot(ctx):
