@@ -41,8 +41,14 @@ struct Arena {
 
   void reset() {
     for (auto &c : chunks) c.used = 0;
+    n_uploads = 0;
   }
   bool frozen = false;  // set while a stream capture is open: no allocation then
+  // a hash of each upload's bytes in allocation order since the last reset:
+  // a re-enqueue that reuses earlier uploads in place checks that its bytes
+  // are the same ones (the sequence must repeat exactly)
+  std::vector<uint64_t> upload_hash;
+  size_t n_uploads = 0;
   void *get(size_t bytes) {
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
@@ -372,7 +378,30 @@ void *upload(ccut_ctx *c, const void *src, size_t bytes) {
   }
   void *d = c->arena.get(bytes);
   if (!d) return nullptr;
-  if (c->replay_uploads || !src || bytes == 0) return d;  // replay: the bytes are already there
+  if (!src || bytes == 0) return d;
+  // a multiply-xorshift hash of the bytes, eight at a time
+  uint64_t hsh = 0x9E3779B97F4A7C15ull ^ bytes;
+  {
+    const unsigned char *q = static_cast<const unsigned char *>(src);
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, q + i, 8);
+      hsh = (hsh ^ w) * 0xFF51AFD7ED558CCDull;
+      hsh ^= hsh >> 29;
+    }
+    for (; i < bytes; ++i) hsh = (hsh ^ q[i]) * 0xC4CEB9FE1A85EC53ull;
+  }
+  Arena &A = c->arena;
+  const size_t ui = A.n_uploads++;
+  if (c->replay_uploads) {
+    // replay: the bytes are already there, provided this is the same upload
+    // as in the run that copied them
+    if (ui < A.upload_hash.size() && A.upload_hash[ui] == hsh) return d;
+    return nullptr;  // (a re-enqueue that does not repeat the first one's uploads)
+  }
+  if (A.upload_hash.size() <= ui) A.upload_hash.resize(ui + 1);
+  A.upload_hash[ui] = hsh;
   c->call_upload_bytes += need;
   if (c->pin_cur < 0 && pin_begin(c) != hipSuccess) return nullptr;
   ccut_ctx::PinSlot &sl = c->pin[c->pin_cur];
@@ -597,13 +626,13 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
           // empty, few enough for its 16-bit LDS counts
           const uint64_t per_block = std::max<uint64_t>(bins, 2048);
           uint64_t want = (shots + per_block - 1) / per_block;
-          uint64_t maxb = (nquads + 255) / 256;
+          uint64_t maxb = (nquads + kSampleThreads - 1) / kSampleThreads;
           nblk = (uint32_t)std::max<uint64_t>(1, std::min(want, maxb));
-          nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * 256 - 1) / (kMaxUnitQpt * 256));
+          nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * kSampleThreads - 1) / (kMaxUnitQpt * kSampleThreads));
         } else {
           nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         }
-        const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
+        const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * kSampleThreads - 1) / ((uint64_t)nblk * kSampleThreads));
         const uint64_t pcount = lds ? cnv * nblk * (uint64_t)bins : cnv * (uint64_t)bins;
         uint32_t *partial = aget<uint32_t>(c, pcount);
         if (!partial) return fail(c, CCUT_E_OOM, "device allocation failed");
@@ -1656,8 +1685,8 @@ ccut_status ccut_shot_records(ccut_plan *p, const ccut_eval_opts *eo, const uint
   const uint64_t nquads = (shots + 3) / 4;
   for (uint64_t v0 = 0; v0 < nv; v0 += 65535) {
     const uint64_t cnv = std::min<uint64_t>(65535, nv - v0);
-    const uint32_t nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 255) / 256, 4096));
-    const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
+    const uint32_t nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + kSampleThreads - 1) / kSampleThreads, 4096));
+    const uint32_t qpt = (uint32_t)((nquads + (uint64_t)nblk * kSampleThreads - 1) / ((uint64_t)nblk * kSampleThreads));
     KTimer t(c, CCUT_K_SAMPLE);
     if (wide)
       HIP_TRY(c, launch_records_wide(models + v0 * model_words(nm), nm, cnv, shots, eo->seed, h.vid_base + v_begin + v0,
@@ -1782,12 +1811,26 @@ struct ccut_batch {
   std::vector<double *> cur_tab;
   std::vector<uint8_t> job_out;
   bool capturing = false;
+  // durations of the state-vector classes (by their widest width) measured
+  // in the creation run, in ms; later enqueues place the classes on the
+  // pool streams by them
+  struct Span {
+    uint32_t key;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Span> spans;
+  std::map<uint32_t, double> sv_ms;
+  bool measured = false;
   ~ccut_batch() {
     if (h_copy) (void)hipHostFree(h_copy);
     if (d_copy) (void)hipFree(d_copy);
     if (h_out_tab) (void)hipHostFree(h_out_tab);
     if (d_out_tab) (void)hipFree(d_out_tab);
     if (done_ev) (void)hipEventDestroy(done_ev);
+    for (const Span &sp : spans) {
+      (void)hipEventDestroy(sp.e0);
+      (void)hipEventDestroy(sp.e1);
+    }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto ps : pool) (void)hipStreamDestroy(ps);
@@ -1928,6 +1971,22 @@ std::string tune_key(ccut_ctx *c, const ccut_batch *b) {
 ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   ccut_ctx *c = b->ctx;
   ccut_status st;
+  // the creation run times its launches (events around them on their streams)
+  auto span_begin = [&](uint32_t key, hipStream_t sm) -> int {
+    if (!tune) return -1;
+    ccut_batch::Span sp{key, nullptr, nullptr};
+    if (hipEventCreate(&sp.e0) != hipSuccess) return -1;
+    if (hipEventCreate(&sp.e1) != hipSuccess) {
+      (void)hipEventDestroy(sp.e0);
+      return -1;
+    }
+    b->spans.push_back(sp);
+    (void)hipEventRecord(sp.e0, sm);
+    return (int)b->spans.size() - 1;
+  };
+  auto span_end = [&](int i, hipStream_t sm) {
+    if (i >= 0) (void)hipEventRecord(b->spans[(size_t)i].e1, sm);
+  };
   c->arena.reset();
   if (!c->replay_uploads) c->staged.clear();
   // (an all-Heisenberg batch has no tableau items: allocate a placeholder, copy nothing)
@@ -1954,16 +2013,77 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   }
   const size_t n_sv_streams = std::min<size_t>(b->pool.size(), 3);
   std::vector<uint8_t> sv_used(n_sv_streams, 0);
-  // (enqueued after the sampling chain below: a graph replay starts its
-  // nodes in capture order, and the chain is the longer of the two)
   // the descriptors' copy goes on the batch stream ahead of the fork point
   // the state-vector streams wait for
   FragDev *d_sv = nullptr;
   if (!b->nc.empty()) {
     d_sv = (FragDev *)upload(c, b->sv_descs.data(), b->sv_descs.size() * sizeof(FragDev));
     if (!d_sv) return fail(c, CCUT_E_OOM, "device allocation failed");
-    if (n_sv_streams) HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
   }
+  // the state-vector classes, their tables and their job lists, uploaded in
+  // the classes' fixed order on the batch stream ahead of the fork point
+  // (the launches come later, on the pool streams, in the order of their
+  // durations)
+  struct SvClass {
+    uint32_t m;
+    std::vector<SvJob> jobs[2];
+    SvJob *d_jobs[2] = {nullptr, nullptr};
+    uint64_t wg[2] = {0, 0};
+    size_t lds[2] = {0, 0};
+    double cost = 0.0;
+  };
+  // one class per launch shape (register and wave bits): every state of
+  // up to 8 qubits shares one; C.m is the class's widest state
+  std::vector<SvClass> classes;
+  auto shape_key = [](uint32_t m) {
+    const SvShape sh = sv_shape(m);
+    return sh.rb * 64u + sh.wb;
+  };
+  for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
+    if (m > 1 && shape_key(m - 1) == shape_key(m)) continue;  // handled with the class's first width
+    SvClass C;
+    C.m = m;
+    for (const auto &ref : b->nc) {
+      const FragDev &h = b->sv_descs[ref.desc];
+      if (shape_key(h.m) != shape_key(m)) continue;
+      C.m = std::max(C.m, h.m);
+      double *dist = aget<double>(c, h.n_variants << ref.n_meas);
+      const size_t sb = sv_states_bytes(h);
+      double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
+      if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
+      pre_dist[ref.plan][ref.frag] = dist;
+      const uint32_t passes[2] = {sb ? 1u : 0u, 2u};
+      for (int k = 0; k < (sb ? 2 : 1); ++k) {
+        uint64_t n_wg;
+        uint32_t bs;
+        size_t l;
+        bool split;
+        sv_pass_shape(h, passes[k], n_wg, bs, l, split);
+        SvJob J{};
+        J.desc = ref.desc;
+        J.split = split ? 1u : 0u;
+        J.wg0 = C.wg[k];
+        J.dist = dist;
+        J.mode = passes[k];
+        J.states = states;
+        C.wg[k] += n_wg;
+        C.lds[k] = std::max(C.lds[k], l);
+        C.cost += (double)n_wg * (double)(1u << h.m) * (passes[k] == 2 ? 8.0 : (double)h.n_ops);
+        C.jobs[k].push_back(J);
+      }
+    }
+    if (!C.jobs[0].empty()) classes.push_back(std::move(C));
+  }
+  // the job lists go up in the classes' fixed order (a re-enqueue reuses
+  // the first run's uploads in place: the order must not depend on the
+  // launch order below)
+  for (SvClass &C : classes)
+    for (int k = 0; k < 2; ++k) {
+      if (C.jobs[k].empty()) continue;
+      C.d_jobs[k] = (SvJob *)upload(c, C.jobs[k].data(), C.jobs[k].size() * sizeof(SvJob));
+      if (!C.d_jobs[k]) return fail(c, CCUT_E_OOM, "device allocation failed");
+    }
+  if (!b->nc.empty() && n_sv_streams) HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
   auto sv_pass = [&]() -> ccut_status {
     if (!b->nc.empty()) {
       // (the fork point was recorded before the sampling chain)
@@ -1974,47 +2094,12 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       // classes go to the streams longest first, each to the stream with the
       // least work so far (work: amplitudes times program length, summed over
       // workgroups)
-      struct SvClass {
-        uint32_t m;
-        std::vector<SvJob> jobs[2];
-        uint64_t wg[2] = {0, 0};
-        size_t lds[2] = {0, 0};
-        double cost = 0.0;
-      };
-      std::vector<SvClass> classes;
-      for (uint32_t m = 1; m <= (uint32_t)kMaxNcQubits; ++m) {
-        SvClass C;
-        C.m = m;
-        for (const auto &ref : b->nc) {
-          const FragDev &h = b->sv_descs[ref.desc];
-          if (h.m != m) continue;
-          double *dist = aget<double>(c, h.n_variants << ref.n_meas);
-          const size_t sb = sv_states_bytes(h);
-          double *states = sb ? aget<double>(c, sb / sizeof(double)) : nullptr;
-          if (!dist || (sb && !states)) return fail(c, CCUT_E_OOM, "device allocation failed");
-          pre_dist[ref.plan][ref.frag] = dist;
-          const uint32_t passes[2] = {sb ? 1u : 0u, 2u};
-          for (int k = 0; k < (sb ? 2 : 1); ++k) {
-            uint64_t n_wg;
-            uint32_t bs;
-            size_t l;
-            bool split;
-            sv_pass_shape(h, passes[k], n_wg, bs, l, split);
-            SvJob J{};
-            J.desc = ref.desc;
-            J.split = split ? 1u : 0u;
-            J.wg0 = C.wg[k];
-            J.dist = dist;
-            J.mode = passes[k];
-            J.states = states;
-            C.wg[k] += n_wg;
-            C.lds[k] = std::max(C.lds[k], l);
-            C.cost += (double)n_wg * (double)(1u << m) * (passes[k] == 2 ? 8.0 : (double)h.n_ops);
-            C.jobs[k].push_back(J);
-          }
+      // measured durations (ms) replace the estimates once the creation run has timed the classes
+      if (b->measured)
+        for (SvClass &C : classes) {
+          auto it = b->sv_ms.find(C.m);
+          if (it != b->sv_ms.end()) C.cost = it->second;
         }
-        if (!C.jobs[0].empty()) classes.push_back(std::move(C));
-      }
       std::stable_sort(classes.begin(), classes.end(),
                        [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
       std::vector<double> load(n_sv_streams, 0.0);
@@ -2025,13 +2110,13 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
           c->cur = b->pool[k];
           sv_used[k] = 1;
         }
+        const int sp = span_begin(C.m, c->cur);
         for (int k = 0; k < 2; ++k) {
           if (C.jobs[k].empty()) continue;
-          SvJob *d_jobs = (SvJob *)upload(c, C.jobs[k].data(), C.jobs[k].size() * sizeof(SvJob));
-          if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
           KTimer tm(c, CCUT_K_SV);
-          HIP_TRY(c, launch_sv_batch(d_sv, d_jobs, (uint32_t)C.jobs[k].size(), C.wg[k], C.m, C.lds[k], c->cur));
+          HIP_TRY(c, launch_sv_batch(d_sv, C.d_jobs[k], (uint32_t)C.jobs[k].size(), C.wg[k], C.m, C.lds[k], c->cur));
         }
+        span_end(sp, c->cur);
       }
       c->cur = b->stream;
       for (size_t k = 0; k < n_sv_streams; ++k)
@@ -2043,6 +2128,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   if ((st = batch_carry(b, &d_rows)) != CCUT_OK) return st;
   TuneEntry cached{};
   std::string tkey;
+  bool time_models = tune;  // the creation run times the model launch's candidates, unless cached
   if (tune && !b->items.empty()) {
     tkey = tune_key(c, b);
     if (tune_lookup(tkey, cached)) {
@@ -2053,10 +2139,10 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       b->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(full, (uint64_t)cus * cached.per_cu));
       b->tuned_ms = cached.ms;
       b->tune_cached = 1;
-      tune = false;
+      time_models = false;
     }
   }
-  if (tune && !b->items.empty()) {
+  if (time_models && !b->items.empty()) {
     // autotune the model launch: waves per workgroup x workgroups per
     // compute unit (a grid-stride loop covers whatever the grid leaves)
     int cus = 256;
@@ -2125,9 +2211,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       uint32_t nblk;
       if (lds) {  // 16384 shots or more per block: a batch has workgroups enough without splitting further
         const uint64_t per_block = std::max<uint64_t>(std::min<uint64_t>(bins, 1u << kLdsHistBits), 16384);
-        nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + 255) / 256));
+        nblk = (uint32_t)std::max<uint64_t>(1, std::min((shots + per_block - 1) / per_block, (nquads + kSampleThreads - 1) / kSampleThreads));
         // and few enough for the 16-bit LDS counts
-        nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * 256 - 1) / (kMaxUnitQpt * 256));
+        nblk = (uint32_t)std::max<uint64_t>(nblk, (nquads + kMaxUnitQpt * kSampleThreads - 1) / (kMaxUnitQpt * kSampleThreads));
       } else {
         nblk = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((nquads + 1023) / 1024, 4096));
         fill_words += nv * (uint64_t)bins;
@@ -2144,7 +2230,7 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       J.nv = nv;
       J.n_meas = nm;
       J.nblk = nblk;
-      J.qpt = (uint32_t)((nquads + (uint64_t)nblk * 256 - 1) / ((uint64_t)nblk * 256));
+      J.qpt = (uint32_t)((nquads + (uint64_t)nblk * kSampleThreads - 1) / ((uint64_t)nblk * kSampleThreads));
       J.nslice = nslice;
       J.wg0 = cls_units[cls];
       J.rb0 = t;
@@ -2201,6 +2287,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     SampleJob *d_jobs = (SampleJob *)upload(c, jobs.data(), jobs.size() * sizeof(SampleJob));
     if (!d_jobs) return fail(c, CCUT_E_OOM, "device allocation failed");
     if (fill_words) HIP_TRY(c, launch_fill_u32(zeroed, fill_words, 0u, c->cur));
+    // every class on the batch stream, one after another: the classes are
+    // throughput-bound, and spread over the pool streams beside the state
+    // vectors they only slowed each other down (measured)
     for (int cls = 0; cls < kClasses; ++cls)
       if (cls_count[cls]) {
         KTimer tm(c, CCUT_K_SAMPLE);
@@ -2212,6 +2301,9 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       HIP_TRY(c, launch_hist_reduce_batch(d_jobs, (uint32_t)jobs.size(), t, c->cur));
     }
   }
+  // the state vectors (pool streams; their job lists went up before the fork
+  // point), enqueued after the sampling chain: a graph replay starts its
+  // nodes in capture order, and the chain is the longer of the two
   if ((st = sv_pass()) != CCUT_OK) return st;
   for (size_t k = 0; k < n_sv_streams; ++k)
     if (sv_used[k]) HIP_TRY(c, hipStreamWaitEvent(b->stream, b->join_ev[k], 0));
@@ -2533,6 +2625,14 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
     if ((st = batch_enqueue(b.get(), true)) != CCUT_OK) return st;
   }
   HIP_TRY(c, hipStreamSynchronize(b->stream));
+  // the creation run's launch durations
+  for (const ccut_batch::Span &sp : b->spans) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sp.e0, sp.e1) != hipSuccess) continue;
+    b->sv_ms[sp.key] = ms;
+  }
+  (void)hipGetLastError();
+  b->measured = !b->spans.empty();
   if (use_graph) {
     BatchScope scope(b.get());
     c->replay_uploads = true;

@@ -30,11 +30,16 @@ enum : uint32_t {
 struct SvShape {
   uint32_t rb, lb, wb;  // register, lane and wave bits
 };
-// At most 4 amplitudes per thread (more spill registers); from 9 qubits on
-// the state spreads over 2^(m - 8) waves, up to 16 (1024 threads).
+// Up to 4 amplitudes per thread (more spill registers): one wave up to 8
+// qubits (register bits first, so ops on the two lowest positions need no
+// exchange), and from 9 qubits on the state spreads over 2^(m - 8) waves,
+// up to 16 (1024 threads).  Every state of up to 8 qubits (from 2) has the
+// same shape, so a batch runs them in one launch.
 __host__ __device__ inline SvShape sv_shape(uint32_t m) {
-  if (m <= 6) return {0u, m, 0u};
-  if (m <= 8) return {m - 6, 6u, 0u};
+  if (m <= 8) {
+    const uint32_t rb = m < 2 ? m : 2u;
+    return {rb, m - rb, 0u};
+  }
   return {2u, 6u, m - 8};
 }
 constexpr int kMaxTableBits = 24;
@@ -226,7 +231,9 @@ struct SampleJob {
 // replaying the shots.
 constexpr uint32_t kLdsHistBits = 16;
 constexpr uint32_t kMaxSliceBits = 3;
-constexpr uint32_t kMaxUnitQpt = 63;  // 63 quads x 256 threads x 4 shots = 64512 < 2^16
+constexpr uint32_t kSampleThreads = 512;  // threads of a sampling workgroup
+constexpr uint32_t kMaxUnitQpt = 31;      // 31 quads x 512 threads x 4 shots = 63488 < 2^16
+static_assert(kMaxUnitQpt * kSampleThreads * 4 < 65536, "16-bit LDS counts");
 __host__ __device__ inline uint32_t sample_tab_groups(uint32_t n_meas) { return (n_meas + 7) / 8; }
 inline size_t sample_lds_bytes(uint32_t n_meas, bool hist, bool sliced = false) {
   const size_t tab = (size_t)sample_tab_groups(n_meas) * 256 * 8;

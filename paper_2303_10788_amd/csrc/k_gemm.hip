@@ -150,6 +150,39 @@ __device__ __attribute__((always_inline)) inline void direct_gather(const DirOp 
   }
 }
 
+// direct_gather in two steps, so a chunk's loads can be issued a chunk
+// ahead: the raw entries (16-bit count or fp64 bits) ...
+template <uint32_t NPER, uint32_t STEP>
+__device__ __attribute__((always_inline)) inline void direct_load(const DirOp &D, uint64_t kb, uint64_t k1,
+                                                                  uint32_t kk0, uint32_t col, bool col_ok,
+                                                                  uint64_t *raw) {
+  uint64_t ix[NPER];
+#pragma unroll
+  for (uint32_t i = 0; i < NPER; ++i) {
+    const uint64_t j = kb + kk0 + STEP * i;
+    ix[i] = col_ok && j < k1 ? j * D.rows + col : 0;
+  }
+  if (D.c16) {
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) raw[i] = D.T16[ix[i]];
+  } else {
+#pragma unroll
+    for (uint32_t i = 0; i < NPER; ++i) raw[i] = (uint64_t)__double_as_longlong(D.T64[ix[i]]);
+  }
+}
+// ... and their values (0 past the K range or the side's extent)
+template <uint32_t NPER, uint32_t STEP>
+__device__ __attribute__((always_inline)) inline void direct_value(const DirOp &D, uint64_t kb, uint64_t k1,
+                                                                   uint32_t kk0, bool col_ok, const uint64_t *raw,
+                                                                   double *v) {
+#pragma unroll
+  for (uint32_t i = 0; i < NPER; ++i) {
+    const bool ok = col_ok && kb + kk0 + STEP * i < k1;
+    const double x = D.c16 ? (double)(uint32_t)raw[i] / D.shots : __longlong_as_double((long long)raw[i]);
+    v[i] = ok ? x : 0.0;
+  }
+}
+
 // Operand factors of a side that is not one direct fragment: the tile's
 // 64 rows (or columns) take only 2^vb distinct row values of fragment t
 // (vb = its row bits below bit 6 of the side index; the 64 indices share
@@ -276,74 +309,111 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
     else if (tid < MT + NT) s_obits[tid] = tn * NT + tid - MT < N ? side_bits(G, G->R, tn * NT + tid - MT) : 0;
     __syncthreads();
   }
-  for (uint64_t kb = k0; kb < k1; kb += KC) {
-    if constexpr (GEN) {
-      if (wA || wB) {
-        if (wA) fac_fill(G, true, tm * MT, kb, k1, facA);
-        if (wB) fac_fill(G, false, tn * NT, kb, k1, facB);
-        __syncthreads();
-      }
+  // both sides direct (GEN false): the next chunk's raw entries are loaded
+  // into registers while this chunk's products run
+  constexpr uint32_t NPA = KC * MT / GEMM_THREADS, STA = GEMM_THREADS / MT;
+  constexpr uint32_t NPB = KC * NT / GEMM_THREADS, STB = GEMM_THREADS / NT;
+  const uint32_t mmA = tid % MT, kkA = tid / MT, mA = tm * MT + mmA;
+  const uint32_t nnB = tid % NT, kkB = tid / NT, nB = tn * NT + nnB;
+  uint64_t rawA[GEN ? 1 : NPA], rawB[GEN ? 1 : NPB];
+  auto prefetch = [&](uint64_t kb) {
+    if constexpr (!GEN) {
+      direct_load<NPA, STA>(DA, kb, k1, kkA, mA, mA < M, rawA);
+      direct_load<NPB, STB>(DB, kb, k1, kkB, nB, nB < N, rawB);
     }
-    if (!GEN || FA) {
-      // one fragment read directly: a thread's entries share its row
-      constexpr uint32_t NPA = KC * MT / GEMM_THREADS, STA = GEMM_THREADS / MT;
-      const uint32_t mm = tid % MT, kk0 = tid / MT, m = tm * MT + mm;
-      double a[NPA];
-      direct_gather<NPA, STA>(DA, kb, k1, kk0, m, m < M, a);
-      double ts[NPA];
-#pragma unroll
-      for (uint32_t i = 0; i < NPA; ++i) {
-        const uint64_t j = kb + kk0 + STA * i;
-        ts[i] = (tscale && m < M && j < k1) ? tscale_g[j] : 1.0;
-      }
+  };
+  prefetch(k0);
+  for (uint64_t kb = k0; kb < k1; kb += KC) {
+    if constexpr (!GEN) {
+      double a[NPA], b[NPB];
+      direct_value<NPA, STA>(DA, kb, k1, kkA, mA < M, rawA, a);
+      direct_value<NPB, STB>(DB, kb, k1, kkB, nB < N, rawB, b);
 #pragma unroll
       for (uint32_t i = 0; i < NPA; ++i) {
         double x = a[i];
-        if (tscale) x *= ts[i];
+        const uint64_t j = kb + kkA + STA * i;
+        if (tscale && mA < M && j < k1) x *= tscale_g[j];  // (term weights: not prefetched, rarely set here)
         if (square) x *= x;
-        As[kk0 + STA * i][mm] = (TS)x;
-        if constexpr (LO) Al[kk0 + STA * i][mm] = (float)(x - (double)(float)x);
+        As[kkA + STA * i][mmA] = (TS)x;
+        if constexpr (LO) Al[kkA + STA * i][mmA] = (float)(x - (double)(float)x);
       }
-    } else {
-      for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
-        const uint32_t kk = e / MT, mm = e % MT;
-        const uint32_t m = tm * MT + mm;
-        const uint64_t j = kb + kk;
-        double a = 0.0;
-        if (m < M && j < k1) {
-          a = wA ? fac_value(G, true, facA, kk, mm) : side_value(G, G->L, m, terms ? terms[j] : j);
-          if (tscale) a *= tscale[j];
-          if (square) a *= a;
-        }
-        As[kk][mm] = (TS)a;
-        if constexpr (LO) Al[kk][mm] = (float)(a - (double)(float)a);
-      }
-    }
-    if (!GEN || FB) {
-      constexpr uint32_t NPB = KC * NT / GEMM_THREADS, STB = GEMM_THREADS / NT;
-      const uint32_t nn = tid % NT, kk0 = tid / NT, n = tn * NT + nn;
-      double b[NPB];
-      direct_gather<NPB, STB>(DB, kb, k1, kk0, n, n < N, b);
 #pragma unroll
       for (uint32_t i = 0; i < NPB; ++i) {
         double x = b[i];
         if (square) x *= x;
-        Bs[kk0 + STB * i][nn] = (TS)x;
-        if constexpr (LO) Bl[kk0 + STB * i][nn] = (float)(x - (double)(float)x);
+        Bs[kkB + STB * i][nnB] = (TS)x;
+        if constexpr (LO) Bl[kkB + STB * i][nnB] = (float)(x - (double)(float)x);
       }
     } else {
-      for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
-        const uint32_t kk = e / NT, nn = e % NT;
-        const uint32_t n = tn * NT + nn;
-        const uint64_t j = kb + kk;
-        double b = 0.0;
-        if (n < N && j < k1) b = wB ? fac_value(G, false, facB, kk, nn) : side_value(G, G->R, n, terms ? terms[j] : j);
-        if (square) b *= b;
-        Bs[kk][nn] = (TS)b;
-        if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
+      if constexpr (GEN) {
+        if (wA || wB) {
+          if (wA) fac_fill(G, true, tm * MT, kb, k1, facA);
+          if (wB) fac_fill(G, false, tn * NT, kb, k1, facB);
+          __syncthreads();
+        }
+      }
+      if (!GEN || FA) {
+        // one fragment read directly: a thread's entries share its row
+        constexpr uint32_t NPA = KC * MT / GEMM_THREADS, STA = GEMM_THREADS / MT;
+        const uint32_t mm = tid % MT, kk0 = tid / MT, m = tm * MT + mm;
+        double a[NPA];
+        direct_gather<NPA, STA>(DA, kb, k1, kk0, m, m < M, a);
+        double ts[NPA];
+#pragma unroll
+        for (uint32_t i = 0; i < NPA; ++i) {
+          const uint64_t j = kb + kk0 + STA * i;
+          ts[i] = (tscale && m < M && j < k1) ? tscale_g[j] : 1.0;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < NPA; ++i) {
+          double x = a[i];
+          if (tscale) x *= ts[i];
+          if (square) x *= x;
+          As[kk0 + STA * i][mm] = (TS)x;
+          if constexpr (LO) Al[kk0 + STA * i][mm] = (float)(x - (double)(float)x);
+        }
+      } else {
+        for (uint32_t e = tid; e < KC * MT; e += GEMM_THREADS) {
+          const uint32_t kk = e / MT, mm = e % MT;
+          const uint32_t m = tm * MT + mm;
+          const uint64_t j = kb + kk;
+          double a = 0.0;
+          if (m < M && j < k1) {
+            a = wA ? fac_value(G, true, facA, kk, mm) : side_value(G, G->L, m, terms ? terms[j] : j);
+            if (tscale) a *= tscale[j];
+            if (square) a *= a;
+          }
+          As[kk][mm] = (TS)a;
+          if constexpr (LO) Al[kk][mm] = (float)(a - (double)(float)a);
+        }
+      }
+      if (!GEN || FB) {
+        constexpr uint32_t NPB = KC * NT / GEMM_THREADS, STB = GEMM_THREADS / NT;
+        const uint32_t nn = tid % NT, kk0 = tid / NT, n = tn * NT + nn;
+        double b[NPB];
+        direct_gather<NPB, STB>(DB, kb, k1, kk0, n, n < N, b);
+#pragma unroll
+        for (uint32_t i = 0; i < NPB; ++i) {
+          double x = b[i];
+          if (square) x *= x;
+          Bs[kk0 + STB * i][nn] = (TS)x;
+          if constexpr (LO) Bl[kk0 + STB * i][nn] = (float)(x - (double)(float)x);
+        }
+      } else {
+        for (uint32_t e = tid; e < KC * NT; e += GEMM_THREADS) {
+          const uint32_t kk = e / NT, nn = e % NT;
+          const uint32_t n = tn * NT + nn;
+          const uint64_t j = kb + kk;
+          double b = 0.0;
+          if (n < N && j < k1) b = wB ? fac_value(G, false, facB, kk, nn) : side_value(G, G->R, n, terms ? terms[j] : j);
+          if (square) b *= b;
+          Bs[kk][nn] = (TS)b;
+          if constexpr (LO) Bl[kk][nn] = (float)(b - (double)(float)b);
+        }
       }
     }
     __syncthreads();
+    if (kb + KC < k1) prefetch(kb + KC);  // in flight during the products below
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
       TS a[2], b[2];
@@ -412,7 +482,7 @@ __device__ __attribute__((always_inline)) inline void gemm_body(const GemmArgs *
 }
 
 template <int MODE, bool GEN>
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
+__global__ __launch_bounds__(GEMM_THREADS, 3) void gemm_kernel(const GemmArgs *__restrict__ G, uint64_t k_per_split,
                                                             double *__restrict__ partial, double *__restrict__ out) {
   gemm_body<MODE, GEN>(G, k_per_split, partial, blockIdx.x, blockIdx.y, out);
 }
@@ -420,7 +490,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_kernel(const GemmArgs *__re
 // Many contractions in one launch: workgroup x runs tile (x - wg0) mod
 // tiles, split (x - wg0) / tiles of the job holding x.
 template <int MODE, bool GEN>
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
+__global__ __launch_bounds__(GEMM_THREADS, 3) void gemm_batch_kernel(const GemmJob *__restrict__ jobs, uint32_t n_jobs) {
   const uint32_t bid = xcd_block(blockIdx.x, gridDim.x);  // the tiles of a job share one XCD's L2
   const uint32_t j = find_job(jobs, n_jobs, bid, [](const GemmJob &J) { return J.wg0; });
   const GemmJob &J = jobs[j];

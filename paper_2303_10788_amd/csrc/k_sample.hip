@@ -31,7 +31,7 @@ __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, boo
   }
 }
 
-constexpr int kSampleBlock = 256;
+constexpr int kSampleBlock = (int)kSampleThreads;
 
 // Shots of variant v, block bx of nbx: each thread handles `qpt` quads;
 // quads are interleaved across the workgroup so record writes are
