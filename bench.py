@@ -102,6 +102,7 @@ def cpu_baseline(w, target_s: float):
 
 
 # kernel name -> the source file whose contents its traffic figure belongs to
+# (with common.hpp, which holds the launch shapes and job layouts)
 KERNEL_SOURCES = {"sv_kernel": "k_sv.hip", "affine_kernel": "k_affine.hip", "carry_kernel": "k_heis.hip",
                   "parity": "k_sample.hip", "sample_kernel": "k_sample.hip"}
 CALIB_BYTES = 64 << 20
@@ -111,8 +112,10 @@ def _source_hash(kernel):
     import hashlib
     for key, fname in KERNEL_SOURCES.items():
         if key in kernel:
-            path = os.path.join(ROOT, "paper_2303_10788_amd", "csrc", fname)
-            return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+            h = hashlib.sha256()
+            for f in (fname, "common.hpp"):
+                h.update(open(os.path.join(ROOT, "paper_2303_10788_amd", "csrc", f), "rb").read())
+            return h.hexdigest()[:16]
     return None
 
 

@@ -165,6 +165,17 @@ typedef struct {
  *    its tensor would come from variant tables, its tables stand in for the
  *    tensor with the input coefficients moved onto the upstream fragments'
  *    tensors; that fragment's columns are then indexed by preparations.)
+ *  CCUT_FLAG_SKIP (ccut_marginal only): fewer downstream evaluations.  The
+ *    support is fixed first from the Clifford fragments' exact Pauli
+ *    tensors (known before any variant is sampled; non-Clifford fragments do
+ *    not restrict it), every sampled Clifford variant that no supported cut
+ *    term reads draws no shots (a quantum input's |0> and |1> serve every
+ *    Pauli, |+> only X, |+i> only Y; a quantum output's Z basis serves I and
+ *    Z, X only X, Y only Y), the tensors stay in the Pauli basis and only the
+ *    supported terms are summed.  Exact data: the dense result up to
+ *    rounding.  Synchronizes (the support is read back); not with
+ *    CCUT_FLAG_ML.  Non-Clifford variants are all evaluated (their state
+ *    vectors share the gate program across preparations).
  *  CCUT_FLAG_SETTLE (ccut_zexpect in sampled mode only): each sampled
  *    Clifford variant's string expectation, which is -1, 0 or +1 on a
  *    stabilizer state, is settled from its shots: 0 if both parities
@@ -189,7 +200,7 @@ typedef struct {
  *    tables and are exact already.
  * A flag outside its call's scope, or in a batch, is CCUT_E_UNSUPPORTED;
  * unknown bits are CCUT_E_INVALID. */
-enum { CCUT_FLAG_SPARSE = 1, CCUT_FLAG_SETTLE = 2, CCUT_FLAG_ML = 4 };
+enum { CCUT_FLAG_SPARSE = 1, CCUT_FLAG_SETTLE = 2, CCUT_FLAG_ML = 4, CCUT_FLAG_SKIP = 8 };
 
 /* ---------------------------------------------------------------- context */
 
@@ -287,7 +298,8 @@ ccut_status ccut_shot_records(ccut_plan *plan, const ccut_eval_opts *eo, const u
 
 /* Parity hook: per-variant outcome distributions of fragment `fragment`
  * under the request: out[v][x], 2^|measured set| doubles per variant
- * (exact tables, state-vector marginals, or shot frequencies). */
+ * (exact tables, state-vector marginals, or shot frequencies: count x
+ * fl(1 / shots), the fp64 product with the rounded reciprocal). */
 ccut_status ccut_variant_tables(ccut_plan *plan, const ccut_eval_opts *eo, const uint32_t *qubits,
                                 uint32_t nq, uint32_t fragment, double *out, int out_on_device);
 

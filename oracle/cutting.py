@@ -331,10 +331,11 @@ def support(frags: Sequence[Fragment], tensors, k: int) -> List[int]:
 
 
 def recombine(frags: Sequence[Fragment], reqs: Sequence[Request], tensors, k: int,
-              nq: int, sparse: bool = False) -> np.ndarray:
+              nq: int, sparse: bool = False, terms=None) -> np.ndarray:
     """R[b] = 2^-k sum_P prod_f T_f[b_f; P|f], summed over P in ascending
     order (the contraction of Sec. V-C, written out).  sparse: only the
-    terms of ``support`` are summed (the skipped terms are exact zeros)."""
+    terms of ``support`` are summed (the skipped terms are exact zeros);
+    terms: only these (ascending)."""
     b = np.arange(1 << nq, dtype=np.int64)
     bidx = []
     for req in reqs:
@@ -343,7 +344,9 @@ def recombine(frags: Sequence[Fragment], reqs: Sequence[Request], tensors, k: in
             bi |= ((b >> u) & 1) << i
         bidx.append(bi)
     R = np.zeros(1 << nq, dtype=np.float64)
-    for P in (support(frags, tensors, k) if sparse else range(4 ** k)):
+    if terms is None:
+        terms = support(frags, tensors, k) if sparse else range(4 ** k)
+    for P in terms:
         term = np.ones(1 << nq, dtype=np.float64)
         for f, T, bi in zip(frags, tensors, bidx):
             term = term * T[bi, f.p_index(P)]
@@ -390,6 +393,70 @@ def recombine_matmul(frags: Sequence[Fragment], reqs: Sequence[Request], tensors
         bR |= ((rr >> i) & 1) << u
     out[bL[:, None] | bR[None, :]] = C
     return out
+
+
+# ------------------------------------------------------------------ Sec. IX: fewer downstream evaluations
+
+# The variants a cut term's column reads, per axis (from the transform above):
+# on a quantum input, I and Z combine |0> and |1>, X also |+>, Y also |+i>;
+# on a quantum output, I and Z come from the Z basis, X from X, Y from Y.
+PREPS_READ = {I_: (0, 1), Z_: (0, 1), X_: (0, 1, 2), Y_: (0, 1, 3)}
+BASES_READ = {I_: (BASIS_Z,), Z_: (BASIS_Z,), X_: (BASIS_X,), Y_: (BASIS_Y,)}
+
+
+def exact_support(frags: Sequence[Fragment], reqs: Sequence[Request], k: int) -> List[int]:
+    """Cut terms whose column is nonzero in every Clifford fragment's exact
+    Pauli tensor, ascending.  A Clifford fragment's exact tensor is known
+    before any of its variants is sampled (its expectations are 0 or +-1,
+    Sec. IX); non-Clifford fragments do not restrict the set."""
+    nz = []
+    for f, r in zip(frags, reqs):
+        if f.clifford:
+            T = pauli_tensor(f, r, variant_distributions(f, r.meas))
+            nz.append(np.any(T != 0.0, axis=0))
+        else:
+            nz.append(None)
+    return [P for P in range(4 ** k) if all(z is None or z[f.p_index(P)] for f, z in zip(frags, nz))]
+
+
+def needed_variants(frag: Fragment, terms) -> np.ndarray:
+    """need[v]: some term of ``terms`` reads variant v of ``frag`` (every
+    axis's preparation or basis is one the term's Pauli on that cut reads)."""
+    need = np.zeros(frag.n_variants, dtype=bool)
+    seen = set()
+    for P in terms:
+        key = frag.p_index(P)
+        if key in seen:
+            continue
+        seen.add(key)
+        opts = [PREPS_READ[(P >> (2 * ax.cut)) & 3] if ax.side == 1 else BASES_READ[(P >> (2 * ax.cut)) & 3]
+                for ax in frag.axes]
+        for digits in itertools.product(*opts):
+            need[frag.variant_index(digits)] = True
+    return need
+
+
+def marginal_skip(n: int, ops, cuts, qubits, *, shots: int = 0, seed: int = 0, circuit: int = 0,
+                  return_parts: bool = False):
+    """The marginal with Sec. IX's downstream skipping: the support S is
+    fixed from the Clifford fragments' exact tensors, the variants no term of
+    S reads are never evaluated (their tables are zero), and only the terms
+    of S are summed.  Exact data: the full sum (the other terms vanish)."""
+    qubits = list(qubits)
+    frags = fragment_circuit(n, ops, cuts)
+    reqs = [make_request(f, qubits) for f in frags]
+    S = exact_support(frags, reqs, len(cuts))
+    dists = []
+    for f, r in zip(frags, reqs):
+        d = variant_distributions(f, r.meas, shots=shots, seed=seed, circuit=circuit)
+        d = np.array(d, dtype=np.float64)
+        d[~needed_variants(f, S)] = 0.0
+        dists.append(d)
+    tensors = [pauli_tensor(f, r, d) for f, r, d in zip(frags, reqs, dists)]
+    R = recombine(frags, reqs, tensors, len(cuts), len(qubits), terms=S)
+    if return_parts:
+        return R, dict(frags=frags, reqs=reqs, dists=dists, tensors=tensors, support=S)
+    return R
 
 
 # ------------------------------------------------------------------ end to end

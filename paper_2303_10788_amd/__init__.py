@@ -25,7 +25,7 @@ CCUT_OK, CCUT_E_INVALID, CCUT_E_OOM, CCUT_E_DEVICE = 0, -1, -2, -3
 CCUT_E_NC_TOO_WIDE, CCUT_E_TOO_MANY_CUTS, CCUT_E_CANCELLED, CCUT_E_UNSUPPORTED = -4, -5, -6, -7
 CCUT_FP64, CCUT_FP32_MFMA_FP64SUM, CCUT_FP32X3_MFMA_FP64SUM = 0, 1, 2
 CCUT_METHOD_AUTO, CCUT_METHOD_VARIANTS, CCUT_METHOD_HEISENBERG = 0, 1, 2
-CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE, CCUT_FLAG_ML = 1, 2, 4
+CCUT_FLAG_SPARSE, CCUT_FLAG_SETTLE, CCUT_FLAG_ML, CCUT_FLAG_SKIP = 1, 2, 4, 8
 KERNELS = ("affine_kernel", "sample_kernel", "hist_reduce_kernel", "exact_kernel", "sv_kernel",
            "parity_kernel", "transform_pass_kernel", "recombine_fp64_kernel", "zrecombine_fp64_kernel",
            "heisenberg_kernels", "mlp_kernels", "term_kernels", "carry_kernel")

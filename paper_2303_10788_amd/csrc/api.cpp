@@ -296,7 +296,7 @@ ccut_status check_eval(ccut_plan *p, const ccut_eval_opts *eo) {
       eo->precision != CCUT_FP32X3_MFMA_FP64SUM)
     return fail(c, CCUT_E_INVALID, "unknown precision mode");
   if (eo->method > CCUT_METHOD_HEISENBERG) return fail(c, CCUT_E_INVALID, "unknown evaluation method");
-  if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE | CCUT_FLAG_ML))
+  if (eo->flags & ~(uint32_t)(CCUT_FLAG_SPARSE | CCUT_FLAG_SETTLE | CCUT_FLAG_ML | CCUT_FLAG_SKIP))
     return fail(c, CCUT_E_INVALID, "unknown evaluation flag");
   // shot counters and histogram counts are 32-bit per variant
   if (eo->shots_per_variant > 0xFFFFFFFFull)
@@ -578,9 +578,11 @@ ccut_status ml_correct(ccut_ctx *c, const Fragment &f, const FragRequest &r, dou
   return CCUT_OK;
 }
 
+// vmask (device, one byte per variant, optional): sampled Clifford variants
+// with vmask[v] == 0 draw no shots (all-zero tables)
 ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment &f,
                           const FragRequest &r, double **dist_out, uint64_t *pre_models = nullptr,
-                          uint16_t **cnt_out = nullptr) {
+                          uint16_t **cnt_out = nullptr, const uint8_t *vmask = nullptr) {
   ccut_ctx *c = p->ctx;
   const uint32_t nm = (uint32_t)r.meas.size();
   const uint64_t nv = f.n_variants;
@@ -640,7 +642,8 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
         {
           KTimer t(c, CCUT_K_SAMPLE);
           HIP_TRY(c, launch_sample_hist(models + v0 * model_words(nm), nm, cnv, shots, eo->seed,
-                                        h.vid_base + v0, partial, nblk, qpt, nullptr, c->cur));
+                                        h.vid_base + v0, partial, nblk, qpt, nullptr, c->cur,
+                                        vmask ? vmask + v0 : nullptr));
         }
         {
           KTimer t(c, CCUT_K_HIST_REDUCE);
@@ -921,6 +924,26 @@ ccut_status run_gemm(ccut_ctx *c, const GemmArgs &g, bool fp32, double *res, boo
 // terms are summed: the plain sum in ascending order when it is small (the
 // same operations as the dense plain sum minus its zero terms), else the
 // term-list contraction.
+// The contraction over a term list (device, ascending, count terms): the
+// plain fp64 sum over the terms when small, else the matrix paths.
+ccut_status contract_terms(ccut_ctx *c, const RecombArgs &args, const RecombArgs *dargs, uint32_t nq, bool fp32,
+                           double *res, const uint64_t *terms, uint64_t count) {
+  if (count == 0) {  // every term vanishes
+    HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(res), 2ull << nq, 0u, c->cur));  // +0.0
+    return CCUT_OK;
+  }
+  if (!fp32 && (count << nq) <= (1ull << 20) && args.n_frags <= 8) {
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_recombine_terms(dargs, nq, terms, count, res, c->cur));
+    return CCUT_OK;
+  }
+  GemmArgs g;
+  make_gemm_args(args, g);
+  g.terms = terms;
+  g.K = count;
+  return run_gemm(c, g, fp32, res, true);
+}
+
 ccut_status recombine_sparse(ccut_ctx *c, const RecombArgs &args, uint32_t nq, bool fp32, double *res) {
   const uint64_t K = 1ull << (2 * args.k);
   SupportArgs sa{};
@@ -943,20 +966,7 @@ ccut_status recombine_sparse(ccut_ctx *c, const RecombArgs &args, uint32_t nq, b
   }
   HIP_TRY(c, hipMemcpyAsync(&count, pos + K - 1, 8, hipMemcpyDeviceToHost, c->cur));
   HIP_TRY(c, hipStreamSynchronize(c->cur));
-  if (count == 0) {  // every term vanishes
-    HIP_TRY(c, launch_fill_u32(reinterpret_cast<uint32_t *>(res), 2ull << nq, 0u, c->cur));  // +0.0
-    return CCUT_OK;
-  }
-  if (!fp32 && (count << nq) <= (1ull << 20) && args.n_frags <= 8) {
-    KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_recombine_terms(dargs, nq, terms, count, res, c->cur));
-    return CCUT_OK;
-  }
-  GemmArgs g;
-  make_gemm_args(args, g);
-  g.terms = terms;
-  g.K = count;
-  return run_gemm(c, g, fp32, res, true);
+  return contract_terms(c, args, dargs, nq, fp32, res, terms, count);
 }
 
 // Contract the fragment tensors into out[2^nq].  fp64 with at most 2^20
@@ -1215,6 +1225,7 @@ ccut_status ccut_variant_tables(ccut_plan *p, const ccut_eval_opts *eo, const ui
   ccut_status st = check_eval(p, eo);
   if (st != CCUT_OK) return st;
   ccut_ctx *c = p->ctx;
+  if (eo->flags & CCUT_FLAG_SKIP) return fail(c, CCUT_E_UNSUPPORTED, "variant skipping applies to marginals");
   if (fragment >= p->pd.frags.size()) return fail(c, CCUT_E_INVALID, "fragment out of range");
   if ((st = check_request(c, p->pd.n, qubits, nq, p->pd.n)) != CCUT_OK) return st;
   const Fragment &f = p->pd.frags[fragment];
@@ -1229,6 +1240,7 @@ ccut_status ccut_fragment_tensor(ccut_plan *p, const ccut_eval_opts *eo, const u
   ccut_status st = check_eval(p, eo);
   if (st != CCUT_OK) return st;
   ccut_ctx *c = p->ctx;
+  if (eo->flags & CCUT_FLAG_SKIP) return fail(c, CCUT_E_UNSUPPORTED, "variant skipping applies to marginals");
   if (fragment >= p->pd.frags.size()) return fail(c, CCUT_E_INVALID, "fragment out of range");
   if ((st = check_request(c, p->pd.n, qubits, nq, p->pd.n)) != CCUT_OK) return st;
   const Fragment &f = p->pd.frags[fragment];
@@ -1259,6 +1271,7 @@ namespace {
 // sparse contraction then reads its support over these folded terms: a
 // skipped term is still an exact zero).  -1: none.
 int fold_target(const PlanData &pd, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq) {
+  if (eo->flags & CCUT_FLAG_SKIP) return -1;  // every tensor in the Pauli basis: the support indexes Paulis
   int best = -1;
   size_t best_bits = 0;
   for (const Fragment &f : pd.frags) {
@@ -1280,7 +1293,8 @@ int fold_target(const PlanData &pd, const ccut_eval_opts *eo, const uint32_t *qu
 // (fewer than 2^16 shots), read by the matrix contraction paths (not the
 // plain sum, not the sparse support search).
 bool counts_contraction(const PlanData &pd, const ccut_eval_opts *eo, uint32_t nq) {
-  if (eo->shots_per_variant == 0 || eo->shots_per_variant > 0xFFFFull || (eo->flags & CCUT_FLAG_SPARSE)) return false;
+  if (eo->shots_per_variant == 0 || eo->shots_per_variant > 0xFFFFull || (eo->flags & (CCUT_FLAG_SPARSE | CCUT_FLAG_SKIP)))
+    return false;
   const uint64_t K = 1ull << (2 * pd.k);
   const bool fp32 = eo->precision != CCUT_FP64;
   return !(!fp32 && pd.frags.size() > 2 && (K << nq) <= (1ull << 20));
@@ -1307,6 +1321,164 @@ void fold_jobs(const PlanData &pd, int g, const RecombArgs &args, std::vector<Fo
     const RecombFrag &rf = args.f[f.index];
     if (mask) jobs.push_back({const_cast<double *>(rf.T), rf.rows, rf.n_axes, mask});
   }
+}
+
+// Sec. IX, fewer downstream evaluations (CCUT_FLAG_SKIP): the support is
+// fixed first from the Clifford fragments' exact Pauli tensors (Heisenberg
+// picture where it applies, else exact variant tables); every sampled
+// Clifford variant no term of the support reads draws no shots; the
+// tensors are formed in the Pauli basis (no fold) and only the support's
+// terms are summed.  The support size is read back (the call synchronizes).
+ccut_status marginal_skip_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
+                                  double *res) {
+  ccut_ctx *c = p->ctx;
+  ccut_status st;
+  const PlanData &pd = p->pd;
+  if (pd.frags.size() > (size_t)kMaxFrags) return fail(c, CCUT_E_UNSUPPORTED, "more than 64 fragments");
+  const uint64_t K = 1ull << (2 * pd.k);
+  const bool fp32 = eo->precision != CCUT_FP64;
+  ccut_eval_opts ex = *eo;  // exact data for the support
+  ex.shots_per_variant = 0;
+  ex.flags = 0;
+  ex.method = CCUT_METHOD_AUTO;
+  RecombArgs sargs{};
+  sargs.n_frags = (uint32_t)pd.frags.size();
+  sargs.k = pd.k;
+  SupportArgs sa{};
+  uint64_t cols_total = 0;
+  for (const Fragment &f : pd.frags) {
+    sa.off[f.index] = cols_total;
+    cols_total += 1ull << (2 * f.axes.size());
+    sargs.f[f.index].n_axes = (uint32_t)f.axes.size();
+    for (size_t j = 0; j < f.axes.size(); ++j) sargs.f[f.index].axis_cut[j] = f.axes[j].cut;
+  }
+  uint8_t *nz = aget<uint8_t>(c, cols_total);
+  uint64_t *pos = aget<uint64_t>(c, K), *scratch = aget<uint64_t>(c, scan_scratch_words(K));
+  uint64_t *terms = aget<uint64_t>(c, K);
+  if (!nz || !pos || !scratch || !terms) return fail(c, CCUT_E_OOM, "device allocation failed");
+  // each Clifford fragment's exact tensor, reused below for exact data
+  // formed the same way
+  std::vector<double *> ex_T(pd.frags.size(), nullptr);
+  std::vector<uint8_t> ex_heis(pd.frags.size(), 0);
+  for (const Fragment &f : pd.frags) {
+    const uint64_t cols = 1ull << (2 * f.axes.size());
+    if (!f.clifford) {  // a non-Clifford fragment does not restrict the support
+      HIP_TRY(c, hipMemsetAsync(nz + sa.off[f.index], 1, cols, c->cur));
+      continue;
+    }
+    FragRequest r = marginal_request(f, qubits, nq);
+    double *T = nullptr;
+    ex_heis[f.index] = use_heisenberg(f, &ex, r.req_pos.size());
+    if (ex_heis[f.index]) {
+      if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
+    } else {
+      double *dist0 = nullptr;
+      if ((st = variant_dists(p, &ex, f, r, &dist0)) != CCUT_OK) return st;
+      if ((st = pauli_passes(c, f, r, dist0, 1ull << r.meas.size(), 0, &T)) != CCUT_OK) return st;
+    }
+    ex_T[f.index] = T;
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_colnz(T, 1u << r.req_pos.size(), cols, nz + sa.off[f.index], c->cur));
+  }
+  RecombArgs *dsargs = (RecombArgs *)upload(c, &sargs, sizeof(sargs));
+  if (!dsargs) return fail(c, CCUT_E_OOM, "device allocation failed");
+  {
+    KTimer t(c, CCUT_K_RECOMBINE);
+    HIP_TRY(c, launch_support_terms(dsargs, sa, nz, K, pos, scratch, terms, c->cur));
+  }
+  uint64_t count = 0;
+  HIP_TRY(c, hipMemcpyAsync(&count, pos + K - 1, 8, hipMemcpyDeviceToHost, c->cur));
+  HIP_TRY(c, hipStreamSynchronize(c->cur));
+  std::vector<uint64_t> S(count);
+  if (count) {
+    HIP_TRY(c, hipMemcpyAsync(S.data(), terms, count * 8, hipMemcpyDeviceToHost, c->cur));
+    HIP_TRY(c, hipStreamSynchronize(c->cur));
+  }
+  // the tensors, sampled Clifford variants restricted to the ones the
+  // support reads: per axis, a quantum input's |0> and |1> serve every
+  // Pauli, |+> X and |+i> Y; a quantum output's Z basis serves I and Z, X X
+  // and Y Y
+  RecombArgs args{};
+  args.n_frags = (uint32_t)pd.frags.size();
+  args.k = pd.k;
+  args.lo_parts = eo->precision == CCUT_FP32X3_MFMA_FP64SUM;
+  for (const Fragment &f : pd.frags) {
+    route(c, f);
+    FragRequest r = marginal_request(f, qubits, nq);
+    double *T = nullptr;
+    const bool heis = use_heisenberg(f, eo, r.req_pos.size());
+    if (f.clifford && eo->shots_per_variant == 0 && heis == (bool)ex_heis[f.index]) {
+      T = ex_T[f.index];
+    } else if (heis) {
+      if ((st = heis_tensor(p, f, r, eo->circuit, nullptr, &T)) != CCUT_OK) return st;
+    } else {
+      const uint8_t *vmask = nullptr;
+      if (f.clifford && eo->shots_per_variant > 0) {
+        // R[key] over the fragment's Pauli keys (2 bits per axis): some
+        // support term projects to key.  Per axis, the four Pauli values are
+        // then replaced by the three variant classes that read them: a
+        // quantum input's {|0>,|1>} read every Pauli, |+> X and |+i> Y; a
+        // quantum output's X basis X, Y basis Y and Z basis I and Z.  After
+        // all axes R[c] says whether a variant of classes c is read.
+        const size_t a = f.axes.size();
+        std::vector<uint8_t> R(size_t(1) << (2 * a), 0);
+        for (uint64_t P : S) {
+          uint64_t key = 0;
+          for (size_t j = 0; j < a; ++j) key |= ((P >> (2 * f.axes[j].cut)) & 3ull) << (2 * j);
+          R[key] = 1;
+        }
+        for (size_t j = 0; j < a; ++j) {
+          const size_t stride = size_t(1) << (2 * j);
+          const bool in = f.axes[j].side == 1;
+          for (size_t base = 0; base < R.size(); ++base) {
+            if ((base >> (2 * j)) & 3u) continue;
+            const uint8_t pi = R[base], px = R[base + stride], py = R[base + 2 * stride], pz = R[base + 3 * stride];
+            if (in) {
+              R[base] = pi | px | py | pz;  // |0>, |1>
+              R[base + stride] = px;            // |+>
+              R[base + 2 * stride] = py;        // |+i>
+            } else {
+              R[base] = px;                 // X basis
+              R[base + stride] = py;            // Y basis
+              R[base + 2 * stride] = pi | pz;   // Z basis
+            }
+            R[base + 3 * stride] = 0;
+          }
+        }
+        static const uint32_t kPrepClass[4] = {0, 0, 1, 2};  // |0> |1> |+> |+i>
+        std::vector<uint8_t> need(f.n_variants, 0);
+        for (uint64_t v = 0; v < f.n_variants; ++v) {
+          uint64_t rest = v, cls = 0;
+          for (size_t j = 0; j < a; ++j) {
+            const uint32_t rad = f.axes[j].side == 1 ? 4u : 3u, d = (uint32_t)(rest % rad);
+            rest /= rad;
+            cls |= (uint64_t)(f.axes[j].side == 1 ? kPrepClass[d] : d) << (2 * j);  // bases X=0 Y=1 Z=2
+          }
+          need[v] = R[cls];
+        }
+        vmask = (const uint8_t *)upload(c, need.data(), need.size());
+        if (!vmask) return fail(c, CCUT_E_OOM, "device allocation failed");
+      }
+      double *dist = nullptr;
+      if ((st = variant_dists(p, eo, f, r, &dist, nullptr, nullptr, vmask)) != CCUT_OK) return st;
+      if (f.axes.empty())
+        T = dist;
+      else if ((st = pauli_passes(c, f, r, dist, 1ull << r.meas.size(), 0, &T)) != CCUT_OK)
+        return st;
+    }
+    RecombFrag &rf = args.f[f.index];
+    rf.T = T;
+    rf.n_axes = (uint32_t)f.axes.size();
+    rf.rows = 1u << r.req_pos.size();
+    rf.n_req = (uint32_t)r.req_pos.size();
+    for (size_t j = 0; j < f.axes.size(); ++j) rf.axis_cut[j] = f.axes[j].cut;
+    for (size_t i = 0; i < r.req_user.size(); ++i) rf.req_user[i] = r.req_user[i];
+    if ((st = cancelled(c)) != CCUT_OK) return st;
+  }
+  if ((st = join(c)) != CCUT_OK) return st;
+  RecombArgs *dargs = (RecombArgs *)upload(c, &args, sizeof(args));
+  if (!dargs) return fail(c, CCUT_E_OOM, "device allocation failed");
+  return contract_terms(c, args, dargs, nq, fp32, res, terms, count);
 }
 
 ccut_status marginal_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
@@ -1477,7 +1649,14 @@ ccut_status marginal_call(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t
   // a device output receives the contraction directly
   double *res = on_device ? out : aget<double>(c, (size_t)1 << nq);
   if (!res) return fail(c, CCUT_E_OOM, "device allocation failed");
-  if ((st = marginal_enqueue(p, eo, qubits, nq, res, nullptr)) != CCUT_OK) return st;
+  if (eo->flags & CCUT_FLAG_SKIP) {
+    if (eo->flags & CCUT_FLAG_ML)
+      return fail(c, CCUT_E_UNSUPPORTED, "the maximum-likelihood correction needs every variant (no skipping)");
+    st = marginal_skip_enqueue(p, eo, qubits, nq, res);
+  } else {
+    st = marginal_enqueue(p, eo, qubits, nq, res, nullptr);
+  }
+  if (st != CCUT_OK) return st;
   return on_device ? CCUT_OK : finish_out(c, res, out, (size_t)1 << nq, on_device);
 }
 
@@ -1487,7 +1666,8 @@ ccut_status zexpect_call(ccut_plan *p, const ccut_eval_opts *eo, const uint64_t 
   if (st != CCUT_OK) return st;
   ccut_ctx *c = p->ctx;
   if (!out || (n_strings && !masks)) return fail(c, CCUT_E_INVALID, "NULL argument");
-  if (eo->flags & CCUT_FLAG_SPARSE) return fail(c, CCUT_E_UNSUPPORTED, "the sparse contraction applies to marginals");
+  if (eo->flags & (CCUT_FLAG_SPARSE | CCUT_FLAG_SKIP))
+    return fail(c, CCUT_E_UNSUPPORTED, "the sparse contraction and variant skipping apply to marginals");
   if (eo->flags & CCUT_FLAG_ML) return fail(c, CCUT_E_UNSUPPORTED, "the maximum-likelihood correction applies to outcome tables");
   if (n_strings == 0) return CCUT_OK;
   const PlanData &pd = p->pd;
@@ -1634,8 +1814,8 @@ extern "C" {
 
 ccut_status ccut_marginal(ccut_plan *p, const ccut_eval_opts *eo, const uint32_t *qubits, uint32_t nq,
                           double *out, int on_device) {
-  // a sparse contraction reads its support size back: never captured
-  if (!p || !eo || !out || (nq && !qubits) || nq > 24 || (eo->flags & CCUT_FLAG_SPARSE))
+  // a sparse or skipping contraction reads its support back: never captured
+  if (!p || !eo || !out || (nq && !qubits) || nq > 24 || (eo->flags & (CCUT_FLAG_SPARSE | CCUT_FLAG_SKIP)))
     return marginal_call(p, eo, qubits, nq, out, on_device);
   return graph_call(p, call_key(0, eo, qubits, (size_t)nq * 4, out), on_device,
                     [&] { return marginal_call(p, eo, qubits, nq, out, on_device); });

@@ -231,8 +231,8 @@ struct SampleJob {
 // replaying the shots.
 constexpr uint32_t kLdsHistBits = 16;
 constexpr uint32_t kMaxSliceBits = 3;
-constexpr uint32_t kSampleThreads = 512;  // threads of a sampling workgroup
-constexpr uint32_t kMaxUnitQpt = 31;      // 31 quads x 512 threads x 4 shots = 63488 < 2^16
+constexpr uint32_t kSampleThreads = 256;  // threads of a sampling workgroup (512: no faster)
+constexpr uint32_t kMaxUnitQpt = 63;      // 63 quads x 256 threads x 4 shots = 64512 < 2^16
 static_assert(kMaxUnitQpt * kSampleThreads * 4 < 65536, "16-bit LDS counts");
 __host__ __device__ inline uint32_t sample_tab_groups(uint32_t n_meas) { return (n_meas + 7) / 8; }
 inline size_t sample_lds_bytes(uint32_t n_meas, bool hist, bool sliced = false) {
@@ -288,7 +288,8 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t n) {
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
-                              uint32_t quads_per_thread, uint64_t *records, hipStream_t s);
+                              uint32_t quads_per_thread, uint64_t *records, hipStream_t s,
+                              const uint8_t *vmask = nullptr);
 hipError_t launch_hist_reduce(const uint32_t *partial, uint64_t nv, uint32_t nblk_x, uint32_t bins,
                               uint64_t shots, double *dist, hipStream_t s, uint16_t *cnt16 = nullptr);
 hipError_t launch_exact_tables(const uint64_t *models, uint32_t n_meas, uint64_t nv, double *dist,

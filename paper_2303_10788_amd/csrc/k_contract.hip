@@ -256,14 +256,14 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
   if (J.in16) {
     const __attribute__((address_space(1))) uint16_t *in16 =
         (const __attribute__((address_space(1))) uint16_t *)J.in16;
-    const double shots = J.shots;
+    const double inv = 1.0 / J.shots;  // a table entry is count x fl(1/shots)
     uint32_t c[kPer];
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) c[i] = in16[idx[i]];
 #pragma unroll
     for (uint32_t i = 0; i < kPer; ++i) {
       const uint32_t e = tid + i * kTileThreads;
-      if (e < n_el) s[e] = (double)c[i] / shots;
+      if (e < n_el) s[e] = (double)c[i] * inv;
     }
   } else {
     const __attribute__((address_space(1))) double *in = (const __attribute__((address_space(1))) double *)J.in;

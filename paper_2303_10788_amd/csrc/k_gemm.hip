@@ -57,10 +57,10 @@ __device__ inline uint64_t frag_p(const GemmArgs *__restrict__ G, uint32_t f, ui
   return p;
 }
 
-// A fragment tensor entry: fp64, or a 16-bit shot count divided by the
-// shots (the value the fp64 table would hold).
+// A fragment tensor entry: fp64, or a 16-bit shot count times fl(1/shots)
+// (the value the fp64 table would hold).
 __device__ inline double tval(const RecombFrag &F, uint64_t i) {
-  return F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[i] / F.shots : F.T[i];
+  return F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[i] * (1.0 / F.shots) : F.T[i];
 }
 
 __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSide &S, uint32_t row, uint64_t P) {
@@ -74,7 +74,7 @@ __device__ inline double side_value(const GemmArgs *__restrict__ G, const GemmSi
     const uint32_t r = (row >> sh) & ((1u << bits) - 1u);
     c_RecombFrag &F = C->f[f];
     const uint64_t idx = frag_p(G, f, P) * F.rows + r;
-    v *= F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] / F.shots : F.T[idx];
+    v *= F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] * (1.0 / F.shots) : F.T[idx];
   }
   return v;
 }
@@ -104,7 +104,7 @@ __device__ inline const RecombFrag *direct_side(const GemmArgs *__restrict__ G, 
 struct DirOp {
   const __attribute__((address_space(1))) double *T64;
   const __attribute__((address_space(1))) uint16_t *T16;
-  double shots;
+  double inv;  // fl(1 / shots): a count's value is count x inv
   uint64_t rows;
   bool c16;
 };
@@ -115,7 +115,7 @@ __device__ inline DirOp dir_op(const RecombFrag *F) {
   c_RecombFrag &C = *(c_RecombFrag *)(uint64_t)F;
   D.T64 = (const __attribute__((address_space(1))) double *)(uint64_t)C.T;
   D.T16 = (const __attribute__((address_space(1))) uint16_t *)(uint64_t)C.T;
-  D.shots = C.shots;
+  D.inv = 1.0 / C.shots;
   D.rows = C.rows;
   D.c16 = C.cnt16 != 0;
   return D;
@@ -123,7 +123,7 @@ __device__ inline DirOp dir_op(const RecombFrag *F) {
 
 // Entries (term kb + kk0 + STEP i, row col) of a direct side, i < NPER;
 // 0 past the K range or the side's extent.  Every load is issued before
-// the first is used (the value is tval's: count / shots, or the fp64 entry).
+// the first is used (the value is tval's: count x fl(1/shots), or the fp64 entry).
 template <uint32_t NPER, uint32_t STEP>
 __device__ __attribute__((always_inline)) inline void direct_gather(const DirOp &D, uint64_t kb, uint64_t k1,
                                                                     uint32_t kk0, uint32_t col, bool col_ok,
@@ -141,7 +141,7 @@ __device__ __attribute__((always_inline)) inline void direct_gather(const DirOp 
 #pragma unroll
     for (uint32_t i = 0; i < NPER; ++i) c[i] = D.T16[ix[i]];
 #pragma unroll
-    for (uint32_t i = 0; i < NPER; ++i) v[i] = ok[i] ? (double)c[i] / D.shots : 0.0;
+    for (uint32_t i = 0; i < NPER; ++i) v[i] = ok[i] ? (double)c[i] * D.inv : 0.0;
   } else {
 #pragma unroll
     for (uint32_t i = 0; i < NPER; ++i) v[i] = D.T64[ix[i]];
@@ -178,7 +178,7 @@ __device__ __attribute__((always_inline)) inline void direct_value(const DirOp &
 #pragma unroll
   for (uint32_t i = 0; i < NPER; ++i) {
     const bool ok = col_ok && kb + kk0 + STEP * i < k1;
-    const double x = D.c16 ? (double)(uint32_t)raw[i] / D.shots : __longlong_as_double((long long)raw[i]);
+    const double x = D.c16 ? (double)(uint32_t)raw[i] * D.inv : __longlong_as_double((long long)raw[i]);
     v[i] = ok ? x : 0.0;
   }
 }
@@ -225,7 +225,7 @@ __device__ inline void fac_fill(const GemmArgs *__restrict__ G, bool left, uint3
       double v = 0.0;
       if (j < k1) {
         const uint64_t idx = frag_p(G, f, C->terms ? C->terms[j] : j) * F.rows + (fixed | r);
-        v = F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] / F.shots : F.T[idx];
+        v = F.cnt16 ? (double)reinterpret_cast<const uint16_t *>(F.T)[idx] * (1.0 / F.shots) : F.T[idx];
       }
       fac[off + e] = v;
     }
@@ -522,7 +522,7 @@ struct ColLoad<1> {
   typedef uint32_t Raw16;
   typedef double Raw64;
   __device__ static Raw16 cnt(g_u16 *p) { return p[0]; }
-  __device__ static void cnt_val(Raw16 w, double shots, double *b) { b[0] = (double)w / shots; }
+  __device__ static void cnt_val(Raw16 w, double inv, double *b) { b[0] = (double)w * inv; }
   __device__ static Raw64 f64(g_f64 *p) { return p[0]; }
   __device__ static void f64_val(Raw64 v, double *b) { b[0] = v; }
 };
@@ -531,9 +531,9 @@ struct ColLoad<2> {
   typedef uint32_t Raw16;
   typedef d2v Raw64;
   __device__ static Raw16 cnt(g_u16 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) uint32_t *>(p); }
-  __device__ static void cnt_val(Raw16 w, double shots, double *b) {
-    b[0] = (double)(w & 0xFFFFu) / shots;
-    b[1] = (double)(w >> 16) / shots;
+  __device__ static void cnt_val(Raw16 w, double inv, double *b) {
+    b[0] = (double)(w & 0xFFFFu) * inv;
+    b[1] = (double)(w >> 16) * inv;
   }
   __device__ static Raw64 f64(g_f64 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) d2v *>(p); }
   __device__ static void f64_val(Raw64 v, double *b) { b[0] = v.x, b[1] = v.y; }
@@ -545,11 +545,11 @@ struct ColLoad<4> {
     d2v a, b;
   };
   __device__ static Raw16 cnt(g_u16 *p) { return *reinterpret_cast<const __attribute__((address_space(1))) u2v *>(p); }
-  __device__ static void cnt_val(Raw16 w, double shots, double *b) {
-    b[0] = (double)(w.x & 0xFFFFu) / shots;
-    b[1] = (double)(w.x >> 16) / shots;
-    b[2] = (double)(w.y & 0xFFFFu) / shots;
-    b[3] = (double)(w.y >> 16) / shots;
+  __device__ static void cnt_val(Raw16 w, double inv, double *b) {
+    b[0] = (double)(w.x & 0xFFFFu) * inv;
+    b[1] = (double)(w.x >> 16) * inv;
+    b[2] = (double)(w.y & 0xFFFFu) * inv;
+    b[3] = (double)(w.y >> 16) * inv;
   }
   __device__ static Raw64 f64(g_f64 *p) {
     const __attribute__((address_space(1))) d2v *q = reinterpret_cast<const __attribute__((address_space(1))) d2v *>(p);
@@ -577,7 +577,7 @@ __device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs
   g_f64 *Tn = (g_f64 *)(uint64_t)FR.T + n;
   g_u16 *Cn = (g_u16 *)(uint64_t)FR.T + n;
   const bool cnt16 = FR.cnt16 != 0;
-  const double shots = FR.shots;
+  const double inv = 1.0 / FR.shots;  // a count's value is count x fl(1/shots)
   const uint64_t rows = FR.rows;
   const bool square = G->square != 0;
   g_f64 *tscale = (g_f64 *)(uint64_t)cargs(G)->tscale;
@@ -607,7 +607,7 @@ __device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs
       double a;
       if (FA) {
         const uint64_t ix = j * DA.rows + m;
-        a = DA.c16 ? (double)DA.T16[ix] / DA.shots : DA.T64[ix];
+        a = DA.c16 ? (double)DA.T16[ix] * DA.inv : DA.T64[ix];
       } else {
         a = side_value(G, G->L, m, terms ? terms[j] : j);
       }
@@ -631,7 +631,7 @@ __device__ __attribute__((always_inline)) inline void skinny_body(const GemmArgs
         for (uint32_t u = 0; u < U; ++u) {
           if (k2 + u >= kn) break;
           double b[CPT];
-          ColLoad<CPT>::cnt_val(w[u], shots, b);
+          ColLoad<CPT>::cnt_val(w[u], inv, b);
 #pragma unroll
           for (uint32_t c = 0; c < CPT; ++c) {
             if (square) b[c] *= b[c];

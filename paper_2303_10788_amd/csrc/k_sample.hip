@@ -49,7 +49,8 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
                             uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt,
                             uint64_t *__restrict__ records, uint64_t v, uint32_t bx, uint32_t nbx,
                             uint64_t *s_dyn, uint64_t *s_model, uint32_t slice = 0, uint32_t nslice = 1,
-                            double *__restrict__ dist = nullptr, uint16_t *__restrict__ cnt16 = nullptr) {
+                            double *__restrict__ dist = nullptr, uint16_t *__restrict__ cnt16 = nullptr,
+                            bool skip = false) {
   const uint32_t mw = model_words(n_meas);
   const uint64_t *md = models + v * mw;
   const uint32_t groups = sample_tab_groups(n_meas);
@@ -73,7 +74,7 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   // sliced (nslice > 1): this workgroup counts the outcomes whose top bits
   // equal `slice` into an LDS histogram of 2^kLdsHistBits bins
   const bool sliced = nslice > 1;
-  // dist (one shot block): the workgroup writes the table itself, count / shots
+  // dist (one shot block): the workgroup writes the table itself, count x fl(1/shots)
   const bool lds_hist = (partial != nullptr || dist != nullptr || cnt16 != nullptr) && (n_meas <= kLdsHistBits || sliced);
   const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
   const uint32_t lwords = (lbins + 1) / 2;  // two 16-bit counts per word
@@ -89,7 +90,9 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   const bool combine = (lds_hist || partial != nullptr) && __popcll(rmask) <= 6;
   const uint32_t lane = threadIdx.x & 63u;
   uint32_t *hist = lds_hist ? s_hist : (partial ? partial + v * (uint64_t)bins : nullptr);
-  for (uint32_t q = 0; q < qpt; ++q) {
+  // a skipped variant draws no shots: its (zero) histogram is still written
+  const uint32_t q_end = skip ? 0u : qpt;
+  for (uint32_t q = 0; q < q_end; ++q) {
     const uint64_t quad = ((uint64_t)bx * qpt + q) * kSampleBlock + threadIdx.x;
     if (!combine && quad >= nquads) break;
     if (combine && ((uint64_t)bx * qpt + q) * kSampleBlock >= nquads) break;  // the whole workgroup is done
@@ -143,7 +146,8 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
       }
     } else if (dist) {
       double *dd = dist + v * (uint64_t)bins + (uint64_t)slice * lbins;
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)count(i) / (double)shots;
+      const double inv = 1.0 / (double)shots;  // an entry is count x fl(1/shots)
+      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)count(i) * inv;
     } else {
       uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins + (uint64_t)slice * lbins;
       for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = count(i);
@@ -152,13 +156,17 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
 }
 
 // grid: (nblk_x, nv)
+// vmask (optional): variant v draws its shots only if vmask[v] != 0; the
+// others keep all-zero counts (variants no supported cut term reads)
 __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
     const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
-    uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records) {
+    uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records,
+    const uint8_t *__restrict__ vmask) {
   extern __shared__ uint64_t s_dyn[];
   __shared__ uint64_t s_model[2 + kMaxMeas];
+  const bool skip = vmask && !vmask[blockIdx.y];
   sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn,
-              s_model);
+              s_model, 0, 1, nullptr, nullptr, skip);
 }
 
 // Many fragments' sampling in one launch: unit g of the job holding it is
@@ -185,7 +193,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const Sample
   }
 }
 
-// dist[v][b] = (sum over shot blocks of counts) / shots
+// dist[v][b] = (sum over shot blocks of counts) x fl(1/shots)
 __global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_t nv, uint32_t nblk,
                                    uint32_t bins, uint64_t shots, double *__restrict__ dist,
                                    uint16_t *__restrict__ cnt16) {
@@ -197,7 +205,7 @@ __global__ void hist_reduce_kernel(const uint32_t *__restrict__ partial, uint64_
   if (cnt16)
     cnt16[i] = (uint16_t)c;
   else
-    dist[i] = (double)c / (double)shots;
+    dist[i] = (double)c * (1.0 / (double)shots);  // count x fl(1/shots)
 }
 
 // The same over every job of a batch: workgroup x reduces entries
@@ -618,14 +626,14 @@ hipError_t launch_records_wide(const uint64_t *models, uint32_t n_meas, uint64_t
 
 hipError_t launch_sample_hist(const uint64_t *models, uint32_t n_meas, uint64_t nv, uint64_t shots,
                               uint64_t seed, uint64_t vid0, uint32_t *partial, uint32_t nblk_x,
-                              uint32_t qpt, uint64_t *records, hipStream_t s) {
+                              uint32_t qpt, uint64_t *records, hipStream_t s, const uint8_t *vmask) {
   if (n_meas > (uint32_t)kMaxMeas || nv == 0 || nv > 65535) return hipErrorInvalidValue;
   if (partial && n_meas <= kLdsHistBits && qpt > kMaxUnitQpt) return hipErrorInvalidValue;  // 16-bit LDS counts
   const size_t lds = sample_lds_bytes(n_meas, partial != nullptr);
   hipError_t e = hipFuncSetAttribute((const void *)sample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sample_kernel, dim3(nblk_x, (unsigned)nv), dim3(kSampleBlock), lds, s, models,
-                     n_meas, shots, seed, vid0, partial, qpt, records);
+                     n_meas, shots, seed, vid0, partial, qpt, records, vmask);
   return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ def test_flag_scope_errors(ctx):
         plan.zexpect(words, flags=cc.CCUT_FLAG_SPARSE)
     assert e.value.status == cc.CCUT_E_UNSUPPORTED
     with pytest.raises(cc.CcutError) as e:
-        plan.marginal(w.qubits, flags=8)
+        plan.marginal(w.qubits, flags=16)
     assert e.value.status == cc.CCUT_E_INVALID
     eo = cc._eval_opts(0, 0, flags=cc.CCUT_FLAG_SPARSE)
     with pytest.raises(cc.CcutError) as e:
@@ -153,3 +153,72 @@ def test_wide_exact_request_takes_variant_path(ctx):
     _log(f"wide exact request: cuts {cuts}, requested bits {reqs}")
     got = plan.marginal(qubits)
     assert np.abs(got - sv.uncut_marginal(w.n, w.ops, qubits)).max() <= 1e-10
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_skip_marginal_vs_oracle(ctx, seed):
+    """Sec. IX downstream skipping: the support from the Clifford fragments'
+    exact tensors, unread sampled variants drawing no shots, the sum over the
+    support only.  Sampled and exact data against the oracle; exact data
+    also against the full contraction (the skipped terms are exactly zero)."""
+    import torch
+    n, ops, cuts, rng = _case(seed, seed % 2 == 0)
+    qubits = [int(q) for q in rng.permutation(n)[: int(rng.integers(1, n + 1))]]
+    _log(f"skip marginal: seed={seed} n={n} k={len(cuts)} nq={len(qubits)}")
+    plan = cc.Plan(ctx, n, ops, cuts)
+    for shots in (0, 500):
+        got = plan.marginal(qubits, shots=shots, seed=seed, flags=cc.CCUT_FLAG_SKIP)
+        ref = C.marginal_skip(n, ops, cuts, qubits, shots=shots, seed=seed)
+        assert np.abs(got - ref).max() <= 1e-10, shots
+        out = torch.full((1 << len(qubits),), 7.0, dtype=torch.float64, device="cuda")
+        plan.marginal(qubits, shots=shots, seed=seed, flags=cc.CCUT_FLAG_SKIP, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), got), shots
+    exact = plan.marginal(qubits)
+    assert np.abs(plan.marginal(qubits, flags=cc.CCUT_FLAG_SKIP) - exact).max() <= 1e-12
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_skip_paper_workloads(ctx, seed):
+    """The paper's workload families with automatic cuts, sampled with
+    skipping: against the oracle; exact with skipping: against the uncut
+    state vector."""
+    from oracle import statevector as sv
+    for w in (W.hwea(12, seed=seed), W.qaoa_sk(10, seed=seed)):
+        cuts = cc.find_cuts(w.n, w.ops, 4)
+        q = w.qubits if w.qubits else list(range(min(w.n, 8)))
+        _log(f"skip on {w.name}: cuts {cuts} nq={len(q)}")
+        plan = cc.Plan(ctx, w.n, w.ops, cuts)
+        got = plan.marginal(q, shots=2000, seed=seed, flags=cc.CCUT_FLAG_SKIP)
+        ref = C.marginal_skip(w.n, w.ops, cuts, q, shots=2000, seed=seed)
+        assert np.abs(got - ref).max() <= 1e-10, w.name
+        ex = plan.marginal(q, flags=cc.CCUT_FLAG_SKIP)
+        assert np.abs(ex - sv.uncut_marginal(w.n, w.ops, q)).max() <= 1e-10, w.name
+
+
+def test_skip_fp32_contraction(ctx):
+    """Skipping with the fp32 MFMA contraction over the support (a term list
+    too long for the plain sum): against the fp64 result."""
+    w = W.learned_circuit(200001)
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    _log(f"skip fp32: {w.name} k={len(w.cuts)} nq={len(w.qubits)}")
+    d = plan.marginal(w.qubits, shots=200, seed=5, flags=cc.CCUT_FLAG_SKIP)
+    f = plan.marginal(w.qubits, shots=200, seed=5, flags=cc.CCUT_FLAG_SKIP, precision=cc.CCUT_FP32_MFMA_FP64SUM)
+    assert np.abs(f - d).max() <= 1e-5
+    ex = plan.marginal(w.qubits)
+    assert np.abs(plan.marginal(w.qubits, flags=cc.CCUT_FLAG_SKIP) - ex).max() <= 1e-12
+
+
+def test_skip_flag_scope(ctx):
+    w = W.tiny()
+    plan = cc.Plan(ctx, w.n, w.ops, w.cuts)
+    words = np.array([[1], [3]], dtype=np.uint64)
+    for call in (lambda: plan.zexpect(words, flags=cc.CCUT_FLAG_SKIP),
+                 lambda: plan.marginal(w.qubits, shots=100, flags=cc.CCUT_FLAG_SKIP | cc.CCUT_FLAG_ML),
+                 lambda: plan.variant_tables(w.qubits, 0, flags=cc.CCUT_FLAG_SKIP),
+                 lambda: plan.fragment_tensor(w.qubits, 0, flags=cc.CCUT_FLAG_SKIP),
+                 lambda: cc.ccut_batch_create(ctx.handle, [plan], cc._eval_opts(0, 0, flags=cc.CCUT_FLAG_SKIP),
+                                              [w.qubits])):
+        with pytest.raises(cc.CcutError) as e:
+            call()
+        assert e.value.status == cc.CCUT_E_UNSUPPORTED

@@ -239,11 +239,12 @@ def test_mid_full_size_sampled(ctx):
     for v in (0, 7, 15):
         exp = _oracle_records(w.n, w.ops, w.cuts, w.qubits, f, v, w.seed, 600)
         assert np.array_equal(rec[v, :600], exp)
-    # the histograms behind the estimate are the records' counts
+    # the histograms behind the estimate are the records' counts (a table
+    # entry is count x fl(1/shots))
     tab = plan.variant_tables(w.qubits, f, shots=w.shots, seed=w.seed)
     for v in (0, 15):
         counts = np.bincount(rec[v].astype(np.int64), minlength=tab.shape[1])
-        assert np.array_equal(counts / w.shots, tab[v])
+        assert np.array_equal(counts * (1.0 / w.shots), tab[v])
 
 
 # ------------------------------------------------------------ Z strings
