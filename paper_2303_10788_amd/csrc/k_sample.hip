@@ -33,6 +33,59 @@ __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, boo
 
 constexpr int kSampleBlock = (int)kSampleThreads;
 
+// Shots counted in an LDS histogram with at most 32 measured indices (no
+// records, more than 6 random indices): two quads (8 shots) per step from
+// two independent Philox calls, every table lookup of the 8 shots issued
+// before its first use, then one packed 16-bit count per shot.  LDS words:
+// the 32-bit tables at [0, tw) (tw = 256 per group, in the lower half of
+// the region sized for 64-bit entries), one dummy word per lane at
+// [tw, tw + 64) that shots outside the count add 0 to (no branch per shot),
+// the histogram from 2 tw.  G table groups per shot; SLICED: only outcomes
+// whose bits above kLdsHistBits equal `slice` count.  The same shots as the
+// generic loop (quad (q0 + q) x kSampleBlock + thread), so the same counts.
+template <int G, bool SLICED>
+__device__ __attribute__((always_inline)) void narrow_lds_shots(uint32_t *lds, uint32_t x0, uint64_t shots,
+                                                                uint64_t vid, uint64_t seed, uint64_t q0,
+                                                                uint32_t q_end, uint32_t slice) {
+  constexpr uint32_t tw = 256u * G;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const uint32_t v_lo = (uint32_t)vid, v_hi = (uint32_t)(vid >> 32);
+  const uint64_t nquads = (shots + 3) >> 2;
+  const uint32_t dummy = tw + (threadIdx.x & 63u);
+  for (uint32_t q = 0; q < q_end; q += 2) {
+    if ((q0 + q) * kSampleBlock >= nquads) break;  // the whole workgroup is done
+    const uint64_t qa = (q0 + q) * kSampleBlock + threadIdx.x, qb = qa + kSampleBlock;
+    // shots of each quad inside the count (0-4)
+    const uint64_t sa = 4 * qa, sb = 4 * qb;
+    const uint32_t na = sa >= shots ? 0u : shots - sa >= 4 ? 4u : (uint32_t)(shots - sa);
+    const uint32_t nb = q + 1 >= q_end || sb >= shots ? 0u : shots - sb >= 4 ? 4u : (uint32_t)(shots - sb);
+    const U4 wa = philox10(0u, (uint32_t)qa, v_lo, v_hi, k0, k1);
+    const U4 wb = philox10(0u, (uint32_t)qb, v_lo, v_hi, k0, k1);
+    uint32_t t[8][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        t[r][g] = lds[(g << 8) | ((wa.w[r] >> (8 * g)) & 255u)];
+        t[4 + r][g] = lds[(g << 8) | ((wb.w[r] >> (8 * g)) & 255u)];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      uint32_t x = x0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) x ^= t[i][g];
+      bool valid = i < 4 ? (uint32_t)i < na : (uint32_t)(i - 4) < nb;
+      if (SLICED) {
+        valid = valid && (x >> kLdsHistBits) == slice;
+        x &= (1u << kLdsHistBits) - 1u;
+      }
+      const uint32_t w = valid ? 2 * tw + (x >> 1) : dummy;
+      atomicAdd(&lds[w], valid ? 1u << (16 * (x & 1u)) : 0u);
+    }
+  }
+}
+
 // Shots of variant v, block bx of nbx: each thread handles `qpt` quads;
 // quads are interleaved across the workgroup so record writes are
 // contiguous.  With n_meas <= kLdsHistBits (or a slice of the bins) the
@@ -60,6 +113,20 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   if (threadIdx.x < mw) s_model[threadIdx.x] = md[threadIdx.x];
   __syncthreads();
   const uint64_t x0 = s_model[0], rmask = s_model[1];
+  const uint32_t bins = 1u << n_meas;
+  // sliced (nslice > 1): this workgroup counts the outcomes whose top bits
+  // equal `slice` into an LDS histogram of 2^kLdsHistBits bins
+  const bool sliced = nslice > 1;
+  // dist (one shot block): the workgroup writes the table itself, count x fl(1/shots)
+  const bool lds_hist = (partial != nullptr || dist != nullptr || cnt16 != nullptr) && (n_meas <= kLdsHistBits || sliced);
+  const bool wide = n_meas > 32;
+  // With few random bits the shots of a wave land on few bins: lanes with
+  // equal outcomes then add their count once (one atomic per distinct
+  // outcome in the wave instead of up to 64 on one address).
+  const bool combine = (lds_hist || partial != nullptr) && __popcll(rmask) <= 6;
+  const bool fast = lds_hist && !wide && records == nullptr && !combine &&
+                    ((!sliced && groups >= 1 && groups <= 2) || (sliced && groups == 3));
+  uint32_t *s_tab32 = reinterpret_cast<uint32_t *>(s_dyn);  // the fast path's 32-bit entries
   for (uint32_t e = threadIdx.x; e < groups * 256; e += kSampleBlock) {
     const uint32_t g = e >> 8, b = e & 255u;
     uint64_t t = 0;
@@ -68,31 +135,32 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
       const uint32_t a = 8 * g + i;
       if (((b >> i) & 1u) && a < n_meas && ((rmask >> a) & 1ull)) t ^= s_model[2 + a];
     }
-    s_tab[e] = t;
+    if (fast)
+      s_tab32[e] = (uint32_t)t;  // at most 32 measured indices: the entry fits
+    else
+      s_tab[e] = t;
   }
-  const uint32_t bins = 1u << n_meas;
-  // sliced (nslice > 1): this workgroup counts the outcomes whose top bits
-  // equal `slice` into an LDS histogram of 2^kLdsHistBits bins
-  const bool sliced = nslice > 1;
-  // dist (one shot block): the workgroup writes the table itself, count x fl(1/shots)
-  const bool lds_hist = (partial != nullptr || dist != nullptr || cnt16 != nullptr) && (n_meas <= kLdsHistBits || sliced);
   const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
   const uint32_t lwords = (lbins + 1) / 2;  // two 16-bit counts per word
   if (lds_hist)
     for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) s_hist[i] = 0;
   __syncthreads();
   const uint64_t vid = vid0 + v;
-  const bool wide = n_meas > 32;
   const uint64_t nquads = (shots + 3) >> 2;
-  // With few random bits the shots of a wave land on few bins: lanes with
-  // equal outcomes then add their count once (one atomic per distinct
-  // outcome in the wave instead of up to 64 on one address).
-  const bool combine = (lds_hist || partial != nullptr) && __popcll(rmask) <= 6;
   const uint32_t lane = threadIdx.x & 63u;
   uint32_t *hist = lds_hist ? s_hist : (partial ? partial + v * (uint64_t)bins : nullptr);
   // a skipped variant draws no shots: its (zero) histogram is still written
   const uint32_t q_end = skip ? 0u : qpt;
-  for (uint32_t q = 0; q < q_end; ++q) {
+  if (fast) {
+    const uint64_t q0 = (uint64_t)bx * qpt;
+    if (groups == 1)
+      narrow_lds_shots<1, false>(s_tab32, (uint32_t)x0, shots, vid, seed, q0, q_end, slice);
+    else if (groups == 2)
+      narrow_lds_shots<2, false>(s_tab32, (uint32_t)x0, shots, vid, seed, q0, q_end, slice);
+    else
+      narrow_lds_shots<3, true>(s_tab32, (uint32_t)x0, shots, vid, seed, q0, q_end, slice);
+  }
+  for (uint32_t q = 0; q < (fast ? 0u : q_end); ++q) {
     const uint64_t quad = ((uint64_t)bx * qpt + q) * kSampleBlock + threadIdx.x;
     if (!combine && quad >= nquads) break;
     if (combine && ((uint64_t)bx * qpt + q) * kSampleBlock >= nquads) break;  // the whole workgroup is done
