@@ -61,26 +61,36 @@ __device__ inline void stage_words(uint32_t *dst, const uint32_t *src, uint32_t 
     if (lane + 64 * k < CAP) dst[lane + 64 * k] = t[k];
 }
 
-template <class D>
+// NW waves per workgroup: a layer's ops are spread over all 64 NW lanes and
+// the waves meet at a barrier after each layer (a lane reads columns other
+// waves wrote in the previous layer); wave 0 stages op words and layer
+// offsets and transposes rows in and out, and the lanes' sign shares are
+// XOR-reduced within each wave, then across the waves through LDS.  NW = 1:
+// no barriers (one wave's LDS accesses complete in issue order).
+template <uint32_t NW, class D>
 __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                  uint32_t n_rows, uint64_t *cols) {
+  constexpr uint32_t T = 64 * NW;
   const uint32_t m = F.m;
   const uint32_t RW = (n_rows + 63) / 64;
-  const uint32_t lane = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   uint32_t lg = 0;
   while ((1u << lg) < RW) ++lg;
-  const uint32_t RWp = 1u << lg, w = lane & (RWp - 1), o = lane >> lg, per = 64u >> lg;
+  const uint32_t RWp = 1u << lg, w = tid & (RWp - 1), o = tid >> lg, per = T >> lg;
   uint64_t *Xc = cols, *Zc = cols + (size_t)m * RW;
   uint32_t *sops = reinterpret_cast<uint32_t *>(Zc + (size_t)m * RW);
   const uint32_t RS = 2 * W + 1;  // row stride in words
   uint64_t sg = 0;  // this lane's share of sign word w
+  auto sync = [] {
+    if (NW > 1) __syncthreads();
+  };
   if (!in) {
-    for (uint32_t idx = lane; idx < m * RW; idx += 64) {  // X_r for rows r < m, then Z_{r - m}
+    for (uint32_t idx = tid; idx < m * RW; idx += T) {  // X_r for rows r < m, then Z_{r - m}
       const uint32_t q = idx / RW, iw = idx % RW;
       Xc[idx] = q >> 6 == iw ? 1ull << (q & 63) : 0ull;
       Zc[idx] = (m + q) >> 6 == iw ? 1ull << ((m + q) & 63) : 0ull;
     }
-  } else {
+  } else if (wave == 0) {
     // transpose in, 64 rows at a time: lane l loads row 64 iw + l whole,
     // and column word (q, iw) is the ballot of bit q over the lanes
     for (uint32_t iw = 0; iw < RW; ++iw) {
@@ -121,17 +131,20 @@ __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restr
   const uint32_t *lay = F.layers;
   const uint32_t n_layers = lay ? F.n_layers : F.n_ops;
   uint32_t stage0 = 0;
-  stage_words<kOpStage>(sops, F.ops, F.n_ops, lane);
+  if (wave == 0) stage_words<kOpStage>(sops, F.ops, F.n_ops, lane);
   uint32_t s0 = 0;
-  uint32_t v_wd = sops[o];  // this lane's first op word of the current layer
   for (uint32_t L0 = 0; L0 < n_layers; L0 += kLayStage) {
     const uint32_t nl = min(kLayStage, n_layers - L0);
-    if (lay) {
-      stage_words<kLayStage + 1>(slay, lay + L0, nl + 1, lane);
-    } else {
-      for (uint32_t i = lane; i <= nl; i += 64) slay[i] = L0 + i;
+    if (wave == 0) {
+      if (lay) {
+        stage_words<kLayStage + 1>(slay, lay + L0, nl + 1, lane);
+      } else {
+        for (uint32_t i = lane; i <= nl; i += 64) slay[i] = L0 + i;
+      }
     }
+    sync();  // the staged words (and, the first time, the op window) are in place
     uint32_t v_s1 = slay[1];
+    uint32_t v_wd = sops[s0 + o - stage0];  // this lane's first op word of the current layer
     for (uint32_t L = 0; L < nl; ++L) {
       const uint32_t s1 = __builtin_amdgcn_readfirstlane(v_s1);
       const uint32_t wd0 = v_wd;
@@ -165,19 +178,31 @@ __device__ void rows_sliced_body(const D &F, uint32_t W, const uint64_t *__restr
         }
       }
       asm volatile("" ::: "memory");
+      sync();  // every wave is done with this layer's columns (and op words)
       if (!keep) {  // restage from the next layer's start (in issue order after this layer's reads)
         stage0 = s1;
-        stage_words<kOpStage>(sops, F.ops + s1, F.n_ops - s1, lane);
+        if (wave == 0) stage_words<kOpStage>(sops, F.ops + s1, F.n_ops - s1, lane);
+        sync();
         v_wdn = sops[o];
       }
       s0 = s1;
       v_s1 = v_s1n;
       v_wd = v_wdn;
     }
+    sync();  // every wave has read this stage's layer offsets
   }
-  // sign word w: XOR of the shares of every lane on row word w (lane w ends with it)
+  // sign word w: XOR of the shares of every lane on row word w (lane w of
+  // wave 0 ends with it)
   for (uint32_t off = RWp; off < 64; off <<= 1) sg ^= __shfl_xor(sg, off);
   __syncthreads();
+  if (NW > 1) {
+    uint64_t *red = reinterpret_cast<uint64_t *>(sops);  // the op window is no longer read
+    if (lane < RWp) red[wave * 64 + lane] = sg;
+    __syncthreads();
+    if (wave == 0 && lane < RWp)
+      for (uint32_t v = 1; v < NW; ++v) sg ^= red[v * 64 + lane];
+  }
+  if (wave != 0) return;
   // transpose out, 64 rows at a time: lane l gathers row 64 rw + l from the
   // column words (each read is the same address for every lane)
   for (uint32_t rw = 0; rw < RW; ++rw) {
@@ -210,18 +235,20 @@ __global__ __launch_bounds__(64) void rows_sliced_kernel(const FragDev F, uint32
   extern __shared__ uint64_t cols[];
   const uint32_t r0 = blockIdx.x * kSlicedRows;
   const size_t RS = 2 * W + 1;
-  rows_sliced_body(F, W, in ? in + r0 * RS : nullptr, out + r0 * RS, min(kSlicedRows, n_rows - r0), cols);
+  rows_sliced_body<1>(F, W, in ? in + r0 * RS : nullptr, out + r0 * RS, min(kSlicedRows, n_rows - r0), cols);
 }
 
 // Carry-back of many fragments' rows: block x carries job x's n_rows input
-// rows (row width W words per half) through its descriptor's stream.
-__global__ __launch_bounds__(64) void carry_batch_kernel(const FragDev *__restrict__ descs,
+// rows (row width W words per half) through its descriptor's stream, with
+// kCarryWaves waves spreading each layer's ops.
+constexpr uint32_t kCarryWaves = 4;
+__global__ __launch_bounds__(64 * kCarryWaves) void carry_batch_kernel(const FragDev *__restrict__ descs,
                                                           const CarryJob *__restrict__ jobs,
                                                           const uint64_t *__restrict__ in, uint64_t *__restrict__ out) {
   extern __shared__ uint64_t cols[];
   const CarryJob &J = jobs[blockIdx.x];
   const g_FragDevH &F = ((const g_FragDevH *)descs)[J.desc];
-  rows_sliced_body(F, J.W, in + J.in_off, out + J.out_off, J.n_rows, cols);
+  rows_sliced_body<kCarryWaves>(F, J.W, in + J.in_off, out + J.out_off, J.n_rows, cols);
 }
 
 struct HeisArgs {
@@ -417,7 +444,7 @@ hipError_t launch_carry_batch(const FragDev *descs, const CarryJob *jobs, uint32
   hipError_t e = hipFuncSetAttribute((const void *)carry_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(carry_batch_kernel, dim3(n_jobs), dim3(64), lds, s, descs, jobs, in, out);
+  hipLaunchKernelGGL(carry_batch_kernel, dim3(n_jobs), dim3(64 * kCarryWaves), lds, s, descs, jobs, in, out);
   return hipGetLastError();
 }
 

@@ -32,6 +32,14 @@ __device__ inline void quad_bits(uint64_t quad, uint64_t vid, uint64_t seed, boo
 }
 
 constexpr int kSampleBlock = (int)kSampleThreads;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) u32x4 gu32x4;
+typedef __attribute__((address_space(1))) u32x2 gu32x2;
+typedef __attribute__((address_space(1))) f64x2 gf64x2;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) double gf64;
 
 // Shots counted in an LDS histogram with at most 32 measured indices (no
 // records, more than 6 random indices): two quads (8 shots) per step from
@@ -142,8 +150,14 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   }
   const uint32_t lbins = sliced ? (1u << kLdsHistBits) : bins;
   const uint32_t lwords = (lbins + 1) / 2;  // two 16-bit counts per word
-  if (lds_hist)
-    for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) s_hist[i] = 0;
+  if (lds_hist) {
+    if (lwords % 4 == 0) {  // 16 bytes per store (the histogram starts 16-byte aligned)
+      u32x4 *h4 = reinterpret_cast<u32x4 *>(s_hist);
+      for (uint32_t i = threadIdx.x; i < lwords / 4; i += kSampleBlock) h4[i] = u32x4{0u, 0u, 0u, 0u};
+    } else {
+      for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) s_hist[i] = 0;
+    }
+  }
   __syncthreads();
   const uint64_t vid = vid0 + v;
   const uint64_t nquads = (shots + 3) >> 2;
@@ -204,10 +218,18 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
   if (lds_hist) {
     __syncthreads();
     auto count = [&](uint32_t i) { return (s_hist[i >> 1] >> (16 * (i & 1u))) & 0xFFFFu; };
+    // Stores go through global pointers (a generic store also counts against
+    // the LDS wait counter, so the next LDS read would wait for it).  With at
+    // least 8 bins every row starts 16-byte aligned: 16 bytes per store.
     if (cnt16) {
       uint16_t *dd = cnt16 + v * (uint64_t)bins + (uint64_t)slice * lbins;
-      if (lbins >= 2) {  // the packed words are the table's layout (little-endian pairs)
-        uint32_t *dw = reinterpret_cast<uint32_t *>(dd);
+      if (lbins >= 8) {  // the packed words are the table's layout (little-endian pairs)
+        gu32x4 *dst = (gu32x4 *)(dd);
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(s_hist);
+#pragma unroll 4
+        for (uint32_t i = threadIdx.x; i < lwords / 4; i += kSampleBlock) dst[i] = src[i];
+      } else if (lbins >= 2) {
+        gu32 *dw = (gu32 *)(dd);
         for (uint32_t i = threadIdx.x; i < lwords; i += kSampleBlock) dw[i] = s_hist[i];
       } else if (threadIdx.x == 0) {
         dd[0] = (uint16_t)count(0);
@@ -215,10 +237,29 @@ __device__ __attribute__((always_inline)) void sample_body(const uint64_t *__res
     } else if (dist) {
       double *dd = dist + v * (uint64_t)bins + (uint64_t)slice * lbins;
       const double inv = 1.0 / (double)shots;  // an entry is count x fl(1/shots)
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dd[i] = (double)(uint64_t)count(i) * inv;
+      if (lbins >= 8) {  // one packed word: two entries, 16 bytes
+        gf64x2 *dst = (gf64x2 *)(dd);
+#pragma unroll 4
+        for (uint32_t w = threadIdx.x; w < lwords; w += kSampleBlock) {
+          const uint32_t c = s_hist[w];
+          dst[w] = f64x2{(double)(c & 0xFFFFu) * inv, (double)(c >> 16) * inv};
+        }
+      } else {
+        gf64 *dst = (gf64 *)(dd);
+        for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = (double)(uint64_t)count(i) * inv;
+      }
     } else {
-      uint32_t *dst = partial + (v * nbx + bx) * (uint64_t)bins + (uint64_t)slice * lbins;
-      for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = count(i);
+      uint32_t *dp = partial + (v * nbx + bx) * (uint64_t)bins + (uint64_t)slice * lbins;
+      if (lbins >= 8) {  // one packed word: two counts, 8 bytes
+        gu32x2 *dst = (gu32x2 *)(dp);
+        for (uint32_t w = threadIdx.x; w < lwords; w += kSampleBlock) {
+          const uint32_t c = s_hist[w];
+          dst[w] = u32x2{c & 0xFFFFu, c >> 16};
+        }
+      } else {
+        gu32 *dst = (gu32 *)(dp);
+        for (uint32_t i = threadIdx.x; i < lbins; i += kSampleBlock) dst[i] = count(i);
+      }
     }
   }
 }
@@ -230,7 +271,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
     const uint64_t *__restrict__ models, uint32_t n_meas, uint64_t shots, uint64_t seed,
     uint64_t vid0, uint32_t *__restrict__ partial, uint32_t qpt, uint64_t *__restrict__ records,
     const uint8_t *__restrict__ vmask) {
-  extern __shared__ uint64_t s_dyn[];
+  extern __shared__ __align__(16) uint64_t s_dyn[];
   __shared__ uint64_t s_model[2 + kMaxMeas];
   const bool skip = vmask && !vmask[blockIdx.y];
   sample_body(models, n_meas, shots, seed, vid0, partial, qpt, records, blockIdx.y, blockIdx.x, gridDim.x, s_dyn,
@@ -243,7 +284,7 @@ __global__ __launch_bounds__(kSampleBlock) void sample_kernel(
 __global__ __launch_bounds__(kSampleBlock) void sample_batch_kernel(const SampleJob *__restrict__ jobs,
                                                                       uint32_t n_jobs, uint64_t total,
                                                                       uint32_t per_wg) {
-  extern __shared__ uint64_t s_dyn[];
+  extern __shared__ __align__(16) uint64_t s_dyn[];
   __shared__ uint64_t s_model[2 + kMaxMeas];
   const uint64_t g0 = (uint64_t)blockIdx.x * per_wg;
   const uint64_t g1 = g0 + per_wg < total ? g0 + per_wg : total;
