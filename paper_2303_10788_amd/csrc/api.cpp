@@ -1991,15 +1991,15 @@ struct ccut_batch {
   std::vector<double *> cur_tab;
   std::vector<uint8_t> job_out;
   bool capturing = false;
-  // durations of the state-vector classes (by their widest width) measured
-  // in the creation run, in ms; later enqueues place the classes on the
-  // pool streams by them
+  // durations of the state-vector classes (by their widest width) and of
+  // the contraction classes (kCtrKey + class) measured in the creation run,
+  // in ms; later enqueues place the classes on the streams by them
   struct Span {
     uint32_t key;
     hipEvent_t e0, e1;
   };
   std::vector<Span> spans;
-  std::map<uint32_t, double> sv_ms;
+  std::map<uint32_t, double> class_ms;
   bool measured = false;
   ~ccut_batch() {
     if (h_copy) (void)hipHostFree(h_copy);
@@ -2148,6 +2148,8 @@ std::string tune_key(ccut_ctx *c, const ccut_batch *b) {
   return buf;
 }
 
+constexpr uint32_t kCtrKey = 1u << 20;  // contraction classes' keys in the measured durations (above any width)
+
 ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   ccut_ctx *c = b->ctx;
   ccut_status st;
@@ -2277,8 +2279,8 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
       // measured durations (ms) replace the estimates once the creation run has timed the classes
       if (b->measured)
         for (SvClass &C : classes) {
-          auto it = b->sv_ms.find(C.m);
-          if (it != b->sv_ms.end()) C.cost = it->second;
+          auto it = b->class_ms.find(C.m);
+          if (it != b->class_ms.end()) C.cost = it->second;
         }
       std::stable_sort(classes.begin(), classes.end(),
                        [](const SvClass &x, const SvClass &y) { return x.cost > y.cost; });
@@ -2683,20 +2685,45 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
     HIP_TRY(c, hipEventRecord(b->fork_ev, b->stream));
     for (size_t k = 0; k < n_side; ++k) HIP_TRY(c, hipStreamWaitEvent(b->pool[k], b->fork_ev, 0));
   }
-  size_t next = 0;  // launch classes in order, round-robin over the streams
-  auto pick = [&]() { c->cur = (next % (n_side + 1)) ? b->pool[next % (n_side + 1) - 1] : b->stream; ++next; };
-  if (!rjobs.empty()) {
-    pick();
-    KTimer t(c, CCUT_K_RECOMBINE);
-    HIP_TRY(c, launch_recombine_batch(d_r, (uint32_t)rjobs.size(), rwg, c->cur));
+  // the launch classes (-1: the plain sums, else the matrix class); the
+  // creation run puts them round-robin on the streams and times them, later
+  // enqueues place them longest first on the least-loaded stream
+  std::vector<int> cls;
+  if (!rjobs.empty()) cls.push_back(-1);
+  for (int sk = 0; sk < kGemmClasses; ++sk)
+    if (!gjobs[sk].empty()) cls.push_back(sk);
+  const size_t n_str = n_side + 1;
+  std::vector<size_t> where(cls.size()), seq(cls.size());
+  for (size_t i = 0; i < cls.size(); ++i) {
+    where[i] = i % n_str;
+    seq[i] = i;
   }
-  for (int sk = 0; sk < kGemmClasses; ++sk) {
-    if (gjobs[sk].empty()) continue;
-    pick();
+  if (b->measured) {
+    std::vector<double> cost(cls.size(), 0.0), load(n_str, 0.0);
+    for (size_t i = 0; i < cls.size(); ++i) {
+      auto it = b->class_ms.find(kCtrKey + (uint32_t)(cls[i] + 1));
+      if (it != b->class_ms.end()) cost[i] = it->second;
+    }
+    std::stable_sort(seq.begin(), seq.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    for (size_t i : seq) {
+      const size_t k = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += cost[i];
+      where[i] = k;
+    }
+  }
+  for (size_t i : seq) {
+    c->cur = where[i] ? b->pool[where[i] - 1] : b->stream;
+    const int sk = cls[i];
+    const int sp = span_begin(kCtrKey + (uint32_t)(sk + 1), c->cur);
     KTimer t(c, CCUT_K_RECOMBINE);
-    const int mode = fp32 ? (b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM ? 2 : 1) : 0;
-    HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], mode, ggen[sk], glds[sk],
-                                 sk ? 1u << ((sk - 1) / 3) : 0u, sk ? 1u << ((sk - 1) % 3) : 0u, c->cur));
+    if (sk < 0) {
+      HIP_TRY(c, launch_recombine_batch(d_r, (uint32_t)rjobs.size(), rwg, c->cur));
+    } else {
+      const int mode = fp32 ? (b->eo.precision == CCUT_FP32X3_MFMA_FP64SUM ? 2 : 1) : 0;
+      HIP_TRY(c, launch_gemm_batch(d_g[sk], (uint32_t)gjobs[sk].size(), gwg[sk], grwg[sk], mode, ggen[sk], glds[sk],
+                                   sk ? 1u << ((sk - 1) / 3) : 0u, sk ? 1u << ((sk - 1) % 3) : 0u, c->cur));
+    }
+    span_end(sp, c->cur);
   }
   c->cur = b->stream;
   for (size_t k = 0; k < n_side; ++k) {
@@ -2809,7 +2836,7 @@ ccut_status ccut_batch_create(ccut_ctx *c, ccut_plan *const *plans, size_t n, co
   for (const ccut_batch::Span &sp : b->spans) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, sp.e0, sp.e1) != hipSuccess) continue;
-    b->sv_ms[sp.key] = ms;
+    b->class_ms[sp.key] = ms;
   }
   (void)hipGetLastError();
   b->measured = !b->spans.empty();
