@@ -800,6 +800,14 @@ def bench_learned(args):
                    "sparse_exhaustive": lambda: plan.marginal(w.qubits, out=buf, flags=cc.CCUT_FLAG_SPARSE),
                    "learned": learned}
             out["ms"] = {k: 1e3 * _timed(f, args.steps, args.warmup) / args.steps for k, f in fns.items()}
+            if w.name == "learned200000":
+                # Sec. IX skipping in sampled mode: the marginal from 1000 shots per
+                # variant with every Clifford variant sampled, and with only the
+                # variants the exact support reads (the support is 1 term here)
+                sfns = {"all_variants": lambda: plan.marginal(w.qubits, shots=1000, seed=5, out=buf),
+                        "skip": lambda: plan.marginal(w.qubits, shots=1000, seed=5, out=buf,
+                                                      flags=cc.CCUT_FLAG_SKIP)}
+                out["sampled_1000_shots_ms"] = {k: 1e3 * _timed(f, 3, 1) / 3 for k, f in sfns.items()}
             # the contraction alone (tensors kept), with its kernel time
             con = {}
             for name, Lk in (("fp64", L), ("fp32", L32)):

@@ -1430,31 +1430,37 @@ ccut_status marginal_skip_enqueue(ccut_plan *p, const ccut_eval_opts *eo, const 
         for (size_t j = 0; j < a; ++j) {
           const size_t stride = size_t(1) << (2 * j);
           const bool in = f.axes[j].side == 1;
-          for (size_t base = 0; base < R.size(); ++base) {
-            if ((base >> (2 * j)) & 3u) continue;
-            const uint8_t pi = R[base], px = R[base + stride], py = R[base + 2 * stride], pz = R[base + 3 * stride];
-            if (in) {
-              R[base] = pi | px | py | pz;  // |0>, |1>
-              R[base + stride] = px;            // |+>
-              R[base + 2 * stride] = py;        // |+i>
-            } else {
-              R[base] = px;                 // X basis
-              R[base + stride] = py;            // Y basis
-              R[base + 2 * stride] = pi | pz;   // Z basis
+          for (size_t hi = 0; hi < R.size(); hi += 4 * stride)  // every index whose digit j is 0
+            for (size_t base = hi; base < hi + stride; ++base) {
+              const uint8_t pi = R[base], px = R[base + stride], py = R[base + 2 * stride], pz = R[base + 3 * stride];
+              if (in) {
+                R[base] = pi | px | py | pz;  // |0>, |1>
+                R[base + stride] = px;        // |+>
+                R[base + 2 * stride] = py;    // |+i>
+              } else {
+                R[base] = px;                 // X basis
+                R[base + stride] = py;        // Y basis
+                R[base + 2 * stride] = pi | pz;  // Z basis
+              }
+              R[base + 3 * stride] = 0;
             }
-            R[base + 3 * stride] = 0;
-          }
         }
+        // variant v's digits counted up in mixed radix (axis 0 fastest), its
+        // class index kept alongside
         static const uint32_t kPrepClass[4] = {0, 0, 1, 2};  // |0> |1> |+> |+i>
         std::vector<uint8_t> need(f.n_variants, 0);
+        std::vector<uint32_t> dig(a, 0);
+        uint64_t cls = 0;
         for (uint64_t v = 0; v < f.n_variants; ++v) {
-          uint64_t rest = v, cls = 0;
-          for (size_t j = 0; j < a; ++j) {
-            const uint32_t rad = f.axes[j].side == 1 ? 4u : 3u, d = (uint32_t)(rest % rad);
-            rest /= rad;
-            cls |= (uint64_t)(f.axes[j].side == 1 ? kPrepClass[d] : d) << (2 * j);  // bases X=0 Y=1 Z=2
-          }
           need[v] = R[cls];
+          for (size_t j = 0; j < a; ++j) {
+            const bool in = f.axes[j].side == 1;
+            const uint32_t rad = in ? 4u : 3u;
+            dig[j] = dig[j] + 1 == rad ? 0u : dig[j] + 1;
+            const uint32_t c_j = in ? kPrepClass[dig[j]] : dig[j];  // bases X=0 Y=1 Z=2
+            cls = (cls & ~(3ull << (2 * j))) | ((uint64_t)c_j << (2 * j));
+            if (dig[j] != 0) break;  // no carry into the next axis
+          }
         }
         vmask = (const uint8_t *)upload(c, need.data(), need.size());
         if (!vmask) return fail(c, CCUT_E_OOM, "device allocation failed");

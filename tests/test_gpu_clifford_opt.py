@@ -222,3 +222,17 @@ def test_skip_flag_scope(ctx):
         with pytest.raises(cc.CcutError) as e:
             call()
         assert e.value.status == cc.CCUT_E_UNSUPPORTED
+
+
+def test_skip_edge_cases(ctx):
+    """Skipping on an empty request, a request of every qubit and a circuit
+    without cuts (one term), sampled and exact, against the oracle."""
+    w = W.tiny()
+    for cuts, qubits in ((w.cuts, []), (w.cuts, list(range(w.n))), ([], w.qubits)):
+        plan = cc.Plan(ctx, w.n, w.ops, cuts)
+        for shots in (0, 300):
+            _log(f"skip edge case: k={len(cuts)} nq={len(qubits)} shots={shots}")
+            got = plan.marginal(qubits, shots=shots, seed=3, flags=cc.CCUT_FLAG_SKIP)
+            ref = C.marginal_skip(w.n, w.ops, cuts, qubits, shots=shots, seed=3)
+            assert got.shape == ref.shape
+            assert np.abs(got - ref).max() <= 1e-10, (len(cuts), len(qubits), shots)
