@@ -504,8 +504,11 @@ std::vector<uint64_t> measured_rows(const Fragment &f, const std::vector<uint32_
   return rows;
 }
 
+// vmask (device, one byte per variant of the fragment, optional): variants
+// with vmask[v] == 0 get no model (64 measured qubits or fewer; wider
+// fragments model every variant)
 ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, const FragRequest &r, uint64_t v0,
-                           uint64_t nv, uint64_t *models) {
+                           uint64_t nv, uint64_t *models, const uint8_t *vmask = nullptr) {
   ccut_ctx *c = p->ctx;
   const uint32_t W = row_words(f.m());
   if (!W) return fail(c, CCUT_E_UNSUPPORTED, "Clifford fragment wider than 512 qubits");
@@ -536,7 +539,7 @@ ccut_status tableau_models(ccut_plan *p, const Fragment &f, const FragDev &h, co
   if (nm > (uint32_t)kMaxMeas)
     HIP_TRY(c, launch_affine_wide(h, W, d_axis, d_row, nm, d_out, v0, nv, models, c->cur));
   else
-    HIP_TRY(c, launch_affine(h, W, d_out, v0, nv, models, c->cur));
+    HIP_TRY(c, launch_affine(h, W, d_out, v0, nv, models, c->cur, vmask));
   return CCUT_OK;
 }
 
@@ -609,7 +612,8 @@ ccut_status variant_dists(ccut_plan *p, const ccut_eval_opts *eo, const Fragment
     if (!models) {
       models = aget<uint64_t>(c, nv * model_words(nm));
       if (!models) return fail(c, CCUT_E_OOM, "device allocation failed");
-      ccut_status st2 = tableau_models(p, f, h, r, 0, nv, models);
+      // (exact tables read every model: only sampled data skip some)
+      ccut_status st2 = tableau_models(p, f, h, r, 0, nv, models, eo->shots_per_variant ? vmask : nullptr);
       if (st2 != CCUT_OK) return st2;
     }
     if (eo->shots_per_variant == 0) {

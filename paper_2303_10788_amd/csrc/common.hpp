@@ -402,7 +402,7 @@ hipError_t launch_carry_batch(const FragDev *descs, const CarryJob *jobs, uint32
 // Affine sample models from carried-back measured Paulis (one wave per
 // variant): rows as built by measured_rows on the host, W words per half.
 hipError_t launch_affine(const FragDev &F, uint32_t W, const uint64_t *rows, uint64_t v0, uint64_t nv,
-                         uint64_t *models, hipStream_t s);
+                         uint64_t *models, hipStream_t s, const uint8_t *vmask = nullptr);
 // More than 64 measurements (up to kMaxMeasWide): one workgroup per
 // variant; meas_axis[j] = the axis of measurement j if it is a quantum
 // output, else -1; row_of[j] = its first row in `rows`.

@@ -223,11 +223,15 @@ __device__ inline void affine_dispatch(uint32_t W, const FragDev &F, const uint6
   }
 }
 
-// Variants [v0, v0 + nv) of one fragment, one wave each.
+// Variants [v0, v0 + nv) of one fragment, one wave each.  vmask
+// (optional, indexed by variant): variants with vmask[v] == 0 get no model
+// (their shots are never drawn).
 __global__ __launch_bounds__(256) void affine_kernel(const FragDev F, uint32_t W, const uint64_t *__restrict__ rows,
-                                                     uint64_t v0, uint64_t nv, uint64_t *__restrict__ models) {
+                                                     uint64_t v0, uint64_t nv, uint64_t *__restrict__ models,
+                                                     const uint8_t *__restrict__ vmask) {
   const uint64_t i = (uint64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
   if (i >= nv) return;  // whole waves leave together
+  if (vmask && !vmask[v0 + i]) return;
   affine_dispatch(W, F, rows, v0 + i, models + i * model_words(F.n_meas));
 }
 
@@ -456,13 +460,13 @@ hipError_t launch_affine_wide(const FragDev &F, uint32_t W, const int8_t *meas_a
 }
 
 hipError_t launch_affine(const FragDev &F, uint32_t W, const uint64_t *rows, uint64_t v0, uint64_t nv,
-                         uint64_t *models, hipStream_t s) {
+                         uint64_t *models, hipStream_t s, const uint8_t *vmask) {
   if (nv == 0) return hipSuccess;
   if (F.n_meas > (uint32_t)kMaxMeas || (W != 1 && W != 2 && W != 4 && W != 8) || F.m > 64 * W)
     return hipErrorInvalidValue;
   const uint64_t blocks = (nv + 3) / 4;
   if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(affine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, F, W, rows, v0, nv, models);
+  hipLaunchKernelGGL(affine_kernel, dim3((unsigned)blocks), dim3(256), 0, s, F, W, rows, v0, nv, models, vmask);
   return hipGetLastError();
 }
 
