@@ -353,8 +353,10 @@ __device__ __attribute__((always_inline)) void tile_body(const TileJob &J, uint6
     }
   }
   // out[P][x_out], P base 4 (axis 0 fastest), x_out = u 2^t + xo: the
-  // source slot from the two byte tables (P < 4^a <= 4096) and s_xdep
-  double *out = J.out;
+  // source slot from the two byte tables (P < 4^a <= 4096) and s_xdep;
+  // stored through a global pointer (a generic store would hold up the next
+  // LDS read until it completes)
+  __attribute__((address_space(1))) double *out = (__attribute__((address_space(1))) double *)J.out;
   const uint64_t x_out = J.x_out, ob = (uint64_t)u << t;
   const uint32_t n_out = XT << (2 * a);
   for (uint32_t e = tid; e < n_out; e += kTileThreads) {

@@ -257,7 +257,9 @@ __device__ __attribute__((always_inline)) void sv_body(const FragDev &F, double 
       uint32_t sub = 0;
       do {
         const uint32_t b = fixed | sub;
-        const C2 v = states[(size_t)b * N + i];
+        const __attribute__((address_space(1))) double *sp =
+            (const __attribute__((address_space(1))) double *)states + 2 * ((size_t)b * N + i);
+        const C2 v{sp[0], sp[1]};
         // the number of +i digits whose input bit is 1 sets the phase i^k
         const uint32_t k = __popc(sub & imul) & 3u;
         const double vr = k == 0 ? v.re : k == 1 ? -v.im : k == 2 ? -v.re : v.im;
@@ -510,7 +512,9 @@ __device__ void sv_outcomes(const FragDev &F, C2 *S, C2 *work, bool copy, uint32
         stride *= F.axis_radix[j];
       }
     }
-    double *out = dist + v * outs;
+    // stored through a global pointer (a generic store would hold up the
+    // next LDS read until it completes)
+    __attribute__((address_space(1))) double *out = (__attribute__((address_space(1))) double *)(dist + v * outs);
     // outcome probabilities: |amp|^2 in place (the work buffer as N
     // doubles; N = BS * R, so each thread holds at most R of them), then a
     // pairwise sum over each unmeasured qubit in turn (fixed order, one
