@@ -2374,12 +2374,13 @@ ccut_status batch_enqueue(ccut_batch *b, bool tune) {
   if ((st = batch_models(b, d_descs, d_w, d_items, d_rows, d_models, b->block, b->grid)) != CCUT_OK) return st;
   if (!b->samp.empty()) {
     // jobs in LDS classes (one launch each, so a launch's workgroups reserve
-    // only their class's histogram): up to 8, 24, 40, 72 and 136 KiB
-    constexpr int kClasses = 5;
+    // only their class's histogram): up to 20 KiB (eight workgroups per CU,
+    // as many as the wave slots allow, so one class), 40, 72 and 136 KiB
+    constexpr int kClasses = 4;
     const uint64_t shots = b->eo.shots_per_variant;
     const uint64_t nquads = (shots + 3) / 4;
     auto lds_class = [](size_t l) {
-      return l <= (8u << 10) ? 0 : l <= (24u << 10) ? 1 : l <= (40u << 10) ? 2 : l <= (72u << 10) ? 3 : 4;
+      return l <= (20u << 10) ? 0 : l <= (40u << 10) ? 1 : l <= (72u << 10) ? 2 : 3;
     };
     auto sliced_bits = [](uint32_t nm) { return nm > kLdsHistBits && nm <= kLdsHistBits + kMaxSliceBits; };
     std::vector<size_t> order;
