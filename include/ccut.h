@@ -169,10 +169,10 @@ typedef struct {
  *    support is fixed first from the Clifford fragments' exact Pauli
  *    tensors (known before any variant is sampled; non-Clifford fragments do
  *    not restrict it), every sampled Clifford variant that no supported cut
- *    term reads gets no sample model and draws no shots (a quantum input's |0> and |1> serve every
- *    Pauli, |+> only X, |+i> only Y; a quantum output's Z basis serves I and
- *    Z, X only X, Y only Y), the tensors stay in the Pauli basis and only the
- *    supported terms are summed.  Exact data: the dense result up to
+ *    term reads gets no sample model and draws no shots (a quantum input's
+ *    |0> and |1> serve every Pauli, |+> only X, |+i> only Y; a quantum
+ *    output's Z basis serves I and Z, X only X, Y only Y), the tensors stay
+ *    in the Pauli basis and only the supported terms are summed.  Exact data: the dense result up to
  *    rounding.  Synchronizes (the support is read back); not with
  *    CCUT_FLAG_ML.  Non-Clifford variants are all evaluated (their state
  *    vectors share the gate program across preparations).
